@@ -1,0 +1,200 @@
+/*
+ * fwils.h -- C ABI of the MI355X library for the matrix-free elastic
+ * Lippmann-Schwinger (LS) solve and the Frechet / adjoint operators of the
+ * distorted-Born method of Xiang, Jakobsen, Shekhar, Eikrem and Naevdal,
+ * arXiv 2402.02116.
+ *
+ * Problem.  A 2-D (x-z) periodic grid of nx * nz square cells of size dx
+ * carries a homogeneous background stiffness C0 (Voigt C11, C13, C33, C55;
+ * VTI or isotropic) and density rho0 (eq. decom), a contrast dC(x), drho(x),
+ * and one frequency f with complex frequency w~ = 2 pi f (1 + i eta).  The
+ * displacement u solves eq. u_2 written as A u = u0 (eqs. A, axb):
+ *
+ *     A u = u - G0 conv b(u),   b(u) = w~^2 drho u + div_h( dC : E_h u ),
+ *
+ * where E_h is the Voigt strain built from 2nd-order central differences,
+ * div_h = -E_h^T is the matching divergence (the integration by parts of eq.
+ * dgv, exact on the torus), and G0 conv f = IFFT2( G_hat(k) FFT2(f) ) is the
+ * circular convolution of eq. FFT with the wavenumber-domain Green's tensor
+ * G_hat(k) = (Gamma(k) - rho0 w~^2 I)^-1 (Fourier transform of eq. Green;
+ * Gamma is the Christoffel matrix of C0).  For even n, products of two
+ * different wavenumber components use k = 0 at the Nyquist index so that
+ * G_hat is even in k and G0 symmetric.
+ *
+ * One plan holds one or more problems ("grids"); each has nsys systems
+ * (sources) that share its grid, background, frequency and contrast.
+ *
+ * Memory layout (all row-major, x fastest):
+ *   field      complex64 [nsys][2][nz][nx], component 0 = u_x, 1 = u_z,
+ *              interleaved (re, im).  A plan-level field is the
+ *              concatenation of its problems' fields in problem order;
+ *              fwils_field_elems gives its length in complex elements.
+ *   maps       float32 [5][nz][nx], absolute units, order
+ *              (dC11, dC13, dC33, dC55, drho) in Pa and kg/m^3.
+ *   data       complex64 [nsys][nrec][2] per problem, concatenated.
+ *   sources,   host int32 [n][2] as (ix, iz); forces host double [n][2]
+ *   receivers  as (fx, fz) in newtons.
+ *
+ * Ownership and execution.
+ *   All field, map and data pointers are DEVICE pointers owned by the caller
+ *   and must stay valid until the stream has finished the call.  Index and
+ *   force arrays are host pointers copied during the call.  The plan owns
+ *   small host metadata only; device scratch is the caller-provided
+ *   workspace (fwils_workspace_size / fwils_set_workspace), which the plan
+ *   uses until it is destroyed or given another workspace.  Every call is
+ *   asynchronous on the plan's stream (fwils_set_stream; default: the null
+ *   stream) unless stated otherwise.  A plan is not thread-safe; separate
+ *   plans are independent.
+ *
+ * Errors.  Every call returns fwils_status.  Argument errors (FWILS_EINVAL)
+ * are detected before any work is enqueued and leave no side effects.  HIP
+ * runtime failures give FWILS_EDEVICE; fwils_last_error() returns a
+ * thread-local text with details.  Non-convergence is not an abort: outputs
+ * are written and FWILS_ENOCONV is returned.
+ */
+#ifndef FWILS_H
+#define FWILS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FWILS_ABI_VERSION 1
+
+typedef enum {
+    FWILS_OK = 0,
+    FWILS_EINVAL = 1,        /* bad argument, shape or state                  */
+    FWILS_ENOMEM = 2,        /* workspace missing or too small                */
+    FWILS_EDEVICE = 3,       /* HIP runtime error                             */
+    FWILS_ENOCONV = 4,       /* some system did not reach the tolerance       */
+    FWILS_EBREAKDOWN = 5,    /* Krylov breakdown or non-finite residual       */
+    FWILS_EUNSUPPORTED = 6   /* valid request this build does not implement   */
+} fwils_status;
+
+typedef enum {
+    FWILS_C64 = 0            /* complex64 fields, fp32 maps, FP64 reductions  */
+} fwils_precision;
+
+typedef enum {
+    FWILS_SYMBOL_SPECTRAL = 0,   /* exact wavenumbers in Gamma(k)              */
+    FWILS_SYMBOL_CENTRAL = 1     /* k -> sin(k dx)/dx: G0 inverts the discrete
+                                    background operator exactly (eq. Ewave)    */
+} fwils_symbol;
+
+/* One (grid, frequency) problem. */
+typedef struct {
+    int32_t nx, nz;      /* cells; each 2^a 3^b with 16 <= n <= 2048        */
+    double  dx;          /* cell size (m), both axes                        */
+    double  c0[4];       /* background Voigt C11, C13, C33, C55 (Pa)        */
+    double  rho0;        /* background density (kg/m^3)                     */
+    double  freq_hz;     /* frequency f (Hz)                                */
+    double  damping;     /* eta in w~ = 2 pi f (1 + i eta); eta > 0         */
+    int32_t nsys;        /* systems (sources) on this problem, >= 1         */
+    int32_t symbol;      /* fwils_symbol                                    */
+} fwils_problem;
+
+typedef struct fwils_plan_s* fwils_plan;
+
+/* Solve flags. */
+#define FWILS_SOLVE_X0       0x1u  /* x holds the initial guess (else x0 = 0)   */
+#define FWILS_SOLVE_PLAIN    0x2u  /* per-source loop, host-synchronous
+                                      convergence check every iteration (the
+                                      plain baseline; same kernels, nsys = 1)  */
+#define FWILS_SOLVE_NOGRAPH  0x4u  /* batched, but launched without HIP graphs */
+
+/* Adjoint flags. */
+#define FWILS_ADJ_ACCUMULATE 0x1u  /* add into g instead of overwriting        */
+
+/* Create a plan for nprob problems (validated; nothing is allocated on the
+ * device).  On success *out receives the plan. */
+fwils_status fwils_plan_create(const fwils_problem* probs, int32_t nprob,
+                               fwils_precision prec, fwils_plan* out);
+void fwils_plan_destroy(fwils_plan plan);
+
+/* Bytes of device workspace the plan needs (256-byte aligned start). */
+fwils_status fwils_workspace_size(fwils_plan plan, size_t* bytes);
+/* Hand the plan its workspace.  Synchronous: initialises constant tables and
+ * zero contrasts in it. */
+fwils_status fwils_set_workspace(fwils_plan plan, void* dev, size_t bytes);
+/* Stream for all later work (a hipStream_t; NULL = null stream). */
+fwils_status fwils_set_stream(fwils_plan plan, void* hip_stream);
+/* Complex elements in one plan-level field: sum_p nsys_p * 2 * nz_p * nx_p. */
+fwils_status fwils_field_elems(fwils_plan plan, int64_t* elems);
+
+/* Contrast of problem iprob (eqs. decom, key): copies the five maps
+ * [5][nz][nx] (device, fp32, absolute units) into the workspace. */
+fwils_status fwils_set_contrast(fwils_plan plan, int32_t iprob, const float* maps);
+
+/* Receivers of problem iprob: host int32 [nrec][2] (ix, iz), 1 <= nrec <= 65536.
+ * Copied into the workspace (synchronous). */
+fwils_status fwils_set_receivers(fwils_plan plan, int32_t iprob,
+                                 const int32_t* rec_ixz, int32_t nrec);
+
+/* Incident field u0 = G0 conv s (eq. u0) for one point force per system:
+ * s = F / dx^2 at cell (ix, iz).  src_ixz, src_f: host [sum nsys][2].
+ * u0: device field (output). */
+fwils_status fwils_incident(fwils_plan plan, const int32_t* src_ixz,
+                            const double* src_f, void* u0);
+
+/* b(u) = w~^2 drho u + div_h(dC : E_h u): the contrast body force (the
+ * right-hand side of eq. Ewave0 without S).  u, b: device fields. */
+fwils_status fwils_body_force(fwils_plan plan, const void* u, void* b);
+
+/* out = G0 conv f (eq. FFT).  f, out: device fields (may alias). */
+fwils_status fwils_convolve(fwils_plan plan, const void* f, void* out);
+
+/* Au = u - G0 conv b(u) (eq. A), one batched application.  u, Au: device
+ * fields, must not alias. */
+fwils_status fwils_apply(fwils_plan plan, const void* u, void* Au);
+
+/* Solve A x = rhs for every system by BiCGSTAB (eq. axb), complex64 vectors
+ * and FP64 inner products.  Stops each system when its recursive residual
+ * satisfies ||r|| <= rtol ||rhs||, or after maxit iterations.  rhs, x:
+ * device fields (x is output, and input with FWILS_SOLVE_X0).  iters (int32)
+ * and relres (double, TRUE residual ||rhs - A x|| / ||rhs||) are device
+ * arrays [sum nsys] or NULL.  Returns FWILS_ENOCONV if any system stopped at
+ * maxit and FWILS_EBREAKDOWN if any broke down; x is written in all cases.
+ * Synchronises the stream before returning. */
+fwils_status fwils_solve(fwils_plan plan, const void* rhs, void* x, double rtol,
+                         int32_t maxit, int32_t* iters, double* relres,
+                         uint32_t flags);
+
+/* Frechet operator (eqs. F, YM, F0, uY): for every system
+ *   d = R A_b^-1 G0 conv P_b(dm),
+ *   P_b(dm) = w~^2 dm_rho u^b + div_h( dC(dm) : E_h u^b ),
+ * with dC(dm) = sum_p B^(p) dm^(p) (eq. dC, App. C) and A_b the operator with
+ * the plan's contrast.  ub: device field of background solutions u^b.
+ * dm: host array of nprob device pointers to fp32 maps [5][nz][nx]
+ * (absolute units; may repeat).  d: device data (output).  The one LS solve
+ * per system uses rtol / maxit as fwils_solve. */
+fwils_status fwils_frechet(fwils_plan plan, const void* ub, const float* const* dm,
+                           void* d, double rtol, int32_t maxit);
+
+/* Adjoint operator (eqs. ad1, ua, ua0; App. B): for every problem
+ *   u^a = A_b^-1 G0 conv R^T conj(r),
+ *   g_rho = sum_sys conj( w~^2 u^a . u^b ),
+ *   g_p   = - sum_sys conj( (E_h u^a)^T B^(p) (E_h u^b) ),  p = C11, C13, C33, C55,
+ * accumulated over systems in FP64.  r: device data.  g: host array of nprob
+ * device pointers to complex64 maps [5][nz][nx] (output; with
+ * FWILS_ADJ_ACCUMULATE added to).  Problems that share a g pointer are
+ * summed when FWILS_ADJ_ACCUMULATE is set. */
+fwils_status fwils_adjoint(fwils_plan plan, const void* ub, const void* r,
+                           void* const* g, uint32_t flags, double rtol, int32_t maxit);
+
+/* 2-D FFT of every field of problem iprob with the library's own transform
+ * kernels (unnormalised forward, exp(-i k.x); inverse with exp(+i k.x) and
+ * no 1/(nx nz)).  A self-test entry point.  in, out: device, may alias. */
+fwils_status fwils_fft2(fwils_plan plan, int32_t iprob, const void* in, void* out,
+                        int32_t inverse);
+
+const char* fwils_status_string(fwils_status s);
+const char* fwils_last_error(void);
+int32_t fwils_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FWILS_H */

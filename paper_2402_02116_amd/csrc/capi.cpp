@@ -1,0 +1,713 @@
+// C ABI of the fwils library: plan and workspace management, the batched
+// BiCGSTAB driver (eq. axb) with HIP-graph iteration chunks, the Frechet
+// operator J (eqs. YM, F0, uY) and its adjoint J* (eqs. ad1, ua, ua0).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/fwils.h"
+#include "launch.h"
+
+using namespace fw;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+void set_error(const char* fmt, ...) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+}
+
+#define FW_HIP(call)                                                                       \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess) {                                                            \
+            set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, __LINE__); \
+            return FWILS_EDEVICE;                                                          \
+        }                                                                                  \
+    } while (0)
+
+#define FW_TRY(expr)                          \
+    do {                                      \
+        fwils_status s_ = (expr);             \
+        if (s_ != FWILS_OK) return s_;        \
+    } while (0)
+
+constexpr int kMaxRec = 65536;
+constexpr int kChunkIters = 4;
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct ProbHost {
+    fwils_problem p;
+    ProbDev dev;
+    size_t field_off;     // complex elements into a plan-level field
+    size_t n_per_sys;     // 2 nz nx
+    size_t sys_off;       // first system index
+    size_t map_off;       // floats into the maps region
+    size_t data_off;      // complex elements into plan-level receiver data
+    int nrec;
+    int np_rows;          // partial records per system from the row epilogues
+    int np_vec;           // partial records per system from vector kernels
+};
+
+}  // namespace
+
+struct fwils_plan_s {
+    std::vector<ProbHost> probs;
+    size_t total_field = 0, total_sys = 0, maps_floats = 0;
+    int max_np = 0;
+    hipStream_t stream = nullptr;
+    // workspace
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    size_t off_tw = 0, off_state = 0, off_part = 0, part_bytes = 0, off_maps = 0, off_rec = 0,
+           off_src = 0, off_vec = 0;
+    float2* tw = nullptr;
+    SysState* state = nullptr;
+    double *partV = nullptr, *partT = nullptr, *partXR = nullptr, *partB = nullptr;
+    float* maps = nullptr;
+    int32_t* rec = nullptr;
+    int32_t* src_i = nullptr;
+    double* src_f = nullptr;
+    float2 *x = nullptr, *r = nullptr, *rhat = nullptr, *p = nullptr, *v = nullptr, *s = nullptr,
+           *t = nullptr, *tmp = nullptr, *rhs = nullptr;
+    // graph of one chunk of iterations over all problems
+    hipGraphExec_t chunk = nullptr;
+    SysState* host_state = nullptr;   // pinned
+};
+
+namespace {
+
+ProbDev make_dev(const fwils_problem& p) {
+    ProbDev d;
+    const double w = 2.0 * M_PI * p.freq_hz, eta = p.damping;
+    const double w2r = w * w * (1.0 - eta * eta), w2i = w * w * 2.0 * eta;
+    const double rw2 = p.rho0 * w * w;
+    d.nx = p.nx;
+    d.nz = p.nz;
+    d.nsys = p.nsys;
+    d.symbol = p.symbol;
+    d.inv4dx2 = (float)(1.0 / (4.0 * p.dx * p.dx));
+    d.w2 = make_float2((float)w2r, (float)w2i);
+    d.gc11 = (float)(p.c0[0] / rw2);
+    d.gc33 = (float)(p.c0[2] / rw2);
+    d.gc55 = (float)(p.c0[3] / rw2);
+    d.gc1355 = (float)((p.c0[1] + p.c0[3]) / rw2);
+    d.ga = make_float2((float)(1.0 - eta * eta), (float)(2.0 * eta));
+    d.gscale = (float)(1.0 / (rw2 * (double)p.nx * (double)p.nz));
+    d.dkx = (float)(2.0 * M_PI / (p.nx * p.dx));
+    d.dkz = (float)(2.0 * M_PI / (p.nz * p.dx));
+    d.dx = (float)p.dx;
+    return d;
+}
+
+fwils_status check_plan(fwils_plan plan, bool need_ws = true) {
+    if (!plan) {
+        set_error("null plan");
+        return FWILS_EINVAL;
+    }
+    if (need_ws && !plan->ws) {
+        set_error("plan has no workspace (fwils_set_workspace)");
+        return FWILS_ENOMEM;
+    }
+    return FWILS_OK;
+}
+
+// Views of the plan-level vectors for problem i.
+inline float2* at(float2* base, const ProbHost& P) { return base + P.field_off; }
+inline const float2* at(const void* base, const ProbHost& P) {
+    return static_cast<const float2*>(base) + P.field_off;
+}
+inline SysState* st_at(fwils_plan pl, const ProbHost& P) { return pl->state + P.sys_off; }
+inline double* part_at(double* base, fwils_plan pl, const ProbHost& P) {
+    return base + P.sys_off * (size_t)pl->max_np * kPartialNV;
+}
+inline float* maps_at(fwils_plan pl, const ProbHost& P) { return pl->maps + P.map_off; }
+
+// y = G0 conv f for problem P (f read, out written; tmp is scratch).
+hipError_t conv_problem(fwils_plan pl, const ProbHost& P, const float2* f, float2* out) {
+    const int rows = P.p.nsys * 2 * P.p.nz;
+    float2* tmp = at(pl->tmp, P);
+    hipError_t e = launch_rows_fwd(P.p.nx, f, tmp, rows, 2 * P.p.nz, nullptr, pl->tw, pl->stream);
+    if (e == hipSuccess) e = launch_cols(COL_GREEN, tmp, P.dev, nullptr, pl->tw, pl->stream);
+    if (e == hipSuccess)
+        e = launch_rows_inv(P.p.nx, EPI_STORE, tmp, nullptr, nullptr, out, nullptr, rows,
+                            2 * P.p.nz, nullptr, pl->tw, pl->stream);
+    return e;
+}
+
+// One LS matvec with an epilogue, for nsys systems starting at the given
+// views (used both batched and per system).
+hipError_t matvec(fwils_plan pl, const ProbHost& P, const ProbDev& d, const float2* u, float2* tmp,
+                  const float* maps, int epi, const float2* aux, float2* out, double* part,
+                  const SysState* st, hipStream_t s) {
+    const int rows = d.nsys * 2 * d.nz;
+    hipError_t e = launch_body_force(u, tmp, maps, d, st, s);
+    if (e == hipSuccess) e = launch_rows_fwd(d.nx, tmp, tmp, rows, 2 * d.nz, st, pl->tw, s);
+    if (e == hipSuccess) e = launch_cols(COL_GREEN, tmp, d, st, pl->tw, s);
+    if (e == hipSuccess)
+        e = launch_rows_inv(d.nx, epi, tmp, u, aux, out, part, rows, 2 * d.nz, st, pl->tw, s);
+    (void)P;
+    return e;
+}
+
+// Views of one problem restricted to systems [s0, s0 + ns).
+// Partial buffers are laid out per problem as [nsys][nb][kPartialNV] with the
+// producer's nb (np_vec for partXR / partB, np_rows for partV / partT), so
+// a view of systems from s0 on starts s0 * nb records into the problem's region.
+struct SysView {
+    ProbDev d;
+    size_t foff;     // complex offset of system s0 within the plan-level field
+    size_t soff;     // state index
+    size_t poff_vec; // doubles: partXR / partB records of system s0
+    size_t poff_row; // doubles: partV / partT records of system s0
+};
+
+SysView make_view(fwils_plan pl, const ProbHost& P, int s0, int ns) {
+    SysView v;
+    v.d = P.dev;
+    v.d.nsys = ns;
+    v.foff = P.field_off + (size_t)s0 * P.n_per_sys;
+    v.soff = P.sys_off + (size_t)s0;
+    const size_t base = P.sys_off * (size_t)pl->max_np * kPartialNV;
+    v.poff_vec = base + (size_t)s0 * P.np_vec * kPartialNV;
+    v.poff_row = base + (size_t)s0 * P.np_rows * kPartialNV;
+    return v;
+}
+
+// One BiCGSTAB iteration on a view (all kernels skip stopped systems).
+hipError_t bicg_iteration(fwils_plan pl, const ProbHost& P, const SysView& V, hipStream_t s) {
+    const int ns = V.d.nsys;
+    const int n = (int)P.n_per_sys;
+    float2 *x = pl->x + V.foff, *r = pl->r + V.foff, *rh = pl->rhat + V.foff, *p = pl->p + V.foff,
+           *v = pl->v + V.foff, *sv = pl->s + V.foff, *t = pl->t + V.foff, *tmp = pl->tmp + V.foff;
+    SysState* st = pl->state + V.soff;
+    double *pV = pl->partV + V.poff_row, *pT = pl->partT + V.poff_row, *pXR = pl->partXR + V.poff_vec;
+    const float* maps = maps_at(pl, P);
+    hipError_t e = launch_bicg_p(r, p, v, pXR, P.np_vec, st, ns, n, s);
+    if (e == hipSuccess) e = matvec(pl, P, V.d, p, tmp, maps, EPI_BICG_V, rh, v, pV, st, s);
+    if (e == hipSuccess) e = launch_bicg_s(r, v, sv, pV, P.np_rows, st, ns, n, s);
+    if (e == hipSuccess) e = matvec(pl, P, V.d, sv, tmp, maps, EPI_BICG_T, nullptr, t, pT, st, s);
+    if (e == hipSuccess) e = launch_bicg_xr(x, r, rh, p, sv, t, pT, P.np_rows, pXR, st, ns, n, s);
+    return e;
+}
+
+fwils_status build_chunk_graph(fwils_plan pl) {
+    if (pl->chunk) return FWILS_OK;
+    const int np = (int)pl->probs.size();
+    std::vector<hipStream_t> ss(np, nullptr);
+    std::vector<hipEvent_t> ev(np + 1, nullptr);
+    for (int i = 0; i < np; ++i) FW_HIP(hipStreamCreateWithFlags(&ss[i], hipStreamNonBlocking));
+    for (int i = 0; i <= np; ++i) FW_HIP(hipEventCreateWithFlags(&ev[i], hipEventDisableTiming));
+    hipGraph_t g = nullptr;
+    FW_HIP(hipStreamBeginCapture(ss[0], hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipEventRecord(ev[np], ss[0]);
+    for (int i = 1; i < np && e == hipSuccess; ++i) e = hipStreamWaitEvent(ss[i], ev[np], 0);
+    for (int i = 0; i < np && e == hipSuccess; ++i) {
+        const ProbHost& P = pl->probs[i];
+        const SysView V = make_view(pl, P, 0, P.p.nsys);
+        for (int it = 0; it < kChunkIters && e == hipSuccess; ++it) e = bicg_iteration(pl, P, V, ss[i]);
+        if (e == hipSuccess)
+            e = launch_bicg_check(st_at(pl, P), part_at(pl->partXR, pl, P), P.np_vec, P.p.nsys, ss[i]);
+        if (i > 0 && e == hipSuccess) e = hipEventRecord(ev[i], ss[i]);
+    }
+    for (int i = 1; i < np && e == hipSuccess; ++i) e = hipStreamWaitEvent(ss[0], ev[i], 0);
+    hipError_t e2 = hipStreamEndCapture(ss[0], &g);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&pl->chunk, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    for (auto& q : ss) (void)hipStreamDestroy(q);
+    for (auto& q : ev) (void)hipEventDestroy(q);
+    if (e != hipSuccess) {
+        pl->chunk = nullptr;
+        set_error("graph capture failed: %s", hipGetErrorString(e));
+        return FWILS_EDEVICE;
+    }
+    return FWILS_OK;
+}
+
+// Solve A x = b where b and the result live in plan-level fields.  x_ws is
+// the workspace solution vector (pl->x).  flags as fwils_solve.
+fwils_status solve_ws(fwils_plan pl, const float2* b, bool use_x0, double rtol, int maxit,
+                      int32_t* iters, double* relres, uint32_t flags) {
+    hipStream_t s = pl->stream;
+    // initial residual, state
+    for (const ProbHost& P : pl->probs) {
+        const int n = (int)P.n_per_sys;
+        const float2* bp = b + P.field_off;
+        if (use_x0) {
+            FW_HIP(matvec(pl, P, P.dev, at(pl->x, P), at(pl->tmp, P), maps_at(pl, P), EPI_TRUERES, bp,
+                          at(pl->r, P), part_at(pl->partT, pl, P), nullptr, s));
+        }
+        FW_HIP(launch_bicg_init(bp, use_x0 ? at(pl->r, P) : nullptr, at(pl->x, P), at(pl->r, P),
+                                at(pl->rhat, P), at(pl->p, P), at(pl->v, P),
+                                part_at(pl->partXR, pl, P), part_at(pl->partB, pl, P), P.p.nsys, n,
+                                !use_x0, s));
+        FW_HIP(launch_bicg_state_init(st_at(pl, P), part_at(pl->partXR, pl, P),
+                                      part_at(pl->partB, pl, P), P.p.nsys, P.np_vec, rtol, maxit, s));
+    }
+    const size_t nst = pl->total_sys;
+    auto all_done = [&](bool& done) -> fwils_status {
+        FW_HIP(hipMemcpyAsync(pl->host_state, pl->state, nst * sizeof(SysState), hipMemcpyDeviceToHost, s));
+        FW_HIP(hipStreamSynchronize(s));
+        done = true;
+        for (size_t i = 0; i < nst; ++i)
+            if (pl->host_state[i].status == ST_RUNNING) done = false;
+        return FWILS_OK;
+    };
+
+    if (flags & FWILS_SOLVE_PLAIN) {
+        // per-source loop, host-synchronous check after every iteration
+        for (const ProbHost& P : pl->probs) {
+            for (int sy = 0; sy < P.p.nsys; ++sy) {
+                const SysView V = make_view(pl, P, sy, 1);
+                for (int it = 0; it <= maxit; ++it) {
+                    FW_HIP(bicg_iteration(pl, P, V, s));
+                    FW_HIP(launch_bicg_check(pl->state + V.soff, pl->partXR + V.poff_vec, P.np_vec, 1, s));
+                    FW_HIP(hipMemcpyAsync(pl->host_state + V.soff, pl->state + V.soff, sizeof(SysState),
+                                          hipMemcpyDeviceToHost, s));
+                    FW_HIP(hipStreamSynchronize(s));
+                    if (pl->host_state[V.soff].status != ST_RUNNING) break;
+                }
+            }
+        }
+    } else {
+        const int max_chunks = maxit / kChunkIters + 2;
+        bool done = false;
+        FW_TRY(all_done(done));
+        if (!(flags & FWILS_SOLVE_NOGRAPH)) FW_TRY(build_chunk_graph(pl));
+        for (int c = 0; c < max_chunks && !done; ++c) {
+            if (flags & FWILS_SOLVE_NOGRAPH) {
+                for (const ProbHost& P : pl->probs) {
+                    const SysView V = make_view(pl, P, 0, P.p.nsys);
+                    for (int it = 0; it < kChunkIters; ++it) FW_HIP(bicg_iteration(pl, P, V, s));
+                    FW_HIP(launch_bicg_check(st_at(pl, P), part_at(pl->partXR, pl, P), P.np_vec,
+                                             P.p.nsys, s));
+                }
+            } else {
+                FW_HIP(hipGraphLaunch(pl->chunk, s));
+            }
+            FW_TRY(all_done(done));
+        }
+    }
+    // true residual and per-system outputs
+    for (const ProbHost& P : pl->probs) {
+        FW_HIP(matvec(pl, P, P.dev, at(pl->x, P), at(pl->tmp, P), maps_at(pl, P), EPI_TRUERES,
+                      b + P.field_off, at(pl->r, P), part_at(pl->partT, pl, P), nullptr, s));
+        FW_HIP(launch_bicg_finish(st_at(pl, P), part_at(pl->partT, pl, P), P.np_rows, P.p.nsys,
+                                  iters ? iters + P.sys_off : nullptr, relres ? relres + P.sys_off : nullptr,
+                                  s));
+    }
+    FW_HIP(hipMemcpyAsync(pl->host_state, pl->state, nst * sizeof(SysState), hipMemcpyDeviceToHost, s));
+    FW_HIP(hipStreamSynchronize(s));
+    bool noconv = false, brk = false;
+    for (size_t i = 0; i < nst; ++i) {
+        const int stt = pl->host_state[i].status;
+        if (stt == ST_MAXIT || stt == ST_RUNNING) noconv = true;
+        if (stt == ST_BREAKDOWN || stt == ST_NONFINITE) brk = true;
+    }
+    if (brk) {
+        set_error("BiCGSTAB breakdown or non-finite residual in at least one system");
+        return FWILS_EBREAKDOWN;
+    }
+    if (noconv) {
+        set_error("at least one system did not reach rtol within maxit");
+        return FWILS_ENOCONV;
+    }
+    return FWILS_OK;
+}
+
+fwils_status check_field_ptrs(std::initializer_list<const void*> ptrs) {
+    for (const void* q : ptrs)
+        if (!q) {
+            set_error("null device pointer");
+            return FWILS_EINVAL;
+        }
+    return FWILS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t fwils_abi_version(void) { return FWILS_ABI_VERSION; }
+
+const char* fwils_status_string(fwils_status s) {
+    switch (s) {
+        case FWILS_OK: return "ok";
+        case FWILS_EINVAL: return "invalid argument";
+        case FWILS_ENOMEM: return "workspace missing or too small";
+        case FWILS_EDEVICE: return "HIP device error";
+        case FWILS_ENOCONV: return "not converged";
+        case FWILS_EBREAKDOWN: return "Krylov breakdown";
+        case FWILS_EUNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char* fwils_last_error(void) { return g_last_error.c_str(); }
+
+fwils_status fwils_plan_create(const fwils_problem* probs, int32_t nprob, fwils_precision prec,
+                               fwils_plan* out) {
+    if (!out || !probs || nprob < 1 || nprob > 64) {
+        set_error("plan_create: need 1..64 problems and an output pointer");
+        return FWILS_EINVAL;
+    }
+    if (prec != FWILS_C64) {
+        set_error("plan_create: only FWILS_C64 is implemented");
+        return FWILS_EUNSUPPORTED;
+    }
+    for (int i = 0; i < nprob; ++i) {
+        const fwils_problem& p = probs[i];
+        if (!fft_size_supported(p.nx) || !fft_size_supported(p.nz)) {
+            set_error("problem %d: nx=%d nz=%d not supported (2^a 3^b, 16..2048)", i, p.nx, p.nz);
+            return FWILS_EINVAL;
+        }
+        if (!(p.dx > 0) || !(p.rho0 > 0) || !(p.freq_hz > 0) || !(p.damping > 0) ||
+            !(p.c0[0] > 0) || !(p.c0[2] > 0) || !(p.c0[3] > 0) || !std::isfinite(p.c0[1])) {
+            set_error("problem %d: dx, rho0, freq_hz, damping, C11, C33, C55 must be > 0", i);
+            return FWILS_EINVAL;
+        }
+        if (p.nsys < 1 || (long long)p.nsys * 2 * p.nx * p.nz > (1LL << 31) * 4) {
+            set_error("problem %d: nsys=%d out of range", i, p.nsys);
+            return FWILS_EINVAL;
+        }
+        if (p.symbol != FWILS_SYMBOL_SPECTRAL && p.symbol != FWILS_SYMBOL_CENTRAL) {
+            set_error("problem %d: unknown symbol %d", i, p.symbol);
+            return FWILS_EINVAL;
+        }
+    }
+    fwils_plan pl = new fwils_plan_s();
+    size_t foff = 0, soff = 0, moff = 0;
+    for (int i = 0; i < nprob; ++i) {
+        ProbHost P;
+        P.p = probs[i];
+        P.dev = make_dev(P.p);
+        P.n_per_sys = (size_t)2 * P.p.nz * P.p.nx;
+        P.field_off = foff;
+        P.sys_off = soff;
+        P.map_off = moff;
+        P.data_off = 0;
+        P.nrec = 0;
+        P.np_rows = row_geom(P.p.nx, 2 * P.p.nz).blocks_per_sys;
+        P.np_vec = vec_blocks_per_sys((int)P.n_per_sys);
+        pl->max_np = std::max(pl->max_np, std::max(P.np_rows, P.np_vec));
+        foff += (size_t)P.p.nsys * P.n_per_sys;
+        soff += (size_t)P.p.nsys;
+        moff += (size_t)5 * P.p.nz * P.p.nx;
+        pl->probs.push_back(P);
+    }
+    pl->total_field = foff;
+    pl->total_sys = soff;
+    pl->maps_floats = moff;
+    // workspace layout
+    size_t o = 0;
+    pl->off_tw = o;
+    o = align256(o + twiddle_table_elems() * sizeof(float2));
+    pl->off_state = o;
+    o = align256(o + pl->total_sys * sizeof(SysState));
+    pl->off_part = o;
+    pl->part_bytes = align256(pl->total_sys * (size_t)pl->max_np * kPartialNV * sizeof(double));
+    o += 4 * pl->part_bytes;
+    pl->off_maps = o;
+    o = align256(o + pl->maps_floats * sizeof(float));
+    pl->off_rec = o;
+    o = align256(o + (size_t)nprob * kMaxRec * 2 * sizeof(int32_t));
+    pl->off_src = o;
+    o = align256(o + pl->total_sys * 2 * (sizeof(int32_t) + sizeof(double)));
+    pl->off_vec = o;
+    o += 9 * align256(pl->total_field * sizeof(float2));
+    pl->ws_bytes = o;
+    *out = pl;
+    return FWILS_OK;
+}
+
+void fwils_plan_destroy(fwils_plan plan) {
+    if (!plan) return;
+    if (plan->chunk) (void)hipGraphExecDestroy(plan->chunk);
+    if (plan->host_state) (void)hipHostFree(plan->host_state);
+    delete plan;
+}
+
+fwils_status fwils_workspace_size(fwils_plan plan, size_t* bytes) {
+    FW_TRY(check_plan(plan, false));
+    if (!bytes) {
+        set_error("null output");
+        return FWILS_EINVAL;
+    }
+    *bytes = plan->ws_bytes;
+    return FWILS_OK;
+}
+
+fwils_status fwils_field_elems(fwils_plan plan, int64_t* elems) {
+    FW_TRY(check_plan(plan, false));
+    if (!elems) {
+        set_error("null output");
+        return FWILS_EINVAL;
+    }
+    *elems = (int64_t)plan->total_field;
+    return FWILS_OK;
+}
+
+fwils_status fwils_set_stream(fwils_plan plan, void* hip_stream) {
+    FW_TRY(check_plan(plan, false));
+    plan->stream = (hipStream_t)hip_stream;
+    return FWILS_OK;
+}
+
+fwils_status fwils_set_workspace(fwils_plan plan, void* dev, size_t bytes) {
+    FW_TRY(check_plan(plan, false));
+    if (!dev || bytes < plan->ws_bytes || ((uintptr_t)dev & 255) != 0) {
+        set_error("set_workspace: need %zu bytes, 256-byte aligned (got %zu)", plan->ws_bytes, bytes);
+        return FWILS_ENOMEM;
+    }
+    if (plan->chunk) {
+        (void)hipGraphExecDestroy(plan->chunk);
+        plan->chunk = nullptr;
+    }
+    if (!plan->host_state) {
+        FW_HIP(hipHostMalloc((void**)&plan->host_state, plan->total_sys * sizeof(SysState),
+                             hipHostMallocDefault));
+    }
+    char* w = (char*)dev;
+    plan->ws = w;
+    plan->tw = (float2*)(w + plan->off_tw);
+    plan->state = (SysState*)(w + plan->off_state);
+    plan->partV = (double*)(w + plan->off_part);
+    plan->partT = (double*)(w + plan->off_part + plan->part_bytes);
+    plan->partXR = (double*)(w + plan->off_part + 2 * plan->part_bytes);
+    plan->partB = (double*)(w + plan->off_part + 3 * plan->part_bytes);
+    plan->maps = (float*)(w + plan->off_maps);
+    plan->rec = (int32_t*)(w + plan->off_rec);
+    plan->src_i = (int32_t*)(w + plan->off_src);
+    plan->src_f = (double*)(w + plan->off_src + align256(plan->total_sys * 2 * sizeof(int32_t)));
+    float2** vecs[9] = {&plan->x, &plan->r, &plan->rhat, &plan->p, &plan->v,
+                        &plan->s, &plan->t, &plan->tmp, &plan->rhs};
+    const size_t vb = align256(plan->total_field * sizeof(float2));
+    for (int i = 0; i < 9; ++i) *vecs[i] = (float2*)(w + plan->off_vec + i * vb);
+    std::vector<float2> tw(twiddle_table_elems());
+    twiddle_table_fill(tw.data());
+    FW_HIP(hipMemcpy(plan->tw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice));
+    FW_HIP(hipMemset(plan->maps, 0, plan->maps_floats * sizeof(float)));
+    FW_HIP(hipMemset(plan->state, 0, plan->total_sys * sizeof(SysState)));
+    FW_HIP(hipDeviceSynchronize());
+    return FWILS_OK;
+}
+
+fwils_status fwils_set_contrast(fwils_plan plan, int32_t iprob, const float* maps) {
+    FW_TRY(check_plan(plan));
+    if (iprob < 0 || iprob >= (int)plan->probs.size() || !maps) {
+        set_error("set_contrast: bad problem index or null maps");
+        return FWILS_EINVAL;
+    }
+    const ProbHost& P = plan->probs[iprob];
+    FW_HIP(hipMemcpyAsync(maps_at(plan, P), maps, (size_t)5 * P.p.nz * P.p.nx * sizeof(float),
+                          hipMemcpyDeviceToDevice, plan->stream));
+    return FWILS_OK;
+}
+
+fwils_status fwils_set_receivers(fwils_plan plan, int32_t iprob, const int32_t* rec_ixz, int32_t nrec) {
+    FW_TRY(check_plan(plan));
+    if (iprob < 0 || iprob >= (int)plan->probs.size() || !rec_ixz || nrec < 1 || nrec > kMaxRec) {
+        set_error("set_receivers: bad problem index, null pointer or nrec out of 1..%d", kMaxRec);
+        return FWILS_EINVAL;
+    }
+    ProbHost& P = plan->probs[iprob];
+    for (int r = 0; r < nrec; ++r) {
+        if (rec_ixz[2 * r] < 0 || rec_ixz[2 * r] >= P.p.nx || rec_ixz[2 * r + 1] < 0 ||
+            rec_ixz[2 * r + 1] >= P.p.nz) {
+            set_error("set_receivers: receiver %d at (%d, %d) outside the %dx%d grid", r, rec_ixz[2 * r],
+                      rec_ixz[2 * r + 1], P.p.nx, P.p.nz);
+            return FWILS_EINVAL;
+        }
+    }
+    FW_HIP(hipStreamSynchronize(plan->stream));
+    FW_HIP(hipMemcpy(plan->rec + (size_t)iprob * kMaxRec * 2, rec_ixz, (size_t)nrec * 2 * sizeof(int32_t),
+                     hipMemcpyHostToDevice));
+    P.nrec = nrec;
+    size_t doff = 0;
+    for (ProbHost& Q : plan->probs) {
+        Q.data_off = doff;
+        doff += (size_t)Q.p.nsys * Q.nrec * 2;
+    }
+    return FWILS_OK;
+}
+
+fwils_status fwils_incident(fwils_plan plan, const int32_t* src_ixz, const double* src_f, void* u0) {
+    FW_TRY(check_plan(plan));
+    if (!src_ixz || !src_f || !u0) {
+        set_error("incident: null pointer");
+        return FWILS_EINVAL;
+    }
+    for (const ProbHost& P : plan->probs) {
+        for (int sy = 0; sy < P.p.nsys; ++sy) {
+            const size_t k = P.sys_off + sy;
+            const int ix = src_ixz[2 * k], iz = src_ixz[2 * k + 1];
+            if (ix < 0 || ix >= P.p.nx || iz < 0 || iz >= P.p.nz || !std::isfinite(src_f[2 * k]) ||
+                !std::isfinite(src_f[2 * k + 1])) {
+                set_error("incident: source %zu at (%d, %d) outside the grid or non-finite force", k, ix, iz);
+                return FWILS_EINVAL;
+            }
+        }
+    }
+    hipStream_t s = plan->stream;
+    FW_HIP(hipStreamSynchronize(s));
+    FW_HIP(hipMemcpy(plan->src_i, src_ixz, plan->total_sys * 2 * sizeof(int32_t), hipMemcpyHostToDevice));
+    FW_HIP(hipMemcpy(plan->src_f, src_f, plan->total_sys * 2 * sizeof(double), hipMemcpyHostToDevice));
+    for (const ProbHost& P : plan->probs) {
+        float2* f = at(plan->rhs, P);
+        FW_HIP(launch_zero(f, (size_t)P.p.nsys * P.n_per_sys, s));
+        FW_HIP(launch_point_sources(f, plan->src_i + 2 * P.sys_off, plan->src_f + 2 * P.sys_off, P.dev, s));
+        FW_HIP(conv_problem(plan, P, f, static_cast<float2*>(u0) + P.field_off));
+    }
+    return FWILS_OK;
+}
+
+fwils_status fwils_body_force(fwils_plan plan, const void* u, void* b) {
+    FW_TRY(check_plan(plan));
+    FW_TRY(check_field_ptrs({u, b}));
+    for (const ProbHost& P : plan->probs)
+        FW_HIP(launch_body_force(at(u, P), static_cast<float2*>(b) + P.field_off, maps_at(plan, P), P.dev,
+                                 nullptr, plan->stream));
+    return FWILS_OK;
+}
+
+fwils_status fwils_convolve(fwils_plan plan, const void* f, void* out) {
+    FW_TRY(check_plan(plan));
+    FW_TRY(check_field_ptrs({f, out}));
+    for (const ProbHost& P : plan->probs)
+        FW_HIP(conv_problem(plan, P, at(f, P), static_cast<float2*>(out) + P.field_off));
+    return FWILS_OK;
+}
+
+fwils_status fwils_apply(fwils_plan plan, const void* u, void* Au) {
+    FW_TRY(check_plan(plan));
+    FW_TRY(check_field_ptrs({u, Au}));
+    if (u == Au) {
+        set_error("apply: u and Au must not alias");
+        return FWILS_EINVAL;
+    }
+    for (const ProbHost& P : plan->probs)
+        FW_HIP(matvec(plan, P, P.dev, at(u, P), at(plan->tmp, P), maps_at(plan, P), EPI_APPLY, nullptr,
+                      static_cast<float2*>(Au) + P.field_off, nullptr, nullptr, plan->stream));
+    return FWILS_OK;
+}
+
+fwils_status fwils_solve(fwils_plan plan, const void* rhs, void* x, double rtol, int32_t maxit,
+                         int32_t* iters, double* relres, uint32_t flags) {
+    FW_TRY(check_plan(plan));
+    FW_TRY(check_field_ptrs({rhs, x}));
+    if (!(rtol > 0) || maxit < 1 || (flags & ~(FWILS_SOLVE_X0 | FWILS_SOLVE_PLAIN | FWILS_SOLVE_NOGRAPH))) {
+        set_error("solve: need rtol > 0, maxit >= 1 and known flags");
+        return FWILS_EINVAL;
+    }
+    hipStream_t s = plan->stream;
+    const bool x0 = (flags & FWILS_SOLVE_X0) != 0;
+    if (x0) FW_HIP(launch_copy(static_cast<const float2*>(x), plan->x, plan->total_field, s));
+    fwils_status st = solve_ws(plan, static_cast<const float2*>(rhs), x0, rtol, maxit, iters, relres, flags);
+    if (st == FWILS_EDEVICE) return st;
+    FW_HIP(launch_copy(plan->x, static_cast<float2*>(x), plan->total_field, s));
+    FW_HIP(hipStreamSynchronize(s));
+    return st;
+}
+
+fwils_status fwils_frechet(fwils_plan plan, const void* ub, const float* const* dm, void* d,
+                           double rtol, int32_t maxit) {
+    FW_TRY(check_plan(plan));
+    FW_TRY(check_field_ptrs({ub, dm, d}));
+    for (size_t i = 0; i < plan->probs.size(); ++i) {
+        if (!dm[i] || plan->probs[i].nrec < 1) {
+            set_error("frechet: problem %zu has a null dm pointer or no receivers", i);
+            return FWILS_EINVAL;
+        }
+    }
+    if (!(rtol > 0) || maxit < 1) {
+        set_error("frechet: need rtol > 0 and maxit >= 1");
+        return FWILS_EINVAL;
+    }
+    hipStream_t s = plan->stream;
+    for (size_t i = 0; i < plan->probs.size(); ++i) {
+        const ProbHost& P = plan->probs[i];
+        // virtual source P_b(dm) (same stencil as the contrast, with u^b and dm)
+        FW_HIP(launch_body_force(at(ub, P), at(plan->s, P), dm[i], P.dev, nullptr, s));
+        FW_HIP(conv_problem(plan, P, at(plan->s, P), at(plan->rhs, P)));
+    }
+    fwils_status st = solve_ws(plan, plan->rhs, false, rtol, maxit, nullptr, nullptr, 0);
+    if (st == FWILS_EDEVICE) return st;
+    for (const ProbHost& P : plan->probs)
+        FW_HIP(launch_gather(at(plan->x, P), static_cast<float2*>(d) + P.data_off,
+                             plan->rec + (size_t)(&P - plan->probs.data()) * kMaxRec * 2, P.nrec, P.dev, s));
+    FW_HIP(hipStreamSynchronize(s));
+    return st;
+}
+
+fwils_status fwils_adjoint(fwils_plan plan, const void* ub, const void* r, void* const* g,
+                           uint32_t flags, double rtol, int32_t maxit) {
+    FW_TRY(check_plan(plan));
+    FW_TRY(check_field_ptrs({ub, r, g}));
+    for (size_t i = 0; i < plan->probs.size(); ++i) {
+        if (!g[i] || plan->probs[i].nrec < 1) {
+            set_error("adjoint: problem %zu has a null g pointer or no receivers", i);
+            return FWILS_EINVAL;
+        }
+    }
+    if (!(rtol > 0) || maxit < 1 || (flags & ~FWILS_ADJ_ACCUMULATE)) {
+        set_error("adjoint: need rtol > 0, maxit >= 1 and known flags");
+        return FWILS_EINVAL;
+    }
+    hipStream_t s = plan->stream;
+    for (size_t i = 0; i < plan->probs.size(); ++i) {
+        const ProbHost& P = plan->probs[i];
+        float2* f = at(plan->s, P);
+        FW_HIP(launch_zero(f, (size_t)P.p.nsys * P.n_per_sys, s));
+        FW_HIP(launch_scatter_conj(static_cast<const float2*>(r) + P.data_off, f,
+                                   plan->rec + i * kMaxRec * 2, P.nrec, P.dev, s));
+        FW_HIP(conv_problem(plan, P, f, at(plan->rhs, P)));
+    }
+    fwils_status st = solve_ws(plan, plan->rhs, false, rtol, maxit, nullptr, nullptr, 0);
+    if (st == FWILS_EDEVICE) return st;
+    for (size_t i = 0; i < plan->probs.size(); ++i) {
+        const ProbHost& P = plan->probs[i];
+        FW_HIP(launch_correlate(at(plan->x, P), at(ub, P), static_cast<float2*>(g[i]), P.dev,
+                                (flags & FWILS_ADJ_ACCUMULATE) != 0, s));
+    }
+    FW_HIP(hipStreamSynchronize(s));
+    return st;
+}
+
+fwils_status fwils_fft2(fwils_plan plan, int32_t iprob, const void* in, void* out, int32_t inverse) {
+    FW_TRY(check_plan(plan));
+    FW_TRY(check_field_ptrs({in, out}));
+    if (iprob < 0 || iprob >= (int)plan->probs.size()) {
+        set_error("fft2: bad problem index");
+        return FWILS_EINVAL;
+    }
+    const ProbHost& P = plan->probs[iprob];
+    const int rows = P.p.nsys * 2 * P.p.nz;
+    const float2* src = static_cast<const float2*>(in);
+    float2* dst = static_cast<float2*>(out);
+    hipStream_t s = plan->stream;
+    if (!inverse) {
+        FW_HIP(launch_rows_fwd(P.p.nx, src, dst, rows, 2 * P.p.nz, nullptr, plan->tw, s));
+        FW_HIP(launch_cols(COL_FWD, dst, P.dev, nullptr, plan->tw, s));
+    } else {
+        FW_HIP(launch_rows_inv(P.p.nx, EPI_STORE, src, nullptr, nullptr, dst, nullptr, rows, 2 * P.p.nz,
+                               nullptr, plan->tw, s));
+        FW_HIP(launch_cols(COL_INV, dst, P.dev, nullptr, plan->tw, s));
+    }
+    return FWILS_OK;
+}
+
+}  // extern "C"

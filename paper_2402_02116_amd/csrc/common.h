@@ -1,0 +1,118 @@
+// Shared device-side definitions for the fwils HIP kernels (gfx950).
+//
+// Complex numbers are float2 (re, im).  Fields are [nsys][2][nz][nx] complex64
+// with x fastest; maps are [5][nz][nx] fp32 in the order
+// (dC11, dC13, dC33, dC55, drho).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fw {
+
+// ---------------------------------------------------------------- complex --
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+// multiply by -i (forward transform) or +i (inverse transform)
+template <bool INV>
+__device__ __forceinline__ float2 mul_mi(float2 z) {
+    return INV ? make_float2(-z.y, z.x) : make_float2(z.y, -z.x);
+}
+
+struct dcomplex { double re, im; };
+
+// --------------------------------------------------------- problem consts --
+// Per-problem constants, passed by value to every kernel of that problem.
+struct ProbDev {
+    int nx, nz, nsys, symbol;
+    float inv4dx2;        // 1 / (4 dx^2): both central differences of the stencil
+    float2 w2;            // w~^2 = (2 pi f (1 + i eta))^2
+    // Green's symbol in units of rho0 w^2 (w real): Gamma' = Gamma / (rho0 w^2)
+    float gc11, gc33, gc55, gc1355;   // C11, C33, C55, C13 + C55 over rho0 w^2
+    float2 ga;            // (1 + i eta)^2 = rho0 w~^2 / (rho0 w^2)
+    float gscale;         // 1 / (rho0 w^2 nx nz): Green's scale and IFFT normalisation
+    float dkx, dkz;       // 2 pi / (nx dx), 2 pi / (nz dx)
+    float dx;
+};
+
+// --------------------------------------------------------- solver state ---
+enum SysStatus : int {
+    ST_RUNNING = 0,
+    ST_CONVERGED = 1,
+    ST_MAXIT = 2,
+    ST_BREAKDOWN = 3,
+    ST_NONFINITE = 4,
+};
+
+// Per-system BiCGSTAB scalars (FP64), one struct per system.
+struct SysState {
+    double rho_re[2], rho_im[2];   // rho_i by iteration parity
+    double alpha_re, alpha_im;     // alpha_i of the current iteration
+    double omega_re, omega_im;     // omega of the last completed iteration
+    double bnorm2;                 // ||b||^2
+    double tol2;                   // rtol^2 ||b||^2
+    double rnorm2;                 // last recursive ||r||^2 seen by a check
+    int iter;                      // completed iterations
+    int status;                    // SysStatus
+    int maxit;
+    int pad;
+};
+
+// ------------------------------------------------------ block reductions --
+// Sum NV doubles over a block of NT threads (NT a multiple of 64), in a fixed
+// order: wave shuffles, then wave partials in index order.  Every thread
+// receives the result.  smem needs NV * NT / 64 doubles.
+template <int NV, int NT>
+__device__ __forceinline__ void block_allreduce(double (&acc)[NV], double* smem) {
+    static_assert(NT % 64 == 0, "block must be whole waves");
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) acc[k] += __shfl_xor(acc[k], off, 64);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) smem[wave * NV + k] = acc[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < NT / 64; ++w) s += smem[w * NV + k];
+        acc[k] = s;
+    }
+    __syncthreads();
+}
+
+// Sum np partial records of NV doubles each (record i at part[i * NV]) with a
+// fixed order; every thread of the block receives the totals.
+template <int NV, int NT>
+__device__ __forceinline__ void sum_partials(const double* __restrict__ part, int np,
+                                             double (&res)[NV], double* smem) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) res[k] = 0.0;
+    for (int i = threadIdx.x; i < np; i += NT) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) res[k] += part[(size_t)i * NV + k];
+    }
+    block_allreduce<NV, NT>(res, smem);
+}
+
+// Workgroup ids are dealt to the 8 XCDs round-robin (id % 8).  Remap so that
+// each XCD works on one contiguous range of logical blocks: neighbouring
+// tiles, which share cache lines and halos, then share an L2.
+__device__ __forceinline__ int xcd_remap(int bid, int nblk) {
+    const int full = nblk & ~7;
+    if (bid >= full) return bid;
+    return (bid & 7) * (full >> 3) + (bid >> 3);
+}
+
+}  // namespace fw

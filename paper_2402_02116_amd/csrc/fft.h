@@ -1,0 +1,250 @@
+// Stockham complex FFT for one workgroup, staged through LDS (gfx950).
+//
+// A length-N transform is done by T = N / P threads; thread t holds the P
+// points at positions t + T*m (m = 0..P-1) in registers.  Every radix-R pass
+// reads exactly those positions: butterfly j = t + T*b (b < P/R) takes the
+// points j + r*N/R = t + T*(b + r*P/R).  It writes its R outputs to the
+// autosort positions (j / Ns) * Ns * R + j % Ns + r * Ns, where Ns is the
+// product of the radices already applied; after the last pass (Ns * R = N)
+// those positions are again t + T*m, so the result stays in registers.  Data
+// is therefore loaded from and stored to global memory in coalesced
+// t-fastest order, and only the passes in between go through LDS.
+//
+// The radix sequence is chosen at compile time from {16, 8, 4, 2, 3}; every
+// radix must divide P.  Twiddles come from a length-N table
+// tw[m] = exp(-2 pi i m / N) (double-rounded on the host); the inverse uses
+// conjugates.  No normalisation is applied in either direction.
+#pragma once
+
+#include "common.h"
+
+namespace fw {
+
+struct RadixPlan {
+    int np;
+    int r[16];
+};
+
+constexpr RadixPlan radix_plan(int N, int P) {
+    RadixPlan pl{0, {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0}};
+    const int cand[5] = {16, 8, 4, 2, 3};
+    int rem = N;
+    while (rem > 1) {
+        int pick = 0;
+        for (int i = 0; i < 5; ++i) {
+            if (P % cand[i] == 0 && rem % cand[i] == 0) { pick = cand[i]; break; }
+        }
+        if (pick == 0 || pl.np == 16) { pl.np = -1; return pl; }
+        pl.r[pl.np++] = pick;
+        rem /= pick;
+    }
+    return pl;
+}
+
+template <int N, int P>
+struct FftShape {
+    static_assert(N % P == 0, "P must divide N");
+    static constexpr int T = N / P;
+    static constexpr RadixPlan plan = radix_plan(N, P);
+    static_assert(plan.np > 0, "no radix sequence for (N, P)");
+    static constexpr int NP = plan.np;
+    static constexpr int ns_before(int i) {
+        int s = 1;
+        for (int k = 0; k < i; ++k) s *= plan.r[k];
+        return s;
+    }
+};
+
+// --------------------------------------------------------- small DFTs -----
+template <bool INV>
+__device__ __forceinline__ void dft2(float2& a, float2& b) {
+    const float2 t = a;
+    a = cadd(t, b);
+    b = csub(t, b);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft4(float2& x0, float2& x1, float2& x2, float2& x3) {
+    const float2 a = cadd(x0, x2), b = csub(x0, x2);
+    const float2 c = cadd(x1, x3), d = mul_mi<INV>(csub(x1, x3));
+    x0 = cadd(a, c);
+    x2 = csub(a, c);
+    x1 = cadd(b, d);
+    x3 = csub(b, d);
+}
+
+// multiply by W_M^e = exp(-+ 2 pi i e / M) for compile-time e, M in {8, 16}
+template <bool INV, int M, int E>
+__device__ __forceinline__ float2 twc(float2 z) {
+    constexpr int e = ((E % M) + M) % M;
+    constexpr int e16 = e * (16 / M);
+    if constexpr (e16 == 0) return z;
+    else if constexpr (e16 == 4) return mul_mi<INV>(z);
+    else if constexpr (e16 == 8) return make_float2(-z.x, -z.y);
+    else if constexpr (e16 == 12) return mul_mi<!INV>(z);
+    else {
+        constexpr double C[16] = {1.0, 0.92387953251128674, 0.70710678118654752, 0.38268343236508978,
+                                  0.0, -0.38268343236508978, -0.70710678118654752, -0.92387953251128674,
+                                  -1.0, -0.92387953251128674, -0.70710678118654752, -0.38268343236508978,
+                                  0.0, 0.38268343236508978, 0.70710678118654752, 0.92387953251128674};
+        constexpr double S[16] = {0.0, 0.38268343236508978, 0.70710678118654752, 0.92387953251128674,
+                                  1.0, 0.92387953251128674, 0.70710678118654752, 0.38268343236508978,
+                                  0.0, -0.38268343236508978, -0.70710678118654752, -0.92387953251128674,
+                                  -1.0, -0.92387953251128674, -0.70710678118654752, -0.38268343236508978};
+        constexpr float c = (float)C[e16];
+        constexpr float s = INV ? (float)S[e16] : -(float)S[e16];   // W = c + i s
+        return make_float2(z.x * c - z.y * s, z.x * s + z.y * c);
+    }
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft8(float2 (&x)[8]) {
+    // even / odd halves, then combine with W_8^k
+    dft4<INV>(x[0], x[2], x[4], x[6]);
+    dft4<INV>(x[1], x[3], x[5], x[7]);
+    float2 y[8];
+    y[0] = cadd(x[0], x[1]);
+    y[4] = csub(x[0], x[1]);
+    const float2 o1 = twc<INV, 8, 1>(x[3]);
+    y[1] = cadd(x[2], o1);
+    y[5] = csub(x[2], o1);
+    const float2 o2 = twc<INV, 8, 2>(x[5]);
+    y[2] = cadd(x[4], o2);
+    y[6] = csub(x[4], o2);
+    const float2 o3 = twc<INV, 8, 3>(x[7]);
+    y[3] = cadd(x[6], o3);
+    y[7] = csub(x[6], o3);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[k] = y[k];
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft16(float2 (&x)[16]) {
+    // n = n1 + 4 n2: DFT4 over n2, twiddle W16^(n1 k1), DFT4 over n1; out k1 + 4 k2
+    dft4<INV>(x[0], x[4], x[8], x[12]);
+    dft4<INV>(x[1], x[5], x[9], x[13]);
+    dft4<INV>(x[2], x[6], x[10], x[14]);
+    dft4<INV>(x[3], x[7], x[11], x[15]);
+    // x[n1 + 4 k1] now holds Z_{n1}[k1]
+    x[5] = twc<INV, 16, 1>(x[5]);
+    x[9] = twc<INV, 16, 2>(x[9]);
+    x[13] = twc<INV, 16, 3>(x[13]);
+    x[6] = twc<INV, 16, 2>(x[6]);
+    x[10] = twc<INV, 16, 4>(x[10]);
+    x[14] = twc<INV, 16, 6>(x[14]);
+    x[7] = twc<INV, 16, 3>(x[7]);
+    x[11] = twc<INV, 16, 6>(x[11]);
+    x[15] = twc<INV, 16, 9>(x[15]);
+    float2 y[16];
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+        float2 a = x[4 * k1 + 0], b = x[4 * k1 + 1], c = x[4 * k1 + 2], d = x[4 * k1 + 3];
+        dft4<INV>(a, b, c, d);
+        y[k1 + 0] = a;
+        y[k1 + 4] = b;
+        y[k1 + 8] = c;
+        y[k1 + 12] = d;
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) x[k] = y[k];
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft3(float2& x0, float2& x1, float2& x2) {
+    const float h = 0.86602540378443865f;   // sqrt(3) / 2
+    const float2 t1 = cadd(x1, x2);
+    const float2 m = make_float2(x0.x - 0.5f * t1.x, x0.y - 0.5f * t1.y);
+    const float2 d = mul_mi<INV>(cscale(csub(x1, x2), h));
+    x0 = cadd(x0, t1);
+    x1 = cadd(m, d);
+    x2 = csub(m, d);
+}
+
+template <int R, bool INV>
+__device__ __forceinline__ void dft(float2 (&x)[R]) {
+    if constexpr (R == 2) dft2<INV>(x[0], x[1]);
+    else if constexpr (R == 3) dft3<INV>(x[0], x[1], x[2]);
+    else if constexpr (R == 4) dft4<INV>(x[0], x[1], x[2], x[3]);
+    else if constexpr (R == 8) dft8<INV>(x);
+    else if constexpr (R == 16) dft16<INV>(x);
+    else static_assert(R == 2, "unsupported radix");
+}
+
+// ----------------------------------------------------------- one pass -----
+// Pass I of an N-point transform for NF independent transforms held by this
+// thread (v[f][m] at position t + T*m).  Non-final passes write to LDS through
+// the accessor `lds(f, pos)`; the final pass leaves its outputs in v.
+template <int N, int P, int I, bool INV, int NF, class Lds>
+__device__ __forceinline__ void fft_pass(float2 (&v)[NF][P], int t,
+                                         const float2* __restrict__ tw, const Lds& lds) {
+    using S = FftShape<N, P>;
+    constexpr int R = S::plan.r[I];
+    constexpr int NS = S::ns_before(I);
+    constexpr int NB = P / R;
+    constexpr bool LAST = (I == S::NP - 1);
+    constexpr int TWS = N / (NS * R);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int j = t + S::T * b;
+        const int k = j % NS;
+        float2 w[R];
+        if constexpr (NS > 1) {
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                const float2 tt = tw[k * r * TWS];
+                w[r] = INV ? cconj(tt) : tt;
+            }
+        }
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            float2 x[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) x[r] = v[f][b + r * NB];
+            if constexpr (NS > 1) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) x[r] = cmul(x[r], w[r]);
+            }
+            dft<R, INV>(x);
+            if constexpr (LAST) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[f][b + r * NB] = x[r];
+            } else {
+                const int base = (j / NS) * NS * R + k;
+#pragma unroll
+                for (int r = 0; r < R; ++r) lds(f, base + r * NS) = x[r];
+            }
+        }
+    }
+}
+
+template <int N, int P, bool INV, int NF, int I, class Lds>
+__device__ __forceinline__ void fft_from(float2 (&v)[NF][P], int t,
+                                         const float2* __restrict__ tw, const Lds& lds) {
+    using S = FftShape<N, P>;
+    fft_pass<N, P, I, INV, NF>(v, t, tw, lds);
+    if constexpr (I + 1 < S::NP) {
+        __syncthreads();
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+#pragma unroll
+            for (int m = 0; m < P; ++m) v[f][m] = lds(f, t + S::T * m);
+        }
+        __syncthreads();
+        fft_from<N, P, INV, NF, I + 1>(v, t, tw, lds);
+    }
+}
+
+// Full transform.  Every thread of the workgroup must call this (barriers).
+template <int N, int P, bool INV, int NF, class Lds>
+__device__ __forceinline__ void fft_run(float2 (&v)[NF][P], int t,
+                                        const float2* __restrict__ tw, const Lds& lds) {
+    fft_from<N, P, INV, NF, 0>(v, t, tw, lds);
+}
+
+// Padded LDS index: one spare slot every 16 elements keeps the stride-R
+// autosort writes of the first passes off a single bank.
+__device__ __forceinline__ int lds_pad(int pos) { return pos + (pos >> 4); }
+template <int N>
+struct PaddedLen { static constexpr int value = N + N / 16 + 1; };
+
+}  // namespace fw

@@ -1,0 +1,390 @@
+// FFT-pass kernels of the LS matvec (eqs. A and FFT):
+//   k_rows  - forward row transforms (after the contrast stencil), and
+//             inverse row transforms fused with the LS / BiCGSTAB epilogues
+//             and their FP64 partial inner products;
+//   k_cols  - column transforms fused with the multiplication by the
+//             wavenumber-domain Green's tensor G_hat(k), in place.
+#include <algorithm>
+#include <numeric>
+
+#include "fft.h"
+#include "launch.h"
+
+namespace fw {
+
+// ------------------------------------------------------------ sizes ------
+#define FW_FOR_EACH_SIZE(X) \
+    X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024) X(1536) X(2048)
+
+static const int kSizes[] = {16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048};
+
+// Points per thread: 16 for powers of two (radix-16 passes), 12 for 3 * 2^k.
+constexpr int points_per_thread(int n) { return (n % 3 == 0) ? 12 : 16; }
+
+bool fft_size_supported(int n) {
+    for (int s : kSizes)
+        if (s == n) return true;
+    return false;
+}
+
+size_t twiddle_table_elems() {
+    size_t t = 0;
+    for (int s : kSizes) t += (size_t)s;
+    return t;
+}
+
+size_t twiddle_offset(int n) {
+    size_t t = 0;
+    for (int s : kSizes) {
+        if (s == n) return t;
+        t += (size_t)s;
+    }
+    return (size_t)-1;
+}
+
+void twiddle_table_fill(float2* host) {
+    size_t off = 0;
+    for (int s : kSizes) {
+        for (int m = 0; m < s; ++m) {
+            // exp(-2 pi i m / s); angle reduced in double
+            const double a = -2.0 * 3.14159265358979323846 * (double)m / (double)s;
+            host[off + m] = make_float2((float)cos(a), (float)sin(a));
+        }
+        off += (size_t)s;
+    }
+}
+
+static int pow2_floor(int x) {
+    int p = 1;
+    while (p * 2 <= x) p *= 2;
+    return p;
+}
+
+RowGeom row_geom(int n, int rows_per_sys) {
+    const int T = n / points_per_thread(n);
+    int F = std::gcd(256 / T, rows_per_sys);
+    RowGeom g;
+    g.F = F;
+    g.threads = ((F * T + 63) / 64) * 64;
+    g.blocks_per_sys = rows_per_sys / F;
+    return g;
+}
+
+static int padded_len(int n) { return n + n / 16 + 1; }
+
+ColGeom col_geom(int nz, int nx) {
+    const int T = nz / points_per_thread(nz);
+    const int lds_w = 65536 / (2 * padded_len(nz) * (int)sizeof(float2));
+    int W = pow2_floor(std::max(1, std::min(256 / T, lds_w)));
+    while (W > 1 && nx % W != 0) W /= 2;
+    ColGeom g;
+    g.W = W;
+    g.threads = ((W * T + 63) / 64) * 64;
+    return g;
+}
+
+// ------------------------------------------------------- block reduce ----
+// Runtime block size (a multiple of 64, at most 256): fixed-order sum of
+// NV doubles; thread 0 receives the total.
+template <int NV>
+__device__ __forceinline__ void block_sum_to0(double (&acc)[NV], double* smem) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) acc[k] += __shfl_xor(acc[k], off, 64);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) smem[wave * NV + k] = acc[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double s = 0.0;
+            for (int w = 0; w < nw; ++w) s += smem[w * NV + k];
+            acc[k] = s;
+        }
+    }
+}
+
+// --------------------------------------------------------- row kernel ----
+struct RowLds {
+    float2* p;
+    __device__ __forceinline__ float2& operator()(int, int pos) const { return p[lds_pad(pos)]; }
+};
+
+template <int N, bool INV, int EPI>
+// `in` and `out` may be the same array (in-place forward pass): every block
+// reads all of its rows before its barriers and writes them after.
+__global__ __launch_bounds__(256) void k_rows(const float2* in, float2* out,
+                                              const float2* __restrict__ u,
+                                              const float2* __restrict__ aux,
+                                              double* __restrict__ partials, int nrows,
+                                              int rows_per_sys, int F,
+                                              const SysState* __restrict__ st,
+                                              const float2* __restrict__ tw) {
+    constexpr int P = points_per_thread(N);
+    using S = FftShape<N, P>;
+    constexpr int T = S::T;
+    constexpr int PL = PaddedLen<N>::value;
+    extern __shared__ float2 lds_dyn[];
+    __shared__ double red[4 * kPartialNV];
+
+    const int tid = threadIdx.x;
+    const int q = tid / T, t = tid % T;
+    const int row0 = blockIdx.x * F;
+    const int sys = row0 / rows_per_sys;
+    if (st != nullptr && st[sys].status != ST_RUNNING) return;
+    const int row = row0 + q;
+    const bool active = (q < F) && (row < nrows);
+
+    float2 v[1][P];
+    if (active) {
+        const float2* src = in + (size_t)row * N;
+#pragma unroll
+        for (int m = 0; m < P; ++m) v[0][m] = src[t + T * m];
+    } else {
+#pragma unroll
+        for (int m = 0; m < P; ++m) v[0][m] = make_float2(0.f, 0.f);
+    }
+    // idle threads (block padded to whole waves) work in a dummy slot F
+    RowLds lds{lds_dyn + (size_t)(q < F ? q : F) * PL};
+    fft_run<N, P, INV, 1>(v, t, tw, lds);
+
+    double acc[kPartialNV] = {0.0, 0.0, 0.0, 0.0};
+    if (active) {
+        const size_t base = (size_t)row * N;
+#pragma unroll
+        for (int m = 0; m < P; ++m) {
+            const size_t i = base + t + T * m;
+            const float2 y = v[0][m];
+            if constexpr (EPI == EPI_STORE) {
+                out[i] = y;
+            } else {
+                const float2 uu = u[i];
+                const float2 o = csub(uu, y);
+                if constexpr (EPI == EPI_APPLY) {
+                    out[i] = o;
+                } else if constexpr (EPI == EPI_BICG_V) {
+                    out[i] = o;
+                    const float2 a = aux[i];
+                    acc[0] += (double)a.x * o.x + (double)a.y * o.y;
+                    acc[1] += (double)a.x * o.y - (double)a.y * o.x;
+                } else if constexpr (EPI == EPI_BICG_T) {
+                    out[i] = o;
+                    acc[0] += (double)o.x * uu.x + (double)o.y * uu.y;
+                    acc[1] += (double)o.x * uu.y - (double)o.y * uu.x;
+                    acc[2] += (double)o.x * o.x + (double)o.y * o.y;
+                } else if constexpr (EPI == EPI_TRUERES) {
+                    const float2 b = aux[i];
+                    const float2 rr = csub(b, o);
+                    out[i] = rr;
+                    acc[0] += (double)rr.x * rr.x + (double)rr.y * rr.y;
+                }
+            }
+        }
+    }
+    if constexpr (EPI >= EPI_BICG_V) {
+        block_sum_to0<kPartialNV>(acc, red);
+        if (tid == 0) {
+            const int nb = rows_per_sys / F;
+            const int bi = (row0 % rows_per_sys) / F;
+            double* dst = partials + ((size_t)sys * nb + bi) * kPartialNV;
+#pragma unroll
+            for (int k = 0; k < kPartialNV; ++k) dst[k] = acc[k];
+        }
+    }
+}
+
+// ------------------------------------------------------ column kernel ----
+struct ColLds {
+    float2* p;
+    int W, c, dummy;     // dummy: idle thread -> private scratch region
+    int PL;
+    __device__ __forceinline__ float2& operator()(int f, int pos) const {
+        const int e = f * PL + lds_pad(pos);
+        return dummy ? p[e] : p[(size_t)e * W + c];
+    }
+};
+
+// Signed FFT index of i on an n-point axis (numpy fftfreq order).
+__device__ __forceinline__ int fft_signed(int i, int n) { return (i < (n + 1) / 2) ? i : i - n; }
+
+template <int N, int MODE>
+__global__ __launch_bounds__(256) void k_cols(float2* __restrict__ data, ProbDev pd, int W,
+                                              const SysState* __restrict__ st,
+                                              const float2* __restrict__ tw) {
+    constexpr int P = points_per_thread(N);
+    using S = FftShape<N, P>;
+    constexpr int T = S::T;
+    constexpr int PL = PaddedLen<N>::value;
+    extern __shared__ float2 lds_dyn[];
+
+    const int nx = pd.nx;
+    const int tid = threadIdx.x;
+    const int c = tid % W, t = tid / W;
+    const int ntile = nx / W;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int sys = blk / ntile;
+    const int x0 = (blk % ntile) * W;
+    if (st != nullptr && st[sys].status != ST_RUNNING) return;
+    const bool active = t < T;
+
+    float2* base = data + (size_t)sys * 2 * N * nx + x0 + c;
+    const size_t plane = (size_t)N * nx;
+    float2 v[2][P];
+    if (active) {
+#pragma unroll
+        for (int f = 0; f < 2; ++f)
+#pragma unroll
+            for (int m = 0; m < P; ++m) v[f][m] = base[f * plane + (size_t)(t + T * m) * nx];
+    } else {
+#pragma unroll
+        for (int f = 0; f < 2; ++f)
+#pragma unroll
+            for (int m = 0; m < P; ++m) v[f][m] = make_float2(0.f, 0.f);
+    }
+    ColLds lds{active ? lds_dyn : lds_dyn + (size_t)2 * PL * W, W, c, active ? 0 : 1, PL};
+    const int tt = active ? t : 0;
+
+    if constexpr (MODE != COL_INV) fft_run<N, P, false, 2>(v, tt, tw, lds);
+    if constexpr (MODE == COL_GREEN) {
+        // u_hat = G_hat(k) b_hat(k), with the IFFT normalisation folded in
+        const int ix = x0 + c;
+        const int sx = fft_signed(ix, nx);
+        float kx = (float)sx * pd.dkx;
+        if (pd.symbol == 1) kx = sinpif(2.0f * (float)sx / (float)nx) / pd.dx;
+        const float kxo = ((nx % 2) == 0 && ix == nx / 2) ? 0.f : kx;
+        const float kx2 = kx * kx;
+        const float axx = pd.gc11 * kx2, azz = pd.gc55 * kx2, axz = pd.gc1355 * kxo;
+#pragma unroll
+        for (int m = 0; m < P; ++m) {
+            const int iz = tt + T * m;
+            const int sz = fft_signed(iz, N);
+            float kz = (float)sz * pd.dkz;
+            if (pd.symbol == 1) kz = sinpif(2.0f * (float)sz / (float)N) / pd.dx;
+            const float kzo = ((N % 2) == 0 && iz == N / 2) ? 0.f : kz;
+            const float kz2 = kz * kz;
+            const float gxx = axx + pd.gc55 * kz2;
+            const float gzz = azz + pd.gc33 * kz2;
+            const float gxz = axz * kzo;
+            const float2 mxx = make_float2(gxx - pd.ga.x, -pd.ga.y);
+            const float2 mzz = make_float2(gzz - pd.ga.x, -pd.ga.y);
+            float2 det = cmul(mxx, mzz);
+            det.x -= gxz * gxz;
+            const float s = pd.gscale / (det.x * det.x + det.y * det.y);
+            const float2 inv = make_float2(det.x * s, -det.y * s);
+            const float2 Gxx = cmul(mzz, inv);
+            const float2 Gzz = cmul(mxx, inv);
+            const float2 Gxz = cscale(inv, -gxz);
+            const float2 bx = v[0][m], bz = v[1][m];
+            v[0][m] = cadd(cmul(Gxx, bx), cmul(Gxz, bz));
+            v[1][m] = cadd(cmul(Gxz, bx), cmul(Gzz, bz));
+        }
+        __syncthreads();
+    }
+    if constexpr (MODE != COL_FWD) fft_run<N, P, true, 2>(v, tt, tw, lds);
+
+    if (active) {
+#pragma unroll
+        for (int f = 0; f < 2; ++f)
+#pragma unroll
+            for (int m = 0; m < P; ++m) base[f * plane + (size_t)(t + T * m) * nx] = v[f][m];
+    }
+}
+
+// ----------------------------------------------------------- launchers ----
+template <int N>
+static hipError_t rows_fwd_n(const float2* in, float2* out, int nrows, int rps, const SysState* st,
+                             const float2* tw, hipStream_t s) {
+    const RowGeom g = row_geom(N, rps);
+    const int blocks = (nrows + g.F - 1) / g.F;
+    const size_t lds = (size_t)(g.F + 1) * PaddedLen<N>::value * sizeof(float2);
+    hipLaunchKernelGGL((k_rows<N, false, EPI_STORE>), dim3(blocks), dim3(g.threads), lds, s, in, out,
+                       nullptr, nullptr, nullptr, nrows, rps, g.F, st, tw);
+    return hipGetLastError();
+}
+
+template <int N>
+static hipError_t rows_inv_n(int epi, const float2* in, const float2* u, const float2* aux,
+                             float2* out, double* part, int nrows, int rps, const SysState* st,
+                             const float2* tw, hipStream_t s) {
+    const RowGeom g = row_geom(N, rps);
+    const int blocks = (nrows + g.F - 1) / g.F;
+    const size_t lds = (size_t)(g.F + 1) * PaddedLen<N>::value * sizeof(float2);
+    switch (epi) {
+#define FW_EPI(E)                                                                                \
+    case E:                                                                                      \
+        hipLaunchKernelGGL((k_rows<N, true, E>), dim3(blocks), dim3(g.threads), lds, s, in, out, \
+                           u, aux, part, nrows, rps, g.F, st, tw);                               \
+        break;
+        FW_EPI(EPI_STORE) FW_EPI(EPI_APPLY) FW_EPI(EPI_BICG_V) FW_EPI(EPI_BICG_T) FW_EPI(EPI_TRUERES)
+#undef FW_EPI
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int N>
+static hipError_t cols_n(int mode, float2* data, const ProbDev& pd, const SysState* st,
+                         const float2* tw, hipStream_t s) {
+    const ColGeom g = col_geom(N, pd.nx);
+    const int blocks = pd.nsys * (pd.nx / g.W);
+    // idle threads (block padded to whole waves) need a private dummy slot
+    const int slots = g.W + (g.threads > g.W * FftShape<N, points_per_thread(N)>::T ? 1 : 0);
+    const size_t lds = (size_t)2 * PaddedLen<N>::value * slots * sizeof(float2);
+    switch (mode) {
+        case COL_GREEN:
+            hipLaunchKernelGGL((k_cols<N, COL_GREEN>), dim3(blocks), dim3(g.threads), lds, s, data, pd,
+                               g.W, st, tw);
+            break;
+        case COL_FWD:
+            hipLaunchKernelGGL((k_cols<N, COL_FWD>), dim3(blocks), dim3(g.threads), lds, s, data, pd,
+                               g.W, st, tw);
+            break;
+        case COL_INV:
+            hipLaunchKernelGGL((k_cols<N, COL_INV>), dim3(blocks), dim3(g.threads), lds, s, data, pd,
+                               g.W, st, tw);
+            break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_rows_fwd(int n, const float2* in, float2* out, int nrows, int rps,
+                           const SysState* st, const float2* tw, hipStream_t s) {
+    switch (n) {
+#define FW_CASE(N) \
+    case N: return rows_fwd_n<N>(in, out, nrows, rps, st, tw + twiddle_offset(N), s);
+        FW_FOR_EACH_SIZE(FW_CASE)
+#undef FW_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_rows_inv(int n, int epi, const float2* in, const float2* u, const float2* aux,
+                           float2* out, double* part, int nrows, int rps, const SysState* st,
+                           const float2* tw, hipStream_t s) {
+    switch (n) {
+#define FW_CASE(N) \
+    case N: return rows_inv_n<N>(epi, in, u, aux, out, part, nrows, rps, st, tw + twiddle_offset(N), s);
+        FW_FOR_EACH_SIZE(FW_CASE)
+#undef FW_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_cols(int mode, float2* data, const ProbDev& pd, const SysState* st,
+                       const float2* tw, hipStream_t s) {
+    switch (pd.nz) {
+#define FW_CASE(N) \
+    case N: return cols_n<N>(mode, data, pd, st, tw + twiddle_offset(N), s);
+        FW_FOR_EACH_SIZE(FW_CASE)
+#undef FW_CASE
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace fw

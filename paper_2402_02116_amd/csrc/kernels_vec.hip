@@ -1,0 +1,566 @@
+// Pointwise and stencil kernels of the LS solve, J and J*:
+//   k_body_force   - contrast stencil b = w~^2 drho u + div_h(dC : E_h u)
+//                    (eqs. Ewave0, u_2; abbreviated subscript section), also
+//                    the virtual source P_b(dm) of eqs. YM / dC;
+//   k_bicg_*       - batched BiCGSTAB vector updates with FP64 scalars;
+//   k_point_sources, k_gather, k_scatter_conj - sources and receivers;
+//   k_correlate    - adjoint correlation of eq. ad1 summed over systems.
+#include "launch.h"
+
+namespace fw {
+
+constexpr int kVecThreads = 256;
+constexpr int kVecEPT = 4;   // complex elements per thread in vector kernels
+
+// ------------------------------------------------------ contrast stencil --
+constexpr int STX = 64, STZ = 16;
+
+__device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// Strain differences use raw central differences e = 2 dx * eps; the stress
+// s' = dC e and the divergence of s' carry 1 / (4 dx^2) at the end.
+__global__ __launch_bounds__(256) void k_body_force(const float2* __restrict__ u,
+                                                    float2* __restrict__ b,
+                                                    const float* __restrict__ maps, ProbDev pd,
+                                                    int TX, int TZ,
+                                                    const SysState* __restrict__ st) {
+    __shared__ float2 su[2][STZ + 4][STX + 4];
+    __shared__ float2 ss[3][STZ + 2][STX + 2];
+    const int nx = pd.nx, nz = pd.nz;
+    const size_t plane = (size_t)nx * nz;
+    const int ntx = nx / TX, ntz = nz / TZ;
+    const int ntiles = ntx * ntz;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int sys = blk / ntiles;
+    const int tile = blk - sys * ntiles;
+    const int z0 = (tile / ntx) * TZ, x0 = (tile % ntx) * TX;
+    if (st != nullptr && st[sys].status != ST_RUNNING) return;
+    const float2* us = u + (size_t)sys * 2 * plane;
+    float2* bs = b + (size_t)sys * 2 * plane;
+
+    const int HX = TX + 4, HZ = TZ + 4;
+    for (int i = threadIdx.x; i < 2 * HZ * HX; i += blockDim.x) {
+        const int f = i / (HZ * HX);
+        const int rem = i - f * HZ * HX;
+        const int hz = rem / HX, hx = rem - hz * HX;
+        const int gz = wrap(z0 - 2 + hz, nz), gx = wrap(x0 - 2 + hx, nx);
+        su[f][hz][hx] = us[f * plane + (size_t)gz * nx + gx];
+    }
+    __syncthreads();
+
+    const int SX = TX + 2, SZ = TZ + 2;
+    for (int i = threadIdx.x; i < SZ * SX; i += blockDim.x) {
+        const int sz = i / SX, sx = i - sz * SX;
+        const int hz = sz + 1, hx = sx + 1;
+        const float2 ex = csub(su[0][hz][hx + 1], su[0][hz][hx - 1]);
+        const float2 ez = csub(su[1][hz + 1][hx], su[1][hz - 1][hx]);
+        const float2 exz = cadd(csub(su[0][hz + 1][hx], su[0][hz - 1][hx]),
+                                csub(su[1][hz][hx + 1], su[1][hz][hx - 1]));
+        const int gz = wrap(z0 - 1 + sz, nz), gx = wrap(x0 - 1 + sx, nx);
+        const size_t gi = (size_t)gz * nx + gx;
+        const float c11 = maps[gi], c13 = maps[plane + gi], c33 = maps[2 * plane + gi],
+                    c55 = maps[3 * plane + gi];
+        ss[0][sz][sx] = make_float2(c11 * ex.x + c13 * ez.x, c11 * ex.y + c13 * ez.y);
+        ss[1][sz][sx] = make_float2(c13 * ex.x + c33 * ez.x, c13 * ex.y + c33 * ez.y);
+        ss[2][sz][sx] = cscale(exz, c55);
+    }
+    __syncthreads();
+
+    const float s = pd.inv4dx2;
+    for (int i = threadIdx.x; i < TZ * TX; i += blockDim.x) {
+        const int lz = i / TX, lx = i - lz * TX;
+        const int sz = lz + 1, sx = lx + 1;
+        const float2 dx1 = csub(ss[0][sz][sx + 1], ss[0][sz][sx - 1]);
+        const float2 dz5 = csub(ss[2][sz + 1][sx], ss[2][sz - 1][sx]);
+        const float2 dx5 = csub(ss[2][sz][sx + 1], ss[2][sz][sx - 1]);
+        const float2 dz3 = csub(ss[1][sz + 1][sx], ss[1][sz - 1][sx]);
+        const size_t gi = (size_t)(z0 + lz) * nx + (x0 + lx);
+        const float rho = maps[4 * plane + gi];
+        const float2 wr = cscale(pd.w2, rho);
+        const float2 ux = su[0][lz + 2][lx + 2], uz = su[1][lz + 2][lx + 2];
+        bs[gi] = cadd(cmul(wr, ux), cscale(cadd(dx1, dz5), s));
+        bs[plane + gi] = cadd(cmul(wr, uz), cscale(cadd(dx5, dz3), s));
+    }
+}
+
+static int tile_dim(int n, int maxt) {
+    const int cand[] = {64, 48, 32, 24, 16, 12, 8};
+    for (int c : cand)
+        if (c <= maxt && n % c == 0) return c;
+    return 0;
+}
+
+hipError_t launch_body_force(const float2* u, float2* b, const float* maps, const ProbDev& pd,
+                             const SysState* st, hipStream_t s) {
+    const int TX = tile_dim(pd.nx, STX), TZ = tile_dim(pd.nz, STZ);
+    if (TX == 0 || TZ == 0) return hipErrorInvalidValue;
+    const int blocks = pd.nsys * (pd.nx / TX) * (pd.nz / TZ);
+    hipLaunchKernelGGL(k_body_force, dim3(blocks), dim3(256), 0, s, u, b, maps, pd, TX, TZ, st);
+    return hipGetLastError();
+}
+
+// -------------------------------------------------------------- vectors --
+int vec_blocks_per_sys(int n) { return (n + kVecThreads * kVecEPT - 1) / (kVecThreads * kVecEPT); }
+
+__device__ __forceinline__ dcomplex zdiv(dcomplex a, dcomplex b) {
+    const double d = b.re * b.re + b.im * b.im;
+    return dcomplex{(a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d};
+}
+__device__ __forceinline__ dcomplex zmul(dcomplex a, dcomplex b) {
+    return dcomplex{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+__device__ __forceinline__ float2 tof(dcomplex a) { return make_float2((float)a.re, (float)a.im); }
+__device__ __forceinline__ bool zzero(dcomplex a) { return a.re == 0.0 && a.im == 0.0; }
+
+// Block -> (system, block within system) for the vector kernels.
+struct VecIdx {
+    int sys, bi, i0;
+};
+__device__ __forceinline__ VecIdx vec_idx(int nb) {
+    VecIdx v;
+    v.sys = blockIdx.x / nb;
+    v.bi = blockIdx.x - v.sys * nb;
+    v.i0 = v.bi * kVecThreads * kVecEPT;
+    return v;
+}
+
+// r = b (or r already holds b - A x0), x = 0 if zero_x, rhat = r, p = v = 0;
+// partials <rhat, r>, ||r||^2 and ||b||^2.
+__global__ __launch_bounds__(256) void k_bicg_init(const float2* __restrict__ b,
+                                                   const float2* __restrict__ r0,
+                                                   float2* __restrict__ x, float2* __restrict__ r,
+                                                   float2* __restrict__ rhat, float2* __restrict__ p,
+                                                   float2* __restrict__ v,
+                                                   double* __restrict__ partXR,
+                                                   double* __restrict__ partB, int n, int nb,
+                                                   int zero_x) {
+    __shared__ double red[4 * 4];
+    const VecIdx vi = vec_idx(nb);
+    const size_t off = (size_t)vi.sys * n;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int e = 0; e < kVecEPT; ++e) {
+        const int i = vi.i0 + e * kVecThreads + threadIdx.x;
+        if (i < n) {
+            const float2 bb = b[off + i];
+            const float2 rr = r0 ? r0[off + i] : bb;
+            if (zero_x) x[off + i] = make_float2(0.f, 0.f);
+            r[off + i] = rr;
+            rhat[off + i] = rr;
+            p[off + i] = make_float2(0.f, 0.f);
+            v[off + i] = make_float2(0.f, 0.f);
+            const double q = (double)rr.x * rr.x + (double)rr.y * rr.y;
+            acc[0] += q;
+            acc[2] += q;
+            acc[3] += (double)bb.x * bb.x + (double)bb.y * bb.y;
+        }
+    }
+    block_allreduce<4, 256>(acc, red);
+    if (threadIdx.x == 0) {
+        double* d = partXR + ((size_t)vi.sys * nb + vi.bi) * kPartialNV;
+        d[0] = acc[0];
+        d[1] = 0.0;
+        d[2] = acc[2];
+        d[3] = 0.0;
+        partB[((size_t)vi.sys * nb + vi.bi) * kPartialNV] = acc[3];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_bicg_state_init(SysState* __restrict__ st,
+                                                         const double* __restrict__ partXR,
+                                                         const double* __restrict__ partB, int np,
+                                                         double rtol, int maxit) {
+    __shared__ double red[4 * 4];
+    const int sys = blockIdx.x;
+    double s[4];
+    sum_partials<4, 256>(partB + (size_t)sys * np * kPartialNV, np, s, red);
+    double q[4];
+    sum_partials<4, 256>(partXR + (size_t)sys * np * kPartialNV, np, q, red);
+    if (threadIdx.x == 0) {
+        SysState z;
+        z.rho_re[0] = 1.0; z.rho_im[0] = 0.0;
+        z.rho_re[1] = 1.0; z.rho_im[1] = 0.0;
+        z.alpha_re = 1.0; z.alpha_im = 0.0;
+        z.omega_re = 1.0; z.omega_im = 0.0;
+        z.bnorm2 = s[0];
+        z.tol2 = rtol * rtol * s[0];
+        z.rnorm2 = q[2];
+        z.iter = 0;
+        z.maxit = maxit;
+        z.pad = 0;
+        z.status = (s[0] == 0.0) ? ST_CONVERGED : ST_RUNNING;
+        st[sys] = z;
+    }
+}
+
+// Convergence / limit / finiteness test of the recursive residual; returns
+// true if the system must stop.  Block 0 records the status.
+__device__ __forceinline__ bool bicg_stop(SysState* st, int sys, double rr, bool writer) {
+    const SysState& s = st[sys];
+    int status = ST_RUNNING;
+    if (!(rr == rr) || rr > 1e300) status = ST_NONFINITE;
+    else if (rr <= s.tol2) status = ST_CONVERGED;
+    else if (s.iter >= s.maxit) status = ST_MAXIT;
+    if (status != ST_RUNNING && writer) {
+        st[sys].status = status;
+        st[sys].rnorm2 = rr;
+    }
+    return status != ST_RUNNING;
+}
+
+// p = r + beta (p - omega v),  beta = (rho_i / rho_{i-1}) (alpha / omega).
+__global__ __launch_bounds__(256) void k_bicg_p(const float2* __restrict__ r, float2* __restrict__ p,
+                                                const float2* __restrict__ v,
+                                                const double* __restrict__ partXR, int npXR,
+                                                SysState* __restrict__ st, int n, int nb) {
+    __shared__ double red[4 * 4];
+    const VecIdx vi = vec_idx(nb);
+    if (st[vi.sys].status != ST_RUNNING) return;
+    double q[4];
+    sum_partials<4, 256>(partXR + (size_t)vi.sys * npXR * kPartialNV, npXR, q, red);
+    const bool writer = (vi.bi == 0 && threadIdx.x == 0);
+    if (bicg_stop(st, vi.sys, q[2], writer)) return;
+    const SysState& s = st[vi.sys];
+    const int it = s.iter + 1;
+    const dcomplex rho{q[0], q[1]};
+    const dcomplex rho_prev{s.rho_re[(it - 1) & 1], s.rho_im[(it - 1) & 1]};
+    const dcomplex alpha{s.alpha_re, s.alpha_im}, omega{s.omega_re, s.omega_im};
+    if (zzero(rho) || zzero(rho_prev) || zzero(omega)) {
+        if (writer) st[vi.sys].status = ST_BREAKDOWN;
+        return;
+    }
+    const dcomplex beta = zmul(zdiv(rho, rho_prev), zdiv(alpha, omega));
+    const float2 bf = tof(beta), of = tof(omega);
+    const size_t off = (size_t)vi.sys * n;
+#pragma unroll
+    for (int e = 0; e < kVecEPT; ++e) {
+        const int i = vi.i0 + e * kVecThreads + threadIdx.x;
+        if (i < n) {
+            const float2 pv = p[off + i], vv = v[off + i], rv = r[off + i];
+            p[off + i] = cadd(rv, cmul(bf, csub(pv, cmul(of, vv))));
+        }
+    }
+    if (writer) {
+        st[vi.sys].rho_re[it & 1] = rho.re;
+        st[vi.sys].rho_im[it & 1] = rho.im;
+    }
+}
+
+// alpha = rho_i / <rhat, v>;  s = r - alpha v.
+__global__ __launch_bounds__(256) void k_bicg_s(const float2* __restrict__ r,
+                                                const float2* __restrict__ v, float2* __restrict__ sv,
+                                                const double* __restrict__ partV, int npV,
+                                                SysState* __restrict__ st, int n, int nb) {
+    __shared__ double red[4 * 4];
+    const VecIdx vi = vec_idx(nb);
+    if (st[vi.sys].status != ST_RUNNING) return;
+    double q[4];
+    sum_partials<4, 256>(partV + (size_t)vi.sys * npV * kPartialNV, npV, q, red);
+    const bool writer = (vi.bi == 0 && threadIdx.x == 0);
+    const SysState& s = st[vi.sys];
+    const int it = s.iter + 1;
+    const dcomplex rho{s.rho_re[it & 1], s.rho_im[it & 1]};
+    const dcomplex rv{q[0], q[1]};
+    if (zzero(rv)) {
+        if (writer) st[vi.sys].status = ST_BREAKDOWN;
+        return;
+    }
+    const dcomplex alpha = zdiv(rho, rv);
+    const float2 af = tof(alpha);
+    const size_t off = (size_t)vi.sys * n;
+#pragma unroll
+    for (int e = 0; e < kVecEPT; ++e) {
+        const int i = vi.i0 + e * kVecThreads + threadIdx.x;
+        if (i < n) sv[off + i] = csub(r[off + i], cmul(af, v[off + i]));
+    }
+    if (writer) {
+        st[vi.sys].alpha_re = alpha.re;
+        st[vi.sys].alpha_im = alpha.im;
+    }
+}
+
+// omega = <t, s> / <t, t>;  x += alpha p + omega s;  r = s - omega t;
+// partials <rhat, r>, ||r||^2.
+__global__ __launch_bounds__(256) void k_bicg_xr(float2* __restrict__ x, float2* __restrict__ r,
+                                                 const float2* __restrict__ rhat,
+                                                 const float2* __restrict__ p,
+                                                 const float2* __restrict__ sv,
+                                                 const float2* __restrict__ t,
+                                                 const double* __restrict__ partT, int npT,
+                                                 double* __restrict__ partXR,
+                                                 SysState* __restrict__ st, int n, int nb) {
+    __shared__ double red[4 * 4];
+    const VecIdx vi = vec_idx(nb);
+    if (st[vi.sys].status != ST_RUNNING) return;
+    double q[4];
+    sum_partials<4, 256>(partT + (size_t)vi.sys * npT * kPartialNV, npT, q, red);
+    const SysState& s = st[vi.sys];
+    const dcomplex alpha{s.alpha_re, s.alpha_im};
+    const dcomplex omega = (q[2] != 0.0) ? dcomplex{q[0] / q[2], q[1] / q[2]} : dcomplex{0.0, 0.0};
+    const float2 af = tof(alpha), of = tof(omega);
+    const size_t off = (size_t)vi.sys * n;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int e = 0; e < kVecEPT; ++e) {
+        const int i = vi.i0 + e * kVecThreads + threadIdx.x;
+        if (i < n) {
+            const float2 sv_ = sv[off + i], tv = t[off + i];
+            x[off + i] = cadd(x[off + i], cadd(cmul(af, p[off + i]), cmul(of, sv_)));
+            const float2 rn = csub(sv_, cmul(of, tv));
+            r[off + i] = rn;
+            const float2 h = rhat[off + i];
+            acc[0] += (double)h.x * rn.x + (double)h.y * rn.y;
+            acc[1] += (double)h.x * rn.y - (double)h.y * rn.x;
+            acc[2] += (double)rn.x * rn.x + (double)rn.y * rn.y;
+        }
+    }
+    block_allreduce<4, 256>(acc, red);
+    if (threadIdx.x == 0) {
+        double* d = partXR + ((size_t)vi.sys * nb + vi.bi) * kPartialNV;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) d[k] = acc[k];
+        if (vi.bi == 0) {
+            st[vi.sys].omega_re = omega.re;
+            st[vi.sys].omega_im = omega.im;
+            st[vi.sys].iter = s.iter + 1;
+        }
+    }
+}
+
+// End-of-chunk test so that the host sees systems that converged in the last
+// iteration of a chunk.
+__global__ __launch_bounds__(256) void k_bicg_check(SysState* __restrict__ st,
+                                                    const double* __restrict__ partXR, int np) {
+    __shared__ double red[4 * 4];
+    const int sys = blockIdx.x;
+    if (st[sys].status != ST_RUNNING) return;
+    double q[4];
+    sum_partials<4, 256>(partXR + (size_t)sys * np * kPartialNV, np, q, red);
+    if (threadIdx.x == 0) {
+        st[sys].rnorm2 = q[2];
+        bicg_stop(st, sys, q[2], true);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_bicg_finish(const SysState* __restrict__ st,
+                                                     const double* __restrict__ partTR, int np,
+                                                     int32_t* __restrict__ iters,
+                                                     double* __restrict__ relres) {
+    __shared__ double red[4 * 4];
+    const int sys = blockIdx.x;
+    double q[4];
+    sum_partials<4, 256>(partTR + (size_t)sys * np * kPartialNV, np, q, red);
+    if (threadIdx.x == 0) {
+        const double bb = st[sys].bnorm2;
+        if (iters) iters[sys] = st[sys].iter;
+        if (relres) relres[sys] = bb > 0.0 ? sqrt(q[0] / bb) : 0.0;
+    }
+}
+
+hipError_t launch_bicg_init(const float2* b, const float2* r0, float2* x, float2* r, float2* rhat,
+                            float2* p, float2* v, double* partXR, double* partB, int nsys, int n,
+                            bool zero_x, hipStream_t s) {
+    const int nb = vec_blocks_per_sys(n);
+    hipLaunchKernelGGL(k_bicg_init, dim3(nsys * nb), dim3(kVecThreads), 0, s, b, r0, x, r, rhat, p,
+                       v, partXR, partB, n, nb, zero_x ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_bicg_state_init(SysState* st, const double* partXR, const double* partB,
+                                  int nsys, int npart, double rtol, int maxit, hipStream_t s) {
+    hipLaunchKernelGGL(k_bicg_state_init, dim3(nsys), dim3(256), 0, s, st, partXR, partB, npart,
+                       rtol, maxit);
+    return hipGetLastError();
+}
+
+hipError_t launch_bicg_p(const float2* r, float2* p, const float2* v, const double* partXR,
+                         int npXR, SysState* st, int nsys, int n, hipStream_t s) {
+    const int nb = vec_blocks_per_sys(n);
+    hipLaunchKernelGGL(k_bicg_p, dim3(nsys * nb), dim3(kVecThreads), 0, s, r, p, v, partXR, npXR,
+                       st, n, nb);
+    return hipGetLastError();
+}
+
+hipError_t launch_bicg_s(const float2* r, const float2* v, float2* sv, const double* partV,
+                         int npV, SysState* st, int nsys, int n, hipStream_t s) {
+    const int nb = vec_blocks_per_sys(n);
+    hipLaunchKernelGGL(k_bicg_s, dim3(nsys * nb), dim3(kVecThreads), 0, s, r, v, sv, partV, npV,
+                       st, n, nb);
+    return hipGetLastError();
+}
+
+hipError_t launch_bicg_xr(float2* x, float2* r, const float2* rhat, const float2* p,
+                          const float2* sv, const float2* t, const double* partT, int npT,
+                          double* partXR, SysState* st, int nsys, int n, hipStream_t s) {
+    const int nb = vec_blocks_per_sys(n);
+    hipLaunchKernelGGL(k_bicg_xr, dim3(nsys * nb), dim3(kVecThreads), 0, s, x, r, rhat, p, sv, t,
+                       partT, npT, partXR, st, n, nb);
+    return hipGetLastError();
+}
+
+hipError_t launch_bicg_check(SysState* st, const double* partXR, int npXR, int nsys,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(k_bicg_check, dim3(nsys), dim3(256), 0, s, st, partXR, npXR);
+    return hipGetLastError();
+}
+
+hipError_t launch_bicg_finish(const SysState* st, const double* partTR, int npTR, int nsys,
+                              int32_t* iters, double* relres, hipStream_t s) {
+    hipLaunchKernelGGL(k_bicg_finish, dim3(nsys), dim3(256), 0, s, st, partTR, npTR, iters, relres);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------ copy and zero -----
+__global__ __launch_bounds__(256) void k_copy(const float4* __restrict__ src, float4* __restrict__ dst,
+                                              size_t n4) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4;
+         i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+__global__ __launch_bounds__(256) void k_zero(float4* __restrict__ dst, size_t n4) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4;
+         i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+// n complex elements; n is even for every field of this library.
+hipError_t launch_copy(const float2* src, float2* dst, size_t n, hipStream_t s) {
+    const size_t n4 = n / 2;
+    const int blocks = (int)std::min<size_t>((n4 + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(256), 0, s, (const float4*)src, (float4*)dst, n4);
+    return hipGetLastError();
+}
+hipError_t launch_zero(float2* dst, size_t n, hipStream_t s) {
+    const size_t n4 = n / 2;
+    const int blocks = (int)std::min<size_t>((n4 + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, s, (float4*)dst, n4);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------- sources, receivers --
+// f must be zero on entry: one force per system, F / dx^2 at (ix, iz).
+__global__ void k_point_sources(float2* __restrict__ f, const int32_t* __restrict__ ixz,
+                                const double* __restrict__ force, ProbDev pd) {
+    const int sys = blockIdx.x * blockDim.x + threadIdx.x;
+    if (sys >= pd.nsys) return;
+    const size_t plane = (size_t)pd.nx * pd.nz;
+    const int ix = ixz[2 * sys], iz = ixz[2 * sys + 1];
+    const double inv = 1.0 / ((double)pd.dx * (double)pd.dx);
+    float2* fs = f + (size_t)sys * 2 * plane + (size_t)iz * pd.nx + ix;
+    fs[0] = make_float2((float)(force[2 * sys] * inv), 0.f);
+    fs[plane] = make_float2((float)(force[2 * sys + 1] * inv), 0.f);
+}
+
+hipError_t launch_point_sources(float2* f, const int32_t* src_ixz, const double* src_f,
+                                const ProbDev& pd, hipStream_t s) {
+    hipLaunchKernelGGL(k_point_sources, dim3((pd.nsys + 63) / 64), dim3(64), 0, s, f, src_ixz, src_f, pd);
+    return hipGetLastError();
+}
+
+// d[sys][rec][c] = w[sys][c][iz][ix]
+__global__ void k_gather(const float2* __restrict__ w, float2* __restrict__ d,
+                         const int32_t* __restrict__ rec, int nrec, ProbDev pd) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int total = pd.nsys * nrec * 2;
+    if (i >= total) return;
+    const int c = i & 1;
+    const int rr = (i >> 1) % nrec;
+    const int sys = (i >> 1) / nrec;
+    const size_t plane = (size_t)pd.nx * pd.nz;
+    d[i] = w[(size_t)sys * 2 * plane + c * plane + (size_t)rec[2 * rr + 1] * pd.nx + rec[2 * rr]];
+}
+
+hipError_t launch_gather(const float2* w, float2* d, const int32_t* rec_ixz, int nrec,
+                         const ProbDev& pd, hipStream_t s) {
+    const int total = pd.nsys * nrec * 2;
+    hipLaunchKernelGGL(k_gather, dim3((total + 255) / 256), dim3(256), 0, s, w, d, rec_ixz, nrec, pd);
+    return hipGetLastError();
+}
+
+// f (zero on entry) += conj(d) at the receivers; one thread per (sys, c)
+// walks the receivers in order, so repeated receivers add deterministically.
+__global__ void k_scatter_conj(const float2* __restrict__ d, float2* __restrict__ f,
+                               const int32_t* __restrict__ rec, int nrec, ProbDev pd) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= pd.nsys * 2) return;
+    const int sys = i >> 1, c = i & 1;
+    const size_t plane = (size_t)pd.nx * pd.nz;
+    float2* fs = f + (size_t)sys * 2 * plane + c * plane;
+    for (int r = 0; r < nrec; ++r) {
+        const float2 dv = d[((size_t)sys * nrec + r) * 2 + c];
+        const size_t gi = (size_t)rec[2 * r + 1] * pd.nx + rec[2 * r];
+        fs[gi] = cadd(fs[gi], cconj(dv));
+    }
+}
+
+hipError_t launch_scatter_conj(const float2* d, float2* f, const int32_t* rec_ixz, int nrec,
+                               const ProbDev& pd, hipStream_t s) {
+    const int total = pd.nsys * 2;
+    hipLaunchKernelGGL(k_scatter_conj, dim3((total + 63) / 64), dim3(64), 0, s, d, f, rec_ixz, nrec, pd);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------- correlation -----
+// g_rho = conj(w~^2 sum_sys u^a . u^b); g_p = -conj(sum_sys eps^a . B^p eps^b),
+// with the 2-D B matrices of the maps (C11, C13, C33, C55):
+//   B11 -> e1 e1,  B13 -> e1 e3 + e3 e1,  B33 -> e3 e3,  B55 -> e5 e5.
+__global__ __launch_bounds__(256) void k_correlate(const float2* __restrict__ ua,
+                                                   const float2* __restrict__ ub,
+                                                   float2* __restrict__ g, ProbDev pd, int accumulate) {
+    const int nx = pd.nx, nz = pd.nz;
+    const size_t plane = (size_t)nx * nz;
+    const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= (int)plane) return;
+    const int z = cell / nx, x = cell - z * nx;
+    const int xp = (x + 1 == nx) ? 0 : x + 1, xm = (x == 0) ? nx - 1 : x - 1;
+    const int zp = (z + 1 == nz) ? 0 : z + 1, zm = (z == 0) ? nz - 1 : z - 1;
+    const size_t ic = cell, ixp = (size_t)z * nx + xp, ixm = (size_t)z * nx + xm;
+    const size_t izp = (size_t)zp * nx + x, izm = (size_t)zm * nx + x;
+    double rr = 0, ri = 0, a11r = 0, a11i = 0, a13r = 0, a13i = 0, a33r = 0, a33i = 0, a55r = 0,
+           a55i = 0;
+    for (int s = 0; s < pd.nsys; ++s) {
+        const float2* A = ua + (size_t)s * 2 * plane;
+        const float2* B = ub + (size_t)s * 2 * plane;
+        const float2 ax = A[ic], az = A[plane + ic], bx = B[ic], bz = B[plane + ic];
+        rr += (double)ax.x * bx.x - (double)ax.y * bx.y + (double)az.x * bz.x - (double)az.y * bz.y;
+        ri += (double)ax.x * bx.y + (double)ax.y * bx.x + (double)az.x * bz.y + (double)az.y * bz.x;
+        const float2 e1a = csub(A[ixp], A[ixm]);
+        const float2 e3a = csub(A[plane + izp], A[plane + izm]);
+        const float2 e5a = cadd(csub(A[izp], A[izm]), csub(A[plane + ixp], A[plane + ixm]));
+        const float2 e1b = csub(B[ixp], B[ixm]);
+        const float2 e3b = csub(B[plane + izp], B[plane + izm]);
+        const float2 e5b = cadd(csub(B[izp], B[izm]), csub(B[plane + ixp], B[plane + ixm]));
+        a11r += (double)e1a.x * e1b.x - (double)e1a.y * e1b.y;
+        a11i += (double)e1a.x * e1b.y + (double)e1a.y * e1b.x;
+        a13r += (double)e1a.x * e3b.x - (double)e1a.y * e3b.y + (double)e3a.x * e1b.x - (double)e3a.y * e1b.y;
+        a13i += (double)e1a.x * e3b.y + (double)e1a.y * e3b.x + (double)e3a.x * e1b.y + (double)e3a.y * e1b.x;
+        a33r += (double)e3a.x * e3b.x - (double)e3a.y * e3b.y;
+        a33i += (double)e3a.x * e3b.y + (double)e3a.y * e3b.x;
+        a55r += (double)e5a.x * e5b.x - (double)e5a.y * e5b.y;
+        a55i += (double)e5a.x * e5b.y + (double)e5a.y * e5b.x;
+    }
+    const double s = (double)pd.inv4dx2;
+    const double wr = pd.w2.x, wi = pd.w2.y;
+    // conj(w2 * rho) ; -conj(a) * s
+    float2 out[5];
+    out[0] = make_float2((float)(-a11r * s), (float)(a11i * s));
+    out[1] = make_float2((float)(-a13r * s), (float)(a13i * s));
+    out[2] = make_float2((float)(-a33r * s), (float)(a33i * s));
+    out[3] = make_float2((float)(-a55r * s), (float)(a55i * s));
+    out[4] = make_float2((float)(wr * rr - wi * ri), (float)(-(wr * ri + wi * rr)));
+#pragma unroll
+    for (int p = 0; p < 5; ++p) {
+        float2* dst = g + (size_t)p * plane + ic;
+        *dst = accumulate ? cadd(*dst, out[p]) : out[p];
+    }
+}
+
+hipError_t launch_correlate(const float2* ua, const float2* ub, float2* g, const ProbDev& pd,
+                            bool accumulate, hipStream_t s) {
+    const int cells = pd.nx * pd.nz;
+    hipLaunchKernelGGL(k_correlate, dim3((cells + 255) / 256), dim3(256), 0, s, ua, ub, g, pd,
+                       accumulate ? 1 : 0);
+    return hipGetLastError();
+}
+
+}  // namespace fw

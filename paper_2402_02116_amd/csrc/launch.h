@@ -1,0 +1,84 @@
+// Host-side launchers of the fwils kernels (internal interface between the
+// C ABI in capi.cpp and the HIP translation units).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+
+namespace fw {
+
+// Epilogues of the inverse row transform that ends a convolution y = G0 conv b.
+enum RowEpilogue : int {
+    EPI_STORE = 0,     // out = y
+    EPI_APPLY = 1,     // out = u - y                          (A u)
+    EPI_BICG_V = 2,    // out = u - y;  partial <aux, out>      (v = A p, <r^, v>)
+    EPI_BICG_T = 3,    // out = u - y;  partials <out, u>, ||out||^2   (t = A s)
+    EPI_TRUERES = 4,   // out = aux - (u - y); partial ||out||^2       (r = b - A x)
+};
+constexpr int kPartialNV = 4;   // doubles per partial-sum record
+
+enum ColMode : int { COL_GREEN = 0, COL_FWD = 1, COL_INV = 2 };
+
+// FFT sizes with kernels in this build: 2^a 3^b, 16 <= n <= 2048.
+bool fft_size_supported(int n);
+
+// Launch geometry chosen for a size (also used to size partial buffers).
+struct RowGeom { int F; int threads; int blocks_per_sys; };
+RowGeom row_geom(int n, int nrows_per_sys);
+struct ColGeom { int W; int threads; };
+ColGeom col_geom(int nz, int nx);
+
+// Twiddle table tw[m] = exp(-2 pi i m / n), m < n, for every supported n,
+// packed back to back; offset of size n in complex elements.
+size_t twiddle_table_elems();
+size_t twiddle_offset(int n);
+void twiddle_table_fill(float2* host);
+
+// Row transforms over nrows rows of length n (rows_per_sys rows per system;
+// a block never straddles systems).  st (may be null): systems whose status is
+// not RUNNING are skipped.
+hipError_t launch_rows_fwd(int n, const float2* in, float2* out, int nrows, int rows_per_sys,
+                           const SysState* st, const float2* tw, hipStream_t s);
+hipError_t launch_rows_inv(int n, int epi, const float2* in, const float2* u, const float2* aux,
+                           float2* out, double* partials, int nrows, int rows_per_sys,
+                           const SysState* st, const float2* tw, hipStream_t s);
+// Column pass over [nsys][2][nz][nx] in place.
+hipError_t launch_cols(int mode, float2* data, const ProbDev& pd, const SysState* st,
+                       const float2* tw, hipStream_t s);
+
+// Body force b = w~^2 drho u + div_h(dC : E_h u) of one problem.
+hipError_t launch_body_force(const float2* u, float2* b, const float* maps, const ProbDev& pd,
+                             const SysState* st, hipStream_t s);
+
+// BiCGSTAB pieces (one problem; n = 2 nz nx complex per system).
+int vec_blocks_per_sys(int n);
+hipError_t launch_bicg_init(const float2* b, const float2* r0, float2* x, float2* r, float2* rhat,
+                            float2* p, float2* v, double* partXR, double* partB, int nsys, int n,
+                            bool zero_x, hipStream_t s);
+hipError_t launch_bicg_state_init(SysState* st, const double* partXR, const double* partB,
+                                  int nsys, int npart, double rtol, int maxit, hipStream_t s);
+hipError_t launch_bicg_p(const float2* r, float2* p, const float2* v, const double* partXR,
+                         int npXR, SysState* st, int nsys, int n, hipStream_t s);
+hipError_t launch_bicg_s(const float2* r, const float2* v, float2* sv, const double* partV,
+                         int npV, SysState* st, int nsys, int n, hipStream_t s);
+hipError_t launch_bicg_xr(float2* x, float2* r, const float2* rhat, const float2* p,
+                          const float2* sv, const float2* t, const double* partT, int npT,
+                          double* partXR, SysState* st, int nsys, int n, hipStream_t s);
+hipError_t launch_bicg_check(SysState* st, const double* partXR, int npXR, int nsys, hipStream_t s);
+hipError_t launch_bicg_finish(const SysState* st, const double* partTR, int npTR, int nsys,
+                              int32_t* iters, double* relres, hipStream_t s);
+
+// Sources, receivers, correlation.
+hipError_t launch_point_sources(float2* f, const int32_t* src_ixz, const double* src_f,
+                                const ProbDev& pd, hipStream_t s);
+hipError_t launch_gather(const float2* w, float2* d, const int32_t* rec_ixz, int nrec,
+                         const ProbDev& pd, hipStream_t s);
+hipError_t launch_scatter_conj(const float2* d, float2* f, const int32_t* rec_ixz, int nrec,
+                               const ProbDev& pd, hipStream_t s);
+hipError_t launch_correlate(const float2* ua, const float2* ub, float2* g, const ProbDev& pd,
+                            bool accumulate, hipStream_t s);
+hipError_t launch_copy(const float2* src, float2* dst, size_t n, hipStream_t s);
+hipError_t launch_zero(float2* dst, size_t n, hipStream_t s);
+
+}  // namespace fw

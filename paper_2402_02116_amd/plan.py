@@ -1,0 +1,257 @@
+"""Python binding of the fwils C ABI (include/fwils.h).
+
+Argument marshalling only: every computation runs in the HIP kernels of
+libfwils.so.  PyTorch supplies device memory (the workspace and the fields)
+and the stream: each call enqueues on torch's current stream of the plan's
+device.
+
+Field tensors are flat complex64 CUDA tensors holding the plan-level field
+(problems concatenated, each [nsys][2][nz][nx]); `view(t, i)` gives problem i
+as a [nsys, 2, nz, nx] view.
+"""
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import check
+
+SYMBOLS = {"spectral": _lib.FWILS_SYMBOL_SPECTRAL, "central": _lib.FWILS_SYMBOL_CENTRAL}
+
+
+@dataclass
+class SolveResult:
+    x: torch.Tensor           # flat field
+    iters: np.ndarray         # [sum nsys] int32
+    relres: np.ndarray        # [sum nsys] true relative residual
+    status: int               # FWILS_OK / FWILS_ENOCONV / FWILS_EBREAKDOWN
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _require_cuda(t, dtype, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+class Plan:
+    """One or more (grid, frequency) problems solved together."""
+
+    def __init__(self, problems, device="cuda"):
+        self.lib = _lib.load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("fwils needs a ROCm GPU (torch.cuda.is_available() is False)")
+        self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.problems = [dict(p) for p in problems]
+        n = len(self.problems)
+        arr = (_lib.FwilsProblem * n)()
+        for i, p in enumerate(self.problems):
+            arr[i].nx, arr[i].nz = int(p["nx"]), int(p["nz"])
+            arr[i].dx = float(p["dx"])
+            for k in range(4):
+                arr[i].c0[k] = float(p["c0"][k])
+            arr[i].rho0 = float(p["rho0"])
+            arr[i].freq_hz = float(p["freq_hz"])
+            arr[i].damping = float(p.get("eta", p.get("damping", 0.02)))
+            arr[i].nsys = int(p["nsys"])
+            sym = p.get("symbol", "spectral")
+            arr[i].symbol = SYMBOLS[sym] if isinstance(sym, str) else int(sym)
+        h = ctypes.c_void_p()
+        check(self.lib.fwils_plan_create(arr, n, _lib.FWILS_C64, ctypes.byref(h)), "fwils_plan_create")
+        self._h = h
+        size = ctypes.c_size_t()
+        check(self.lib.fwils_workspace_size(h, ctypes.byref(size)), "fwils_workspace_size")
+        self.workspace_bytes = size.value
+        with torch.cuda.device(self.device):
+            raw = torch.empty(size.value + 256, dtype=torch.uint8, device=self.device)
+        off = (-raw.data_ptr()) % 256
+        self._ws_raw = raw
+        self._ws_ptr = raw.data_ptr() + off
+        self._bind_stream()
+        check(self.lib.fwils_set_workspace(h, ctypes.c_void_p(self._ws_ptr), size.value),
+              "fwils_set_workspace")
+        fe = ctypes.c_int64()
+        check(self.lib.fwils_field_elems(h, ctypes.byref(fe)), "fwils_field_elems")
+        self.field_elems = fe.value
+        self.offsets, self.sys_offsets = [], []
+        o = so = 0
+        for p in self.problems:
+            self.offsets.append(o)
+            self.sys_offsets.append(so)
+            o += p["nsys"] * 2 * p["nz"] * p["nx"]
+            so += p["nsys"]
+        self.total_sys = so
+        self.nrec = [0] * n
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                torch.cuda.synchronize(self.device)
+            except Exception:
+                pass
+            self.lib.fwils_plan_destroy(h)
+            self._h = None
+
+    # ------------------------------------------------------------ helpers --
+    def _bind_stream(self):
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        check(self.lib.fwils_set_stream(self._h, ctypes.c_void_p(s)), "fwils_set_stream")
+
+    def new_field(self):
+        return torch.zeros(self.field_elems, dtype=torch.complex64, device=self.device)
+
+    def view(self, t, i):
+        p = self.problems[i]
+        n = p["nsys"] * 2 * p["nz"] * p["nx"]
+        return t[self.offsets[i]:self.offsets[i] + n].view(p["nsys"], 2, p["nz"], p["nx"])
+
+    def pack(self, parts):
+        """Concatenate per-problem [nsys, 2, nz, nx] arrays into a plan-level field."""
+        flat = [torch.as_tensor(np.asarray(x) if not isinstance(x, torch.Tensor) else x)
+                .to(torch.complex64).reshape(-1) for x in parts]
+        return torch.cat(flat).to(self.device).contiguous()
+
+    def _field(self, t, name):
+        _require_cuda(t, torch.complex64, name)
+        if t.numel() != self.field_elems:
+            raise ValueError(f"{name} has {t.numel()} elements, the plan's fields have {self.field_elems}")
+        return t
+
+    def data_elems(self):
+        return sum(p["nsys"] * nr * 2 for p, nr in zip(self.problems, self.nrec))
+
+    def data_view(self, d, i):
+        p = self.problems[i]
+        off = sum(q["nsys"] * nr * 2 for q, nr in zip(self.problems[:i], self.nrec[:i]))
+        return d[off:off + p["nsys"] * self.nrec[i] * 2].view(p["nsys"], self.nrec[i], 2)
+
+    # ---------------------------------------------------------- the ABI ----
+    def set_contrast(self, i, maps):
+        p = self.problems[i]
+        m = torch.as_tensor(maps, dtype=torch.float32).to(self.device).contiguous()
+        if tuple(m.shape) != (5, p["nz"], p["nx"]):
+            raise ValueError(f"maps must be [5, {p['nz']}, {p['nx']}]")
+        self._bind_stream()
+        check(self.lib.fwils_set_contrast(self._h, i, _ptr(m)), "fwils_set_contrast")
+        torch.cuda.current_stream(self.device).synchronize()
+
+    def set_receivers(self, i, rec_ixz):
+        r = np.ascontiguousarray(np.asarray(rec_ixz, dtype=np.int32).reshape(-1, 2))
+        self._bind_stream()
+        check(self.lib.fwils_set_receivers(self._h, i, r.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                           r.shape[0]), "fwils_set_receivers")
+        self.nrec[i] = r.shape[0]
+
+    def incident(self, src_ixz, src_f):
+        s = np.ascontiguousarray(np.asarray(src_ixz, dtype=np.int32).reshape(-1, 2))
+        f = np.ascontiguousarray(np.asarray(src_f, dtype=np.float64).reshape(-1, 2))
+        if s.shape[0] != self.total_sys or f.shape[0] != self.total_sys:
+            raise ValueError(f"need {self.total_sys} sources and forces")
+        u0 = self.new_field()
+        self._bind_stream()
+        check(self.lib.fwils_incident(self._h, s.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                      f.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _ptr(u0)),
+              "fwils_incident")
+        return u0
+
+    def body_force(self, u, out=None):
+        self._field(u, "u")
+        out = self.new_field() if out is None else self._field(out, "out")
+        self._bind_stream()
+        check(self.lib.fwils_body_force(self._h, _ptr(u), _ptr(out)), "fwils_body_force")
+        return out
+
+    def convolve(self, f, out=None):
+        self._field(f, "f")
+        out = self.new_field() if out is None else self._field(out, "out")
+        self._bind_stream()
+        check(self.lib.fwils_convolve(self._h, _ptr(f), _ptr(out)), "fwils_convolve")
+        return out
+
+    def apply(self, u, out=None):
+        self._field(u, "u")
+        out = self.new_field() if out is None else self._field(out, "out")
+        self._bind_stream()
+        check(self.lib.fwils_apply(self._h, _ptr(u), _ptr(out)), "fwils_apply")
+        return out
+
+    def solve(self, rhs, x0=None, rtol=1e-6, maxit=1000, plain=False, graph=True, out=None,
+              strict=False):
+        """BiCGSTAB solve of A x = rhs; returns SolveResult (iters, true relres)."""
+        self._field(rhs, "rhs")
+        flags = 0
+        if x0 is not None:
+            x = self._field(x0, "x0").clone() if out is None else out.copy_(x0)
+            flags |= _lib.FWILS_SOLVE_X0
+        else:
+            x = self.new_field() if out is None else self._field(out, "out")
+        if plain:
+            flags |= _lib.FWILS_SOLVE_PLAIN
+        if not graph:
+            flags |= _lib.FWILS_SOLVE_NOGRAPH
+        iters = torch.zeros(self.total_sys, dtype=torch.int32, device=self.device)
+        relres = torch.zeros(self.total_sys, dtype=torch.float64, device=self.device)
+        self._bind_stream()
+        st = self.lib.fwils_solve(self._h, _ptr(rhs), _ptr(x), float(rtol), int(maxit),
+                                  _ptr(iters), _ptr(relres), flags)
+        if st not in (_lib.FWILS_OK, _lib.FWILS_ENOCONV, _lib.FWILS_EBREAKDOWN) or (strict and st != 0):
+            check(st, "fwils_solve")
+        return SolveResult(x, iters.cpu().numpy(), relres.cpu().numpy(), st)
+
+    def frechet(self, ub, dm, rtol=1e-6, maxit=1000):
+        """J dm for every system; dm: list (one per problem) of float32 [5, nz, nx]."""
+        self._field(ub, "ub")
+        dms = []
+        for i, p in enumerate(self.problems):
+            m = dm[i]
+            _require_cuda(m, torch.float32, f"dm[{i}]")
+            if tuple(m.shape) != (5, p["nz"], p["nx"]):
+                raise ValueError(f"dm[{i}] must be [5, {p['nz']}, {p['nx']}]")
+            dms.append(m)
+        arr = (ctypes.c_void_p * len(dms))(*[m.data_ptr() for m in dms])
+        d = torch.zeros(self.data_elems(), dtype=torch.complex64, device=self.device)
+        self._bind_stream()
+        st = self.lib.fwils_frechet(self._h, _ptr(ub), arr, _ptr(d), float(rtol), int(maxit))
+        if st != _lib.FWILS_OK:
+            check(st, "fwils_frechet")
+        return d
+
+    def adjoint(self, ub, r, rtol=1e-6, maxit=1000, g=None, accumulate=False):
+        """J* r: list (one per problem) of complex64 [5, nz, nx] maps."""
+        self._field(ub, "ub")
+        _require_cuda(r, torch.complex64, "r")
+        if r.numel() != self.data_elems():
+            raise ValueError(f"r must hold {self.data_elems()} complex values")
+        if g is None:
+            g = [torch.zeros(5, p["nz"], p["nx"], dtype=torch.complex64, device=self.device)
+                 for p in self.problems]
+        for i, gi in enumerate(g):
+            _require_cuda(gi, torch.complex64, f"g[{i}]")
+        arr = (ctypes.c_void_p * len(g))(*[gi.data_ptr() for gi in g])
+        self._bind_stream()
+        st = self.lib.fwils_adjoint(self._h, _ptr(ub), _ptr(r), arr,
+                                    _lib.FWILS_ADJ_ACCUMULATE if accumulate else 0,
+                                    float(rtol), int(maxit))
+        if st != _lib.FWILS_OK:
+            check(st, "fwils_adjoint")
+        return g
+
+    def fft2(self, i, x, inverse=False, out=None):
+        """2-D FFT (unnormalised) of every field of problem i; x: [nsys, 2, nz, nx]."""
+        _require_cuda(x, torch.complex64, "x")
+        out = torch.empty_like(x) if out is None else out
+        self._bind_stream()
+        check(self.lib.fwils_fft2(self._h, i, _ptr(x), _ptr(out), 1 if inverse else 0), "fwils_fft2")
+        return out

@@ -1,0 +1,121 @@
+"""Host-only tests of the C ABI: the library loads, exports every declared
+entry point, validates arguments before touching the device, and the Python
+binding refuses to run without a GPU.  No compute calls."""
+
+import ctypes
+import os
+
+import pytest
+import torch
+
+from paper_2402_02116_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return _lib.load()
+
+
+def _prob(**kw):
+    p = _lib.FwilsProblem()
+    p.nx, p.nz, p.dx = kw.get("nx", 64), kw.get("nz", 32), kw.get("dx", 8.0)
+    c0 = kw.get("c0", (1.7875e10, 8.0805e9, 1.375e10, 3.168e9))
+    for k in range(4):
+        p.c0[k] = c0[k]
+    p.rho0, p.freq_hz, p.damping = kw.get("rho0", 2200.0), kw.get("freq_hz", 5.0), kw.get("damping", 0.02)
+    p.nsys, p.symbol = kw.get("nsys", 3), kw.get("symbol", 0)
+    return p
+
+
+def _create(lib, probs, prec=0):
+    arr = (_lib.FwilsProblem * len(probs))(*probs)
+    h = ctypes.c_void_p()
+    st = lib.fwils_plan_create(arr, len(probs), prec, ctypes.byref(h))
+    return st, h
+
+
+def test_library_exports_every_declared_symbol(lib):
+    names = _lib.header_functions()
+    assert len(names) >= 19
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(_lib.SIGNATURES)
+    assert lib.fwils_abi_version() == 1
+
+
+def test_status_strings(lib):
+    for s in range(7):
+        assert lib.fwils_status_string(s)
+    assert b"unknown" in lib.fwils_status_string(99)
+
+
+def test_problem_struct_layout_matches_header():
+    assert ctypes.sizeof(_lib.FwilsProblem) == 80
+    assert _lib.FwilsProblem.nsys.offset == 72
+
+
+@pytest.mark.parametrize("bad", [
+    dict(nx=17), dict(nz=4096), dict(nx=8), dict(nx=80), dict(dx=0.0), dict(rho0=-1.0),
+    dict(freq_hz=0.0), dict(damping=0.0), dict(nsys=0), dict(symbol=2),
+    dict(c0=(0.0, 1e9, 1e10, 1e9)), dict(c0=(1e10, float("nan"), 1e10, 1e9)),
+])
+def test_plan_create_rejects_bad_problems(lib, bad):
+    st, h = _create(lib, [_prob(), _prob(**bad)])
+    assert st == _lib.FWILS_EINVAL
+    assert not h.value
+    assert b"problem 1" in lib.fwils_last_error()
+
+
+def test_plan_create_argument_errors(lib):
+    h = ctypes.c_void_p()
+    assert lib.fwils_plan_create(None, 1, 0, ctypes.byref(h)) == _lib.FWILS_EINVAL
+    arr = (_lib.FwilsProblem * 1)(_prob())
+    assert lib.fwils_plan_create(arr, 0, 0, ctypes.byref(h)) == _lib.FWILS_EINVAL
+    assert lib.fwils_plan_create(arr, 1, 0, None) == _lib.FWILS_EINVAL
+    assert lib.fwils_plan_create(arr, 1, 7, ctypes.byref(h)) == _lib.FWILS_EUNSUPPORTED
+
+
+def test_plan_metadata_without_device(lib):
+    probs = [_prob(nx=64, nz=32, nsys=3), _prob(nx=96, nz=48, nsys=2), _prob(nx=2048, nz=16, nsys=1)]
+    st, h = _create(lib, probs)
+    assert st == _lib.FWILS_OK and h.value
+    try:
+        fe = ctypes.c_int64()
+        assert lib.fwils_field_elems(h, ctypes.byref(fe)) == 0
+        assert fe.value == 3 * 2 * 64 * 32 + 2 * 2 * 96 * 48 + 1 * 2 * 2048 * 16
+        sz = ctypes.c_size_t()
+        assert lib.fwils_workspace_size(h, ctypes.byref(sz)) == 0
+        # nine Krylov / scratch vectors at least
+        assert sz.value >= 9 * fe.value * 8
+        assert lib.fwils_workspace_size(h, None) == _lib.FWILS_EINVAL
+        # everything that needs device memory refuses before any launch
+        assert lib.fwils_apply(h, ctypes.c_void_p(256), ctypes.c_void_p(512)) == _lib.FWILS_ENOMEM
+        assert lib.fwils_solve(h, ctypes.c_void_p(256), ctypes.c_void_p(512), 1e-6, 10, None, None, 0) \
+            == _lib.FWILS_ENOMEM
+        assert lib.fwils_set_workspace(h, None, sz.value) == _lib.FWILS_ENOMEM
+        assert lib.fwils_set_workspace(h, ctypes.c_void_p(256), sz.value - 1) == _lib.FWILS_ENOMEM
+        assert lib.fwils_set_workspace(h, ctypes.c_void_p(257), sz.value) == _lib.FWILS_ENOMEM
+        assert lib.fwils_set_stream(h, None) == _lib.FWILS_OK
+    finally:
+        lib.fwils_plan_destroy(h)
+
+
+def test_null_plan_is_rejected(lib):
+    assert lib.fwils_apply(None, None, None) == _lib.FWILS_EINVAL
+    assert lib.fwils_solve(None, None, None, 1e-6, 10, None, None, 0) == _lib.FWILS_EINVAL
+    lib.fwils_plan_destroy(None)
+
+
+def test_python_binding_fails_loudly_without_gpu():
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    from paper_2402_02116_amd.plan import Plan
+    with pytest.raises(RuntimeError, match="GPU"):
+        Plan([dict(nx=32, nz=32, dx=10.0, c0=(8e9, 4e9, 8e9, 2e9), rho0=2000.0, freq_hz=10.0, nsys=1)])
+
+
+def test_missing_library_raises(tmp_path):
+    with pytest.raises(_lib.FwilsLibraryError, match="not built"):
+        _lib.load(str(tmp_path / "libfwils.so"))
