@@ -1,0 +1,238 @@
+#!/usr/bin/env python
+"""Benchmark of the elastic Lippmann-Schwinger hot path on one MI355X.
+
+Workload: 256 x 256 VTI grid (dx 8 m; Vp0 2500, Vs0 1200, eps 0.15,
+delta 0.05, rho 2200), random-layered contrast (seed 1), 16 surface point
+forces, 5 Hz, 2 % damping, complex64 fields with FP64 Krylov scalars.
+
+One step = the whole hot path over this batch: incident fields u0 = G0 conv s
+for the 16 sources, the batched BiCGSTAB solve of A u^b = u0 to 1e-6, one
+Frechet application J dm (virtual source, one solve per system, receiver
+gather) and one adjoint application J* r (receiver scatter, one solve per
+system, correlation summed over sources), each solve graph-captured and run
+to 1e-6.  `value` is the sustained LS matvec rate of the step:
+    sum over the three solves and all systems of (2 iters + 1) * nx * nz
+divided by the step's wall time (G cell-systems per second).
+
+Also reported: the isolated batched matvec rate, time-to-1e-6 of the batched
+solve against the plain per-source solve (same kernels, nsys = 1, host check
+every iteration), the per-pass kernel times, the roofline of the dominant
+kernel and the CPU oracle timed on a bounded sample of the same step.
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "LS matvec GPoints/s + time-to-1e-6 residual, batched c64 vs plain, % HBM peak"
+HBM_PEAK_GBS = 8000.0
+RTOL = 1e-6
+NREC = 128
+PASS_NAMES = ["k_body_force (contrast stencil)", "k_rows<256,fwd> (row FFT)",
+              "k_cols<256,GREEN> (column FFT + G_hat + inverse column FFT)",
+              "k_rows<256,inv,APPLY> (inverse row FFT + LS epilogue)"]
+# algorithmic HBM bytes per cell-system for each pass (complex64 = 8 B per
+# component, 2 components): read + write of the field, plus the epilogue's
+# read of u; pass 0 also reads the 5 fp32 maps once per cell (20 B per cell,
+# shared by the nsys systems).
+PASS_BYTES = [32.0, 32.0, 32.0, 48.0]
+MAP_BYTES_PER_CELL = 20.0
+
+
+def _kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("fft.h", "common.h", "kernels_fft.hip", "kernels_vec.hip"):
+        with open(os.path.join(ROOT, "paper_2402_02116_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic_from_profiles(kernel_pass, launch_cells):
+    """HBM bytes per launch from the committed counter summary, or None when the
+    kernels changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "counters_config1.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        c = json.load(fh)
+    if c.get("source_hash") != _kernel_source_hash():
+        return None
+    ent = c.get("passes", {}).get(str(kernel_pass))
+    if not ent:
+        return None
+    return float(ent["hbm_bytes_per_launch"])
+
+
+def build_workload():
+    import numpy as np
+    import workloads as W
+    c = W.config1()
+    rec = W.surface_receivers(c["nx"], NREC)
+    m0 = W.model_scales(c["c0"], c["rho0"])
+    dm = W.round_f32(m0 * W.smooth_maps(4, c["nz"], c["nx"], 10, 0.01)).astype(np.float32)
+    r = W.round_f32(W.complex_normal(5, (c["nsys"], NREC, 2))).astype(np.complex64)
+    return c, rec, dm, r
+
+
+def cpu_baseline(c, rec, dm, r, nsample):
+    """The oracle on the host cores, on `nsample` of the systems of one step."""
+    import numpy as np
+    from oracle import LSProblem, operators
+    P = LSProblem(c["nx"], c["nz"], c["dx"], c["c0"], c["rho0"], c["freq_hz"], c["eta"], c["maps"])
+    src, f = c["src_ixz"][:nsample], c["src_f"][:nsample]
+    t = time.perf_counter()
+    u0 = P.incident(src, f)
+    ub, i1 = P.solve(u0, tol=RTOL)
+    w, i2 = P.solve(P.convolve(P.virtual_source(ub, dm.astype(np.float64))), tol=RTOL)
+    operators.sample(w, rec)
+    fa = operators.sample_transpose(np.conj(r[:nsample].astype(np.complex128)), rec, c["nx"], c["nz"])
+    ua, i3 = P.solve(P.convolve(fa), tol=RTOL)
+    P.correlate(ua, ub)
+    dt = time.perf_counter() - t
+    mv = sum(2 * i.iters + 1 for i in i1 + i2 + i3)
+    return dict(value=mv * c["nx"] * c["nz"] / dt / 1e9, unit="GPoints/s", cores=operators._WORKERS,
+                kind="oracle",
+                sample=f"{nsample} of the {c['nsys']} systems through the whole step (incident, solve, "
+                       f"J, J*), complex128 numpy/scipy, {mv} matvecs in {dt:.1f} s")
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--reps", type=int, default=50, help="launches per kernel timing")
+    ap.add_argument("--cpu-sample", type=int, default=4, help="systems in the CPU oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    a = ap.parse_args(argv)
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported (the path shards "
+              f"independent systems across GPUs, see DESIGN.md)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+    from paper_2402_02116_amd.plan import Plan
+
+    torch.cuda.set_device(0)
+    c, rec, dm_np, r_np = build_workload()
+    nx, nz, ns = c["nx"], c["nz"], c["nsys"]
+    cells = nx * nz
+    plan = Plan([dict(nx=nx, nz=nz, dx=c["dx"], c0=c["c0"], rho0=c["rho0"], freq_hz=c["freq_hz"],
+                      eta=c["eta"], nsys=ns)], device="cuda:0")
+    plan.set_contrast(0, c["maps"])
+    plan.set_receivers(0, rec)
+    dm = torch.as_tensor(dm_np).cuda()
+    r = torch.as_tensor(r_np.ravel()).cuda()
+
+    def step():
+        u0 = plan.incident(c["src_ixz"], c["src_f"])
+        res = plan.solve(u0, rtol=RTOL, maxit=1000)
+        n1 = int(np.sum(2 * res.iters + 1))
+        plan.frechet(res.x, [dm], rtol=RTOL)
+        n2 = int(np.sum(2 * plan.solve_stats()[0] + 1))
+        plan.adjoint(res.x, r, rtol=RTOL)
+        n3 = int(np.sum(2 * plan.solve_stats()[0] + 1))
+        return n1 + n2 + n3
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mv = 0
+    for _ in range(a.steps):
+        mv += step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_step = dt / a.steps * 1e3
+    value = mv * cells / dt / 1e9
+    print(f"[bench] {a.steps} steps: {ms_step:.3f} ms/step, {mv / a.steps:.0f} matvecs/step, "
+          f"{value:.2f} GPoints/s sustained", file=sys.stderr, flush=True)
+
+    # time-to-1e-6: batched graph solve vs plain per-source solve
+    u0 = plan.incident(c["src_ixz"], c["src_f"])
+    def timed_solve(**kw):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        res = plan.solve(u0, rtol=RTOL, maxit=1000, **kw)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) * 1e3, res
+    for _ in range(2):
+        timed_solve()
+        timed_solve(plain=True)
+    tb = sorted(timed_solve()[0] for _ in range(5))
+    tbr = timed_solve()[1]
+    tp = sorted(timed_solve(plain=True)[0] for _ in range(3))
+    tpr = timed_solve(plain=True)[1]
+    same = bool(torch.equal(tbr.x, tpr.x))
+    print(f"[bench] time to 1e-6: batched {tb[len(tb) // 2]:.3f} ms, plain {tp[len(tp) // 2]:.3f} ms, "
+          f"iters {tbr.iters.min()}-{tbr.iters.max()}, max true relres {tbr.relres.max():.2e}, "
+          f"identical results {same}", file=sys.stderr, flush=True)
+
+    # isolated batched matvec and its four kernels, HIP events on the plan's stream
+    u = tbr.x
+    Au = plan.new_field()
+    stream = torch.cuda.current_stream()
+    def event_time(fn, reps):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+    t_apply = event_time(lambda: plan.apply(u, out=Au), a.reps)
+    t_pass = []
+    for k in range(4):
+        if k > 0:
+            for j in range(k):
+                plan.apply_pass(j, u, Au)
+        t_pass.append(event_time(lambda k=k: plan.apply_pass(k, u, Au), a.reps))
+    matvec_gps = ns * cells / (t_apply * 1e-3) / 1e9
+    bytes_per_launch = [PASS_BYTES[k] * ns * cells + (MAP_BYTES_PER_CELL * cells if k == 0 else 0.0)
+                        for k in range(4)]
+    gbs = [bytes_per_launch[k] / (t_pass[k] * 1e-3) / 1e9 for k in range(4)]
+    dom = int(np.argmax(t_pass))
+    traffic = _traffic_from_profiles(dom, ns * cells)
+    for k in range(4):
+        print(f"[bench] pass {k} {PASS_NAMES[k]}: {t_pass[k] * 1e3:.2f} us/launch, "
+              f"{gbs[k]:.0f} GB/s algorithmic", file=sys.stderr, flush=True)
+    unfused_bytes = sum(bytes_per_launch)
+    print(f"[bench] batched matvec: {t_apply * 1e3:.2f} us, {matvec_gps:.2f} GPoints/s, "
+          f"{unfused_bytes / (t_apply * 1e-3) / 1e9:.0f} GB/s over the 4 passes", file=sys.stderr, flush=True)
+
+    roof = dict(bound="hbm", kernel=PASS_NAMES[dom], achieved=round(gbs[dom], 1), peak=HBM_PEAK_GBS,
+                unit="GB/s", frac=round(gbs[dom] / HBM_PEAK_GBS, 4),
+                traffic=None if traffic is None else round(traffic, 1),
+                bytes_per_launch=bytes_per_launch[dom], avg_launch_us=round(t_pass[dom] * 1e3, 3))
+    out = dict(metric=METRIC, value=round(value, 3), unit="GPoints/s", n_gpus=1, steps=a.steps,
+               warmup=a.warmup, ms_per_step=round(ms_step, 4), higher_is_better=True, scaling="weak",
+               vs_baseline=None, dtype="c64", data="synthetic",
+               config=dict(workload="256x256 VTI (dx 8 m), random-layered contrast, 16 surface forces, "
+                                    "5 Hz, 128 receivers: incident + solve + J + J* to 1e-6",
+                           grid=[nz, nx], nsys=ns, freq_hz=c["freq_hz"], rtol=RTOL, nrec=NREC),
+               roofline=roof,
+               time_to_1e6_ms=dict(batched=round(tb[len(tb) // 2], 3), plain=round(tp[len(tp) // 2], 3),
+                                   speedup=round(tp[len(tp) // 2] / tb[len(tb) // 2], 2),
+                                   iters=[int(tbr.iters.min()), int(tbr.iters.max())],
+                                   max_true_relres=float(tbr.relres.max()), identical=same),
+               matvec=dict(gpoints_s=round(matvec_gps, 3), us=round(t_apply * 1e3, 3),
+                           pass_us=[round(t * 1e3, 3) for t in t_pass],
+                           pass_gbs=[round(g, 1) for g in gbs]))
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(c, rec, dm_np, r_np, a.cpu_sample)
+        print(f"[bench] cpu oracle: {out['cpu_baseline']}", file=sys.stderr, flush=True)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -184,6 +184,23 @@ fwils_status fwils_frechet(fwils_plan plan, const void* ub, const float* const* 
 fwils_status fwils_adjoint(fwils_plan plan, const void* ub, const void* r,
                            void* const* g, uint32_t flags, double rtol, int32_t maxit);
 
+/* One of the four passes of fwils_apply, on the plan's workspace scratch
+ * field (the sequence 0, 1, 2, 3 computes exactly fwils_apply):
+ *   pass 0: scratch = b(u)                 (contrast stencil)
+ *   pass 1: scratch = FFT_x(scratch)       (forward row transforms)
+ *   pass 2: scratch = IFFT_z(G_hat FFT_z(scratch))  (column transforms with
+ *           the Green's multiply, normalisation 1/(nx nz) included)
+ *   pass 3: Au = u - IFFT_x(scratch)       (inverse rows + LS epilogue)
+ * u is read by passes 0 and 3, Au written by pass 3 (others ignore them).
+ * Exists so that a caller can time each kernel of the matvec. */
+fwils_status fwils_apply_pass(fwils_plan plan, int32_t pass, const void* u, void* Au);
+
+/* Per-system results of the most recent Krylov solve of this plan (from
+ * fwils_solve, fwils_frechet or fwils_adjoint): completed iterations and the
+ * recursive relative residual ||r|| / ||rhs||.  Host arrays [sum nsys] or
+ * NULL.  Synchronous. */
+fwils_status fwils_solve_stats(fwils_plan plan, int32_t* iters, double* relres);
+
 /* 2-D FFT of every field of problem iprob with the library's own transform
  * kernels (unnormalised forward, exp(-i k.x); inverse with exp(+i k.x) and
  * no 1/(nx nz)).  A self-test entry point.  in, out: device, may alias. */

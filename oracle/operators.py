@@ -26,7 +26,8 @@ import os
 import numpy as np
 import scipy.fft
 
-_WORKERS = os.cpu_count() or 1
+# threads for scipy.fft: the host cores, at most 16 (one GPU's share of a box)
+_WORKERS = max(1, min(os.cpu_count() or 1, 16))
 
 
 def ddx(f, dx):

@@ -46,6 +46,8 @@ SIGNATURES = {
     "fwils_frechet": (c_int32, [P, P, ctypes.POINTER(c_void_p), P, c_double, c_int32]),
     "fwils_adjoint": (c_int32, [P, P, P, ctypes.POINTER(c_void_p), c_uint32, c_double, c_int32]),
     "fwils_fft2": (c_int32, [P, c_int32, P, P, c_int32]),
+    "fwils_apply_pass": (c_int32, [P, c_int32, P, P]),
+    "fwils_solve_stats": (c_int32, [P, ctypes.POINTER(c_int32), ctypes.POINTER(c_double)]),
     "fwils_status_string": (ctypes.c_char_p, [c_int32]),
     "fwils_last_error": (ctypes.c_char_p, []),
     "fwils_abi_version": (c_int32, []),

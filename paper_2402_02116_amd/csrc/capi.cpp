@@ -687,6 +687,42 @@ fwils_status fwils_adjoint(fwils_plan plan, const void* ub, const void* r, void*
     return st;
 }
 
+fwils_status fwils_apply_pass(fwils_plan plan, int32_t pass, const void* u, void* Au) {
+    FW_TRY(check_plan(plan));
+    if (pass < 0 || pass > 3 || ((pass == 0 || pass == 3) && !u) || (pass == 3 && (!Au || u == Au))) {
+        set_error("apply_pass: pass must be 0..3 with u (passes 0, 3) and a distinct Au (pass 3)");
+        return FWILS_EINVAL;
+    }
+    hipStream_t s = plan->stream;
+    for (const ProbHost& P : plan->probs) {
+        const int rows = P.p.nsys * 2 * P.p.nz;
+        float2* tmp = at(plan->tmp, P);
+        switch (pass) {
+            case 0: FW_HIP(launch_body_force(at(u, P), tmp, maps_at(plan, P), P.dev, nullptr, s)); break;
+            case 1: FW_HIP(launch_rows_fwd(P.p.nx, tmp, tmp, rows, 2 * P.p.nz, nullptr, plan->tw, s)); break;
+            case 2: FW_HIP(launch_cols(COL_GREEN, tmp, P.dev, nullptr, plan->tw, s)); break;
+            default:
+                FW_HIP(launch_rows_inv(P.p.nx, EPI_APPLY, tmp, at(u, P), nullptr,
+                                       static_cast<float2*>(Au) + P.field_off, nullptr, rows, 2 * P.p.nz,
+                                       nullptr, plan->tw, s));
+        }
+    }
+    return FWILS_OK;
+}
+
+fwils_status fwils_solve_stats(fwils_plan plan, int32_t* iters, double* relres) {
+    FW_TRY(check_plan(plan));
+    FW_HIP(hipStreamSynchronize(plan->stream));
+    FW_HIP(hipMemcpy(plan->host_state, plan->state, plan->total_sys * sizeof(SysState),
+                     hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < plan->total_sys; ++i) {
+        const SysState& z = plan->host_state[i];
+        if (iters) iters[i] = z.iter;
+        if (relres) relres[i] = z.bnorm2 > 0 ? std::sqrt(z.rnorm2 / z.bnorm2) : 0.0;
+    }
+    return FWILS_OK;
+}
+
 fwils_status fwils_fft2(fwils_plan plan, int32_t iprob, const void* in, void* out, int32_t inverse) {
     FW_TRY(check_plan(plan));
     FW_TRY(check_field_ptrs({in, out}));

@@ -248,6 +248,26 @@ class Plan:
             check(st, "fwils_adjoint")
         return g
 
+    def apply_pass(self, k, u=None, out=None):
+        """Pass k (0..3) of apply(); passes 0..3 in order compute apply(u)."""
+        if u is not None:
+            self._field(u, "u")
+        if out is not None:
+            self._field(out, "out")
+        self._bind_stream()
+        check(self.lib.fwils_apply_pass(self._h, int(k), None if u is None else _ptr(u),
+                                        None if out is None else _ptr(out)), "fwils_apply_pass")
+        return out
+
+    def solve_stats(self):
+        """(iters, recursive relres) of the last Krylov solve, per system."""
+        it = np.zeros(self.total_sys, dtype=np.int32)
+        rr = np.zeros(self.total_sys, dtype=np.float64)
+        check(self.lib.fwils_solve_stats(self._h, it.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                         rr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+              "fwils_solve_stats")
+        return it, rr
+
     def fft2(self, i, x, inverse=False, out=None):
         """2-D FFT (unnormalised) of every field of problem i; x: [nsys, 2, nz, nx]."""
         _require_cuda(x, torch.complex64, "x")
