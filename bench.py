@@ -209,6 +209,16 @@ def main(argv=None):
     print(f"[bench] batched matvec: {t_apply * 1e3:.2f} us, {matvec_gps:.2f} GPoints/s, "
           f"{unfused_bytes / (t_apply * 1e-3) / 1e9:.0f} GB/s over the 4 passes", file=sys.stderr, flush=True)
 
+    # attainable device bandwidth: a plain 1 GiB device-to-device copy (also the
+    # reference kernel for scaling the FETCH_SIZE / WRITE_SIZE counters)
+    src = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    t_copy = event_time(lambda: dst.copy_(src), 10)
+    copy_gbs = 2 * src.numel() * 4 / (t_copy * 1e-3) / 1e9
+    del src, dst
+    print(f"[bench] device copy 1 GiB: {t_copy * 1e3:.1f} us, {copy_gbs:.0f} GB/s (read + write)",
+          file=sys.stderr, flush=True)
+
     roof = dict(bound="hbm", kernel=PASS_NAMES[dom], achieved=round(gbs[dom], 1), peak=HBM_PEAK_GBS,
                 unit="GB/s", frac=round(gbs[dom] / HBM_PEAK_GBS, 4),
                 traffic=None if traffic is None else round(traffic, 1),
@@ -224,6 +234,7 @@ def main(argv=None):
                                    speedup=round(tp[len(tp) // 2] / tb[len(tb) // 2], 2),
                                    iters=[int(tbr.iters.min()), int(tbr.iters.max())],
                                    max_true_relres=float(tbr.relres.max()), identical=same),
+               copy_gbs=round(copy_gbs, 1),
                matvec=dict(gpoints_s=round(matvec_gps, 3), us=round(t_apply * 1e3, 3),
                            pass_us=[round(t * 1e3, 3) for t in t_pass],
                            pass_gbs=[round(g, 1) for g in gbs]))

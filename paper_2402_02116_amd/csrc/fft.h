@@ -170,6 +170,37 @@ __device__ __forceinline__ void dft(float2 (&x)[R]) {
     else static_assert(R == 2, "unsupported radix");
 }
 
+// --------------------------------------------------------------- twiddles --
+// w[r] = W^(r e) for r = 1..R-1, where W^e = tw[e] (forward; conjugated for
+// the inverse).  Only W^e and, for R >= 8, W^(4e) are read from the table; the
+// other powers are products of at most four factors (a few ulp).
+template <int R, bool INV>
+__device__ __forceinline__ void twiddles(float2 (&w)[R], const float2* __restrict__ tw, int e) {
+    float2 w1 = tw[e];
+    if (INV) w1 = cconj(w1);
+    w[1] = w1;
+    if constexpr (R >= 3) w[2] = cmul(w1, w1);
+    if constexpr (R >= 4) w[3] = cmul(w[2], w1);
+    if constexpr (R >= 8) {
+        float2 w4 = tw[4 * e];
+        if (INV) w4 = cconj(w4);
+        w[4] = w4;
+#pragma unroll
+        for (int r = 5; r < 8; ++r) w[r] = cmul(w4, w[r - 4]);
+    }
+    if constexpr (R == 16) {
+        const float2 w8 = cmul(w[4], w[4]);
+        const float2 w12 = cmul(w8, w[4]);
+        w[8] = w8;
+        w[12] = w12;
+#pragma unroll
+        for (int r = 1; r < 4; ++r) {
+            w[8 + r] = cmul(w8, w[r]);
+            w[12 + r] = cmul(w12, w[r]);
+        }
+    }
+}
+
 // ----------------------------------------------------------- one pass -----
 // Pass I of an N-point transform for NF independent transforms held by this
 // thread (v[f][m] at position t + T*m).  Non-final passes write to LDS through
@@ -188,13 +219,7 @@ __device__ __forceinline__ void fft_pass(float2 (&v)[NF][P], int t,
         const int j = t + S::T * b;
         const int k = j % NS;
         float2 w[R];
-        if constexpr (NS > 1) {
-#pragma unroll
-            for (int r = 1; r < R; ++r) {
-                const float2 tt = tw[k * r * TWS];
-                w[r] = INV ? cconj(tt) : tt;
-            }
-        }
+        if constexpr (NS > 1) twiddles<R, INV>(w, tw, k * TWS);
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             float2 x[R];
@@ -239,6 +264,69 @@ template <int N, int P, bool INV, int NF, class Lds>
 __device__ __forceinline__ void fft_run(float2 (&v)[NF][P], int t,
                                         const float2* __restrict__ tw, const Lds& lds) {
     fft_from<N, P, INV, NF, 0>(v, t, tw, lds);
+}
+
+// ------------------------------------------- sequential LDS exchange -----
+// Same transform, but the NF transforms of a thread share ONE LDS buffer: a
+// pass finishes transform f (butterflies, LDS write, barrier, LDS read,
+// barrier) before it starts transform f + 1.  Half the LDS of fft_run for
+// NF = 2, at the price of two more barriers per pass.
+template <int N, int P, int I, bool INV, int NF, class Lds>
+__device__ __forceinline__ void fft_pass_seq(float2 (&v)[NF][P], int t,
+                                             const float2* __restrict__ tw, const Lds& lds) {
+    using S = FftShape<N, P>;
+    constexpr int R = S::plan.r[I];
+    constexpr int NS = S::ns_before(I);
+    constexpr int NB = P / R;
+    constexpr bool LAST = (I == S::NP - 1);
+    constexpr int TWS = N / (NS * R);
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int j = t + S::T * b;
+            const int k = j % NS;
+            float2 x[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) x[r] = v[f][b + r * NB];
+            if constexpr (NS > 1) {
+                float2 w[R];
+                twiddles<R, INV>(w, tw, k * TWS);
+#pragma unroll
+                for (int r = 1; r < R; ++r) x[r] = cmul(x[r], w[r]);
+            }
+            dft<R, INV>(x);
+            if constexpr (LAST) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[f][b + r * NB] = x[r];
+            } else {
+                const int base = (j / NS) * NS * R + k;
+#pragma unroll
+                for (int r = 0; r < R; ++r) lds(0, base + r * NS) = x[r];
+            }
+        }
+        if constexpr (!LAST) {
+            __syncthreads();
+#pragma unroll
+            for (int m = 0; m < P; ++m) v[f][m] = lds(0, t + S::T * m);
+            __syncthreads();
+        }
+    }
+}
+
+template <int N, int P, bool INV, int NF, int I, class Lds>
+__device__ __forceinline__ void fft_from_seq(float2 (&v)[NF][P], int t,
+                                             const float2* __restrict__ tw, const Lds& lds) {
+    fft_pass_seq<N, P, I, INV, NF>(v, t, tw, lds);
+    if constexpr (I + 1 < FftShape<N, P>::NP) fft_from_seq<N, P, INV, NF, I + 1>(v, t, tw, lds);
+}
+
+// Full transform with one shared LDS buffer; every thread must call it.  The
+// caller must make sure no thread still reads the buffer from earlier use.
+template <int N, int P, bool INV, int NF, class Lds>
+__device__ __forceinline__ void fft_run_seq(float2 (&v)[NF][P], int t,
+                                            const float2* __restrict__ tw, const Lds& lds) {
+    fft_from_seq<N, P, INV, NF, 0>(v, t, tw, lds);
 }
 
 // Padded LDS index: one spare slot every 16 elements keeps the stride-R

@@ -18,8 +18,11 @@ namespace fw {
 
 static const int kSizes[] = {16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048};
 
-// Points per thread: 16 for powers of two (radix-16 passes), 12 for 3 * 2^k.
+// Points per thread.  Row passes: 16 for powers of two (radix-16 passes), 12
+// for 3 * 2^k.  Column passes hold both field components per thread, so they
+// use 8 (radix 8) to keep registers low and the thread count high.
 constexpr int points_per_thread(int n) { return (n % 3 == 0) ? 12 : 16; }
+constexpr int col_points_per_thread(int n) { return (n % 3 == 0) ? 12 : 8; }
 
 bool fft_size_supported(int n) {
     for (int s : kSizes)
@@ -72,10 +75,13 @@ RowGeom row_geom(int n, int rows_per_sys) {
 
 static int padded_len(int n) { return n + n / 16 + 1; }
 
+// Column blocks: W columns x T threads per column, at most 512 threads; one
+// field component goes through LDS at a time.  W = 16 makes every 16-lane LDS
+// access group one contiguous 128-byte row segment (no bank conflicts) and
+// every global access a full 128-byte line.
 ColGeom col_geom(int nz, int nx) {
-    const int T = nz / points_per_thread(nz);
-    const int lds_w = 65536 / (2 * padded_len(nz) * (int)sizeof(float2));
-    int W = pow2_floor(std::max(1, std::min(256 / T, lds_w)));
+    const int T = nz / col_points_per_thread(nz);
+    int W = std::max(1, std::min(16, 512 / T));
     while (W > 1 && nx % W != 0) W /= 2;
     ColGeom g;
     g.W = W;
@@ -200,23 +206,39 @@ __global__ __launch_bounds__(256) void k_rows(const float2* in, float2* out,
 
 // ------------------------------------------------------ column kernel ----
 struct ColLds {
-    float2* p;
-    int W, c, dummy;     // dummy: idle thread -> private scratch region
+    float2* base;   // this thread's column (or its private dummy slot)
+    int stride;     // W (columns interleaved) or 1 (dummy slot)
     int PL;
     __device__ __forceinline__ float2& operator()(int f, int pos) const {
-        const int e = f * PL + lds_pad(pos);
-        return dummy ? p[e] : p[(size_t)e * W + c];
+        return base[(f * PL + lds_pad(pos)) * stride];
     }
 };
+
+// (bx, bz) <- G_hat (bx, bz) with G_hat = gscale (Gamma' - ga I)^-1 for the
+// real symmetric scaled Christoffel matrix Gamma' = [[gxx, gxz], [gxz, gzz]].
+__device__ __forceinline__ void green_mul(float2& bx, float2& bz, float gxx, float gzz, float gxz,
+                                          float2 ga, float gscale) {
+    const float2 mxx = make_float2(gxx - ga.x, -ga.y);
+    const float2 mzz = make_float2(gzz - ga.x, -ga.y);
+    float2 det = cmul(mxx, mzz);
+    det.x -= gxz * gxz;
+    const float s = gscale / (det.x * det.x + det.y * det.y);
+    const float2 inv = make_float2(det.x * s, -det.y * s);
+    const float2 gx = cmul(inv, bx), gz = cmul(inv, bz);   // inv b
+    const float2 ox = csub(cmul(mzz, gx), cscale(gz, gxz));
+    const float2 oz = csub(cmul(mxx, gz), cscale(gx, gxz));
+    bx = ox;
+    bz = oz;
+}
 
 // Signed FFT index of i on an n-point axis (numpy fftfreq order).
 __device__ __forceinline__ int fft_signed(int i, int n) { return (i < (n + 1) / 2) ? i : i - n; }
 
 template <int N, int MODE>
-__global__ __launch_bounds__(256) void k_cols(float2* __restrict__ data, ProbDev pd, int W,
+__global__ __launch_bounds__(512) void k_cols(float2* __restrict__ data, ProbDev pd, int W,
                                               const SysState* __restrict__ st,
                                               const float2* __restrict__ tw) {
-    constexpr int P = points_per_thread(N);
+    constexpr int P = col_points_per_thread(N);
     using S = FftShape<N, P>;
     constexpr int T = S::T;
     constexpr int PL = PaddedLen<N>::value;
@@ -246,46 +268,34 @@ __global__ __launch_bounds__(256) void k_cols(float2* __restrict__ data, ProbDev
 #pragma unroll
             for (int m = 0; m < P; ++m) v[f][m] = make_float2(0.f, 0.f);
     }
-    ColLds lds{active ? lds_dyn : lds_dyn + (size_t)2 * PL * W, W, c, active ? 0 : 1, PL};
+    ColLds lds{active ? lds_dyn + c : lds_dyn + (size_t)PL * W, active ? W : 1, PL};
     const int tt = active ? t : 0;
 
-    if constexpr (MODE != COL_INV) fft_run<N, P, false, 2>(v, tt, tw, lds);
+    if constexpr (MODE != COL_INV) fft_run_seq<N, P, false, 2>(v, tt, tw, lds);
     if constexpr (MODE == COL_GREEN) {
         // u_hat = G_hat(k) b_hat(k), with the IFFT normalisation folded in
         const int ix = x0 + c;
         const int sx = fft_signed(ix, nx);
-        float kx = (float)sx * pd.dkx;
-        if (pd.symbol == 1) kx = sinpif(2.0f * (float)sx / (float)nx) / pd.dx;
+        const bool central = pd.symbol == 1;
+        const float kx = central ? sinpif(2.0f * (float)sx / (float)nx) / pd.dx : (float)sx * pd.dkx;
         const float kxo = ((nx % 2) == 0 && ix == nx / 2) ? 0.f : kx;
         const float kx2 = kx * kx;
         const float axx = pd.gc11 * kx2, azz = pd.gc55 * kx2, axz = pd.gc1355 * kxo;
+        const float dk = central ? 2.0f / (float)N : pd.dkz;
 #pragma unroll
         for (int m = 0; m < P; ++m) {
             const int iz = tt + T * m;
             const int sz = fft_signed(iz, N);
-            float kz = (float)sz * pd.dkz;
-            if (pd.symbol == 1) kz = sinpif(2.0f * (float)sz / (float)N) / pd.dx;
+            float kz = (float)sz * dk;
+            if (central) kz = sinpif(kz) / pd.dx;
             const float kzo = ((N % 2) == 0 && iz == N / 2) ? 0.f : kz;
-            const float kz2 = kz * kz;
-            const float gxx = axx + pd.gc55 * kz2;
-            const float gzz = azz + pd.gc33 * kz2;
-            const float gxz = axz * kzo;
-            const float2 mxx = make_float2(gxx - pd.ga.x, -pd.ga.y);
-            const float2 mzz = make_float2(gzz - pd.ga.x, -pd.ga.y);
-            float2 det = cmul(mxx, mzz);
-            det.x -= gxz * gxz;
-            const float s = pd.gscale / (det.x * det.x + det.y * det.y);
-            const float2 inv = make_float2(det.x * s, -det.y * s);
-            const float2 Gxx = cmul(mzz, inv);
-            const float2 Gzz = cmul(mxx, inv);
-            const float2 Gxz = cscale(inv, -gxz);
-            const float2 bx = v[0][m], bz = v[1][m];
-            v[0][m] = cadd(cmul(Gxx, bx), cmul(Gxz, bz));
-            v[1][m] = cadd(cmul(Gxz, bx), cmul(Gzz, bz));
+            green_mul(v[0][m], v[1][m], axx + pd.gc55 * kz * kz, azz + pd.gc33 * kz * kz, axz * kzo,
+                      pd.ga, pd.gscale);
+            __builtin_amdgcn_sched_barrier(0);   // one point at a time: bounded registers
         }
         __syncthreads();
     }
-    if constexpr (MODE != COL_FWD) fft_run<N, P, true, 2>(v, tt, tw, lds);
+    if constexpr (MODE != COL_FWD) fft_run_seq<N, P, true, 2>(v, tt, tw, lds);
 
     if (active) {
 #pragma unroll
@@ -333,8 +343,8 @@ static hipError_t cols_n(int mode, float2* data, const ProbDev& pd, const SysSta
     const ColGeom g = col_geom(N, pd.nx);
     const int blocks = pd.nsys * (pd.nx / g.W);
     // idle threads (block padded to whole waves) need a private dummy slot
-    const int slots = g.W + (g.threads > g.W * FftShape<N, points_per_thread(N)>::T ? 1 : 0);
-    const size_t lds = (size_t)2 * PaddedLen<N>::value * slots * sizeof(float2);
+    const int slots = g.W + (g.threads > g.W * FftShape<N, col_points_per_thread(N)>::T ? 1 : 0);
+    const size_t lds = (size_t)PaddedLen<N>::value * slots * sizeof(float2);
     switch (mode) {
         case COL_GREEN:
             hipLaunchKernelGGL((k_cols<N, COL_GREEN>), dim3(blocks), dim3(g.threads), lds, s, data, pd,

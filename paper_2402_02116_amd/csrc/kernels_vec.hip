@@ -13,89 +13,156 @@ constexpr int kVecThreads = 256;
 constexpr int kVecEPT = 4;   // complex elements per thread in vector kernels
 
 // ------------------------------------------------------ contrast stencil --
-constexpr int STX = 64, STZ = 16;
+// A block owns a TZ x TX tile of cells and loops over S systems of the same
+// problem.  Threads are laid out 64 (x) by 4 (z); lanes x >= TX idle.  The
+// contrast of the tile (and of its 1-cell halo) is loaded into registers
+// together with the first displacement tile, and reused for every system.
+// Per system:
+//   1. the displacement tile with a 2-cell halo goes to LDS;
+//   2. the stress s' = dC e (e = raw central differences, 2 dx times the
+//      Voigt strain) is formed on the tile plus a 1-cell halo, in LDS;
+//   3. b = w~^2 drho u + (1 / 4 dx^2) div'(s') on the tile.
+constexpr int STX = 64, STZ = 8;
 
 __device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
-// Strain differences use raw central differences e = 2 dx * eps; the stress
-// s' = dC e and the divergence of s' carry 1 / (4 dx^2) at the end.
+template <int TX, int TZ>
 __global__ __launch_bounds__(256) void k_body_force(const float2* __restrict__ u,
                                                     float2* __restrict__ b,
                                                     const float* __restrict__ maps, ProbDev pd,
-                                                    int TX, int TZ,
-                                                    const SysState* __restrict__ st) {
-    __shared__ float2 su[2][STZ + 4][STX + 4];
-    __shared__ float2 ss[3][STZ + 2][STX + 2];
+                                                    int S, const SysState* __restrict__ st) {
+    static_assert(TX <= 64 && TZ % 4 == 0, "tile");
+    constexpr int HX = TX + 4, HZ = TZ + 4, SX = TX + 2, SZ = TZ + 2;
+    constexpr int KS = (SZ + 3) / 4;     // stress rows per thread
+    constexpr int KB = TZ / 4;           // output rows per thread
+    constexpr int KH = HZ / 4;           // displacement rows per thread
+    __shared__ float2 su[2][HZ][HX];
+    __shared__ float2 ss[3][SZ][SX];
     const int nx = pd.nx, nz = pd.nz;
     const size_t plane = (size_t)nx * nz;
-    const int ntx = nx / TX, ntz = nz / TZ;
-    const int ntiles = ntx * ntz;
+    const int ntx = nx / TX;
+    const int nsg = (pd.nsys + S - 1) / S;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int sys = blk / ntiles;
-    const int tile = blk - sys * ntiles;
+    const int tile = blk / nsg;              // neighbouring blocks: same tile, next systems
+    const int sys0 = (blk - tile * nsg) * S;
     const int z0 = (tile / ntx) * TZ, x0 = (tile % ntx) * TX;
-    if (st != nullptr && st[sys].status != ST_RUNNING) return;
-    const float2* us = u + (size_t)sys * 2 * plane;
-    float2* bs = b + (size_t)sys * 2 * plane;
+    const int tx = threadIdx.x & 63, tg = threadIdx.x >> 6;
+    const bool lane = tx < TX;
+    const int hsx = (tx == 0) ? 0 : TX + 1;   // halo stress column of lanes 0 and 1
+    const int hux = (tx < 2) ? tx : TX + tx;  // halo displacement column of lanes 0..3
 
-    const int HX = TX + 4, HZ = TZ + 4;
-    for (int i = threadIdx.x; i < 2 * HZ * HX; i += blockDim.x) {
-        const int f = i / (HZ * HX);
-        const int rem = i - f * HZ * HX;
-        const int hz = rem / HX, hx = rem - hz * HX;
-        const int gz = wrap(z0 - 2 + hz, nz), gx = wrap(x0 - 2 + hx, nx);
-        su[f][hz][hx] = us[f * plane + (size_t)gz * nx + gx];
+    float m_in[KS][4], m_h[KS][4], rho[KB];
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+        const int sz = tg + 4 * k;
+        const bool row = sz < SZ;
+        const size_t gz = (size_t)wrap(z0 - 1 + sz, nz) * nx;
+        const size_t gi = gz + (size_t)(x0 + (lane ? tx : 0));
+        const size_t gh = gz + (size_t)wrap(x0 - 1 + hsx, nx);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            m_in[k][c] = (row && lane) ? maps[c * plane + gi] : 0.f;
+            m_h[k][c] = (row && tx < 2) ? maps[c * plane + gh] : 0.f;
+        }
     }
-    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < KB; ++k)
+        rho[k] = lane ? maps[4 * plane + (size_t)(z0 + tg + 4 * k) * nx + x0 + tx] : 0.f;
 
-    const int SX = TX + 2, SZ = TZ + 2;
-    for (int i = threadIdx.x; i < SZ * SX; i += blockDim.x) {
-        const int sz = i / SX, sx = i - sz * SX;
-        const int hz = sz + 1, hx = sx + 1;
-        const float2 ex = csub(su[0][hz][hx + 1], su[0][hz][hx - 1]);
-        const float2 ez = csub(su[1][hz + 1][hx], su[1][hz - 1][hx]);
-        const float2 exz = cadd(csub(su[0][hz + 1][hx], su[0][hz - 1][hx]),
-                                csub(su[1][hz][hx + 1], su[1][hz][hx - 1]));
-        const int gz = wrap(z0 - 1 + sz, nz), gx = wrap(x0 - 1 + sx, nx);
-        const size_t gi = (size_t)gz * nx + gx;
-        const float c11 = maps[gi], c13 = maps[plane + gi], c33 = maps[2 * plane + gi],
-                    c55 = maps[3 * plane + gi];
-        ss[0][sz][sx] = make_float2(c11 * ex.x + c13 * ez.x, c11 * ex.y + c13 * ez.y);
-        ss[1][sz][sx] = make_float2(c13 * ex.x + c33 * ez.x, c13 * ex.y + c33 * ez.y);
-        ss[2][sz][sx] = cscale(exz, c55);
-    }
-    __syncthreads();
-
-    const float s = pd.inv4dx2;
-    for (int i = threadIdx.x; i < TZ * TX; i += blockDim.x) {
-        const int lz = i / TX, lx = i - lz * TX;
-        const int sz = lz + 1, sx = lx + 1;
-        const float2 dx1 = csub(ss[0][sz][sx + 1], ss[0][sz][sx - 1]);
-        const float2 dz5 = csub(ss[2][sz + 1][sx], ss[2][sz - 1][sx]);
-        const float2 dx5 = csub(ss[2][sz][sx + 1], ss[2][sz][sx - 1]);
-        const float2 dz3 = csub(ss[1][sz + 1][sx], ss[1][sz - 1][sx]);
-        const size_t gi = (size_t)(z0 + lz) * nx + (x0 + lx);
-        const float rho = maps[4 * plane + gi];
-        const float2 wr = cscale(pd.w2, rho);
-        const float2 ux = su[0][lz + 2][lx + 2], uz = su[1][lz + 2][lx + 2];
-        bs[gi] = cadd(cmul(wr, ux), cscale(cadd(dx1, dz5), s));
-        bs[plane + gi] = cadd(cmul(wr, uz), cscale(cadd(dx5, dz3), s));
+    const float sc = pd.inv4dx2;
+    for (int sys = sys0; sys < sys0 + S && sys < pd.nsys; ++sys) {
+        if (st != nullptr && st[sys].status != ST_RUNNING) continue;   // uniform over the block
+        const float2* us = u + (size_t)sys * 2 * plane;
+        float2* bs = b + (size_t)sys * 2 * plane;
+        __syncthreads();   // previous system's reads of su / ss are done
+#pragma unroll
+        for (int k = 0; k < KH; ++k) {
+            const int hz = tg + 4 * k;
+            const size_t row = (size_t)wrap(z0 - 2 + hz, nz) * nx;
+            if (lane) {
+                su[0][hz][tx + 2] = us[row + x0 + tx];
+                su[1][hz][tx + 2] = us[plane + row + x0 + tx];
+            }
+            if (tx < 4) {
+                const int gx = wrap(x0 - 2 + hux, nx);
+                su[0][hz][hux] = us[row + gx];
+                su[1][hz][hux] = us[plane + row + gx];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < KS; ++k) {
+            const int sz = tg + 4 * k;
+            if (sz < SZ) {
+                const int hz = sz + 1;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    if (h == 0 ? lane : (tx < 2)) {
+                        const int sx = (h == 0) ? tx + 1 : hsx;
+                        const int hx = sx + 1;
+                        const float* m = (h == 0) ? m_in[k] : m_h[k];
+                        const float2 ex = csub(su[0][hz][hx + 1], su[0][hz][hx - 1]);
+                        const float2 ez = csub(su[1][hz + 1][hx], su[1][hz - 1][hx]);
+                        const float2 exz = cadd(csub(su[0][hz + 1][hx], su[0][hz - 1][hx]),
+                                                csub(su[1][hz][hx + 1], su[1][hz][hx - 1]));
+                        ss[0][sz][sx] = make_float2(m[0] * ex.x + m[1] * ez.x, m[0] * ex.y + m[1] * ez.y);
+                        ss[1][sz][sx] = make_float2(m[1] * ex.x + m[2] * ez.x, m[1] * ex.y + m[2] * ez.y);
+                        ss[2][sz][sx] = cscale(exz, m[3]);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        if (lane) {
+#pragma unroll
+            for (int k = 0; k < KB; ++k) {
+                const int lz = tg + 4 * k;
+                const int sz = lz + 1, sx = tx + 1;
+                const float2 dx1 = csub(ss[0][sz][sx + 1], ss[0][sz][sx - 1]);
+                const float2 dz5 = csub(ss[2][sz + 1][sx], ss[2][sz - 1][sx]);
+                const float2 dx5 = csub(ss[2][sz][sx + 1], ss[2][sz][sx - 1]);
+                const float2 dz3 = csub(ss[1][sz + 1][sx], ss[1][sz - 1][sx]);
+                const float2 wr = cscale(pd.w2, rho[k]);
+                const size_t gi = (size_t)(z0 + lz) * nx + x0 + tx;
+                bs[gi] = cadd(cmul(wr, su[0][lz + 2][tx + 2]), cscale(cadd(dx1, dz5), sc));
+                bs[plane + gi] = cadd(cmul(wr, su[1][lz + 2][tx + 2]), cscale(cadd(dx5, dz3), sc));
+            }
+        }
     }
 }
 
-static int tile_dim(int n, int maxt) {
-    const int cand[] = {64, 48, 32, 24, 16, 12, 8};
+// Tile width for nx: the largest of 64, 48, 32, 24, 16 dividing it.
+static int tile_x(int nx) {
+    const int cand[] = {64, 48, 32, 24, 16};
     for (int c : cand)
-        if (c <= maxt && n % c == 0) return c;
+        if (nx % c == 0) return c;
     return 0;
+}
+
+template <int TX, int TZ>
+static void body_force_launch(const float2* u, float2* b, const float* maps, const ProbDev& pd,
+                              const SysState* st, hipStream_t s) {
+    const int ntiles = (pd.nx / TX) * (pd.nz / TZ);
+    // several systems per block once there are plenty of blocks
+    int S = 1;
+    while (S < pd.nsys && (long long)ntiles * ((pd.nsys + 2 * S - 1) / (2 * S)) >= 2048) S *= 2;
+    const int blocks = ntiles * ((pd.nsys + S - 1) / S);
+    hipLaunchKernelGGL((k_body_force<TX, TZ>), dim3(blocks), dim3(256), 0, s, u, b, maps, pd, S, st);
 }
 
 hipError_t launch_body_force(const float2* u, float2* b, const float* maps, const ProbDev& pd,
                              const SysState* st, hipStream_t s) {
-    const int TX = tile_dim(pd.nx, STX), TZ = tile_dim(pd.nz, STZ);
-    if (TX == 0 || TZ == 0) return hipErrorInvalidValue;
-    const int blocks = pd.nsys * (pd.nx / TX) * (pd.nz / TZ);
-    hipLaunchKernelGGL(k_body_force, dim3(blocks), dim3(256), 0, s, u, b, maps, pd, TX, TZ, st);
+    const int TX = tile_x(pd.nx);
+    if (TX == 0 || pd.nz % STZ != 0) return hipErrorInvalidValue;
+#define FW_BF(X)                                                                          \
+    case X:                                                                               \
+        body_force_launch<X, STZ>(u, b, maps, pd, st, s);                                 \
+        break;
+    switch (TX) {
+        FW_BF(64) FW_BF(48) FW_BF(32) FW_BF(24) FW_BF(16)
+        default: return hipErrorInvalidValue;
+    }
+#undef FW_BF
     return hipGetLastError();
 }
 
