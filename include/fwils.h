@@ -201,6 +201,52 @@ fwils_status fwils_apply_pass(fwils_plan plan, int32_t pass, const void* u, void
  * NULL.  Synchronous. */
 fwils_status fwils_solve_stats(fwils_plan plan, int32_t* iters, double* relres);
 
+/* ---- Generalised Tikhonov step (eqs. obj, norm) ------------------------
+ * Unknowns are relative maps q, float32 [5][nz][nx] on the device, with
+ * dm_p = m0_p q_p (m0: host double[5], e.g. the background C11, C13, C33,
+ * C55, rho0).  All problems of the plan must share one grid (nx, nz, dx);
+ * their data stack: J q = [J_1 q; J_2 q; ...], J* r = sum_f J_f* r_f.
+ * With rr = ||r||^2 and L = I or the periodic unscaled 5-point Laplacian:
+ *   f(q)      = ||J q - r||^2 / rr + lam ||L q||^2
+ *   grad f(q) = 2 m0 Re J*(J q - r) / rr + 2 lam L^T L q
+ *   N q       = m0 Re J*(J q) / rr + lam L^T L q          (normal operator)
+ * r: device data (complex64, plan data layout); dscratch: device complex64
+ * buffer with the same number of elements as r; ub: background solutions.
+ * Every J and J* application is one LS solve per system (rtol, maxit). */
+#define FWILS_REG_IDENTITY  0
+#define FWILS_REG_LAPLACIAN 1
+
+/* grad (device float [5][nz][nx]) and, if fval != NULL, *fval = f(q).  Synchronous. */
+fwils_status fwils_tikhonov_grad(fwils_plan plan, const void* ub, const void* r, const double* m0,
+                                 double lam, int32_t reg, const float* q, float* grad, double* fval,
+                                 void* dscratch, double rtol, int32_t maxit);
+
+/* q_out = N q_in for a given rr (> 0).  Synchronous. */
+fwils_status fwils_normal_apply(fwils_plan plan, const void* ub, const double* m0, double rr,
+                                double lam, int32_t reg, const float* q_in, float* q_out,
+                                void* dscratch, double rtol, int32_t maxit);
+
+/* niter iterations (1..1000) of CG on N q = m0 Re J* r / rr (eq. norm) from q = 0,
+ * FP64 scalars kept on the device.  q: device output.  hist (host double
+ * [niter + 1] or NULL) receives the normal-equation residual norm before each
+ * iteration and after the last.  Synchronous. */
+fwils_status fwils_normal_cg(fwils_plan plan, const void* ub, const void* r, const double* m0,
+                             double lam, int32_t reg, int32_t niter, float* q, double* hist,
+                             void* dscratch, double rtol, int32_t maxit);
+
+/* J and J* in the relative units of the Tikhonov step (single-grid plans):
+ *   fwils_frechet_rel: d = J (m0 q)                     (q: device float [5][nz][nx])
+ *   fwils_adjoint_rel: gq = m0 Re(J* r), summed over problems (gq: device float)
+ * These are the forward and backward of the differentiable operator q -> J q. */
+fwils_status fwils_frechet_rel(fwils_plan plan, const void* ub, const float* q, const double* m0,
+                               void* d, double rtol, int32_t maxit);
+fwils_status fwils_adjoint_rel(fwils_plan plan, const void* ub, const void* r, const double* m0,
+                               float* gq, double rtol, int32_t maxit);
+
+/* out = L q: periodic unscaled 5-point Laplacian of the 5 maps [5][nz][nx]
+ * (single-grid plans).  Self-adjoint, so it is also L^T q. */
+fwils_status fwils_laplacian(fwils_plan plan, const float* q, float* out);
+
 /* 2-D FFT of every field of problem iprob with the library's own transform
  * kernels (unnormalised forward, exp(-i k.x); inverse with exp(+i k.x) and
  * no 1/(nx nz)).  A self-test entry point.  in, out: device, may alias. */

@@ -9,14 +9,15 @@ no CPU fallback: without the built library or a GPU, calls raise.
 
 from ._lib import FwilsError, FwilsLibraryError, load  # noqa: F401
 
-__all__ = ["Plan", "FrechetFn", "load", "FwilsError", "FwilsLibraryError"]
+__all__ = ["Plan", "FrechetFn", "FrechetOperator", "LaplacianFn", "tikhonov_loss", "load", "FwilsError",
+           "FwilsLibraryError"]
 
 
 def __getattr__(name):
     if name == "Plan":
         from .plan import Plan
         return Plan
-    if name in ("FrechetFn", "frechet_operator"):
+    if name in ("FrechetFn", "FrechetOperator", "LaplacianFn", "tikhonov_loss"):
         from . import autograd
         return getattr(autograd, name)
     raise AttributeError(name)

@@ -20,6 +20,7 @@ FWILS_C64 = 0
 FWILS_SYMBOL_SPECTRAL, FWILS_SYMBOL_CENTRAL = 0, 1
 FWILS_SOLVE_X0, FWILS_SOLVE_PLAIN, FWILS_SOLVE_NOGRAPH = 0x1, 0x2, 0x4
 FWILS_ADJ_ACCUMULATE = 0x1
+FWILS_REG_IDENTITY, FWILS_REG_LAPLACIAN = 0, 1
 
 
 class FwilsProblem(ctypes.Structure):
@@ -47,6 +48,15 @@ SIGNATURES = {
     "fwils_adjoint": (c_int32, [P, P, P, ctypes.POINTER(c_void_p), c_uint32, c_double, c_int32]),
     "fwils_fft2": (c_int32, [P, c_int32, P, P, c_int32]),
     "fwils_apply_pass": (c_int32, [P, c_int32, P, P]),
+    "fwils_tikhonov_grad": (c_int32, [P, P, P, ctypes.POINTER(c_double), c_double, c_int32, P, P,
+                                      ctypes.POINTER(c_double), P, c_double, c_int32]),
+    "fwils_normal_apply": (c_int32, [P, P, ctypes.POINTER(c_double), c_double, c_double, c_int32, P, P, P,
+                                     c_double, c_int32]),
+    "fwils_normal_cg": (c_int32, [P, P, P, ctypes.POINTER(c_double), c_double, c_int32, c_int32, P,
+                                  ctypes.POINTER(c_double), P, c_double, c_int32]),
+    "fwils_frechet_rel": (c_int32, [P, P, P, ctypes.POINTER(c_double), P, c_double, c_int32]),
+    "fwils_adjoint_rel": (c_int32, [P, P, P, ctypes.POINTER(c_double), P, c_double, c_int32]),
+    "fwils_laplacian": (c_int32, [P, P, P]),
     "fwils_solve_stats": (c_int32, [P, ctypes.POINTER(c_int32), ctypes.POINTER(c_double)]),
     "fwils_status_string": (ctypes.c_char_p, [c_int32]),
     "fwils_last_error": (ctypes.c_char_p, []),

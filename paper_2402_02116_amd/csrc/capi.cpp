@@ -46,6 +46,7 @@ void set_error(const char* fmt, ...) {
 
 constexpr int kMaxRec = 65536;
 constexpr int kChunkIters = 4;
+constexpr int kMaxCgIters = 1000;
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -83,6 +84,12 @@ struct fwils_plan_s {
     double* src_f = nullptr;
     float2 *x = nullptr, *r = nullptr, *rhat = nullptr, *p = nullptr, *v = nullptr, *s = nullptr,
            *t = nullptr, *tmp = nullptr, *rhs = nullptr;
+    // model-map scratch of the Tikhonov step (single-grid plans only)
+    size_t map_n = 0, off_mapws = 0;
+    float *mq_dm = nullptr, *mq_x = nullptr, *mq_res = nullptr, *mq_p = nullptr, *mq_Ap = nullptr,
+          *mq_l1 = nullptr, *mq_l2 = nullptr;
+    float2* mq_g = nullptr;
+    double *mq_part = nullptr, *mq_sc = nullptr, *mq_hist = nullptr;
     // graph of one chunk of iterations over all problems
     hipGraphExec_t chunk = nullptr;
     SysState* host_state = nullptr;   // pinned
@@ -429,6 +436,17 @@ fwils_status fwils_plan_create(const fwils_problem* probs, int32_t nprob, fwils_
     o = align256(o + pl->total_sys * 2 * (sizeof(int32_t) + sizeof(double)));
     pl->off_vec = o;
     o += 9 * align256(pl->total_field * sizeof(float2));
+    bool one_grid = true;
+    for (int i = 1; i < nprob; ++i)
+        one_grid = one_grid && probs[i].nx == probs[0].nx && probs[i].nz == probs[0].nz &&
+                   probs[i].dx == probs[0].dx;
+    pl->map_n = one_grid ? (size_t)probs[0].nx * probs[0].nz : 0;
+    pl->off_mapws = o;
+    if (pl->map_n) {
+        o += 7 * align256(5 * pl->map_n * sizeof(float)) + align256(5 * pl->map_n * sizeof(float2));
+        o += align256(kDotPartials * sizeof(double)) + align256(16 * sizeof(double)) +
+             align256(kMaxCgIters + 1) * sizeof(double);
+    }
     pl->ws_bytes = o;
     *out = pl;
     return FWILS_OK;
@@ -497,6 +515,21 @@ fwils_status fwils_set_workspace(fwils_plan plan, void* dev, size_t bytes) {
                         &plan->s, &plan->t, &plan->tmp, &plan->rhs};
     const size_t vb = align256(plan->total_field * sizeof(float2));
     for (int i = 0; i < 9; ++i) *vecs[i] = (float2*)(w + plan->off_vec + i * vb);
+    if (plan->map_n) {
+        char* m = w + plan->off_mapws;
+        const size_t fb = align256(5 * plan->map_n * sizeof(float));
+        float** fm[7] = {&plan->mq_dm, &plan->mq_x, &plan->mq_res, &plan->mq_p,
+                         &plan->mq_Ap, &plan->mq_l1, &plan->mq_l2};
+        for (int i = 0; i < 7; ++i) *fm[i] = (float*)(m + i * fb);
+        m += 7 * fb;
+        plan->mq_g = (float2*)m;
+        m += align256(5 * plan->map_n * sizeof(float2));
+        plan->mq_part = (double*)m;
+        m += align256(kDotPartials * sizeof(double));
+        plan->mq_sc = (double*)m;
+        m += align256(16 * sizeof(double));
+        plan->mq_hist = (double*)m;
+    }
     std::vector<float2> tw(twiddle_table_elems());
     twiddle_table_fill(tw.data());
     FW_HIP(hipMemcpy(plan->tw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice));
@@ -623,50 +656,35 @@ fwils_status fwils_solve(fwils_plan plan, const void* rhs, void* x, double rtol,
     return st;
 }
 
-fwils_status fwils_frechet(fwils_plan plan, const void* ub, const float* const* dm, void* d,
-                           double rtol, int32_t maxit) {
-    FW_TRY(check_plan(plan));
-    FW_TRY(check_field_ptrs({ub, dm, d}));
-    for (size_t i = 0; i < plan->probs.size(); ++i) {
-        if (!dm[i] || plan->probs[i].nrec < 1) {
-            set_error("frechet: problem %zu has a null dm pointer or no receivers", i);
-            return FWILS_EINVAL;
-        }
-    }
-    if (!(rtol > 0) || maxit < 1) {
-        set_error("frechet: need rtol > 0 and maxit >= 1");
-        return FWILS_EINVAL;
-    }
+}  // extern "C"
+
+namespace {
+
+// J dm (validated arguments): one virtual source, one convolution and one
+// gather per problem around one batched solve.
+fwils_status frechet_ws(fwils_plan plan, const void* ub, const float* const* dm, void* d, double rtol,
+                        int32_t maxit) {
     hipStream_t s = plan->stream;
     for (size_t i = 0; i < plan->probs.size(); ++i) {
         const ProbHost& P = plan->probs[i];
-        // virtual source P_b(dm) (same stencil as the contrast, with u^b and dm)
+        // virtual source P_b(dm): the contrast stencil applied to u^b with dm
         FW_HIP(launch_body_force(at(ub, P), at(plan->s, P), dm[i], P.dev, nullptr, s));
         FW_HIP(conv_problem(plan, P, at(plan->s, P), at(plan->rhs, P)));
     }
     fwils_status st = solve_ws(plan, plan->rhs, false, rtol, maxit, nullptr, nullptr, 0);
     if (st == FWILS_EDEVICE) return st;
-    for (const ProbHost& P : plan->probs)
+    for (size_t i = 0; i < plan->probs.size(); ++i) {
+        const ProbHost& P = plan->probs[i];
         FW_HIP(launch_gather(at(plan->x, P), static_cast<float2*>(d) + P.data_off,
-                             plan->rec + (size_t)(&P - plan->probs.data()) * kMaxRec * 2, P.nrec, P.dev, s));
-    FW_HIP(hipStreamSynchronize(s));
+                             plan->rec + i * kMaxRec * 2, P.nrec, P.dev, s));
+    }
     return st;
 }
 
-fwils_status fwils_adjoint(fwils_plan plan, const void* ub, const void* r, void* const* g,
-                           uint32_t flags, double rtol, int32_t maxit) {
-    FW_TRY(check_plan(plan));
-    FW_TRY(check_field_ptrs({ub, r, g}));
-    for (size_t i = 0; i < plan->probs.size(); ++i) {
-        if (!g[i] || plan->probs[i].nrec < 1) {
-            set_error("adjoint: problem %zu has a null g pointer or no receivers", i);
-            return FWILS_EINVAL;
-        }
-    }
-    if (!(rtol > 0) || maxit < 1 || (flags & ~FWILS_ADJ_ACCUMULATE)) {
-        set_error("adjoint: need rtol > 0, maxit >= 1 and known flags");
-        return FWILS_EINVAL;
-    }
+// J* r (validated arguments): receiver scatter and convolution per problem,
+// one batched solve, correlation with u^b per problem.
+fwils_status adjoint_ws(fwils_plan plan, const void* ub, const void* r, void* const* g, bool accumulate,
+                        double rtol, int32_t maxit) {
     hipStream_t s = plan->stream;
     for (size_t i = 0; i < plan->probs.size(); ++i) {
         const ProbHost& P = plan->probs[i];
@@ -681,8 +699,281 @@ fwils_status fwils_adjoint(fwils_plan plan, const void* ub, const void* r, void*
     for (size_t i = 0; i < plan->probs.size(); ++i) {
         const ProbHost& P = plan->probs[i];
         FW_HIP(launch_correlate(at(plan->x, P), at(ub, P), static_cast<float2*>(g[i]), P.dev,
-                                (flags & FWILS_ADJ_ACCUMULATE) != 0, s));
+                                accumulate, s));
     }
+    return st;
+}
+
+fwils_status check_jj(fwils_plan plan, double rtol, int32_t maxit, const char* what) {
+    for (size_t i = 0; i < plan->probs.size(); ++i) {
+        if (plan->probs[i].nrec < 1) {
+            set_error("%s: problem %zu has no receivers", what, i);
+            return FWILS_EINVAL;
+        }
+    }
+    if (!(rtol > 0) || maxit < 1) {
+        set_error("%s: need rtol > 0 and maxit >= 1", what);
+        return FWILS_EINVAL;
+    }
+    return FWILS_OK;
+}
+
+fwils_status worst(fwils_status a, fwils_status b) {
+    if (a == FWILS_EBREAKDOWN || b == FWILS_EBREAKDOWN) return FWILS_EBREAKDOWN;
+    if (a == FWILS_ENOCONV || b == FWILS_ENOCONV) return FWILS_ENOCONV;
+    return a != FWILS_OK ? a : b;
+}
+
+// ---- Tikhonov step --------------------------------------------------------
+fwils_status check_tik(fwils_plan plan, const double* m0, double lam, int32_t reg, double rtol,
+                       int32_t maxit, const char* what) {
+    FW_TRY(check_jj(plan, rtol, maxit, what));
+    if (!plan->map_n) {
+        set_error("%s: the plan's problems do not share one grid", what);
+        return FWILS_EINVAL;
+    }
+    if (!m0 || !(lam >= 0) || (reg != FWILS_REG_IDENTITY && reg != FWILS_REG_LAPLACIAN)) {
+        set_error("%s: need m0[5], lam >= 0 and a known regulariser", what);
+        return FWILS_EINVAL;
+    }
+    for (int k = 0; k < 5; ++k)
+        if (!std::isfinite(m0[k])) {
+            set_error("%s: m0 must be finite", what);
+            return FWILS_EINVAL;
+        }
+    return FWILS_OK;
+}
+
+size_t data_elems(fwils_plan plan) {
+    size_t n = 0;
+    for (const ProbHost& P : plan->probs) n += (size_t)P.p.nsys * P.nrec * 2;
+    return n;
+}
+
+// reg_out = L^T L q (Laplacian) or q (identity) into mq_l2; also L q in mq_l1.
+fwils_status regulariser(fwils_plan plan, int32_t reg, const float* q, const float** rq) {
+    const ProbHost& P = plan->probs[0];
+    if (reg == FWILS_REG_LAPLACIAN) {
+        FW_HIP(launch_laplacian(q, plan->mq_l1, P.p.nx, P.p.nz, 5, plan->stream));
+        FW_HIP(launch_laplacian(plan->mq_l1, plan->mq_l2, P.p.nx, P.p.nz, 5, plan->stream));
+        *rq = plan->mq_l2;
+    } else {
+        *rq = q;
+    }
+    return FWILS_OK;
+}
+
+// out = N q for a given rr (the normal operator of eq. norm)
+fwils_status normal_apply_ws(fwils_plan plan, const void* ub, const MapScales& m0, double rr, double lam,
+                             int32_t reg, const float* q, float* out, void* dscratch, double rtol,
+                             int32_t maxit) {
+    hipStream_t s = plan->stream;
+    const int n = (int)plan->map_n;
+    FW_HIP(launch_map_scale(q, plan->mq_dm, m0, n, s));
+    std::vector<const float*> dms(plan->probs.size(), plan->mq_dm);
+    fwils_status st = frechet_ws(plan, ub, dms.data(), dscratch, rtol, maxit);
+    if (st == FWILS_EDEVICE) return st;
+    std::vector<void*> gs(plan->probs.size(), plan->mq_g);
+    FW_HIP(launch_zero(plan->mq_g, 5 * plan->map_n, s));
+    fwils_status st2 = adjoint_ws(plan, ub, dscratch, gs.data(), true, rtol, maxit);
+    if (st2 == FWILS_EDEVICE) return st2;
+    const float* rq = nullptr;
+    FW_TRY(regulariser(plan, reg, q, &rq));
+    FW_HIP(launch_map_combine(plan->mq_g, rq, out, m0, 1.0 / rr, lam, n, s));
+    return worst(st, st2);
+}
+
+MapScales scales(const double* m0) {
+    MapScales m;
+    for (int k = 0; k < 5; ++k) m.s[k] = m0[k];
+    return m;
+}
+
+}  // namespace
+
+extern "C" {
+
+fwils_status fwils_frechet(fwils_plan plan, const void* ub, const float* const* dm, void* d,
+                           double rtol, int32_t maxit) {
+    FW_TRY(check_plan(plan));
+    FW_TRY(check_field_ptrs({ub, dm, d}));
+    for (size_t i = 0; i < plan->probs.size(); ++i) {
+        if (!dm[i]) {
+            set_error("frechet: problem %zu has a null dm pointer", i);
+            return FWILS_EINVAL;
+        }
+    }
+    FW_TRY(check_jj(plan, rtol, maxit, "frechet"));
+    fwils_status st = frechet_ws(plan, ub, dm, d, rtol, maxit);
+    if (st == FWILS_EDEVICE) return st;
+    FW_HIP(hipStreamSynchronize(plan->stream));
+    return st;
+}
+
+fwils_status fwils_adjoint(fwils_plan plan, const void* ub, const void* r, void* const* g,
+                           uint32_t flags, double rtol, int32_t maxit) {
+    FW_TRY(check_plan(plan));
+    FW_TRY(check_field_ptrs({ub, r, g}));
+    for (size_t i = 0; i < plan->probs.size(); ++i) {
+        if (!g[i]) {
+            set_error("adjoint: problem %zu has a null g pointer", i);
+            return FWILS_EINVAL;
+        }
+    }
+    FW_TRY(check_jj(plan, rtol, maxit, "adjoint"));
+    if (flags & ~FWILS_ADJ_ACCUMULATE) {
+        set_error("adjoint: unknown flags");
+        return FWILS_EINVAL;
+    }
+    fwils_status st = adjoint_ws(plan, ub, r, g, (flags & FWILS_ADJ_ACCUMULATE) != 0, rtol, maxit);
+    if (st == FWILS_EDEVICE) return st;
+    FW_HIP(hipStreamSynchronize(plan->stream));
+    return st;
+}
+
+fwils_status fwils_normal_apply(fwils_plan plan, const void* ub, const double* m0, double rr, double lam,
+                                int32_t reg, const float* q_in, float* q_out, void* dscratch, double rtol,
+                                int32_t maxit) {
+    FW_TRY(check_plan(plan));
+    FW_TRY(check_field_ptrs({ub, q_in, q_out, dscratch}));
+    FW_TRY(check_tik(plan, m0, lam, reg, rtol, maxit, "normal_apply"));
+    if (!(rr > 0) || q_in == q_out) {
+        set_error("normal_apply: need rr > 0 and distinct q_in, q_out");
+        return FWILS_EINVAL;
+    }
+    fwils_status st = normal_apply_ws(plan, ub, scales(m0), rr, lam, reg, q_in, q_out, dscratch, rtol, maxit);
+    if (st == FWILS_EDEVICE) return st;
+    FW_HIP(hipStreamSynchronize(plan->stream));
+    return st;
+}
+
+fwils_status fwils_tikhonov_grad(fwils_plan plan, const void* ub, const void* r, const double* m0, double lam,
+                                 int32_t reg, const float* q, float* grad, double* fval, void* dscratch,
+                                 double rtol, int32_t maxit) {
+    FW_TRY(check_plan(plan));
+    FW_TRY(check_field_ptrs({ub, r, q, grad, dscratch}));
+    FW_TRY(check_tik(plan, m0, lam, reg, rtol, maxit, "tikhonov_grad"));
+    hipStream_t s = plan->stream;
+    const MapScales ms = scales(m0);
+    const int n = (int)plan->map_n;
+    const size_t nd = data_elems(plan);
+    double* sc = plan->mq_sc;
+    // rr = ||r||^2
+    FW_HIP(launch_norm2_complex(static_cast<const float2*>(r), nd, plan->mq_part, sc + 4, s));
+    // residual J q - r and its norm
+    FW_HIP(launch_map_scale(q, plan->mq_dm, ms, n, s));
+    std::vector<const float*> dms(plan->probs.size(), plan->mq_dm);
+    fwils_status st = frechet_ws(plan, ub, dms.data(), dscratch, rtol, maxit);
+    if (st == FWILS_EDEVICE) return st;
+    FW_HIP(launch_sub_complex(static_cast<float2*>(dscratch), static_cast<const float2*>(r), nd, s));
+    FW_HIP(launch_norm2_complex(static_cast<const float2*>(dscratch), nd, plan->mq_part, sc + 5, s));
+    std::vector<void*> gs(plan->probs.size(), plan->mq_g);
+    FW_HIP(launch_zero(plan->mq_g, 5 * plan->map_n, s));
+    fwils_status st2 = adjoint_ws(plan, ub, dscratch, gs.data(), true, rtol, maxit);
+    if (st2 == FWILS_EDEVICE) return st2;
+    const float* rq = nullptr;
+    FW_TRY(regulariser(plan, reg, q, &rq));
+    // ||L q||^2
+    const float* lq = (reg == FWILS_REG_LAPLACIAN) ? plan->mq_l1 : q;
+    FW_HIP(launch_dot_real(lq, lq, 5 * plan->map_n, plan->mq_part, sc + 6, s));
+    double h[3];
+    FW_HIP(hipMemcpyAsync(h, sc + 4, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+    FW_HIP(hipStreamSynchronize(s));
+    if (!(h[0] > 0)) {
+        set_error("tikhonov_grad: ||r|| is zero");
+        return FWILS_EINVAL;
+    }
+    FW_HIP(launch_map_combine(plan->mq_g, rq, grad, ms, 2.0 / h[0], 2.0 * lam, n, s));
+    FW_HIP(hipStreamSynchronize(s));
+    if (fval) *fval = h[1] / h[0] + lam * h[2];
+    return worst(st, st2);
+}
+
+fwils_status fwils_frechet_rel(fwils_plan plan, const void* ub, const float* q, const double* m0, void* d,
+                               double rtol, int32_t maxit) {
+    FW_TRY(check_plan(plan));
+    FW_TRY(check_field_ptrs({ub, q, d}));
+    FW_TRY(check_tik(plan, m0, 0.0, FWILS_REG_IDENTITY, rtol, maxit, "frechet_rel"));
+    FW_HIP(launch_map_scale(q, plan->mq_dm, scales(m0), (int)plan->map_n, plan->stream));
+    std::vector<const float*> dms(plan->probs.size(), plan->mq_dm);
+    fwils_status st = frechet_ws(plan, ub, dms.data(), d, rtol, maxit);
+    if (st == FWILS_EDEVICE) return st;
+    FW_HIP(hipStreamSynchronize(plan->stream));
+    return st;
+}
+
+fwils_status fwils_adjoint_rel(fwils_plan plan, const void* ub, const void* r, const double* m0, float* gq,
+                               double rtol, int32_t maxit) {
+    FW_TRY(check_plan(plan));
+    FW_TRY(check_field_ptrs({ub, r, gq}));
+    FW_TRY(check_tik(plan, m0, 0.0, FWILS_REG_IDENTITY, rtol, maxit, "adjoint_rel"));
+    std::vector<void*> gs(plan->probs.size(), plan->mq_g);
+    FW_HIP(launch_zero(plan->mq_g, 5 * plan->map_n, plan->stream));
+    fwils_status st = adjoint_ws(plan, ub, r, gs.data(), true, rtol, maxit);
+    if (st == FWILS_EDEVICE) return st;
+    FW_HIP(launch_map_combine(plan->mq_g, nullptr, gq, scales(m0), 1.0, 0.0, (int)plan->map_n, plan->stream));
+    FW_HIP(hipStreamSynchronize(plan->stream));
+    return st;
+}
+
+fwils_status fwils_laplacian(fwils_plan plan, const float* q, float* out) {
+    FW_TRY(check_plan(plan));
+    FW_TRY(check_field_ptrs({q, out}));
+    if (!plan->map_n || q == out) {
+        set_error("laplacian: needs a single-grid plan and distinct q, out");
+        return FWILS_EINVAL;
+    }
+    FW_HIP(launch_laplacian(q, out, plan->probs[0].p.nx, plan->probs[0].p.nz, 5, plan->stream));
+    return FWILS_OK;
+}
+
+fwils_status fwils_normal_cg(fwils_plan plan, const void* ub, const void* r, const double* m0, double lam,
+                             int32_t reg, int32_t niter, float* q, double* hist, void* dscratch, double rtol,
+                             int32_t maxit) {
+    FW_TRY(check_plan(plan));
+    FW_TRY(check_field_ptrs({ub, r, q, dscratch}));
+    FW_TRY(check_tik(plan, m0, lam, reg, rtol, maxit, "normal_cg"));
+    if (niter < 1 || niter > kMaxCgIters) {
+        set_error("normal_cg: niter must be 1..%d", kMaxCgIters);
+        return FWILS_EINVAL;
+    }
+    hipStream_t s = plan->stream;
+    const MapScales ms = scales(m0);
+    const int n = (int)plan->map_n;
+    const size_t nm = 5 * plan->map_n;
+    double* sc = plan->mq_sc;
+    // rr and the right-hand side m0 Re J* r / rr
+    FW_HIP(launch_norm2_complex(static_cast<const float2*>(r), data_elems(plan), plan->mq_part, sc + 4, s));
+    double rr = 0;
+    FW_HIP(hipMemcpyAsync(&rr, sc + 4, sizeof(double), hipMemcpyDeviceToHost, s));
+    FW_HIP(hipStreamSynchronize(s));
+    if (!(rr > 0)) {
+        set_error("normal_cg: ||r|| is zero");
+        return FWILS_EINVAL;
+    }
+    std::vector<void*> gs(plan->probs.size(), plan->mq_g);
+    FW_HIP(launch_zero(plan->mq_g, nm, s));
+    fwils_status st = adjoint_ws(plan, ub, r, gs.data(), true, rtol, maxit);
+    if (st == FWILS_EDEVICE) return st;
+    FW_HIP(launch_map_combine(plan->mq_g, nullptr, plan->mq_res, ms, 1.0 / rr, 0.0, n, s));
+    FW_HIP(launch_zero_f(plan->mq_x, nm, s));
+    FW_HIP(launch_copy_f(plan->mq_res, plan->mq_p, nm, s));
+    FW_HIP(launch_dot_real(plan->mq_res, plan->mq_res, nm, plan->mq_part, sc + 2, s));
+    FW_HIP(launch_cg_shift(sc, plan->mq_hist, 0, s));
+    for (int it = 0; it < niter; ++it) {
+        fwils_status sa = normal_apply_ws(plan, ub, ms, rr, lam, reg, plan->mq_p, plan->mq_Ap, dscratch,
+                                          rtol, maxit);
+        if (sa == FWILS_EDEVICE) return sa;
+        st = worst(st, sa);
+        FW_HIP(launch_dot_real(plan->mq_p, plan->mq_Ap, nm, plan->mq_part, sc + 1, s));
+        FW_HIP(launch_cg_xr(plan->mq_x, plan->mq_res, plan->mq_p, plan->mq_Ap, sc, nm, s));
+        FW_HIP(launch_dot_real(plan->mq_res, plan->mq_res, nm, plan->mq_part, sc + 2, s));
+        FW_HIP(launch_cg_p(plan->mq_p, plan->mq_res, sc, nm, s));
+        FW_HIP(launch_cg_shift(sc, plan->mq_hist, it + 1, s));
+    }
+    FW_HIP(launch_copy_f(plan->mq_x, q, nm, s));
+    if (hist)
+        FW_HIP(hipMemcpyAsync(hist, plan->mq_hist, (size_t)(niter + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
     FW_HIP(hipStreamSynchronize(s));
     return st;
 }

@@ -81,4 +81,22 @@ hipError_t launch_correlate(const float2* ua, const float2* ub, float2* g, const
 hipError_t launch_copy(const float2* src, float2* dst, size_t n, hipStream_t s);
 hipError_t launch_zero(float2* dst, size_t n, hipStream_t s);
 
+// Tikhonov-step model maps (5 maps of one grid).
+struct MapScales { double s[5]; };
+hipError_t launch_map_scale(const float* q, float* out, const MapScales& m0, int n, hipStream_t s);
+hipError_t launch_laplacian(const float* q, float* out, int nx, int nz, int nmaps, hipStream_t s);
+hipError_t launch_map_combine(const float2* g, const float* reg, float* out, const MapScales& m0,
+                              double cj, double cl, int n, hipStream_t s);
+constexpr int kDotPartials = 512;
+hipError_t launch_dot_real(const float* a, const float* b, size_t n, double* part, double* out,
+                           hipStream_t s);
+hipError_t launch_norm2_complex(const float2* a, size_t n, double* part, double* out, hipStream_t s);
+hipError_t launch_cg_xr(float* x, float* res, const float* p, const float* Ap, const double* sc, size_t n,
+                        hipStream_t s);
+hipError_t launch_cg_p(float* p, const float* res, const double* sc, size_t n, hipStream_t s);
+hipError_t launch_cg_shift(double* sc, double* hist, int it, hipStream_t s);
+hipError_t launch_copy_f(const float* a, float* b, size_t n, hipStream_t s);
+hipError_t launch_zero_f(float* b, size_t n, hipStream_t s);
+hipError_t launch_sub_complex(float2* d, const float2* r, size_t n, hipStream_t s);
+
 }  // namespace fw

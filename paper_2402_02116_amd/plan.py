@@ -268,6 +268,106 @@ class Plan:
               "fwils_solve_stats")
         return it, rr
 
+    # ------------------------------------------------- Tikhonov step ----
+    REGS = {"identity": _lib.FWILS_REG_IDENTITY, "laplacian": _lib.FWILS_REG_LAPLACIAN}
+
+    def _maps(self, q, name):
+        p = self.problems[0]
+        _require_cuda(q, torch.float32, name)
+        if tuple(q.shape) != (5, p["nz"], p["nx"]):
+            raise ValueError(f"{name} must be [5, {p['nz']}, {p['nx']}]")
+        return q
+
+    @staticmethod
+    def _m0(m0):
+        a = np.ascontiguousarray(np.asarray(m0, dtype=np.float64).reshape(5))
+        return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+    def _data(self, r, name):
+        _require_cuda(r, torch.complex64, name)
+        if r.numel() != self.data_elems():
+            raise ValueError(f"{name} must hold {self.data_elems()} complex values")
+        return r
+
+    def frechet_rel(self, ub, q, m0, rtol=1e-6, maxit=1000):
+        """d = J (m0 q) for relative maps q [5, nz, nx] (float32)."""
+        self._field(ub, "ub")
+        self._maps(q, "q")
+        m, mp = self._m0(m0)
+        d = torch.zeros(self.data_elems(), dtype=torch.complex64, device=self.device)
+        self._bind_stream()
+        st = self.lib.fwils_frechet_rel(self._h, _ptr(ub), _ptr(q), mp, _ptr(d), float(rtol), int(maxit))
+        if st != _lib.FWILS_OK:
+            check(st, "fwils_frechet_rel")
+        return d
+
+    def adjoint_rel(self, ub, r, m0, rtol=1e-6, maxit=1000):
+        """gq = m0 Re(J* r) summed over problems, float32 [5, nz, nx]."""
+        self._field(ub, "ub")
+        self._data(r, "r")
+        m, mp = self._m0(m0)
+        p = self.problems[0]
+        gq = torch.zeros(5, p["nz"], p["nx"], dtype=torch.float32, device=self.device)
+        self._bind_stream()
+        st = self.lib.fwils_adjoint_rel(self._h, _ptr(ub), _ptr(r), mp, _ptr(gq), float(rtol), int(maxit))
+        if st != _lib.FWILS_OK:
+            check(st, "fwils_adjoint_rel")
+        return gq
+
+    def laplacian(self, q):
+        self._maps(q, "q")
+        out = torch.empty_like(q)
+        self._bind_stream()
+        check(self.lib.fwils_laplacian(self._h, _ptr(q), _ptr(out)), "fwils_laplacian")
+        return out
+
+    def tikhonov_grad(self, ub, r, m0, q, lam=1e-3, reg="laplacian", rtol=1e-6, maxit=1000):
+        """(f(q), grad f(q)) of the generalised Tikhonov objective."""
+        self._field(ub, "ub")
+        self._data(r, "r")
+        self._maps(q, "q")
+        m, mp = self._m0(m0)
+        grad = torch.empty_like(q)
+        d = torch.empty_like(r)
+        f = ctypes.c_double()
+        self._bind_stream()
+        st = self.lib.fwils_tikhonov_grad(self._h, _ptr(ub), _ptr(r), mp, float(lam), self.REGS[reg],
+                                          _ptr(q), _ptr(grad), ctypes.byref(f), _ptr(d), float(rtol),
+                                          int(maxit))
+        if st != _lib.FWILS_OK:
+            check(st, "fwils_tikhonov_grad")
+        return f.value, grad
+
+    def normal_apply(self, ub, m0, rr, q, lam=1e-3, reg="identity", rtol=1e-6, maxit=1000):
+        self._field(ub, "ub")
+        self._maps(q, "q")
+        m, mp = self._m0(m0)
+        out = torch.empty_like(q)
+        d = torch.zeros(self.data_elems(), dtype=torch.complex64, device=self.device)
+        self._bind_stream()
+        st = self.lib.fwils_normal_apply(self._h, _ptr(ub), mp, float(rr), float(lam), self.REGS[reg],
+                                         _ptr(q), _ptr(out), _ptr(d), float(rtol), int(maxit))
+        if st != _lib.FWILS_OK:
+            check(st, "fwils_normal_apply")
+        return out
+
+    def normal_cg(self, ub, r, m0, niter=20, lam=1e-3, reg="identity", rtol=1e-6, maxit=1000):
+        """niter CG iterations on the normal equation from q = 0: (q, residual history)."""
+        self._field(ub, "ub")
+        self._data(r, "r")
+        m, mp = self._m0(m0)
+        p = self.problems[0]
+        q = torch.empty(5, p["nz"], p["nx"], dtype=torch.float32, device=self.device)
+        d = torch.empty_like(r)
+        hist = np.zeros(niter + 1, dtype=np.float64)
+        self._bind_stream()
+        st = self.lib.fwils_normal_cg(self._h, _ptr(ub), _ptr(r), mp, float(lam), self.REGS[reg],
+                                      int(niter), _ptr(q), hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                      _ptr(d), float(rtol), int(maxit))
+        if st != _lib.FWILS_OK:
+            check(st, "fwils_normal_cg")
+        return q, hist
+
     def fft2(self, i, x, inverse=False, out=None):
         """2-D FFT (unnormalised) of every field of problem i; x: [nsys, 2, nz, nx]."""
         _require_cuda(x, torch.complex64, "x")

@@ -1,0 +1,110 @@
+"""GPU parity of the generalised Tikhonov step (eqs. obj, norm) and of the
+autograd operator: relative-unit J / J*, gradient, normal operator and
+normal-equation CG against the complex128 oracle on a two-frequency plan."""
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import LSProblem, tikhonov
+
+pytestmark = pytest.mark.gpu
+
+NX, NZ, NSYS, NREC, FREQS = 48, 32, 2, 6, (10.0, 14.0)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+
+
+@pytest.fixture(scope="module")
+def case():
+    from paper_2402_02116_amd.plan import Plan
+    assert torch.cuda.is_available()
+    c0, rho0 = W.vti_background()
+    m0 = W.model_scales(c0, rho0)
+    maps = W.round_f32(m0 * W.smooth_maps(31, NZ, NX, 2.0, 0.08))
+    src, f = W.surface_sources(NX, NSYS, iz=1)
+    rec = W.surface_receivers(NX, NREC, iz=2)
+    probs = [dict(nx=NX, nz=NZ, dx=8.0, c0=c0, rho0=rho0, freq_hz=fr, eta=0.02, nsys=NSYS) for fr in FREQS]
+    plan = Plan(probs)
+    for i in range(len(FREQS)):
+        plan.set_contrast(i, maps)
+        plan.set_receivers(i, rec)
+    ub = plan.solve(plan.incident(src * len(FREQS), f * len(FREQS)), rtol=1e-7, maxit=500).x
+    items = []
+    for fr in FREQS:
+        P = LSProblem(NX, NZ, 8.0, c0, rho0, fr, 0.02, maps)
+        ubr, _ = P.solve(P.incident(src, f), tol=1e-12)
+        items.append((P, ubr, rec))
+    r_np = [W.round_f32(W.complex_normal(40 + k, (NSYS, NREC, 2))) for k in range(len(FREQS))]
+    r = torch.as_tensor(np.concatenate([x.ravel() for x in r_np]).astype(np.complex64)).cuda()
+    q = W.round_f32(W.smooth_maps(33, NZ, NX, 2.0, 0.02))
+    return dict(plan=plan, ub=ub, items=items, r_np=r_np, r=r, m0=m0, m0v=m0.ravel(), q=q,
+                qt=torch.as_tensor(q, dtype=torch.float32).cuda())
+
+
+def test_frechet_rel_and_adjoint_rel_match_oracle(case):
+    T = tikhonov.Tikhonov(case["items"], case["m0"], case["r_np"], lam=0.0, tol=1e-12)
+    d = case["plan"].frechet_rel(case["ub"], case["qt"], case["m0v"], rtol=1e-7).cpu().numpy()
+    d_ref = np.concatenate([x.ravel() for x in T.J(case["q"])])
+    assert _rel(d, d_ref) < 1e-4
+    g = case["plan"].adjoint_rel(case["ub"], case["r"], case["m0v"], rtol=1e-7).cpu().numpy()
+    g_ref = np.real(T.Jstar(case["r_np"]))
+    assert _rel(g, g_ref) < 1e-4
+
+
+def test_laplacian_matches_oracle(case):
+    out = case["plan"].laplacian(case["qt"]).cpu().numpy()
+    assert _rel(out, tikhonov.laplacian(case["q"])) < 1e-6
+
+
+@pytest.mark.parametrize("reg", ["laplacian", "identity"])
+def test_tikhonov_gradient_matches_oracle(case, reg):
+    T = tikhonov.Tikhonov(case["items"], case["m0"], case["r_np"], lam=1e-3, reg=reg, tol=1e-12)
+    f, g = case["plan"].tikhonov_grad(case["ub"], case["r"], case["m0v"], case["qt"], lam=1e-3, reg=reg,
+                                      rtol=1e-7)
+    assert abs(f - T.objective(case["q"])) <= 1e-5 * abs(T.objective(case["q"]))
+    assert _rel(g.cpu().numpy(), T.gradient(case["q"])) < 1e-4
+
+
+def test_gpu_gradient_is_the_derivative_of_gpu_objective(case):
+    """The objective is quadratic, so the central difference is exact up to rounding."""
+    plan = case["plan"]
+    d = torch.as_tensor(W.smooth_maps(34, NZ, NX, 2.0, 0.02), dtype=torch.float32).cuda()
+    h = 0.5
+    fp, _ = plan.tikhonov_grad(case["ub"], case["r"], case["m0v"], case["qt"] + h * d, rtol=1e-7)
+    fm, _ = plan.tikhonov_grad(case["ub"], case["r"], case["m0v"], case["qt"] - h * d, rtol=1e-7)
+    _, g = plan.tikhonov_grad(case["ub"], case["r"], case["m0v"], case["qt"], rtol=1e-7)
+    gd = float(torch.sum(g.double() * d.double()))
+    assert abs((fp - fm) / (2 * h) - gd) <= 1e-3 * abs(gd)
+
+
+def test_autograd_matches_library_gradient(case):
+    from paper_2402_02116_amd.autograd import FrechetOperator, tikhonov_loss
+    op = FrechetOperator(case["plan"], case["ub"], case["m0v"], rtol=1e-7)
+    q = case["qt"].clone().requires_grad_(True)
+    loss = tikhonov_loss(q, op, case["r"], 1e-3, reg="laplacian")
+    loss.backward()
+    f, g = case["plan"].tikhonov_grad(case["ub"], case["r"], case["m0v"], case["qt"], lam=1e-3,
+                                      reg="laplacian", rtol=1e-7)
+    assert abs(float(loss.detach()) - f) <= 1e-5 * abs(f)
+    assert _rel(q.grad.cpu().numpy(), g.cpu().numpy()) < 1e-5
+
+
+def test_normal_apply_matches_oracle(case):
+    T = tikhonov.Tikhonov(case["items"], case["m0"], case["r_np"], lam=1e-3, reg="laplacian", tol=1e-12)
+    out = case["plan"].normal_apply(case["ub"], case["m0v"], T.rr, case["qt"], lam=1e-3, reg="laplacian",
+                                    rtol=1e-7)
+    assert _rel(out.cpu().numpy(), T.normal_apply(case["q"])) < 1e-4
+
+
+def test_normal_cg_matches_oracle(case):
+    T = tikhonov.Tikhonov(case["items"], case["m0"], case["r_np"], lam=1e-3, reg="identity", tol=1e-12)
+    qo, hist_o = T.solve_cg(4)
+    q, hist = case["plan"].normal_cg(case["ub"], case["r"], case["m0v"], niter=4, lam=1e-3, reg="identity",
+                                     rtol=1e-7)
+    assert _rel(hist, np.array(hist_o)) < 1e-3
+    assert _rel(q.cpu().numpy(), qo) < 1e-3
+    assert hist[-1] < hist[0]
