@@ -45,7 +45,8 @@ void set_error(const char* fmt, ...) {
     } while (0)
 
 constexpr int kMaxRec = 65536;
-constexpr int kChunkIters = 4;
+constexpr int kChunkIters = 4;        // iterations per graph chunk (even: p buffers alternate)
+constexpr int kNumVec = 10;           // field-sized workspace vectors
 constexpr int kMaxCgIters = 1000;
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -82,8 +83,8 @@ struct fwils_plan_s {
     int32_t* rec = nullptr;
     int32_t* src_i = nullptr;
     double* src_f = nullptr;
-    float2 *x = nullptr, *r = nullptr, *rhat = nullptr, *p = nullptr, *v = nullptr, *s = nullptr,
-           *t = nullptr, *tmp = nullptr, *rhs = nullptr;
+    float2 *x = nullptr, *r = nullptr, *rhat = nullptr, *p = nullptr, *p2 = nullptr, *v = nullptr,
+           *s = nullptr, *t = nullptr, *tmp = nullptr, *rhs = nullptr;
     // model-map scratch of the Tikhonov step (single-grid plans only)
     size_t map_n = 0, off_mapws = 0;
     float *mq_dm = nullptr, *mq_x = nullptr, *mq_res = nullptr, *mq_p = nullptr, *mq_Ap = nullptr,
@@ -194,20 +195,34 @@ SysView make_view(fwils_plan pl, const ProbHost& P, int s0, int ns) {
     return v;
 }
 
-// One BiCGSTAB iteration on a view (all kernels skip stopped systems).
-hipError_t bicg_iteration(fwils_plan pl, const ProbHost& P, const SysView& V, hipStream_t s) {
+// One BiCGSTAB iteration on a view (all kernels skip stopped systems): nine
+// kernels.  The direction update p = r + beta (p_old - omega v) is fused into
+// the first contrast stencil and s = r - alpha v into the second; p
+// alternates between two buffers with the iteration parity.
+hipError_t bicg_iteration(fwils_plan pl, const ProbHost& P, const SysView& V, int parity, hipStream_t s) {
     const int ns = V.d.nsys;
     const int n = (int)P.n_per_sys;
-    float2 *x = pl->x + V.foff, *r = pl->r + V.foff, *rh = pl->rhat + V.foff, *p = pl->p + V.foff,
-           *v = pl->v + V.foff, *sv = pl->s + V.foff, *t = pl->t + V.foff, *tmp = pl->tmp + V.foff;
+    const int rows = ns * 2 * V.d.nz;
+    float2 *x = pl->x + V.foff, *r = pl->r + V.foff, *rh = pl->rhat + V.foff, *v = pl->v + V.foff,
+           *sv = pl->s + V.foff, *t = pl->t + V.foff, *tmp = pl->tmp + V.foff;
+    float2* pold = (parity ? pl->p2 : pl->p) + V.foff;
+    float2* pnew = (parity ? pl->p : pl->p2) + V.foff;
     SysState* st = pl->state + V.soff;
     double *pV = pl->partV + V.poff_row, *pT = pl->partT + V.poff_row, *pXR = pl->partXR + V.poff_vec;
     const float* maps = maps_at(pl, P);
-    hipError_t e = launch_bicg_p(r, p, v, pXR, P.np_vec, st, ns, n, s);
-    if (e == hipSuccess) e = matvec(pl, P, V.d, p, tmp, maps, EPI_BICG_V, rh, v, pV, st, s);
-    if (e == hipSuccess) e = launch_bicg_s(r, v, sv, pV, P.np_rows, st, ns, n, s);
-    if (e == hipSuccess) e = matvec(pl, P, V.d, sv, tmp, maps, EPI_BICG_T, nullptr, t, pT, st, s);
-    if (e == hipSuccess) e = launch_bicg_xr(x, r, rh, p, sv, t, pT, P.np_rows, pXR, st, ns, n, s);
+    const StencilArgs ap{r, pold, v, pnew, tmp, maps, pXR, P.np_vec};
+    hipError_t e = launch_stencil(1, ap, V.d, st, s);
+    if (e == hipSuccess) e = launch_rows_fwd(V.d.nx, tmp, tmp, rows, 2 * V.d.nz, st, pl->tw, s);
+    if (e == hipSuccess) e = launch_cols(COL_GREEN, tmp, V.d, st, pl->tw, s);
+    if (e == hipSuccess)
+        e = launch_rows_inv(V.d.nx, EPI_BICG_V, tmp, pnew, rh, v, pV, rows, 2 * V.d.nz, st, pl->tw, s);
+    const StencilArgs as{r, v, nullptr, sv, tmp, maps, pV, P.np_rows};
+    if (e == hipSuccess) e = launch_stencil(2, as, V.d, st, s);
+    if (e == hipSuccess) e = launch_rows_fwd(V.d.nx, tmp, tmp, rows, 2 * V.d.nz, st, pl->tw, s);
+    if (e == hipSuccess) e = launch_cols(COL_GREEN, tmp, V.d, st, pl->tw, s);
+    if (e == hipSuccess)
+        e = launch_rows_inv(V.d.nx, EPI_BICG_T, tmp, sv, nullptr, t, pT, rows, 2 * V.d.nz, st, pl->tw, s);
+    if (e == hipSuccess) e = launch_bicg_xr(x, r, rh, pnew, sv, t, pT, P.np_rows, pXR, st, ns, n, s);
     return e;
 }
 
@@ -225,7 +240,7 @@ fwils_status build_chunk_graph(fwils_plan pl) {
     for (int i = 0; i < np && e == hipSuccess; ++i) {
         const ProbHost& P = pl->probs[i];
         const SysView V = make_view(pl, P, 0, P.p.nsys);
-        for (int it = 0; it < kChunkIters && e == hipSuccess; ++it) e = bicg_iteration(pl, P, V, ss[i]);
+        for (int it = 0; it < kChunkIters && e == hipSuccess; ++it) e = bicg_iteration(pl, P, V, it & 1, ss[i]);
         if (e == hipSuccess)
             e = launch_bicg_check(st_at(pl, P), part_at(pl->partXR, pl, P), P.np_vec, P.p.nsys, ss[i]);
         if (i > 0 && e == hipSuccess) e = hipEventRecord(ev[i], ss[i]);
@@ -281,7 +296,7 @@ fwils_status solve_ws(fwils_plan pl, const float2* b, bool use_x0, double rtol, 
             for (int sy = 0; sy < P.p.nsys; ++sy) {
                 const SysView V = make_view(pl, P, sy, 1);
                 for (int it = 0; it <= maxit; ++it) {
-                    FW_HIP(bicg_iteration(pl, P, V, s));
+                    FW_HIP(bicg_iteration(pl, P, V, it & 1, s));
                     FW_HIP(launch_bicg_check(pl->state + V.soff, pl->partXR + V.poff_vec, P.np_vec, 1, s));
                     FW_HIP(hipMemcpyAsync(pl->host_state + V.soff, pl->state + V.soff, sizeof(SysState),
                                           hipMemcpyDeviceToHost, s));
@@ -299,7 +314,7 @@ fwils_status solve_ws(fwils_plan pl, const float2* b, bool use_x0, double rtol, 
             if (flags & FWILS_SOLVE_NOGRAPH) {
                 for (const ProbHost& P : pl->probs) {
                     const SysView V = make_view(pl, P, 0, P.p.nsys);
-                    for (int it = 0; it < kChunkIters; ++it) FW_HIP(bicg_iteration(pl, P, V, s));
+                    for (int it = 0; it < kChunkIters; ++it) FW_HIP(bicg_iteration(pl, P, V, it & 1, s));
                     FW_HIP(launch_bicg_check(st_at(pl, P), part_at(pl->partXR, pl, P), P.np_vec,
                                              P.p.nsys, s));
                 }
@@ -435,7 +450,7 @@ fwils_status fwils_plan_create(const fwils_problem* probs, int32_t nprob, fwils_
     pl->off_src = o;
     o = align256(o + pl->total_sys * 2 * (sizeof(int32_t) + sizeof(double)));
     pl->off_vec = o;
-    o += 9 * align256(pl->total_field * sizeof(float2));
+    o += kNumVec * align256(pl->total_field * sizeof(float2));
     bool one_grid = true;
     for (int i = 1; i < nprob; ++i)
         one_grid = one_grid && probs[i].nx == probs[0].nx && probs[i].nz == probs[0].nz &&
@@ -511,10 +526,10 @@ fwils_status fwils_set_workspace(fwils_plan plan, void* dev, size_t bytes) {
     plan->rec = (int32_t*)(w + plan->off_rec);
     plan->src_i = (int32_t*)(w + plan->off_src);
     plan->src_f = (double*)(w + plan->off_src + align256(plan->total_sys * 2 * sizeof(int32_t)));
-    float2** vecs[9] = {&plan->x, &plan->r, &plan->rhat, &plan->p, &plan->v,
-                        &plan->s, &plan->t, &plan->tmp, &plan->rhs};
+    float2** vecs[kNumVec] = {&plan->x, &plan->r, &plan->rhat, &plan->p, &plan->p2,
+                              &plan->v, &plan->s, &plan->t, &plan->tmp, &plan->rhs};
     const size_t vb = align256(plan->total_field * sizeof(float2));
-    for (int i = 0; i < 9; ++i) *vecs[i] = (float2*)(w + plan->off_vec + i * vb);
+    for (int i = 0; i < kNumVec; ++i) *vecs[i] = (float2*)(w + plan->off_vec + i * vb);
     if (plan->map_n) {
         char* m = w + plan->off_mapws;
         const size_t fb = align256(5 * plan->map_n * sizeof(float));

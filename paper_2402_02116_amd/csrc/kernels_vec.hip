@@ -26,11 +26,31 @@ constexpr int STX = 64, STZ = 8;
 
 __device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
-template <int TX, int TZ>
+// Stopping test of the recursive residual (defined with the vector kernels
+// below); true if the system must stop.  `writer` records the status.
+__device__ __forceinline__ bool bicg_stop(SysState* st, int sys, double rr, bool writer);
+__device__ __forceinline__ dcomplex zdiv(dcomplex a, dcomplex b);
+__device__ __forceinline__ dcomplex zmul(dcomplex a, dcomplex b);
+__device__ __forceinline__ bool zzero(dcomplex a);
+
+// Vector update fused into the stencil's load of its input field:
+//   VM_NONE: the input is u itself;
+//   VM_P:    p = r + beta (p_old - omega v)   (BiCGSTAB direction update)
+//   VM_S:    s = r - alpha v                  (BiCGSTAB intermediate residual)
+// The updated field is written for the tile's own cells and used (halo
+// included) as the stencil's input.  p is double-buffered by the caller
+// because neighbouring tiles read p_old in their halos.
+enum StencilVec : int { VM_NONE = 0, VM_P = 1, VM_S = 2 };
+
+template <int TX, int TZ, int VM>
 __global__ __launch_bounds__(256) void k_body_force(const float2* __restrict__ u,
+                                                    const float2* __restrict__ a1,
+                                                    const float2* __restrict__ a2,
+                                                    float2* __restrict__ wout,
                                                     float2* __restrict__ b,
                                                     const float* __restrict__ maps, ProbDev pd,
-                                                    int S, const SysState* __restrict__ st) {
+                                                    int S, SysState* __restrict__ st,
+                                                    const double* __restrict__ part, int np) {
     static_assert(TX <= 64 && TZ % 4 == 0, "tile");
     constexpr int HX = TX + 4, HZ = TZ + 4, SX = TX + 2, SZ = TZ + 2;
     constexpr int KS = (SZ + 3) / 4;     // stress rows per thread
@@ -38,6 +58,7 @@ __global__ __launch_bounds__(256) void k_body_force(const float2* __restrict__ u
     constexpr int KH = HZ / 4;           // displacement rows per thread
     __shared__ float2 su[2][HZ][HX];
     __shared__ float2 ss[3][SZ][SX];
+    __shared__ double red[4 * 4];
     const int nx = pd.nx, nz = pd.nz;
     const size_t plane = (size_t)nx * nz;
     const int ntx = nx / TX;
@@ -72,21 +93,77 @@ __global__ __launch_bounds__(256) void k_body_force(const float2* __restrict__ u
     const float sc = pd.inv4dx2;
     for (int sys = sys0; sys < sys0 + S && sys < pd.nsys; ++sys) {
         if (st != nullptr && st[sys].status != ST_RUNNING) continue;   // uniform over the block
-        const float2* us = u + (size_t)sys * 2 * plane;
-        float2* bs = b + (size_t)sys * 2 * plane;
+        float2 c1 = make_float2(0.f, 0.f), c2 = make_float2(0.f, 0.f);
+        if constexpr (VM != VM_NONE) {
+            double q[4];
+            sum_partials<4, 256>(part + (size_t)sys * np * kPartialNV, np, q, red);
+            const bool writer = (tile == 0 && threadIdx.x == 0);
+            const SysState& z = st[sys];
+            const int it = z.iter + 1;
+            if constexpr (VM == VM_P) {
+                if (bicg_stop(st, sys, q[2], writer)) continue;
+                const dcomplex rho_i{q[0], q[1]};
+                const dcomplex rho_prev{z.rho_re[(it - 1) & 1], z.rho_im[(it - 1) & 1]};
+                const dcomplex alpha{z.alpha_re, z.alpha_im}, omega{z.omega_re, z.omega_im};
+                if (zzero(rho_i) || zzero(rho_prev) || zzero(omega)) {
+                    if (writer) st[sys].status = ST_BREAKDOWN;
+                    continue;
+                }
+                const dcomplex beta = zmul(zdiv(rho_i, rho_prev), zdiv(alpha, omega));
+                c1 = make_float2((float)beta.re, (float)beta.im);
+                c2 = make_float2((float)omega.re, (float)omega.im);
+                if (writer) {
+                    st[sys].rho_re[it & 1] = rho_i.re;
+                    st[sys].rho_im[it & 1] = rho_i.im;
+                }
+            } else {
+                const dcomplex rho_i{z.rho_re[it & 1], z.rho_im[it & 1]};
+                const dcomplex rv{q[0], q[1]};
+                if (zzero(rv)) {
+                    if (writer) st[sys].status = ST_BREAKDOWN;
+                    continue;
+                }
+                const dcomplex alpha = zdiv(rho_i, rv);
+                c1 = make_float2((float)alpha.re, (float)alpha.im);
+                if (writer) {
+                    st[sys].alpha_re = alpha.re;
+                    st[sys].alpha_im = alpha.im;
+                }
+            }
+        }
+        const size_t so = (size_t)sys * 2 * plane;
+        float2* bs = b + so;
+        // input field value at global index gi of this system (comp offset included)
+        auto field = [&](size_t gi) -> float2 {
+            if constexpr (VM == VM_NONE) {
+                return u[so + gi];
+            } else if constexpr (VM == VM_P) {
+                const float2 pv = a1[so + gi], vv = a2[so + gi], rv = u[so + gi];
+                return cadd(rv, cmul(c1, csub(pv, cmul(c2, vv))));
+            } else {
+                return csub(u[so + gi], cmul(c1, a1[so + gi]));
+            }
+        };
         __syncthreads();   // previous system's reads of su / ss are done
 #pragma unroll
         for (int k = 0; k < KH; ++k) {
             const int hz = tg + 4 * k;
             const size_t row = (size_t)wrap(z0 - 2 + hz, nz) * nx;
             if (lane) {
-                su[0][hz][tx + 2] = us[row + x0 + tx];
-                su[1][hz][tx + 2] = us[plane + row + x0 + tx];
+                const float2 f0 = field(row + x0 + tx), f1 = field(plane + row + x0 + tx);
+                su[0][hz][tx + 2] = f0;
+                su[1][hz][tx + 2] = f1;
+                if constexpr (VM != VM_NONE) {
+                    if (hz >= 2 && hz < TZ + 2) {     // the tile's own cells
+                        wout[so + row + x0 + tx] = f0;
+                        wout[so + plane + row + x0 + tx] = f1;
+                    }
+                }
             }
             if (tx < 4) {
                 const int gx = wrap(x0 - 2 + hux, nx);
-                su[0][hz][hux] = us[row + gx];
-                su[1][hz][hux] = us[plane + row + gx];
+                su[0][hz][hux] = field(row + gx);
+                su[1][hz][hux] = field(plane + row + gx);
             }
         }
         __syncthreads();
@@ -139,24 +216,25 @@ static int tile_x(int nx) {
     return 0;
 }
 
-template <int TX, int TZ>
-static void body_force_launch(const float2* u, float2* b, const float* maps, const ProbDev& pd,
-                              const SysState* st, hipStream_t s) {
+template <int TX, int TZ, int VM>
+static void body_force_launch(const StencilArgs& a, const ProbDev& pd, SysState* st, hipStream_t s) {
     const int ntiles = (pd.nx / TX) * (pd.nz / TZ);
     // several systems per block once there are plenty of blocks
     int S = 1;
     while (S < pd.nsys && (long long)ntiles * ((pd.nsys + 2 * S - 1) / (2 * S)) >= 2048) S *= 2;
     const int blocks = ntiles * ((pd.nsys + S - 1) / S);
-    hipLaunchKernelGGL((k_body_force<TX, TZ>), dim3(blocks), dim3(256), 0, s, u, b, maps, pd, S, st);
+    hipLaunchKernelGGL((k_body_force<TX, TZ, VM>), dim3(blocks), dim3(256), 0, s, a.u, a.a1, a.a2, a.wout,
+                       a.b, a.maps, pd, S, st, a.part, a.np);
 }
 
-hipError_t launch_body_force(const float2* u, float2* b, const float* maps, const ProbDev& pd,
-                             const SysState* st, hipStream_t s) {
+hipError_t launch_stencil(int vm, const StencilArgs& a, const ProbDev& pd, SysState* st, hipStream_t s) {
     const int TX = tile_x(pd.nx);
-    if (TX == 0 || pd.nz % STZ != 0) return hipErrorInvalidValue;
+    if (TX == 0 || pd.nz % STZ != 0 || vm < 0 || vm > 2 || (vm != 0 && !st)) return hipErrorInvalidValue;
 #define FW_BF(X)                                                                          \
     case X:                                                                               \
-        body_force_launch<X, STZ>(u, b, maps, pd, st, s);                                 \
+        if (vm == VM_NONE) body_force_launch<X, STZ, VM_NONE>(a, pd, st, s);              \
+        else if (vm == VM_P) body_force_launch<X, STZ, VM_P>(a, pd, st, s);               \
+        else body_force_launch<X, STZ, VM_S>(a, pd, st, s);                               \
         break;
     switch (TX) {
         FW_BF(64) FW_BF(48) FW_BF(32) FW_BF(24) FW_BF(16)
@@ -164,6 +242,12 @@ hipError_t launch_body_force(const float2* u, float2* b, const float* maps, cons
     }
 #undef FW_BF
     return hipGetLastError();
+}
+
+hipError_t launch_body_force(const float2* u, float2* b, const float* maps, const ProbDev& pd,
+                             const SysState* st, hipStream_t s) {
+    StencilArgs a{u, nullptr, nullptr, nullptr, b, maps, nullptr, 0};
+    return launch_stencil(VM_NONE, a, pd, const_cast<SysState*>(st), s);
 }
 
 // -------------------------------------------------------------- vectors --
@@ -275,77 +359,6 @@ __device__ __forceinline__ bool bicg_stop(SysState* st, int sys, double rr, bool
     return status != ST_RUNNING;
 }
 
-// p = r + beta (p - omega v),  beta = (rho_i / rho_{i-1}) (alpha / omega).
-__global__ __launch_bounds__(256) void k_bicg_p(const float2* __restrict__ r, float2* __restrict__ p,
-                                                const float2* __restrict__ v,
-                                                const double* __restrict__ partXR, int npXR,
-                                                SysState* __restrict__ st, int n, int nb) {
-    __shared__ double red[4 * 4];
-    const VecIdx vi = vec_idx(nb);
-    if (st[vi.sys].status != ST_RUNNING) return;
-    double q[4];
-    sum_partials<4, 256>(partXR + (size_t)vi.sys * npXR * kPartialNV, npXR, q, red);
-    const bool writer = (vi.bi == 0 && threadIdx.x == 0);
-    if (bicg_stop(st, vi.sys, q[2], writer)) return;
-    const SysState& s = st[vi.sys];
-    const int it = s.iter + 1;
-    const dcomplex rho{q[0], q[1]};
-    const dcomplex rho_prev{s.rho_re[(it - 1) & 1], s.rho_im[(it - 1) & 1]};
-    const dcomplex alpha{s.alpha_re, s.alpha_im}, omega{s.omega_re, s.omega_im};
-    if (zzero(rho) || zzero(rho_prev) || zzero(omega)) {
-        if (writer) st[vi.sys].status = ST_BREAKDOWN;
-        return;
-    }
-    const dcomplex beta = zmul(zdiv(rho, rho_prev), zdiv(alpha, omega));
-    const float2 bf = tof(beta), of = tof(omega);
-    const size_t off = (size_t)vi.sys * n;
-#pragma unroll
-    for (int e = 0; e < kVecEPT; ++e) {
-        const int i = vi.i0 + e * kVecThreads + threadIdx.x;
-        if (i < n) {
-            const float2 pv = p[off + i], vv = v[off + i], rv = r[off + i];
-            p[off + i] = cadd(rv, cmul(bf, csub(pv, cmul(of, vv))));
-        }
-    }
-    if (writer) {
-        st[vi.sys].rho_re[it & 1] = rho.re;
-        st[vi.sys].rho_im[it & 1] = rho.im;
-    }
-}
-
-// alpha = rho_i / <rhat, v>;  s = r - alpha v.
-__global__ __launch_bounds__(256) void k_bicg_s(const float2* __restrict__ r,
-                                                const float2* __restrict__ v, float2* __restrict__ sv,
-                                                const double* __restrict__ partV, int npV,
-                                                SysState* __restrict__ st, int n, int nb) {
-    __shared__ double red[4 * 4];
-    const VecIdx vi = vec_idx(nb);
-    if (st[vi.sys].status != ST_RUNNING) return;
-    double q[4];
-    sum_partials<4, 256>(partV + (size_t)vi.sys * npV * kPartialNV, npV, q, red);
-    const bool writer = (vi.bi == 0 && threadIdx.x == 0);
-    const SysState& s = st[vi.sys];
-    const int it = s.iter + 1;
-    const dcomplex rho{s.rho_re[it & 1], s.rho_im[it & 1]};
-    const dcomplex rv{q[0], q[1]};
-    if (zzero(rv)) {
-        if (writer) st[vi.sys].status = ST_BREAKDOWN;
-        return;
-    }
-    const dcomplex alpha = zdiv(rho, rv);
-    const float2 af = tof(alpha);
-    const size_t off = (size_t)vi.sys * n;
-#pragma unroll
-    for (int e = 0; e < kVecEPT; ++e) {
-        const int i = vi.i0 + e * kVecThreads + threadIdx.x;
-        if (i < n) sv[off + i] = csub(r[off + i], cmul(af, v[off + i]));
-    }
-    if (writer) {
-        st[vi.sys].alpha_re = alpha.re;
-        st[vi.sys].alpha_im = alpha.im;
-    }
-}
-
 // omega = <t, s> / <t, t>;  x += alpha p + omega s;  r = s - omega t;
 // partials <rhat, r>, ||r||^2.
 __global__ __launch_bounds__(256) void k_bicg_xr(float2* __restrict__ x, float2* __restrict__ r,
@@ -437,22 +450,6 @@ hipError_t launch_bicg_state_init(SysState* st, const double* partXR, const doub
                                   int nsys, int npart, double rtol, int maxit, hipStream_t s) {
     hipLaunchKernelGGL(k_bicg_state_init, dim3(nsys), dim3(256), 0, s, st, partXR, partB, npart,
                        rtol, maxit);
-    return hipGetLastError();
-}
-
-hipError_t launch_bicg_p(const float2* r, float2* p, const float2* v, const double* partXR,
-                         int npXR, SysState* st, int nsys, int n, hipStream_t s) {
-    const int nb = vec_blocks_per_sys(n);
-    hipLaunchKernelGGL(k_bicg_p, dim3(nsys * nb), dim3(kVecThreads), 0, s, r, p, v, partXR, npXR,
-                       st, n, nb);
-    return hipGetLastError();
-}
-
-hipError_t launch_bicg_s(const float2* r, const float2* v, float2* sv, const double* partV,
-                         int npV, SysState* st, int nsys, int n, hipStream_t s) {
-    const int nb = vec_blocks_per_sys(n);
-    hipLaunchKernelGGL(k_bicg_s, dim3(nsys * nb), dim3(kVecThreads), 0, s, r, v, sv, partV, npV,
-                       st, n, nb);
     return hipGetLastError();
 }
 

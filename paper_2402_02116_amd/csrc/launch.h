@@ -50,6 +50,21 @@ hipError_t launch_cols(int mode, float2* data, const ProbDev& pd, const SysState
 // Body force b = w~^2 drho u + div_h(dC : E_h u) of one problem.
 hipError_t launch_body_force(const float2* u, float2* b, const float* maps, const ProbDev& pd,
                              const SysState* st, hipStream_t s);
+// The stencil with a BiCGSTAB vector update fused into its input (vm: 0 none,
+// 1 p = r + beta (p_old - omega v) [u = r, a1 = p_old, a2 = v, wout = p_new,
+// part = <rhat, r> records], 2 s = r - alpha v [u = r, a1 = v, wout = s,
+// part = <rhat, v> records]).
+struct StencilArgs {
+    const float2* u;
+    const float2* a1;
+    const float2* a2;
+    float2* wout;
+    float2* b;
+    const float* maps;
+    const double* part;
+    int np;
+};
+hipError_t launch_stencil(int vm, const StencilArgs& a, const ProbDev& pd, SysState* st, hipStream_t s);
 
 // BiCGSTAB pieces (one problem; n = 2 nz nx complex per system).
 int vec_blocks_per_sys(int n);
@@ -58,10 +73,6 @@ hipError_t launch_bicg_init(const float2* b, const float2* r0, float2* x, float2
                             bool zero_x, hipStream_t s);
 hipError_t launch_bicg_state_init(SysState* st, const double* partXR, const double* partB,
                                   int nsys, int npart, double rtol, int maxit, hipStream_t s);
-hipError_t launch_bicg_p(const float2* r, float2* p, const float2* v, const double* partXR,
-                         int npXR, SysState* st, int nsys, int n, hipStream_t s);
-hipError_t launch_bicg_s(const float2* r, const float2* v, float2* sv, const double* partV,
-                         int npV, SysState* st, int nsys, int n, hipStream_t s);
 hipError_t launch_bicg_xr(float2* x, float2* r, const float2* rhat, const float2* p,
                           const float2* sv, const float2* t, const double* partT, int npT,
                           double* partXR, SysState* st, int nsys, int n, hipStream_t s);
