@@ -81,6 +81,55 @@ def build_workload():
     return c, rec, dm, r
 
 
+def multigrid(a):
+    """Batching workload: 128^2 / 192^2 / 256^2 / 384^2 grids at 4 / 6 / 8 / 12 Hz over
+    one 4800 m square, 64 surface forces each, in ONE plan (one graph per chunk).
+    One step = incident fields + batched solve to 1e-6 of all 256 systems."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2402_02116_amd.plan import Plan
+    probs = W.config2()
+    plan = Plan([dict(nx=p["nx"], nz=p["nz"], dx=p["dx"], c0=p["c0"], rho0=p["rho0"],
+                      freq_hz=p["freq_hz"], eta=p["eta"], nsys=p["nsys"]) for p in probs], device="cuda:0")
+    for i, p in enumerate(probs):
+        plan.set_contrast(i, p["maps"])
+    src = sum((p["src_ixz"] for p in probs), [])
+    frc = sum((p["src_f"] for p in probs), [])
+    cells = np.array(sum(([p["nx"] * p["nz"]] * p["nsys"] for p in probs), []))
+
+    def step():
+        u0 = plan.incident(src, frc)
+        res = plan.solve(u0, rtol=RTOL, maxit=1000)
+        return int(np.sum((2 * res.iters + 1) * cells)), res
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pts = 0
+    for _ in range(a.steps):
+        n, res = step()
+        pts += n
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    u0 = plan.incident(src, frc)
+    t = time.perf_counter()
+    res = plan.solve(u0, rtol=RTOL, maxit=1000)
+    t_solve = (time.perf_counter() - t) * 1e3
+    out = dict(metric=METRIC, value=round(pts / dt / 1e9, 3), unit="GPoints/s", n_gpus=1, steps=a.steps,
+               warmup=a.warmup, ms_per_step=round(dt / a.steps * 1e3, 4), higher_is_better=True,
+               scaling="weak", vs_baseline=None, dtype="c64", data="synthetic",
+               config=dict(workload="4 grids 128^2..384^2 (4, 6, 8, 12 Hz), 64 forces each, one plan: "
+                                    "incident + batched solve to 1e-6",
+                           grids=[p["nx"] for p in probs], nsys=int(len(src)), rtol=RTOL,
+                           cells_per_matvec=int(cells.sum())),
+               time_to_1e6_ms=round(t_solve, 3), iters=[int(res.iters.min()), int(res.iters.max())],
+               max_true_relres=float(res.relres.max()))
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def cpu_baseline(c, rec, dm, r, nsample):
     """The oracle on the host cores, on `nsample` of the systems of one step."""
     import numpy as np
@@ -111,6 +160,7 @@ def main(argv=None):
     ap.add_argument("--reps", type=int, default=50, help="launches per kernel timing")
     ap.add_argument("--cpu-sample", type=int, default=4, help="systems in the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=["vti256x16", "multigrid"], default="vti256x16")
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported (the path shards "
@@ -122,6 +172,8 @@ def main(argv=None):
     from paper_2402_02116_amd.plan import Plan
 
     torch.cuda.set_device(0)
+    if a.workload == "multigrid":
+        return multigrid(a)
     c, rec, dm_np, r_np = build_workload()
     nx, nz, ns = c["nx"], c["nz"], c["nsys"]
     cells = nx * nz

@@ -47,6 +47,8 @@ void set_error(const char* fmt, ...) {
 constexpr int kMaxRec = 65536;
 constexpr int kChunkIters = 4;        // iterations per graph chunk (even: p buffers alternate)
 constexpr int kNumVec = 10;           // field-sized workspace vectors
+constexpr int kMaxRestarts = 3;       // restarts from the true residual per solve
+constexpr double kTrueResFactor = 2.0; // restart when ||b - A x|| > 2 rtol ||b||
 constexpr int kMaxCgIters = 1000;
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -289,23 +291,25 @@ fwils_status solve_ws(fwils_plan pl, const float2* b, bool use_x0, double rtol, 
             if (pl->host_state[i].status == ST_RUNNING) done = false;
         return FWILS_OK;
     };
-
-    if (flags & FWILS_SOLVE_PLAIN) {
-        // per-source loop, host-synchronous check after every iteration
-        for (const ProbHost& P : pl->probs) {
-            for (int sy = 0; sy < P.p.nsys; ++sy) {
-                const SysView V = make_view(pl, P, sy, 1);
-                for (int it = 0; it <= maxit; ++it) {
-                    FW_HIP(bicg_iteration(pl, P, V, it & 1, s));
-                    FW_HIP(launch_bicg_check(pl->state + V.soff, pl->partXR + V.poff_vec, P.np_vec, 1, s));
-                    FW_HIP(hipMemcpyAsync(pl->host_state + V.soff, pl->state + V.soff, sizeof(SysState),
-                                          hipMemcpyDeviceToHost, s));
-                    FW_HIP(hipStreamSynchronize(s));
-                    if (pl->host_state[V.soff].status != ST_RUNNING) break;
+    auto iterate = [&]() -> fwils_status {
+        if (flags & FWILS_SOLVE_PLAIN) {
+            // per-source loop, host-synchronous check after every iteration
+            for (const ProbHost& P : pl->probs) {
+                for (int sy = 0; sy < P.p.nsys; ++sy) {
+                    const SysView V = make_view(pl, P, sy, 1);
+                    if (pl->host_state[V.soff].status != ST_RUNNING) continue;
+                    for (int it = 0; it <= maxit; ++it) {
+                        FW_HIP(bicg_iteration(pl, P, V, it & 1, s));
+                        FW_HIP(launch_bicg_check(pl->state + V.soff, pl->partXR + V.poff_vec, P.np_vec, 1, s));
+                        FW_HIP(hipMemcpyAsync(pl->host_state + V.soff, pl->state + V.soff, sizeof(SysState),
+                                              hipMemcpyDeviceToHost, s));
+                        FW_HIP(hipStreamSynchronize(s));
+                        if (pl->host_state[V.soff].status != ST_RUNNING) break;
+                    }
                 }
             }
+            return FWILS_OK;
         }
-    } else {
         const int max_chunks = maxit / kChunkIters + 2;
         bool done = false;
         FW_TRY(all_done(done));
@@ -323,15 +327,41 @@ fwils_status solve_ws(fwils_plan pl, const float2* b, bool use_x0, double rtol, 
             }
             FW_TRY(all_done(done));
         }
+        return FWILS_OK;
+    };
+    // Iterate; then check the true residual and restart, from it, systems whose
+    // recursive residual drifted (bounded number of restarts per system).
+    const double limit2 = (kTrueResFactor * rtol) * (kTrueResFactor * rtol);
+    for (int round = 0;; ++round) {
+        FW_HIP(hipMemcpyAsync(pl->host_state, pl->state, nst * sizeof(SysState), hipMemcpyDeviceToHost, s));
+        FW_HIP(hipStreamSynchronize(s));
+        FW_TRY(iterate());
+        for (const ProbHost& P : pl->probs)
+            FW_HIP(matvec(pl, P, P.dev, at(pl->x, P), at(pl->tmp, P), maps_at(pl, P), EPI_TRUERES,
+                          b + P.field_off, at(pl->r, P), part_at(pl->partT, pl, P), nullptr, s));
+        if (round == kMaxRestarts) break;
+        for (const ProbHost& P : pl->probs)
+            FW_HIP(launch_bicg_restart_mark(st_at(pl, P), part_at(pl->partT, pl, P), P.np_rows, P.p.nsys,
+                                            limit2, kMaxRestarts, s));
+        FW_HIP(hipMemcpyAsync(pl->host_state, pl->state, nst * sizeof(SysState), hipMemcpyDeviceToHost, s));
+        FW_HIP(hipStreamSynchronize(s));
+        bool any = false;
+        for (const ProbHost& P : pl->probs) {
+            bool here = false;
+            for (int sy = 0; sy < P.p.nsys; ++sy) here = here || pl->host_state[P.sys_off + sy].status == ST_RESTART;
+            if (!here) continue;
+            any = true;
+            // r already holds b - A x; restart from it (converged systems are not touched again)
+            FW_HIP(launch_bicg_init(b + P.field_off, at(pl->r, P), at(pl->x, P), at(pl->r, P), at(pl->rhat, P),
+                                    at(pl->p, P), at(pl->v, P), part_at(pl->partXR, pl, P),
+                                    part_at(pl->partB, pl, P), P.p.nsys, (int)P.n_per_sys, false, s));
+            FW_HIP(launch_bicg_restart(st_at(pl, P), P.p.nsys, s));
+        }
+        if (!any) break;
     }
-    // true residual and per-system outputs
-    for (const ProbHost& P : pl->probs) {
-        FW_HIP(matvec(pl, P, P.dev, at(pl->x, P), at(pl->tmp, P), maps_at(pl, P), EPI_TRUERES,
-                      b + P.field_off, at(pl->r, P), part_at(pl->partT, pl, P), nullptr, s));
+    for (const ProbHost& P : pl->probs)
         FW_HIP(launch_bicg_finish(st_at(pl, P), part_at(pl->partT, pl, P), P.np_rows, P.p.nsys,
-                                  iters ? iters + P.sys_off : nullptr, relres ? relres + P.sys_off : nullptr,
-                                  s));
-    }
+                                  iters ? iters + P.sys_off : nullptr, relres ? relres + P.sys_off : nullptr, s));
     FW_HIP(hipMemcpyAsync(pl->host_state, pl->state, nst * sizeof(SysState), hipMemcpyDeviceToHost, s));
     FW_HIP(hipStreamSynchronize(s));
     bool noconv = false, brk = false;

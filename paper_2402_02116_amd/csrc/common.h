@@ -47,6 +47,7 @@ enum SysStatus : int {
     ST_MAXIT = 2,
     ST_BREAKDOWN = 3,
     ST_NONFINITE = 4,
+    ST_RESTART = 5,        // converged on the recursive residual, true residual too large
 };
 
 // Per-system BiCGSTAB scalars (FP64), one struct per system.
@@ -60,7 +61,7 @@ struct SysState {
     int iter;                      // completed iterations
     int status;                    // SysStatus
     int maxit;
-    int pad;
+    int restarts;                  // restarts from the true residual so far
 };
 
 // ------------------------------------------------------ block reductions --

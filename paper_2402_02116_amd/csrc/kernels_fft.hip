@@ -183,6 +183,7 @@ __global__ __launch_bounds__(256) void k_rows(const float2* in, float2* out,
                     acc[0] += (double)o.x * uu.x + (double)o.y * uu.y;
                     acc[1] += (double)o.x * uu.y - (double)o.y * uu.x;
                     acc[2] += (double)o.x * o.x + (double)o.y * o.y;
+                    acc[3] += (double)uu.x * uu.x + (double)uu.y * uu.y;
                 } else if constexpr (EPI == EPI_TRUERES) {
                     const float2 b = aux[i];
                     const float2 rr = csub(b, o);

@@ -11,6 +11,7 @@ namespace fw {
 
 constexpr int kVecThreads = 256;
 constexpr int kVecEPT = 4;   // complex elements per thread in vector kernels
+constexpr double kOmegaLimit = 0.7;
 
 // ------------------------------------------------------ contrast stencil --
 // A block owns a TZ x TX tile of cells and loops over S systems of the same
@@ -278,8 +279,8 @@ __device__ __forceinline__ VecIdx vec_idx(int nb) {
 // r = b (or r already holds b - A x0), x = 0 if zero_x, rhat = r, p = v = 0;
 // partials <rhat, r>, ||r||^2 and ||b||^2.
 __global__ __launch_bounds__(256) void k_bicg_init(const float2* __restrict__ b,
-                                                   const float2* __restrict__ r0,
-                                                   float2* __restrict__ x, float2* __restrict__ r,
+                                                   const float2* r0,   // may alias r
+                                                   float2* __restrict__ x, float2* r,
                                                    float2* __restrict__ rhat, float2* __restrict__ p,
                                                    float2* __restrict__ v,
                                                    double* __restrict__ partXR,
@@ -338,7 +339,7 @@ __global__ __launch_bounds__(256) void k_bicg_state_init(SysState* __restrict__ 
         z.rnorm2 = q[2];
         z.iter = 0;
         z.maxit = maxit;
-        z.pad = 0;
+        z.restarts = 0;
         z.status = (s[0] == 0.0) ? ST_CONVERGED : ST_RUNNING;
         st[sys] = z;
     }
@@ -359,7 +360,7 @@ __device__ __forceinline__ bool bicg_stop(SysState* st, int sys, double rr, bool
     return status != ST_RUNNING;
 }
 
-// omega = <t, s> / <t, t>;  x += alpha p + omega s;  r = s - omega t;
+// omega (see below);  x += alpha p + omega s;  r = s - omega t;
 // partials <rhat, r>, ||r||^2.
 __global__ __launch_bounds__(256) void k_bicg_xr(float2* __restrict__ x, float2* __restrict__ r,
                                                  const float2* __restrict__ rhat,
@@ -376,7 +377,19 @@ __global__ __launch_bounds__(256) void k_bicg_xr(float2* __restrict__ x, float2*
     sum_partials<4, 256>(partT + (size_t)vi.sys * npT * kPartialNV, npT, q, red);
     const SysState& s = st[vi.sys];
     const dcomplex alpha{s.alpha_re, s.alpha_im};
-    const dcomplex omega = (q[2] != 0.0) ? dcomplex{q[0] / q[2], q[1] / q[2]} : dcomplex{0.0, 0.0};
+    // omega = <t, s> / <t, t>, enlarged when t and s are far from parallel
+    // (|<t, s>| < 0.7 |t| |s|): the finite-precision safeguard of Sleijpen and
+    // van der Vorst (1995), which keeps the BiCG part from stalling.
+    dcomplex omega{0.0, 0.0};
+    if (q[2] != 0.0) {
+        omega = dcomplex{q[0] / q[2], q[1] / q[2]};
+        const double ts = sqrt(q[0] * q[0] + q[1] * q[1]);
+        const double c = (q[3] > 0.0) ? ts / sqrt(q[2] * q[3]) : 1.0;
+        if (c < kOmegaLimit && c > 0.0) {
+            omega.re *= kOmegaLimit / c;
+            omega.im *= kOmegaLimit / c;
+        }
+    }
     const float2 af = tof(alpha), of = tof(omega);
     const size_t off = (size_t)vi.sys * n;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -435,6 +448,48 @@ __global__ __launch_bounds__(256) void k_bicg_finish(const SysState* __restrict_
         if (iters) iters[sys] = st[sys].iter;
         if (relres) relres[sys] = bb > 0.0 ? sqrt(q[0] / bb) : 0.0;
     }
+}
+
+// After a solve: a system that converged on its recursive residual but whose
+// true residual ||b - A x||^2 (partials partTR) exceeds limit2 ||b||^2 is
+// marked ST_RESTART (at most max_restarts times).
+__global__ __launch_bounds__(256) void k_bicg_restart_mark(SysState* __restrict__ st,
+                                                           const double* __restrict__ partTR, int np,
+                                                           double limit2, int max_restarts) {
+    __shared__ double red[4 * 4];
+    const int sys = blockIdx.x;
+    if (st[sys].status != ST_CONVERGED) return;
+    double q[4];
+    sum_partials<4, 256>(partTR + (size_t)sys * np * kPartialNV, np, q, red);
+    if (threadIdx.x == 0 && q[0] > limit2 * st[sys].bnorm2 && st[sys].restarts < max_restarts) {
+        st[sys].status = ST_RESTART;
+        st[sys].restarts += 1;
+    }
+}
+
+// Restart marked systems from the true residual now in r (the caller reran
+// k_bicg_init with r0 = r): fresh BiCGSTAB scalars, iteration count kept.
+__global__ void k_bicg_restart(SysState* __restrict__ st, int nsys) {
+    const int sys = blockIdx.x * blockDim.x + threadIdx.x;
+    if (sys >= nsys || st[sys].status != ST_RESTART) return;
+    SysState& z = st[sys];
+    z.rho_re[0] = z.rho_re[1] = 1.0;
+    z.rho_im[0] = z.rho_im[1] = 0.0;
+    z.alpha_re = z.omega_re = 1.0;
+    z.alpha_im = z.omega_im = 0.0;
+    z.status = (z.iter >= z.maxit) ? ST_MAXIT : ST_RUNNING;
+}
+
+hipError_t launch_bicg_restart_mark(SysState* st, const double* partTR, int npTR, int nsys, double limit2,
+                                    int max_restarts, hipStream_t s) {
+    hipLaunchKernelGGL(k_bicg_restart_mark, dim3(nsys), dim3(256), 0, s, st, partTR, npTR, limit2,
+                       max_restarts);
+    return hipGetLastError();
+}
+
+hipError_t launch_bicg_restart(SysState* st, int nsys, hipStream_t s) {
+    hipLaunchKernelGGL(k_bicg_restart, dim3((nsys + 63) / 64), dim3(64), 0, s, st, nsys);
+    return hipGetLastError();
 }
 
 hipError_t launch_bicg_init(const float2* b, const float2* r0, float2* x, float2* r, float2* rhat,

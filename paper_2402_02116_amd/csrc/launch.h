@@ -13,7 +13,7 @@ enum RowEpilogue : int {
     EPI_STORE = 0,     // out = y
     EPI_APPLY = 1,     // out = u - y                          (A u)
     EPI_BICG_V = 2,    // out = u - y;  partial <aux, out>      (v = A p, <r^, v>)
-    EPI_BICG_T = 3,    // out = u - y;  partials <out, u>, ||out||^2   (t = A s)
+    EPI_BICG_T = 3,    // out = u - y;  partials <out, u>, ||out||^2, ||u||^2   (t = A s)
     EPI_TRUERES = 4,   // out = aux - (u - y); partial ||out||^2       (r = b - A x)
 };
 constexpr int kPartialNV = 4;   // doubles per partial-sum record
@@ -77,6 +77,9 @@ hipError_t launch_bicg_xr(float2* x, float2* r, const float2* rhat, const float2
                           const float2* sv, const float2* t, const double* partT, int npT,
                           double* partXR, SysState* st, int nsys, int n, hipStream_t s);
 hipError_t launch_bicg_check(SysState* st, const double* partXR, int npXR, int nsys, hipStream_t s);
+hipError_t launch_bicg_restart_mark(SysState* st, const double* partTR, int npTR, int nsys, double limit2,
+                                    int max_restarts, hipStream_t s);
+hipError_t launch_bicg_restart(SysState* st, int nsys, hipStream_t s);
 hipError_t launch_bicg_finish(const SysState* st, const double* partTR, int npTR, int nsys,
                               int32_t* iters, double* relres, hipStream_t s);
 
