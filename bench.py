@@ -103,6 +103,31 @@ def multigrid(a):
         res = plan.solve(u0, rtol=RTOL, maxit=1000)
         return int(np.sum((2 * res.iters + 1) * cells)), res
 
+    def solve_ms():
+        u0 = plan.incident(src, frc)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        plan.solve(u0, rtol=RTOL, maxit=1000)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) * 1e3
+
+    tuning = None
+    if not a.no_autotune:
+        step()
+        t_default = min(solve_ms() for _ in range(2))
+        t0 = time.perf_counter()
+        tuned = plan.autotune(reps=10)
+        t_tune = time.perf_counter() - t0
+        step()
+        t_tuned = min(solve_ms() for _ in range(2))
+        tuning = dict(tune_s=round(t_tune, 2), solve_ms_default=round(t_default, 3),
+                      solve_ms_tuned=round(t_tuned, 3),
+                      choices={str(p["nx"]): t for p, t in zip(probs, tuned)})
+        print(f"[bench] autotune {t_tune:.2f} s: solve {t_default:.1f} ms (default variants) -> "
+              f"{t_tuned:.1f} ms (tuned)", file=sys.stderr, flush=True)
+        for p, t in zip(probs, tuned):
+            print(f"[bench]   {p['nx']}^2: {t}", file=sys.stderr, flush=True)
+
     for _ in range(a.warmup):
         step()
     torch.cuda.synchronize()
@@ -125,7 +150,7 @@ def multigrid(a):
                            grids=[p["nx"] for p in probs], nsys=int(len(src)), rtol=RTOL,
                            cells_per_matvec=int(cells.sum())),
                time_to_1e6_ms=round(t_solve, 3), iters=[int(res.iters.min()), int(res.iters.max())],
-               max_true_relres=float(res.relres.max()))
+               max_true_relres=float(res.relres.max()), autotune=tuning)
     print(json.dumps(out), flush=True)
     return 0
 
@@ -160,6 +185,7 @@ def main(argv=None):
     ap.add_argument("--reps", type=int, default=50, help="launches per kernel timing")
     ap.add_argument("--cpu-sample", type=int, default=4, help="systems in the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the built-in kernel variants")
     ap.add_argument("--workload", choices=["vti256x16", "multigrid"], default="vti256x16")
     a = ap.parse_args(argv)
     if a.gpus != 1:
@@ -181,6 +207,12 @@ def main(argv=None):
                       eta=c["eta"], nsys=ns)], device="cuda:0")
     plan.set_contrast(0, c["maps"])
     plan.set_receivers(0, rec)
+    tuning = None
+    if not a.no_autotune:
+        t0 = time.perf_counter()
+        tuning = dict(choice=plan.autotune(reps=20)[0])
+        tuning["tune_s"] = round(time.perf_counter() - t0, 2)
+        print(f"[bench] autotune: {tuning}", file=sys.stderr, flush=True)
     dm = torch.as_tensor(dm_np).cuda()
     r = torch.as_tensor(r_np.ravel()).cuda()
 
@@ -297,7 +329,7 @@ def main(argv=None):
                                    speedup=round(tp[len(tp) // 2] / tb[len(tb) // 2], 2),
                                    iters=[int(tbr.iters.min()), int(tbr.iters.max())],
                                    max_true_relres=float(tbr.relres.max()), identical=same),
-               copy_gbs=round(copy_gbs, 1),
+               copy_gbs=round(copy_gbs, 1), autotune=tuning,
                matvec=dict(gpoints_s=round(matvec_gps, 3), us=round(t_apply * 1e3, 3),
                            pass_us=[round(t * 1e3, 3) for t in t_pass],
                            pass_gbs=[round(g, 1) for g in gbs]))

@@ -62,7 +62,7 @@
 extern "C" {
 #endif
 
-#define FWILS_ABI_VERSION 1
+#define FWILS_ABI_VERSION 2
 
 typedef enum {
     FWILS_OK = 0,
@@ -252,6 +252,45 @@ fwils_status fwils_laplacian(fwils_plan plan, const float* q, float* out);
  * no 1/(nx nz)).  A self-test entry point.  in, out: device, may alias. */
 fwils_status fwils_fft2(fwils_plan plan, int32_t iprob, const void* in, void* out,
                         int32_t inverse);
+
+/* ---------------------------------------------------------- autotuner ----
+ * The batched schedule over uneven grids picks, per problem, one variant of
+ * each hot kernel: the radix sequence of the row and column transforms
+ * (points per thread), the column tile width and LDS sharing of the column
+ * pass, and the contrast-stencil tile height and systems per workgroup.
+ * Every variant computes the same operator; different radix orders round
+ * differently (fp32 rounding level).  A new plan starts from built-in
+ * defaults.  Changing a problem's variants drops the plan's cached graph. */
+typedef struct {
+    int32_t row_points;    /* row-transform points per thread (radix sequence) */
+    int32_t col_points;    /* column-transform points per thread */
+    int32_t col_width;     /* columns per column workgroup (power of two) */
+    int32_t col_shared;    /* 1: the two components share one LDS buffer */
+    int32_t stencil_rows;  /* contrast-stencil tile height: 4, 8 or 16 */
+    int32_t stencil_sys;   /* systems per stencil workgroup, 0 = from the grid size */
+    float time_us[3];      /* autotuner's time of the chosen stencil, row and column
+                              kernel over all systems of the problem (0 if not tuned) */
+} fwils_tuning;
+
+#define FWILS_TUNE_STENCIL 0
+#define FWILS_TUNE_ROWS 1
+#define FWILS_TUNE_COLS 2
+
+/* Time every candidate variant of each kernel kind on the plan's workspace
+ * (which must be set; its field vectors are overwritten), reps launches each
+ * (1..1000) with HIP events on the plan's stream, and keep the fastest per
+ * problem.  Synchronous. */
+fwils_status fwils_autotune(fwils_plan plan, int32_t reps);
+/* Current variants of problem iprob. */
+fwils_status fwils_get_tuning(fwils_plan plan, int32_t iprob, fwils_tuning* out);
+/* Set the variants of problem iprob (time_us ignored).  EINVAL, with nothing
+ * changed, if any field is not a built variant for this grid. */
+fwils_status fwils_set_tuning(fwils_plan plan, int32_t iprob, const fwils_tuning* t);
+/* The candidates of one kernel kind (FWILS_TUNE_*) for problem iprob, each
+ * the current variants with that kind's fields replaced.  Writes up to cap
+ * entries to out (host) and the total number to *count. */
+fwils_status fwils_tuning_candidates(fwils_plan plan, int32_t iprob, int32_t kind, fwils_tuning* out,
+                                     int32_t cap, int32_t* count);
 
 const char* fwils_status_string(fwils_status s);
 const char* fwils_last_error(void);

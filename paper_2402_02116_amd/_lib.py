@@ -29,6 +29,21 @@ class FwilsProblem(ctypes.Structure):
                 ("nsys", c_int32), ("symbol", c_int32)]
 
 
+class FwilsTuning(ctypes.Structure):
+    _fields_ = [("row_points", c_int32), ("col_points", c_int32), ("col_width", c_int32),
+                ("col_shared", c_int32), ("stencil_rows", c_int32), ("stencil_sys", c_int32),
+                ("time_us", ctypes.c_float * 3)]
+
+    FIELDS = ("row_points", "col_points", "col_width", "col_shared", "stencil_rows", "stencil_sys")
+
+    def to_dict(self):
+        d = {k: int(getattr(self, k)) for k in self.FIELDS}
+        d["time_us"] = [float(x) for x in self.time_us]
+        return d
+
+
+FWILS_TUNE_STENCIL, FWILS_TUNE_ROWS, FWILS_TUNE_COLS = 0, 1, 2
+
 P = c_void_p
 SIGNATURES = {
     "fwils_plan_create": (c_int32, [ctypes.POINTER(FwilsProblem), c_int32, c_int32, ctypes.POINTER(c_void_p)]),
@@ -58,6 +73,11 @@ SIGNATURES = {
     "fwils_adjoint_rel": (c_int32, [P, P, P, ctypes.POINTER(c_double), P, c_double, c_int32]),
     "fwils_laplacian": (c_int32, [P, P, P]),
     "fwils_solve_stats": (c_int32, [P, ctypes.POINTER(c_int32), ctypes.POINTER(c_double)]),
+    "fwils_autotune": (c_int32, [P, c_int32]),
+    "fwils_get_tuning": (c_int32, [P, c_int32, ctypes.POINTER(FwilsTuning)]),
+    "fwils_set_tuning": (c_int32, [P, c_int32, ctypes.POINTER(FwilsTuning)]),
+    "fwils_tuning_candidates": (c_int32, [P, c_int32, c_int32, ctypes.POINTER(FwilsTuning), c_int32,
+                                          ctypes.POINTER(c_int32)]),
     "fwils_status_string": (ctypes.c_char_p, [c_int32]),
     "fwils_last_error": (ctypes.c_char_p, []),
     "fwils_abi_version": (c_int32, []),

@@ -19,7 +19,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfwils.so")
-SOURCES = ["kernels_fft.hip", "kernels_vec.hip", "kernels_maps.hip", "capi.cpp"]
+SOURCES = ["kernels_rows.hip", "kernels_cols.hip", "kernels_fft.hip", "kernels_vec.hip", "kernels_maps.hip",
+           "capi.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -64,6 +64,8 @@ struct ProbHost {
     int nrec;
     int np_rows;          // partial records per system from the row epilogues
     int np_vec;           // partial records per system from vector kernels
+    KernelCfg cfg;        // kernel variants (defaults, the autotuner's or the caller's)
+    float tuned_us[3];    // autotune: stencil, row, column time of the choice
 };
 
 }  // namespace
@@ -150,10 +152,10 @@ inline float* maps_at(fwils_plan pl, const ProbHost& P) { return pl->maps + P.ma
 hipError_t conv_problem(fwils_plan pl, const ProbHost& P, const float2* f, float2* out) {
     const int rows = P.p.nsys * 2 * P.p.nz;
     float2* tmp = at(pl->tmp, P);
-    hipError_t e = launch_rows_fwd(P.p.nx, f, tmp, rows, 2 * P.p.nz, nullptr, pl->tw, pl->stream);
-    if (e == hipSuccess) e = launch_cols(COL_GREEN, tmp, P.dev, nullptr, pl->tw, pl->stream);
+    hipError_t e = launch_rows_fwd(P.p.nx, P.cfg.row_p, f, tmp, rows, 2 * P.p.nz, nullptr, pl->tw, pl->stream);
+    if (e == hipSuccess) e = launch_cols(COL_GREEN, P.cfg.col, tmp, P.dev, nullptr, pl->tw, pl->stream);
     if (e == hipSuccess)
-        e = launch_rows_inv(P.p.nx, EPI_STORE, tmp, nullptr, nullptr, out, nullptr, rows,
+        e = launch_rows_inv(P.p.nx, P.cfg.row_p, EPI_STORE, tmp, nullptr, nullptr, out, nullptr, rows,
                             2 * P.p.nz, nullptr, pl->tw, pl->stream);
     return e;
 }
@@ -164,12 +166,12 @@ hipError_t matvec(fwils_plan pl, const ProbHost& P, const ProbDev& d, const floa
                   const float* maps, int epi, const float2* aux, float2* out, double* part,
                   const SysState* st, hipStream_t s) {
     const int rows = d.nsys * 2 * d.nz;
-    hipError_t e = launch_body_force(u, tmp, maps, d, st, s);
-    if (e == hipSuccess) e = launch_rows_fwd(d.nx, tmp, tmp, rows, 2 * d.nz, st, pl->tw, s);
-    if (e == hipSuccess) e = launch_cols(COL_GREEN, tmp, d, st, pl->tw, s);
+    const KernelCfg& k = P.cfg;
+    hipError_t e = launch_body_force(k.st, u, tmp, maps, d, st, s);
+    if (e == hipSuccess) e = launch_rows_fwd(d.nx, k.row_p, tmp, tmp, rows, 2 * d.nz, st, pl->tw, s);
+    if (e == hipSuccess) e = launch_cols(COL_GREEN, k.col, tmp, d, st, pl->tw, s);
     if (e == hipSuccess)
-        e = launch_rows_inv(d.nx, epi, tmp, u, aux, out, part, rows, 2 * d.nz, st, pl->tw, s);
-    (void)P;
+        e = launch_rows_inv(d.nx, k.row_p, epi, tmp, u, aux, out, part, rows, 2 * d.nz, st, pl->tw, s);
     return e;
 }
 
@@ -213,17 +215,19 @@ hipError_t bicg_iteration(fwils_plan pl, const ProbHost& P, const SysView& V, in
     double *pV = pl->partV + V.poff_row, *pT = pl->partT + V.poff_row, *pXR = pl->partXR + V.poff_vec;
     const float* maps = maps_at(pl, P);
     const StencilArgs ap{r, pold, v, pnew, tmp, maps, pXR, P.np_vec};
-    hipError_t e = launch_stencil(1, ap, V.d, st, s);
-    if (e == hipSuccess) e = launch_rows_fwd(V.d.nx, tmp, tmp, rows, 2 * V.d.nz, st, pl->tw, s);
-    if (e == hipSuccess) e = launch_cols(COL_GREEN, tmp, V.d, st, pl->tw, s);
+    const KernelCfg& k = P.cfg;
+    hipError_t e = launch_stencil(1, k.st, ap, V.d, st, s);
+    if (e == hipSuccess) e = launch_rows_fwd(V.d.nx, k.row_p, tmp, tmp, rows, 2 * V.d.nz, st, pl->tw, s);
+    if (e == hipSuccess) e = launch_cols(COL_GREEN, k.col, tmp, V.d, st, pl->tw, s);
     if (e == hipSuccess)
-        e = launch_rows_inv(V.d.nx, EPI_BICG_V, tmp, pnew, rh, v, pV, rows, 2 * V.d.nz, st, pl->tw, s);
+        e = launch_rows_inv(V.d.nx, k.row_p, EPI_BICG_V, tmp, pnew, rh, v, pV, rows, 2 * V.d.nz, st, pl->tw, s);
     const StencilArgs as{r, v, nullptr, sv, tmp, maps, pV, P.np_rows};
-    if (e == hipSuccess) e = launch_stencil(2, as, V.d, st, s);
-    if (e == hipSuccess) e = launch_rows_fwd(V.d.nx, tmp, tmp, rows, 2 * V.d.nz, st, pl->tw, s);
-    if (e == hipSuccess) e = launch_cols(COL_GREEN, tmp, V.d, st, pl->tw, s);
+    if (e == hipSuccess) e = launch_stencil(2, k.st, as, V.d, st, s);
+    if (e == hipSuccess) e = launch_rows_fwd(V.d.nx, k.row_p, tmp, tmp, rows, 2 * V.d.nz, st, pl->tw, s);
+    if (e == hipSuccess) e = launch_cols(COL_GREEN, k.col, tmp, V.d, st, pl->tw, s);
     if (e == hipSuccess)
-        e = launch_rows_inv(V.d.nx, EPI_BICG_T, tmp, sv, nullptr, t, pT, rows, 2 * V.d.nz, st, pl->tw, s);
+        e = launch_rows_inv(V.d.nx, k.row_p, EPI_BICG_T, tmp, sv, nullptr, t, pT, rows, 2 * V.d.nz, st, pl->tw,
+                            s);
     if (e == hipSuccess) e = launch_bicg_xr(x, r, rh, pnew, sv, t, pT, P.np_rows, pXR, st, ns, n, s);
     return e;
 }
@@ -453,9 +457,17 @@ fwils_status fwils_plan_create(const fwils_problem* probs, int32_t nprob, fwils_
         P.map_off = moff;
         P.data_off = 0;
         P.nrec = 0;
-        P.np_rows = row_geom(P.p.nx, 2 * P.p.nz).blocks_per_sys;
+        P.cfg = kernel_cfg_default(P.p.nx, P.p.nz);
+        P.tuned_us[0] = P.tuned_us[1] = P.tuned_us[2] = 0.f;
+        P.np_rows = row_geom(P.p.nx, P.cfg.row_p, 2 * P.p.nz).blocks_per_sys;
         P.np_vec = vec_blocks_per_sys((int)P.n_per_sys);
-        pl->max_np = std::max(pl->max_np, std::max(P.np_rows, P.np_vec));
+        pl->max_np = std::max(pl->max_np, P.np_vec);
+        {   // partial buffers fit every row-transform variant
+            int cand[2];
+            const int nc = row_candidates(P.p.nx, cand);
+            for (int c = 0; c < nc; ++c)
+                pl->max_np = std::max(pl->max_np, row_geom(P.p.nx, cand[c], 2 * P.p.nz).blocks_per_sys);
+        }
         foff += (size_t)P.p.nsys * P.n_per_sys;
         soff += (size_t)P.p.nsys;
         moff += (size_t)5 * P.p.nz * P.p.nx;
@@ -657,7 +669,7 @@ fwils_status fwils_body_force(fwils_plan plan, const void* u, void* b) {
     FW_TRY(check_plan(plan));
     FW_TRY(check_field_ptrs({u, b}));
     for (const ProbHost& P : plan->probs)
-        FW_HIP(launch_body_force(at(u, P), static_cast<float2*>(b) + P.field_off, maps_at(plan, P), P.dev,
+        FW_HIP(launch_body_force(P.cfg.st, at(u, P), static_cast<float2*>(b) + P.field_off, maps_at(plan, P), P.dev,
                                  nullptr, plan->stream));
     return FWILS_OK;
 }
@@ -713,7 +725,7 @@ fwils_status frechet_ws(fwils_plan plan, const void* ub, const float* const* dm,
     for (size_t i = 0; i < plan->probs.size(); ++i) {
         const ProbHost& P = plan->probs[i];
         // virtual source P_b(dm): the contrast stencil applied to u^b with dm
-        FW_HIP(launch_body_force(at(ub, P), at(plan->s, P), dm[i], P.dev, nullptr, s));
+        FW_HIP(launch_body_force(P.cfg.st, at(ub, P), at(plan->s, P), dm[i], P.dev, nullptr, s));
         FW_HIP(conv_problem(plan, P, at(plan->s, P), at(plan->rhs, P)));
     }
     fwils_status st = solve_ws(plan, plan->rhs, false, rtol, maxit, nullptr, nullptr, 0);
@@ -1034,11 +1046,13 @@ fwils_status fwils_apply_pass(fwils_plan plan, int32_t pass, const void* u, void
         const int rows = P.p.nsys * 2 * P.p.nz;
         float2* tmp = at(plan->tmp, P);
         switch (pass) {
-            case 0: FW_HIP(launch_body_force(at(u, P), tmp, maps_at(plan, P), P.dev, nullptr, s)); break;
-            case 1: FW_HIP(launch_rows_fwd(P.p.nx, tmp, tmp, rows, 2 * P.p.nz, nullptr, plan->tw, s)); break;
-            case 2: FW_HIP(launch_cols(COL_GREEN, tmp, P.dev, nullptr, plan->tw, s)); break;
+            case 0: FW_HIP(launch_body_force(P.cfg.st, at(u, P), tmp, maps_at(plan, P), P.dev, nullptr, s)); break;
+            case 1:
+                FW_HIP(launch_rows_fwd(P.p.nx, P.cfg.row_p, tmp, tmp, rows, 2 * P.p.nz, nullptr, plan->tw, s));
+                break;
+            case 2: FW_HIP(launch_cols(COL_GREEN, P.cfg.col, tmp, P.dev, nullptr, plan->tw, s)); break;
             default:
-                FW_HIP(launch_rows_inv(P.p.nx, EPI_APPLY, tmp, at(u, P), nullptr,
+                FW_HIP(launch_rows_inv(P.p.nx, P.cfg.row_p, EPI_APPLY, tmp, at(u, P), nullptr,
                                        static_cast<float2*>(Au) + P.field_off, nullptr, rows, 2 * P.p.nz,
                                        nullptr, plan->tw, s));
         }
@@ -1059,6 +1073,198 @@ fwils_status fwils_solve_stats(fwils_plan plan, int32_t* iters, double* relres) 
     return FWILS_OK;
 }
 
+}  // extern "C"
+
+// ------------------------------------------------------------ autotuner --
+namespace {
+
+fwils_tuning to_tuning(const ProbHost& P) {
+    fwils_tuning t;
+    t.row_points = P.cfg.row_p;
+    t.col_points = P.cfg.col.P;
+    t.col_width = P.cfg.col.W;
+    t.col_shared = P.cfg.col.seq;
+    t.stencil_rows = P.cfg.st.TZ;
+    t.stencil_sys = P.cfg.st.S;
+    for (int k = 0; k < 3; ++k) t.time_us[k] = P.tuned_us[k];
+    return t;
+}
+
+KernelCfg from_tuning(const fwils_tuning& t) {
+    KernelCfg k;
+    k.row_p = t.row_points;
+    k.col = ColCfg{t.col_points, t.col_width, t.col_shared};
+    k.st = StCfg{t.stencil_rows, t.stencil_sys};
+    return k;
+}
+
+bool cfg_ok(const ProbHost& P, const KernelCfg& k) {
+    return row_points_ok(P.p.nx, k.row_p) && col_cfg_ok(P.p.nz, P.p.nx, k.col) &&
+           st_cfg_ok(P.p.nx, P.p.nz, k.st);
+}
+
+void apply_cfg(fwils_plan pl, ProbHost& P, const KernelCfg& k) {
+    P.cfg = k;
+    P.np_rows = row_geom(P.p.nx, k.row_p, 2 * P.p.nz).blocks_per_sys;
+    if (pl->chunk) {
+        (void)hipGraphExecDestroy(pl->chunk);
+        pl->chunk = nullptr;
+    }
+}
+
+// Candidates of one kind: the problem's current variants with that kind's
+// fields replaced.
+std::vector<KernelCfg> candidates(const ProbHost& P, int kind) {
+    std::vector<KernelCfg> out;
+    if (kind == FWILS_TUNE_STENCIL) {
+        StCfg c[32];
+        const int n = st_candidates(P.p.nx, P.p.nz, c, 32);
+        for (int i = 0; i < n; ++i) {
+            KernelCfg k = P.cfg;
+            k.st = c[i];
+            out.push_back(k);
+        }
+    } else if (kind == FWILS_TUNE_ROWS) {
+        int c[2];
+        const int n = row_candidates(P.p.nx, c);
+        for (int i = 0; i < n; ++i) {
+            KernelCfg k = P.cfg;
+            k.row_p = c[i];
+            out.push_back(k);
+        }
+    } else if (kind == FWILS_TUNE_COLS) {
+        ColCfg c[64];
+        const int n = col_candidates(P.p.nz, P.p.nx, c, 64);
+        for (int i = 0; i < n; ++i) {
+            KernelCfg k = P.cfg;
+            k.col = c[i];
+            out.push_back(k);
+        }
+    }
+    return out;
+}
+
+// One launch of the kernel of the given kind, variant k, over all systems of
+// problem P (fields from the workspace vectors; every system active).
+hipError_t tune_launch(fwils_plan pl, const ProbHost& P, int kind, const KernelCfg& k) {
+    const int rows = P.p.nsys * 2 * P.p.nz;
+    float2* u = at(pl->x, P);
+    float2* tmp = at(pl->tmp, P);
+    if (kind == FWILS_TUNE_STENCIL) return launch_body_force(k.st, u, tmp, maps_at(pl, P), P.dev, nullptr, pl->stream);
+    if (kind == FWILS_TUNE_ROWS)
+        return launch_rows_fwd(P.p.nx, k.row_p, tmp, tmp, rows, 2 * P.p.nz, nullptr, pl->tw, pl->stream);
+    return launch_cols(COL_GREEN, k.col, tmp, P.dev, nullptr, pl->tw, pl->stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+fwils_status fwils_autotune(fwils_plan plan, int32_t reps) {
+    FW_TRY(check_plan(plan));
+    if (reps < 1 || reps > 1000) {
+        set_error("autotune: reps must be 1..1000");
+        return FWILS_EINVAL;
+    }
+    hipStream_t s = plan->stream;
+    hipEvent_t e0, e1;
+    FW_HIP(hipEventCreate(&e0));
+    FW_HIP(hipEventCreate(&e1));
+    fwils_status st = FWILS_OK;
+    for (ProbHost& P : plan->probs) {
+        // finite inputs for every candidate
+        hipError_t he = launch_zero(at(plan->x, P), (size_t)P.p.nsys * P.n_per_sys, s);
+        if (he == hipSuccess) he = launch_zero(at(plan->tmp, P), (size_t)P.p.nsys * P.n_per_sys, s);
+        if (he != hipSuccess) {
+            set_error("autotune: %s", hipGetErrorString(he));
+            st = FWILS_EDEVICE;
+            break;
+        }
+        KernelCfg best = P.cfg;
+        float best_us[3] = {0.f, 0.f, 0.f};
+        for (int kind = 0; kind < 3 && st == FWILS_OK; ++kind) {
+            float tbest = 0.f;
+            for (const KernelCfg& k : candidates(P, kind)) {
+                float ms = 0.f;
+                he = tune_launch(plan, P, kind, k);   // warm-up (and first-use set-up)
+                if (he == hipSuccess) he = hipEventRecord(e0, s);
+                for (int r = 0; r < reps && he == hipSuccess; ++r) he = tune_launch(plan, P, kind, k);
+                if (he == hipSuccess) he = hipEventRecord(e1, s);
+                if (he == hipSuccess) he = hipEventSynchronize(e1);
+                if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+                if (he != hipSuccess) {
+                    set_error("autotune: %s", hipGetErrorString(he));
+                    st = FWILS_EDEVICE;
+                    break;
+                }
+                const float us = ms * 1e3f / (float)reps;
+                if (tbest == 0.f || us < tbest) {
+                    tbest = us;
+                    if (kind == FWILS_TUNE_STENCIL) best.st = k.st;
+                    else if (kind == FWILS_TUNE_ROWS) best.row_p = k.row_p;
+                    else best.col = k.col;
+                }
+            }
+            best_us[kind] = tbest;
+        }
+        if (st != FWILS_OK) break;
+        apply_cfg(plan, P, best);
+        for (int k = 0; k < 3; ++k) P.tuned_us[k] = best_us[k];
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return st;
+}
+
+fwils_status fwils_get_tuning(fwils_plan plan, int32_t iprob, fwils_tuning* out) {
+    FW_TRY(check_plan(plan, false));
+    if (!out || iprob < 0 || iprob >= (int)plan->probs.size()) {
+        set_error("get_tuning: bad problem index or null output");
+        return FWILS_EINVAL;
+    }
+    *out = to_tuning(plan->probs[iprob]);
+    return FWILS_OK;
+}
+
+fwils_status fwils_set_tuning(fwils_plan plan, int32_t iprob, const fwils_tuning* t) {
+    FW_TRY(check_plan(plan, false));
+    if (!t || iprob < 0 || iprob >= (int)plan->probs.size()) {
+        set_error("set_tuning: bad problem index or null input");
+        return FWILS_EINVAL;
+    }
+    ProbHost& P = plan->probs[iprob];
+    const KernelCfg k = from_tuning(*t);
+    if (!cfg_ok(P, k)) {
+        set_error("set_tuning: not a built variant for %dx%d (rows %d, cols %d/%d/%d, stencil %d/%d)",
+                  P.p.nz, P.p.nx, t->row_points, t->col_points, t->col_width, t->col_shared,
+                  t->stencil_rows, t->stencil_sys);
+        return FWILS_EINVAL;
+    }
+    apply_cfg(plan, P, k);
+    P.tuned_us[0] = P.tuned_us[1] = P.tuned_us[2] = 0.f;
+    return FWILS_OK;
+}
+
+fwils_status fwils_tuning_candidates(fwils_plan plan, int32_t iprob, int32_t kind, fwils_tuning* out,
+                                     int32_t cap, int32_t* count) {
+    FW_TRY(check_plan(plan, false));
+    if (!count || iprob < 0 || iprob >= (int)plan->probs.size() || kind < 0 || kind > 2 || cap < 0 ||
+        (cap > 0 && !out)) {
+        set_error("tuning_candidates: bad arguments");
+        return FWILS_EINVAL;
+    }
+    const ProbHost& P = plan->probs[iprob];
+    const std::vector<KernelCfg> c = candidates(P, kind);
+    *count = (int32_t)c.size();
+    for (int i = 0; i < (int)c.size() && i < cap; ++i) {
+        ProbHost Q = P;
+        Q.cfg = c[i];
+        Q.tuned_us[0] = Q.tuned_us[1] = Q.tuned_us[2] = 0.f;
+        out[i] = to_tuning(Q);
+    }
+    return FWILS_OK;
+}
+
 fwils_status fwils_fft2(fwils_plan plan, int32_t iprob, const void* in, void* out, int32_t inverse) {
     FW_TRY(check_plan(plan));
     FW_TRY(check_field_ptrs({in, out}));
@@ -1072,12 +1278,14 @@ fwils_status fwils_fft2(fwils_plan plan, int32_t iprob, const void* in, void* ou
     float2* dst = static_cast<float2*>(out);
     hipStream_t s = plan->stream;
     if (!inverse) {
-        FW_HIP(launch_rows_fwd(P.p.nx, src, dst, rows, 2 * P.p.nz, nullptr, plan->tw, s));
-        FW_HIP(launch_cols(COL_FWD, dst, P.dev, nullptr, plan->tw, s));
+        FW_HIP(launch_rows_fwd(P.p.nx, row_points_default(P.p.nx), src, dst, rows, 2 * P.p.nz, nullptr,
+                               plan->tw, s));
+        FW_HIP(launch_cols(COL_FWD, col_default(P.p.nz, P.p.nx), dst, P.dev, nullptr, plan->tw, s));
     } else {
-        FW_HIP(launch_rows_inv(P.p.nx, EPI_STORE, src, nullptr, nullptr, dst, nullptr, rows, 2 * P.p.nz,
+        FW_HIP(launch_rows_inv(P.p.nx, row_points_default(P.p.nx), EPI_STORE, src, nullptr, nullptr, dst,
+                               nullptr, rows, 2 * P.p.nz,
                                nullptr, plan->tw, s));
-        FW_HIP(launch_cols(COL_INV, dst, P.dev, nullptr, plan->tw, s));
+        FW_HIP(launch_cols(COL_INV, col_default(P.p.nz, P.p.nx), dst, P.dev, nullptr, plan->tw, s));
     }
     return FWILS_OK;
 }

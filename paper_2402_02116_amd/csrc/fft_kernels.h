@@ -1,0 +1,288 @@
+// Kernel templates of the FFT passes of the LS matvec (eqs. A and FFT):
+//   k_rows  - forward row transforms (after the contrast stencil), and
+//             inverse row transforms fused with the LS / BiCGSTAB epilogues
+//             and their FP64 partial inner products;
+//   k_cols  - column transforms fused with the multiplication by the
+//             wavenumber-domain Green's tensor G_hat(k), in place.
+// Each translation unit that launches a (size, points-per-thread) variant
+// instantiates it from here.
+#pragma once
+
+#include "fft.h"
+#include "launch.h"
+
+namespace fw {
+
+// ------------------------------------------------------- block reduce ----
+// Runtime block size (a multiple of 64, at most 256): fixed-order sum of
+// NV doubles; thread 0 receives the total.
+template <int NV>
+__device__ __forceinline__ void block_sum_to0(double (&acc)[NV], double* smem) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) acc[k] += __shfl_xor(acc[k], off, 64);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) smem[wave * NV + k] = acc[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double s = 0.0;
+            for (int w = 0; w < nw; ++w) s += smem[w * NV + k];
+            acc[k] = s;
+        }
+    }
+}
+
+// --------------------------------------------------------- row kernel ----
+struct RowLds {
+    float2* p;
+    __device__ __forceinline__ float2& operator()(int, int pos) const { return p[lds_pad(pos)]; }
+};
+
+// Row transforms of F rows per block, P points per thread (T = N / P threads
+// per row).  `in` and `out` may be the same array (in-place forward pass):
+// every block reads all of its rows before its barriers and writes them after.
+template <int N, int P, bool INV, int EPI>
+__global__ __launch_bounds__(256) void k_rows(const float2* in, float2* out,
+                                              const float2* __restrict__ u,
+                                              const float2* __restrict__ aux,
+                                              double* __restrict__ partials, int nrows,
+                                              int rows_per_sys, int F,
+                                              const SysState* __restrict__ st,
+                                              const float2* __restrict__ tw) {
+    using S = FftShape<N, P>;
+    constexpr int T = S::T;
+    constexpr int PL = PaddedLen<N>::value;
+    extern __shared__ float2 lds_dyn[];
+    __shared__ double red[4 * kPartialNV];
+
+    const int tid = threadIdx.x;
+    const int q = tid / T, t = tid % T;
+    const int row0 = blockIdx.x * F;
+    const int sys = row0 / rows_per_sys;
+    if (st != nullptr && st[sys].status != ST_RUNNING) return;
+    const int row = row0 + q;
+    const bool active = (q < F) && (row < nrows);
+
+    float2 v[1][P];
+    if (active) {
+        const float2* src = in + (size_t)row * N;
+#pragma unroll
+        for (int m = 0; m < P; ++m) v[0][m] = src[t + T * m];
+    } else {
+#pragma unroll
+        for (int m = 0; m < P; ++m) v[0][m] = make_float2(0.f, 0.f);
+    }
+    // idle threads (block padded to whole waves) work in a dummy slot F
+    RowLds lds{lds_dyn + (size_t)(q < F ? q : F) * PL};
+    fft_run<N, P, INV, 1>(v, t, tw, lds);
+
+    double acc[kPartialNV] = {0.0, 0.0, 0.0, 0.0};
+    if (active) {
+        const size_t base = (size_t)row * N;
+#pragma unroll
+        for (int m = 0; m < P; ++m) {
+            const size_t i = base + t + T * m;
+            const float2 y = v[0][m];
+            if constexpr (EPI == EPI_STORE) {
+                out[i] = y;
+            } else {
+                const float2 uu = u[i];
+                const float2 o = csub(uu, y);
+                if constexpr (EPI == EPI_APPLY) {
+                    out[i] = o;
+                } else if constexpr (EPI == EPI_BICG_V) {
+                    out[i] = o;
+                    const float2 a = aux[i];
+                    acc[0] += (double)a.x * o.x + (double)a.y * o.y;
+                    acc[1] += (double)a.x * o.y - (double)a.y * o.x;
+                } else if constexpr (EPI == EPI_BICG_T) {
+                    out[i] = o;
+                    acc[0] += (double)o.x * uu.x + (double)o.y * uu.y;
+                    acc[1] += (double)o.x * uu.y - (double)o.y * uu.x;
+                    acc[2] += (double)o.x * o.x + (double)o.y * o.y;
+                    acc[3] += (double)uu.x * uu.x + (double)uu.y * uu.y;
+                } else if constexpr (EPI == EPI_TRUERES) {
+                    const float2 b = aux[i];
+                    const float2 rr = csub(b, o);
+                    out[i] = rr;
+                    acc[0] += (double)rr.x * rr.x + (double)rr.y * rr.y;
+                }
+            }
+        }
+    }
+    if constexpr (EPI >= EPI_BICG_V) {
+        block_sum_to0<kPartialNV>(acc, red);
+        if (tid == 0) {
+            const int nb = rows_per_sys / F;
+            const int bi = (row0 % rows_per_sys) / F;
+            double* dst = partials + ((size_t)sys * nb + bi) * kPartialNV;
+#pragma unroll
+            for (int k = 0; k < kPartialNV; ++k) dst[k] = acc[k];
+        }
+    }
+}
+
+// ------------------------------------------------------ column kernel ----
+struct ColLds {
+    float2* base;   // this thread's column (or its private dummy slot)
+    int stride;     // W (columns interleaved) or 1 (dummy slot)
+    int PL;
+    __device__ __forceinline__ float2& operator()(int f, int pos) const {
+        return base[(f * PL + lds_pad(pos)) * stride];
+    }
+};
+
+// (bx, bz) <- G_hat (bx, bz) with G_hat = gscale (Gamma' - ga I)^-1 for the
+// real symmetric scaled Christoffel matrix Gamma' = [[gxx, gxz], [gxz, gzz]].
+__device__ __forceinline__ void green_mul(float2& bx, float2& bz, float gxx, float gzz, float gxz,
+                                          float2 ga, float gscale) {
+    const float2 mxx = make_float2(gxx - ga.x, -ga.y);
+    const float2 mzz = make_float2(gzz - ga.x, -ga.y);
+    float2 det = cmul(mxx, mzz);
+    det.x -= gxz * gxz;
+    const float s = gscale / (det.x * det.x + det.y * det.y);
+    const float2 inv = make_float2(det.x * s, -det.y * s);
+    const float2 gx = cmul(inv, bx), gz = cmul(inv, bz);   // inv b
+    const float2 ox = csub(cmul(mzz, gx), cscale(gz, gxz));
+    const float2 oz = csub(cmul(mxx, gz), cscale(gx, gxz));
+    bx = ox;
+    bz = oz;
+}
+
+// Signed FFT index of i on an n-point axis (numpy fftfreq order).
+__device__ __forceinline__ int fft_signed(int i, int n) { return (i < (n + 1) / 2) ? i : i - n; }
+
+// Column transforms (with the Green multiply in COL_GREEN mode) of W columns
+// per block, P points per thread.  SEQ: the two field components share one
+// LDS buffer and go through each pass one after the other; otherwise each
+// has its own buffer (twice the LDS, half the barriers).
+template <int N, int P, int MODE, bool SEQ>
+__global__ __launch_bounds__(512) void k_cols(float2* __restrict__ data, ProbDev pd, int W,
+                                              const SysState* __restrict__ st,
+                                              const float2* __restrict__ tw) {
+    using S = FftShape<N, P>;
+    constexpr int T = S::T;
+    constexpr int PL = PaddedLen<N>::value;
+    extern __shared__ float2 lds_dyn[];
+
+    const int nx = pd.nx;
+    const int tid = threadIdx.x;
+    const int c = tid % W, t = tid / W;
+    const int ntile = nx / W;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int sys = blk / ntile;
+    const int x0 = (blk % ntile) * W;
+    if (st != nullptr && st[sys].status != ST_RUNNING) return;
+    const bool active = t < T;
+
+    float2* base = data + (size_t)sys * 2 * N * nx + x0 + c;
+    const size_t plane = (size_t)N * nx;
+    float2 v[2][P];
+    if (active) {
+#pragma unroll
+        for (int f = 0; f < 2; ++f)
+#pragma unroll
+            for (int m = 0; m < P; ++m) v[f][m] = base[f * plane + (size_t)(t + T * m) * nx];
+    } else {
+#pragma unroll
+        for (int f = 0; f < 2; ++f)
+#pragma unroll
+            for (int m = 0; m < P; ++m) v[f][m] = make_float2(0.f, 0.f);
+    }
+    ColLds lds{active ? lds_dyn + c : lds_dyn + (size_t)PL * W * (SEQ ? 1 : 2), active ? W : 1, PL};
+    const int tt = active ? t : 0;
+
+    if constexpr (MODE != COL_INV) {
+        if constexpr (SEQ) fft_run_seq<N, P, false, 2>(v, tt, tw, lds);
+        else fft_run<N, P, false, 2>(v, tt, tw, lds);
+    }
+    if constexpr (MODE == COL_GREEN) {
+        // u_hat = G_hat(k) b_hat(k), with the IFFT normalisation folded in
+        const int ix = x0 + c;
+        const int sx = fft_signed(ix, nx);
+        const bool central = pd.symbol == 1;
+        const float kx = central ? sinpif(2.0f * (float)sx / (float)nx) / pd.dx : (float)sx * pd.dkx;
+        const float kxo = ((nx % 2) == 0 && ix == nx / 2) ? 0.f : kx;
+        const float kx2 = kx * kx;
+        const float axx = pd.gc11 * kx2, azz = pd.gc55 * kx2, axz = pd.gc1355 * kxo;
+        const float rdx = 1.0f / pd.dx;
+#pragma unroll
+        for (int m = 0; m < P; ++m) {
+            const int iz = tt + T * m;
+            const int sz = fft_signed(iz, N);
+            // central symbol sin(2 pi iz / N) / dx from the twiddle table
+            // (tw[iz] = exp(-2 pi i iz / N))
+            const float kz = central ? -tw[iz].y * rdx : (float)sz * pd.dkz;
+            const float kzo = ((N % 2) == 0 && iz == N / 2) ? 0.f : kz;
+            green_mul(v[0][m], v[1][m], axx + pd.gc55 * kz * kz, azz + pd.gc33 * kz * kz, axz * kzo,
+                      pd.ga, pd.gscale);
+            __builtin_amdgcn_sched_barrier(0);   // one point at a time: bounded registers
+        }
+        __syncthreads();
+    }
+    if constexpr (MODE != COL_FWD) {
+        // The inverse reads the same twiddle entries as the forward pass; an
+        // opaque copy of the table pointer keeps the compiler from holding the
+        // forward pass's twiddles in registers across the Green multiply.
+        // Likewise for the LDS addresses, which are the same in both passes.
+        const float2* twi = tw;
+        int ti = tt;
+        ColLds ldi = lds;
+        asm volatile("" : "+s"(twi));
+        asm volatile("" : "+v"(ti), "+v"(ldi.base), "+v"(ldi.stride));
+        if constexpr (SEQ) fft_run_seq<N, P, true, 2>(v, ti, twi, ldi);
+        else fft_run<N, P, true, 2>(v, ti, twi, ldi);
+    }
+
+    if (active) {
+#pragma unroll
+        for (int f = 0; f < 2; ++f)
+#pragma unroll
+            for (int m = 0; m < P; ++m) base[f * plane + (size_t)(t + T * m) * nx] = v[f][m];
+    }
+}
+
+
+// ----------------------------------------------------- launch helpers ----
+// Dynamic LDS above the default limit must be enabled once per kernel.
+template <class K>
+inline hipError_t allow_lds(K kernel, size_t bytes) {
+    if (bytes <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <int N, int P, bool INV, int EPI>
+inline hipError_t rows_launch(const float2* in, float2* out, const float2* u, const float2* aux,
+                              double* part, int nrows, int rps, const SysState* st, const float2* tw,
+                              hipStream_t s) {
+    const RowGeom g = row_geom(N, P, rps);
+    const int blocks = (nrows + g.F - 1) / g.F;
+    const size_t lds = (size_t)(g.F + 1) * PaddedLen<N>::value * sizeof(float2);
+    hipError_t e = allow_lds(k_rows<N, P, INV, EPI>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_rows<N, P, INV, EPI>), dim3(blocks), dim3(g.threads), lds, s, in, out, u, aux,
+                       part, nrows, rps, g.F, st, tw);
+    return hipGetLastError();
+}
+
+template <int N, int P, int MODE, bool SEQ>
+inline hipError_t cols_launch(float2* data, const ProbDev& pd, int W, const SysState* st,
+                              const float2* tw, hipStream_t s) {
+    const ColGeom g = col_geom(N, pd.nx, ColCfg{P, W, SEQ ? 1 : 0});
+    const int blocks = pd.nsys * (pd.nx / W);
+    hipError_t e = allow_lds(k_cols<N, P, MODE, SEQ>, g.lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_cols<N, P, MODE, SEQ>), dim3(blocks), dim3(g.threads), g.lds, s, data, pd, W,
+                       st, tw);
+    return hipGetLastError();
+}
+
+}  // namespace fw

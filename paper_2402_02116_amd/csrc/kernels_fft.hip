@@ -1,9 +1,6 @@
-// FFT-pass kernels of the LS matvec (eqs. A and FFT):
-//   k_rows  - forward row transforms (after the contrast stencil), and
-//             inverse row transforms fused with the LS / BiCGSTAB epilogues
-//             and their FP64 partial inner products;
-//   k_cols  - column transforms fused with the multiplication by the
-//             wavenumber-domain Green's tensor G_hat(k), in place.
+// Host side of the FFT passes: supported sizes, the twiddle table, launch
+// geometry and the kernel variants (points per thread, columns per block,
+// LDS sharing) that the autotuner chooses from.
 #include <algorithm>
 #include <numeric>
 
@@ -18,11 +15,14 @@ namespace fw {
 
 static const int kSizes[] = {16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048};
 
-// Points per thread.  Row passes: 16 for powers of two (radix-16 passes), 12
-// for 3 * 2^k.  Column passes hold both field components per thread, so they
-// use 8 (radix 8) to keep registers low and the thread count high.
-constexpr int points_per_thread(int n) { return (n % 3 == 0) ? 12 : 16; }
-constexpr int col_points_per_thread(int n) { return (n % 3 == 0) ? 12 : 8; }
+// Default points per thread.  Row passes: 16 for powers of two (radix-16
+// passes), 12 for 3 * 2^k.  Column passes hold both field components per
+// thread, so they default to 8 (radix 8) to keep registers low and the
+// thread count high.  Each size also has one alternative per pass kind.
+int row_points_default(int n) { return (n % 3 == 0) ? 12 : 16; }
+static int row_points_alt(int n) { return (n % 3 == 0) ? 24 : 8; }
+static int col_points_default(int n) { return (n % 3 == 0) ? 12 : 8; }
+static int col_points_alt(int n) { return (n % 3 == 0) ? 24 : 16; }
 
 bool fft_size_supported(int n) {
     for (int s : kSizes)
@@ -57,14 +57,19 @@ void twiddle_table_fill(float2* host) {
     }
 }
 
-static int pow2_floor(int x) {
-    int p = 1;
-    while (p * 2 <= x) p *= 2;
-    return p;
+bool row_points_ok(int n, int P) {
+    return fft_size_supported(n) && (P == row_points_default(n) || P == row_points_alt(n)) && n % P == 0;
 }
 
-RowGeom row_geom(int n, int rows_per_sys) {
-    const int T = n / points_per_thread(n);
+int row_candidates(int n, int* out) {
+    int k = 0;
+    out[k++] = row_points_default(n);
+    if (n % row_points_alt(n) == 0) out[k++] = row_points_alt(n);
+    return k;
+}
+
+RowGeom row_geom(int n, int P, int rows_per_sys) {
+    const int T = n / P;
     int F = std::gcd(256 / T, rows_per_sys);
     RowGeom g;
     g.F = F;
@@ -75,327 +80,46 @@ RowGeom row_geom(int n, int rows_per_sys) {
 
 static int padded_len(int n) { return n + n / 16 + 1; }
 
-// Column blocks: W columns x T threads per column, at most 512 threads; one
-// field component goes through LDS at a time.  W = 16 makes every 16-lane LDS
-// access group one contiguous 128-byte row segment (no bank conflicts) and
-// every global access a full 128-byte line.
-ColGeom col_geom(int nz, int nx) {
-    const int T = nz / col_points_per_thread(nz);
-    int W = std::max(1, std::min(16, 512 / T));
-    while (W > 1 && nx % W != 0) W /= 2;
+// Column blocks: W columns x T threads per column, at most 512 threads.  With
+// W = 16 every 16-lane LDS access group is one contiguous 128-byte row segment
+// (no bank conflicts) and every global access a full 128-byte line.
+ColGeom col_geom(int nz, int nx, const ColCfg& c) {
+    (void)nx;
+    const int T = nz / c.P;
     ColGeom g;
-    g.W = W;
-    g.threads = ((W * T + 63) / 64) * 64;
+    g.threads = ((c.W * T + 63) / 64) * 64;
+    g.slots = c.W + (g.threads > c.W * T ? 1 : 0);   // idle threads need a private dummy slot
+    g.lds = (size_t)padded_len(nz) * g.slots * (c.seq ? 1 : 2) * sizeof(float2);
     return g;
 }
 
-// ------------------------------------------------------- block reduce ----
-// Runtime block size (a multiple of 64, at most 256): fixed-order sum of
-// NV doubles; thread 0 receives the total.
-template <int NV>
-__device__ __forceinline__ void block_sum_to0(double (&acc)[NV], double* smem) {
-#pragma unroll
-    for (int k = 0; k < NV; ++k) {
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) acc[k] += __shfl_xor(acc[k], off, 64);
-    }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    if (lane == 0) {
-#pragma unroll
-        for (int k = 0; k < NV; ++k) smem[wave * NV + k] = acc[k];
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < NV; ++k) {
-            double s = 0.0;
-            for (int w = 0; w < nw; ++w) s += smem[w * NV + k];
-            acc[k] = s;
-        }
-    }
+bool col_cfg_ok(int nz, int nx, const ColCfg& c) {
+    if (!fft_size_supported(nz) || c.P <= 0 || nz % c.P != 0) return false;
+    if (c.P != col_points_default(nz) && c.P != col_points_alt(nz)) return false;
+    if (c.seq != 0 && c.seq != 1) return false;
+    if (c.W < 1 || c.W > 64 || nx % c.W != 0 || (c.W & (c.W - 1)) != 0) return false;
+    const ColGeom g = col_geom(nz, nx, c);
+    return g.threads <= 512 && g.lds <= kMaxLds;
 }
 
-// --------------------------------------------------------- row kernel ----
-struct RowLds {
-    float2* p;
-    __device__ __forceinline__ float2& operator()(int, int pos) const { return p[lds_pad(pos)]; }
-};
+ColCfg col_default(int nz, int nx) {
+    ColCfg c{col_points_default(nz), 1, 1};
+    const int T = nz / c.P;
+    int W = std::max(1, std::min(16, 512 / T));
+    while (W > 1 && nx % W != 0) W /= 2;
+    c.W = W;
+    return c;
+}
 
-template <int N, bool INV, int EPI>
-// `in` and `out` may be the same array (in-place forward pass): every block
-// reads all of its rows before its barriers and writes them after.
-__global__ __launch_bounds__(256) void k_rows(const float2* in, float2* out,
-                                              const float2* __restrict__ u,
-                                              const float2* __restrict__ aux,
-                                              double* __restrict__ partials, int nrows,
-                                              int rows_per_sys, int F,
-                                              const SysState* __restrict__ st,
-                                              const float2* __restrict__ tw) {
-    constexpr int P = points_per_thread(N);
-    using S = FftShape<N, P>;
-    constexpr int T = S::T;
-    constexpr int PL = PaddedLen<N>::value;
-    extern __shared__ float2 lds_dyn[];
-    __shared__ double red[4 * kPartialNV];
-
-    const int tid = threadIdx.x;
-    const int q = tid / T, t = tid % T;
-    const int row0 = blockIdx.x * F;
-    const int sys = row0 / rows_per_sys;
-    if (st != nullptr && st[sys].status != ST_RUNNING) return;
-    const int row = row0 + q;
-    const bool active = (q < F) && (row < nrows);
-
-    float2 v[1][P];
-    if (active) {
-        const float2* src = in + (size_t)row * N;
-#pragma unroll
-        for (int m = 0; m < P; ++m) v[0][m] = src[t + T * m];
-    } else {
-#pragma unroll
-        for (int m = 0; m < P; ++m) v[0][m] = make_float2(0.f, 0.f);
-    }
-    // idle threads (block padded to whole waves) work in a dummy slot F
-    RowLds lds{lds_dyn + (size_t)(q < F ? q : F) * PL};
-    fft_run<N, P, INV, 1>(v, t, tw, lds);
-
-    double acc[kPartialNV] = {0.0, 0.0, 0.0, 0.0};
-    if (active) {
-        const size_t base = (size_t)row * N;
-#pragma unroll
-        for (int m = 0; m < P; ++m) {
-            const size_t i = base + t + T * m;
-            const float2 y = v[0][m];
-            if constexpr (EPI == EPI_STORE) {
-                out[i] = y;
-            } else {
-                const float2 uu = u[i];
-                const float2 o = csub(uu, y);
-                if constexpr (EPI == EPI_APPLY) {
-                    out[i] = o;
-                } else if constexpr (EPI == EPI_BICG_V) {
-                    out[i] = o;
-                    const float2 a = aux[i];
-                    acc[0] += (double)a.x * o.x + (double)a.y * o.y;
-                    acc[1] += (double)a.x * o.y - (double)a.y * o.x;
-                } else if constexpr (EPI == EPI_BICG_T) {
-                    out[i] = o;
-                    acc[0] += (double)o.x * uu.x + (double)o.y * uu.y;
-                    acc[1] += (double)o.x * uu.y - (double)o.y * uu.x;
-                    acc[2] += (double)o.x * o.x + (double)o.y * o.y;
-                    acc[3] += (double)uu.x * uu.x + (double)uu.y * uu.y;
-                } else if constexpr (EPI == EPI_TRUERES) {
-                    const float2 b = aux[i];
-                    const float2 rr = csub(b, o);
-                    out[i] = rr;
-                    acc[0] += (double)rr.x * rr.x + (double)rr.y * rr.y;
-                }
+int col_candidates(int nz, int nx, ColCfg* out, int cap) {
+    int k = 0;
+    const int ps[2] = {col_points_default(nz), col_points_alt(nz)};
+    for (int P : ps)
+        for (int seq = 1; seq >= 0; --seq)
+            for (int W = 4; W <= 32; W *= 2) {
+                const ColCfg c{P, W, seq};
+                if (col_cfg_ok(nz, nx, c) && k < cap) out[k++] = c;
             }
-        }
-    }
-    if constexpr (EPI >= EPI_BICG_V) {
-        block_sum_to0<kPartialNV>(acc, red);
-        if (tid == 0) {
-            const int nb = rows_per_sys / F;
-            const int bi = (row0 % rows_per_sys) / F;
-            double* dst = partials + ((size_t)sys * nb + bi) * kPartialNV;
-#pragma unroll
-            for (int k = 0; k < kPartialNV; ++k) dst[k] = acc[k];
-        }
-    }
+    return k;
 }
-
-// ------------------------------------------------------ column kernel ----
-struct ColLds {
-    float2* base;   // this thread's column (or its private dummy slot)
-    int stride;     // W (columns interleaved) or 1 (dummy slot)
-    int PL;
-    __device__ __forceinline__ float2& operator()(int f, int pos) const {
-        return base[(f * PL + lds_pad(pos)) * stride];
-    }
-};
-
-// (bx, bz) <- G_hat (bx, bz) with G_hat = gscale (Gamma' - ga I)^-1 for the
-// real symmetric scaled Christoffel matrix Gamma' = [[gxx, gxz], [gxz, gzz]].
-__device__ __forceinline__ void green_mul(float2& bx, float2& bz, float gxx, float gzz, float gxz,
-                                          float2 ga, float gscale) {
-    const float2 mxx = make_float2(gxx - ga.x, -ga.y);
-    const float2 mzz = make_float2(gzz - ga.x, -ga.y);
-    float2 det = cmul(mxx, mzz);
-    det.x -= gxz * gxz;
-    const float s = gscale / (det.x * det.x + det.y * det.y);
-    const float2 inv = make_float2(det.x * s, -det.y * s);
-    const float2 gx = cmul(inv, bx), gz = cmul(inv, bz);   // inv b
-    const float2 ox = csub(cmul(mzz, gx), cscale(gz, gxz));
-    const float2 oz = csub(cmul(mxx, gz), cscale(gx, gxz));
-    bx = ox;
-    bz = oz;
-}
-
-// Signed FFT index of i on an n-point axis (numpy fftfreq order).
-__device__ __forceinline__ int fft_signed(int i, int n) { return (i < (n + 1) / 2) ? i : i - n; }
-
-template <int N, int MODE>
-__global__ __launch_bounds__(512) void k_cols(float2* __restrict__ data, ProbDev pd, int W,
-                                              const SysState* __restrict__ st,
-                                              const float2* __restrict__ tw) {
-    constexpr int P = col_points_per_thread(N);
-    using S = FftShape<N, P>;
-    constexpr int T = S::T;
-    constexpr int PL = PaddedLen<N>::value;
-    extern __shared__ float2 lds_dyn[];
-
-    const int nx = pd.nx;
-    const int tid = threadIdx.x;
-    const int c = tid % W, t = tid / W;
-    const int ntile = nx / W;
-    const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int sys = blk / ntile;
-    const int x0 = (blk % ntile) * W;
-    if (st != nullptr && st[sys].status != ST_RUNNING) return;
-    const bool active = t < T;
-
-    float2* base = data + (size_t)sys * 2 * N * nx + x0 + c;
-    const size_t plane = (size_t)N * nx;
-    float2 v[2][P];
-    if (active) {
-#pragma unroll
-        for (int f = 0; f < 2; ++f)
-#pragma unroll
-            for (int m = 0; m < P; ++m) v[f][m] = base[f * plane + (size_t)(t + T * m) * nx];
-    } else {
-#pragma unroll
-        for (int f = 0; f < 2; ++f)
-#pragma unroll
-            for (int m = 0; m < P; ++m) v[f][m] = make_float2(0.f, 0.f);
-    }
-    ColLds lds{active ? lds_dyn + c : lds_dyn + (size_t)PL * W, active ? W : 1, PL};
-    const int tt = active ? t : 0;
-
-    if constexpr (MODE != COL_INV) fft_run_seq<N, P, false, 2>(v, tt, tw, lds);
-    if constexpr (MODE == COL_GREEN) {
-        // u_hat = G_hat(k) b_hat(k), with the IFFT normalisation folded in
-        const int ix = x0 + c;
-        const int sx = fft_signed(ix, nx);
-        const bool central = pd.symbol == 1;
-        const float kx = central ? sinpif(2.0f * (float)sx / (float)nx) / pd.dx : (float)sx * pd.dkx;
-        const float kxo = ((nx % 2) == 0 && ix == nx / 2) ? 0.f : kx;
-        const float kx2 = kx * kx;
-        const float axx = pd.gc11 * kx2, azz = pd.gc55 * kx2, axz = pd.gc1355 * kxo;
-        const float dk = central ? 2.0f / (float)N : pd.dkz;
-#pragma unroll
-        for (int m = 0; m < P; ++m) {
-            const int iz = tt + T * m;
-            const int sz = fft_signed(iz, N);
-            float kz = (float)sz * dk;
-            if (central) kz = sinpif(kz) / pd.dx;
-            const float kzo = ((N % 2) == 0 && iz == N / 2) ? 0.f : kz;
-            green_mul(v[0][m], v[1][m], axx + pd.gc55 * kz * kz, azz + pd.gc33 * kz * kz, axz * kzo,
-                      pd.ga, pd.gscale);
-            __builtin_amdgcn_sched_barrier(0);   // one point at a time: bounded registers
-        }
-        __syncthreads();
-    }
-    if constexpr (MODE != COL_FWD) fft_run_seq<N, P, true, 2>(v, tt, tw, lds);
-
-    if (active) {
-#pragma unroll
-        for (int f = 0; f < 2; ++f)
-#pragma unroll
-            for (int m = 0; m < P; ++m) base[f * plane + (size_t)(t + T * m) * nx] = v[f][m];
-    }
-}
-
-// ----------------------------------------------------------- launchers ----
-template <int N>
-static hipError_t rows_fwd_n(const float2* in, float2* out, int nrows, int rps, const SysState* st,
-                             const float2* tw, hipStream_t s) {
-    const RowGeom g = row_geom(N, rps);
-    const int blocks = (nrows + g.F - 1) / g.F;
-    const size_t lds = (size_t)(g.F + 1) * PaddedLen<N>::value * sizeof(float2);
-    hipLaunchKernelGGL((k_rows<N, false, EPI_STORE>), dim3(blocks), dim3(g.threads), lds, s, in, out,
-                       nullptr, nullptr, nullptr, nrows, rps, g.F, st, tw);
-    return hipGetLastError();
-}
-
-template <int N>
-static hipError_t rows_inv_n(int epi, const float2* in, const float2* u, const float2* aux,
-                             float2* out, double* part, int nrows, int rps, const SysState* st,
-                             const float2* tw, hipStream_t s) {
-    const RowGeom g = row_geom(N, rps);
-    const int blocks = (nrows + g.F - 1) / g.F;
-    const size_t lds = (size_t)(g.F + 1) * PaddedLen<N>::value * sizeof(float2);
-    switch (epi) {
-#define FW_EPI(E)                                                                                \
-    case E:                                                                                      \
-        hipLaunchKernelGGL((k_rows<N, true, E>), dim3(blocks), dim3(g.threads), lds, s, in, out, \
-                           u, aux, part, nrows, rps, g.F, st, tw);                               \
-        break;
-        FW_EPI(EPI_STORE) FW_EPI(EPI_APPLY) FW_EPI(EPI_BICG_V) FW_EPI(EPI_BICG_T) FW_EPI(EPI_TRUERES)
-#undef FW_EPI
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-template <int N>
-static hipError_t cols_n(int mode, float2* data, const ProbDev& pd, const SysState* st,
-                         const float2* tw, hipStream_t s) {
-    const ColGeom g = col_geom(N, pd.nx);
-    const int blocks = pd.nsys * (pd.nx / g.W);
-    // idle threads (block padded to whole waves) need a private dummy slot
-    const int slots = g.W + (g.threads > g.W * FftShape<N, col_points_per_thread(N)>::T ? 1 : 0);
-    const size_t lds = (size_t)PaddedLen<N>::value * slots * sizeof(float2);
-    switch (mode) {
-        case COL_GREEN:
-            hipLaunchKernelGGL((k_cols<N, COL_GREEN>), dim3(blocks), dim3(g.threads), lds, s, data, pd,
-                               g.W, st, tw);
-            break;
-        case COL_FWD:
-            hipLaunchKernelGGL((k_cols<N, COL_FWD>), dim3(blocks), dim3(g.threads), lds, s, data, pd,
-                               g.W, st, tw);
-            break;
-        case COL_INV:
-            hipLaunchKernelGGL((k_cols<N, COL_INV>), dim3(blocks), dim3(g.threads), lds, s, data, pd,
-                               g.W, st, tw);
-            break;
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_rows_fwd(int n, const float2* in, float2* out, int nrows, int rps,
-                           const SysState* st, const float2* tw, hipStream_t s) {
-    switch (n) {
-#define FW_CASE(N) \
-    case N: return rows_fwd_n<N>(in, out, nrows, rps, st, tw + twiddle_offset(N), s);
-        FW_FOR_EACH_SIZE(FW_CASE)
-#undef FW_CASE
-        default: return hipErrorInvalidValue;
-    }
-}
-
-hipError_t launch_rows_inv(int n, int epi, const float2* in, const float2* u, const float2* aux,
-                           float2* out, double* part, int nrows, int rps, const SysState* st,
-                           const float2* tw, hipStream_t s) {
-    switch (n) {
-#define FW_CASE(N) \
-    case N: return rows_inv_n<N>(epi, in, u, aux, out, part, nrows, rps, st, tw + twiddle_offset(N), s);
-        FW_FOR_EACH_SIZE(FW_CASE)
-#undef FW_CASE
-        default: return hipErrorInvalidValue;
-    }
-}
-
-hipError_t launch_cols(int mode, float2* data, const ProbDev& pd, const SysState* st,
-                       const float2* tw, hipStream_t s) {
-    switch (pd.nz) {
-#define FW_CASE(N) \
-    case N: return cols_n<N>(mode, data, pd, st, tw + twiddle_offset(N), s);
-        FW_FOR_EACH_SIZE(FW_CASE)
-#undef FW_CASE
-        default: return hipErrorInvalidValue;
-    }
-}
-
 }  // namespace fw

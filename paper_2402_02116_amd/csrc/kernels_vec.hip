@@ -5,6 +5,8 @@
 //   k_bicg_*       - batched BiCGSTAB vector updates with FP64 scalars;
 //   k_point_sources, k_gather, k_scatter_conj - sources and receivers;
 //   k_correlate    - adjoint correlation of eq. ad1 summed over systems.
+#include <algorithm>
+
 #include "launch.h"
 
 namespace fw {
@@ -217,38 +219,85 @@ static int tile_x(int nx) {
     return 0;
 }
 
+StCfg st_default() { return StCfg{STZ, 0}; }
+
+bool st_cfg_ok(int nx, int nz, const StCfg& c) {
+    if (tile_x(nx) == 0) return false;
+    if (c.TZ != 4 && c.TZ != 8 && c.TZ != 16) return false;
+    if (nz % c.TZ != 0) return false;
+    return c.S == 0 || c.S == 1 || c.S == 2 || c.S == 4 || c.S == 8 || c.S == 16;
+}
+
+int st_candidates(int nx, int nz, StCfg* out, int cap) {
+    int k = 0;
+    const int tzs[3] = {8, 4, 16};
+    const int ss[5] = {0, 1, 2, 4, 8};
+    for (int tz : tzs)
+        for (int sv : ss) {
+            const StCfg c{tz, sv};
+            if (st_cfg_ok(nx, nz, c) && k < cap) out[k++] = c;
+        }
+    return k;
+}
+
 template <int TX, int TZ, int VM>
-static void body_force_launch(const StencilArgs& a, const ProbDev& pd, SysState* st, hipStream_t s) {
+static void body_force_launch(const StCfg& c, const StencilArgs& a, const ProbDev& pd, SysState* st,
+                              hipStream_t s) {
     const int ntiles = (pd.nx / TX) * (pd.nz / TZ);
-    // several systems per block once there are plenty of blocks
-    int S = 1;
-    while (S < pd.nsys && (long long)ntiles * ((pd.nsys + 2 * S - 1) / (2 * S)) >= 2048) S *= 2;
+    int S = c.S;
+    if (S == 0) {
+        // several systems per block once there are plenty of blocks
+        S = 1;
+        while (S < pd.nsys && (long long)ntiles * ((pd.nsys + 2 * S - 1) / (2 * S)) >= 2048) S *= 2;
+    }
+    S = std::min(S, std::max(pd.nsys, 1));
     const int blocks = ntiles * ((pd.nsys + S - 1) / S);
     hipLaunchKernelGGL((k_body_force<TX, TZ, VM>), dim3(blocks), dim3(256), 0, s, a.u, a.a1, a.a2, a.wout,
                        a.b, a.maps, pd, S, st, a.part, a.np);
 }
 
-hipError_t launch_stencil(int vm, const StencilArgs& a, const ProbDev& pd, SysState* st, hipStream_t s) {
-    const int TX = tile_x(pd.nx);
-    if (TX == 0 || pd.nz % STZ != 0 || vm < 0 || vm > 2 || (vm != 0 && !st)) return hipErrorInvalidValue;
-#define FW_BF(X)                                                                          \
-    case X:                                                                               \
-        if (vm == VM_NONE) body_force_launch<X, STZ, VM_NONE>(a, pd, st, s);              \
-        else if (vm == VM_P) body_force_launch<X, STZ, VM_P>(a, pd, st, s);               \
-        else body_force_launch<X, STZ, VM_S>(a, pd, st, s);                               \
-        break;
-    switch (TX) {
-        FW_BF(64) FW_BF(48) FW_BF(32) FW_BF(24) FW_BF(16)
+template <int TX, int TZ>
+static void body_force_vm(int vm, const StCfg& c, const StencilArgs& a, const ProbDev& pd, SysState* st,
+                          hipStream_t s) {
+    if (vm == VM_NONE) body_force_launch<TX, TZ, VM_NONE>(c, a, pd, st, s);
+    else if (vm == VM_P) body_force_launch<TX, TZ, VM_P>(c, a, pd, st, s);
+    else body_force_launch<TX, TZ, VM_S>(c, a, pd, st, s);
+}
+
+template <int TX>
+static void body_force_tz(int vm, const StCfg& c, const StencilArgs& a, const ProbDev& pd, SysState* st,
+                          hipStream_t s) {
+    if (c.TZ == 4) body_force_vm<TX, 4>(vm, c, a, pd, st, s);
+    else if (c.TZ == 16) body_force_vm<TX, 16>(vm, c, a, pd, st, s);
+    else body_force_vm<TX, 8>(vm, c, a, pd, st, s);
+}
+
+hipError_t launch_stencil(int vm, const StCfg& c, const StencilArgs& a, const ProbDev& pd, SysState* st,
+                          hipStream_t s) {
+    if (!st_cfg_ok(pd.nx, pd.nz, c) || vm < 0 || vm > 2 || (vm != 0 && !st)) return hipErrorInvalidValue;
+    switch (tile_x(pd.nx)) {
+        case 64: body_force_tz<64>(vm, c, a, pd, st, s); break;
+        case 48: body_force_tz<48>(vm, c, a, pd, st, s); break;
+        case 32: body_force_tz<32>(vm, c, a, pd, st, s); break;
+        case 24: body_force_tz<24>(vm, c, a, pd, st, s); break;
+        case 16: body_force_tz<16>(vm, c, a, pd, st, s); break;
         default: return hipErrorInvalidValue;
     }
-#undef FW_BF
     return hipGetLastError();
 }
 
-hipError_t launch_body_force(const float2* u, float2* b, const float* maps, const ProbDev& pd,
-                             const SysState* st, hipStream_t s) {
+hipError_t launch_body_force(const StCfg& c, const float2* u, float2* b, const float* maps,
+                             const ProbDev& pd, const SysState* st, hipStream_t s) {
     StencilArgs a{u, nullptr, nullptr, nullptr, b, maps, nullptr, 0};
-    return launch_stencil(VM_NONE, a, pd, const_cast<SysState*>(st), s);
+    return launch_stencil(VM_NONE, c, a, pd, const_cast<SysState*>(st), s);
+}
+
+KernelCfg kernel_cfg_default(int nx, int nz) {
+    KernelCfg k;
+    k.row_p = row_points_default(nx);
+    k.col = col_default(nz, nx);
+    k.st = st_default();
+    return k;
 }
 
 // -------------------------------------------------------------- vectors --

@@ -23,11 +23,41 @@ enum ColMode : int { COL_GREEN = 0, COL_FWD = 1, COL_INV = 2 };
 // FFT sizes with kernels in this build: 2^a 3^b, 16 <= n <= 2048.
 bool fft_size_supported(int n);
 
-// Launch geometry chosen for a size (also used to size partial buffers).
+constexpr size_t kMaxLds = 160 * 1024;   // LDS per workgroup on gfx950
+
+// Kernel variants of one problem (chosen by the autotuner or the caller).
+struct ColCfg {
+    int P;     // points per thread
+    int W;     // columns per block
+    int seq;   // 1: the two components share one LDS buffer
+};
+struct StCfg {
+    int TZ;    // tile height (rows)
+    int S;     // systems per block, 0 = chosen from the grid size
+};
+struct KernelCfg {
+    int row_p;   // row-transform points per thread
+    ColCfg col;
+    StCfg st;
+};
+
+// Launch geometry of a variant (also used to size partial buffers).
 struct RowGeom { int F; int threads; int blocks_per_sys; };
-RowGeom row_geom(int n, int nrows_per_sys);
-struct ColGeom { int W; int threads; };
-ColGeom col_geom(int nz, int nx);
+RowGeom row_geom(int n, int P, int nrows_per_sys);
+struct ColGeom { int threads; int slots; size_t lds; };
+ColGeom col_geom(int nz, int nx, const ColCfg& c);
+
+// Variants: defaults, validity, and the candidate lists of the autotuner.
+int row_points_default(int n);
+bool row_points_ok(int n, int P);
+int row_candidates(int n, int* out);          // at most 2
+ColCfg col_default(int nz, int nx);
+bool col_cfg_ok(int nz, int nx, const ColCfg& c);
+int col_candidates(int nz, int nx, ColCfg* out, int cap);
+StCfg st_default();
+bool st_cfg_ok(int nx, int nz, const StCfg& c);
+int st_candidates(int nx, int nz, StCfg* out, int cap);
+KernelCfg kernel_cfg_default(int nx, int nz);
 
 // Twiddle table tw[m] = exp(-2 pi i m / n), m < n, for every supported n,
 // packed back to back; offset of size n in complex elements.
@@ -38,18 +68,20 @@ void twiddle_table_fill(float2* host);
 // Row transforms over nrows rows of length n (rows_per_sys rows per system;
 // a block never straddles systems).  st (may be null): systems whose status is
 // not RUNNING are skipped.
-hipError_t launch_rows_fwd(int n, const float2* in, float2* out, int nrows, int rows_per_sys,
+// P is the points-per-thread variant (row_points_ok).
+hipError_t launch_rows_fwd(int n, int P, const float2* in, float2* out, int nrows, int rows_per_sys,
                            const SysState* st, const float2* tw, hipStream_t s);
-hipError_t launch_rows_inv(int n, int epi, const float2* in, const float2* u, const float2* aux,
+hipError_t launch_rows_inv(int n, int P, int epi, const float2* in, const float2* u, const float2* aux,
                            float2* out, double* partials, int nrows, int rows_per_sys,
                            const SysState* st, const float2* tw, hipStream_t s);
-// Column pass over [nsys][2][nz][nx] in place.
-hipError_t launch_cols(int mode, float2* data, const ProbDev& pd, const SysState* st,
+// Column pass over [nsys][2][nz][nx] in place.  COL_FWD / COL_INV exist in
+// the default points-per-thread variant with shared LDS only.
+hipError_t launch_cols(int mode, const ColCfg& c, float2* data, const ProbDev& pd, const SysState* st,
                        const float2* tw, hipStream_t s);
 
 // Body force b = w~^2 drho u + div_h(dC : E_h u) of one problem.
-hipError_t launch_body_force(const float2* u, float2* b, const float* maps, const ProbDev& pd,
-                             const SysState* st, hipStream_t s);
+hipError_t launch_body_force(const StCfg& c, const float2* u, float2* b, const float* maps,
+                             const ProbDev& pd, const SysState* st, hipStream_t s);
 // The stencil with a BiCGSTAB vector update fused into its input (vm: 0 none,
 // 1 p = r + beta (p_old - omega v) [u = r, a1 = p_old, a2 = v, wout = p_new,
 // part = <rhat, r> records], 2 s = r - alpha v [u = r, a1 = v, wout = s,
@@ -64,7 +96,8 @@ struct StencilArgs {
     const double* part;
     int np;
 };
-hipError_t launch_stencil(int vm, const StencilArgs& a, const ProbDev& pd, SysState* st, hipStream_t s);
+hipError_t launch_stencil(int vm, const StCfg& c, const StencilArgs& a, const ProbDev& pd, SysState* st,
+                          hipStream_t s);
 
 // BiCGSTAB pieces (one problem; n = 2 nz nx complex per system).
 int vec_blocks_per_sys(int n);

@@ -368,6 +368,48 @@ class Plan:
             check(st, "fwils_normal_cg")
         return q, hist
 
+    # ----------------------------------------------------- autotuner ----
+    TUNE_KINDS = {"stencil": _lib.FWILS_TUNE_STENCIL, "rows": _lib.FWILS_TUNE_ROWS, "cols": _lib.FWILS_TUNE_COLS}
+
+    def autotune(self, reps=20):
+        """Time every kernel variant on this plan's workspace and keep the fastest
+        per problem (overwrites the plan's field vectors).  Returns tuning()."""
+        self._bind_stream()
+        check(self.lib.fwils_autotune(self._h, int(reps)), "fwils_autotune")
+        return [self.tuning(i) for i in range(len(self.problems))]
+
+    def tuning(self, i):
+        """Kernel variants of problem i (dict of the fwils_tuning fields)."""
+        t = _lib.FwilsTuning()
+        check(self.lib.fwils_get_tuning(self._h, int(i), ctypes.byref(t)), "fwils_get_tuning")
+        return t.to_dict()
+
+    def set_tuning(self, i, **fields):
+        """Replace some variant fields of problem i (the others stay)."""
+        cur = self.tuning(i)
+        t = _lib.FwilsTuning()
+        for k in _lib.FwilsTuning.FIELDS:
+            setattr(t, k, int(fields.pop(k, cur[k])))
+        if fields:
+            raise ValueError(f"unknown tuning fields {sorted(fields)}")
+        check(self.lib.fwils_set_tuning(self._h, int(i), ctypes.byref(t)), "fwils_set_tuning")
+
+    def tuning_candidates(self, i, kind):
+        """Candidate variants of one kernel kind ('stencil', 'rows', 'cols') for problem i."""
+        k = self.TUNE_KINDS[kind]
+        n = ctypes.c_int32(0)
+        check(self.lib.fwils_tuning_candidates(self._h, int(i), k, None, 0, ctypes.byref(n)),
+              "fwils_tuning_candidates")
+        arr = (_lib.FwilsTuning * max(n.value, 1))()
+        check(self.lib.fwils_tuning_candidates(self._h, int(i), k, arr, n.value, ctypes.byref(n)),
+              "fwils_tuning_candidates")
+        out = []
+        for j in range(n.value):
+            d = arr[j].to_dict()
+            d.pop("time_us")
+            out.append(d)
+        return out
+
     def fft2(self, i, x, inverse=False, out=None):
         """2-D FFT (unnormalised) of every field of problem i; x: [nsys, 2, nz, nx]."""
         _require_cuda(x, torch.complex64, "x")

@@ -3,6 +3,7 @@ entry point, validates arguments before touching the device, and the Python
 binding refuses to run without a GPU.  No compute calls."""
 
 import ctypes
+import re
 import os
 
 import pytest
@@ -42,7 +43,47 @@ def test_library_exports_every_declared_symbol(lib):
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(_lib.SIGNATURES)
-    assert lib.fwils_abi_version() == 1
+    ver = re.search(r"#define FWILS_ABI_VERSION (\d+)", open(_lib.HEADER).read())
+    assert lib.fwils_abi_version() == int(ver.group(1))
+
+
+def test_tuning_defaults_candidates_and_validation(lib):
+    """Host-side autotuner bookkeeping (no device work): defaults, candidate
+    lists, and rejection of variants that are not built for the grid."""
+    st, h = _create(lib, [_prob(nx=384, nz=384, nsys=4), _prob(nx=256, nz=24, nsys=2)])
+    assert st == 0
+    try:
+        t = _lib.FwilsTuning()
+        assert lib.fwils_get_tuning(h, 0, ctypes.byref(t)) == 0
+        assert (t.row_points, t.col_points, t.col_width, t.col_shared, t.stencil_rows) == (12, 12, 16, 1, 8)
+        assert list(t.time_us) == [0.0, 0.0, 0.0]
+        for kind, field in ((0, "stencil_rows"), (1, "row_points"), (2, "col_points")):
+            n = ctypes.c_int32()
+            assert lib.fwils_tuning_candidates(h, 0, kind, None, 0, ctypes.byref(n)) == 0
+            arr = (_lib.FwilsTuning * n.value)()
+            assert lib.fwils_tuning_candidates(h, 0, kind, arr, n.value, ctypes.byref(n)) == 0
+            assert n.value >= 2
+            for c in arr:
+                assert lib.fwils_set_tuning(h, 0, ctypes.byref(c)) == 0
+        # 24 rows: no 16-row stencil tiles; widths must divide nx; bad radix
+        bad = _lib.FwilsTuning()
+        assert lib.fwils_get_tuning(h, 1, ctypes.byref(bad)) == 0
+        good = _lib.FwilsTuning.from_buffer_copy(bad)
+        bad.stencil_rows = 16
+        assert lib.fwils_set_tuning(h, 1, ctypes.byref(bad)) == _lib.FWILS_EINVAL
+        bad = _lib.FwilsTuning.from_buffer_copy(good)
+        bad.col_width = 3
+        assert lib.fwils_set_tuning(h, 1, ctypes.byref(bad)) == _lib.FWILS_EINVAL
+        bad = _lib.FwilsTuning.from_buffer_copy(good)
+        bad.row_points = 7
+        assert lib.fwils_set_tuning(h, 1, ctypes.byref(bad)) == _lib.FWILS_EINVAL
+        after = _lib.FwilsTuning()
+        assert lib.fwils_get_tuning(h, 1, ctypes.byref(after)) == 0
+        assert bytes(after) == bytes(good)
+        # autotune needs the workspace
+        assert lib.fwils_autotune(h, 5) == _lib.FWILS_ENOMEM
+    finally:
+        lib.fwils_plan_destroy(h)
 
 
 def test_status_strings(lib):
