@@ -94,6 +94,8 @@ def multigrid(a):
                       freq_hz=p["freq_hz"], eta=p["eta"], nsys=p["nsys"]) for p in probs], device="cuda:0")
     for i, p in enumerate(probs):
         plan.set_contrast(i, p["maps"])
+    if a.krylov == "gmres":
+        plan.set_krylov("gmres", restart=a.restart, cgs2=not a.cgs1)
     src = sum((p["src_ixz"] for p in probs), [])
     frc = sum((p["src_f"] for p in probs), [])
     cells = np.array(sum(([p["nx"] * p["nz"]] * p["nsys"] for p in probs), []))
@@ -101,7 +103,8 @@ def multigrid(a):
     def step():
         u0 = plan.incident(src, frc)
         res = plan.solve(u0, rtol=RTOL, maxit=1000)
-        return int(np.sum((2 * res.iters + 1) * cells)), res
+        per = 1 if a.krylov == "gmres" else 2   # matvecs per iteration
+        return int(np.sum((per * res.iters + 1) * cells)), res
 
     def solve_ms():
         u0 = plan.incident(src, frc)
@@ -150,7 +153,8 @@ def multigrid(a):
                            grids=[p["nx"] for p in probs], nsys=int(len(src)), rtol=RTOL,
                            cells_per_matvec=int(cells.sum())),
                time_to_1e6_ms=round(t_solve, 3), iters=[int(res.iters.min()), int(res.iters.max())],
-               max_true_relres=float(res.relres.max()), autotune=tuning)
+               max_true_relres=float(res.relres.max()), autotune=tuning,
+               krylov=a.krylov if a.krylov == "bicgstab" else f"gmres({a.restart}, {'cgs1' if a.cgs1 else 'cgs2'})")
     print(json.dumps(out), flush=True)
     return 0
 
@@ -186,6 +190,12 @@ def main(argv=None):
     ap.add_argument("--cpu-sample", type=int, default=4, help="systems in the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the built-in kernel variants")
+    ap.add_argument("--krylov", choices=["auto", "bicgstab", "gmres"], default="auto",
+                    help="auto: BiCGSTAB for the 256^2 workload (few iterations), GMRES(32) with one "
+                         "Gram-Schmidt pass for the four-grid workload (hard 12 Hz systems)")
+    ap.add_argument("--restart", type=int, default=32, help="GMRES restart length (<= 32)")
+    ap.add_argument("--cgs1", action="store_true", help="GMRES without the re-orthogonalisation pass")
+    ap.add_argument("--cgs2", action="store_true", help="GMRES with the re-orthogonalisation pass")
     ap.add_argument("--workload", choices=["vti256x16", "multigrid"], default="vti256x16")
     a = ap.parse_args(argv)
     if a.gpus != 1:
@@ -198,6 +208,11 @@ def main(argv=None):
     from paper_2402_02116_amd.plan import Plan
 
     torch.cuda.set_device(0)
+    if a.krylov == "auto":
+        a.krylov = "gmres" if a.workload == "multigrid" else "bicgstab"
+        a.cgs1 = a.cgs1 or not a.cgs2
+    elif a.cgs2:
+        a.cgs1 = False
     if a.workload == "multigrid":
         return multigrid(a)
     c, rec, dm_np, r_np = build_workload()
@@ -207,6 +222,9 @@ def main(argv=None):
                       eta=c["eta"], nsys=ns)], device="cuda:0")
     plan.set_contrast(0, c["maps"])
     plan.set_receivers(0, rec)
+    if a.krylov == "gmres":
+        plan.set_krylov("gmres", restart=a.restart, cgs2=not a.cgs1)
+    mv_per_iter = 1 if a.krylov == "gmres" else 2
     tuning = None
     if not a.no_autotune:
         t0 = time.perf_counter()
@@ -219,11 +237,11 @@ def main(argv=None):
     def step():
         u0 = plan.incident(c["src_ixz"], c["src_f"])
         res = plan.solve(u0, rtol=RTOL, maxit=1000)
-        n1 = int(np.sum(2 * res.iters + 1))
+        n1 = int(np.sum(mv_per_iter * res.iters + 1))
         plan.frechet(res.x, [dm], rtol=RTOL)
-        n2 = int(np.sum(2 * plan.solve_stats()[0] + 1))
+        n2 = int(np.sum(mv_per_iter * plan.solve_stats()[0] + 1))
         plan.adjoint(res.x, r, rtol=RTOL)
-        n3 = int(np.sum(2 * plan.solve_stats()[0] + 1))
+        n3 = int(np.sum(mv_per_iter * plan.solve_stats()[0] + 1))
         return n1 + n2 + n3
 
     for _ in range(a.warmup):
@@ -248,11 +266,16 @@ def main(argv=None):
         res = plan.solve(u0, rtol=RTOL, maxit=1000, **kw)
         torch.cuda.synchronize()
         return (time.perf_counter() - t) * 1e3, res
+    plain_krylov = a.krylov
     for _ in range(2):
         timed_solve()
-        timed_solve(plain=True)
     tb = sorted(timed_solve()[0] for _ in range(5))
     tbr = timed_solve()[1]
+    if a.krylov == "gmres":   # the per-source plain loop is BiCGSTAB's
+        plan.set_krylov("bicgstab")
+        plain_krylov = "bicgstab"
+    for _ in range(2):
+        timed_solve(plain=True)
     tp = sorted(timed_solve(plain=True)[0] for _ in range(3))
     tpr = timed_solve(plain=True)[1]
     same = bool(torch.equal(tbr.x, tpr.x))
@@ -325,7 +348,9 @@ def main(argv=None):
                                     "5 Hz, 128 receivers: incident + solve + J + J* to 1e-6",
                            grid=[nz, nx], nsys=ns, freq_hz=c["freq_hz"], rtol=RTOL, nrec=NREC),
                roofline=roof,
+               krylov=a.krylov if a.krylov == "bicgstab" else f"gmres({a.restart}, {'cgs1' if a.cgs1 else 'cgs2'})",
                time_to_1e6_ms=dict(batched=round(tb[len(tb) // 2], 3), plain=round(tp[len(tp) // 2], 3),
+                                   plain_krylov=plain_krylov,
                                    speedup=round(tp[len(tp) // 2] / tb[len(tb) // 2], 2),
                                    iters=[int(tbr.iters.min()), int(tbr.iters.max())],
                                    max_true_relres=float(tbr.relres.max()), identical=same),

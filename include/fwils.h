@@ -62,7 +62,7 @@
 extern "C" {
 #endif
 
-#define FWILS_ABI_VERSION 2
+#define FWILS_ABI_VERSION 3
 
 typedef enum {
     FWILS_OK = 0,
@@ -252,6 +252,33 @@ fwils_status fwils_laplacian(fwils_plan plan, const float* q, float* out);
  * no 1/(nx nz)).  A self-test entry point.  in, out: device, may alias. */
 fwils_status fwils_fft2(fwils_plan plan, int32_t iprob, const void* in, void* out,
                         int32_t inverse);
+
+/* ------------------------------------------------------- Krylov method ----
+ * Every solve of the plan (fwils_solve, and the solves inside J, J*, the
+ * Tikhonov gradient and the normal-equation CG) uses the plan's Krylov
+ * method: BiCGSTAB (default; needs no extra memory) or restarted GMRES(m),
+ * the method of the paper's numerical examples (section on numerical
+ * examples), with Arnoldi by classical Gram-Schmidt with one
+ * re-orthogonalisation pass (or one pass with FWILS_GMRES_CGS1) and the
+ * Hessenberg least-squares problem solved by Givens rotations in FP64.
+ * GMRES stops a cycle when its residual estimate reaches rtol and accepts
+ * a system only when the true residual ||b - A x|| / ||b|| of the next cycle
+ * start is <= rtol; fwils_solve's iters count Arnoldi steps (one matvec
+ * each; a BiCGSTAB iteration is two).  FWILS_SOLVE_PLAIN is BiCGSTAB only. */
+#define FWILS_KRYLOV_BICGSTAB 0
+#define FWILS_KRYLOV_GMRES 1
+#define FWILS_GMRES_CGS1 0x1u
+
+/* Bytes of device memory GMRES(restart), restart 1..32, needs for this plan:
+ * (restart + 1) field-sized basis vectors plus per-system FP64 state. */
+fwils_status fwils_gmres_workspace_size(fwils_plan plan, int32_t restart, size_t* bytes);
+/* Select the Krylov method.  For FWILS_KRYLOV_GMRES, gws is caller-owned
+ * device memory of at least fwils_gmres_workspace_size bytes, 256-byte
+ * aligned, kept until the method changes or the plan is destroyed; the plan
+ * workspace must already be set.  restart, flags and gws are ignored for
+ * BiCGSTAB.  Synchronous. */
+fwils_status fwils_set_krylov(fwils_plan plan, int32_t method, int32_t restart, uint32_t flags, void* gws,
+                              size_t bytes);
 
 /* ---------------------------------------------------------- autotuner ----
  * The batched schedule over uneven grids picks, per problem, one variant of

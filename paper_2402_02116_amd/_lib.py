@@ -43,6 +43,8 @@ class FwilsTuning(ctypes.Structure):
 
 
 FWILS_TUNE_STENCIL, FWILS_TUNE_ROWS, FWILS_TUNE_COLS = 0, 1, 2
+FWILS_KRYLOV_BICGSTAB, FWILS_KRYLOV_GMRES = 0, 1
+FWILS_GMRES_CGS1 = 0x1
 
 P = c_void_p
 SIGNATURES = {
@@ -74,6 +76,8 @@ SIGNATURES = {
     "fwils_laplacian": (c_int32, [P, P, P]),
     "fwils_solve_stats": (c_int32, [P, ctypes.POINTER(c_int32), ctypes.POINTER(c_double)]),
     "fwils_autotune": (c_int32, [P, c_int32]),
+    "fwils_gmres_workspace_size": (c_int32, [P, c_int32, ctypes.POINTER(c_size_t)]),
+    "fwils_set_krylov": (c_int32, [P, c_int32, c_int32, c_uint32, P, c_size_t]),
     "fwils_get_tuning": (c_int32, [P, c_int32, ctypes.POINTER(FwilsTuning)]),
     "fwils_set_tuning": (c_int32, [P, c_int32, ctypes.POINTER(FwilsTuning)]),
     "fwils_tuning_candidates": (c_int32, [P, c_int32, c_int32, ctypes.POINTER(FwilsTuning), c_int32,

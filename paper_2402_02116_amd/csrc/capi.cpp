@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -97,6 +98,16 @@ struct fwils_plan_s {
     double *mq_part = nullptr, *mq_sc = nullptr, *mq_hist = nullptr;
     // graph of one chunk of iterations over all problems
     hipGraphExec_t chunk = nullptr;
+    // Krylov method; GMRES state lives in a caller-provided workspace
+    int krylov = FWILS_KRYLOV_BICGSTAB;
+    int gm_m = 0;
+    bool gm_cgs2 = true;
+    size_t gm_maxnb = 0;
+    float2* gm_V = nullptr;
+    GmSys* gm_sys = nullptr;
+    double *gm_part = nullptr, *gm_tot1 = nullptr, *gm_tot2 = nullptr, *gm_tot3 = nullptr;
+    hipGraphExec_t gm_cycle = nullptr;
+    double gm_rtol = 0.0;           // tolerance the cycle graph was built for
     SysState* host_state = nullptr;   // pinned
 };
 
@@ -164,14 +175,14 @@ hipError_t conv_problem(fwils_plan pl, const ProbHost& P, const float2* f, float
 // views (used both batched and per system).
 hipError_t matvec(fwils_plan pl, const ProbHost& P, const ProbDev& d, const float2* u, float2* tmp,
                   const float* maps, int epi, const float2* aux, float2* out, double* part,
-                  const SysState* st, hipStream_t s) {
+                  const SysState* st, hipStream_t s, const GmEpi* ge = nullptr) {
     const int rows = d.nsys * 2 * d.nz;
     const KernelCfg& k = P.cfg;
     hipError_t e = launch_body_force(k.st, u, tmp, maps, d, st, s);
     if (e == hipSuccess) e = launch_rows_fwd(d.nx, k.row_p, tmp, tmp, rows, 2 * d.nz, st, pl->tw, s);
     if (e == hipSuccess) e = launch_cols(COL_GREEN, k.col, tmp, d, st, pl->tw, s);
     if (e == hipSuccess)
-        e = launch_rows_inv(d.nx, k.row_p, epi, tmp, u, aux, out, part, rows, 2 * d.nz, st, pl->tw, s);
+        e = launch_rows_inv(d.nx, k.row_p, epi, tmp, u, aux, out, part, rows, 2 * d.nz, st, pl->tw, s, ge);
     return e;
 }
 
@@ -232,8 +243,10 @@ hipError_t bicg_iteration(fwils_plan pl, const ProbHost& P, const SysView& V, in
     return e;
 }
 
-fwils_status build_chunk_graph(fwils_plan pl) {
-    if (pl->chunk) return FWILS_OK;
+// Capture one launch sequence per problem, each on its own forked stream, into
+// one graph (problems run concurrently; the graph ends when all have).
+fwils_status capture_graph(fwils_plan pl, hipGraphExec_t* out,
+                           const std::function<hipError_t(const ProbHost&, hipStream_t)>& body) {
     const int np = (int)pl->probs.size();
     std::vector<hipStream_t> ss(np, nullptr);
     std::vector<hipEvent_t> ev(np + 1, nullptr);
@@ -244,32 +257,40 @@ fwils_status build_chunk_graph(fwils_plan pl) {
     hipError_t e = hipEventRecord(ev[np], ss[0]);
     for (int i = 1; i < np && e == hipSuccess; ++i) e = hipStreamWaitEvent(ss[i], ev[np], 0);
     for (int i = 0; i < np && e == hipSuccess; ++i) {
-        const ProbHost& P = pl->probs[i];
-        const SysView V = make_view(pl, P, 0, P.p.nsys);
-        for (int it = 0; it < kChunkIters && e == hipSuccess; ++it) e = bicg_iteration(pl, P, V, it & 1, ss[i]);
-        if (e == hipSuccess)
-            e = launch_bicg_check(st_at(pl, P), part_at(pl->partXR, pl, P), P.np_vec, P.p.nsys, ss[i]);
+        e = body(pl->probs[i], ss[i]);
         if (i > 0 && e == hipSuccess) e = hipEventRecord(ev[i], ss[i]);
     }
     for (int i = 1; i < np && e == hipSuccess; ++i) e = hipStreamWaitEvent(ss[0], ev[i], 0);
     hipError_t e2 = hipStreamEndCapture(ss[0], &g);
     if (e == hipSuccess) e = e2;
-    if (e == hipSuccess) e = hipGraphInstantiate(&pl->chunk, g, nullptr, nullptr, 0);
+    if (e == hipSuccess) e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
     if (g) (void)hipGraphDestroy(g);
     for (auto& q : ss) (void)hipStreamDestroy(q);
     for (auto& q : ev) (void)hipEventDestroy(q);
     if (e != hipSuccess) {
-        pl->chunk = nullptr;
+        *out = nullptr;
         set_error("graph capture failed: %s", hipGetErrorString(e));
         return FWILS_EDEVICE;
     }
     return FWILS_OK;
 }
 
+fwils_status build_chunk_graph(fwils_plan pl) {
+    if (pl->chunk) return FWILS_OK;
+    return capture_graph(pl, &pl->chunk, [pl](const ProbHost& P, hipStream_t s) -> hipError_t {
+        const SysView V = make_view(pl, P, 0, P.p.nsys);
+        hipError_t e = hipSuccess;
+        for (int it = 0; it < kChunkIters && e == hipSuccess; ++it) e = bicg_iteration(pl, P, V, it & 1, s);
+        if (e == hipSuccess) e = launch_bicg_check(st_at(pl, P), part_at(pl->partXR, pl, P), P.np_vec, P.p.nsys, s);
+        return e;
+    });
+}
+
+
 // Solve A x = b where b and the result live in plan-level fields.  x_ws is
 // the workspace solution vector (pl->x).  flags as fwils_solve.
-fwils_status solve_ws(fwils_plan pl, const float2* b, bool use_x0, double rtol, int maxit,
-                      int32_t* iters, double* relres, uint32_t flags) {
+fwils_status bicg_solve_ws(fwils_plan pl, const float2* b, bool use_x0, double rtol, int maxit,
+                           int32_t* iters, double* relres, uint32_t flags) {
     hipStream_t s = pl->stream;
     // initial residual, state
     for (const ProbHost& P : pl->probs) {
@@ -383,6 +404,141 @@ fwils_status solve_ws(fwils_plan pl, const float2* b, bool use_x0, double rtol, 
         return FWILS_ENOCONV;
     }
     return FWILS_OK;
+}
+
+// ------------------------------------------------------------- GMRES ----
+void drop_graphs(fwils_plan pl) {
+    if (pl->chunk) (void)hipGraphExecDestroy(pl->chunk);
+    if (pl->gm_cycle) (void)hipGraphExecDestroy(pl->gm_cycle);
+    pl->chunk = nullptr;
+    pl->gm_cycle = nullptr;
+}
+
+GmArgs gm_args(fwils_plan pl, const ProbHost& P) {
+    GmArgs a;
+    a.V = pl->gm_V + P.field_off;
+    a.vstride = pl->total_field;
+    a.gs = pl->gm_sys + P.sys_off;
+    a.st = pl->state + P.sys_off;
+    a.part = pl->gm_part + P.sys_off * pl->gm_maxnb * kGmRec;
+    a.tot1 = pl->gm_tot1 + P.sys_off * kGmRec;
+    a.tot2 = pl->gm_tot2 + P.sys_off * kGmRec;
+    a.tot3 = pl->gm_tot3 + P.sys_off * kGmRec;
+    a.nsys = P.p.nsys;
+    a.n = (int)P.n_per_sys;
+    return a;
+}
+
+// r = b - A x into basis slot 0 with ||r||^2, ||b||^2, then the cycle start.
+hipError_t gm_start(fwils_plan pl, const ProbHost& P, const float2* b, double rtol, bool first, hipStream_t s) {
+    const GmArgs a = gm_args(pl, P);
+    const GmEpi ge{nullptr, 0, 0, a.part};
+    hipError_t e = matvec(pl, P, P.dev, at(pl->x, P), at(pl->tmp, P), maps_at(pl, P), EPI_GMRES_R0,
+                          b + P.field_off, a.V, nullptr, a.st, s, &ge);
+    if (e == hipSuccess) e = launch_gm_sum(a, GM_SUM_BEGIN, P.np_rows, 0, false, rtol, first, s);
+    return e;
+}
+
+// One GMRES cycle of m Arnoldi steps, the solution update, and the start of
+// the next cycle (true residual).  Systems that are not RUNNING skip.
+// Per step: the matvec whose epilogue projects w on the basis, the sum of
+// those projections, w -= W c, and (CGS2) the projections of the result,
+// their sum and the second subtraction; the last subtraction leaves ||w||^2
+// records, whose sum builds the Hessenberg column.
+hipError_t gm_cycle(fwils_plan pl, const ProbHost& P, const float2* b, double rtol, hipStream_t s) {
+    const GmArgs a = gm_args(pl, P);
+    const int nbv = gm_blocks_per_sys((int)P.n_per_sys);
+    const bool cgs2 = pl->gm_cgs2;
+    hipError_t e = hipSuccess;
+    for (int j = 0; j < pl->gm_m && e == hipSuccess; ++j) {
+        const GmEpi ge{a.V, a.vstride, j + 1, a.part};
+        float2* wj = a.V + (size_t)j * a.vstride;
+        float2* wn = a.V + (size_t)(j + 1) * a.vstride;
+        e = matvec(pl, P, P.dev, wj, at(pl->tmp, P), maps_at(pl, P), EPI_ARNOLDI, nullptr, wn, nullptr, a.st, s,
+                   &ge);
+        if (e == hipSuccess) e = launch_gm_sum(a, GM_SUM_PROJ1, P.np_rows, j, cgs2, rtol, false, s);
+        if (e == hipSuccess) e = launch_gm_update(a, j, 1, !cgs2, s);
+        if (cgs2) {
+            if (e == hipSuccess) e = launch_gm_dots(a, j, s);
+            if (e == hipSuccess) e = launch_gm_sum(a, GM_SUM_PROJ2, nbv, j, cgs2, rtol, false, s);
+            if (e == hipSuccess) e = launch_gm_update(a, j, 2, true, s);
+        }
+        if (e == hipSuccess) e = launch_gm_sum(a, GM_SUM_HESS, nbv, j, cgs2, rtol, false, s);
+    }
+    if (e == hipSuccess) e = launch_gm_finish_cycle(at(pl->x, P), a, s);
+    if (e == hipSuccess) e = gm_start(pl, P, b, rtol, false, s);
+    return e;
+}
+
+fwils_status gm_solve_ws(fwils_plan pl, const float2* b, bool use_x0, double rtol, int maxit, int32_t* iters,
+                         double* relres, uint32_t flags) {
+    if (flags & FWILS_SOLVE_PLAIN) {
+        set_error("solve: the per-source plain loop is a BiCGSTAB mode");
+        return FWILS_EUNSUPPORTED;
+    }
+    hipStream_t s = pl->stream;
+    // the cycle graph reads the right-hand side from the plan's rhs vector
+    if (b != pl->rhs) FW_HIP(launch_copy(b, pl->rhs, pl->total_field, s));
+    b = pl->rhs;
+    for (const ProbHost& P : pl->probs) {
+        const GmArgs a = gm_args(pl, P);
+        if (!use_x0) FW_HIP(launch_zero(at(pl->x, P), (size_t)P.p.nsys * P.n_per_sys, s));
+        FW_HIP(launch_gm_init(a.st, a.gs, a.nsys, maxit, pl->gm_m, s));
+        FW_HIP(gm_start(pl, P, b, rtol, true, s));
+    }
+    const size_t nst = pl->total_sys;
+    auto any_running = [&](bool& any) -> fwils_status {
+        FW_HIP(hipMemcpyAsync(pl->host_state, pl->state, nst * sizeof(SysState), hipMemcpyDeviceToHost, s));
+        FW_HIP(hipStreamSynchronize(s));
+        any = false;
+        for (size_t i = 0; i < nst; ++i)
+            if (pl->host_state[i].status == ST_RUNNING) any = true;
+        return FWILS_OK;
+    };
+    bool any = false;
+    FW_TRY(any_running(any));
+    const bool graph = !(flags & FWILS_SOLVE_NOGRAPH);
+    if (any && graph && (!pl->gm_cycle || pl->gm_rtol != rtol)) {
+        if (pl->gm_cycle) (void)hipGraphExecDestroy(pl->gm_cycle);
+        pl->gm_cycle = nullptr;
+        const float2* rhs = pl->rhs;
+        FW_TRY(capture_graph(pl, &pl->gm_cycle, [pl, rhs, rtol](const ProbHost& P, hipStream_t q) {
+            return gm_cycle(pl, P, rhs, rtol, q);
+        }));
+        pl->gm_rtol = rtol;
+    }
+    for (int c = 0; any && c <= maxit; ++c) {
+        if (graph) {
+            FW_HIP(hipGraphLaunch(pl->gm_cycle, s));
+        } else {
+            for (const ProbHost& P : pl->probs) FW_HIP(gm_cycle(pl, P, b, rtol, s));
+        }
+        FW_TRY(any_running(any));
+    }
+    FW_HIP(launch_gm_report(pl->state, iters, relres, (int)nst, s));
+    FW_HIP(hipMemcpyAsync(pl->host_state, pl->state, nst * sizeof(SysState), hipMemcpyDeviceToHost, s));
+    FW_HIP(hipStreamSynchronize(s));
+    bool noconv = false, brk = false;
+    for (size_t i = 0; i < nst; ++i) {
+        const int stt = pl->host_state[i].status;
+        if (stt == ST_MAXIT || stt == ST_RUNNING) noconv = true;
+        if (stt == ST_BREAKDOWN || stt == ST_NONFINITE) brk = true;
+    }
+    if (brk) {
+        set_error("GMRES breakdown or non-finite residual in at least one system");
+        return FWILS_EBREAKDOWN;
+    }
+    if (noconv) {
+        set_error("at least one system did not reach rtol within maxit");
+        return FWILS_ENOCONV;
+    }
+    return FWILS_OK;
+}
+
+fwils_status solve_ws(fwils_plan pl, const float2* b, bool use_x0, double rtol, int maxit, int32_t* iters,
+                      double* relres, uint32_t flags) {
+    if (pl->krylov == FWILS_KRYLOV_GMRES) return gm_solve_ws(pl, b, use_x0, rtol, maxit, iters, relres, flags);
+    return bicg_solve_ws(pl, b, use_x0, rtol, maxit, iters, relres, flags);
 }
 
 fwils_status check_field_ptrs(std::initializer_list<const void*> ptrs) {
@@ -511,7 +667,7 @@ fwils_status fwils_plan_create(const fwils_problem* probs, int32_t nprob, fwils_
 
 void fwils_plan_destroy(fwils_plan plan) {
     if (!plan) return;
-    if (plan->chunk) (void)hipGraphExecDestroy(plan->chunk);
+    drop_graphs(plan);
     if (plan->host_state) (void)hipHostFree(plan->host_state);
     delete plan;
 }
@@ -548,10 +704,7 @@ fwils_status fwils_set_workspace(fwils_plan plan, void* dev, size_t bytes) {
         set_error("set_workspace: need %zu bytes, 256-byte aligned (got %zu)", plan->ws_bytes, bytes);
         return FWILS_ENOMEM;
     }
-    if (plan->chunk) {
-        (void)hipGraphExecDestroy(plan->chunk);
-        plan->chunk = nullptr;
-    }
+    drop_graphs(plan);
     if (!plan->host_state) {
         FW_HIP(hipHostMalloc((void**)&plan->host_state, plan->total_sys * sizeof(SysState),
                              hipHostMallocDefault));
@@ -1073,6 +1226,91 @@ fwils_status fwils_solve_stats(fwils_plan plan, int32_t* iters, double* relres) 
     return FWILS_OK;
 }
 
+namespace {
+
+// Layout of the GMRES workspace for restart length m.
+struct GmLayout {
+    size_t basis, sys, part, tot, total, maxnb;
+};
+GmLayout gm_layout(fwils_plan pl, int m) {
+    GmLayout L;
+    L.maxnb = 0;
+    for (const ProbHost& P : pl->probs) {
+        int cand[2];
+        const int nc = row_candidates(P.p.nx, cand);
+        for (int c = 0; c < nc; ++c)
+            L.maxnb = std::max(L.maxnb, (size_t)row_geom(P.p.nx, cand[c], 2 * P.p.nz).blocks_per_sys);
+        L.maxnb = std::max(L.maxnb, (size_t)gm_blocks_per_sys((int)P.n_per_sys));
+    }
+    size_t o = 0;
+    L.basis = o;
+    o = align256(o + (size_t)(m + 1) * pl->total_field * sizeof(float2));
+    L.sys = o;
+    o = align256(o + pl->total_sys * sizeof(GmSys));
+    L.part = o;
+    o = align256(o + pl->total_sys * L.maxnb * kGmRec * sizeof(double));
+    L.tot = o;
+    o = align256(o + 3 * pl->total_sys * kGmRec * sizeof(double));
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+
+fwils_status fwils_gmres_workspace_size(fwils_plan plan, int32_t restart, size_t* bytes) {
+    FW_TRY(check_plan(plan, false));
+    if (!bytes || restart < 1 || restart > kGmMax) {
+        set_error("gmres_workspace_size: restart must be 1..%d", kGmMax);
+        return FWILS_EINVAL;
+    }
+    *bytes = gm_layout(plan, restart).total;
+    return FWILS_OK;
+}
+
+fwils_status fwils_set_krylov(fwils_plan plan, int32_t method, int32_t restart, uint32_t flags, void* gws,
+                              size_t bytes) {
+    FW_TRY(check_plan(plan, false));
+    if (flags & ~(uint32_t)FWILS_GMRES_CGS1) {
+        set_error("set_krylov: unknown flags");
+        return FWILS_EINVAL;
+    }
+    if (method == FWILS_KRYLOV_BICGSTAB) {
+        drop_graphs(plan);
+        plan->krylov = method;
+        return FWILS_OK;
+    }
+    if (method != FWILS_KRYLOV_GMRES) {
+        set_error("set_krylov: unknown method %d", method);
+        return FWILS_EINVAL;
+    }
+    if (restart < 1 || restart > kGmMax) {
+        set_error("set_krylov: restart must be 1..%d", kGmMax);
+        return FWILS_EINVAL;
+    }
+    const GmLayout L = gm_layout(plan, restart);
+    if (!gws || bytes < L.total || ((uintptr_t)gws & 255) != 0) {
+        set_error("set_krylov: GMRES needs %zu bytes, 256-byte aligned (got %zu)", L.total, bytes);
+        return FWILS_ENOMEM;
+    }
+    if (!plan->ws) {
+        set_error("set_krylov: set the plan workspace first");
+        return FWILS_ENOMEM;
+    }
+    char* w = static_cast<char*>(gws);
+    drop_graphs(plan);
+    plan->krylov = method;
+    plan->gm_m = restart;
+    plan->gm_cgs2 = !(flags & FWILS_GMRES_CGS1);
+    plan->gm_maxnb = L.maxnb;
+    plan->gm_V = reinterpret_cast<float2*>(w + L.basis);
+    plan->gm_sys = reinterpret_cast<GmSys*>(w + L.sys);
+    plan->gm_part = reinterpret_cast<double*>(w + L.part);
+    plan->gm_tot1 = reinterpret_cast<double*>(w + L.tot);
+    plan->gm_tot2 = plan->gm_tot1 + plan->total_sys * kGmRec;
+    plan->gm_tot3 = plan->gm_tot2 + plan->total_sys * kGmRec;
+    return FWILS_OK;
+}
+
 }  // extern "C"
 
 // ------------------------------------------------------------ autotuner --
@@ -1106,10 +1344,7 @@ bool cfg_ok(const ProbHost& P, const KernelCfg& k) {
 void apply_cfg(fwils_plan pl, ProbHost& P, const KernelCfg& k) {
     P.cfg = k;
     P.np_rows = row_geom(P.p.nx, k.row_p, 2 * P.p.nz).blocks_per_sys;
-    if (pl->chunk) {
-        (void)hipGraphExecDestroy(pl->chunk);
-        pl->chunk = nullptr;
-    }
+    drop_graphs(pl);
 }
 
 // Candidates of one kind: the problem's current variants with that kind's

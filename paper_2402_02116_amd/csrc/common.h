@@ -48,6 +48,7 @@ enum SysStatus : int {
     ST_BREAKDOWN = 3,
     ST_NONFINITE = 4,
     ST_RESTART = 5,        // converged on the recursive residual, true residual too large
+    ST_CYCLE_DONE = 6,     // GMRES: cycle finished, solution update pending
 };
 
 // Per-system BiCGSTAB scalars (FP64), one struct per system.
@@ -106,6 +107,51 @@ __device__ __forceinline__ void sum_partials(const double* __restrict__ part, in
     }
     block_allreduce<NV, NT>(res, smem);
 }
+
+// ------------------------------------------------------ record reduction --
+// tot[k] = sum over records b < nb of rec[b * stride + k], k < nval, by one
+// block: groups of 64 threads (one value per lane) add records q, q + G,
+// q + 2G, ... and the G group sums are added in group order, so the result
+// does not depend on timing.  blockDim.x must be a multiple of 64 and smem
+// must hold blockDim.x doubles.
+__device__ __forceinline__ void sum_records(const double* rec, int nb, int stride, int nval, double* tot,
+                                            double* smem) {
+    const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6, ngrp = blockDim.x >> 6;
+    for (int k0 = 0; k0 < nval; k0 += 64) {
+        const int k = k0 + lane;
+        double s = 0.0;
+        if (k < nval)
+            for (int b = grp; b < nb; b += ngrp) s += rec[(size_t)b * stride + k];
+        smem[threadIdx.x] = s;
+        __syncthreads();
+        if (grp == 0 && k < nval) {
+            double t = 0.0;
+            for (int q = 0; q < ngrp; ++q) t += smem[q * 64 + lane];
+            tot[k] = t;
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------ GMRES state --
+constexpr int kGmMax = 32;                      // largest restart length
+constexpr int kGmRec = 2 * (kGmMax + 1) + 2;    // doubles per partial record
+
+// Per-system FP64 state of restarted GMRES with an unnormalised Arnoldi basis
+// (basis vector i stored as w_i = n_i v_i, n_i = ||w_i||).  R is the
+// Hessenberg matrix after the Givens rotations, column-major with leading
+// dimension kGmMax + 1.
+struct GmSys {
+    double n2[kGmMax + 1];                       // ||w_i||^2
+    double rre[(kGmMax + 1) * kGmMax], rim[(kGmMax + 1) * kGmMax];
+    double cs[kGmMax], sre[kGmMax], sim[kGmMax];   // rotations (c real, s complex)
+    double gre[kGmMax + 1], gim[kGmMax + 1];       // rotated right-hand side
+    double yre[kGmMax], yim[kGmMax];               // update coefficients y_i / n_i
+    int j;                                          // Arnoldi steps of the current cycle
+    int m;                                          // restart length
+    int cycles;
+    int pad;
+};
 
 // Workgroup ids are dealt to the 8 XCDs round-robin (id % 8).  Remap so that
 // each XCD works on one contiguous range of logical blocks: neighbouring

@@ -55,7 +55,7 @@ __global__ __launch_bounds__(256) void k_rows(const float2* in, float2* out,
                                               double* __restrict__ partials, int nrows,
                                               int rows_per_sys, int F,
                                               const SysState* __restrict__ st,
-                                              const float2* __restrict__ tw) {
+                                              const float2* __restrict__ tw, GmEpi ge) {
     using S = FftShape<N, P>;
     constexpr int T = S::T;
     constexpr int PL = PaddedLen<N>::value;
@@ -108,16 +108,59 @@ __global__ __launch_bounds__(256) void k_rows(const float2* in, float2* out,
                     acc[1] += (double)o.x * uu.y - (double)o.y * uu.x;
                     acc[2] += (double)o.x * o.x + (double)o.y * o.y;
                     acc[3] += (double)uu.x * uu.x + (double)uu.y * uu.y;
-                } else if constexpr (EPI == EPI_TRUERES) {
+                } else if constexpr (EPI == EPI_TRUERES || EPI == EPI_GMRES_R0) {
                     const float2 b = aux[i];
                     const float2 rr = csub(b, o);
                     out[i] = rr;
                     acc[0] += (double)rr.x * rr.x + (double)rr.y * rr.y;
+                    if constexpr (EPI == EPI_GMRES_R0) acc[1] += (double)b.x * b.x + (double)b.y * b.y;
+                } else if constexpr (EPI == EPI_ARNOLDI) {
+                    out[i] = o;
+                    v[0][m] = o;   // kept for the projections below
                 }
             }
         }
     }
-    if constexpr (EPI >= EPI_BICG_V) {
+    if constexpr (EPI == EPI_ARNOLDI || EPI == EPI_GMRES_R0) {
+        // GMRES: one partial record per block (summed by a later kernel)
+        const int nb = rows_per_sys / F;
+        const int bi = (row0 % rows_per_sys) / F;
+        double* rec = ge.part + ((size_t)sys * nb + bi) * kGmRec;
+        if constexpr (EPI == EPI_GMRES_R0) {
+            block_sum_to0<kPartialNV>(acc, red);
+            if (tid == 0) {
+                rec[0] = acc[0];
+                rec[1] = acc[1];
+            }
+        } else {
+            const size_t base = (size_t)row * N;
+            for (int l0 = 0; l0 < ge.nv; l0 += 2) {
+                double a[4] = {0.0, 0.0, 0.0, 0.0};
+                if (active) {
+#pragma unroll
+                    for (int m = 0; m < P; ++m) {
+                        const size_t i = base + t + T * m;
+                        const float2 w = v[0][m];
+#pragma unroll
+                        for (int k = 0; k < 2; ++k) {
+                            if (l0 + k < ge.nv) {
+                                const float2 b = ge.V[(size_t)(l0 + k) * ge.vstride + i];
+                                a[2 * k] += (double)b.x * w.x + (double)b.y * w.y;
+                                a[2 * k + 1] += (double)b.x * w.y - (double)b.y * w.x;
+                            }
+                        }
+                    }
+                }
+                block_sum_to0<4>(a, red);
+                if (tid == 0) {
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        if (2 * l0 + k < 2 * ge.nv) rec[2 * l0 + k] = a[k];
+                }
+                __syncthreads();
+            }
+        }
+    } else if constexpr (EPI >= EPI_BICG_V) {
         block_sum_to0<kPartialNV>(acc, red);
         if (tid == 0) {
             const int nb = rows_per_sys / F;
@@ -262,14 +305,15 @@ inline hipError_t allow_lds(K kernel, size_t bytes) {
 template <int N, int P, bool INV, int EPI>
 inline hipError_t rows_launch(const float2* in, float2* out, const float2* u, const float2* aux,
                               double* part, int nrows, int rps, const SysState* st, const float2* tw,
-                              hipStream_t s) {
+                              hipStream_t s, const GmEpi* ge = nullptr) {
+    const GmEpi gz{nullptr, 0, 0, nullptr};
     const RowGeom g = row_geom(N, P, rps);
     const int blocks = (nrows + g.F - 1) / g.F;
     const size_t lds = (size_t)(g.F + 1) * PaddedLen<N>::value * sizeof(float2);
     hipError_t e = allow_lds(k_rows<N, P, INV, EPI>, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_rows<N, P, INV, EPI>), dim3(blocks), dim3(g.threads), lds, s, in, out, u, aux,
-                       part, nrows, rps, g.F, st, tw);
+                       part, nrows, rps, g.F, st, tw, ge ? *ge : gz);
     return hipGetLastError();
 }
 

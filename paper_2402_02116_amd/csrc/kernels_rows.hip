@@ -27,11 +27,15 @@ hipError_t launch_rows_fwd(int n, int P, const float2* in, float2* out, int nrow
 template <int N, int P>
 static hipError_t rows_inv_np(int epi, const float2* in, const float2* u, const float2* aux, float2* out,
                               double* part, int nrows, int rps, const SysState* st, const float2* tw,
-                              hipStream_t s) {
+                              hipStream_t s, const GmEpi* ge) {
+    if ((epi == EPI_ARNOLDI || epi == EPI_GMRES_R0) && (!ge || !ge->part))
+        return hipErrorInvalidValue;
+    if (epi == EPI_ARNOLDI && (!ge->V || ge->nv < 1 || ge->nv > kGmMax + 1)) return hipErrorInvalidValue;
     switch (epi) {
 #define FW_EPI(E) \
-    case E: return rows_launch<N, P, true, E>(in, out, u, aux, part, nrows, rps, st, tw, s);
+    case E: return rows_launch<N, P, true, E>(in, out, u, aux, part, nrows, rps, st, tw, s, ge);
         FW_EPI(EPI_STORE) FW_EPI(EPI_APPLY) FW_EPI(EPI_BICG_V) FW_EPI(EPI_BICG_T) FW_EPI(EPI_TRUERES)
+        FW_EPI(EPI_ARNOLDI) FW_EPI(EPI_GMRES_R0)
 #undef FW_EPI
         default: return hipErrorInvalidValue;
     }
@@ -39,11 +43,11 @@ static hipError_t rows_inv_np(int epi, const float2* in, const float2* u, const 
 
 hipError_t launch_rows_inv(int n, int P, int epi, const float2* in, const float2* u, const float2* aux,
                            float2* out, double* part, int nrows, int rps, const SysState* st,
-                           const float2* tw, hipStream_t s) {
+                           const float2* tw, hipStream_t s, const GmEpi* ge) {
     if (!row_points_ok(n, P)) return hipErrorInvalidValue;
     const float2* t = tw + twiddle_offset(n);
 #define FW_CASE(N, PP) \
-    if (n == N && P == PP) return rows_inv_np<N, PP>(epi, in, u, aux, out, part, nrows, rps, st, t, s);
+    if (n == N && P == PP) return rows_inv_np<N, PP>(epi, in, u, aux, out, part, nrows, rps, st, t, s, ge);
     FW_ROW_VARIANTS(FW_CASE)
 #undef FW_CASE
     return hipErrorInvalidValue;

@@ -15,6 +15,16 @@ enum RowEpilogue : int {
     EPI_BICG_V = 2,    // out = u - y;  partial <aux, out>      (v = A p, <r^, v>)
     EPI_BICG_T = 3,    // out = u - y;  partials <out, u>, ||out||^2, ||u||^2   (t = A s)
     EPI_TRUERES = 4,   // out = aux - (u - y); partial ||out||^2       (r = b - A x)
+    EPI_ARNOLDI = 5,   // out = u - y = w; partial <basis_l, w>, l < nv
+    EPI_GMRES_R0 = 6,  // out = aux - (u - y); partial ||out||^2, ||aux||^2
+};
+
+// Extra arguments of the GMRES epilogues (unused by the others).
+struct GmEpi {
+    const float2* V;   // basis vector 0, indexed like the transform's output
+    size_t vstride;    // complex elements between basis vectors
+    int nv;            // basis vectors to project on
+    double* part;      // [sys][blocks][kGmRec] partial records
 };
 constexpr int kPartialNV = 4;   // doubles per partial-sum record
 
@@ -73,7 +83,7 @@ hipError_t launch_rows_fwd(int n, int P, const float2* in, float2* out, int nrow
                            const SysState* st, const float2* tw, hipStream_t s);
 hipError_t launch_rows_inv(int n, int P, int epi, const float2* in, const float2* u, const float2* aux,
                            float2* out, double* partials, int nrows, int rows_per_sys,
-                           const SysState* st, const float2* tw, hipStream_t s);
+                           const SysState* st, const float2* tw, hipStream_t s, const GmEpi* ge = nullptr);
 // Column pass over [nsys][2][nz][nx] in place.  COL_FWD / COL_INV exist in
 // the default points-per-thread variant with shared LDS only.
 hipError_t launch_cols(int mode, const ColCfg& c, float2* data, const ProbDev& pd, const SysState* st,
@@ -115,6 +125,34 @@ hipError_t launch_bicg_restart_mark(SysState* st, const double* partTR, int npTR
 hipError_t launch_bicg_restart(SysState* st, int nsys, hipStream_t s);
 hipError_t launch_bicg_finish(const SysState* st, const double* partTR, int npTR, int nsys,
                               int32_t* iters, double* relres, hipStream_t s);
+
+// Batched restarted GMRES (one problem).
+struct GmArgs {
+    float2* V;          // basis slot 0 of this problem (system 0)
+    size_t vstride;     // complex elements between basis slots
+    GmSys* gs;          // per-system FP64 state
+    SysState* st;       // per-system status / iteration count
+    double* part;       // [sys][blocks][kGmRec] partial records
+    double* tot1;       // [sys][kGmRec] projections of the Arnoldi epilogue
+    double* tot2;       // [sys][kGmRec] projections of the re-orthogonalisation
+    double* tot3;       // [sys][kGmRec] norms
+    int nsys;
+    int n;              // complex elements per system
+};
+int gm_blocks_per_sys(int n);
+hipError_t launch_gm_init(SysState* st, GmSys* gs, int nsys, int maxit, int m, hipStream_t s);
+// Sums of the per-block records (nb per system) of the previous GMRES kernel:
+// GM_SUM_PROJ1 / GM_SUM_PROJ2 into tot1 / tot2 (2 (j + 1) values),
+// GM_SUM_HESS ||w||^2 into tot3 and then Hessenberg column j, Givens
+// rotation and stopping test, GM_SUM_BEGIN ||r||^2, ||b||^2 into tot3 and
+// then the cycle-start test (first: also sets ||b||).
+enum GmSum : int { GM_SUM_PROJ1 = 0, GM_SUM_PROJ2 = 1, GM_SUM_HESS = 2, GM_SUM_BEGIN = 3 };
+hipError_t launch_gm_sum(const GmArgs& a, int mode, int nb, int j, bool cgs2, double rtol, bool first,
+                         hipStream_t s);
+hipError_t launch_gm_update(const GmArgs& a, int j, int pass, bool final, hipStream_t s);
+hipError_t launch_gm_dots(const GmArgs& a, int j, hipStream_t s);
+hipError_t launch_gm_finish_cycle(float2* x, const GmArgs& a, hipStream_t s);
+hipError_t launch_gm_report(const SysState* st, int32_t* iters, double* relres, int nsys, hipStream_t s);
 
 // Sources, receivers, correlation.
 hipError_t launch_point_sources(float2* f, const int32_t* src_ixz, const double* src_f,

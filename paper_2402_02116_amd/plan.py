@@ -189,7 +189,8 @@ class Plan:
 
     def solve(self, rhs, x0=None, rtol=1e-6, maxit=1000, plain=False, graph=True, out=None,
               strict=False):
-        """BiCGSTAB solve of A x = rhs; returns SolveResult (iters, true relres)."""
+        """Krylov solve of A x = rhs with the plan's method (set_krylov); returns
+        SolveResult (iters, true relres)."""
         self._field(rhs, "rhs")
         flags = 0
         if x0 is not None:
@@ -367,6 +368,31 @@ class Plan:
         if st != _lib.FWILS_OK:
             check(st, "fwils_normal_cg")
         return q, hist
+
+    # ------------------------------------------------- Krylov method ----
+    def set_krylov(self, method="bicgstab", restart=20, cgs2=True):
+        """Krylov method of every solve of this plan: 'bicgstab' (default) or
+        'gmres' (restarted GMRES(restart), restart <= 32; allocates its basis)."""
+        if method == "bicgstab":
+            check(self.lib.fwils_set_krylov(self._h, _lib.FWILS_KRYLOV_BICGSTAB, 0, 0, None, 0),
+                  "fwils_set_krylov")
+            self._gm_raw = None
+            self.krylov = ("bicgstab", 0)
+            return
+        if method != "gmres":
+            raise ValueError(f"unknown Krylov method {method!r}")
+        size = ctypes.c_size_t()
+        check(self.lib.fwils_gmres_workspace_size(self._h, int(restart), ctypes.byref(size)),
+              "fwils_gmres_workspace_size")
+        with torch.cuda.device(self.device):
+            raw = torch.empty(size.value + 256, dtype=torch.uint8, device=self.device)
+        ptr = raw.data_ptr() + (-raw.data_ptr()) % 256
+        self._bind_stream()
+        check(self.lib.fwils_set_krylov(self._h, _lib.FWILS_KRYLOV_GMRES, int(restart),
+                                        0 if cgs2 else _lib.FWILS_GMRES_CGS1, ctypes.c_void_p(ptr), size.value),
+              "fwils_set_krylov")
+        self._gm_raw = raw
+        self.krylov = ("gmres", int(restart))
 
     # ----------------------------------------------------- autotuner ----
     TUNE_KINDS = {"stencil": _lib.FWILS_TUNE_STENCIL, "rows": _lib.FWILS_TUNE_ROWS, "cols": _lib.FWILS_TUNE_COLS}

@@ -1,0 +1,136 @@
+"""GPU parity of the batched restarted GMRES path (Arnoldi with CGS2 or CGS1,
+FP64 Hessenberg / Givens on the device) against the complex128 oracle: solved
+fields, the true residual it reports, multi-problem plans, J and J* through
+GMRES solves, and its stopping / error behaviour."""
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import LSProblem
+
+pytestmark = pytest.mark.gpu
+
+FIELD_TOL = 1e-4
+
+
+def _rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def _np(t):
+    return t.detach().cpu().numpy().astype(np.complex128)
+
+
+def _case(nx, nz, nsys, f=6.0, seed=3, amp=0.1, dx=8.0):
+    c0, rho0 = W.vti_background()
+    maps = W.round_f32(W.model_scales(c0, rho0) * W.smooth_maps(seed, nz, nx, 3.0, amp))
+    p = dict(nx=nx, nz=nz, dx=dx, c0=c0, rho0=rho0, freq_hz=f, eta=0.02, nsys=nsys)
+    return p, maps
+
+
+def _oracle(p, maps):
+    return LSProblem(p["nx"], p["nz"], p["dx"], p["c0"], p["rho0"], p["freq_hz"], 0.02, maps)
+
+
+@pytest.mark.parametrize("restart,cgs2", [(20, True), (5, True), (20, False)])
+def test_gmres_solve_matches_oracle(restart, cgs2):
+    from paper_2402_02116_amd.plan import Plan
+    print(f"gmres restart={restart} cgs2={cgs2}", flush=True)
+    cases = [_case(64, 48, 3, seed=4), _case(96, 96, 2, f=9.0, seed=5)]
+    plan = Plan([c[0] for c in cases])
+    src, fv = [], []
+    for i, (p, m) in enumerate(cases):
+        plan.set_contrast(i, m)
+        s, f = W.surface_sources(p["nx"], p["nsys"], iz=p["nz"] // 4)
+        src += s
+        fv += f
+    plan.set_krylov("gmres", restart=restart, cgs2=cgs2)
+    u0 = plan.incident(src, fv)
+    res = plan.solve(u0, rtol=1e-6, maxit=2000)
+    assert res.status == 0, (res.status, res.iters)
+    assert np.all(res.relres <= 1e-6), res.relres
+    k = 0
+    for i, (p, m) in enumerate(cases):
+        P = _oracle(p, m)
+        ns = p["nsys"]
+        b = _np(plan.view(u0, i))
+        x = _np(plan.view(res.x, i))
+        # with the complex128 operator: rtol plus the fp32 rounding of A (< 2e-6)
+        for q in range(ns):
+            rel = np.linalg.norm(b[q] - P.apply(x[q][None])[0]) / np.linalg.norm(b[q])
+            assert rel <= 3e-6, (i, q, rel)
+        uref, _ = P.solve(P.incident(src[k:k + ns], fv[k:k + ns]), tol=1e-11)
+        assert _rel(x, uref) < FIELD_TOL
+        k += ns
+
+
+def test_gmres_graph_and_direct_launches_agree_and_repeat():
+    from paper_2402_02116_amd.plan import Plan
+    p, maps = _case(96, 64, 3, seed=6)
+    plan = Plan([p])
+    plan.set_contrast(0, maps)
+    plan.set_krylov("gmres", restart=10)
+    u0 = plan.incident(*W.surface_sources(96, 3))
+    a = plan.solve(u0, rtol=1e-6, maxit=1000)
+    b = plan.solve(u0, rtol=1e-6, maxit=1000)
+    c = plan.solve(u0, rtol=1e-6, maxit=1000, graph=False)
+    assert torch.equal(a.x, b.x) and torch.equal(a.x, c.x)
+    assert np.array_equal(a.iters, c.iters)
+    with pytest.raises(Exception):
+        plan.solve(u0, rtol=1e-6, maxit=100, plain=True)
+
+
+def test_gmres_and_bicgstab_agree_and_edge_cases():
+    from paper_2402_02116_amd import _lib
+    from paper_2402_02116_amd.plan import Plan
+    p, maps = _case(64, 64, 2, amp=0.15, seed=7)
+    plan = Plan([p])
+    plan.set_contrast(0, maps)
+    u0 = plan.incident([(3, 0), (40, 0)], [(0.0, 1.0), (0.0, 1.0)])
+    xb = plan.solve(u0, rtol=1e-7, maxit=1000).x.clone()
+    plan.set_krylov("gmres", restart=16)
+    xg = plan.solve(u0, rtol=1e-7, maxit=1000).x
+    assert _rel(_np(xg), _np(xb)) < 1e-5
+    # zero right-hand side: zero solution, no iterations
+    z = plan.solve(plan.new_field(), rtol=1e-6, maxit=10)
+    assert z.status == 0 and np.all(z.iters == 0) and not torch.any(z.x != 0)
+    # maxit reached: ENOCONV, outputs still written
+    r = plan.solve(u0, rtol=1e-12, maxit=3)
+    assert r.status == _lib.FWILS_ENOCONV and np.all(r.iters == 3)
+    # warm start from the solution
+    w = plan.solve(u0, x0=xg, rtol=1e-5, maxit=100)
+    assert w.status == 0 and np.all(w.iters == 0)
+    plan.set_krylov("bicgstab")
+    assert _rel(_np(plan.solve(u0, rtol=1e-7, maxit=1000).x), _np(xb)) == 0.0
+
+
+def test_frechet_and_adjoint_through_gmres_match_oracle():
+    from paper_2402_02116_amd.plan import Plan
+    c0, rho0 = W.vti_background()
+    m0 = W.model_scales(c0, rho0)
+    nx, nz, ns, nrec = 48, 32, 2, 6
+    maps = W.round_f32(m0 * W.smooth_maps(21, nz, nx, 2.0, 0.08))
+    p = dict(nx=nx, nz=nz, dx=8.0, c0=c0, rho0=rho0, freq_hz=12.0, eta=0.02, nsys=ns)
+    plan = Plan([p])
+    plan.set_contrast(0, maps)
+    plan.set_krylov("gmres", restart=20)
+    src, f = W.surface_sources(nx, ns, iz=1)
+    rec = W.surface_receivers(nx, nrec, iz=2)
+    plan.set_receivers(0, rec)
+    ub = plan.solve(plan.incident(src, f), rtol=1e-7, maxit=2000).x
+    P = _oracle(p, maps)
+    ub_ref, _ = P.solve(P.incident(src, f), tol=1e-12)
+    assert _rel(_np(plan.view(ub, 0)), ub_ref) < FIELD_TOL
+    dm = W.round_f32(m0 * W.smooth_maps(4, nz, nx, 2.0, 0.05))
+    d = plan.frechet(ub, [torch.as_tensor(dm, dtype=torch.float32).cuda()], rtol=1e-7)
+    assert _rel(_np(plan.data_view(d, 0)), P.frechet(ub_ref, dm, rec, tol=1e-12)) < FIELD_TOL
+    rng = np.random.default_rng(3)
+    r = W.round_f32(rng.standard_normal((ns, nrec, 2)) + 1j * rng.standard_normal((ns, nrec, 2)))
+    g = plan.adjoint(ub, torch.as_tensor(r.astype(np.complex64).ravel()).cuda(), rtol=1e-7)
+    g_ref = P.adjoint(ub_ref, r, rec, tol=1e-12)
+    gg = _np(g[0])
+    for k in range(5):
+        assert _rel(gg[k], g_ref[k]) < FIELD_TOL, k
