@@ -57,7 +57,7 @@ def _kernel_source_hash():
 def _traffic_from_profiles(kernel_pass, launch_cells):
     """HBM bytes per launch from the committed counter summary, or None when the
     kernels changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "counters_config1.json")
+    path = os.path.join(ROOT, "profiles", "counters_vti256x16.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
@@ -73,7 +73,7 @@ def _traffic_from_profiles(kernel_pass, launch_cells):
 def build_workload():
     import numpy as np
     import workloads as W
-    c = W.config1()
+    c = W.vti256_layered()
     rec = W.surface_receivers(c["nx"], NREC)
     m0 = W.model_scales(c["c0"], c["rho0"])
     dm = W.round_f32(m0 * W.smooth_maps(4, c["nz"], c["nx"], 10, 0.01)).astype(np.float32)
@@ -89,7 +89,7 @@ def multigrid(a):
     import torch
     import workloads as W
     from paper_2402_02116_amd.plan import Plan
-    probs = W.config2()
+    probs = W.four_grids()
     plan = Plan([dict(nx=p["nx"], nz=p["nz"], dx=p["dx"], c0=p["c0"], rho0=p["rho0"],
                       freq_hz=p["freq_hz"], eta=p["eta"], nsys=p["nsys"]) for p in probs], device="cuda:0")
     for i, p in enumerate(probs):
@@ -200,7 +200,7 @@ def main(argv=None):
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported (the path shards "
-              f"independent systems across GPUs, see DESIGN.md)", file=sys.stderr)
+              f"independent (source, frequency) systems across GPUs, one process per GPU)", file=sys.stderr)
         return 2
 
     import numpy as np

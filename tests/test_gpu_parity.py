@@ -135,10 +135,10 @@ def test_incident_matches_oracle():
 
 
 # ---------------------------------------------------------------- solves --
-def test_solve_config0_matches_oracle():
-    """Config 0 (32^2 isotropic, Gaussian blob, 10 Hz): c64 BiCGSTAB vs the
+def test_solve_iso32_blob_matches_oracle():
+    """32^2 isotropic background, Gaussian blob, 10 Hz: c64 BiCGSTAB vs the
     oracle's solution (itself pinned to a dense direct solve)."""
-    c = W.config0()
+    c = W.iso32_blob()
     p = _pd(c["nx"], c["nz"], c["dx"], c["c0"], c["rho0"], c["freq_hz"], 1)
     plan = _plan([p])
     plan.set_contrast(0, c["maps"])
@@ -167,10 +167,10 @@ def test_solve_rectangular_vti_matches_oracle(nx, nz, nsys):
         assert _rel(u[k], uref[k]) < FIELD_TOL
 
 
-def test_solve_config1_full_size_sampled():
-    """Config 1 at full size (256^2, 16 sources, 5 Hz), batched c64 to 1e-6:
+def test_solve_vti256_full_size_sampled():
+    """256^2 VTI, 16 sources, 5 Hz at full size, batched c64 to 1e-6:
     every true residual <= 2e-6; three of the systems against the oracle."""
-    c = W.config1()
+    c = W.vti256_layered()
     p = _pd(c["nx"], c["nz"], c["dx"], c["c0"], c["rho0"], c["freq_hz"], c["nsys"])
     plan = _plan([p])
     plan.set_contrast(0, c["maps"])
@@ -269,7 +269,7 @@ def test_solve_multigrid_full_size_oracle_residual():
     systems of every grid the complex128 oracle operator gives the same
     bound for the returned field; the smallest grid is also solved by the
     oracle and compared field to field."""
-    probs = W.config2()
+    probs = W.four_grids()
     pds = [_pd(c["nx"], c["nz"], c["dx"], c["c0"], c["rho0"], c["freq_hz"], c["nsys"]) for c in probs]
     plan = _plan(pds)
     src, fv = [], []

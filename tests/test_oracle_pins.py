@@ -21,11 +21,11 @@ def _het_problem(nx=32, nz=32, dx=10.0, seed=11, amp=0.1, freq=10.0, symbol="spe
 
 
 # ---------------------------------------------------------------- pin 1 ----
-def test_dense_direct_solve_config0():
-    """Config 0: BiCGSTAB on the FFT operator vs a dense solve of
+def test_dense_direct_solve_iso32_blob():
+    """32^2 isotropic blob: BiCGSTAB on the FFT operator vs a dense solve of
     (I - G V) u = u0 with G from a direct DFT sum and V from explicit stencils
     (eqs. A, axb, FFT)."""
-    c = W.config0()
+    c = W.iso32_blob()
     P = LSProblem(c["nx"], c["nz"], c["dx"], c["c0"], c["rho0"], c["freq_hz"], c["eta"], c["maps"])
     u0 = P.incident(c["src_ixz"], c["src_f"])
     u, info = P.solve(u0, tol=1e-8)
@@ -57,7 +57,7 @@ def test_dense_direct_solve_rectangular_vti():
 # ---------------------------------------------------------------- pin 2 ----
 def test_zero_contrast_gives_incident_field():
     """With dC = drho = 0 the operator of eq. A is the identity: u = u0."""
-    c = W.config0()
+    c = W.iso32_blob()
     P = LSProblem(32, 32, 10.0, c["c0"], c["rho0"], 10.0, 0.02, np.zeros((5, 32, 32)))
     u0 = P.incident([(4, 9), (20, 3)], [(0.0, 1.0), (1.0, 0.0)])
     u, infos = P.solve(u0, tol=1e-14)
@@ -385,7 +385,7 @@ def test_bicgstab_and_cg_textbook():
 def test_incident_field_mirror_symmetry():
     """A vertical force in an isotropic medium: u_z is even and u_x is odd
     under the mirror x -> 2 x_s - x."""
-    c = W.config0()
+    c = W.iso32_blob()
     P = LSProblem(32, 32, 10.0, c["c0"], c["rho0"], 10.0, 0.02)
     u0 = P.incident([(16, 16)], [(0.0, 1.0)])[0]
     mirror = lambda a: np.roll(a[:, ::-1], 33, axis=1)   # x -> 32 - x (mod 32)

@@ -140,13 +140,13 @@ def surface_receivers(nx, nr, iz=0):
     return [(int(round(r * (nx - 1) / (nr - 1))), iz) for r in range(nr)]
 
 
-# -------------------------------------------------------------- configs ----
+# ------------------------------------------------------------ workloads ----
 def problem_dict(nx, nz, dx, c0, rho0, freq_hz, eta, maps, src_ixz, src_f):
     return dict(nx=nx, nz=nz, dx=dx, c0=tuple(c0), rho0=rho0, freq_hz=freq_hz,
                 eta=eta, maps=maps, src_ixz=src_ixz, src_f=src_f, nsys=len(src_ixz))
 
 
-def config0():
+def iso32_blob():
     """32^2 isotropic, Gaussian blob contrast, one vertical force at the centre, 10 Hz."""
     nx = nz = 32
     c0 = iso_voigt(2000.0, 1000.0, 2000.0)
@@ -156,7 +156,7 @@ def config0():
     return problem_dict(nx, nz, 10.0, c0, rho0, 10.0, 0.02, maps, [(16, 16)], [(0.0, 1.0)])
 
 
-def config1(nsrc=16):
+def vti256_layered(nsrc=16):
     """256^2 VTI at 8 m, random-layered contrast (seed 1), 16 surface forces, 5 Hz."""
     nx = nz = 256
     c0, rho0 = vti_background()
@@ -166,15 +166,15 @@ def config1(nsrc=16):
     return problem_dict(nx, nz, 8.0, c0, rho0, 5.0, 0.02, maps, src, f)
 
 
-CONFIG2_GRIDS = ((128, 37.5, 4.0), (192, 25.0, 6.0), (256, 18.75, 8.0), (384, 12.5, 12.0))
+FOUR_GRIDS = ((128, 37.5, 4.0), (192, 25.0, 6.0), (256, 18.75, 8.0), (384, 12.5, 12.0))
 
 
-def config2(nsrc=64):
+def four_grids(nsrc=64):
     """Four (grid, frequency) problems over one 4800 m square, 64 forces each."""
     c0, rho0 = vti_background()
     q384 = random_layered(2, 384, 384)
     out = []
-    for n, dx, f in CONFIG2_GRIDS:
+    for n, dx, f in FOUR_GRIDS:
         q = q384 if n == 384 else resample_periodic(q384, n, n)
         maps = round_f32(model_scales(c0, rho0) * q)
         src, fv = surface_sources(n, nsrc)
@@ -182,7 +182,7 @@ def config2(nsrc=64):
     return out
 
 
-def config3(n=512, dx=5.0, nsrc=32, nrec=101, freqs=(5.0, 8.0)):
+def vti512_jacobian(n=512, dx=5.0, nsrc=32, nrec=101, freqs=(5.0, 8.0)):
     """J / J* workload: reference contrast, perturbation, data and FD direction."""
     c0, rho0 = vti_background()
     qb = random_layered(3, n, n)
@@ -197,7 +197,7 @@ def config3(n=512, dx=5.0, nsrc=32, nrec=101, freqs=(5.0, 8.0)):
                 reg="laplacian", m0=model_scales(c0, rho0))
 
 
-def config4(n=1024, dx=5.0, nsrc=128, nrec=201, freqs=(4.0, 7.0, 10.0)):
+def vti1024_normal(n=1024, dx=5.0, nsrc=128, nrec=201, freqs=(4.0, 7.0, 10.0)):
     """Normal-equation CG workload: smooth background contrast and truth."""
     c0, rho0 = vti_background()
     qb = smooth_maps(7, n, n, 20, 0.08)
