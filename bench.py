@@ -159,6 +159,107 @@ def multigrid(a):
     return 0
 
 
+def _tik_plan(probs, rec, krylov, a):
+    from paper_2402_02116_amd.plan import Plan
+    plan = Plan([dict(nx=p["nx"], nz=p["nz"], dx=p["dx"], c0=p["c0"], rho0=p["rho0"], freq_hz=p["freq_hz"],
+                      eta=p["eta"], nsys=p["nsys"]) for p in probs], device="cuda:0")
+    for i, p in enumerate(probs):
+        plan.set_contrast(i, p["maps"])
+        plan.set_receivers(i, rec)
+    if krylov == "gmres":
+        plan.set_krylov("gmres", restart=a.restart, cgs2=not a.cgs1)
+    tuned = None if a.no_autotune else plan.autotune(reps=5)
+    return plan, tuned
+
+
+def jacobian(a):
+    """Differentiation workload: 512^2 VTI at 5 m, 32 surface forces x (5, 8) Hz =
+    64 systems, 101 receivers.  Times one J (m0 q), one J* r and one
+    Tikhonov loss + gradient (J and J* together, Laplacian regulariser)."""
+    import numpy as np
+    import torch
+    import workloads as W
+    w = W.vti512_jacobian()
+    probs, rec = w["problems"], w["rec_ixz"]
+    plan, tuned = _tik_plan(probs, rec, a.krylov, a)
+    src = sum((p["src_ixz"] for p in probs), [])
+    frc = sum((p["src_f"] for p in probs), [])
+    ub = plan.solve(plan.incident(src, frc), rtol=RTOL, maxit=2000).x
+    m0v = w["m0"].ravel()
+    q = torch.as_tensor(w["dq"], dtype=torch.float32).cuda()
+    r = torch.as_tensor(np.concatenate([x.ravel() for x in w["r"]]).astype(np.complex64)).cuda()
+    cells = np.array(sum(([p["nx"] * p["nz"]] * p["nsys"] for p in probs), []))
+    per = 1 if a.krylov == "gmres" else 2
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) * 1e3, int(np.sum((per * plan.solve_stats()[0] + 1) * cells))
+
+    for _ in range(a.warmup):
+        plan.tikhonov_grad(ub, r, m0v, q, lam=w["lam"], reg=w["reg"], rtol=RTOL)
+    tj, pj = zip(*[timed(lambda: plan.frechet_rel(ub, q, m0v, rtol=RTOL)) for _ in range(a.steps)])
+    ta, pa = zip(*[timed(lambda: plan.adjoint_rel(ub, r, m0v, rtol=RTOL)) for _ in range(a.steps)])
+    tg = [timed(lambda: plan.tikhonov_grad(ub, r, m0v, q, lam=w["lam"], reg=w["reg"], rtol=RTOL))[0]
+          for _ in range(a.steps)]
+    ms = float(np.median(tg))
+    pts = (np.median(pj) + np.median(pa)) / ms * 1e3 / 1e9
+    out = dict(metric=METRIC, value=round(float(pts), 3), unit="GPoints/s", n_gpus=1, steps=a.steps,
+               warmup=a.warmup, ms_per_step=round(ms, 3), higher_is_better=True, scaling="weak", vs_baseline=None,
+               dtype="c64", data="synthetic",
+               config=dict(workload="512x512 VTI (dx 5 m), 32 surface forces x (5, 8) Hz, 101 receivers: "
+                                    "Tikhonov loss + gradient (J and J*, Laplacian, lambda 1e-3) to 1e-6",
+                           nsys=int(len(src)), rtol=RTOL),
+               ms_per_J=round(float(np.median(tj)), 3), ms_per_Jstar=round(float(np.median(ta)), 3),
+               ms_per_gradient=round(ms, 3), krylov=a.krylov, autotune=tuned)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def normal_cg(a):
+    """Full linear DBI step: 1024^2 VTI at 5 m, 128 surface forces x (4, 7, 10) Hz =
+    384 systems, 201 receivers; data r = J dq* (linearised about the smooth
+    background); CG on the Tikhonov normal equation (L = I, lambda 1e-3).  Times
+    one CG iteration as the difference of 2 and 1 iterations."""
+    import numpy as np
+    import torch
+    import workloads as W
+    w = W.vti1024_normal()
+    probs, rec = w["problems"], w["rec_ixz"]
+    plan, tuned = _tik_plan(probs, rec, a.krylov, a)
+    src = sum((p["src_ixz"] for p in probs), [])
+    frc = sum((p["src_f"] for p in probs), [])
+    t0 = time.perf_counter()
+    ub = plan.solve(plan.incident(src, frc), rtol=RTOL, maxit=2000).x
+    torch.cuda.synchronize()
+    t_ub = time.perf_counter() - t0
+    print(f"[bench] background solve of {len(src)} systems: {t_ub:.2f} s", file=sys.stderr, flush=True)
+    m0v = w["m0"].ravel()
+    r = plan.frechet_rel(ub, torch.as_tensor(w["dq_true"], dtype=torch.float32).cuda(), m0v, rtol=RTOL)
+    times = {}
+    for n in (1, 2):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, hist = plan.normal_cg(ub, r, m0v, niter=n, lam=w["lam"], reg=w["reg"], rtol=RTOL)
+        torch.cuda.synchronize()
+        times[n] = time.perf_counter() - t
+        print(f"[bench] normal CG, {n} iteration(s): {times[n]:.2f} s, residual history {hist}",
+              file=sys.stderr, flush=True)
+    it = times[2] - times[1]
+    out = dict(metric=METRIC, value=round(1.0 / it, 4), unit="CG iterations/s", n_gpus=1, steps=1, warmup=0,
+               ms_per_step=round(it * 1e3, 1), higher_is_better=True, scaling="weak", vs_baseline=None,
+               dtype="c64", data="synthetic",
+               config=dict(workload="1024x1024 VTI (dx 5 m), 128 surface forces x (4, 7, 10) Hz, 201 receivers: "
+                                    "one CG iteration of the Tikhonov normal equation (L = I, lambda 1e-3)",
+                           nsys=int(len(src)), rtol=RTOL),
+               s_background_solve=round(t_ub, 2), s_cg_1=round(times[1], 2), s_cg_2=round(times[2], 2),
+               krylov=a.krylov, autotune=tuned)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def cpu_baseline(c, rec, dm, r, nsample):
     """The oracle on the host cores, on `nsample` of the systems of one step."""
     import numpy as np
@@ -196,7 +297,7 @@ def main(argv=None):
     ap.add_argument("--restart", type=int, default=32, help="GMRES restart length (<= 32)")
     ap.add_argument("--cgs1", action="store_true", help="GMRES without the re-orthogonalisation pass")
     ap.add_argument("--cgs2", action="store_true", help="GMRES with the re-orthogonalisation pass")
-    ap.add_argument("--workload", choices=["vti256x16", "multigrid"], default="vti256x16")
+    ap.add_argument("--workload", choices=["vti256x16", "multigrid", "jacobian", "normal"], default="vti256x16")
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported (the path shards "
@@ -215,6 +316,10 @@ def main(argv=None):
         a.cgs1 = False
     if a.workload == "multigrid":
         return multigrid(a)
+    if a.workload == "jacobian":
+        return jacobian(a)
+    if a.workload == "normal":
+        return normal_cg(a)
     c, rec, dm_np, r_np = build_workload()
     nx, nz, ns = c["nx"], c["nz"], c["nsys"]
     cells = nx * nz

@@ -200,6 +200,16 @@ fwils_status fwils_apply_pass(fwils_plan plan, int32_t pass, const void* u, void
  * recursive relative residual ||r|| / ||rhs||.  Host arrays [sum nsys] or
  * NULL.  Synchronous. */
 fwils_status fwils_solve_stats(fwils_plan plan, int32_t* iters, double* relres);
+/* Per-system outcome of the most recent Krylov solve (host int32 [sum nsys]):
+ * FWILS_SYS_CONVERGED, _MAXIT (iteration limit), _BREAKDOWN (a Krylov scalar
+ * became exactly zero), _NONFINITE (NaN or overflow), _RUNNING (not finished,
+ * e.g. the call failed).  Synchronous. */
+#define FWILS_SYS_RUNNING 0
+#define FWILS_SYS_CONVERGED 1
+#define FWILS_SYS_MAXIT 2
+#define FWILS_SYS_BREAKDOWN 3
+#define FWILS_SYS_NONFINITE 4
+fwils_status fwils_solve_status(fwils_plan plan, int32_t* status);
 
 /* ---- Generalised Tikhonov step (eqs. obj, norm) ------------------------
  * Unknowns are relative maps q, float32 [5][nz][nx] on the device, with

@@ -75,6 +75,7 @@ SIGNATURES = {
     "fwils_adjoint_rel": (c_int32, [P, P, P, ctypes.POINTER(c_double), P, c_double, c_int32]),
     "fwils_laplacian": (c_int32, [P, P, P]),
     "fwils_solve_stats": (c_int32, [P, ctypes.POINTER(c_int32), ctypes.POINTER(c_double)]),
+    "fwils_solve_status": (c_int32, [P, ctypes.POINTER(c_int32)]),
     "fwils_autotune": (c_int32, [P, c_int32]),
     "fwils_gmres_workspace_size": (c_int32, [P, c_int32, ctypes.POINTER(c_size_t)]),
     "fwils_set_krylov": (c_int32, [P, c_int32, c_int32, c_uint32, P, c_size_t]),

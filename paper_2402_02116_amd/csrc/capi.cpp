@@ -225,7 +225,7 @@ hipError_t bicg_iteration(fwils_plan pl, const ProbHost& P, const SysView& V, in
     SysState* st = pl->state + V.soff;
     double *pV = pl->partV + V.poff_row, *pT = pl->partT + V.poff_row, *pXR = pl->partXR + V.poff_vec;
     const float* maps = maps_at(pl, P);
-    const StencilArgs ap{r, pold, v, pnew, tmp, maps, pXR, P.np_vec};
+    const StencilArgs ap{r, pold, v, pnew, tmp, maps, pXR, P.np_vec, rh};
     const KernelCfg& k = P.cfg;
     hipError_t e = launch_stencil(1, k.st, ap, V.d, st, s);
     if (e == hipSuccess) e = launch_rows_fwd(V.d.nx, k.row_p, tmp, tmp, rows, 2 * V.d.nz, st, pl->tw, s);
@@ -1208,6 +1208,26 @@ fwils_status fwils_apply_pass(fwils_plan plan, int32_t pass, const void* u, void
                 FW_HIP(launch_rows_inv(P.p.nx, P.cfg.row_p, EPI_APPLY, tmp, at(u, P), nullptr,
                                        static_cast<float2*>(Au) + P.field_off, nullptr, rows, 2 * P.p.nz,
                                        nullptr, plan->tw, s));
+        }
+    }
+    return FWILS_OK;
+}
+
+fwils_status fwils_solve_status(fwils_plan plan, int32_t* status) {
+    FW_TRY(check_plan(plan));
+    if (!status) {
+        set_error("solve_status: null output");
+        return FWILS_EINVAL;
+    }
+    FW_HIP(hipStreamSynchronize(plan->stream));
+    FW_HIP(hipMemcpy(plan->host_state, plan->state, plan->total_sys * sizeof(SysState), hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < plan->total_sys; ++i) {
+        switch (plan->host_state[i].status) {
+            case ST_CONVERGED: status[i] = FWILS_SYS_CONVERGED; break;
+            case ST_MAXIT: status[i] = FWILS_SYS_MAXIT; break;
+            case ST_BREAKDOWN: status[i] = FWILS_SYS_BREAKDOWN; break;
+            case ST_NONFINITE: status[i] = FWILS_SYS_NONFINITE; break;
+            default: status[i] = FWILS_SYS_RUNNING; break;
         }
     }
     return FWILS_OK;

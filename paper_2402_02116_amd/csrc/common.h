@@ -59,10 +59,13 @@ struct SysState {
     double bnorm2;                 // ||b||^2
     double tol2;                   // rtol^2 ||b||^2
     double rnorm2;                 // last recursive ||r||^2 seen by a check
+    double best2;                  // smallest recursive ||r||^2 at a check
     int iter;                      // completed iterations
     int status;                    // SysStatus
     int maxit;
     int restarts;                  // restarts from the true residual so far
+    int best_iter;                 // iteration of best2
+    int fresh_at;                  // iteration that restarts with r^ = r (0: none)
 };
 
 // ------------------------------------------------------ block reductions --

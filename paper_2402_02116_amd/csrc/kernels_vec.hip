@@ -14,6 +14,7 @@ namespace fw {
 constexpr int kVecThreads = 256;
 constexpr int kVecEPT = 4;   // complex elements per thread in vector kernels
 constexpr double kOmegaLimit = 0.7;
+constexpr int kStallIters = 150;   // iterations without halving ||r|| before a restart
 
 // ------------------------------------------------------ contrast stencil --
 // A block owns a TZ x TX tile of cells and loops over S systems of the same
@@ -53,7 +54,8 @@ __global__ __launch_bounds__(256) void k_body_force(const float2* __restrict__ u
                                                     float2* __restrict__ b,
                                                     const float* __restrict__ maps, ProbDev pd,
                                                     int S, SysState* __restrict__ st,
-                                                    const double* __restrict__ part, int np) {
+                                                    const double* __restrict__ part, int np,
+                                                    float2* __restrict__ rhat) {
     static_assert(TX <= 64 && TZ % 4 == 0, "tile");
     constexpr int HX = TX + 4, HZ = TZ + 4, SX = TX + 2, SZ = TZ + 2;
     constexpr int KS = (SZ + 3) / 4;     // stress rows per thread
@@ -97,6 +99,7 @@ __global__ __launch_bounds__(256) void k_body_force(const float2* __restrict__ u
     for (int sys = sys0; sys < sys0 + S && sys < pd.nsys; ++sys) {
         if (st != nullptr && st[sys].status != ST_RUNNING) continue;   // uniform over the block
         float2 c1 = make_float2(0.f, 0.f), c2 = make_float2(0.f, 0.f);
+        bool fresh = false;
         if constexpr (VM != VM_NONE) {
             double q[4];
             sum_partials<4, 256>(part + (size_t)sys * np * kPartialNV, np, q, red);
@@ -105,15 +108,20 @@ __global__ __launch_bounds__(256) void k_body_force(const float2* __restrict__ u
             const int it = z.iter + 1;
             if constexpr (VM == VM_P) {
                 if (bicg_stop(st, sys, q[2], writer)) continue;
-                const dcomplex rho_i{q[0], q[1]};
+                dcomplex rho_i{q[0], q[1]};
                 const dcomplex rho_prev{z.rho_re[(it - 1) & 1], z.rho_im[(it - 1) & 1]};
                 const dcomplex alpha{z.alpha_re, z.alpha_im}, omega{z.omega_re, z.omega_im};
-                if (zzero(rho_i) || zzero(rho_prev) || zzero(omega)) {
-                    if (writer) st[sys].status = ST_BREAKDOWN;
-                    continue;
+                // Restart of the recurrence from the current iterate: scheduled
+                // after a stagnation, or forced by a zero scalar (which would
+                // otherwise break the iteration down): r^ = r, p = r.
+                fresh = (z.fresh_at == it) || zzero(rho_i) || zzero(rho_prev) || zzero(omega);
+                if (fresh) {
+                    rho_i = dcomplex{q[2], 0.0};   // <r, r>
+                    c1 = make_float2(0.f, 0.f);
+                } else {
+                    const dcomplex beta = zmul(zdiv(rho_i, rho_prev), zdiv(alpha, omega));
+                    c1 = make_float2((float)beta.re, (float)beta.im);
                 }
-                const dcomplex beta = zmul(zdiv(rho_i, rho_prev), zdiv(alpha, omega));
-                c1 = make_float2((float)beta.re, (float)beta.im);
                 c2 = make_float2((float)omega.re, (float)omega.im);
                 if (writer) {
                     st[sys].rho_re[it & 1] = rho_i.re;
@@ -141,7 +149,9 @@ __global__ __launch_bounds__(256) void k_body_force(const float2* __restrict__ u
             if constexpr (VM == VM_NONE) {
                 return u[so + gi];
             } else if constexpr (VM == VM_P) {
-                const float2 pv = a1[so + gi], vv = a2[so + gi], rv = u[so + gi];
+                const float2 rv = u[so + gi];
+                if (fresh) return rv;
+                const float2 pv = a1[so + gi], vv = a2[so + gi];
                 return cadd(rv, cmul(c1, csub(pv, cmul(c2, vv))));
             } else {
                 return csub(u[so + gi], cmul(c1, a1[so + gi]));
@@ -160,6 +170,12 @@ __global__ __launch_bounds__(256) void k_body_force(const float2* __restrict__ u
                     if (hz >= 2 && hz < TZ + 2) {     // the tile's own cells
                         wout[so + row + x0 + tx] = f0;
                         wout[so + plane + row + x0 + tx] = f1;
+                        if constexpr (VM == VM_P) {
+                            if (fresh) {              // p = r here
+                                rhat[so + row + x0 + tx] = f0;
+                                rhat[so + plane + row + x0 + tx] = f1;
+                            }
+                        }
                     }
                 }
             }
@@ -253,7 +269,7 @@ static void body_force_launch(const StCfg& c, const StencilArgs& a, const ProbDe
     S = std::min(S, std::max(pd.nsys, 1));
     const int blocks = ntiles * ((pd.nsys + S - 1) / S);
     hipLaunchKernelGGL((k_body_force<TX, TZ, VM>), dim3(blocks), dim3(256), 0, s, a.u, a.a1, a.a2, a.wout,
-                       a.b, a.maps, pd, S, st, a.part, a.np);
+                       a.b, a.maps, pd, S, st, a.part, a.np, a.rhat);
 }
 
 template <int TX, int TZ>
@@ -274,7 +290,8 @@ static void body_force_tz(int vm, const StCfg& c, const StencilArgs& a, const Pr
 
 hipError_t launch_stencil(int vm, const StCfg& c, const StencilArgs& a, const ProbDev& pd, SysState* st,
                           hipStream_t s) {
-    if (!st_cfg_ok(pd.nx, pd.nz, c) || vm < 0 || vm > 2 || (vm != 0 && !st)) return hipErrorInvalidValue;
+    if (!st_cfg_ok(pd.nx, pd.nz, c) || vm < 0 || vm > 2 || (vm != 0 && !st) || (vm == VM_P && !a.rhat))
+        return hipErrorInvalidValue;
     switch (tile_x(pd.nx)) {
         case 64: body_force_tz<64>(vm, c, a, pd, st, s); break;
         case 48: body_force_tz<48>(vm, c, a, pd, st, s); break;
@@ -389,6 +406,9 @@ __global__ __launch_bounds__(256) void k_bicg_state_init(SysState* __restrict__ 
         z.iter = 0;
         z.maxit = maxit;
         z.restarts = 0;
+        z.best2 = q[2];
+        z.best_iter = 0;
+        z.fresh_at = 0;
         z.status = (s[0] == 0.0) ? ST_CONVERGED : ST_RUNNING;
         st[sys] = z;
     }
@@ -479,8 +499,19 @@ __global__ __launch_bounds__(256) void k_bicg_check(SysState* __restrict__ st,
     double q[4];
     sum_partials<4, 256>(partXR + (size_t)sys * np * kPartialNV, np, q, red);
     if (threadIdx.x == 0) {
-        st[sys].rnorm2 = q[2];
-        bicg_stop(st, sys, q[2], true);
+        SysState& z = st[sys];
+        z.rnorm2 = q[2];
+        if (bicg_stop(st, sys, q[2], true)) return;
+        // stagnation: the best residual norm has not halved for kStallIters
+        // iterations -> the next iteration restarts the recurrence (r^ = r)
+        if (q[2] < 0.25 * z.best2) {
+            z.best2 = q[2];
+            z.best_iter = z.iter;
+        } else if (z.iter - z.best_iter >= kStallIters) {
+            z.fresh_at = z.iter + 1;
+            z.best2 = q[2];
+            z.best_iter = z.iter;
+        }
     }
 }
 
@@ -499,18 +530,23 @@ __global__ __launch_bounds__(256) void k_bicg_finish(const SysState* __restrict_
     }
 }
 
-// After a solve: a system that converged on its recursive residual but whose
-// true residual ||b - A x||^2 (partials partTR) exceeds limit2 ||b||^2 is
-// marked ST_RESTART (at most max_restarts times).
+// After a solve, systems are restarted from their current x (r = b - A x in
+// partTR, fresh shadow residual r^ = r), at most max_restarts times each:
+//   - converged on the recursive residual while the true residual ||b - A x||^2
+//     exceeds limit2 ||b||^2 (the recursion drifted in finite precision);
+//   - broken down (a BiCGSTAB scalar became exactly zero): x is the last
+//     completed iterate, so restarting with r^ = r resumes the solve.
 __global__ __launch_bounds__(256) void k_bicg_restart_mark(SysState* __restrict__ st,
                                                            const double* __restrict__ partTR, int np,
                                                            double limit2, int max_restarts) {
     __shared__ double red[4 * 4];
     const int sys = blockIdx.x;
-    if (st[sys].status != ST_CONVERGED) return;
+    const int status = st[sys].status;
+    if (status != ST_CONVERGED && status != ST_BREAKDOWN) return;
     double q[4];
     sum_partials<4, 256>(partTR + (size_t)sys * np * kPartialNV, np, q, red);
-    if (threadIdx.x == 0 && q[0] > limit2 * st[sys].bnorm2 && st[sys].restarts < max_restarts) {
+    if (threadIdx.x == 0 && st[sys].restarts < max_restarts &&
+        (status == ST_BREAKDOWN || q[0] > limit2 * st[sys].bnorm2)) {
         st[sys].status = ST_RESTART;
         st[sys].restarts += 1;
     }
@@ -526,6 +562,9 @@ __global__ void k_bicg_restart(SysState* __restrict__ st, int nsys) {
     z.rho_im[0] = z.rho_im[1] = 0.0;
     z.alpha_re = z.omega_re = 1.0;
     z.alpha_im = z.omega_im = 0.0;
+    z.best2 = 1e300;
+    z.best_iter = z.iter;
+    z.fresh_at = 0;
     z.status = (z.iter >= z.maxit) ? ST_MAXIT : ST_RUNNING;
 }
 

@@ -105,6 +105,7 @@ struct StencilArgs {
     const float* maps;
     const double* part;
     int np;
+    float2* rhat = nullptr;   // vm 1: shadow residual, set to r when the iteration restarts
 };
 hipError_t launch_stencil(int vm, const StCfg& c, const StencilArgs& a, const ProbDev& pd, SysState* st,
                           hipStream_t s);

@@ -269,6 +269,15 @@ class Plan:
               "fwils_solve_stats")
         return it, rr
 
+    SYS_STATUS = {0: "running", 1: "converged", 2: "maxit", 3: "breakdown", 4: "nonfinite"}
+
+    def solve_status(self):
+        """Per-system outcome of the last Krylov solve (names of SYS_STATUS)."""
+        st = np.zeros(self.total_sys, dtype=np.int32)
+        check(self.lib.fwils_solve_status(self._h, st.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))),
+              "fwils_solve_status")
+        return [self.SYS_STATUS.get(int(v), "?") for v in st]
+
     # ------------------------------------------------- Tikhonov step ----
     REGS = {"identity": _lib.FWILS_REG_IDENTITY, "laplacian": _lib.FWILS_REG_LAPLACIAN}
 
