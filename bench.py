@@ -26,6 +26,7 @@ import json
 import os
 import sys
 import time
+from types import SimpleNamespace
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
@@ -46,28 +47,92 @@ PASS_BYTES = [32.0, 32.0, 32.0, 48.0]
 MAP_BYTES_PER_CELL = 20.0
 
 
+CSRC = os.path.join(ROOT, "paper_2402_02116_amd", "csrc")
+COUNTERS = os.path.join(ROOT, "profiles", "counters_vti256x16.json")
+
+
 def _kernel_source_hash():
+    """Hash of every kernel source: counter summaries taken on other sources are stale."""
     h = hashlib.sha256()
-    for f in ("fft.h", "common.h", "kernels_fft.hip", "kernels_vec.hip"):
-        with open(os.path.join(ROOT, "paper_2402_02116_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    for f in sorted(os.listdir(CSRC)):
+        if f.endswith((".h", ".hip", ".cpp")):
+            with open(os.path.join(CSRC, f), "rb") as fh:
+                h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
 
 
-def _traffic_from_profiles(kernel_pass, launch_cells):
+# kernel-name test of each pass (template arguments vary with the tuned variant)
+PASS_MATCH = [lambda n: n.startswith("void fw::k_body_force<") and ", 0>(" in n,
+              lambda n: n.startswith("void fw::k_rows<") and ", false, 0>" in n,
+              lambda n: n.startswith("void fw::k_cols<") and ", 0, " in n,
+              lambda n: n.startswith("void fw::k_rows<") and ", true, 1>" in n]
+
+
+def summarize_counters(fetch_csv, write_csv, cmd):
+    """profiles/counters_vti256x16.json from two rocprofv3 --pmc runs of
+    `bench.py --passes-only` (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch).
+    Each counter is scaled by what it reads for the 1 GiB device copy that the
+    same run ends with (2 x 512 MiB moved: read 1 GiB, write 1 GiB)."""
+    import csv
+    import statistics
+
+    def per_kernel(path, counter):
+        out = {}
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            out.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return out
+
+    fetch, write = per_kernel(fetch_csv, "FETCH_SIZE"), per_kernel(write_csv, "WRITE_SIZE")
+    gib_kib = 1024.0 * 1024.0
+    # the largest copy dispatch is the 1 GiB device-to-device copy
+    copy_f = max((max(v) for n, v in fetch.items() if "copy" in n.lower()), default=None)
+    copy_w = max((max(v) for n, v in write.items() if "copy" in n.lower()), default=None)
+    sf, sw = gib_kib / copy_f, gib_kib / copy_w
+    passes = {}
+    for k, match in enumerate(PASS_MATCH):
+        inst = {}
+        for n in fetch:
+            if not match(n) or n not in write:
+                continue
+            f, w = statistics.median(fetch[n]), statistics.median(write[n])
+            inst[n.split("(")[0].replace("void ", "")] = dict(
+                fetch_kib=f, write_kib=w, launches=len(fetch[n]), hbm_bytes_per_launch=(f * sf + w * sw) * 1024.0)
+        if inst:
+            passes[str(k)] = dict(kernel=PASS_NAMES[k], instances=inst)
+    out = dict(source_hash=_kernel_source_hash(), command=cmd, fetch_scale=sf, write_scale=sw,
+               copy_fetch_kib=copy_f, copy_write_kib=copy_w, passes=passes)
+    with open(COUNTERS, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out, indent=1))
+    return 0
+
+
+def _pass_instance(k, tuning, n=256):
+    """Kernel instance of pass k on an n^2 grid under the plan's variants."""
+    if k == 0:
+        return f"fw::k_body_force<64, {tuning['stencil_rows']}, 0>"
+    if k == 1:
+        return f"fw::k_rows<{n}, {tuning['row_points']}, false, 0>"
+    if k == 2:
+        seq = "true" if tuning["col_shared"] else "false"
+        return f"fw::k_cols<{n}, {tuning['col_points']}, 0, {seq}>"
+    return f"fw::k_rows<{n}, {tuning['row_points']}, true, 1>"
+
+
+def _traffic_from_profiles(kernel_pass, tuning):
     """HBM bytes per launch from the committed counter summary, or None when the
-    kernels changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "counters_vti256x16.json")
+    kernels (sources or the chosen variant) differ from those the counters saw."""
+    path = COUNTERS
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         c = json.load(fh)
     if c.get("source_hash") != _kernel_source_hash():
         return None
-    ent = c.get("passes", {}).get(str(kernel_pass))
-    if not ent:
-        return None
-    return float(ent["hbm_bytes_per_launch"])
+    ent = c.get("passes", {}).get(str(kernel_pass), {}).get("instances", {}).get(_pass_instance(kernel_pass, tuning))
+    return None if not ent else float(ent["hbm_bytes_per_launch"])
 
 
 def build_workload():
@@ -298,7 +363,14 @@ def main(argv=None):
     ap.add_argument("--cgs1", action="store_true", help="GMRES without the re-orthogonalisation pass")
     ap.add_argument("--cgs2", action="store_true", help="GMRES with the re-orthogonalisation pass")
     ap.add_argument("--workload", choices=["vti256x16", "multigrid", "jacobian", "normal"], default="vti256x16")
+    ap.add_argument("--passes-only", action="store_true",
+                    help="only the per-pass kernel launches and the 1 GiB copy (for counter runs)")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/counters_vti256x16.json from two rocprofv3 --pmc runs")
+    ap.add_argument("--counter-command", default="", help="the rocprofv3 command, recorded in the summary")
     a = ap.parse_args(argv)
+    if a.summarize_counters:
+        return summarize_counters(a.summarize_counters[0], a.summarize_counters[1], a.counter_command)
     if a.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported (the path shards "
               f"independent (source, frequency) systems across GPUs, one process per GPU)", file=sys.stderr)
@@ -339,54 +411,57 @@ def main(argv=None):
     dm = torch.as_tensor(dm_np).cuda()
     r = torch.as_tensor(r_np.ravel()).cuda()
 
-    def step():
+    if a.passes_only:
+        tbr = SimpleNamespace(x=plan.incident(c["src_ixz"], c["src_f"]))
+    else:
+        def step():
+            u0 = plan.incident(c["src_ixz"], c["src_f"])
+            res = plan.solve(u0, rtol=RTOL, maxit=1000)
+            n1 = int(np.sum(mv_per_iter * res.iters + 1))
+            plan.frechet(res.x, [dm], rtol=RTOL)
+            n2 = int(np.sum(mv_per_iter * plan.solve_stats()[0] + 1))
+            plan.adjoint(res.x, r, rtol=RTOL)
+            n3 = int(np.sum(mv_per_iter * plan.solve_stats()[0] + 1))
+            return n1 + n2 + n3
+
+        for _ in range(a.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mv = 0
+        for _ in range(a.steps):
+            mv += step()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ms_step = dt / a.steps * 1e3
+        value = mv * cells / dt / 1e9
+        print(f"[bench] {a.steps} steps: {ms_step:.3f} ms/step, {mv / a.steps:.0f} matvecs/step, "
+              f"{value:.2f} GPoints/s sustained", file=sys.stderr, flush=True)
+
+        # time-to-1e-6: batched graph solve vs plain per-source solve
         u0 = plan.incident(c["src_ixz"], c["src_f"])
-        res = plan.solve(u0, rtol=RTOL, maxit=1000)
-        n1 = int(np.sum(mv_per_iter * res.iters + 1))
-        plan.frechet(res.x, [dm], rtol=RTOL)
-        n2 = int(np.sum(mv_per_iter * plan.solve_stats()[0] + 1))
-        plan.adjoint(res.x, r, rtol=RTOL)
-        n3 = int(np.sum(mv_per_iter * plan.solve_stats()[0] + 1))
-        return n1 + n2 + n3
-
-    for _ in range(a.warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    mv = 0
-    for _ in range(a.steps):
-        mv += step()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ms_step = dt / a.steps * 1e3
-    value = mv * cells / dt / 1e9
-    print(f"[bench] {a.steps} steps: {ms_step:.3f} ms/step, {mv / a.steps:.0f} matvecs/step, "
-          f"{value:.2f} GPoints/s sustained", file=sys.stderr, flush=True)
-
-    # time-to-1e-6: batched graph solve vs plain per-source solve
-    u0 = plan.incident(c["src_ixz"], c["src_f"])
-    def timed_solve(**kw):
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        res = plan.solve(u0, rtol=RTOL, maxit=1000, **kw)
-        torch.cuda.synchronize()
-        return (time.perf_counter() - t) * 1e3, res
-    plain_krylov = a.krylov
-    for _ in range(2):
-        timed_solve()
-    tb = sorted(timed_solve()[0] for _ in range(5))
-    tbr = timed_solve()[1]
-    if a.krylov == "gmres":   # the per-source plain loop is BiCGSTAB's
-        plan.set_krylov("bicgstab")
-        plain_krylov = "bicgstab"
-    for _ in range(2):
-        timed_solve(plain=True)
-    tp = sorted(timed_solve(plain=True)[0] for _ in range(3))
-    tpr = timed_solve(plain=True)[1]
-    same = bool(torch.equal(tbr.x, tpr.x))
-    print(f"[bench] time to 1e-6: batched {tb[len(tb) // 2]:.3f} ms, plain {tp[len(tp) // 2]:.3f} ms, "
-          f"iters {tbr.iters.min()}-{tbr.iters.max()}, max true relres {tbr.relres.max():.2e}, "
-          f"identical results {same}", file=sys.stderr, flush=True)
+        def timed_solve(**kw):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            res = plan.solve(u0, rtol=RTOL, maxit=1000, **kw)
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t) * 1e3, res
+        plain_krylov = a.krylov
+        for _ in range(2):
+            timed_solve()
+        tb = sorted(timed_solve()[0] for _ in range(5))
+        tbr = timed_solve()[1]
+        if a.krylov == "gmres":   # the per-source plain loop is BiCGSTAB's
+            plan.set_krylov("bicgstab")
+            plain_krylov = "bicgstab"
+        for _ in range(2):
+            timed_solve(plain=True)
+        tp = sorted(timed_solve(plain=True)[0] for _ in range(3))
+        tpr = timed_solve(plain=True)[1]
+        same = bool(torch.equal(tbr.x, tpr.x))
+        print(f"[bench] time to 1e-6: batched {tb[len(tb) // 2]:.3f} ms, plain {tp[len(tp) // 2]:.3f} ms, "
+              f"iters {tbr.iters.min()}-{tbr.iters.max()}, max true relres {tbr.relres.max():.2e}, "
+              f"identical results {same}", file=sys.stderr, flush=True)
 
     # isolated batched matvec and its four kernels, HIP events on the plan's stream
     u = tbr.x
@@ -424,7 +499,7 @@ def main(argv=None):
                         for k in range(4)]
     gbs = [bytes_per_launch[k] / (t_pass[k] * 1e-3) / 1e9 for k in range(4)]
     dom = int(np.argmax(t_pass))
-    traffic = _traffic_from_profiles(dom, ns * cells)
+    traffic = _traffic_from_profiles(dom, plan.tuning(0))
     for k in range(4):
         print(f"[bench] pass {k} {PASS_NAMES[k]}: {t_pass[k] * 1e3:.2f} us/launch, "
               f"{gbs[k]:.0f} GB/s algorithmic", file=sys.stderr, flush=True)
@@ -442,6 +517,23 @@ def main(argv=None):
     print(f"[bench] device copy 1 GiB: {t_copy * 1e3:.1f} us, {copy_gbs:.0f} GB/s (read + write)",
           file=sys.stderr, flush=True)
 
+    if a.passes_only:
+        # every candidate variant of every pass, so that the counter summary
+        # covers whichever variant the autotuner picks in a timed run
+        chosen = plan.tuning(0)
+        for k, kind in enumerate(("stencil", "rows", "cols", "rows")):
+            for cand in plan.tuning_candidates(0, kind):
+                plan.set_tuning(0, **cand)
+                for j in range(k):
+                    plan.apply_pass(j, u, Au)
+                for _ in range(a.reps):
+                    plan.apply_pass(k, u, Au)
+        plan.set_tuning(0, **{f: chosen[f] for f in chosen if f != "time_us"})
+        torch.cuda.synchronize()
+        print(json.dumps(dict(passes_only=True, pass_us=[round(t * 1e3, 3) for t in t_pass],
+                              pass_gbs=[round(g, 1) for g in gbs], copy_gbs=round(copy_gbs, 1),
+                              tuning=plan.tuning(0))), flush=True)
+        return 0
     roof = dict(bound="hbm", kernel=PASS_NAMES[dom], achieved=round(gbs[dom], 1), peak=HBM_PEAK_GBS,
                 unit="GB/s", frac=round(gbs[dom] / HBM_PEAK_GBS, 4),
                 traffic=None if traffic is None else round(traffic, 1),

@@ -26,6 +26,13 @@ __device__ __forceinline__ float2 mul_mi(float2 z) {
 
 struct dcomplex { double re, im; };
 
+// Store of one complex value that writes through the L2 (system-coherent
+// policy): the kernel's output leaves no dirty L2 lines behind, so the cache
+// write-back at the kernel boundary has nothing to flush.
+__device__ __forceinline__ void st_wt(float2* p, float2 v) {
+    asm volatile("global_store_dwordx2 %0, %1, off sc0 sc1" ::"v"(p), "v"(v) : "memory");
+}
+
 // --------------------------------------------------------- problem consts --
 // Per-problem constants, passed by value to every kernel of that problem.
 struct ProbDev {

@@ -91,19 +91,19 @@ __global__ __launch_bounds__(256) void k_rows(const float2* in, float2* out,
             const size_t i = base + t + T * m;
             const float2 y = v[0][m];
             if constexpr (EPI == EPI_STORE) {
-                out[i] = y;
+                st_wt(out + i, y);
             } else {
                 const float2 uu = u[i];
                 const float2 o = csub(uu, y);
                 if constexpr (EPI == EPI_APPLY) {
-                    out[i] = o;
+                    st_wt(out + i, o);
                 } else if constexpr (EPI == EPI_BICG_V) {
-                    out[i] = o;
+                    st_wt(out + i, o);
                     const float2 a = aux[i];
                     acc[0] += (double)a.x * o.x + (double)a.y * o.y;
                     acc[1] += (double)a.x * o.y - (double)a.y * o.x;
                 } else if constexpr (EPI == EPI_BICG_T) {
-                    out[i] = o;
+                    st_wt(out + i, o);
                     acc[0] += (double)o.x * uu.x + (double)o.y * uu.y;
                     acc[1] += (double)o.x * uu.y - (double)o.y * uu.x;
                     acc[2] += (double)o.x * o.x + (double)o.y * o.y;
@@ -111,11 +111,11 @@ __global__ __launch_bounds__(256) void k_rows(const float2* in, float2* out,
                 } else if constexpr (EPI == EPI_TRUERES || EPI == EPI_GMRES_R0) {
                     const float2 b = aux[i];
                     const float2 rr = csub(b, o);
-                    out[i] = rr;
+                    st_wt(out + i, rr);
                     acc[0] += (double)rr.x * rr.x + (double)rr.y * rr.y;
                     if constexpr (EPI == EPI_GMRES_R0) acc[1] += (double)b.x * b.x + (double)b.y * b.y;
                 } else if constexpr (EPI == EPI_ARNOLDI) {
-                    out[i] = o;
+                    st_wt(out + i, o);
                     v[0][m] = o;   // kept for the projections below
                 }
             }
@@ -288,7 +288,7 @@ __global__ __launch_bounds__(512) void k_cols(float2* __restrict__ data, ProbDev
 #pragma unroll
         for (int f = 0; f < 2; ++f)
 #pragma unroll
-            for (int m = 0; m < P; ++m) base[f * plane + (size_t)(t + T * m) * nx] = v[f][m];
+            for (int m = 0; m < P; ++m) st_wt(base + f * plane + (size_t)(t + T * m) * nx, v[f][m]);
     }
 }
 

@@ -168,8 +168,8 @@ __global__ __launch_bounds__(256) void k_body_force(const float2* __restrict__ u
                 su[1][hz][tx + 2] = f1;
                 if constexpr (VM != VM_NONE) {
                     if (hz >= 2 && hz < TZ + 2) {     // the tile's own cells
-                        wout[so + row + x0 + tx] = f0;
-                        wout[so + plane + row + x0 + tx] = f1;
+                        st_wt(wout + so + row + x0 + tx, f0);
+                        st_wt(wout + so + plane + row + x0 + tx, f1);
                         if constexpr (VM == VM_P) {
                             if (fresh) {              // p = r here
                                 rhat[so + row + x0 + tx] = f0;
@@ -220,8 +220,8 @@ __global__ __launch_bounds__(256) void k_body_force(const float2* __restrict__ u
                 const float2 dz3 = csub(ss[1][sz + 1][sx], ss[1][sz - 1][sx]);
                 const float2 wr = cscale(pd.w2, rho[k]);
                 const size_t gi = (size_t)(z0 + lz) * nx + x0 + tx;
-                bs[gi] = cadd(cmul(wr, su[0][lz + 2][tx + 2]), cscale(cadd(dx1, dz5), sc));
-                bs[plane + gi] = cadd(cmul(wr, su[1][lz + 2][tx + 2]), cscale(cadd(dx5, dz3), sc));
+                st_wt(bs + gi, cadd(cmul(wr, su[0][lz + 2][tx + 2]), cscale(cadd(dx1, dz5), sc)));
+                st_wt(bs + plane + gi, cadd(cmul(wr, su[1][lz + 2][tx + 2]), cscale(cadd(dx5, dz3), sc)));
             }
         }
     }
@@ -467,9 +467,9 @@ __global__ __launch_bounds__(256) void k_bicg_xr(float2* __restrict__ x, float2*
         const int i = vi.i0 + e * kVecThreads + threadIdx.x;
         if (i < n) {
             const float2 sv_ = sv[off + i], tv = t[off + i];
-            x[off + i] = cadd(x[off + i], cadd(cmul(af, p[off + i]), cmul(of, sv_)));
+            st_wt(x + off + i, cadd(x[off + i], cadd(cmul(af, p[off + i]), cmul(of, sv_))));
             const float2 rn = csub(sv_, cmul(of, tv));
-            r[off + i] = rn;
+            st_wt(r + off + i, rn);
             const float2 h = rhat[off + i];
             acc[0] += (double)h.x * rn.x + (double)h.y * rn.y;
             acc[1] += (double)h.x * rn.y - (double)h.y * rn.x;
