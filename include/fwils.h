@@ -272,9 +272,11 @@ fwils_status fwils_fft2(fwils_plan plan, int32_t iprob, const void* in, void* ou
  * re-orthogonalisation pass (or one pass with FWILS_GMRES_CGS1) and the
  * Hessenberg least-squares problem solved by Givens rotations in FP64.
  * GMRES stops a cycle when its residual estimate reaches rtol and accepts
- * a system only when the true residual ||b - A x|| / ||b|| of the next cycle
- * start is <= rtol; fwils_solve's iters count Arnoldi steps (one matvec
- * each; a BiCGSTAB iteration is two).  FWILS_SOLVE_PLAIN is BiCGSTAB only. */
+ * a system when the true residual ||b - A x|| / ||b|| at the next cycle start
+ * is <= rtol, or <= 2 rtol after a cycle that reached rtol on its estimate
+ * (BiCGSTAB likewise accepts a recursive residual <= rtol with a true one
+ * <= 2 rtol); fwils_solve's iters count Arnoldi steps (one matvec each; a
+ * BiCGSTAB iteration is two).  FWILS_SOLVE_PLAIN is BiCGSTAB only. */
 #define FWILS_KRYLOV_BICGSTAB 0
 #define FWILS_KRYLOV_GMRES 1
 #define FWILS_GMRES_CGS1 0x1u

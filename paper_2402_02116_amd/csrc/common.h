@@ -160,7 +160,7 @@ struct GmSys {
     int j;                                          // Arnoldi steps of the current cycle
     int m;                                          // restart length
     int cycles;
-    int pad;
+    int est_conv;                                   // the cycle ended on its residual estimate
 };
 
 // Workgroup ids are dealt to the 8 XCDs round-robin (id % 8).  Remap so that

@@ -47,6 +47,7 @@ __global__ void k_gm_init(SysState* __restrict__ st, GmSys* __restrict__ gs, int
     gs[sys].j = 0;
     gs[sys].m = m;
     gs[sys].cycles = 0;
+    gs[sys].est_conv = 0;
 }
 
 // Start of a cycle, after r = b - A x was written to basis slot 0 with
@@ -60,8 +61,13 @@ __device__ void gm_begin(SysState& z, GmSys& g, double r2, double b2, double rto
     z.rnorm2 = r2;
     g.n2[0] = r2;
     g.j = 0;
+    // accepted when the true residual meets rtol, or 2 rtol after a cycle that
+    // met rtol on its own residual estimate (the finite-precision gap between
+    // the two, as for the recursive residual of BiCGSTAB)
+    const bool est = !first && g.est_conv;
+    g.est_conv = 0;
     if (!(r2 == r2) || r2 > 1e300) z.status = ST_NONFINITE;
-    else if (z.bnorm2 == 0.0 || r2 <= z.tol2) z.status = ST_CONVERGED;
+    else if (z.bnorm2 == 0.0 || r2 <= z.tol2 || (est && r2 <= 4.0 * z.tol2)) z.status = ST_CONVERGED;
     else if (z.iter >= z.maxit) z.status = ST_MAXIT;
     else {
         g.gre[0] = sqrt(r2);
@@ -147,7 +153,10 @@ __device__ void gm_hessenberg(SysState& z, GmSys& g, const double* tot1, const d
     const double res2 = g.gre[j + 1] * g.gre[j + 1] + g.gim[j + 1] * g.gim[j + 1];
     z.rnorm2 = res2;
     if (!(res2 == res2)) z.status = ST_NONFINITE;
-    else if (res2 <= z.tol2 || g.j == g.m || z.iter >= z.maxit || !(n2next > 0.0)) z.status = ST_CYCLE_DONE;
+    else if (res2 <= z.tol2 || g.j == g.m || z.iter >= z.maxit || !(n2next > 0.0)) {
+        z.status = ST_CYCLE_DONE;
+        g.est_conv = res2 <= z.tol2 ? 1 : 0;
+    }
 }
 
 // w <- w - sum_{l <= j} c_l w_l in basis slot j + 1, with c from tot (pass 1:
