@@ -62,7 +62,7 @@
 extern "C" {
 #endif
 
-#define FWILS_ABI_VERSION 3
+#define FWILS_ABI_VERSION 4
 
 typedef enum {
     FWILS_OK = 0,
@@ -296,7 +296,8 @@ fwils_status fwils_set_krylov(fwils_plan plan, int32_t method, int32_t restart, 
  * The batched schedule over uneven grids picks, per problem, one variant of
  * each hot kernel: the radix sequence of the row and column transforms
  * (points per thread), the column tile width and LDS sharing of the column
- * pass, and the contrast-stencil tile height and systems per workgroup.
+ * pass, the contrast-stencil tile height and systems per workgroup, and
+ * whether the stencil is fused into the forward row transform.
  * Every variant computes the same operator; different radix orders round
  * differently (fp32 rounding level).  A new plan starts from built-in
  * defaults.  Changing a problem's variants drops the plan's cached graph. */
@@ -307,13 +308,18 @@ typedef struct {
     int32_t col_shared;    /* 1: the two components share one LDS buffer */
     int32_t stencil_rows;  /* contrast-stencil tile height: 4, 8 or 16 */
     int32_t stencil_sys;   /* systems per stencil workgroup, 0 = from the grid size */
-    float time_us[3];      /* autotuner's time of the chosen stencil, row and column
-                              kernel over all systems of the problem (0 if not tuned) */
+    int32_t fused_points;  /* 0: contrast stencil and forward row transform as two
+                              kernels; else one fused kernel with this many points
+                              per thread (rows of at most 512 points) */
+    float time_us[4];      /* autotuner's time of the chosen stencil, row, column and
+                              stencil + row kernels over all systems of the problem
+                              (0 if not tuned) */
 } fwils_tuning;
 
 #define FWILS_TUNE_STENCIL 0
 #define FWILS_TUNE_ROWS 1
 #define FWILS_TUNE_COLS 2
+#define FWILS_TUNE_FUSE 3
 
 /* Time every candidate variant of each kernel kind on the plan's workspace
  * (which must be set; its field vectors are overwritten), reps launches each

@@ -32,9 +32,10 @@ class FwilsProblem(ctypes.Structure):
 class FwilsTuning(ctypes.Structure):
     _fields_ = [("row_points", c_int32), ("col_points", c_int32), ("col_width", c_int32),
                 ("col_shared", c_int32), ("stencil_rows", c_int32), ("stencil_sys", c_int32),
-                ("time_us", ctypes.c_float * 3)]
+                ("fused_points", c_int32), ("time_us", ctypes.c_float * 4)]
 
-    FIELDS = ("row_points", "col_points", "col_width", "col_shared", "stencil_rows", "stencil_sys")
+    FIELDS = ("row_points", "col_points", "col_width", "col_shared", "stencil_rows", "stencil_sys",
+              "fused_points")
 
     def to_dict(self):
         d = {k: int(getattr(self, k)) for k in self.FIELDS}
@@ -42,7 +43,7 @@ class FwilsTuning(ctypes.Structure):
         return d
 
 
-FWILS_TUNE_STENCIL, FWILS_TUNE_ROWS, FWILS_TUNE_COLS = 0, 1, 2
+FWILS_TUNE_STENCIL, FWILS_TUNE_ROWS, FWILS_TUNE_COLS, FWILS_TUNE_FUSE = 0, 1, 2, 3
 FWILS_KRYLOV_BICGSTAB, FWILS_KRYLOV_GMRES = 0, 1
 FWILS_GMRES_CGS1 = 0x1
 

@@ -20,7 +20,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfwils.so")
 SOURCES = ["kernels_rows.hip", "kernels_cols.hip", "kernels_fft.hip", "kernels_vec.hip", "kernels_maps.hip",
-           "kernels_gmres.hip", "capi.cpp"]
+           "kernels_gmres.hip", "kernels_srows.hip", "capi.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -66,7 +66,7 @@ struct ProbHost {
     int np_rows;          // partial records per system from the row epilogues
     int np_vec;           // partial records per system from vector kernels
     KernelCfg cfg;        // kernel variants (defaults, the autotuner's or the caller's)
-    float tuned_us[3];    // autotune: stencil, row, column time of the choice
+    float tuned_us[4];    // autotune: stencil, row, column, stencil + rows time of the choice
 };
 
 }  // namespace
@@ -178,8 +178,14 @@ hipError_t matvec(fwils_plan pl, const ProbHost& P, const ProbDev& d, const floa
                   const SysState* st, hipStream_t s, const GmEpi* ge = nullptr) {
     const int rows = d.nsys * 2 * d.nz;
     const KernelCfg& k = P.cfg;
-    hipError_t e = launch_body_force(k.st, u, tmp, maps, d, st, s);
-    if (e == hipSuccess) e = launch_rows_fwd(d.nx, k.row_p, tmp, tmp, rows, 2 * d.nz, st, pl->tw, s);
+    hipError_t e = hipSuccess;
+    if (k.fuse_p) {
+        const StencilArgs a{u, nullptr, nullptr, nullptr, nullptr, maps, nullptr, 0};
+        e = launch_srows(0, k.fuse_p, a, tmp, d, const_cast<SysState*>(st), pl->tw, s);
+    } else {
+        e = launch_body_force(k.st, u, tmp, maps, d, st, s);
+        if (e == hipSuccess) e = launch_rows_fwd(d.nx, k.row_p, tmp, tmp, rows, 2 * d.nz, st, pl->tw, s);
+    }
     if (e == hipSuccess) e = launch_cols(COL_GREEN, k.col, tmp, d, st, pl->tw, s);
     if (e == hipSuccess)
         e = launch_rows_inv(d.nx, k.row_p, epi, tmp, u, aux, out, part, rows, 2 * d.nz, st, pl->tw, s, ge);
@@ -227,14 +233,20 @@ hipError_t bicg_iteration(fwils_plan pl, const ProbHost& P, const SysView& V, in
     const float* maps = maps_at(pl, P);
     const StencilArgs ap{r, pold, v, pnew, tmp, maps, pXR, P.np_vec, rh};
     const KernelCfg& k = P.cfg;
-    hipError_t e = launch_stencil(1, k.st, ap, V.d, st, s);
-    if (e == hipSuccess) e = launch_rows_fwd(V.d.nx, k.row_p, tmp, tmp, rows, 2 * V.d.nz, st, pl->tw, s);
+    // contrast stencil with the fused vector update, then the forward rows
+    // (one fused kernel, or two)
+    auto stencil_rows = [&](int vm, const StencilArgs& a) -> hipError_t {
+        if (k.fuse_p) return launch_srows(vm, k.fuse_p, a, tmp, V.d, st, pl->tw, s);
+        hipError_t r = launch_stencil(vm, k.st, a, V.d, st, s);
+        if (r == hipSuccess) r = launch_rows_fwd(V.d.nx, k.row_p, tmp, tmp, rows, 2 * V.d.nz, st, pl->tw, s);
+        return r;
+    };
+    hipError_t e = stencil_rows(1, ap);
     if (e == hipSuccess) e = launch_cols(COL_GREEN, k.col, tmp, V.d, st, pl->tw, s);
     if (e == hipSuccess)
         e = launch_rows_inv(V.d.nx, k.row_p, EPI_BICG_V, tmp, pnew, rh, v, pV, rows, 2 * V.d.nz, st, pl->tw, s);
     const StencilArgs as{r, v, nullptr, sv, tmp, maps, pV, P.np_rows};
-    if (e == hipSuccess) e = launch_stencil(2, k.st, as, V.d, st, s);
-    if (e == hipSuccess) e = launch_rows_fwd(V.d.nx, k.row_p, tmp, tmp, rows, 2 * V.d.nz, st, pl->tw, s);
+    if (e == hipSuccess) e = stencil_rows(2, as);
     if (e == hipSuccess) e = launch_cols(COL_GREEN, k.col, tmp, V.d, st, pl->tw, s);
     if (e == hipSuccess)
         e = launch_rows_inv(V.d.nx, k.row_p, EPI_BICG_T, tmp, sv, nullptr, t, pT, rows, 2 * V.d.nz, st, pl->tw,
@@ -614,7 +626,7 @@ fwils_status fwils_plan_create(const fwils_problem* probs, int32_t nprob, fwils_
         P.data_off = 0;
         P.nrec = 0;
         P.cfg = kernel_cfg_default(P.p.nx, P.p.nz);
-        P.tuned_us[0] = P.tuned_us[1] = P.tuned_us[2] = 0.f;
+        P.tuned_us[0] = P.tuned_us[1] = P.tuned_us[2] = P.tuned_us[3] = 0.f;
         P.np_rows = row_geom(P.p.nx, P.cfg.row_p, 2 * P.p.nz).blocks_per_sys;
         P.np_vec = vec_blocks_per_sys((int)P.n_per_sys);
         pl->max_np = std::max(pl->max_np, P.np_vec);
@@ -1199,9 +1211,17 @@ fwils_status fwils_apply_pass(fwils_plan plan, int32_t pass, const void* u, void
         const int rows = P.p.nsys * 2 * P.p.nz;
         float2* tmp = at(plan->tmp, P);
         switch (pass) {
-            case 0: FW_HIP(launch_body_force(P.cfg.st, at(u, P), tmp, maps_at(plan, P), P.dev, nullptr, s)); break;
-            case 1:
-                FW_HIP(launch_rows_fwd(P.p.nx, P.cfg.row_p, tmp, tmp, rows, 2 * P.p.nz, nullptr, plan->tw, s));
+            case 0:
+                if (P.cfg.fuse_p) {
+                    const StencilArgs a{at(u, P), nullptr, nullptr, nullptr, nullptr, maps_at(plan, P), nullptr, 0};
+                    FW_HIP(launch_srows(0, P.cfg.fuse_p, a, tmp, P.dev, nullptr, plan->tw, s));
+                } else {
+                    FW_HIP(launch_body_force(P.cfg.st, at(u, P), tmp, maps_at(plan, P), P.dev, nullptr, s));
+                }
+                break;
+            case 1:   // part of pass 0 when the stencil and the rows are fused
+                if (!P.cfg.fuse_p)
+                    FW_HIP(launch_rows_fwd(P.p.nx, P.cfg.row_p, tmp, tmp, rows, 2 * P.p.nz, nullptr, plan->tw, s));
                 break;
             case 2: FW_HIP(launch_cols(COL_GREEN, P.cfg.col, tmp, P.dev, nullptr, plan->tw, s)); break;
             default:
@@ -1344,7 +1364,8 @@ fwils_tuning to_tuning(const ProbHost& P) {
     t.col_shared = P.cfg.col.seq;
     t.stencil_rows = P.cfg.st.TZ;
     t.stencil_sys = P.cfg.st.S;
-    for (int k = 0; k < 3; ++k) t.time_us[k] = P.tuned_us[k];
+    t.fused_points = P.cfg.fuse_p;
+    for (int k = 0; k < 4; ++k) t.time_us[k] = P.tuned_us[k];
     return t;
 }
 
@@ -1353,12 +1374,20 @@ KernelCfg from_tuning(const fwils_tuning& t) {
     k.row_p = t.row_points;
     k.col = ColCfg{t.col_points, t.col_width, t.col_shared};
     k.st = StCfg{t.stencil_rows, t.stencil_sys};
+    k.fuse_p = t.fused_points;
     return k;
+}
+
+bool fuse_ok(const ProbHost& P, int fp) {
+    if (fp == 0) return true;
+    if (!row_points_ok(P.p.nx, fp)) return false;
+    const int F = srows_rows(P.p.nx, P.p.nz, fp);
+    return F > 0 && srows_lds(P.p.nx, F) <= kMaxLds;
 }
 
 bool cfg_ok(const ProbHost& P, const KernelCfg& k) {
     return row_points_ok(P.p.nx, k.row_p) && col_cfg_ok(P.p.nz, P.p.nx, k.col) &&
-           st_cfg_ok(P.p.nx, P.p.nz, k.st);
+           st_cfg_ok(P.p.nx, P.p.nz, k.st) && fuse_ok(P, k.fuse_p);
 }
 
 void apply_cfg(fwils_plan pl, ProbHost& P, const KernelCfg& k) {
@@ -1395,6 +1424,17 @@ std::vector<KernelCfg> candidates(const ProbHost& P, int kind) {
             k.col = c[i];
             out.push_back(k);
         }
+    } else if (kind == FWILS_TUNE_FUSE) {
+        KernelCfg k = P.cfg;
+        k.fuse_p = 0;
+        out.push_back(k);
+        int c[2];
+        const int n = row_candidates(P.p.nx, c);
+        for (int i = 0; i < n; ++i) {
+            if (!fuse_ok(P, c[i])) continue;
+            k.fuse_p = c[i];
+            out.push_back(k);
+        }
     }
     return out;
 }
@@ -1408,6 +1448,16 @@ hipError_t tune_launch(fwils_plan pl, const ProbHost& P, int kind, const KernelC
     if (kind == FWILS_TUNE_STENCIL) return launch_body_force(k.st, u, tmp, maps_at(pl, P), P.dev, nullptr, pl->stream);
     if (kind == FWILS_TUNE_ROWS)
         return launch_rows_fwd(P.p.nx, k.row_p, tmp, tmp, rows, 2 * P.p.nz, nullptr, pl->tw, pl->stream);
+    if (kind == FWILS_TUNE_FUSE) {
+        // the stencil and the forward rows, fused or as two kernels
+        if (k.fuse_p) {
+            const StencilArgs a{u, nullptr, nullptr, nullptr, nullptr, maps_at(pl, P), nullptr, 0};
+            return launch_srows(0, k.fuse_p, a, tmp, P.dev, nullptr, pl->tw, pl->stream);
+        }
+        hipError_t e = launch_body_force(k.st, u, tmp, maps_at(pl, P), P.dev, nullptr, pl->stream);
+        if (e == hipSuccess) e = launch_rows_fwd(P.p.nx, k.row_p, tmp, tmp, rows, 2 * P.p.nz, nullptr, pl->tw, pl->stream);
+        return e;
+    }
     return launch_cols(COL_GREEN, k.col, tmp, P.dev, nullptr, pl->tw, pl->stream);
 }
 
@@ -1436,9 +1486,11 @@ fwils_status fwils_autotune(fwils_plan plan, int32_t reps) {
             break;
         }
         KernelCfg best = P.cfg;
-        float best_us[3] = {0.f, 0.f, 0.f};
-        for (int kind = 0; kind < 3 && st == FWILS_OK; ++kind) {
+        float best_us[4] = {0.f, 0.f, 0.f, 0.f};
+        for (int kind = 0; kind < 4 && st == FWILS_OK; ++kind) {
             float tbest = 0.f;
+            if (kind == FWILS_TUNE_FUSE) best.fuse_p = 0;
+            P.cfg = best;   // later kinds are timed with the earlier choices
             for (const KernelCfg& k : candidates(P, kind)) {
                 float ms = 0.f;
                 he = tune_launch(plan, P, kind, k);   // warm-up (and first-use set-up)
@@ -1457,14 +1509,15 @@ fwils_status fwils_autotune(fwils_plan plan, int32_t reps) {
                     tbest = us;
                     if (kind == FWILS_TUNE_STENCIL) best.st = k.st;
                     else if (kind == FWILS_TUNE_ROWS) best.row_p = k.row_p;
-                    else best.col = k.col;
+                    else if (kind == FWILS_TUNE_COLS) best.col = k.col;
+                    else best.fuse_p = k.fuse_p;
                 }
             }
             best_us[kind] = tbest;
         }
         if (st != FWILS_OK) break;
         apply_cfg(plan, P, best);
-        for (int k = 0; k < 3; ++k) P.tuned_us[k] = best_us[k];
+        for (int k = 0; k < 4; ++k) P.tuned_us[k] = best_us[k];
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -1490,20 +1543,20 @@ fwils_status fwils_set_tuning(fwils_plan plan, int32_t iprob, const fwils_tuning
     ProbHost& P = plan->probs[iprob];
     const KernelCfg k = from_tuning(*t);
     if (!cfg_ok(P, k)) {
-        set_error("set_tuning: not a built variant for %dx%d (rows %d, cols %d/%d/%d, stencil %d/%d)",
+        set_error("set_tuning: not a built variant for %dx%d (rows %d, cols %d/%d/%d, stencil %d/%d, fused %d)",
                   P.p.nz, P.p.nx, t->row_points, t->col_points, t->col_width, t->col_shared,
-                  t->stencil_rows, t->stencil_sys);
+                  t->stencil_rows, t->stencil_sys, t->fused_points);
         return FWILS_EINVAL;
     }
     apply_cfg(plan, P, k);
-    P.tuned_us[0] = P.tuned_us[1] = P.tuned_us[2] = 0.f;
+    P.tuned_us[0] = P.tuned_us[1] = P.tuned_us[2] = P.tuned_us[3] = 0.f;
     return FWILS_OK;
 }
 
 fwils_status fwils_tuning_candidates(fwils_plan plan, int32_t iprob, int32_t kind, fwils_tuning* out,
                                      int32_t cap, int32_t* count) {
     FW_TRY(check_plan(plan, false));
-    if (!count || iprob < 0 || iprob >= (int)plan->probs.size() || kind < 0 || kind > 2 || cap < 0 ||
+    if (!count || iprob < 0 || iprob >= (int)plan->probs.size() || kind < 0 || kind > 3 || cap < 0 ||
         (cap > 0 && !out)) {
         set_error("tuning_candidates: bad arguments");
         return FWILS_EINVAL;
@@ -1514,7 +1567,7 @@ fwils_status fwils_tuning_candidates(fwils_plan plan, int32_t iprob, int32_t kin
     for (int i = 0; i < (int)c.size() && i < cap; ++i) {
         ProbHost Q = P;
         Q.cfg = c[i];
-        Q.tuned_us[0] = Q.tuned_us[1] = Q.tuned_us[2] = 0.f;
+        Q.tuned_us[0] = Q.tuned_us[1] = Q.tuned_us[2] = Q.tuned_us[3] = 0.f;
         out[i] = to_tuning(Q);
     }
     return FWILS_OK;

@@ -1,0 +1,213 @@
+// Contrast stencil fused with the forward row transform (eqs. u_2, A, FFT):
+// a block owns F whole rows (both field components) of one system, loads
+// them with a 2-row halo into LDS (applying the BiCGSTAB update of the input
+// on the way, as k_body_force does), forms
+//     b = w~^2 drho u + (1 / 4 dx^2) div'(dC : e'),   e' = raw central differences,
+// directly in the register layout of the row transform (each thread the
+// positions t + T m of one row), transforms the 2F rows, and writes the
+// row-transformed b.  One kernel and one HBM round trip of b fewer per matvec
+// than the separate stencil and row passes.
+#include "bicg.h"
+#include "fft.h"
+
+namespace fw {
+
+namespace {
+
+__device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+struct RowLdsF {
+    float2* p;
+    __device__ __forceinline__ float2& operator()(int, int pos) const { return p[lds_pad(pos)]; }
+};
+
+template <int N, int P, int VM>
+__global__ __launch_bounds__(256) void k_srows(const float2* __restrict__ u, const float2* __restrict__ a1,
+                                               const float2* __restrict__ a2, float2* __restrict__ wout,
+                                               float2* __restrict__ rhat, float2* __restrict__ out,
+                                               const float* __restrict__ maps, ProbDev pd, int F,
+                                               SysState* __restrict__ st, const double* __restrict__ part,
+                                               int np, const float2* __restrict__ tw) {
+    using S = FftShape<N, P>;
+    constexpr int T = S::T;
+    constexpr int PL = PaddedLen<N>::value;
+    extern __shared__ float2 lds_dyn[];
+    __shared__ double red[4 * 4];
+
+    const int nz = pd.nz;
+    const size_t plane = (size_t)N * nz;
+    const int bps = nz / F;                         // blocks per system
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int sys = blk / bps;
+    const int z0 = (blk - sys * bps) * F;
+    if (st != nullptr && st[sys].status != ST_RUNNING) return;   // uniform over the block
+
+    float2 c1 = make_float2(0.f, 0.f), c2 = make_float2(0.f, 0.f);
+    bool fresh = false;
+    if constexpr (VM != VM_NONE) {
+        if (!stencil_scalars<VM>(st, sys, part, np, red, z0 == 0 && threadIdx.x == 0, c1, c2, fresh)) return;
+    }
+    const size_t so = (size_t)sys * 2 * plane;
+    auto field = [&](size_t gi) -> float2 {
+        if constexpr (VM == VM_NONE) {
+            return u[so + gi];
+        } else if constexpr (VM == VM_P) {
+            const float2 rv = u[so + gi];
+            if (fresh) return rv;
+            const float2 pv = a1[so + gi], vv = a2[so + gi];
+            return cadd(rv, cmul(c1, csub(pv, cmul(c2, vv))));
+        } else {
+            return csub(u[so + gi], cmul(c1, a1[so + gi]));
+        }
+    };
+
+    // 1. the 2F + 8 rows (F + 4 per component) of the input into LDS
+    const int HR = F + 4;
+    float2* su = lds_dyn;                           // [2][HR][N]
+    const int total = 2 * HR * N;
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
+        const int c = idx / (HR * N);
+        const int rem = idx - c * HR * N;
+        const int tr = rem / N, x = rem - tr * N;
+        const size_t gi = c * plane + (size_t)wrapi(z0 - 2 + tr, nz) * N + x;
+        const float2 f = field(gi);
+        su[idx] = f;
+        if constexpr (VM != VM_NONE) {
+            if (tr >= 2 && tr < F + 2) {            // the block's own rows
+                st_wt(wout + so + gi, f);
+                if constexpr (VM == VM_P) {
+                    if (fresh) st_wt(rhat + so + gi, f);
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    // 2. b on the own rows, in the transform's layout: row q = (component
+    //    c = q / F, row z0 + q % F), thread t holds x = t + T m
+    const int q = threadIdx.x / T, t = threadIdx.x - (threadIdx.x / T) * T;
+    const bool active = q < 2 * F;
+    const int c = active ? q / F : 0;
+    const int zl = active ? q - c * F : 0;
+    const int z = z0 + zl;
+    const float sc = pd.inv4dx2;
+    const float* mc11 = maps;
+    const float* mc13 = maps + plane;
+    const float* mc33 = maps + 2 * plane;
+    const float* mc55 = maps + 3 * plane;
+    const float* mrho = maps + 4 * plane;
+    auto U = [&](int cc, int dz, int x) -> float2 { return su[(cc * HR + zl + 2 + dz) * N + wrapi(x, N)]; };
+    const size_t zr = (size_t)z * N, zu = (size_t)wrapi(z - 1, nz) * N, zd = (size_t)wrapi(z + 1, nz) * N;
+    float2 v[1][P];
+#pragma unroll
+    for (int m = 0; m < P; ++m) {
+        const int x = t + T * m;
+        float2 b = make_float2(0.f, 0.f);
+        if (active) {
+            const int xl = wrapi(x - 1, N), xr = wrapi(x + 1, N);
+            const float2 wr = cscale(pd.w2, mrho[zr + x]);
+            if (c == 0) {
+                // sigma_1 at (z, x +- 1), sigma_5 at (z +- 1, x)
+                const float2 exr = csub(U(0, 0, x + 2), U(0, 0, x)), ezr = csub(U(1, 1, x + 1), U(1, -1, x + 1));
+                const float2 exl = csub(U(0, 0, x), U(0, 0, x - 2)), ezl = csub(U(1, 1, x - 1), U(1, -1, x - 1));
+                const float2 s1r = make_float2(mc11[zr + xr] * exr.x + mc13[zr + xr] * ezr.x,
+                                               mc11[zr + xr] * exr.y + mc13[zr + xr] * ezr.y);
+                const float2 s1l = make_float2(mc11[zr + xl] * exl.x + mc13[zr + xl] * ezl.x,
+                                               mc11[zr + xl] * exl.y + mc13[zr + xl] * ezl.y);
+                const float2 exzd = cadd(csub(U(0, 2, x), U(0, 0, x)), csub(U(1, 1, x + 1), U(1, 1, x - 1)));
+                const float2 exzu = cadd(csub(U(0, 0, x), U(0, -2, x)), csub(U(1, -1, x + 1), U(1, -1, x - 1)));
+                const float2 dx1 = csub(s1r, s1l);
+                const float2 dz5 = csub(cscale(exzd, mc55[zd + x]), cscale(exzu, mc55[zu + x]));
+                b = cadd(cmul(wr, U(0, 0, x)), cscale(cadd(dx1, dz5), sc));
+            } else {
+                // sigma_5 at (z, x +- 1), sigma_3 at (z +- 1, x)
+                const float2 exzr = cadd(csub(U(0, 1, x + 1), U(0, -1, x + 1)), csub(U(1, 0, x + 2), U(1, 0, x)));
+                const float2 exzl = cadd(csub(U(0, 1, x - 1), U(0, -1, x - 1)), csub(U(1, 0, x), U(1, 0, x - 2)));
+                const float2 exd = csub(U(0, 1, x + 1), U(0, 1, x - 1)), ezd = csub(U(1, 2, x), U(1, 0, x));
+                const float2 exu = csub(U(0, -1, x + 1), U(0, -1, x - 1)), ezu = csub(U(1, 0, x), U(1, -2, x));
+                const float2 s3d = make_float2(mc13[zd + x] * exd.x + mc33[zd + x] * ezd.x,
+                                               mc13[zd + x] * exd.y + mc33[zd + x] * ezd.y);
+                const float2 s3u = make_float2(mc13[zu + x] * exu.x + mc33[zu + x] * ezu.x,
+                                               mc13[zu + x] * exu.y + mc33[zu + x] * ezu.y);
+                const float2 dx5 = csub(cscale(exzr, mc55[zr + xr]), cscale(exzl, mc55[zr + xl]));
+                const float2 dz3 = csub(s3d, s3u);
+                b = cadd(cmul(wr, U(1, 0, x)), cscale(cadd(dx5, dz3), sc));
+            }
+        }
+        v[0][m] = b;
+    }
+    __syncthreads();   // the tile is read; its LDS now holds the transform's rows
+
+    // 3. forward row transforms (idle threads work in a dummy slot)
+    RowLdsF lds{lds_dyn + (size_t)(active ? q : 2 * F) * PL};
+    fft_run<N, P, false, 1>(v, t, tw, lds);
+    if (active) {
+        float2* o = out + so + c * plane + zr;
+#pragma unroll
+        for (int m = 0; m < P; ++m) st_wt(o + t + T * m, v[0][m]);
+    }
+}
+
+}  // namespace
+
+// Largest rows per block (a power of two <= 128 / T dividing nz) for n-point
+// rows with P points per thread; 0 when the fused kernel does not apply.
+int srows_rows(int nx, int nz, int P) {
+    if (nx > kSrowsMaxN || nx % P != 0) return 0;
+    const int T = nx / P;
+    if (T > 128) return 0;
+    int F = 128 / T;
+    while (F > 1 && nz % F != 0) F /= 2;
+    return F;
+}
+
+size_t srows_lds(int nx, int F) {
+    const size_t tile = (size_t)2 * (F + 4) * nx * sizeof(float2);
+    const size_t fft = (size_t)(2 * F + 1) * (nx + nx / 16 + 1) * sizeof(float2);
+    return tile > fft ? tile : fft;
+}
+
+template <int N, int P, int VM>
+static hipError_t srows_launch(const StencilArgs& a, float2* out, const ProbDev& pd, SysState* st,
+                               const float2* tw, hipStream_t s) {
+    const int F = srows_rows(N, pd.nz, P);
+    if (F == 0) return hipErrorInvalidValue;
+    const size_t lds = srows_lds(N, F);
+    if (lds > kMaxLds) return hipErrorInvalidValue;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_srows<N, P, VM>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    const int blocks = pd.nsys * (pd.nz / F);
+    hipLaunchKernelGGL((k_srows<N, P, VM>), dim3(blocks), dim3(256), lds, s, a.u, a.a1, a.a2, a.wout, a.rhat, out,
+                       a.maps, pd, F, st, a.part, a.np, tw);
+    return hipGetLastError();
+}
+
+template <int N, int P>
+static hipError_t srows_vm(int vm, const StencilArgs& a, float2* out, const ProbDev& pd, SysState* st,
+                           const float2* tw, hipStream_t s) {
+    if (vm == VM_NONE) return srows_launch<N, P, VM_NONE>(a, out, pd, st, tw, s);
+    if (vm == VM_P) return srows_launch<N, P, VM_P>(a, out, pd, st, tw, s);
+    return srows_launch<N, P, VM_S>(a, out, pd, st, tw, s);
+}
+
+#define FW_SROWS_VARIANTS(X)                                                                         \
+    X(16, 16) X(16, 8) X(24, 12) X(24, 24) X(32, 16) X(32, 8) X(48, 12) X(48, 24) X(64, 16) X(64, 8) \
+    X(96, 12) X(96, 24) X(128, 16) X(128, 8) X(192, 12) X(192, 24) X(256, 16) X(256, 8) X(384, 12)  \
+    X(384, 24) X(512, 16) X(512, 8)
+
+hipError_t launch_srows(int vm, int P, const StencilArgs& a, float2* out, const ProbDev& pd, SysState* st,
+                        const float2* tw, hipStream_t s) {
+    if (vm < 0 || vm > 2 || (vm != VM_NONE && !st) || (vm == VM_P && !a.rhat)) return hipErrorInvalidValue;
+    if (!row_points_ok(pd.nx, P) || srows_rows(pd.nx, pd.nz, P) == 0) return hipErrorInvalidValue;
+    const float2* t = tw + twiddle_offset(pd.nx);
+#define FW_CASE(N, PP) \
+    if (pd.nx == N && P == PP) return srows_vm<N, PP>(vm, a, out, pd, st, t, s);
+    FW_SROWS_VARIANTS(FW_CASE)
+#undef FW_CASE
+    return hipErrorInvalidValue;
+}
+
+}  // namespace fw

@@ -7,7 +7,7 @@
 //   k_correlate    - adjoint correlation of eq. ad1 summed over systems.
 #include <algorithm>
 
-#include "launch.h"
+#include "bicg.h"
 
 namespace fw {
 
@@ -30,21 +30,10 @@ constexpr int STX = 64, STZ = 8;
 
 __device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
-// Stopping test of the recursive residual (defined with the vector kernels
-// below); true if the system must stop.  `writer` records the status.
-__device__ __forceinline__ bool bicg_stop(SysState* st, int sys, double rr, bool writer);
-__device__ __forceinline__ dcomplex zdiv(dcomplex a, dcomplex b);
-__device__ __forceinline__ dcomplex zmul(dcomplex a, dcomplex b);
-__device__ __forceinline__ bool zzero(dcomplex a);
-
-// Vector update fused into the stencil's load of its input field:
-//   VM_NONE: the input is u itself;
-//   VM_P:    p = r + beta (p_old - omega v)   (BiCGSTAB direction update)
-//   VM_S:    s = r - alpha v                  (BiCGSTAB intermediate residual)
-// The updated field is written for the tile's own cells and used (halo
-// included) as the stencil's input.  p is double-buffered by the caller
-// because neighbouring tiles read p_old in their halos.
-enum StencilVec : int { VM_NONE = 0, VM_P = 1, VM_S = 2 };
+// The vector update of the input (StencilVec, bicg.h) is written for the
+// tile's own cells and used (halo included) as the stencil's input.  p is
+// double-buffered by the caller because neighbouring tiles read p_old in
+// their halos.
 
 template <int TX, int TZ, int VM>
 __global__ __launch_bounds__(256) void k_body_force(const float2* __restrict__ u,
@@ -101,46 +90,8 @@ __global__ __launch_bounds__(256) void k_body_force(const float2* __restrict__ u
         float2 c1 = make_float2(0.f, 0.f), c2 = make_float2(0.f, 0.f);
         bool fresh = false;
         if constexpr (VM != VM_NONE) {
-            double q[4];
-            sum_partials<4, 256>(part + (size_t)sys * np * kPartialNV, np, q, red);
-            const bool writer = (tile == 0 && threadIdx.x == 0);
-            const SysState& z = st[sys];
-            const int it = z.iter + 1;
-            if constexpr (VM == VM_P) {
-                if (bicg_stop(st, sys, q[2], writer)) continue;
-                dcomplex rho_i{q[0], q[1]};
-                const dcomplex rho_prev{z.rho_re[(it - 1) & 1], z.rho_im[(it - 1) & 1]};
-                const dcomplex alpha{z.alpha_re, z.alpha_im}, omega{z.omega_re, z.omega_im};
-                // Restart of the recurrence from the current iterate: scheduled
-                // after a stagnation, or forced by a zero scalar (which would
-                // otherwise break the iteration down): r^ = r, p = r.
-                fresh = (z.fresh_at == it) || zzero(rho_i) || zzero(rho_prev) || zzero(omega);
-                if (fresh) {
-                    rho_i = dcomplex{q[2], 0.0};   // <r, r>
-                    c1 = make_float2(0.f, 0.f);
-                } else {
-                    const dcomplex beta = zmul(zdiv(rho_i, rho_prev), zdiv(alpha, omega));
-                    c1 = make_float2((float)beta.re, (float)beta.im);
-                }
-                c2 = make_float2((float)omega.re, (float)omega.im);
-                if (writer) {
-                    st[sys].rho_re[it & 1] = rho_i.re;
-                    st[sys].rho_im[it & 1] = rho_i.im;
-                }
-            } else {
-                const dcomplex rho_i{z.rho_re[it & 1], z.rho_im[it & 1]};
-                const dcomplex rv{q[0], q[1]};
-                if (zzero(rv)) {
-                    if (writer) st[sys].status = ST_BREAKDOWN;
-                    continue;
-                }
-                const dcomplex alpha = zdiv(rho_i, rv);
-                c1 = make_float2((float)alpha.re, (float)alpha.im);
-                if (writer) {
-                    st[sys].alpha_re = alpha.re;
-                    st[sys].alpha_im = alpha.im;
-                }
-            }
+            if (!stencil_scalars<VM>(st, sys, part, np, red, tile == 0 && threadIdx.x == 0, c1, c2, fresh))
+                continue;
         }
         const size_t so = (size_t)sys * 2 * plane;
         float2* bs = b + so;
@@ -314,21 +265,13 @@ KernelCfg kernel_cfg_default(int nx, int nz) {
     k.row_p = row_points_default(nx);
     k.col = col_default(nz, nx);
     k.st = st_default();
+    k.fuse_p = 0;
     return k;
 }
 
 // -------------------------------------------------------------- vectors --
 int vec_blocks_per_sys(int n) { return (n + kVecThreads * kVecEPT - 1) / (kVecThreads * kVecEPT); }
 
-__device__ __forceinline__ dcomplex zdiv(dcomplex a, dcomplex b) {
-    const double d = b.re * b.re + b.im * b.im;
-    return dcomplex{(a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d};
-}
-__device__ __forceinline__ dcomplex zmul(dcomplex a, dcomplex b) {
-    return dcomplex{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
-}
-__device__ __forceinline__ float2 tof(dcomplex a) { return make_float2((float)a.re, (float)a.im); }
-__device__ __forceinline__ bool zzero(dcomplex a) { return a.re == 0.0 && a.im == 0.0; }
 
 // Block -> (system, block within system) for the vector kernels.
 struct VecIdx {
@@ -414,20 +357,6 @@ __global__ __launch_bounds__(256) void k_bicg_state_init(SysState* __restrict__ 
     }
 }
 
-// Convergence / limit / finiteness test of the recursive residual; returns
-// true if the system must stop.  Block 0 records the status.
-__device__ __forceinline__ bool bicg_stop(SysState* st, int sys, double rr, bool writer) {
-    const SysState& s = st[sys];
-    int status = ST_RUNNING;
-    if (!(rr == rr) || rr > 1e300) status = ST_NONFINITE;
-    else if (rr <= s.tol2) status = ST_CONVERGED;
-    else if (s.iter >= s.maxit) status = ST_MAXIT;
-    if (status != ST_RUNNING && writer) {
-        st[sys].status = status;
-        st[sys].rnorm2 = rr;
-    }
-    return status != ST_RUNNING;
-}
 
 // omega (see below);  x += alpha p + omega s;  r = s - omega t;
 // partials <rhat, r>, ||r||^2.

@@ -49,6 +49,8 @@ struct KernelCfg {
     int row_p;   // row-transform points per thread
     ColCfg col;
     StCfg st;
+    int fuse_p;  // 0: separate stencil and forward row pass; else the fused
+                 // stencil + row kernel with this many points per thread
 };
 
 // Launch geometry of a variant (also used to size partial buffers).
@@ -109,6 +111,13 @@ struct StencilArgs {
 };
 hipError_t launch_stencil(int vm, const StCfg& c, const StencilArgs& a, const ProbDev& pd, SysState* st,
                           hipStream_t s);
+// The stencil fused with the forward row transform: b (of the updated input,
+// vm as above, a.b unused) row-transformed into out.  Rows up to kSrowsMaxN.
+constexpr int kSrowsMaxN = 512;
+int srows_rows(int nx, int nz, int P);          // rows per block, 0 if unavailable
+size_t srows_lds(int nx, int F);
+hipError_t launch_srows(int vm, int P, const StencilArgs& a, float2* out, const ProbDev& pd, SysState* st,
+                        const float2* tw, hipStream_t s);
 
 // BiCGSTAB pieces (one problem; n = 2 nz nx complex per system).
 int vec_blocks_per_sys(int n);

@@ -404,7 +404,8 @@ class Plan:
         self.krylov = ("gmres", int(restart))
 
     # ----------------------------------------------------- autotuner ----
-    TUNE_KINDS = {"stencil": _lib.FWILS_TUNE_STENCIL, "rows": _lib.FWILS_TUNE_ROWS, "cols": _lib.FWILS_TUNE_COLS}
+    TUNE_KINDS = {"stencil": _lib.FWILS_TUNE_STENCIL, "rows": _lib.FWILS_TUNE_ROWS, "cols": _lib.FWILS_TUNE_COLS,
+                  "fuse": _lib.FWILS_TUNE_FUSE}
 
     def autotune(self, reps=20):
         """Time every kernel variant on this plan's workspace and keep the fastest

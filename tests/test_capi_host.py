@@ -56,8 +56,9 @@ def test_tuning_defaults_candidates_and_validation(lib):
         t = _lib.FwilsTuning()
         assert lib.fwils_get_tuning(h, 0, ctypes.byref(t)) == 0
         assert (t.row_points, t.col_points, t.col_width, t.col_shared, t.stencil_rows) == (12, 12, 16, 1, 8)
-        assert list(t.time_us) == [0.0, 0.0, 0.0]
-        for kind, field in ((0, "stencil_rows"), (1, "row_points"), (2, "col_points")):
+        assert t.fused_points == 0
+        assert list(t.time_us) == [0.0, 0.0, 0.0, 0.0]
+        for kind, field in ((0, "stencil_rows"), (1, "row_points"), (2, "col_points"), (3, "fused_points")):
             n = ctypes.c_int32()
             assert lib.fwils_tuning_candidates(h, 0, kind, None, 0, ctypes.byref(n)) == 0
             arr = (_lib.FwilsTuning * n.value)()

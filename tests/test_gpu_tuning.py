@@ -39,7 +39,7 @@ def test_every_variant_matches_oracle(nx, nz):
     ref = P.apply(u)
     default = plan.tuning(0)
     seen = 0
-    for kind in ("stencil", "rows", "cols"):
+    for kind in ("stencil", "rows", "cols", "fuse"):
         cands = plan.tuning_candidates(0, kind)
         assert len(cands) >= 2, kind
         for c in cands:
