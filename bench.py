@@ -481,18 +481,6 @@ def main(argv=None):
         e1.record(stream)
         e1.synchronize()
         return e0.elapsed_time(e1) / reps
-    def launch_time(fn, reps):
-        # one event pair around every launch, averaged: the kernel's own
-        # duration, not the host's launch rate
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-               for _ in range(reps)]
-        fn()
-        for e0, e1 in evs:
-            e0.record(stream)
-            fn()
-            e1.record(stream)
-        evs[-1][1].synchronize()
-        return sum(e0.elapsed_time(e1) for e0, e1 in evs) / reps
     t_apply = event_time(lambda: plan.apply(u, out=Au), a.reps)
     # the kernels of one matvec under the chosen variants: with the stencil
     # fused into the forward rows, pass 1 launches nothing
@@ -503,7 +491,7 @@ def main(argv=None):
     for k in passes:
         for j in range(k):
             plan.apply_pass(j, u, Au)
-        t_pass.append(launch_time(lambda k=k: plan.apply_pass(k, u, Au), a.reps))
+        t_pass.append(plan.time_pass(k, u, Au, a.reps) * 1e-3)   # ms per launch
     matvec_gps = ns * cells / (t_apply * 1e-3) / 1e9
     bytes_per_launch = [PASS_BYTES[k] * ns * cells + (MAP_BYTES_PER_CELL * cells if k == 0 else 0.0)
                         for k in passes]

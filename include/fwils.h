@@ -194,6 +194,10 @@ fwils_status fwils_adjoint(fwils_plan plan, const void* ub, const void* r,
  * u is read by passes 0 and 3, Au written by pass 3 (others ignore them).
  * Exists so that a caller can time each kernel of the matvec. */
 fwils_status fwils_apply_pass(fwils_plan plan, int32_t pass, const void* u, void* Au);
+/* Average duration in microseconds (*us, host) of pass `pass` of
+ * fwils_apply_pass over reps (1..10000) back-to-back launches, measured with
+ * HIP events on the plan's stream after one warm-up launch.  Synchronous. */
+fwils_status fwils_time_pass(fwils_plan plan, int32_t pass, const void* u, void* Au, int32_t reps, float* us);
 
 /* Per-system results of the most recent Krylov solve of this plan (from
  * fwils_solve, fwils_frechet or fwils_adjoint): completed iterations and the

@@ -66,6 +66,7 @@ SIGNATURES = {
     "fwils_adjoint": (c_int32, [P, P, P, ctypes.POINTER(c_void_p), c_uint32, c_double, c_int32]),
     "fwils_fft2": (c_int32, [P, c_int32, P, P, c_int32]),
     "fwils_apply_pass": (c_int32, [P, c_int32, P, P]),
+    "fwils_time_pass": (c_int32, [P, c_int32, P, P, c_int32, ctypes.POINTER(ctypes.c_float)]),
     "fwils_tikhonov_grad": (c_int32, [P, P, P, ctypes.POINTER(c_double), c_double, c_int32, P, P,
                                       ctypes.POINTER(c_double), P, c_double, c_int32]),
     "fwils_normal_apply": (c_int32, [P, P, ctypes.POINTER(c_double), c_double, c_double, c_int32, P, P, P,

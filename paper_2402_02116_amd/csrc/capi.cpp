@@ -1233,6 +1233,33 @@ fwils_status fwils_apply_pass(fwils_plan plan, int32_t pass, const void* u, void
     return FWILS_OK;
 }
 
+fwils_status fwils_time_pass(fwils_plan plan, int32_t pass, const void* u, void* Au, int32_t reps, float* us) {
+    if (!us || reps < 1 || reps > 10000) {
+        set_error("time_pass: need reps 1..10000 and an output");
+        return FWILS_EINVAL;
+    }
+    FW_TRY(fwils_apply_pass(plan, pass, u, Au));   // validates, and warms up
+    hipEvent_t e0, e1;
+    FW_HIP(hipEventCreate(&e0));
+    FW_HIP(hipEventCreate(&e1));
+    fwils_status st = FWILS_OK;
+    hipError_t he = hipEventRecord(e0, plan->stream);
+    for (int r = 0; r < reps && he == hipSuccess && st == FWILS_OK; ++r) st = fwils_apply_pass(plan, pass, u, Au);
+    if (he == hipSuccess) he = hipEventRecord(e1, plan->stream);
+    if (he == hipSuccess) he = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != FWILS_OK) return st;
+    if (he != hipSuccess) {
+        set_error("time_pass: %s", hipGetErrorString(he));
+        return FWILS_EDEVICE;
+    }
+    *us = ms * 1e3f / (float)reps;
+    return FWILS_OK;
+}
+
 fwils_status fwils_solve_status(fwils_plan plan, int32_t* status) {
     FW_TRY(check_plan(plan));
     if (!status) {

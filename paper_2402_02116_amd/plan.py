@@ -260,6 +260,16 @@ class Plan:
                                         None if out is None else _ptr(out)), "fwils_apply_pass")
         return out
 
+    def time_pass(self, k, u, out, reps=50):
+        """Average duration (us) of pass k of apply() over reps back-to-back launches."""
+        self._field(u, "u")
+        self._field(out, "out")
+        us = ctypes.c_float()
+        self._bind_stream()
+        check(self.lib.fwils_time_pass(self._h, int(k), _ptr(u), _ptr(out), int(reps), ctypes.byref(us)),
+              "fwils_time_pass")
+        return us.value
+
     def solve_stats(self):
         """(iters, recursive relres) of the last Krylov solve, per system."""
         it = np.zeros(self.total_sys, dtype=np.int32)
