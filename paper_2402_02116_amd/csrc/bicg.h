@@ -32,60 +32,164 @@ __device__ __forceinline__ bool bicg_stop(SysState* st, int sys, double rr, bool
     return status != ST_RUNNING;
 }
 
-// Vector update fused into a stencil's load of its input field:
-//   VM_NONE: the input is u itself;
-//   VM_P:    p = r + beta (p_old - omega v)   (BiCGSTAB direction update)
-//   VM_S:    s = r - alpha v                  (BiCGSTAB intermediate residual)
-enum StencilVec : int { VM_NONE = 0, VM_P = 1, VM_S = 2 };
+
+constexpr double kOmegaLimit = 0.7;
+
+// From the t-pass records q = (<t,s>, ||t||^2, ||s||^2, <r^,s>, <r^,t>):
+// omega = <t,s> / ||t||^2, enlarged when t and s are far from parallel
+// (|<t,s>| < 0.7 |t| |s|; the finite-precision safeguard of Sleijpen and van
+// der Vorst, 1995, which keeps the BiCG part from stalling), and for the next
+// residual r = s - omega t its norm ||r||^2 = ||s||^2 - 2 Re(conj(omega)
+// <t,s>) + |omega|^2 ||t||^2 and <r^, r> = <r^,s> - omega <r^,t>.
+struct OmegaStep {
+    dcomplex omega;
+    double rr;
+    dcomplex rho;
+};
+__device__ __forceinline__ OmegaStep omega_step(const double (&q)[kPartialNV]) {
+    OmegaStep o;
+    o.omega = dcomplex{0.0, 0.0};
+    if (q[2] != 0.0) {
+        o.omega = dcomplex{q[0] / q[2], q[1] / q[2]};
+        const double ts = sqrt(q[0] * q[0] + q[1] * q[1]);
+        const double c = (q[3] > 0.0) ? ts / sqrt(q[2] * q[3]) : 1.0;
+        if (c < kOmegaLimit && c > 0.0) {
+            o.omega.re *= kOmegaLimit / c;
+            o.omega.im *= kOmegaLimit / c;
+        }
+    }
+    const double wr = o.omega.re, wi = o.omega.im;
+    const double rr = q[3] - 2.0 * (wr * q[0] + wi * q[1]) + (wr * wr + wi * wi) * q[2];
+    o.rr = rr > 0.0 ? rr : 0.0;
+    o.rho = dcomplex{q[4] - (wr * q[6] - wi * q[7]), q[5] - (wr * q[7] + wi * q[6])};
+    return o;
+}
+
+// Whether a block of a launch that closes iterations (tag kStampPx or
+// kStampClose) has work for a system with status word s: the system runs, or
+// another block of this very launch stopped it with its last solution update
+// still owed.
+__device__ __forceinline__ bool closing_enters(int s, int tag) {
+    if (s == ST_RUNNING) return true;
+    const int c = st_code(s);
+    return (c == ST_CONVERGED || c == ST_MAXIT) && st_tag(s) == tag;
+}
+
+// The stop decision at the end of an iteration, from the t-pass records:
+// non-finite, converged (||r||^2 <= tol2) or out of iterations; ST_RUNNING
+// otherwise.
+__device__ __forceinline__ int close_code(const SysState& z, const OmegaStep& o) {
+    if (!(o.rr == o.rr) || o.rr > 1e300 || !(o.omega.re == o.omega.re) || !(o.omega.im == o.omega.im))
+        return ST_NONFINITE;
+    if (o.rr <= z.tol2) return ST_CONVERGED;
+    if (z.iter >= z.maxit) return ST_MAXIT;
+    return ST_RUNNING;
+}
+
+// The closing updates of an iteration on one element: r = s - omega t and
+// x + alpha p + omega s.  Contraction is off so that every kernel that closes
+// an iteration (stencils, close kernel) rounds it identically.
+__device__ __forceinline__ float2 close_r(float2 sv, float2 tv, float2 omega) {
+#pragma clang fp contract(off)
+    return make_float2(sv.x - (omega.x * tv.x - omega.y * tv.y), sv.y - (omega.x * tv.y + omega.y * tv.x));
+}
+__device__ __forceinline__ float2 close_x(float2 xv, float2 pv, float2 sv, float2 alpha, float2 omega) {
+#pragma clang fp contract(off)
+    const float ax = alpha.x * pv.x - alpha.y * pv.y, ay = alpha.x * pv.y + alpha.y * pv.x;
+    const float wx = omega.x * sv.x - omega.y * sv.y, wy = omega.x * sv.y + omega.y * sv.x;
+    return make_float2(xv.x + (ax + wx), xv.y + (ay + wy));
+}
+
+enum StencilStep : int { SS_SKIP = 0, SS_FULL = 1, SS_XONLY = 2 };
 
 // Scalars of the update of system sys from its producer's partial records
-// (summed by every block in the same order): VM_P -> c1 = beta, c2 = omega,
+// (summed by every block in the same order).  VM_P -> c1 = beta, c2 = omega,
 // and `fresh` when the recurrence restarts from the current iterate (r^ = r,
 // p = r): scheduled after a stagnation, or forced by a zero scalar that would
-// otherwise break the iteration down.  VM_S -> c1 = alpha.  Returns false if
-// the system stops (converged, limit, breakdown); `writer` (one thread of one
-// block per system) records scalars and status.  Every thread of the block
-// must call it (block reduction).
+// otherwise break the iteration down.  VM_S -> c1 = alpha.  VM_PX -> c1 =
+// beta, c2 = omega, c3 = alpha; the stopping test is on the residual r = s -
+// omega t, and a stopped system still receives its solution update
+// (SS_XONLY).  Returns SS_SKIP if the system stops (converged, limit,
+// breakdown) with nothing left to do; `writer` (one thread of one block per
+// system) records scalars and status.  Every thread of the block must call it
+// (block reduction).
 template <int VM>
-__device__ __forceinline__ bool stencil_scalars(SysState* st, int sys, const double* part, int np, double* red,
-                                                bool writer, float2& c1, float2& c2, bool& fresh) {
-    double q[4];
-    sum_partials<4, 256>(part + (size_t)sys * np * kPartialNV, np, q, red);
+__device__ __forceinline__ int stencil_scalars(SysState* st, int sys, const double* part, int np, double* red,
+                                               bool writer, float2& c1, float2& c2, float2& c3, bool& fresh) {
     const SysState& z = st[sys];
     const int it = z.iter + 1;
-    if constexpr (VM == VM_P) {
-        if (bicg_stop(st, sys, q[2], writer)) return false;
-        dcomplex rho_i{q[0], q[1]};
+    if constexpr (VM == VM_PX) {
+        double q[kPartialNV];
+        sum_partials<kPartialNV, 256>(part + (size_t)sys * np * kPartialNV, np, q, red);
+        const OmegaStep o = omega_step(q);
+        const dcomplex alpha{z.alpha_re, z.alpha_im};
+        c2 = tof(o.omega);
+        c3 = tof(alpha);
+        const int code = close_code(z, o);
+        if (code != ST_RUNNING) {
+            if (writer) {
+                st[sys].status = st_stamp(code, kStampPx);
+                st[sys].omega_re = o.omega.re;
+                st[sys].omega_im = o.omega.im;
+                st[sys].rnorm2 = o.rr;
+            }
+            return code == ST_NONFINITE ? SS_SKIP : SS_XONLY;
+        }
+        dcomplex rho_i = o.rho;
         const dcomplex rho_prev{z.rho_re[(it - 1) & 1], z.rho_im[(it - 1) & 1]};
-        const dcomplex alpha{z.alpha_re, z.alpha_im}, omega{z.omega_re, z.omega_im};
-        fresh = (z.fresh_at == it) || zzero(rho_i) || zzero(rho_prev) || zzero(omega);
+        fresh = (z.fresh_at == it) || zzero(rho_i) || zzero(rho_prev) || zzero(o.omega);
         if (fresh) {
-            rho_i = dcomplex{q[2], 0.0};   // <r, r>
+            rho_i = dcomplex{o.rr, 0.0};   // <r, r>
             c1 = make_float2(0.f, 0.f);
         } else {
-            const dcomplex beta = zmul(zdiv(rho_i, rho_prev), zdiv(alpha, omega));
+            const dcomplex beta = zmul(zdiv(rho_i, rho_prev), zdiv(alpha, o.omega));
             c1 = make_float2((float)beta.re, (float)beta.im);
         }
-        c2 = make_float2((float)omega.re, (float)omega.im);
         if (writer) {
             st[sys].rho_re[it & 1] = rho_i.re;
             st[sys].rho_im[it & 1] = rho_i.im;
+            st[sys].omega_re = o.omega.re;
+            st[sys].omega_im = o.omega.im;
+            st[sys].rnorm2 = o.rr;
         }
+        return SS_FULL;
     } else {
-        const dcomplex rho_i{z.rho_re[it & 1], z.rho_im[it & 1]};
-        const dcomplex rv{q[0], q[1]};
-        if (zzero(rv)) {
-            if (writer) st[sys].status = ST_BREAKDOWN;
-            return false;
+        double q[4];
+        sum_partials<4, 256>(part + (size_t)sys * np * kPartialNV, np, q, red);
+        if constexpr (VM == VM_P) {
+            if (bicg_stop(st, sys, q[2], writer)) return SS_SKIP;
+            dcomplex rho_i{q[0], q[1]};
+            const dcomplex rho_prev{z.rho_re[(it - 1) & 1], z.rho_im[(it - 1) & 1]};
+            const dcomplex alpha{z.alpha_re, z.alpha_im}, omega{z.omega_re, z.omega_im};
+            fresh = (z.fresh_at == it) || zzero(rho_i) || zzero(rho_prev) || zzero(omega);
+            if (fresh) {
+                rho_i = dcomplex{q[2], 0.0};   // <r, r>
+                c1 = make_float2(0.f, 0.f);
+            } else {
+                const dcomplex beta = zmul(zdiv(rho_i, rho_prev), zdiv(alpha, omega));
+                c1 = make_float2((float)beta.re, (float)beta.im);
+            }
+            c2 = make_float2((float)omega.re, (float)omega.im);
+            if (writer) {
+                st[sys].rho_re[it & 1] = rho_i.re;
+                st[sys].rho_im[it & 1] = rho_i.im;
+            }
+        } else {
+            const dcomplex rho_i{z.rho_re[it & 1], z.rho_im[it & 1]};
+            const dcomplex rv{q[0], q[1]};
+            if (zzero(rv)) {
+                if (writer) st[sys].status = ST_BREAKDOWN;
+                return SS_SKIP;
+            }
+            const dcomplex alpha = zdiv(rho_i, rv);
+            c1 = make_float2((float)alpha.re, (float)alpha.im);
+            if (writer) {
+                st[sys].alpha_re = alpha.re;
+                st[sys].alpha_im = alpha.im;
+            }
         }
-        const dcomplex alpha = zdiv(rho_i, rv);
-        c1 = make_float2((float)alpha.re, (float)alpha.im);
-        if (writer) {
-            st[sys].alpha_re = alpha.re;
-            st[sys].alpha_im = alpha.im;
-        }
+        return SS_FULL;
     }
-    return true;
 }
 
 }  // namespace fw

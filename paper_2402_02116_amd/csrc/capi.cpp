@@ -96,8 +96,9 @@ struct fwils_plan_s {
           *mq_l1 = nullptr, *mq_l2 = nullptr;
     float2* mq_g = nullptr;
     double *mq_part = nullptr, *mq_sc = nullptr, *mq_hist = nullptr;
-    // graph of one chunk of iterations over all problems
-    hipGraphExec_t chunk = nullptr;
+    // graphs of one chunk of iterations over all problems (the first chunk of
+    // a solve or restart starts from r)
+    hipGraphExec_t chunk = nullptr, chunk_first = nullptr;
     // Krylov method; GMRES state lives in a caller-provided workspace
     int krylov = FWILS_KRYLOV_BICGSTAB;
     int gm_m = 0;
@@ -216,13 +217,17 @@ SysView make_view(fwils_plan pl, const ProbHost& P, int s0, int ns) {
     return v;
 }
 
-// One BiCGSTAB iteration on a view (all kernels skip stopped systems): nine
-// kernels.  The direction update p = r + beta (p_old - omega v) is fused into
-// the first contrast stencil and s = r - alpha v into the second; p
-// alternates between two buffers with the iteration parity.
-hipError_t bicg_iteration(fwils_plan pl, const ProbHost& P, const SysView& V, int parity, hipStream_t s) {
+// One BiCGSTAB iteration on a view (all kernels skip stopped systems): six
+// kernels, five with the stencil fused into the forward rows.  The first
+// contrast stencil takes the direction update p = r + beta (p_old - omega v)
+// into its input and, past the first iteration of a (re)start, the previous
+// iteration's closing updates r = s - omega t, x += alpha p_old + omega s
+// (decided from the t-pass records, so a system that stops there gets only
+// those); the second takes s = r - alpha v.  p alternates between two buffers
+// with the iteration parity.
+hipError_t bicg_iteration(fwils_plan pl, const ProbHost& P, const SysView& V, int parity, bool first,
+                          hipStream_t s) {
     const int ns = V.d.nsys;
-    const int n = (int)P.n_per_sys;
     const int rows = ns * 2 * V.d.nz;
     float2 *x = pl->x + V.foff, *r = pl->r + V.foff, *rh = pl->rhat + V.foff, *v = pl->v + V.foff,
            *sv = pl->s + V.foff, *t = pl->t + V.foff, *tmp = pl->tmp + V.foff;
@@ -231,7 +236,13 @@ hipError_t bicg_iteration(fwils_plan pl, const ProbHost& P, const SysView& V, in
     SysState* st = pl->state + V.soff;
     double *pV = pl->partV + V.poff_row, *pT = pl->partT + V.poff_row, *pXR = pl->partXR + V.poff_vec;
     const float* maps = maps_at(pl, P);
-    const StencilArgs ap{r, pold, v, pnew, tmp, maps, pXR, P.np_vec, rh};
+    StencilArgs ap{r, pold, v, pnew, tmp, maps, pXR, P.np_vec, rh};
+    if (!first) {
+        ap = StencilArgs{sv, pold, v, pnew, tmp, maps, pT, P.np_rows, rh};
+        ap.a3 = t;
+        ap.xio = x;
+        ap.rout = r;
+    }
     const KernelCfg& k = P.cfg;
     // contrast stencil with the fused vector update, then the forward rows
     // (one fused kernel, or two)
@@ -241,17 +252,33 @@ hipError_t bicg_iteration(fwils_plan pl, const ProbHost& P, const SysView& V, in
         if (r == hipSuccess) r = launch_rows_fwd(V.d.nx, k.row_p, tmp, tmp, rows, 2 * V.d.nz, st, pl->tw, s);
         return r;
     };
-    hipError_t e = stencil_rows(1, ap);
+    hipError_t e = stencil_rows(first ? VM_P : VM_PX, ap);
     if (e == hipSuccess) e = launch_cols(COL_GREEN, k.col, tmp, V.d, st, pl->tw, s);
     if (e == hipSuccess)
         e = launch_rows_inv(V.d.nx, k.row_p, EPI_BICG_V, tmp, pnew, rh, v, pV, rows, 2 * V.d.nz, st, pl->tw, s);
     const StencilArgs as{r, v, nullptr, sv, tmp, maps, pV, P.np_rows};
-    if (e == hipSuccess) e = stencil_rows(2, as);
+    if (e == hipSuccess) e = stencil_rows(VM_S, as);
     if (e == hipSuccess) e = launch_cols(COL_GREEN, k.col, tmp, V.d, st, pl->tw, s);
     if (e == hipSuccess)
-        e = launch_rows_inv(V.d.nx, k.row_p, EPI_BICG_T, tmp, sv, nullptr, t, pT, rows, 2 * V.d.nz, st, pl->tw,
-                            s);
-    if (e == hipSuccess) e = launch_bicg_xr(x, r, rh, pnew, sv, t, pT, P.np_rows, pXR, st, ns, n, s);
+        e = launch_rows_inv(V.d.nx, k.row_p, EPI_BICG_T, tmp, sv, rh, t, pT, rows, 2 * V.d.nz, st, pl->tw, s);
+    return e;
+}
+
+// The end-of-chunk close kernel after an iteration of the given parity.
+hipError_t bicg_close(fwils_plan pl, const ProbHost& P, const SysView& V, int parity, hipStream_t s) {
+    float2* pnew = (parity ? pl->p : pl->p2) + V.foff;
+    return launch_bicg_close(pl->x + V.foff, pl->r + V.foff, pnew, pl->s + V.foff, pl->t + V.foff,
+                             pl->partT + V.poff_row, P.np_rows, pl->state + V.soff, V.d.nsys,
+                             (int)P.n_per_sys, s);
+}
+
+// One chunk of kChunkIters iterations and the close kernel; `first` when the
+// chunk starts a solve or a restart (its first iteration reads r).
+hipError_t bicg_chunk(fwils_plan pl, const ProbHost& P, const SysView& V, bool first, hipStream_t s) {
+    hipError_t e = hipSuccess;
+    for (int it = 0; it < kChunkIters && e == hipSuccess; ++it)
+        e = bicg_iteration(pl, P, V, it & 1, first && it == 0, s);
+    if (e == hipSuccess) e = bicg_close(pl, P, V, (kChunkIters - 1) & 1, s);
     return e;
 }
 
@@ -287,15 +314,15 @@ fwils_status capture_graph(fwils_plan pl, hipGraphExec_t* out,
     return FWILS_OK;
 }
 
-fwils_status build_chunk_graph(fwils_plan pl) {
-    if (pl->chunk) return FWILS_OK;
-    return capture_graph(pl, &pl->chunk, [pl](const ProbHost& P, hipStream_t s) -> hipError_t {
-        const SysView V = make_view(pl, P, 0, P.p.nsys);
-        hipError_t e = hipSuccess;
-        for (int it = 0; it < kChunkIters && e == hipSuccess; ++it) e = bicg_iteration(pl, P, V, it & 1, s);
-        if (e == hipSuccess) e = launch_bicg_check(st_at(pl, P), part_at(pl->partXR, pl, P), P.np_vec, P.p.nsys, s);
-        return e;
-    });
+fwils_status build_chunk_graphs(fwils_plan pl) {
+    for (int f = 0; f < 2; ++f) {
+        hipGraphExec_t* g = f ? &pl->chunk_first : &pl->chunk;
+        if (*g) continue;
+        FW_TRY(capture_graph(pl, g, [pl, f](const ProbHost& P, hipStream_t s) -> hipError_t {
+            return bicg_chunk(pl, P, make_view(pl, P, 0, P.p.nsys), f == 1, s);
+        }));
+    }
+    return FWILS_OK;
 }
 
 
@@ -336,8 +363,8 @@ fwils_status bicg_solve_ws(fwils_plan pl, const float2* b, bool use_x0, double r
                     const SysView V = make_view(pl, P, sy, 1);
                     if (pl->host_state[V.soff].status != ST_RUNNING) continue;
                     for (int it = 0; it <= maxit; ++it) {
-                        FW_HIP(bicg_iteration(pl, P, V, it & 1, s));
-                        FW_HIP(launch_bicg_check(pl->state + V.soff, pl->partXR + V.poff_vec, P.np_vec, 1, s));
+                        FW_HIP(bicg_iteration(pl, P, V, it & 1, it == 0, s));
+                        FW_HIP(bicg_close(pl, P, V, it & 1, s));
                         FW_HIP(hipMemcpyAsync(pl->host_state + V.soff, pl->state + V.soff, sizeof(SysState),
                                               hipMemcpyDeviceToHost, s));
                         FW_HIP(hipStreamSynchronize(s));
@@ -350,17 +377,13 @@ fwils_status bicg_solve_ws(fwils_plan pl, const float2* b, bool use_x0, double r
         const int max_chunks = maxit / kChunkIters + 2;
         bool done = false;
         FW_TRY(all_done(done));
-        if (!(flags & FWILS_SOLVE_NOGRAPH)) FW_TRY(build_chunk_graph(pl));
+        if (!(flags & FWILS_SOLVE_NOGRAPH)) FW_TRY(build_chunk_graphs(pl));
         for (int c = 0; c < max_chunks && !done; ++c) {
             if (flags & FWILS_SOLVE_NOGRAPH) {
-                for (const ProbHost& P : pl->probs) {
-                    const SysView V = make_view(pl, P, 0, P.p.nsys);
-                    for (int it = 0; it < kChunkIters; ++it) FW_HIP(bicg_iteration(pl, P, V, it & 1, s));
-                    FW_HIP(launch_bicg_check(st_at(pl, P), part_at(pl->partXR, pl, P), P.np_vec,
-                                             P.p.nsys, s));
-                }
+                for (const ProbHost& P : pl->probs)
+                    FW_HIP(bicg_chunk(pl, P, make_view(pl, P, 0, P.p.nsys), c == 0, s));
             } else {
-                FW_HIP(hipGraphLaunch(pl->chunk, s));
+                FW_HIP(hipGraphLaunch(c == 0 ? pl->chunk_first : pl->chunk, s));
             }
             FW_TRY(all_done(done));
         }
@@ -403,7 +426,7 @@ fwils_status bicg_solve_ws(fwils_plan pl, const float2* b, bool use_x0, double r
     FW_HIP(hipStreamSynchronize(s));
     bool noconv = false, brk = false;
     for (size_t i = 0; i < nst; ++i) {
-        const int stt = pl->host_state[i].status;
+        const int stt = st_code(pl->host_state[i].status);
         if (stt == ST_MAXIT || stt == ST_RUNNING) noconv = true;
         if (stt == ST_BREAKDOWN || stt == ST_NONFINITE) brk = true;
     }
@@ -421,6 +444,8 @@ fwils_status bicg_solve_ws(fwils_plan pl, const float2* b, bool use_x0, double r
 // ------------------------------------------------------------- GMRES ----
 void drop_graphs(fwils_plan pl) {
     if (pl->chunk) (void)hipGraphExecDestroy(pl->chunk);
+    if (pl->chunk_first) (void)hipGraphExecDestroy(pl->chunk_first);
+    pl->chunk_first = nullptr;
     if (pl->gm_cycle) (void)hipGraphExecDestroy(pl->gm_cycle);
     pl->chunk = nullptr;
     pl->gm_cycle = nullptr;
@@ -532,7 +557,7 @@ fwils_status gm_solve_ws(fwils_plan pl, const float2* b, bool use_x0, double rto
     FW_HIP(hipStreamSynchronize(s));
     bool noconv = false, brk = false;
     for (size_t i = 0; i < nst; ++i) {
-        const int stt = pl->host_state[i].status;
+        const int stt = st_code(pl->host_state[i].status);
         if (stt == ST_MAXIT || stt == ST_RUNNING) noconv = true;
         if (stt == ST_BREAKDOWN || stt == ST_NONFINITE) brk = true;
     }
@@ -1269,7 +1294,7 @@ fwils_status fwils_solve_status(fwils_plan plan, int32_t* status) {
     FW_HIP(hipStreamSynchronize(plan->stream));
     FW_HIP(hipMemcpy(plan->host_state, plan->state, plan->total_sys * sizeof(SysState), hipMemcpyDeviceToHost));
     for (size_t i = 0; i < plan->total_sys; ++i) {
-        switch (plan->host_state[i].status) {
+        switch (st_code(plan->host_state[i].status)) {
             case ST_CONVERGED: status[i] = FWILS_SYS_CONVERGED; break;
             case ST_MAXIT: status[i] = FWILS_SYS_MAXIT; break;
             case ST_BREAKDOWN: status[i] = FWILS_SYS_BREAKDOWN; break;

@@ -48,6 +48,19 @@ struct ProbDev {
 };
 
 // --------------------------------------------------------- solver state ---
+constexpr int kPartialNV = 8;   // doubles per partial-sum record
+
+// A status word holds a SysStatus code in its low byte.  A stop decided inside
+// a kernel whose blocks still owe the system its last solution update carries
+// a tag above it (the kernel that decided it), so that the blocks of that
+// kernel that read the status after the decision still do their part; a later
+// kernel of the iteration removes the tag.
+constexpr int kStampPx = 1;      // decided by a direction-update stencil
+constexpr int kStampClose = 2;   // decided by the end-of-chunk close kernel
+__host__ __device__ inline int st_code(int s) { return s & 0xFF; }
+__host__ __device__ inline int st_tag(int s) { return s >> 8; }
+__host__ __device__ inline int st_stamp(int code, int tag) { return code | (tag << 8); }
+
 enum SysStatus : int {
     ST_RUNNING = 0,
     ST_CONVERGED = 1,
@@ -104,16 +117,18 @@ __device__ __forceinline__ void block_allreduce(double (&acc)[NV], double* smem)
     __syncthreads();
 }
 
-// Sum np partial records of NV doubles each (record i at part[i * NV]) with a
-// fixed order; every thread of the block receives the totals.
-template <int NV, int NT>
+// Sum the first NV doubles of np partial records (record i at
+// part[i * STRIDE]) in a fixed order; every thread of the block receives the
+// totals.
+template <int NV, int NT, int STRIDE = kPartialNV>
 __device__ __forceinline__ void sum_partials(const double* __restrict__ part, int np,
                                              double (&res)[NV], double* smem) {
+    static_assert(NV <= STRIDE, "record too short");
 #pragma unroll
     for (int k = 0; k < NV; ++k) res[k] = 0.0;
     for (int i = threadIdx.x; i < np; i += NT) {
 #pragma unroll
-        for (int k = 0; k < NV; ++k) res[k] += part[(size_t)i * NV + k];
+        for (int k = 0; k < NV; ++k) res[k] += part[(size_t)i * STRIDE + k];
     }
     block_allreduce<NV, NT>(res, smem);
 }

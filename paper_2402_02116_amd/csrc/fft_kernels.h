@@ -54,7 +54,7 @@ __global__ __launch_bounds__(256) void k_rows(const float2* in, float2* out,
                                               const float2* __restrict__ aux,
                                               double* __restrict__ partials, int nrows,
                                               int rows_per_sys, int F,
-                                              const SysState* __restrict__ st,
+                                              SysState* __restrict__ st,
                                               const float2* __restrict__ tw, GmEpi ge) {
     using S = FftShape<N, P>;
     constexpr int T = S::T;
@@ -83,7 +83,7 @@ __global__ __launch_bounds__(256) void k_rows(const float2* in, float2* out,
     RowLds lds{lds_dyn + (size_t)(q < F ? q : F) * PL};
     fft_run<N, P, INV, 1>(v, t, tw, lds);
 
-    double acc[kPartialNV] = {0.0, 0.0, 0.0, 0.0};
+    double acc[kPartialNV] = {};
     if (active) {
         const size_t base = (size_t)row * N;
 #pragma unroll
@@ -104,10 +104,15 @@ __global__ __launch_bounds__(256) void k_rows(const float2* in, float2* out,
                     acc[1] += (double)a.x * o.y - (double)a.y * o.x;
                 } else if constexpr (EPI == EPI_BICG_T) {
                     st_wt(out + i, o);
+                    const float2 h = aux[i];
                     acc[0] += (double)o.x * uu.x + (double)o.y * uu.y;
                     acc[1] += (double)o.x * uu.y - (double)o.y * uu.x;
                     acc[2] += (double)o.x * o.x + (double)o.y * o.y;
                     acc[3] += (double)uu.x * uu.x + (double)uu.y * uu.y;
+                    acc[4] += (double)h.x * uu.x + (double)h.y * uu.y;   // <r^, s>
+                    acc[5] += (double)h.x * uu.y - (double)h.y * uu.x;
+                    acc[6] += (double)h.x * o.x + (double)h.y * o.y;     // <r^, t>
+                    acc[7] += (double)h.x * o.y - (double)h.y * o.x;
                 } else if constexpr (EPI == EPI_TRUERES || EPI == EPI_GMRES_R0) {
                     const float2 b = aux[i];
                     const float2 rr = csub(b, o);
@@ -168,6 +173,10 @@ __global__ __launch_bounds__(256) void k_rows(const float2* in, float2* out,
             double* dst = partials + ((size_t)sys * nb + bi) * kPartialNV;
 #pragma unroll
             for (int k = 0; k < kPartialNV; ++k) dst[k] = acc[k];
+            // the iteration is complete up to its solution update
+            if constexpr (EPI == EPI_BICG_T) {
+                if (bi == 0) st[sys].iter += 1;
+            }
         }
     }
 }
@@ -313,7 +322,7 @@ inline hipError_t rows_launch(const float2* in, float2* out, const float2* u, co
     hipError_t e = allow_lds(k_rows<N, P, INV, EPI>, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_rows<N, P, INV, EPI>), dim3(blocks), dim3(g.threads), lds, s, in, out, u, aux,
-                       part, nrows, rps, g.F, st, tw, ge ? *ge : gz);
+                       part, nrows, rps, g.F, const_cast<SysState*>(st), tw, ge ? *ge : gz);
     return hipGetLastError();
 }
 

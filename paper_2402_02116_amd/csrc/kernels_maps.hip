@@ -91,7 +91,7 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__
                                                       double* __restrict__ out) {
     __shared__ double red[4 * 1];
     double r[1];
-    sum_partials<1, 256>(part, np, r, red);
+    sum_partials<1, 256, 1>(part, np, r, red);
     if (threadIdx.x == 0) *out = r[0];
 }
 

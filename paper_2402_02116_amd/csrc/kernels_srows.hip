@@ -1,7 +1,8 @@
 // Contrast stencil fused with the forward row transform (eqs. u_2, A, FFT):
 // a block owns F whole rows (both field components) of one system, loads
 // them with a 2-row halo into LDS (applying the BiCGSTAB update of the input
-// on the way, as k_body_force does), forms
+// on the way, and for the own rows the previous iteration's r and x updates,
+// as k_body_force does), forms
 //     b = w~^2 drho u + (1 / 4 dx^2) div'(dC : e'),   e' = raw central differences,
 // directly in the register layout of the row transform (each thread the
 // positions t + T m of one row), transforms the 2F rows, and writes the
@@ -27,12 +28,14 @@ __global__ __launch_bounds__(256) void k_srows(const float2* __restrict__ u, con
                                                float2* __restrict__ rhat, float2* __restrict__ out,
                                                const float* __restrict__ maps, ProbDev pd, int F,
                                                SysState* __restrict__ st, const double* __restrict__ part,
-                                               int np, const float2* __restrict__ tw) {
+                                               int np, const float2* __restrict__ tw,
+                                               const float2* __restrict__ a3, float2* __restrict__ xio,
+                                               float2* __restrict__ rout) {
     using S = FftShape<N, P>;
     constexpr int T = S::T;
     constexpr int PL = PaddedLen<N>::value;
     extern __shared__ float2 lds_dyn[];
-    __shared__ double red[4 * 4];
+    __shared__ double red[4 * kPartialNV];
 
     const int nz = pd.nz;
     const size_t plane = (size_t)N * nz;
@@ -40,19 +43,56 @@ __global__ __launch_bounds__(256) void k_srows(const float2* __restrict__ u, con
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int sys = blk / bps;
     const int z0 = (blk - sys * bps) * F;
-    if (st != nullptr && st[sys].status != ST_RUNNING) return;   // uniform over the block
+    if (st != nullptr) {   // uniform over the block
+        const int stw = st[sys].status;
+        if constexpr (VM == VM_PX) {
+            if (!closing_enters(stw, kStampPx)) return;
+        } else {
+            if (stw != ST_RUNNING) {
+                // the iteration's closing kernel is done: drop its tag
+                if (VM == VM_S && st_tag(stw) != 0 && z0 == 0 && threadIdx.x == 0) st[sys].status = st_code(stw);
+                return;
+            }
+        }
+    }
 
-    float2 c1 = make_float2(0.f, 0.f), c2 = make_float2(0.f, 0.f);
+    float2 c1 = make_float2(0.f, 0.f), c2 = make_float2(0.f, 0.f), c3 = make_float2(0.f, 0.f);
     bool fresh = false;
+    int step = SS_FULL;
     if constexpr (VM != VM_NONE) {
-        if (!stencil_scalars<VM>(st, sys, part, np, red, z0 == 0 && threadIdx.x == 0, c1, c2, fresh)) return;
+        step = stencil_scalars<VM>(st, sys, part, np, red, z0 == 0 && threadIdx.x == 0, c1, c2, c3, fresh);
+        if (step == SS_SKIP) return;
     }
     const size_t so = (size_t)sys * 2 * plane;
+    // VM_PX on an own cell: r = s - omega t, x += alpha p_old + omega s
+    auto close_iteration = [&](size_t gi) {
+        const float2 sv = u[so + gi], tv = a3[so + gi], pv = a1[so + gi];
+        const float2 rv = close_r(sv, tv, c2);
+        st_wt(rout + so + gi, rv);
+        st_wt(xio + so + gi, close_x(xio[so + gi], pv, sv, c3, c2));
+        if (fresh) st_wt(rhat + so + gi, rv);
+    };
+    if constexpr (VM == VM_PX) {
+        if (step == SS_XONLY) {   // stopped: the last solution update only
+            const int own = 2 * F * N;
+            for (int idx = threadIdx.x; idx < own; idx += blockDim.x) {
+                const int c = idx / (F * N);
+                const int rem = idx - c * F * N;
+                close_iteration(c * plane + (size_t)z0 * N + rem);
+            }
+            return;
+        }
+    }
     auto field = [&](size_t gi) -> float2 {
         if constexpr (VM == VM_NONE) {
             return u[so + gi];
         } else if constexpr (VM == VM_P) {
             const float2 rv = u[so + gi];
+            if (fresh) return rv;
+            const float2 pv = a1[so + gi], vv = a2[so + gi];
+            return cadd(rv, cmul(c1, csub(pv, cmul(c2, vv))));
+        } else if constexpr (VM == VM_PX) {
+            const float2 rv = close_r(u[so + gi], a3[so + gi], c2);
             if (fresh) return rv;
             const float2 pv = a1[so + gi], vv = a2[so + gi];
             return cadd(rv, cmul(c1, csub(pv, cmul(c2, vv))));
@@ -77,6 +117,8 @@ __global__ __launch_bounds__(256) void k_srows(const float2* __restrict__ u, con
                 st_wt(wout + so + gi, f);
                 if constexpr (VM == VM_P) {
                     if (fresh) st_wt(rhat + so + gi, f);
+                } else if constexpr (VM == VM_PX) {
+                    close_iteration(gi);
                 }
             }
         }
@@ -181,7 +223,7 @@ static hipError_t srows_launch(const StencilArgs& a, float2* out, const ProbDev&
     }
     const int blocks = pd.nsys * (pd.nz / F);
     hipLaunchKernelGGL((k_srows<N, P, VM>), dim3(blocks), dim3(256), lds, s, a.u, a.a1, a.a2, a.wout, a.rhat, out,
-                       a.maps, pd, F, st, a.part, a.np, tw);
+                       a.maps, pd, F, st, a.part, a.np, tw, a.a3, a.xio, a.rout);
     return hipGetLastError();
 }
 
@@ -190,6 +232,7 @@ static hipError_t srows_vm(int vm, const StencilArgs& a, float2* out, const Prob
                            const float2* tw, hipStream_t s) {
     if (vm == VM_NONE) return srows_launch<N, P, VM_NONE>(a, out, pd, st, tw, s);
     if (vm == VM_P) return srows_launch<N, P, VM_P>(a, out, pd, st, tw, s);
+    if (vm == VM_PX) return srows_launch<N, P, VM_PX>(a, out, pd, st, tw, s);
     return srows_launch<N, P, VM_S>(a, out, pd, st, tw, s);
 }
 
@@ -200,7 +243,9 @@ static hipError_t srows_vm(int vm, const StencilArgs& a, float2* out, const Prob
 
 hipError_t launch_srows(int vm, int P, const StencilArgs& a, float2* out, const ProbDev& pd, SysState* st,
                         const float2* tw, hipStream_t s) {
-    if (vm < 0 || vm > 2 || (vm != VM_NONE && !st) || (vm == VM_P && !a.rhat)) return hipErrorInvalidValue;
+    if (vm < 0 || vm > 3 || (vm != VM_NONE && !st) || ((vm == VM_P || vm == VM_PX) && !a.rhat) ||
+        (vm == VM_PX && (!a.a3 || !a.xio || !a.rout)))
+        return hipErrorInvalidValue;
     if (!row_points_ok(pd.nx, P) || srows_rows(pd.nx, pd.nz, P) == 0) return hipErrorInvalidValue;
     const float2* t = tw + twiddle_offset(pd.nx);
 #define FW_CASE(N, PP) \

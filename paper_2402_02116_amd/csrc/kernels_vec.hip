@@ -13,7 +13,6 @@ namespace fw {
 
 constexpr int kVecThreads = 256;
 constexpr int kVecEPT = 4;   // complex elements per thread in vector kernels
-constexpr double kOmegaLimit = 0.7;
 constexpr int kStallIters = 150;   // iterations without halving ||r|| before a restart
 
 // ------------------------------------------------------ contrast stencil --
@@ -44,7 +43,10 @@ __global__ __launch_bounds__(256) void k_body_force(const float2* __restrict__ u
                                                     const float* __restrict__ maps, ProbDev pd,
                                                     int S, SysState* __restrict__ st,
                                                     const double* __restrict__ part, int np,
-                                                    float2* __restrict__ rhat) {
+                                                    float2* __restrict__ rhat,
+                                                    const float2* __restrict__ a3,
+                                                    float2* __restrict__ xio,
+                                                    float2* __restrict__ rout) {
     static_assert(TX <= 64 && TZ % 4 == 0, "tile");
     constexpr int HX = TX + 4, HZ = TZ + 4, SX = TX + 2, SZ = TZ + 2;
     constexpr int KS = (SZ + 3) / 4;     // stress rows per thread
@@ -52,7 +54,7 @@ __global__ __launch_bounds__(256) void k_body_force(const float2* __restrict__ u
     constexpr int KH = HZ / 4;           // displacement rows per thread
     __shared__ float2 su[2][HZ][HX];
     __shared__ float2 ss[3][SZ][SX];
-    __shared__ double red[4 * 4];
+    __shared__ double red[4 * kPartialNV];
     const int nx = pd.nx, nz = pd.nz;
     const size_t plane = (size_t)nx * nz;
     const int ntx = nx / TX;
@@ -86,21 +88,60 @@ __global__ __launch_bounds__(256) void k_body_force(const float2* __restrict__ u
 
     const float sc = pd.inv4dx2;
     for (int sys = sys0; sys < sys0 + S && sys < pd.nsys; ++sys) {
-        if (st != nullptr && st[sys].status != ST_RUNNING) continue;   // uniform over the block
-        float2 c1 = make_float2(0.f, 0.f), c2 = make_float2(0.f, 0.f);
+        if (st != nullptr) {   // uniform over the block
+            const int stw = st[sys].status;
+            if constexpr (VM == VM_PX) {
+                if (!closing_enters(stw, kStampPx)) continue;
+            } else {
+                if (stw != ST_RUNNING) {
+                    // the iteration's closing kernel is done: drop its tag
+                    if (VM == VM_S && st_tag(stw) != 0 && tile == 0 && threadIdx.x == 0)
+                        st[sys].status = st_code(stw);
+                    continue;
+                }
+            }
+        }
+        float2 c1 = make_float2(0.f, 0.f), c2 = make_float2(0.f, 0.f), c3 = make_float2(0.f, 0.f);
         bool fresh = false;
+        int step = SS_FULL;
         if constexpr (VM != VM_NONE) {
-            if (!stencil_scalars<VM>(st, sys, part, np, red, tile == 0 && threadIdx.x == 0, c1, c2, fresh))
-                continue;
+            step = stencil_scalars<VM>(st, sys, part, np, red, tile == 0 && threadIdx.x == 0, c1, c2, c3, fresh);
+            if (step == SS_SKIP) continue;
         }
         const size_t so = (size_t)sys * 2 * plane;
         float2* bs = b + so;
+        // VM_PX on an own cell: r = s - omega t, x += alpha p_old + omega s
+        auto close_iteration = [&](size_t gi) {
+            const float2 sv = u[so + gi], tv = a3[so + gi], pv = a1[so + gi];
+            const float2 rv = close_r(sv, tv, c2);
+            st_wt(rout + so + gi, rv);
+            st_wt(xio + so + gi, close_x(xio[so + gi], pv, sv, c3, c2));
+            if (fresh) rhat[so + gi] = rv;
+        };
+        if constexpr (VM == VM_PX) {
+            if (step == SS_XONLY) {   // stopped: the last solution update only
+                if (lane) {
+#pragma unroll
+                    for (int k = 0; k < KB; ++k) {
+                        const size_t gi = (size_t)(z0 + tg + 4 * k) * nx + x0 + tx;
+                        close_iteration(gi);
+                        close_iteration(plane + gi);
+                    }
+                }
+                continue;
+            }
+        }
         // input field value at global index gi of this system (comp offset included)
         auto field = [&](size_t gi) -> float2 {
             if constexpr (VM == VM_NONE) {
                 return u[so + gi];
             } else if constexpr (VM == VM_P) {
                 const float2 rv = u[so + gi];
+                if (fresh) return rv;
+                const float2 pv = a1[so + gi], vv = a2[so + gi];
+                return cadd(rv, cmul(c1, csub(pv, cmul(c2, vv))));
+            } else if constexpr (VM == VM_PX) {
+                const float2 rv = close_r(u[so + gi], a3[so + gi], c2);
                 if (fresh) return rv;
                 const float2 pv = a1[so + gi], vv = a2[so + gi];
                 return cadd(rv, cmul(c1, csub(pv, cmul(c2, vv))));
@@ -126,6 +167,9 @@ __global__ __launch_bounds__(256) void k_body_force(const float2* __restrict__ u
                                 rhat[so + row + x0 + tx] = f0;
                                 rhat[so + plane + row + x0 + tx] = f1;
                             }
+                        } else if constexpr (VM == VM_PX) {
+                            close_iteration(row + x0 + tx);
+                            close_iteration(plane + row + x0 + tx);
                         }
                     }
                 }
@@ -220,7 +264,7 @@ static void body_force_launch(const StCfg& c, const StencilArgs& a, const ProbDe
     S = std::min(S, std::max(pd.nsys, 1));
     const int blocks = ntiles * ((pd.nsys + S - 1) / S);
     hipLaunchKernelGGL((k_body_force<TX, TZ, VM>), dim3(blocks), dim3(256), 0, s, a.u, a.a1, a.a2, a.wout,
-                       a.b, a.maps, pd, S, st, a.part, a.np, a.rhat);
+                       a.b, a.maps, pd, S, st, a.part, a.np, a.rhat, a.a3, a.xio, a.rout);
 }
 
 template <int TX, int TZ>
@@ -228,6 +272,7 @@ static void body_force_vm(int vm, const StCfg& c, const StencilArgs& a, const Pr
                           hipStream_t s) {
     if (vm == VM_NONE) body_force_launch<TX, TZ, VM_NONE>(c, a, pd, st, s);
     else if (vm == VM_P) body_force_launch<TX, TZ, VM_P>(c, a, pd, st, s);
+    else if (vm == VM_PX) body_force_launch<TX, TZ, VM_PX>(c, a, pd, st, s);
     else body_force_launch<TX, TZ, VM_S>(c, a, pd, st, s);
 }
 
@@ -241,7 +286,8 @@ static void body_force_tz(int vm, const StCfg& c, const StencilArgs& a, const Pr
 
 hipError_t launch_stencil(int vm, const StCfg& c, const StencilArgs& a, const ProbDev& pd, SysState* st,
                           hipStream_t s) {
-    if (!st_cfg_ok(pd.nx, pd.nz, c) || vm < 0 || vm > 2 || (vm != 0 && !st) || (vm == VM_P && !a.rhat))
+    if (!st_cfg_ok(pd.nx, pd.nz, c) || vm < 0 || vm > 3 || (vm != 0 && !st) || ((vm == VM_P || vm == VM_PX) && !a.rhat) ||
+        (vm == VM_PX && (!a.a3 || !a.xio || !a.rout)))
         return hipErrorInvalidValue;
     switch (tile_x(pd.nx)) {
         case 64: body_force_tz<64>(vm, c, a, pd, st, s); break;
@@ -358,89 +404,60 @@ __global__ __launch_bounds__(256) void k_bicg_state_init(SysState* __restrict__ 
 }
 
 
-// omega (see below);  x += alpha p + omega s;  r = s - omega t;
-// partials <rhat, r>, ||r||^2.
-__global__ __launch_bounds__(256) void k_bicg_xr(float2* __restrict__ x, float2* __restrict__ r,
-                                                 const float2* __restrict__ rhat,
-                                                 const float2* __restrict__ p,
-                                                 const float2* __restrict__ sv,
-                                                 const float2* __restrict__ t,
-                                                 const double* __restrict__ partT, int npT,
-                                                 double* __restrict__ partXR,
-                                                 SysState* __restrict__ st, int n, int nb) {
-    __shared__ double red[4 * 4];
+// End of a chunk of iterations: the stop decision of the last iteration from
+// its t-pass records (so that the host sees every stopped system), with the
+// closing updates x += alpha p + omega s, r = s - omega t owed to a stopped
+// system.  A running system gets its stagnation bookkeeping only; its closing
+// updates are left to the next direction-update stencil.
+__global__ __launch_bounds__(256) void k_bicg_close(float2* __restrict__ x, float2* __restrict__ r,
+                                                    const float2* __restrict__ p,
+                                                    const float2* __restrict__ sv,
+                                                    const float2* __restrict__ t,
+                                                    const double* __restrict__ partT, int npT,
+                                                    SysState* __restrict__ st, int n, int nb) {
+    __shared__ double red[4 * kPartialNV];
     const VecIdx vi = vec_idx(nb);
-    if (st[vi.sys].status != ST_RUNNING) return;
-    double q[4];
-    sum_partials<4, 256>(partT + (size_t)vi.sys * npT * kPartialNV, npT, q, red);
-    const SysState& s = st[vi.sys];
-    const dcomplex alpha{s.alpha_re, s.alpha_im};
-    // omega = <t, s> / <t, t>, enlarged when t and s are far from parallel
-    // (|<t, s>| < 0.7 |t| |s|): the finite-precision safeguard of Sleijpen and
-    // van der Vorst (1995), which keeps the BiCG part from stalling.
-    dcomplex omega{0.0, 0.0};
-    if (q[2] != 0.0) {
-        omega = dcomplex{q[0] / q[2], q[1] / q[2]};
-        const double ts = sqrt(q[0] * q[0] + q[1] * q[1]);
-        const double c = (q[3] > 0.0) ? ts / sqrt(q[2] * q[3]) : 1.0;
-        if (c < kOmegaLimit && c > 0.0) {
-            omega.re *= kOmegaLimit / c;
-            omega.im *= kOmegaLimit / c;
+    if (!closing_enters(st[vi.sys].status, kStampClose)) return;   // uniform over the block
+    double q[kPartialNV];
+    sum_partials<kPartialNV, 256>(partT + (size_t)vi.sys * npT * kPartialNV, npT, q, red);
+    SysState& z = st[vi.sys];
+    const OmegaStep o = omega_step(q);
+    const int code = close_code(z, o);
+    const bool writer = vi.bi == 0 && threadIdx.x == 0;
+    if (code == ST_RUNNING) {
+        if (writer) {
+            // stagnation: the best residual norm has not halved for kStallIters
+            // iterations -> the next iteration restarts the recurrence (r^ = r)
+            z.rnorm2 = o.rr;
+            if (o.rr < 0.25 * z.best2) {
+                z.best2 = o.rr;
+                z.best_iter = z.iter;
+            } else if (z.iter - z.best_iter >= kStallIters) {
+                z.fresh_at = z.iter + 1;
+                z.best2 = o.rr;
+                z.best_iter = z.iter;
+            }
         }
+        return;
     }
-    const float2 af = tof(alpha), of = tof(omega);
-    const size_t off = (size_t)vi.sys * n;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (code != ST_NONFINITE) {
+        const float2 af = tof(dcomplex{z.alpha_re, z.alpha_im}), of = tof(o.omega);
+        const size_t off = (size_t)vi.sys * n;
 #pragma unroll
-    for (int e = 0; e < kVecEPT; ++e) {
-        const int i = vi.i0 + e * kVecThreads + threadIdx.x;
-        if (i < n) {
-            const float2 sv_ = sv[off + i], tv = t[off + i];
-            st_wt(x + off + i, cadd(x[off + i], cadd(cmul(af, p[off + i]), cmul(of, sv_))));
-            const float2 rn = csub(sv_, cmul(of, tv));
-            st_wt(r + off + i, rn);
-            const float2 h = rhat[off + i];
-            acc[0] += (double)h.x * rn.x + (double)h.y * rn.y;
-            acc[1] += (double)h.x * rn.y - (double)h.y * rn.x;
-            acc[2] += (double)rn.x * rn.x + (double)rn.y * rn.y;
+        for (int e = 0; e < kVecEPT; ++e) {
+            const int i = vi.i0 + e * kVecThreads + threadIdx.x;
+            if (i < n) {
+                const float2 svv = sv[off + i];
+                st_wt(r + off + i, close_r(svv, t[off + i], of));
+                st_wt(x + off + i, close_x(x[off + i], p[off + i], svv, af, of));
+            }
         }
     }
-    block_allreduce<4, 256>(acc, red);
-    if (threadIdx.x == 0) {
-        double* d = partXR + ((size_t)vi.sys * nb + vi.bi) * kPartialNV;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) d[k] = acc[k];
-        if (vi.bi == 0) {
-            st[vi.sys].omega_re = omega.re;
-            st[vi.sys].omega_im = omega.im;
-            st[vi.sys].iter = s.iter + 1;
-        }
-    }
-}
-
-// End-of-chunk test so that the host sees systems that converged in the last
-// iteration of a chunk.
-__global__ __launch_bounds__(256) void k_bicg_check(SysState* __restrict__ st,
-                                                    const double* __restrict__ partXR, int np) {
-    __shared__ double red[4 * 4];
-    const int sys = blockIdx.x;
-    if (st[sys].status != ST_RUNNING) return;
-    double q[4];
-    sum_partials<4, 256>(partXR + (size_t)sys * np * kPartialNV, np, q, red);
-    if (threadIdx.x == 0) {
-        SysState& z = st[sys];
-        z.rnorm2 = q[2];
-        if (bicg_stop(st, sys, q[2], true)) return;
-        // stagnation: the best residual norm has not halved for kStallIters
-        // iterations -> the next iteration restarts the recurrence (r^ = r)
-        if (q[2] < 0.25 * z.best2) {
-            z.best2 = q[2];
-            z.best_iter = z.iter;
-        } else if (z.iter - z.best_iter >= kStallIters) {
-            z.fresh_at = z.iter + 1;
-            z.best2 = q[2];
-            z.best_iter = z.iter;
-        }
+    if (writer) {
+        z.status = st_stamp(code, kStampClose);
+        z.omega_re = o.omega.re;
+        z.omega_im = o.omega.im;
+        z.rnorm2 = o.rr;
     }
 }
 
@@ -470,7 +487,7 @@ __global__ __launch_bounds__(256) void k_bicg_restart_mark(SysState* __restrict_
                                                            double limit2, int max_restarts) {
     __shared__ double red[4 * 4];
     const int sys = blockIdx.x;
-    const int status = st[sys].status;
+    const int status = st_code(st[sys].status);
     if (status != ST_CONVERGED && status != ST_BREAKDOWN) return;
     double q[4];
     sum_partials<4, 256>(partTR + (size_t)sys * np * kPartialNV, np, q, red);
@@ -525,18 +542,11 @@ hipError_t launch_bicg_state_init(SysState* st, const double* partXR, const doub
     return hipGetLastError();
 }
 
-hipError_t launch_bicg_xr(float2* x, float2* r, const float2* rhat, const float2* p,
-                          const float2* sv, const float2* t, const double* partT, int npT,
-                          double* partXR, SysState* st, int nsys, int n, hipStream_t s) {
+hipError_t launch_bicg_close(float2* x, float2* r, const float2* p, const float2* sv, const float2* t,
+                             const double* partT, int npT, SysState* st, int nsys, int n, hipStream_t s) {
     const int nb = vec_blocks_per_sys(n);
-    hipLaunchKernelGGL(k_bicg_xr, dim3(nsys * nb), dim3(kVecThreads), 0, s, x, r, rhat, p, sv, t,
-                       partT, npT, partXR, st, n, nb);
-    return hipGetLastError();
-}
-
-hipError_t launch_bicg_check(SysState* st, const double* partXR, int npXR, int nsys,
-                             hipStream_t s) {
-    hipLaunchKernelGGL(k_bicg_check, dim3(nsys), dim3(256), 0, s, st, partXR, npXR);
+    hipLaunchKernelGGL(k_bicg_close, dim3(nsys * nb), dim3(kVecThreads), 0, s, x, r, p, sv, t, partT, npT, st, n,
+                       nb);
     return hipGetLastError();
 }
 

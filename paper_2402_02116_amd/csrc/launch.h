@@ -13,7 +13,8 @@ enum RowEpilogue : int {
     EPI_STORE = 0,     // out = y
     EPI_APPLY = 1,     // out = u - y                          (A u)
     EPI_BICG_V = 2,    // out = u - y;  partial <aux, out>      (v = A p, <r^, v>)
-    EPI_BICG_T = 3,    // out = u - y;  partials <out, u>, ||out||^2, ||u||^2   (t = A s)
+    EPI_BICG_T = 3,    // out = u - y;  partials <out, u>, ||out||^2, ||u||^2, <aux, u>, <aux, out>
+                       //   (t = A s, aux = r^); block 0 of each system counts the iteration
     EPI_TRUERES = 4,   // out = aux - (u - y); partial ||out||^2       (r = b - A x)
     EPI_ARNOLDI = 5,   // out = u - y = w; partial <basis_l, w>, l < nv
     EPI_GMRES_R0 = 6,  // out = aux - (u - y); partial ||out||^2, ||aux||^2
@@ -26,7 +27,6 @@ struct GmEpi {
     int nv;            // basis vectors to project on
     double* part;      // [sys][blocks][kGmRec] partial records
 };
-constexpr int kPartialNV = 4;   // doubles per partial-sum record
 
 enum ColMode : int { COL_GREEN = 0, COL_FWD = 1, COL_INV = 2 };
 
@@ -94,10 +94,22 @@ hipError_t launch_cols(int mode, const ColCfg& c, float2* data, const ProbDev& p
 // Body force b = w~^2 drho u + div_h(dC : E_h u) of one problem.
 hipError_t launch_body_force(const StCfg& c, const float2* u, float2* b, const float* maps,
                              const ProbDev& pd, const SysState* st, hipStream_t s);
+// Vector update fused into a stencil's load of its input field:
+//   VM_NONE: the input is u itself;
+//   VM_P:    p = r + beta (p_old - omega v)   (BiCGSTAB direction update)
+//   VM_S:    s = r - alpha v                  (BiCGSTAB intermediate residual)
+//   VM_PX:   the previous iteration's closing updates folded into the next
+//            direction update: r = s - omega t, x += alpha p_old + omega s
+//            (own cells), then p = r + beta (p_old - omega v)
+enum StencilVec : int { VM_NONE = 0, VM_P = 1, VM_S = 2, VM_PX = 3 };
+
 // The stencil with a BiCGSTAB vector update fused into its input (vm: 0 none,
 // 1 p = r + beta (p_old - omega v) [u = r, a1 = p_old, a2 = v, wout = p_new,
 // part = <rhat, r> records], 2 s = r - alpha v [u = r, a1 = v, wout = s,
-// part = <rhat, v> records]).
+// part = <rhat, v> records], 3 the previous iteration's r = s - omega t and
+// x += alpha p_old + omega s, then p = r + beta (p_old - omega v) [u = s,
+// a1 = p_old, a2 = v, a3 = t, xio = x, rout = r, wout = p_new, part = the
+// t-pass records]).
 struct StencilArgs {
     const float2* u;
     const float2* a1;
@@ -107,7 +119,10 @@ struct StencilArgs {
     const float* maps;
     const double* part;
     int np;
-    float2* rhat = nullptr;   // vm 1: shadow residual, set to r when the iteration restarts
+    float2* rhat = nullptr;        // vm 1, 3: shadow residual, set to r when the iteration restarts
+    const float2* a3 = nullptr;    // vm 3: t
+    float2* xio = nullptr;         // vm 3: x (updated)
+    float2* rout = nullptr;        // vm 3: r (written)
 };
 hipError_t launch_stencil(int vm, const StCfg& c, const StencilArgs& a, const ProbDev& pd, SysState* st,
                           hipStream_t s);
@@ -126,10 +141,8 @@ hipError_t launch_bicg_init(const float2* b, const float2* r0, float2* x, float2
                             bool zero_x, hipStream_t s);
 hipError_t launch_bicg_state_init(SysState* st, const double* partXR, const double* partB,
                                   int nsys, int npart, double rtol, int maxit, hipStream_t s);
-hipError_t launch_bicg_xr(float2* x, float2* r, const float2* rhat, const float2* p,
-                          const float2* sv, const float2* t, const double* partT, int npT,
-                          double* partXR, SysState* st, int nsys, int n, hipStream_t s);
-hipError_t launch_bicg_check(SysState* st, const double* partXR, int npXR, int nsys, hipStream_t s);
+hipError_t launch_bicg_close(float2* x, float2* r, const float2* p, const float2* sv, const float2* t,
+                             const double* partT, int npT, SysState* st, int nsys, int n, hipStream_t s);
 hipError_t launch_bicg_restart_mark(SysState* st, const double* partTR, int npTR, int nsys, double limit2,
                                     int max_restarts, hipStream_t s);
 hipError_t launch_bicg_restart(SysState* st, int nsys, hipStream_t s);
