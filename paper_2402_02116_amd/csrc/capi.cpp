@@ -110,6 +110,10 @@ struct fwils_plan_s {
     hipGraphExec_t gm_cycle = nullptr;
     double gm_rtol = 0.0;           // tolerance the cycle graph was built for
     SysState* host_state = nullptr;   // pinned
+    // pinned copies of the state after two consecutive chunks, and the events
+    // that mark their arrival (the host checks one chunk while the next runs)
+    SysState* host_pipe = nullptr;
+    hipEvent_t pipe_ev[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -377,15 +381,53 @@ fwils_status bicg_solve_ws(fwils_plan pl, const float2* b, bool use_x0, double r
         const int max_chunks = maxit / kChunkIters + 2;
         bool done = false;
         FW_TRY(all_done(done));
+        if (done) return FWILS_OK;
         if (!(flags & FWILS_SOLVE_NOGRAPH)) FW_TRY(build_chunk_graphs(pl));
-        for (int c = 0; c < max_chunks && !done; ++c) {
+        // Chunk c + 1 is queued before the state after chunk c is inspected, so
+        // the device does not wait for the host between chunks; a chunk queued
+        // after every system stopped only runs kernels that exit at once.  The
+        // speculation is skipped when the residual trend says the chunk just
+        // queued is likely the last one.
+        SysState* hp[2] = {pl->host_pipe, pl->host_pipe + nst};
+        auto launch = [&](int c) -> fwils_status {
             if (flags & FWILS_SOLVE_NOGRAPH) {
                 for (const ProbHost& P : pl->probs)
                     FW_HIP(bicg_chunk(pl, P, make_view(pl, P, 0, P.p.nsys), c == 0, s));
             } else {
                 FW_HIP(hipGraphLaunch(c == 0 ? pl->chunk_first : pl->chunk, s));
             }
-            FW_TRY(all_done(done));
+            FW_HIP(hipMemcpyAsync(hp[c & 1], pl->state, nst * sizeof(SysState), hipMemcpyDeviceToHost, s));
+            FW_HIP(hipEventRecord(pl->pipe_ev[c & 1], s));
+            return FWILS_OK;
+        };
+        std::vector<double> prev(nst);
+        for (size_t i = 0; i < nst; ++i) prev[i] = pl->host_state[i].rnorm2;
+        int launched = 0;
+        bool last_likely = false;
+        FW_TRY(launch(0));
+        launched = 1;
+        for (int c = 0; c < max_chunks; ++c) {
+            if (launched == c + 1 && c + 1 < max_chunks && !last_likely) {
+                FW_TRY(launch(c + 1));
+                ++launched;
+            }
+            FW_HIP(hipEventSynchronize(pl->pipe_ev[c & 1]));
+            const SysState* h = hp[c & 1];
+            done = true;
+            last_likely = true;
+            for (size_t i = 0; i < nst; ++i) {
+                if (h[i].status != ST_RUNNING) continue;
+                done = false;
+                // geometric extrapolation of ||r||^2 over one more chunk
+                const double cur = h[i].rnorm2, ratio = prev[i] > 0.0 ? cur / prev[i] : 1.0;
+                if (!(cur * ratio <= h[i].tol2)) last_likely = false;
+                prev[i] = cur;
+            }
+            if (done) break;
+            if (launched == c + 1 && c + 1 < max_chunks) {
+                FW_TRY(launch(c + 1));
+                ++launched;
+            }
         }
         return FWILS_OK;
     };
@@ -706,6 +748,9 @@ void fwils_plan_destroy(fwils_plan plan) {
     if (!plan) return;
     drop_graphs(plan);
     if (plan->host_state) (void)hipHostFree(plan->host_state);
+    if (plan->host_pipe) (void)hipHostFree(plan->host_pipe);
+    for (auto& e : plan->pipe_ev)
+        if (e) (void)hipEventDestroy(e);
     delete plan;
 }
 
@@ -745,6 +790,9 @@ fwils_status fwils_set_workspace(fwils_plan plan, void* dev, size_t bytes) {
     if (!plan->host_state) {
         FW_HIP(hipHostMalloc((void**)&plan->host_state, plan->total_sys * sizeof(SysState),
                              hipHostMallocDefault));
+        FW_HIP(hipHostMalloc((void**)&plan->host_pipe, 2 * plan->total_sys * sizeof(SysState),
+                             hipHostMallocDefault));
+        for (auto& e : plan->pipe_ev) FW_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     }
     char* w = (char*)dev;
     plan->ws = w;

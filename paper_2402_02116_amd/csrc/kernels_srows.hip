@@ -83,42 +83,62 @@ __global__ __launch_bounds__(256) void k_srows(const float2* __restrict__ u, con
             return;
         }
     }
-    auto field = [&](size_t gi) -> float2 {
-        if constexpr (VM == VM_NONE) {
-            return u[so + gi];
-        } else if constexpr (VM == VM_P) {
-            const float2 rv = u[so + gi];
-            if (fresh) return rv;
-            const float2 pv = a1[so + gi], vv = a2[so + gi];
-            return cadd(rv, cmul(c1, csub(pv, cmul(c2, vv))));
-        } else if constexpr (VM == VM_PX) {
-            const float2 rv = close_r(u[so + gi], a3[so + gi], c2);
-            if (fresh) return rv;
-            const float2 pv = a1[so + gi], vv = a2[so + gi];
-            return cadd(rv, cmul(c1, csub(pv, cmul(c2, vv))));
-        } else {
-            return csub(u[so + gi], cmul(c1, a1[so + gi]));
-        }
-    };
-
-    // 1. the 2F + 8 rows (F + 4 per component) of the input into LDS
+    // 1. the 2F + 8 rows (F + 4 per component) of the input into LDS, kB
+    //    elements per thread at a time: every load of a batch is issued before
+    //    its stores (out-of-range slots load element 0 and are dropped)
     const int HR = F + 4;
     float2* su = lds_dyn;                           // [2][HR][N]
     const int total = 2 * HR * N;
-    for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-        const int c = idx / (HR * N);
-        const int rem = idx - c * HR * N;
-        const int tr = rem / N, x = rem - tr * N;
-        const size_t gi = c * plane + (size_t)wrapi(z0 - 2 + tr, nz) * N + x;
-        const float2 f = field(gi);
-        su[idx] = f;
+    constexpr int kB = VM == VM_PX ? 4 : 8;
+    for (int i0 = threadIdx.x; i0 < total; i0 += kB * 256) {
+        size_t gi[kB];
+        bool ok[kB], own[kB];
+        float2 f[kB], sv[kB], pv[kB], rv[kB], xv[kB];
+#pragma unroll
+        for (int j = 0; j < kB; ++j) {
+            const int idx = i0 + j * 256;
+            ok[j] = idx < total;
+            const int id = ok[j] ? idx : 0;
+            const int c = id / (HR * N);
+            const int rem = id - c * HR * N;
+            const int tr = rem / N, x = rem - tr * N;
+            gi[j] = so + c * plane + (size_t)wrapi(z0 - 2 + tr, nz) * N + x;
+            own[j] = ok[j] && tr >= 2 && tr < F + 2;
+        }
+#pragma unroll
+        for (int j = 0; j < kB; ++j) {
+            const size_t g = gi[j];
+            if constexpr (VM == VM_NONE) {
+                f[j] = u[g];
+            } else if constexpr (VM == VM_P) {
+                const float2 r0 = u[g], p0 = a1[g], v0 = a2[g];
+                f[j] = fresh ? r0 : cadd(r0, cmul(c1, csub(p0, cmul(c2, v0))));
+            } else if constexpr (VM == VM_PX) {
+                sv[j] = u[g];
+                const float2 t0 = a3[g];
+                pv[j] = a1[g];
+                const float2 v0 = a2[g];
+                xv[j] = own[j] ? xio[g] : make_float2(0.f, 0.f);
+                rv[j] = close_r(sv[j], t0, c2);
+                f[j] = fresh ? rv[j] : cadd(rv[j], cmul(c1, csub(pv[j], cmul(c2, v0))));
+            } else {
+                f[j] = csub(u[g], cmul(c1, a1[g]));
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kB; ++j)
+            if (ok[j]) su[i0 + j * 256] = f[j];
         if constexpr (VM != VM_NONE) {
-            if (tr >= 2 && tr < F + 2) {            // the block's own rows
-                st_wt(wout + so + gi, f);
+#pragma unroll
+            for (int j = 0; j < kB; ++j) {
+                if (!own[j]) continue;              // the block's own rows
+                st_wt(wout + gi[j], f[j]);
                 if constexpr (VM == VM_P) {
-                    if (fresh) st_wt(rhat + so + gi, f);
+                    if (fresh) st_wt(rhat + gi[j], f[j]);
                 } else if constexpr (VM == VM_PX) {
-                    close_iteration(gi);
+                    st_wt(rout + gi[j], rv[j]);
+                    st_wt(xio + gi[j], close_x(xv[j], pv[j], sv[j], c3, c2));
+                    if (fresh) st_wt(rhat + gi[j], rv[j]);
                 }
             }
         }
@@ -140,43 +160,75 @@ __global__ __launch_bounds__(256) void k_srows(const float2* __restrict__ u, con
     const float* mrho = maps + 4 * plane;
     auto U = [&](int cc, int dz, int x) -> float2 { return su[(cc * HR + zl + 2 + dz) * N + wrapi(x, N)]; };
     const size_t zr = (size_t)z * N, zu = (size_t)wrapi(z - 1, nz) * N, zd = (size_t)wrapi(z + 1, nz) * N;
+    // the map values of kG points are loaded before any of them is used
+    constexpr int kG = P % 8 == 0 ? 8 : (P % 6 == 0 ? 6 : 4);
+    static_assert(P % kG == 0, "points per thread");
     float2 v[1][P];
+    if (active && c == 0) {
 #pragma unroll
-    for (int m = 0; m < P; ++m) {
-        const int x = t + T * m;
-        float2 b = make_float2(0.f, 0.f);
-        if (active) {
-            const int xl = wrapi(x - 1, N), xr = wrapi(x + 1, N);
-            const float2 wr = cscale(pd.w2, mrho[zr + x]);
-            if (c == 0) {
-                // sigma_1 at (z, x +- 1), sigma_5 at (z +- 1, x)
-                const float2 exr = csub(U(0, 0, x + 2), U(0, 0, x)), ezr = csub(U(1, 1, x + 1), U(1, -1, x + 1));
-                const float2 exl = csub(U(0, 0, x), U(0, 0, x - 2)), ezl = csub(U(1, 1, x - 1), U(1, -1, x - 1));
-                const float2 s1r = make_float2(mc11[zr + xr] * exr.x + mc13[zr + xr] * ezr.x,
-                                               mc11[zr + xr] * exr.y + mc13[zr + xr] * ezr.y);
-                const float2 s1l = make_float2(mc11[zr + xl] * exl.x + mc13[zr + xl] * ezl.x,
-                                               mc11[zr + xl] * exl.y + mc13[zr + xl] * ezl.y);
-                const float2 exzd = cadd(csub(U(0, 2, x), U(0, 0, x)), csub(U(1, 1, x + 1), U(1, 1, x - 1)));
-                const float2 exzu = cadd(csub(U(0, 0, x), U(0, -2, x)), csub(U(1, -1, x + 1), U(1, -1, x - 1)));
-                const float2 dx1 = csub(s1r, s1l);
-                const float2 dz5 = csub(cscale(exzd, mc55[zd + x]), cscale(exzu, mc55[zu + x]));
-                b = cadd(cmul(wr, U(0, 0, x)), cscale(cadd(dx1, dz5), sc));
-            } else {
-                // sigma_5 at (z, x +- 1), sigma_3 at (z +- 1, x)
-                const float2 exzr = cadd(csub(U(0, 1, x + 1), U(0, -1, x + 1)), csub(U(1, 0, x + 2), U(1, 0, x)));
-                const float2 exzl = cadd(csub(U(0, 1, x - 1), U(0, -1, x - 1)), csub(U(1, 0, x), U(1, 0, x - 2)));
-                const float2 exd = csub(U(0, 1, x + 1), U(0, 1, x - 1)), ezd = csub(U(1, 2, x), U(1, 0, x));
-                const float2 exu = csub(U(0, -1, x + 1), U(0, -1, x - 1)), ezu = csub(U(1, 0, x), U(1, -2, x));
-                const float2 s3d = make_float2(mc13[zd + x] * exd.x + mc33[zd + x] * ezd.x,
-                                               mc13[zd + x] * exd.y + mc33[zd + x] * ezd.y);
-                const float2 s3u = make_float2(mc13[zu + x] * exu.x + mc33[zu + x] * ezu.x,
-                                               mc13[zu + x] * exu.y + mc33[zu + x] * ezu.y);
-                const float2 dx5 = csub(cscale(exzr, mc55[zr + xr]), cscale(exzl, mc55[zr + xl]));
-                const float2 dz3 = csub(s3d, s3u);
-                b = cadd(cmul(wr, U(1, 0, x)), cscale(cadd(dx5, dz3), sc));
-            }
+      for (int m0 = 0; m0 < P; m0 += kG) {
+        float rh[kG], a11r[kG], a13r[kG], a11l[kG], a13l[kG], a55d[kG], a55u[kG];
+#pragma unroll
+        for (int g = 0; g < kG; ++g) {
+            const int m = g;
+            const int x = t + T * (m0 + g), xl = wrapi(x - 1, N), xr = wrapi(x + 1, N);
+            rh[m] = mrho[zr + x];
+            a11r[m] = mc11[zr + xr];
+            a13r[m] = mc13[zr + xr];
+            a11l[m] = mc11[zr + xl];
+            a13l[m] = mc13[zr + xl];
+            a55d[m] = mc55[zd + x];
+            a55u[m] = mc55[zu + x];
         }
-        v[0][m] = b;
+#pragma unroll
+        for (int m = 0; m < kG; ++m) {
+            // sigma_1 at (z, x +- 1), sigma_5 at (z +- 1, x)
+            const int x = t + T * (m0 + m);
+            const float2 exr = csub(U(0, 0, x + 2), U(0, 0, x)), ezr = csub(U(1, 1, x + 1), U(1, -1, x + 1));
+            const float2 exl = csub(U(0, 0, x), U(0, 0, x - 2)), ezl = csub(U(1, 1, x - 1), U(1, -1, x - 1));
+            const float2 s1r = make_float2(a11r[m] * exr.x + a13r[m] * ezr.x, a11r[m] * exr.y + a13r[m] * ezr.y);
+            const float2 s1l = make_float2(a11l[m] * exl.x + a13l[m] * ezl.x, a11l[m] * exl.y + a13l[m] * ezl.y);
+            const float2 exzd = cadd(csub(U(0, 2, x), U(0, 0, x)), csub(U(1, 1, x + 1), U(1, 1, x - 1)));
+            const float2 exzu = cadd(csub(U(0, 0, x), U(0, -2, x)), csub(U(1, -1, x + 1), U(1, -1, x - 1)));
+            const float2 dx1 = csub(s1r, s1l);
+            const float2 dz5 = csub(cscale(exzd, a55d[m]), cscale(exzu, a55u[m]));
+            v[0][m0 + m] = cadd(cmul(cscale(pd.w2, rh[m]), U(0, 0, x)), cscale(cadd(dx1, dz5), sc));
+        }
+      }
+    } else if (active) {
+#pragma unroll
+      for (int m0 = 0; m0 < P; m0 += kG) {
+        float rh[kG], a13d[kG], a33d[kG], a13u[kG], a33u[kG], a55r[kG], a55l[kG];
+#pragma unroll
+        for (int g = 0; g < kG; ++g) {
+            const int m = g;
+            const int x = t + T * (m0 + g), xl = wrapi(x - 1, N), xr = wrapi(x + 1, N);
+            rh[m] = mrho[zr + x];
+            a13d[m] = mc13[zd + x];
+            a33d[m] = mc33[zd + x];
+            a13u[m] = mc13[zu + x];
+            a33u[m] = mc33[zu + x];
+            a55r[m] = mc55[zr + xr];
+            a55l[m] = mc55[zr + xl];
+        }
+#pragma unroll
+        for (int m = 0; m < kG; ++m) {
+            // sigma_5 at (z, x +- 1), sigma_3 at (z +- 1, x)
+            const int x = t + T * (m0 + m);
+            const float2 exzr = cadd(csub(U(0, 1, x + 1), U(0, -1, x + 1)), csub(U(1, 0, x + 2), U(1, 0, x)));
+            const float2 exzl = cadd(csub(U(0, 1, x - 1), U(0, -1, x - 1)), csub(U(1, 0, x), U(1, 0, x - 2)));
+            const float2 exd = csub(U(0, 1, x + 1), U(0, 1, x - 1)), ezd = csub(U(1, 2, x), U(1, 0, x));
+            const float2 exu = csub(U(0, -1, x + 1), U(0, -1, x - 1)), ezu = csub(U(1, 0, x), U(1, -2, x));
+            const float2 s3d = make_float2(a13d[m] * exd.x + a33d[m] * ezd.x, a13d[m] * exd.y + a33d[m] * ezd.y);
+            const float2 s3u = make_float2(a13u[m] * exu.x + a33u[m] * ezu.x, a13u[m] * exu.y + a33u[m] * ezu.y);
+            const float2 dx5 = csub(cscale(exzr, a55r[m]), cscale(exzl, a55l[m]));
+            const float2 dz3 = csub(s3d, s3u);
+            v[0][m0 + m] = cadd(cmul(cscale(pd.w2, rh[m]), U(1, 0, x)), cscale(cadd(dx5, dz3), sc));
+        }
+      }
+    } else {
+#pragma unroll
+        for (int m = 0; m < P; ++m) v[0][m] = make_float2(0.f, 0.f);
     }
     __syncthreads();   // the tile is read; its LDS now holds the transform's rows
 
