@@ -24,14 +24,20 @@
  * One plan holds one or more problems ("grids"); each has nsys systems
  * (sources) that share its grid, background, frequency and contrast.
  *
+ * Precision.  A plan is complex64 (FWILS_C64: complex64 fields and data,
+ * float32 maps) or complex128 (FWILS_C128: complex128 fields and data,
+ * float64 maps, the FP64 reference of the same path).  Krylov scalars, inner
+ * products and norms are FP64 in both.  "complex" and "real" below are the
+ * plan's types.
+ *
  * Memory layout (all row-major, x fastest):
- *   field      complex64 [nsys][2][nz][nx], component 0 = u_x, 1 = u_z,
+ *   field      complex [nsys][2][nz][nx], component 0 = u_x, 1 = u_z,
  *              interleaved (re, im).  A plan-level field is the
  *              concatenation of its problems' fields in problem order;
  *              fwils_field_elems gives its length in complex elements.
- *   maps       float32 [5][nz][nx], absolute units, order
+ *   maps       real [5][nz][nx], absolute units, order
  *              (dC11, dC13, dC33, dC55, drho) in Pa and kg/m^3.
- *   data       complex64 [nsys][nrec][2] per problem, concatenated.
+ *   data       complex [nsys][nrec][2] per problem, concatenated.
  *   sources,   host int32 [n][2] as (ix, iz); forces host double [n][2]
  *   receivers  as (fx, fz) in newtons.
  *
@@ -62,7 +68,7 @@
 extern "C" {
 #endif
 
-#define FWILS_ABI_VERSION 4
+#define FWILS_ABI_VERSION 5
 
 typedef enum {
     FWILS_OK = 0,
@@ -75,7 +81,8 @@ typedef enum {
 } fwils_status;
 
 typedef enum {
-    FWILS_C64 = 0            /* complex64 fields, fp32 maps, FP64 reductions  */
+    FWILS_C64 = 0,           /* complex64 fields, fp32 maps, FP64 reductions  */
+    FWILS_C128 = 1           /* complex128 fields, fp64 maps (FP64 reference) */
 } fwils_precision;
 
 typedef enum {
@@ -126,7 +133,7 @@ fwils_status fwils_field_elems(fwils_plan plan, int64_t* elems);
 
 /* Contrast of problem iprob (eqs. decom, key): copies the five maps
  * [5][nz][nx] (device, fp32, absolute units) into the workspace. */
-fwils_status fwils_set_contrast(fwils_plan plan, int32_t iprob, const float* maps);
+fwils_status fwils_set_contrast(fwils_plan plan, int32_t iprob, const void* maps);
 
 /* Receivers of problem iprob: host int32 [nrec][2] (ix, iz), 1 <= nrec <= 65536.
  * Copied into the workspace (synchronous). */
@@ -150,8 +157,9 @@ fwils_status fwils_convolve(fwils_plan plan, const void* f, void* out);
  * fields, must not alias. */
 fwils_status fwils_apply(fwils_plan plan, const void* u, void* Au);
 
-/* Solve A x = rhs for every system by BiCGSTAB (eq. axb), complex64 vectors
- * and FP64 inner products.  Stops each system when its recursive residual
+/* Solve A x = rhs for every system by the plan's Krylov method (eq. axb;
+ * BiCGSTAB unless fwils_set_krylov chose GMRES), vectors of the plan's
+ * precision and FP64 inner products.  Stops each system when its recursive residual
  * satisfies ||r|| <= rtol ||rhs||, or after maxit iterations.  rhs, x:
  * device fields (x is output, and input with FWILS_SOLVE_X0).  iters (int32)
  * and relres (double, TRUE residual ||rhs - A x|| / ||rhs||) are device
@@ -170,7 +178,7 @@ fwils_status fwils_solve(fwils_plan plan, const void* rhs, void* x, double rtol,
  * dm: host array of nprob device pointers to fp32 maps [5][nz][nx]
  * (absolute units; may repeat).  d: device data (output).  The one LS solve
  * per system uses rtol / maxit as fwils_solve. */
-fwils_status fwils_frechet(fwils_plan plan, const void* ub, const float* const* dm,
+fwils_status fwils_frechet(fwils_plan plan, const void* ub, const void* const* dm,
                            void* d, double rtol, int32_t maxit);
 
 /* Adjoint operator (eqs. ad1, ua, ua0; App. B): for every problem
@@ -178,7 +186,7 @@ fwils_status fwils_frechet(fwils_plan plan, const void* ub, const float* const* 
  *   g_rho = sum_sys conj( w~^2 u^a . u^b ),
  *   g_p   = - sum_sys conj( (E_h u^a)^T B^(p) (E_h u^b) ),  p = C11, C13, C33, C55,
  * accumulated over systems in FP64.  r: device data.  g: host array of nprob
- * device pointers to complex64 maps [5][nz][nx] (output; with
+ * device pointers to complex maps [5][nz][nx] (output; with
  * FWILS_ADJ_ACCUMULATE added to).  Problems that share a g pointer are
  * summed when FWILS_ADJ_ACCUMULATE is set. */
 fwils_status fwils_adjoint(fwils_plan plan, const void* ub, const void* r,
@@ -216,7 +224,7 @@ fwils_status fwils_solve_stats(fwils_plan plan, int32_t* iters, double* relres);
 fwils_status fwils_solve_status(fwils_plan plan, int32_t* status);
 
 /* ---- Generalised Tikhonov step (eqs. obj, norm) ------------------------
- * Unknowns are relative maps q, float32 [5][nz][nx] on the device, with
+ * Unknowns are relative maps q, real [5][nz][nx] on the device, with
  * dm_p = m0_p q_p (m0: host double[5], e.g. the background C11, C13, C33,
  * C55, rho0).  All problems of the plan must share one grid (nx, nz, dx);
  * their data stack: J q = [J_1 q; J_2 q; ...], J* r = sum_f J_f* r_f.
@@ -224,42 +232,44 @@ fwils_status fwils_solve_status(fwils_plan plan, int32_t* status);
  *   f(q)      = ||J q - r||^2 / rr + lam ||L q||^2
  *   grad f(q) = 2 m0 Re J*(J q - r) / rr + 2 lam L^T L q
  *   N q       = m0 Re J*(J q) / rr + lam L^T L q          (normal operator)
- * r: device data (complex64, plan data layout); dscratch: device complex64
+ * r: device data (complex, plan data layout); dscratch: device complex
  * buffer with the same number of elements as r; ub: background solutions.
  * Every J and J* application is one LS solve per system (rtol, maxit). */
 #define FWILS_REG_IDENTITY  0
 #define FWILS_REG_LAPLACIAN 1
 
-/* grad (device float [5][nz][nx]) and, if fval != NULL, *fval = f(q).  Synchronous. */
+/* grad (device real [5][nz][nx]) and, if fval != NULL, *fval = f(q).  Synchronous. */
 fwils_status fwils_tikhonov_grad(fwils_plan plan, const void* ub, const void* r, const double* m0,
-                                 double lam, int32_t reg, const float* q, float* grad, double* fval,
+                                 double lam, int32_t reg, const void* q, void* grad, double* fval,
                                  void* dscratch, double rtol, int32_t maxit);
 
 /* q_out = N q_in for a given rr (> 0).  Synchronous. */
 fwils_status fwils_normal_apply(fwils_plan plan, const void* ub, const double* m0, double rr,
-                                double lam, int32_t reg, const float* q_in, float* q_out,
+                                double lam, int32_t reg, const void* q_in, void* q_out,
                                 void* dscratch, double rtol, int32_t maxit);
 
 /* niter iterations (1..1000) of CG on N q = m0 Re J* r / rr (eq. norm) from q = 0,
- * FP64 scalars kept on the device.  q: device output.  hist (host double
- * [niter + 1] or NULL) receives the normal-equation residual norm before each
- * iteration and after the last.  Synchronous. */
+ * FP64 scalars kept on the device; the iteration ends early once the squared
+ * residual norm has dropped by 1e30 (converged to working precision).  q:
+ * device output.  hist (host double [niter + 1] or NULL) receives the
+ * normal-equation residual norm before each iteration and after the last
+ * (repeated after an early end).  Synchronous. */
 fwils_status fwils_normal_cg(fwils_plan plan, const void* ub, const void* r, const double* m0,
-                             double lam, int32_t reg, int32_t niter, float* q, double* hist,
+                             double lam, int32_t reg, int32_t niter, void* q, double* hist,
                              void* dscratch, double rtol, int32_t maxit);
 
 /* J and J* in the relative units of the Tikhonov step (single-grid plans):
- *   fwils_frechet_rel: d = J (m0 q)                     (q: device float [5][nz][nx])
- *   fwils_adjoint_rel: gq = m0 Re(J* r), summed over problems (gq: device float)
+ *   fwils_frechet_rel: d = J (m0 q)                     (q: device real [5][nz][nx])
+ *   fwils_adjoint_rel: gq = m0 Re(J* r), summed over problems (gq: device real)
  * These are the forward and backward of the differentiable operator q -> J q. */
-fwils_status fwils_frechet_rel(fwils_plan plan, const void* ub, const float* q, const double* m0,
+fwils_status fwils_frechet_rel(fwils_plan plan, const void* ub, const void* q, const double* m0,
                                void* d, double rtol, int32_t maxit);
 fwils_status fwils_adjoint_rel(fwils_plan plan, const void* ub, const void* r, const double* m0,
-                               float* gq, double rtol, int32_t maxit);
+                               void* gq, double rtol, int32_t maxit);
 
 /* out = L q: periodic unscaled 5-point Laplacian of the 5 maps [5][nz][nx]
  * (single-grid plans).  Self-adjoint, so it is also L^T q. */
-fwils_status fwils_laplacian(fwils_plan plan, const float* q, float* out);
+fwils_status fwils_laplacian(fwils_plan plan, const void* q, void* out);
 
 /* 2-D FFT of every field of problem iprob with the library's own transform
  * kernels (unnormalised forward, exp(-i k.x); inverse with exp(+i k.x) and

@@ -17,6 +17,7 @@ c_int32, c_double, c_size_t, c_void_p, c_uint32, c_int64 = (
 
 FWILS_OK, FWILS_EINVAL, FWILS_ENOMEM, FWILS_EDEVICE, FWILS_ENOCONV, FWILS_EBREAKDOWN, FWILS_EUNSUPPORTED = range(7)
 FWILS_C64 = 0
+FWILS_C128 = 1
 FWILS_SYMBOL_SPECTRAL, FWILS_SYMBOL_CENTRAL = 0, 1
 FWILS_SOLVE_X0, FWILS_SOLVE_PLAIN, FWILS_SOLVE_NOGRAPH = 0x1, 0x2, 0x4
 FWILS_ADJ_ACCUMULATE = 0x1

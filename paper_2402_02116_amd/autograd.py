@@ -1,6 +1,6 @@
 """Differentiable Frechet operator and Laplacian for torch.autograd.
 
-FrechetFn maps relative model maps q (float32 [5, nz, nx], dm_p = m0_p q_p)
+FrechetFn maps relative model maps q (the plan's real type, [5, nz, nx], dm_p = m0_p q_p)
 to the complex receiver data J q of every system of a plan (eqs. F, YM, F0,
 uY); its backward applies the adjoint (eqs. ad1, ua): for a real input and
 PyTorch's conjugate-Wirtinger convention the vector-Jacobian product of an

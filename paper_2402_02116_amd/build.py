@@ -19,8 +19,12 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfwils.so")
-SOURCES = ["kernels_rows.hip", "kernels_cols.hip", "kernels_fft.hip", "kernels_vec.hip", "kernels_maps.hip",
-           "kernels_gmres.hip", "kernels_srows.hip", "capi.cpp"]
+# The core (kernels and capi.cpp) is compiled once per precision: complex64
+# and, with -DFW_C128, complex128; abi.cpp (the public entry points) once.
+CORE = ["kernels_rows.hip", "kernels_cols.hip", "kernels_fft.hip", "kernels_vec.hip", "kernels_maps.hip",
+        "kernels_gmres.hip", "kernels_srows.hip", "capi.cpp"]
+UNITS = [(s, "c64") for s in CORE] + [(s, "c128") for s in CORE] + [("abi.cpp", None)]
+SOURCES = CORE + ["abi.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -33,9 +37,12 @@ FLAGS = [
 ]
 
 
-def _compile(src, verbose):
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+def _compile(unit, verbose):
+    src, prec = unit
+    obj = os.path.join(BUILD, os.path.splitext(src)[0] + (f"_{prec}" if prec else "") + ".o")
     cmd = [HIPCC] + FLAGS
+    if prec == "c128":
+        cmd += ["-DFW_C128"]
     if src.endswith(".cpp"):
         cmd += ["-x", "hip"]
     cmd += ["-c", os.path.join(CSRC, src), "-o", obj]
@@ -44,7 +51,7 @@ def _compile(src, verbose):
     if res.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{res.stderr}")
     if verbose:
-        print(f"  {src}: {time.time() - t:.1f}s", flush=True)
+        print(f"  {src} ({prec or 'abi'}): {time.time() - t:.1f}s", flush=True)
         if res.stderr.strip():
             print(res.stderr)
     return obj
@@ -54,9 +61,12 @@ def build(jobs=None, verbose=False):
     if not os.path.exists(HIPCC):
         raise RuntimeError(f"hipcc not found at {HIPCC}")
     os.makedirs(BUILD, exist_ok=True)
-    jobs = jobs or min(len(SOURCES), os.cpu_count() or 1)
+    jobs = jobs or min(len(UNITS), os.cpu_count() or 1)
+    # longest units first
+    order = sorted(UNITS, key=lambda u: (u[0] not in ("kernels_rows.hip", "kernels_cols.hip",
+                                                     "kernels_srows.hip", "kernels_vec.hip"), u[1] != "c64"))
     with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
+        objs = list(ex.map(lambda u: _compile(u, verbose), order))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs
     res = subprocess.run(cmd, capture_output=True, text=True)

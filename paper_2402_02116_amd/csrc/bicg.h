@@ -5,8 +5,7 @@
 
 #include "launch.h"
 
-namespace fw {
-
+FW_BEGIN
 __device__ __forceinline__ dcomplex zdiv(dcomplex a, dcomplex b) {
     const double d = b.re * b.re + b.im * b.im;
     return dcomplex{(a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d};
@@ -14,7 +13,7 @@ __device__ __forceinline__ dcomplex zdiv(dcomplex a, dcomplex b) {
 __device__ __forceinline__ dcomplex zmul(dcomplex a, dcomplex b) {
     return dcomplex{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
 }
-__device__ __forceinline__ float2 tof(dcomplex a) { return make_float2((float)a.re, (float)a.im); }
+__device__ __forceinline__ cplx toc(dcomplex a) { return mkc((real)a.re, (real)a.im); }
 __device__ __forceinline__ bool zzero(dcomplex a) { return a.re == 0.0 && a.im == 0.0; }
 
 // Convergence / limit / finiteness test of the recursive residual; returns
@@ -52,7 +51,9 @@ __device__ __forceinline__ OmegaStep omega_step(const double (&q)[kPartialNV]) {
     if (q[2] != 0.0) {
         o.omega = dcomplex{q[0] / q[2], q[1] / q[2]};
         const double ts = sqrt(q[0] * q[0] + q[1] * q[1]);
-        const double c = (q[3] > 0.0) ? ts / sqrt(q[2] * q[3]) : 1.0;
+        // |t| |s| as a product of roots: the product of the squares can
+        // underflow for tiny fields
+        const double c = (q[3] > 0.0) ? ts / (sqrt(q[2]) * sqrt(q[3])) : 1.0;
         if (c < kOmegaLimit && c > 0.0) {
             o.omega.re *= kOmegaLimit / c;
             o.omega.im *= kOmegaLimit / c;
@@ -89,15 +90,15 @@ __device__ __forceinline__ int close_code(const SysState& z, const OmegaStep& o)
 // The closing updates of an iteration on one element: r = s - omega t and
 // x + alpha p + omega s.  Contraction is off so that every kernel that closes
 // an iteration (stencils, close kernel) rounds it identically.
-__device__ __forceinline__ float2 close_r(float2 sv, float2 tv, float2 omega) {
+__device__ __forceinline__ cplx close_r(cplx sv, cplx tv, cplx omega) {
 #pragma clang fp contract(off)
-    return make_float2(sv.x - (omega.x * tv.x - omega.y * tv.y), sv.y - (omega.x * tv.y + omega.y * tv.x));
+    return mkc(sv.x - (omega.x * tv.x - omega.y * tv.y), sv.y - (omega.x * tv.y + omega.y * tv.x));
 }
-__device__ __forceinline__ float2 close_x(float2 xv, float2 pv, float2 sv, float2 alpha, float2 omega) {
+__device__ __forceinline__ cplx close_x(cplx xv, cplx pv, cplx sv, cplx alpha, cplx omega) {
 #pragma clang fp contract(off)
-    const float ax = alpha.x * pv.x - alpha.y * pv.y, ay = alpha.x * pv.y + alpha.y * pv.x;
-    const float wx = omega.x * sv.x - omega.y * sv.y, wy = omega.x * sv.y + omega.y * sv.x;
-    return make_float2(xv.x + (ax + wx), xv.y + (ay + wy));
+    const real ax = alpha.x * pv.x - alpha.y * pv.y, ay = alpha.x * pv.y + alpha.y * pv.x;
+    const real wx = omega.x * sv.x - omega.y * sv.y, wy = omega.x * sv.y + omega.y * sv.x;
+    return mkc(xv.x + (ax + wx), xv.y + (ay + wy));
 }
 
 enum StencilStep : int { SS_SKIP = 0, SS_FULL = 1, SS_XONLY = 2 };
@@ -115,7 +116,7 @@ enum StencilStep : int { SS_SKIP = 0, SS_FULL = 1, SS_XONLY = 2 };
 // (block reduction).
 template <int VM>
 __device__ __forceinline__ int stencil_scalars(SysState* st, int sys, const double* part, int np, double* red,
-                                               bool writer, float2& c1, float2& c2, float2& c3, bool& fresh) {
+                                               bool writer, cplx& c1, cplx& c2, cplx& c3, bool& fresh) {
     const SysState& z = st[sys];
     const int it = z.iter + 1;
     if constexpr (VM == VM_PX) {
@@ -123,8 +124,8 @@ __device__ __forceinline__ int stencil_scalars(SysState* st, int sys, const doub
         sum_partials<kPartialNV, 256>(part + (size_t)sys * np * kPartialNV, np, q, red);
         const OmegaStep o = omega_step(q);
         const dcomplex alpha{z.alpha_re, z.alpha_im};
-        c2 = tof(o.omega);
-        c3 = tof(alpha);
+        c2 = toc(o.omega);
+        c3 = toc(alpha);
         const int code = close_code(z, o);
         if (code != ST_RUNNING) {
             if (writer) {
@@ -140,10 +141,10 @@ __device__ __forceinline__ int stencil_scalars(SysState* st, int sys, const doub
         fresh = (z.fresh_at == it) || zzero(rho_i) || zzero(rho_prev) || zzero(o.omega);
         if (fresh) {
             rho_i = dcomplex{o.rr, 0.0};   // <r, r>
-            c1 = make_float2(0.f, 0.f);
+            c1 = mkc(0.f, 0.f);
         } else {
             const dcomplex beta = zmul(zdiv(rho_i, rho_prev), zdiv(alpha, o.omega));
-            c1 = make_float2((float)beta.re, (float)beta.im);
+            c1 = mkc((real)beta.re, (real)beta.im);
         }
         if (writer) {
             st[sys].rho_re[it & 1] = rho_i.re;
@@ -164,12 +165,12 @@ __device__ __forceinline__ int stencil_scalars(SysState* st, int sys, const doub
             fresh = (z.fresh_at == it) || zzero(rho_i) || zzero(rho_prev) || zzero(omega);
             if (fresh) {
                 rho_i = dcomplex{q[2], 0.0};   // <r, r>
-                c1 = make_float2(0.f, 0.f);
+                c1 = mkc(0.f, 0.f);
             } else {
                 const dcomplex beta = zmul(zdiv(rho_i, rho_prev), zdiv(alpha, omega));
-                c1 = make_float2((float)beta.re, (float)beta.im);
+                c1 = mkc((real)beta.re, (real)beta.im);
             }
-            c2 = make_float2((float)omega.re, (float)omega.im);
+            c2 = mkc((real)omega.re, (real)omega.im);
             if (writer) {
                 st[sys].rho_re[it & 1] = rho_i.re;
                 st[sys].rho_im[it & 1] = rho_i.im;
@@ -182,7 +183,7 @@ __device__ __forceinline__ int stencil_scalars(SysState* st, int sys, const doub
                 return SS_SKIP;
             }
             const dcomplex alpha = zdiv(rho_i, rv);
-            c1 = make_float2((float)alpha.re, (float)alpha.im);
+            c1 = mkc((real)alpha.re, (real)alpha.im);
             if (writer) {
                 st[sys].alpha_re = alpha.re;
                 st[sys].alpha_im = alpha.im;
@@ -192,4 +193,4 @@ __device__ __forceinline__ int stencil_scalars(SysState* st, int sys, const doub
     }
 }
 
-}  // namespace fw
+FW_END

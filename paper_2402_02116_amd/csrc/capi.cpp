@@ -12,14 +12,23 @@
 #include <string>
 #include <vector>
 
-#include "../../include/fwils.h"
 #include "launch.h"
+// after launch.h (which selects the precision): the entry points of this
+// build carry the precision in their names; abi.cpp dispatches to them
+#include "core_names.h"
+#include "../../include/fwils.h"
 
 using namespace fw;
 
+extern "C" void fwils_internal_set_error(const char* msg);
+
 namespace {
 
-thread_local std::string g_last_error;
+#ifdef FW_C128
+constexpr fwils_precision kPrec = FWILS_C128;
+#else
+constexpr fwils_precision kPrec = FWILS_C64;
+#endif
 
 void set_error(const char* fmt, ...) {
     char buf[1024];
@@ -27,7 +36,7 @@ void set_error(const char* fmt, ...) {
     va_start(ap, fmt);
     vsnprintf(buf, sizeof(buf), fmt, ap);
     va_end(ap);
-    g_last_error = buf;
+    fwils_internal_set_error(buf);
 }
 
 #define FW_HIP(call)                                                                       \
@@ -51,6 +60,7 @@ constexpr int kNumVec = 10;           // field-sized workspace vectors
 constexpr int kMaxRestarts = 3;       // restarts from the true residual per solve
 constexpr double kTrueResFactor = 2.0; // restart when ||b - A x|| > 2 rtol ||b||
 constexpr int kMaxCgIters = 1000;
+constexpr double kCgFloor = 1e-30;    // normal CG stops when ||res||^2 <= kCgFloor ||res_0||^2
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -72,6 +82,7 @@ struct ProbHost {
 }  // namespace
 
 struct fwils_plan_s {
+    int32_t prec = kPrec;   // first member in both precisions: read by the dispatch
     std::vector<ProbHost> probs;
     size_t total_field = 0, total_sys = 0, maps_floats = 0;
     int max_np = 0;
@@ -81,20 +92,20 @@ struct fwils_plan_s {
     size_t ws_bytes = 0;
     size_t off_tw = 0, off_state = 0, off_part = 0, part_bytes = 0, off_maps = 0, off_rec = 0,
            off_src = 0, off_vec = 0;
-    float2* tw = nullptr;
+    cplx* tw = nullptr;
     SysState* state = nullptr;
     double *partV = nullptr, *partT = nullptr, *partXR = nullptr, *partB = nullptr;
-    float* maps = nullptr;
+    real* maps = nullptr;
     int32_t* rec = nullptr;
     int32_t* src_i = nullptr;
     double* src_f = nullptr;
-    float2 *x = nullptr, *r = nullptr, *rhat = nullptr, *p = nullptr, *p2 = nullptr, *v = nullptr,
+    cplx *x = nullptr, *r = nullptr, *rhat = nullptr, *p = nullptr, *p2 = nullptr, *v = nullptr,
            *s = nullptr, *t = nullptr, *tmp = nullptr, *rhs = nullptr;
     // model-map scratch of the Tikhonov step (single-grid plans only)
     size_t map_n = 0, off_mapws = 0;
-    float *mq_dm = nullptr, *mq_x = nullptr, *mq_res = nullptr, *mq_p = nullptr, *mq_Ap = nullptr,
+    real *mq_dm = nullptr, *mq_x = nullptr, *mq_res = nullptr, *mq_p = nullptr, *mq_Ap = nullptr,
           *mq_l1 = nullptr, *mq_l2 = nullptr;
-    float2* mq_g = nullptr;
+    cplx* mq_g = nullptr;
     double *mq_part = nullptr, *mq_sc = nullptr, *mq_hist = nullptr;
     // graphs of one chunk of iterations over all problems (the first chunk of
     // a solve or restart starts from r)
@@ -104,7 +115,7 @@ struct fwils_plan_s {
     int gm_m = 0;
     bool gm_cgs2 = true;
     size_t gm_maxnb = 0;
-    float2* gm_V = nullptr;
+    cplx* gm_V = nullptr;
     GmSys* gm_sys = nullptr;
     double *gm_part = nullptr, *gm_tot1 = nullptr, *gm_tot2 = nullptr, *gm_tot3 = nullptr;
     hipGraphExec_t gm_cycle = nullptr;
@@ -127,17 +138,17 @@ ProbDev make_dev(const fwils_problem& p) {
     d.nz = p.nz;
     d.nsys = p.nsys;
     d.symbol = p.symbol;
-    d.inv4dx2 = (float)(1.0 / (4.0 * p.dx * p.dx));
-    d.w2 = make_float2((float)w2r, (float)w2i);
-    d.gc11 = (float)(p.c0[0] / rw2);
-    d.gc33 = (float)(p.c0[2] / rw2);
-    d.gc55 = (float)(p.c0[3] / rw2);
-    d.gc1355 = (float)((p.c0[1] + p.c0[3]) / rw2);
-    d.ga = make_float2((float)(1.0 - eta * eta), (float)(2.0 * eta));
-    d.gscale = (float)(1.0 / (rw2 * (double)p.nx * (double)p.nz));
-    d.dkx = (float)(2.0 * M_PI / (p.nx * p.dx));
-    d.dkz = (float)(2.0 * M_PI / (p.nz * p.dx));
-    d.dx = (float)p.dx;
+    d.inv4dx2 = (real)(1.0 / (4.0 * p.dx * p.dx));
+    d.w2 = mkc((real)w2r, (real)w2i);
+    d.gc11 = (real)(p.c0[0] / rw2);
+    d.gc33 = (real)(p.c0[2] / rw2);
+    d.gc55 = (real)(p.c0[3] / rw2);
+    d.gc1355 = (real)((p.c0[1] + p.c0[3]) / rw2);
+    d.ga = mkc((real)(1.0 - eta * eta), (real)(2.0 * eta));
+    d.gscale = (real)(1.0 / (rw2 * (double)p.nx * (double)p.nz));
+    d.dkx = (real)(2.0 * M_PI / (p.nx * p.dx));
+    d.dkz = (real)(2.0 * M_PI / (p.nz * p.dx));
+    d.dx = (real)p.dx;
     return d;
 }
 
@@ -154,20 +165,20 @@ fwils_status check_plan(fwils_plan plan, bool need_ws = true) {
 }
 
 // Views of the plan-level vectors for problem i.
-inline float2* at(float2* base, const ProbHost& P) { return base + P.field_off; }
-inline const float2* at(const void* base, const ProbHost& P) {
-    return static_cast<const float2*>(base) + P.field_off;
+inline cplx* at(cplx* base, const ProbHost& P) { return base + P.field_off; }
+inline const cplx* at(const void* base, const ProbHost& P) {
+    return static_cast<const cplx*>(base) + P.field_off;
 }
 inline SysState* st_at(fwils_plan pl, const ProbHost& P) { return pl->state + P.sys_off; }
 inline double* part_at(double* base, fwils_plan pl, const ProbHost& P) {
     return base + P.sys_off * (size_t)pl->max_np * kPartialNV;
 }
-inline float* maps_at(fwils_plan pl, const ProbHost& P) { return pl->maps + P.map_off; }
+inline real* maps_at(fwils_plan pl, const ProbHost& P) { return pl->maps + P.map_off; }
 
 // y = G0 conv f for problem P (f read, out written; tmp is scratch).
-hipError_t conv_problem(fwils_plan pl, const ProbHost& P, const float2* f, float2* out) {
+hipError_t conv_problem(fwils_plan pl, const ProbHost& P, const cplx* f, cplx* out) {
     const int rows = P.p.nsys * 2 * P.p.nz;
-    float2* tmp = at(pl->tmp, P);
+    cplx* tmp = at(pl->tmp, P);
     hipError_t e = launch_rows_fwd(P.p.nx, P.cfg.row_p, f, tmp, rows, 2 * P.p.nz, nullptr, pl->tw, pl->stream);
     if (e == hipSuccess) e = launch_cols(COL_GREEN, P.cfg.col, tmp, P.dev, nullptr, pl->tw, pl->stream);
     if (e == hipSuccess)
@@ -178,8 +189,8 @@ hipError_t conv_problem(fwils_plan pl, const ProbHost& P, const float2* f, float
 
 // One LS matvec with an epilogue, for nsys systems starting at the given
 // views (used both batched and per system).
-hipError_t matvec(fwils_plan pl, const ProbHost& P, const ProbDev& d, const float2* u, float2* tmp,
-                  const float* maps, int epi, const float2* aux, float2* out, double* part,
+hipError_t matvec(fwils_plan pl, const ProbHost& P, const ProbDev& d, const cplx* u, cplx* tmp,
+                  const real* maps, int epi, const cplx* aux, cplx* out, double* part,
                   const SysState* st, hipStream_t s, const GmEpi* ge = nullptr) {
     const int rows = d.nsys * 2 * d.nz;
     const KernelCfg& k = P.cfg;
@@ -233,13 +244,13 @@ hipError_t bicg_iteration(fwils_plan pl, const ProbHost& P, const SysView& V, in
                           hipStream_t s) {
     const int ns = V.d.nsys;
     const int rows = ns * 2 * V.d.nz;
-    float2 *x = pl->x + V.foff, *r = pl->r + V.foff, *rh = pl->rhat + V.foff, *v = pl->v + V.foff,
+    cplx *x = pl->x + V.foff, *r = pl->r + V.foff, *rh = pl->rhat + V.foff, *v = pl->v + V.foff,
            *sv = pl->s + V.foff, *t = pl->t + V.foff, *tmp = pl->tmp + V.foff;
-    float2* pold = (parity ? pl->p2 : pl->p) + V.foff;
-    float2* pnew = (parity ? pl->p : pl->p2) + V.foff;
+    cplx* pold = (parity ? pl->p2 : pl->p) + V.foff;
+    cplx* pnew = (parity ? pl->p : pl->p2) + V.foff;
     SysState* st = pl->state + V.soff;
     double *pV = pl->partV + V.poff_row, *pT = pl->partT + V.poff_row, *pXR = pl->partXR + V.poff_vec;
-    const float* maps = maps_at(pl, P);
+    const real* maps = maps_at(pl, P);
     StencilArgs ap{r, pold, v, pnew, tmp, maps, pXR, P.np_vec, rh};
     if (!first) {
         ap = StencilArgs{sv, pold, v, pnew, tmp, maps, pT, P.np_rows, rh};
@@ -270,7 +281,7 @@ hipError_t bicg_iteration(fwils_plan pl, const ProbHost& P, const SysView& V, in
 
 // The end-of-chunk close kernel after an iteration of the given parity.
 hipError_t bicg_close(fwils_plan pl, const ProbHost& P, const SysView& V, int parity, hipStream_t s) {
-    float2* pnew = (parity ? pl->p : pl->p2) + V.foff;
+    cplx* pnew = (parity ? pl->p : pl->p2) + V.foff;
     return launch_bicg_close(pl->x + V.foff, pl->r + V.foff, pnew, pl->s + V.foff, pl->t + V.foff,
                              pl->partT + V.poff_row, P.np_rows, pl->state + V.soff, V.d.nsys,
                              (int)P.n_per_sys, s);
@@ -332,13 +343,13 @@ fwils_status build_chunk_graphs(fwils_plan pl) {
 
 // Solve A x = b where b and the result live in plan-level fields.  x_ws is
 // the workspace solution vector (pl->x).  flags as fwils_solve.
-fwils_status bicg_solve_ws(fwils_plan pl, const float2* b, bool use_x0, double rtol, int maxit,
+fwils_status bicg_solve_ws(fwils_plan pl, const cplx* b, bool use_x0, double rtol, int maxit,
                            int32_t* iters, double* relres, uint32_t flags) {
     hipStream_t s = pl->stream;
     // initial residual, state
     for (const ProbHost& P : pl->probs) {
         const int n = (int)P.n_per_sys;
-        const float2* bp = b + P.field_off;
+        const cplx* bp = b + P.field_off;
         if (use_x0) {
             FW_HIP(matvec(pl, P, P.dev, at(pl->x, P), at(pl->tmp, P), maps_at(pl, P), EPI_TRUERES, bp,
                           at(pl->r, P), part_at(pl->partT, pl, P), nullptr, s));
@@ -509,7 +520,7 @@ GmArgs gm_args(fwils_plan pl, const ProbHost& P) {
 }
 
 // r = b - A x into basis slot 0 with ||r||^2, ||b||^2, then the cycle start.
-hipError_t gm_start(fwils_plan pl, const ProbHost& P, const float2* b, double rtol, bool first, hipStream_t s) {
+hipError_t gm_start(fwils_plan pl, const ProbHost& P, const cplx* b, double rtol, bool first, hipStream_t s) {
     const GmArgs a = gm_args(pl, P);
     const GmEpi ge{nullptr, 0, 0, a.part};
     hipError_t e = matvec(pl, P, P.dev, at(pl->x, P), at(pl->tmp, P), maps_at(pl, P), EPI_GMRES_R0,
@@ -524,15 +535,15 @@ hipError_t gm_start(fwils_plan pl, const ProbHost& P, const float2* b, double rt
 // those projections, w -= W c, and (CGS2) the projections of the result,
 // their sum and the second subtraction; the last subtraction leaves ||w||^2
 // records, whose sum builds the Hessenberg column.
-hipError_t gm_cycle(fwils_plan pl, const ProbHost& P, const float2* b, double rtol, hipStream_t s) {
+hipError_t gm_cycle(fwils_plan pl, const ProbHost& P, const cplx* b, double rtol, hipStream_t s) {
     const GmArgs a = gm_args(pl, P);
     const int nbv = gm_blocks_per_sys((int)P.n_per_sys);
     const bool cgs2 = pl->gm_cgs2;
     hipError_t e = hipSuccess;
     for (int j = 0; j < pl->gm_m && e == hipSuccess; ++j) {
         const GmEpi ge{a.V, a.vstride, j + 1, a.part};
-        float2* wj = a.V + (size_t)j * a.vstride;
-        float2* wn = a.V + (size_t)(j + 1) * a.vstride;
+        cplx* wj = a.V + (size_t)j * a.vstride;
+        cplx* wn = a.V + (size_t)(j + 1) * a.vstride;
         e = matvec(pl, P, P.dev, wj, at(pl->tmp, P), maps_at(pl, P), EPI_ARNOLDI, nullptr, wn, nullptr, a.st, s,
                    &ge);
         if (e == hipSuccess) e = launch_gm_sum(a, GM_SUM_PROJ1, P.np_rows, j, cgs2, rtol, false, s);
@@ -549,7 +560,7 @@ hipError_t gm_cycle(fwils_plan pl, const ProbHost& P, const float2* b, double rt
     return e;
 }
 
-fwils_status gm_solve_ws(fwils_plan pl, const float2* b, bool use_x0, double rtol, int maxit, int32_t* iters,
+fwils_status gm_solve_ws(fwils_plan pl, const cplx* b, bool use_x0, double rtol, int maxit, int32_t* iters,
                          double* relres, uint32_t flags) {
     if (flags & FWILS_SOLVE_PLAIN) {
         set_error("solve: the per-source plain loop is a BiCGSTAB mode");
@@ -580,7 +591,7 @@ fwils_status gm_solve_ws(fwils_plan pl, const float2* b, bool use_x0, double rto
     if (any && graph && (!pl->gm_cycle || pl->gm_rtol != rtol)) {
         if (pl->gm_cycle) (void)hipGraphExecDestroy(pl->gm_cycle);
         pl->gm_cycle = nullptr;
-        const float2* rhs = pl->rhs;
+        const cplx* rhs = pl->rhs;
         FW_TRY(capture_graph(pl, &pl->gm_cycle, [pl, rhs, rtol](const ProbHost& P, hipStream_t q) {
             return gm_cycle(pl, P, rhs, rtol, q);
         }));
@@ -614,7 +625,7 @@ fwils_status gm_solve_ws(fwils_plan pl, const float2* b, bool use_x0, double rto
     return FWILS_OK;
 }
 
-fwils_status solve_ws(fwils_plan pl, const float2* b, bool use_x0, double rtol, int maxit, int32_t* iters,
+fwils_status solve_ws(fwils_plan pl, const cplx* b, bool use_x0, double rtol, int maxit, int32_t* iters,
                       double* relres, uint32_t flags) {
     if (pl->krylov == FWILS_KRYLOV_GMRES) return gm_solve_ws(pl, b, use_x0, rtol, maxit, iters, relres, flags);
     return bicg_solve_ws(pl, b, use_x0, rtol, maxit, iters, relres, flags);
@@ -633,32 +644,15 @@ fwils_status check_field_ptrs(std::initializer_list<const void*> ptrs) {
 
 extern "C" {
 
-int32_t fwils_abi_version(void) { return FWILS_ABI_VERSION; }
-
-const char* fwils_status_string(fwils_status s) {
-    switch (s) {
-        case FWILS_OK: return "ok";
-        case FWILS_EINVAL: return "invalid argument";
-        case FWILS_ENOMEM: return "workspace missing or too small";
-        case FWILS_EDEVICE: return "HIP device error";
-        case FWILS_ENOCONV: return "not converged";
-        case FWILS_EBREAKDOWN: return "Krylov breakdown";
-        case FWILS_EUNSUPPORTED: return "unsupported";
-    }
-    return "unknown status";
-}
-
-const char* fwils_last_error(void) { return g_last_error.c_str(); }
-
 fwils_status fwils_plan_create(const fwils_problem* probs, int32_t nprob, fwils_precision prec,
                                fwils_plan* out) {
     if (!out || !probs || nprob < 1 || nprob > 64) {
         set_error("plan_create: need 1..64 problems and an output pointer");
         return FWILS_EINVAL;
     }
-    if (prec != FWILS_C64) {
-        set_error("plan_create: only FWILS_C64 is implemented");
-        return FWILS_EUNSUPPORTED;
+    if (prec != kPrec) {
+        set_error("plan_create: precision %d reached the wrong library core", (int)prec);
+        return FWILS_EINVAL;
     }
     for (int i = 0; i < nprob; ++i) {
         const fwils_problem& p = probs[i];
@@ -714,20 +708,20 @@ fwils_status fwils_plan_create(const fwils_problem* probs, int32_t nprob, fwils_
     // workspace layout
     size_t o = 0;
     pl->off_tw = o;
-    o = align256(o + twiddle_table_elems() * sizeof(float2));
+    o = align256(o + twiddle_table_elems() * sizeof(cplx));
     pl->off_state = o;
     o = align256(o + pl->total_sys * sizeof(SysState));
     pl->off_part = o;
     pl->part_bytes = align256(pl->total_sys * (size_t)pl->max_np * kPartialNV * sizeof(double));
     o += 4 * pl->part_bytes;
     pl->off_maps = o;
-    o = align256(o + pl->maps_floats * sizeof(float));
+    o = align256(o + pl->maps_floats * sizeof(real));
     pl->off_rec = o;
     o = align256(o + (size_t)nprob * kMaxRec * 2 * sizeof(int32_t));
     pl->off_src = o;
     o = align256(o + pl->total_sys * 2 * (sizeof(int32_t) + sizeof(double)));
     pl->off_vec = o;
-    o += kNumVec * align256(pl->total_field * sizeof(float2));
+    o += kNumVec * align256(pl->total_field * sizeof(cplx));
     bool one_grid = true;
     for (int i = 1; i < nprob; ++i)
         one_grid = one_grid && probs[i].nx == probs[0].nx && probs[i].nz == probs[0].nz &&
@@ -735,7 +729,7 @@ fwils_status fwils_plan_create(const fwils_problem* probs, int32_t nprob, fwils_
     pl->map_n = one_grid ? (size_t)probs[0].nx * probs[0].nz : 0;
     pl->off_mapws = o;
     if (pl->map_n) {
-        o += 7 * align256(5 * pl->map_n * sizeof(float)) + align256(5 * pl->map_n * sizeof(float2));
+        o += 7 * align256(5 * pl->map_n * sizeof(real)) + align256(5 * pl->map_n * sizeof(cplx));
         o += align256(kDotPartials * sizeof(double)) + align256(16 * sizeof(double)) +
              align256(kMaxCgIters + 1) * sizeof(double);
     }
@@ -796,52 +790,53 @@ fwils_status fwils_set_workspace(fwils_plan plan, void* dev, size_t bytes) {
     }
     char* w = (char*)dev;
     plan->ws = w;
-    plan->tw = (float2*)(w + plan->off_tw);
+    plan->tw = (cplx*)(w + plan->off_tw);
     plan->state = (SysState*)(w + plan->off_state);
     plan->partV = (double*)(w + plan->off_part);
     plan->partT = (double*)(w + plan->off_part + plan->part_bytes);
     plan->partXR = (double*)(w + plan->off_part + 2 * plan->part_bytes);
     plan->partB = (double*)(w + plan->off_part + 3 * plan->part_bytes);
-    plan->maps = (float*)(w + plan->off_maps);
+    plan->maps = (real*)(w + plan->off_maps);
     plan->rec = (int32_t*)(w + plan->off_rec);
     plan->src_i = (int32_t*)(w + plan->off_src);
     plan->src_f = (double*)(w + plan->off_src + align256(plan->total_sys * 2 * sizeof(int32_t)));
-    float2** vecs[kNumVec] = {&plan->x, &plan->r, &plan->rhat, &plan->p, &plan->p2,
+    cplx** vecs[kNumVec] = {&plan->x, &plan->r, &plan->rhat, &plan->p, &plan->p2,
                               &plan->v, &plan->s, &plan->t, &plan->tmp, &plan->rhs};
-    const size_t vb = align256(plan->total_field * sizeof(float2));
-    for (int i = 0; i < kNumVec; ++i) *vecs[i] = (float2*)(w + plan->off_vec + i * vb);
+    const size_t vb = align256(plan->total_field * sizeof(cplx));
+    for (int i = 0; i < kNumVec; ++i) *vecs[i] = (cplx*)(w + plan->off_vec + i * vb);
     if (plan->map_n) {
         char* m = w + plan->off_mapws;
-        const size_t fb = align256(5 * plan->map_n * sizeof(float));
-        float** fm[7] = {&plan->mq_dm, &plan->mq_x, &plan->mq_res, &plan->mq_p,
+        const size_t fb = align256(5 * plan->map_n * sizeof(real));
+        real** fm[7] = {&plan->mq_dm, &plan->mq_x, &plan->mq_res, &plan->mq_p,
                          &plan->mq_Ap, &plan->mq_l1, &plan->mq_l2};
-        for (int i = 0; i < 7; ++i) *fm[i] = (float*)(m + i * fb);
+        for (int i = 0; i < 7; ++i) *fm[i] = (real*)(m + i * fb);
         m += 7 * fb;
-        plan->mq_g = (float2*)m;
-        m += align256(5 * plan->map_n * sizeof(float2));
+        plan->mq_g = (cplx*)m;
+        m += align256(5 * plan->map_n * sizeof(cplx));
         plan->mq_part = (double*)m;
         m += align256(kDotPartials * sizeof(double));
         plan->mq_sc = (double*)m;
         m += align256(16 * sizeof(double));
         plan->mq_hist = (double*)m;
     }
-    std::vector<float2> tw(twiddle_table_elems());
+    std::vector<cplx> tw(twiddle_table_elems());
     twiddle_table_fill(tw.data());
-    FW_HIP(hipMemcpy(plan->tw, tw.data(), tw.size() * sizeof(float2), hipMemcpyHostToDevice));
-    FW_HIP(hipMemset(plan->maps, 0, plan->maps_floats * sizeof(float)));
+    FW_HIP(hipMemcpy(plan->tw, tw.data(), tw.size() * sizeof(cplx), hipMemcpyHostToDevice));
+    FW_HIP(hipMemset(plan->maps, 0, plan->maps_floats * sizeof(real)));
     FW_HIP(hipMemset(plan->state, 0, plan->total_sys * sizeof(SysState)));
     FW_HIP(hipDeviceSynchronize());
     return FWILS_OK;
 }
 
-fwils_status fwils_set_contrast(fwils_plan plan, int32_t iprob, const float* maps) {
+fwils_status fwils_set_contrast(fwils_plan plan, int32_t iprob, const void* maps_) {
+    const real* maps = static_cast<const real*>(maps_);
     FW_TRY(check_plan(plan));
     if (iprob < 0 || iprob >= (int)plan->probs.size() || !maps) {
         set_error("set_contrast: bad problem index or null maps");
         return FWILS_EINVAL;
     }
     const ProbHost& P = plan->probs[iprob];
-    FW_HIP(hipMemcpyAsync(maps_at(plan, P), maps, (size_t)5 * P.p.nz * P.p.nx * sizeof(float),
+    FW_HIP(hipMemcpyAsync(maps_at(plan, P), maps, (size_t)5 * P.p.nz * P.p.nx * sizeof(real),
                           hipMemcpyDeviceToDevice, plan->stream));
     return FWILS_OK;
 }
@@ -895,10 +890,10 @@ fwils_status fwils_incident(fwils_plan plan, const int32_t* src_ixz, const doubl
     FW_HIP(hipMemcpy(plan->src_i, src_ixz, plan->total_sys * 2 * sizeof(int32_t), hipMemcpyHostToDevice));
     FW_HIP(hipMemcpy(plan->src_f, src_f, plan->total_sys * 2 * sizeof(double), hipMemcpyHostToDevice));
     for (const ProbHost& P : plan->probs) {
-        float2* f = at(plan->rhs, P);
+        cplx* f = at(plan->rhs, P);
         FW_HIP(launch_zero(f, (size_t)P.p.nsys * P.n_per_sys, s));
         FW_HIP(launch_point_sources(f, plan->src_i + 2 * P.sys_off, plan->src_f + 2 * P.sys_off, P.dev, s));
-        FW_HIP(conv_problem(plan, P, f, static_cast<float2*>(u0) + P.field_off));
+        FW_HIP(conv_problem(plan, P, f, static_cast<cplx*>(u0) + P.field_off));
     }
     return FWILS_OK;
 }
@@ -907,7 +902,7 @@ fwils_status fwils_body_force(fwils_plan plan, const void* u, void* b) {
     FW_TRY(check_plan(plan));
     FW_TRY(check_field_ptrs({u, b}));
     for (const ProbHost& P : plan->probs)
-        FW_HIP(launch_body_force(P.cfg.st, at(u, P), static_cast<float2*>(b) + P.field_off, maps_at(plan, P), P.dev,
+        FW_HIP(launch_body_force(P.cfg.st, at(u, P), static_cast<cplx*>(b) + P.field_off, maps_at(plan, P), P.dev,
                                  nullptr, plan->stream));
     return FWILS_OK;
 }
@@ -916,7 +911,7 @@ fwils_status fwils_convolve(fwils_plan plan, const void* f, void* out) {
     FW_TRY(check_plan(plan));
     FW_TRY(check_field_ptrs({f, out}));
     for (const ProbHost& P : plan->probs)
-        FW_HIP(conv_problem(plan, P, at(f, P), static_cast<float2*>(out) + P.field_off));
+        FW_HIP(conv_problem(plan, P, at(f, P), static_cast<cplx*>(out) + P.field_off));
     return FWILS_OK;
 }
 
@@ -929,7 +924,7 @@ fwils_status fwils_apply(fwils_plan plan, const void* u, void* Au) {
     }
     for (const ProbHost& P : plan->probs)
         FW_HIP(matvec(plan, P, P.dev, at(u, P), at(plan->tmp, P), maps_at(plan, P), EPI_APPLY, nullptr,
-                      static_cast<float2*>(Au) + P.field_off, nullptr, nullptr, plan->stream));
+                      static_cast<cplx*>(Au) + P.field_off, nullptr, nullptr, plan->stream));
     return FWILS_OK;
 }
 
@@ -943,10 +938,10 @@ fwils_status fwils_solve(fwils_plan plan, const void* rhs, void* x, double rtol,
     }
     hipStream_t s = plan->stream;
     const bool x0 = (flags & FWILS_SOLVE_X0) != 0;
-    if (x0) FW_HIP(launch_copy(static_cast<const float2*>(x), plan->x, plan->total_field, s));
-    fwils_status st = solve_ws(plan, static_cast<const float2*>(rhs), x0, rtol, maxit, iters, relres, flags);
+    if (x0) FW_HIP(launch_copy(static_cast<const cplx*>(x), plan->x, plan->total_field, s));
+    fwils_status st = solve_ws(plan, static_cast<const cplx*>(rhs), x0, rtol, maxit, iters, relres, flags);
     if (st == FWILS_EDEVICE) return st;
-    FW_HIP(launch_copy(plan->x, static_cast<float2*>(x), plan->total_field, s));
+    FW_HIP(launch_copy(plan->x, static_cast<cplx*>(x), plan->total_field, s));
     FW_HIP(hipStreamSynchronize(s));
     return st;
 }
@@ -957,7 +952,7 @@ namespace {
 
 // J dm (validated arguments): one virtual source, one convolution and one
 // gather per problem around one batched solve.
-fwils_status frechet_ws(fwils_plan plan, const void* ub, const float* const* dm, void* d, double rtol,
+fwils_status frechet_ws(fwils_plan plan, const void* ub, const real* const* dm, void* d, double rtol,
                         int32_t maxit) {
     hipStream_t s = plan->stream;
     for (size_t i = 0; i < plan->probs.size(); ++i) {
@@ -970,7 +965,7 @@ fwils_status frechet_ws(fwils_plan plan, const void* ub, const float* const* dm,
     if (st == FWILS_EDEVICE) return st;
     for (size_t i = 0; i < plan->probs.size(); ++i) {
         const ProbHost& P = plan->probs[i];
-        FW_HIP(launch_gather(at(plan->x, P), static_cast<float2*>(d) + P.data_off,
+        FW_HIP(launch_gather(at(plan->x, P), static_cast<cplx*>(d) + P.data_off,
                              plan->rec + i * kMaxRec * 2, P.nrec, P.dev, s));
     }
     return st;
@@ -983,9 +978,9 @@ fwils_status adjoint_ws(fwils_plan plan, const void* ub, const void* r, void* co
     hipStream_t s = plan->stream;
     for (size_t i = 0; i < plan->probs.size(); ++i) {
         const ProbHost& P = plan->probs[i];
-        float2* f = at(plan->s, P);
+        cplx* f = at(plan->s, P);
         FW_HIP(launch_zero(f, (size_t)P.p.nsys * P.n_per_sys, s));
-        FW_HIP(launch_scatter_conj(static_cast<const float2*>(r) + P.data_off, f,
+        FW_HIP(launch_scatter_conj(static_cast<const cplx*>(r) + P.data_off, f,
                                    plan->rec + i * kMaxRec * 2, P.nrec, P.dev, s));
         FW_HIP(conv_problem(plan, P, f, at(plan->rhs, P)));
     }
@@ -993,7 +988,7 @@ fwils_status adjoint_ws(fwils_plan plan, const void* ub, const void* r, void* co
     if (st == FWILS_EDEVICE) return st;
     for (size_t i = 0; i < plan->probs.size(); ++i) {
         const ProbHost& P = plan->probs[i];
-        FW_HIP(launch_correlate(at(plan->x, P), at(ub, P), static_cast<float2*>(g[i]), P.dev,
+        FW_HIP(launch_correlate(at(plan->x, P), at(ub, P), static_cast<cplx*>(g[i]), P.dev,
                                 accumulate, s));
     }
     return st;
@@ -1046,7 +1041,7 @@ size_t data_elems(fwils_plan plan) {
 }
 
 // reg_out = L^T L q (Laplacian) or q (identity) into mq_l2; also L q in mq_l1.
-fwils_status regulariser(fwils_plan plan, int32_t reg, const float* q, const float** rq) {
+fwils_status regulariser(fwils_plan plan, int32_t reg, const real* q, const real** rq) {
     const ProbHost& P = plan->probs[0];
     if (reg == FWILS_REG_LAPLACIAN) {
         FW_HIP(launch_laplacian(q, plan->mq_l1, P.p.nx, P.p.nz, 5, plan->stream));
@@ -1060,19 +1055,19 @@ fwils_status regulariser(fwils_plan plan, int32_t reg, const float* q, const flo
 
 // out = N q for a given rr (the normal operator of eq. norm)
 fwils_status normal_apply_ws(fwils_plan plan, const void* ub, const MapScales& m0, double rr, double lam,
-                             int32_t reg, const float* q, float* out, void* dscratch, double rtol,
+                             int32_t reg, const real* q, real* out, void* dscratch, double rtol,
                              int32_t maxit) {
     hipStream_t s = plan->stream;
     const int n = (int)plan->map_n;
     FW_HIP(launch_map_scale(q, plan->mq_dm, m0, n, s));
-    std::vector<const float*> dms(plan->probs.size(), plan->mq_dm);
+    std::vector<const real*> dms(plan->probs.size(), plan->mq_dm);
     fwils_status st = frechet_ws(plan, ub, dms.data(), dscratch, rtol, maxit);
     if (st == FWILS_EDEVICE) return st;
     std::vector<void*> gs(plan->probs.size(), plan->mq_g);
     FW_HIP(launch_zero(plan->mq_g, 5 * plan->map_n, s));
     fwils_status st2 = adjoint_ws(plan, ub, dscratch, gs.data(), true, rtol, maxit);
     if (st2 == FWILS_EDEVICE) return st2;
-    const float* rq = nullptr;
+    const real* rq = nullptr;
     FW_TRY(regulariser(plan, reg, q, &rq));
     FW_HIP(launch_map_combine(plan->mq_g, rq, out, m0, 1.0 / rr, lam, n, s));
     return worst(st, st2);
@@ -1088,8 +1083,9 @@ MapScales scales(const double* m0) {
 
 extern "C" {
 
-fwils_status fwils_frechet(fwils_plan plan, const void* ub, const float* const* dm, void* d,
+fwils_status fwils_frechet(fwils_plan plan, const void* ub, const void* const* dm_, void* d,
                            double rtol, int32_t maxit) {
+    const real* const* dm = reinterpret_cast<const real* const*>(dm_);
     FW_TRY(check_plan(plan));
     FW_TRY(check_field_ptrs({ub, dm, d}));
     for (size_t i = 0; i < plan->probs.size(); ++i) {
@@ -1127,8 +1123,10 @@ fwils_status fwils_adjoint(fwils_plan plan, const void* ub, const void* r, void*
 }
 
 fwils_status fwils_normal_apply(fwils_plan plan, const void* ub, const double* m0, double rr, double lam,
-                                int32_t reg, const float* q_in, float* q_out, void* dscratch, double rtol,
+                                int32_t reg, const void* q_in_, void* q_out_, void* dscratch, double rtol,
                                 int32_t maxit) {
+    const real* q_in = static_cast<const real*>(q_in_);
+    real* q_out = static_cast<real*>(q_out_);
     FW_TRY(check_plan(plan));
     FW_TRY(check_field_ptrs({ub, q_in, q_out, dscratch}));
     FW_TRY(check_tik(plan, m0, lam, reg, rtol, maxit, "normal_apply"));
@@ -1143,8 +1141,10 @@ fwils_status fwils_normal_apply(fwils_plan plan, const void* ub, const double* m
 }
 
 fwils_status fwils_tikhonov_grad(fwils_plan plan, const void* ub, const void* r, const double* m0, double lam,
-                                 int32_t reg, const float* q, float* grad, double* fval, void* dscratch,
+                                 int32_t reg, const void* q_, void* grad_, double* fval, void* dscratch,
                                  double rtol, int32_t maxit) {
+    const real* q = static_cast<const real*>(q_);
+    real* grad = static_cast<real*>(grad_);
     FW_TRY(check_plan(plan));
     FW_TRY(check_field_ptrs({ub, r, q, grad, dscratch}));
     FW_TRY(check_tik(plan, m0, lam, reg, rtol, maxit, "tikhonov_grad"));
@@ -1154,22 +1154,22 @@ fwils_status fwils_tikhonov_grad(fwils_plan plan, const void* ub, const void* r,
     const size_t nd = data_elems(plan);
     double* sc = plan->mq_sc;
     // rr = ||r||^2
-    FW_HIP(launch_norm2_complex(static_cast<const float2*>(r), nd, plan->mq_part, sc + 4, s));
+    FW_HIP(launch_norm2_complex(static_cast<const cplx*>(r), nd, plan->mq_part, sc + 4, s));
     // residual J q - r and its norm
     FW_HIP(launch_map_scale(q, plan->mq_dm, ms, n, s));
-    std::vector<const float*> dms(plan->probs.size(), plan->mq_dm);
+    std::vector<const real*> dms(plan->probs.size(), plan->mq_dm);
     fwils_status st = frechet_ws(plan, ub, dms.data(), dscratch, rtol, maxit);
     if (st == FWILS_EDEVICE) return st;
-    FW_HIP(launch_sub_complex(static_cast<float2*>(dscratch), static_cast<const float2*>(r), nd, s));
-    FW_HIP(launch_norm2_complex(static_cast<const float2*>(dscratch), nd, plan->mq_part, sc + 5, s));
+    FW_HIP(launch_sub_complex(static_cast<cplx*>(dscratch), static_cast<const cplx*>(r), nd, s));
+    FW_HIP(launch_norm2_complex(static_cast<const cplx*>(dscratch), nd, plan->mq_part, sc + 5, s));
     std::vector<void*> gs(plan->probs.size(), plan->mq_g);
     FW_HIP(launch_zero(plan->mq_g, 5 * plan->map_n, s));
     fwils_status st2 = adjoint_ws(plan, ub, dscratch, gs.data(), true, rtol, maxit);
     if (st2 == FWILS_EDEVICE) return st2;
-    const float* rq = nullptr;
+    const real* rq = nullptr;
     FW_TRY(regulariser(plan, reg, q, &rq));
     // ||L q||^2
-    const float* lq = (reg == FWILS_REG_LAPLACIAN) ? plan->mq_l1 : q;
+    const real* lq = (reg == FWILS_REG_LAPLACIAN) ? plan->mq_l1 : q;
     FW_HIP(launch_dot_real(lq, lq, 5 * plan->map_n, plan->mq_part, sc + 6, s));
     double h[3];
     FW_HIP(hipMemcpyAsync(h, sc + 4, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1184,21 +1184,23 @@ fwils_status fwils_tikhonov_grad(fwils_plan plan, const void* ub, const void* r,
     return worst(st, st2);
 }
 
-fwils_status fwils_frechet_rel(fwils_plan plan, const void* ub, const float* q, const double* m0, void* d,
+fwils_status fwils_frechet_rel(fwils_plan plan, const void* ub, const void* q_, const double* m0, void* d,
                                double rtol, int32_t maxit) {
+    const real* q = static_cast<const real*>(q_);
     FW_TRY(check_plan(plan));
     FW_TRY(check_field_ptrs({ub, q, d}));
     FW_TRY(check_tik(plan, m0, 0.0, FWILS_REG_IDENTITY, rtol, maxit, "frechet_rel"));
     FW_HIP(launch_map_scale(q, plan->mq_dm, scales(m0), (int)plan->map_n, plan->stream));
-    std::vector<const float*> dms(plan->probs.size(), plan->mq_dm);
+    std::vector<const real*> dms(plan->probs.size(), plan->mq_dm);
     fwils_status st = frechet_ws(plan, ub, dms.data(), d, rtol, maxit);
     if (st == FWILS_EDEVICE) return st;
     FW_HIP(hipStreamSynchronize(plan->stream));
     return st;
 }
 
-fwils_status fwils_adjoint_rel(fwils_plan plan, const void* ub, const void* r, const double* m0, float* gq,
+fwils_status fwils_adjoint_rel(fwils_plan plan, const void* ub, const void* r, const double* m0, void* gq_,
                                double rtol, int32_t maxit) {
+    real* gq = static_cast<real*>(gq_);
     FW_TRY(check_plan(plan));
     FW_TRY(check_field_ptrs({ub, r, gq}));
     FW_TRY(check_tik(plan, m0, 0.0, FWILS_REG_IDENTITY, rtol, maxit, "adjoint_rel"));
@@ -1211,7 +1213,9 @@ fwils_status fwils_adjoint_rel(fwils_plan plan, const void* ub, const void* r, c
     return st;
 }
 
-fwils_status fwils_laplacian(fwils_plan plan, const float* q, float* out) {
+fwils_status fwils_laplacian(fwils_plan plan, const void* q_, void* out_) {
+    const real* q = static_cast<const real*>(q_);
+    real* out = static_cast<real*>(out_);
     FW_TRY(check_plan(plan));
     FW_TRY(check_field_ptrs({q, out}));
     if (!plan->map_n || q == out) {
@@ -1223,8 +1227,9 @@ fwils_status fwils_laplacian(fwils_plan plan, const float* q, float* out) {
 }
 
 fwils_status fwils_normal_cg(fwils_plan plan, const void* ub, const void* r, const double* m0, double lam,
-                             int32_t reg, int32_t niter, float* q, double* hist, void* dscratch, double rtol,
+                             int32_t reg, int32_t niter, void* q_, double* hist, void* dscratch, double rtol,
                              int32_t maxit) {
+    real* q = static_cast<real*>(q_);
     FW_TRY(check_plan(plan));
     FW_TRY(check_field_ptrs({ub, r, q, dscratch}));
     FW_TRY(check_tik(plan, m0, lam, reg, rtol, maxit, "normal_cg"));
@@ -1238,7 +1243,7 @@ fwils_status fwils_normal_cg(fwils_plan plan, const void* ub, const void* r, con
     const size_t nm = 5 * plan->map_n;
     double* sc = plan->mq_sc;
     // rr and the right-hand side m0 Re J* r / rr
-    FW_HIP(launch_norm2_complex(static_cast<const float2*>(r), data_elems(plan), plan->mq_part, sc + 4, s));
+    FW_HIP(launch_norm2_complex(static_cast<const cplx*>(r), data_elems(plan), plan->mq_part, sc + 4, s));
     double rr = 0;
     FW_HIP(hipMemcpyAsync(&rr, sc + 4, sizeof(double), hipMemcpyDeviceToHost, s));
     FW_HIP(hipStreamSynchronize(s));
@@ -1255,6 +1260,10 @@ fwils_status fwils_normal_cg(fwils_plan plan, const void* ub, const void* r, con
     FW_HIP(launch_copy_f(plan->mq_res, plan->mq_p, nm, s));
     FW_HIP(launch_dot_real(plan->mq_res, plan->mq_res, nm, plan->mq_part, sc + 2, s));
     FW_HIP(launch_cg_shift(sc, plan->mq_hist, 0, s));
+    double rs0 = 0.0;
+    FW_HIP(hipMemcpyAsync(&rs0, sc + 2, sizeof(double), hipMemcpyDeviceToHost, s));
+    FW_HIP(hipStreamSynchronize(s));
+    int done = niter;   // iterations run: fewer once the residual is at the floor
     for (int it = 0; it < niter; ++it) {
         fwils_status sa = normal_apply_ws(plan, ub, ms, rr, lam, reg, plan->mq_p, plan->mq_Ap, dscratch,
                                           rtol, maxit);
@@ -1265,11 +1274,22 @@ fwils_status fwils_normal_cg(fwils_plan plan, const void* ub, const void* r, con
         FW_HIP(launch_dot_real(plan->mq_res, plan->mq_res, nm, plan->mq_part, sc + 2, s));
         FW_HIP(launch_cg_p(plan->mq_p, plan->mq_res, sc, nm, s));
         FW_HIP(launch_cg_shift(sc, plan->mq_hist, it + 1, s));
+        // converged to working precision: further iterations would only push
+        // the direction vectors towards underflow
+        double rs = 0.0;
+        FW_HIP(hipMemcpyAsync(&rs, sc + 2, sizeof(double), hipMemcpyDeviceToHost, s));
+        FW_HIP(hipStreamSynchronize(s));
+        if (!(rs > kCgFloor * rs0)) {
+            done = it + 1;
+            break;
+        }
     }
     FW_HIP(launch_copy_f(plan->mq_x, q, nm, s));
     if (hist)
-        FW_HIP(hipMemcpyAsync(hist, plan->mq_hist, (size_t)(niter + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+        FW_HIP(hipMemcpyAsync(hist, plan->mq_hist, (size_t)(done + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
     FW_HIP(hipStreamSynchronize(s));
+    if (hist)
+        for (int i = done + 1; i <= niter; ++i) hist[i] = hist[done];
     return st;
 }
 
@@ -1282,7 +1302,7 @@ fwils_status fwils_apply_pass(fwils_plan plan, int32_t pass, const void* u, void
     hipStream_t s = plan->stream;
     for (const ProbHost& P : plan->probs) {
         const int rows = P.p.nsys * 2 * P.p.nz;
-        float2* tmp = at(plan->tmp, P);
+        cplx* tmp = at(plan->tmp, P);
         switch (pass) {
             case 0:
                 if (P.cfg.fuse_p) {
@@ -1299,7 +1319,7 @@ fwils_status fwils_apply_pass(fwils_plan plan, int32_t pass, const void* u, void
             case 2: FW_HIP(launch_cols(COL_GREEN, P.cfg.col, tmp, P.dev, nullptr, plan->tw, s)); break;
             default:
                 FW_HIP(launch_rows_inv(P.p.nx, P.cfg.row_p, EPI_APPLY, tmp, at(u, P), nullptr,
-                                       static_cast<float2*>(Au) + P.field_off, nullptr, rows, 2 * P.p.nz,
+                                       static_cast<cplx*>(Au) + P.field_off, nullptr, rows, 2 * P.p.nz,
                                        nullptr, plan->tw, s));
         }
     }
@@ -1366,6 +1386,8 @@ fwils_status fwils_solve_stats(fwils_plan plan, int32_t* iters, double* relres) 
     return FWILS_OK;
 }
 
+}  // extern "C"
+
 namespace {
 
 // Layout of the GMRES workspace for restart length m.
@@ -1384,7 +1406,7 @@ GmLayout gm_layout(fwils_plan pl, int m) {
     }
     size_t o = 0;
     L.basis = o;
-    o = align256(o + (size_t)(m + 1) * pl->total_field * sizeof(float2));
+    o = align256(o + (size_t)(m + 1) * pl->total_field * sizeof(cplx));
     L.sys = o;
     o = align256(o + pl->total_sys * sizeof(GmSys));
     L.part = o;
@@ -1396,6 +1418,8 @@ GmLayout gm_layout(fwils_plan pl, int m) {
 }
 
 }  // namespace
+
+extern "C" {
 
 fwils_status fwils_gmres_workspace_size(fwils_plan plan, int32_t restart, size_t* bytes) {
     FW_TRY(check_plan(plan, false));
@@ -1442,7 +1466,7 @@ fwils_status fwils_set_krylov(fwils_plan plan, int32_t method, int32_t restart, 
     plan->gm_m = restart;
     plan->gm_cgs2 = !(flags & FWILS_GMRES_CGS1);
     plan->gm_maxnb = L.maxnb;
-    plan->gm_V = reinterpret_cast<float2*>(w + L.basis);
+    plan->gm_V = reinterpret_cast<cplx*>(w + L.basis);
     plan->gm_sys = reinterpret_cast<GmSys*>(w + L.sys);
     plan->gm_part = reinterpret_cast<double*>(w + L.part);
     plan->gm_tot1 = reinterpret_cast<double*>(w + L.tot);
@@ -1543,8 +1567,8 @@ std::vector<KernelCfg> candidates(const ProbHost& P, int kind) {
 // problem P (fields from the workspace vectors; every system active).
 hipError_t tune_launch(fwils_plan pl, const ProbHost& P, int kind, const KernelCfg& k) {
     const int rows = P.p.nsys * 2 * P.p.nz;
-    float2* u = at(pl->x, P);
-    float2* tmp = at(pl->tmp, P);
+    cplx* u = at(pl->x, P);
+    cplx* tmp = at(pl->tmp, P);
     if (kind == FWILS_TUNE_STENCIL) return launch_body_force(k.st, u, tmp, maps_at(pl, P), P.dev, nullptr, pl->stream);
     if (kind == FWILS_TUNE_ROWS)
         return launch_rows_fwd(P.p.nx, k.row_p, tmp, tmp, rows, 2 * P.p.nz, nullptr, pl->tw, pl->stream);
@@ -1682,8 +1706,8 @@ fwils_status fwils_fft2(fwils_plan plan, int32_t iprob, const void* in, void* ou
     }
     const ProbHost& P = plan->probs[iprob];
     const int rows = P.p.nsys * 2 * P.p.nz;
-    const float2* src = static_cast<const float2*>(in);
-    float2* dst = static_cast<float2*>(out);
+    const cplx* src = static_cast<const cplx*>(in);
+    cplx* dst = static_cast<cplx*>(out);
     hipStream_t s = plan->stream;
     if (!inverse) {
         FW_HIP(launch_rows_fwd(P.p.nx, row_points_default(P.p.nx), src, dst, rows, 2 * P.p.nz, nullptr,

@@ -1,50 +1,91 @@
 // Shared device-side definitions for the fwils HIP kernels (gfx950).
 //
-// Complex numbers are float2 (re, im).  Fields are [nsys][2][nz][nx] complex64
-// with x fastest; maps are [5][nz][nx] fp32 in the order
-// (dC11, dC13, dC33, dC55, drho).
+// The library core is compiled twice from the same sources: complex64 fields
+// with fp32 maps (namespace fw::c64, the product path) and, with FW_C128
+// defined, complex128 fields with fp64 maps (namespace fw::c128, the FP64
+// reference of the same path).  `cplx` / `real` are the field and map types
+// of the build.  Fields are [nsys][2][nz][nx] complex with x fastest; maps are
+// [5][nz][nx] real in the order (dC11, dC13, dC33, dC55, drho).  Krylov
+// scalars, inner products and norms are FP64 in both builds.
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-namespace fw {
+#ifdef FW_C128
+#define FW_NS c128
+#else
+#define FW_NS c64
+#endif
+#define FW_BEGIN namespace fw { inline namespace FW_NS {
+#define FW_END } }
+
+FW_BEGIN
+
+#ifdef FW_C128
+using real = double;
+using cplx = double2;
+#else
+using real = float;
+using cplx = float2;
+#endif
 
 // ---------------------------------------------------------------- complex --
-__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
-__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+__host__ __device__ __forceinline__ cplx mkc(real re, real im) {
+    cplx z;
+    z.x = re;
+    z.y = im;
+    return z;
 }
-__device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
-__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+__device__ __forceinline__ cplx cadd(cplx a, cplx b) { return mkc(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ cplx csub(cplx a, cplx b) { return mkc(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ cplx cmul(cplx a, cplx b) { return mkc(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+__device__ __forceinline__ cplx cscale(cplx a, real s) { return mkc(a.x * s, a.y * s); }
+__device__ __forceinline__ cplx cconj(cplx a) { return mkc(a.x, -a.y); }
 // multiply by -i (forward transform) or +i (inverse transform)
 template <bool INV>
-__device__ __forceinline__ float2 mul_mi(float2 z) {
-    return INV ? make_float2(-z.y, z.x) : make_float2(z.y, -z.x);
+__device__ __forceinline__ cplx mul_mi(cplx z) {
+    return INV ? mkc(-z.y, z.x) : mkc(z.y, -z.x);
+}
+
+__device__ __forceinline__ real rsinpi(real x) {
+#ifdef FW_C128
+    return sinpi(x);
+#else
+    return sinpif(x);
+#endif
 }
 
 struct dcomplex { double re, im; };
 
 // Store of one complex value that writes through the L2 (system-coherent
 // policy): the kernel's output leaves no dirty L2 lines behind, so the cache
-// write-back at the kernel boundary has nothing to flush.
-__device__ __forceinline__ void st_wt(float2* p, float2 v) {
+// write-back at the kernel boundary has nothing to flush.  A store of more
+// than 8 bytes keeps reading its data registers after issue, and the compiler
+// cannot see that inside inline assembly: the 16-byte form waits itself
+// (s_nop) before any later instruction may overwrite them.
+__device__ __forceinline__ void st_wt(cplx* p, cplx v) {
+#ifdef FW_C128
+    typedef double d2v __attribute__((ext_vector_type(2)));
+    const d2v w = {v.x, v.y};
+    asm volatile("global_store_dwordx4 %0, %1, off sc0 sc1\n\ts_nop 1" ::"v"(p), "v"(w) : "memory");
+#else
     asm volatile("global_store_dwordx2 %0, %1, off sc0 sc1" ::"v"(p), "v"(v) : "memory");
+#endif
 }
 
 // --------------------------------------------------------- problem consts --
 // Per-problem constants, passed by value to every kernel of that problem.
 struct ProbDev {
     int nx, nz, nsys, symbol;
-    float inv4dx2;        // 1 / (4 dx^2): both central differences of the stencil
-    float2 w2;            // w~^2 = (2 pi f (1 + i eta))^2
+    real inv4dx2;         // 1 / (4 dx^2): both central differences of the stencil
+    cplx w2;              // w~^2 = (2 pi f (1 + i eta))^2
     // Green's symbol in units of rho0 w^2 (w real): Gamma' = Gamma / (rho0 w^2)
-    float gc11, gc33, gc55, gc1355;   // C11, C33, C55, C13 + C55 over rho0 w^2
-    float2 ga;            // (1 + i eta)^2 = rho0 w~^2 / (rho0 w^2)
-    float gscale;         // 1 / (rho0 w^2 nx nz): Green's scale and IFFT normalisation
-    float dkx, dkz;       // 2 pi / (nx dx), 2 pi / (nz dx)
-    float dx;
+    real gc11, gc33, gc55, gc1355;    // C11, C33, C55, C13 + C55 over rho0 w^2
+    cplx ga;              // (1 + i eta)^2 = rho0 w~^2 / (rho0 w^2)
+    real gscale;          // 1 / (rho0 w^2 nx nz): Green's scale and IFFT normalisation
+    real dkx, dkz;        // 2 pi / (nx dx), 2 pi / (nz dx)
+    real dx;
 };
 
 // --------------------------------------------------------- solver state ---
@@ -187,4 +228,4 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblk) {
     return (bid & 7) * (full >> 3) + (bid >> 3);
 }
 
-}  // namespace fw
+FW_END

@@ -18,8 +18,7 @@
 
 #include "common.h"
 
-namespace fw {
-
+FW_BEGIN
 struct RadixPlan {
     int np;
     int r[16];
@@ -57,16 +56,16 @@ struct FftShape {
 
 // --------------------------------------------------------- small DFTs -----
 template <bool INV>
-__device__ __forceinline__ void dft2(float2& a, float2& b) {
-    const float2 t = a;
+__device__ __forceinline__ void dft2(cplx& a, cplx& b) {
+    const cplx t = a;
     a = cadd(t, b);
     b = csub(t, b);
 }
 
 template <bool INV>
-__device__ __forceinline__ void dft4(float2& x0, float2& x1, float2& x2, float2& x3) {
-    const float2 a = cadd(x0, x2), b = csub(x0, x2);
-    const float2 c = cadd(x1, x3), d = mul_mi<INV>(csub(x1, x3));
+__device__ __forceinline__ void dft4(cplx& x0, cplx& x1, cplx& x2, cplx& x3) {
+    const cplx a = cadd(x0, x2), b = csub(x0, x2);
+    const cplx c = cadd(x1, x3), d = mul_mi<INV>(csub(x1, x3));
     x0 = cadd(a, c);
     x2 = csub(a, c);
     x1 = cadd(b, d);
@@ -75,12 +74,12 @@ __device__ __forceinline__ void dft4(float2& x0, float2& x1, float2& x2, float2&
 
 // multiply by W_M^e = exp(-+ 2 pi i e / M) for compile-time e, M in {8, 16}
 template <bool INV, int M, int E>
-__device__ __forceinline__ float2 twc(float2 z) {
+__device__ __forceinline__ cplx twc(cplx z) {
     constexpr int e = ((E % M) + M) % M;
     constexpr int e16 = e * (16 / M);
     if constexpr (e16 == 0) return z;
     else if constexpr (e16 == 4) return mul_mi<INV>(z);
-    else if constexpr (e16 == 8) return make_float2(-z.x, -z.y);
+    else if constexpr (e16 == 8) return mkc(-z.x, -z.y);
     else if constexpr (e16 == 12) return mul_mi<!INV>(z);
     else {
         constexpr double C[16] = {1.0, 0.92387953251128674, 0.70710678118654752, 0.38268343236508978,
@@ -91,27 +90,27 @@ __device__ __forceinline__ float2 twc(float2 z) {
                                   1.0, 0.92387953251128674, 0.70710678118654752, 0.38268343236508978,
                                   0.0, -0.38268343236508978, -0.70710678118654752, -0.92387953251128674,
                                   -1.0, -0.92387953251128674, -0.70710678118654752, -0.38268343236508978};
-        constexpr float c = (float)C[e16];
-        constexpr float s = INV ? (float)S[e16] : -(float)S[e16];   // W = c + i s
-        return make_float2(z.x * c - z.y * s, z.x * s + z.y * c);
+        constexpr real c = (real)C[e16];
+        constexpr real s = INV ? (real)S[e16] : -(real)S[e16];   // W = c + i s
+        return mkc(z.x * c - z.y * s, z.x * s + z.y * c);
     }
 }
 
 template <bool INV>
-__device__ __forceinline__ void dft8(float2 (&x)[8]) {
+__device__ __forceinline__ void dft8(cplx (&x)[8]) {
     // even / odd halves, then combine with W_8^k
     dft4<INV>(x[0], x[2], x[4], x[6]);
     dft4<INV>(x[1], x[3], x[5], x[7]);
-    float2 y[8];
+    cplx y[8];
     y[0] = cadd(x[0], x[1]);
     y[4] = csub(x[0], x[1]);
-    const float2 o1 = twc<INV, 8, 1>(x[3]);
+    const cplx o1 = twc<INV, 8, 1>(x[3]);
     y[1] = cadd(x[2], o1);
     y[5] = csub(x[2], o1);
-    const float2 o2 = twc<INV, 8, 2>(x[5]);
+    const cplx o2 = twc<INV, 8, 2>(x[5]);
     y[2] = cadd(x[4], o2);
     y[6] = csub(x[4], o2);
-    const float2 o3 = twc<INV, 8, 3>(x[7]);
+    const cplx o3 = twc<INV, 8, 3>(x[7]);
     y[3] = cadd(x[6], o3);
     y[7] = csub(x[6], o3);
 #pragma unroll
@@ -119,7 +118,7 @@ __device__ __forceinline__ void dft8(float2 (&x)[8]) {
 }
 
 template <bool INV>
-__device__ __forceinline__ void dft16(float2 (&x)[16]) {
+__device__ __forceinline__ void dft16(cplx (&x)[16]) {
     // n = n1 + 4 n2: DFT4 over n2, twiddle W16^(n1 k1), DFT4 over n1; out k1 + 4 k2
     dft4<INV>(x[0], x[4], x[8], x[12]);
     dft4<INV>(x[1], x[5], x[9], x[13]);
@@ -135,10 +134,10 @@ __device__ __forceinline__ void dft16(float2 (&x)[16]) {
     x[7] = twc<INV, 16, 3>(x[7]);
     x[11] = twc<INV, 16, 6>(x[11]);
     x[15] = twc<INV, 16, 9>(x[15]);
-    float2 y[16];
+    cplx y[16];
 #pragma unroll
     for (int k1 = 0; k1 < 4; ++k1) {
-        float2 a = x[4 * k1 + 0], b = x[4 * k1 + 1], c = x[4 * k1 + 2], d = x[4 * k1 + 3];
+        cplx a = x[4 * k1 + 0], b = x[4 * k1 + 1], c = x[4 * k1 + 2], d = x[4 * k1 + 3];
         dft4<INV>(a, b, c, d);
         y[k1 + 0] = a;
         y[k1 + 4] = b;
@@ -150,18 +149,18 @@ __device__ __forceinline__ void dft16(float2 (&x)[16]) {
 }
 
 template <bool INV>
-__device__ __forceinline__ void dft3(float2& x0, float2& x1, float2& x2) {
-    const float h = 0.86602540378443865f;   // sqrt(3) / 2
-    const float2 t1 = cadd(x1, x2);
-    const float2 m = make_float2(x0.x - 0.5f * t1.x, x0.y - 0.5f * t1.y);
-    const float2 d = mul_mi<INV>(cscale(csub(x1, x2), h));
+__device__ __forceinline__ void dft3(cplx& x0, cplx& x1, cplx& x2) {
+    const real h = (real)0.86602540378443864676;   // sqrt(3) / 2
+    const cplx t1 = cadd(x1, x2);
+    const cplx m = mkc(x0.x - 0.5f * t1.x, x0.y - 0.5f * t1.y);
+    const cplx d = mul_mi<INV>(cscale(csub(x1, x2), h));
     x0 = cadd(x0, t1);
     x1 = cadd(m, d);
     x2 = csub(m, d);
 }
 
 template <int R, bool INV>
-__device__ __forceinline__ void dft(float2 (&x)[R]) {
+__device__ __forceinline__ void dft(cplx (&x)[R]) {
     if constexpr (R == 2) dft2<INV>(x[0], x[1]);
     else if constexpr (R == 3) dft3<INV>(x[0], x[1], x[2]);
     else if constexpr (R == 4) dft4<INV>(x[0], x[1], x[2], x[3]);
@@ -175,22 +174,22 @@ __device__ __forceinline__ void dft(float2 (&x)[R]) {
 // the inverse).  Only W^e and, for R >= 8, W^(4e) are read from the table; the
 // other powers are products of at most four factors (a few ulp).
 template <int R, bool INV>
-__device__ __forceinline__ void twiddles(float2 (&w)[R], const float2* __restrict__ tw, int e) {
-    float2 w1 = tw[e];
+__device__ __forceinline__ void twiddles(cplx (&w)[R], const cplx* __restrict__ tw, int e) {
+    cplx w1 = tw[e];
     if (INV) w1 = cconj(w1);
     w[1] = w1;
     if constexpr (R >= 3) w[2] = cmul(w1, w1);
     if constexpr (R >= 4) w[3] = cmul(w[2], w1);
     if constexpr (R >= 8) {
-        float2 w4 = tw[4 * e];
+        cplx w4 = tw[4 * e];
         if (INV) w4 = cconj(w4);
         w[4] = w4;
 #pragma unroll
         for (int r = 5; r < 8; ++r) w[r] = cmul(w4, w[r - 4]);
     }
     if constexpr (R == 16) {
-        const float2 w8 = cmul(w[4], w[4]);
-        const float2 w12 = cmul(w8, w[4]);
+        const cplx w8 = cmul(w[4], w[4]);
+        const cplx w12 = cmul(w8, w[4]);
         w[8] = w8;
         w[12] = w12;
 #pragma unroll
@@ -206,8 +205,8 @@ __device__ __forceinline__ void twiddles(float2 (&w)[R], const float2* __restric
 // thread (v[f][m] at position t + T*m).  Non-final passes write to LDS through
 // the accessor `lds(f, pos)`; the final pass leaves its outputs in v.
 template <int N, int P, int I, bool INV, int NF, class Lds>
-__device__ __forceinline__ void fft_pass(float2 (&v)[NF][P], int t,
-                                         const float2* __restrict__ tw, const Lds& lds) {
+__device__ __forceinline__ void fft_pass(cplx (&v)[NF][P], int t,
+                                         const cplx* __restrict__ tw, const Lds& lds) {
     using S = FftShape<N, P>;
     constexpr int R = S::plan.r[I];
     constexpr int NS = S::ns_before(I);
@@ -218,11 +217,11 @@ __device__ __forceinline__ void fft_pass(float2 (&v)[NF][P], int t,
     for (int b = 0; b < NB; ++b) {
         const int j = t + S::T * b;
         const int k = j % NS;
-        float2 w[R];
+        cplx w[R];
         if constexpr (NS > 1) twiddles<R, INV>(w, tw, k * TWS);
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
-            float2 x[R];
+            cplx x[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) x[r] = v[f][b + r * NB];
             if constexpr (NS > 1) {
@@ -243,8 +242,8 @@ __device__ __forceinline__ void fft_pass(float2 (&v)[NF][P], int t,
 }
 
 template <int N, int P, bool INV, int NF, int I, class Lds>
-__device__ __forceinline__ void fft_from(float2 (&v)[NF][P], int t,
-                                         const float2* __restrict__ tw, const Lds& lds) {
+__device__ __forceinline__ void fft_from(cplx (&v)[NF][P], int t,
+                                         const cplx* __restrict__ tw, const Lds& lds) {
     using S = FftShape<N, P>;
     fft_pass<N, P, I, INV, NF>(v, t, tw, lds);
     if constexpr (I + 1 < S::NP) {
@@ -261,8 +260,8 @@ __device__ __forceinline__ void fft_from(float2 (&v)[NF][P], int t,
 
 // Full transform.  Every thread of the workgroup must call this (barriers).
 template <int N, int P, bool INV, int NF, class Lds>
-__device__ __forceinline__ void fft_run(float2 (&v)[NF][P], int t,
-                                        const float2* __restrict__ tw, const Lds& lds) {
+__device__ __forceinline__ void fft_run(cplx (&v)[NF][P], int t,
+                                        const cplx* __restrict__ tw, const Lds& lds) {
     fft_from<N, P, INV, NF, 0>(v, t, tw, lds);
 }
 
@@ -272,8 +271,8 @@ __device__ __forceinline__ void fft_run(float2 (&v)[NF][P], int t,
 // barrier) before it starts transform f + 1.  Half the LDS of fft_run for
 // NF = 2, at the price of two more barriers per pass.
 template <int N, int P, int I, bool INV, int NF, class Lds>
-__device__ __forceinline__ void fft_pass_seq(float2 (&v)[NF][P], int t,
-                                             const float2* __restrict__ tw, const Lds& lds) {
+__device__ __forceinline__ void fft_pass_seq(cplx (&v)[NF][P], int t,
+                                             const cplx* __restrict__ tw, const Lds& lds) {
     using S = FftShape<N, P>;
     constexpr int R = S::plan.r[I];
     constexpr int NS = S::ns_before(I);
@@ -286,11 +285,11 @@ __device__ __forceinline__ void fft_pass_seq(float2 (&v)[NF][P], int t,
         for (int b = 0; b < NB; ++b) {
             const int j = t + S::T * b;
             const int k = j % NS;
-            float2 x[R];
+            cplx x[R];
 #pragma unroll
             for (int r = 0; r < R; ++r) x[r] = v[f][b + r * NB];
             if constexpr (NS > 1) {
-                float2 w[R];
+                cplx w[R];
                 twiddles<R, INV>(w, tw, k * TWS);
 #pragma unroll
                 for (int r = 1; r < R; ++r) x[r] = cmul(x[r], w[r]);
@@ -315,8 +314,8 @@ __device__ __forceinline__ void fft_pass_seq(float2 (&v)[NF][P], int t,
 }
 
 template <int N, int P, bool INV, int NF, int I, class Lds>
-__device__ __forceinline__ void fft_from_seq(float2 (&v)[NF][P], int t,
-                                             const float2* __restrict__ tw, const Lds& lds) {
+__device__ __forceinline__ void fft_from_seq(cplx (&v)[NF][P], int t,
+                                             const cplx* __restrict__ tw, const Lds& lds) {
     fft_pass_seq<N, P, I, INV, NF>(v, t, tw, lds);
     if constexpr (I + 1 < FftShape<N, P>::NP) fft_from_seq<N, P, INV, NF, I + 1>(v, t, tw, lds);
 }
@@ -324,8 +323,8 @@ __device__ __forceinline__ void fft_from_seq(float2 (&v)[NF][P], int t,
 // Full transform with one shared LDS buffer; every thread must call it.  The
 // caller must make sure no thread still reads the buffer from earlier use.
 template <int N, int P, bool INV, int NF, class Lds>
-__device__ __forceinline__ void fft_run_seq(float2 (&v)[NF][P], int t,
-                                            const float2* __restrict__ tw, const Lds& lds) {
+__device__ __forceinline__ void fft_run_seq(cplx (&v)[NF][P], int t,
+                                            const cplx* __restrict__ tw, const Lds& lds) {
     fft_from_seq<N, P, INV, NF, 0>(v, t, tw, lds);
 }
 
@@ -335,4 +334,4 @@ __device__ __forceinline__ int lds_pad(int pos) { return pos + (pos >> 4); }
 template <int N>
 struct PaddedLen { static constexpr int value = N + N / 16 + 1; };
 
-}  // namespace fw
+FW_END

@@ -11,8 +11,7 @@
 #include "fft.h"
 #include "launch.h"
 
-namespace fw {
-
+FW_BEGIN
 // ------------------------------------------------------- block reduce ----
 // Runtime block size (a multiple of 64, at most 256): fixed-order sum of
 // NV doubles; thread 0 receives the total.
@@ -41,25 +40,25 @@ __device__ __forceinline__ void block_sum_to0(double (&acc)[NV], double* smem) {
 
 // --------------------------------------------------------- row kernel ----
 struct RowLds {
-    float2* p;
-    __device__ __forceinline__ float2& operator()(int, int pos) const { return p[lds_pad(pos)]; }
+    cplx* p;
+    __device__ __forceinline__ cplx& operator()(int, int pos) const { return p[lds_pad(pos)]; }
 };
 
 // Row transforms of F rows per block, P points per thread (T = N / P threads
 // per row).  `in` and `out` may be the same array (in-place forward pass):
 // every block reads all of its rows before its barriers and writes them after.
 template <int N, int P, bool INV, int EPI>
-__global__ __launch_bounds__(256) void k_rows(const float2* in, float2* out,
-                                              const float2* __restrict__ u,
-                                              const float2* __restrict__ aux,
+__global__ __launch_bounds__(256) void k_rows(const cplx* in, cplx* out,
+                                              const cplx* __restrict__ u,
+                                              const cplx* __restrict__ aux,
                                               double* __restrict__ partials, int nrows,
                                               int rows_per_sys, int F,
                                               SysState* __restrict__ st,
-                                              const float2* __restrict__ tw, GmEpi ge) {
+                                              const cplx* __restrict__ tw, GmEpi ge) {
     using S = FftShape<N, P>;
     constexpr int T = S::T;
     constexpr int PL = PaddedLen<N>::value;
-    extern __shared__ float2 lds_dyn[];
+    extern __shared__ cplx lds_dyn[];
     __shared__ double red[4 * kPartialNV];
 
     const int tid = threadIdx.x;
@@ -70,14 +69,14 @@ __global__ __launch_bounds__(256) void k_rows(const float2* in, float2* out,
     const int row = row0 + q;
     const bool active = (q < F) && (row < nrows);
 
-    float2 v[1][P];
+    cplx v[1][P];
     if (active) {
-        const float2* src = in + (size_t)row * N;
+        const cplx* src = in + (size_t)row * N;
 #pragma unroll
         for (int m = 0; m < P; ++m) v[0][m] = src[t + T * m];
     } else {
 #pragma unroll
-        for (int m = 0; m < P; ++m) v[0][m] = make_float2(0.f, 0.f);
+        for (int m = 0; m < P; ++m) v[0][m] = mkc(0.f, 0.f);
     }
     // idle threads (block padded to whole waves) work in a dummy slot F
     RowLds lds{lds_dyn + (size_t)(q < F ? q : F) * PL};
@@ -89,22 +88,22 @@ __global__ __launch_bounds__(256) void k_rows(const float2* in, float2* out,
 #pragma unroll
         for (int m = 0; m < P; ++m) {
             const size_t i = base + t + T * m;
-            const float2 y = v[0][m];
+            const cplx y = v[0][m];
             if constexpr (EPI == EPI_STORE) {
                 st_wt(out + i, y);
             } else {
-                const float2 uu = u[i];
-                const float2 o = csub(uu, y);
+                const cplx uu = u[i];
+                const cplx o = csub(uu, y);
                 if constexpr (EPI == EPI_APPLY) {
                     st_wt(out + i, o);
                 } else if constexpr (EPI == EPI_BICG_V) {
                     st_wt(out + i, o);
-                    const float2 a = aux[i];
+                    const cplx a = aux[i];
                     acc[0] += (double)a.x * o.x + (double)a.y * o.y;
                     acc[1] += (double)a.x * o.y - (double)a.y * o.x;
                 } else if constexpr (EPI == EPI_BICG_T) {
                     st_wt(out + i, o);
-                    const float2 h = aux[i];
+                    const cplx h = aux[i];
                     acc[0] += (double)o.x * uu.x + (double)o.y * uu.y;
                     acc[1] += (double)o.x * uu.y - (double)o.y * uu.x;
                     acc[2] += (double)o.x * o.x + (double)o.y * o.y;
@@ -114,8 +113,8 @@ __global__ __launch_bounds__(256) void k_rows(const float2* in, float2* out,
                     acc[6] += (double)h.x * o.x + (double)h.y * o.y;     // <r^, t>
                     acc[7] += (double)h.x * o.y - (double)h.y * o.x;
                 } else if constexpr (EPI == EPI_TRUERES || EPI == EPI_GMRES_R0) {
-                    const float2 b = aux[i];
-                    const float2 rr = csub(b, o);
+                    const cplx b = aux[i];
+                    const cplx rr = csub(b, o);
                     st_wt(out + i, rr);
                     acc[0] += (double)rr.x * rr.x + (double)rr.y * rr.y;
                     if constexpr (EPI == EPI_GMRES_R0) acc[1] += (double)b.x * b.x + (double)b.y * b.y;
@@ -145,11 +144,11 @@ __global__ __launch_bounds__(256) void k_rows(const float2* in, float2* out,
 #pragma unroll
                     for (int m = 0; m < P; ++m) {
                         const size_t i = base + t + T * m;
-                        const float2 w = v[0][m];
+                        const cplx w = v[0][m];
 #pragma unroll
                         for (int k = 0; k < 2; ++k) {
                             if (l0 + k < ge.nv) {
-                                const float2 b = ge.V[(size_t)(l0 + k) * ge.vstride + i];
+                                const cplx b = ge.V[(size_t)(l0 + k) * ge.vstride + i];
                                 a[2 * k] += (double)b.x * w.x + (double)b.y * w.y;
                                 a[2 * k + 1] += (double)b.x * w.y - (double)b.y * w.x;
                             }
@@ -183,27 +182,27 @@ __global__ __launch_bounds__(256) void k_rows(const float2* in, float2* out,
 
 // ------------------------------------------------------ column kernel ----
 struct ColLds {
-    float2* base;   // this thread's column (or its private dummy slot)
+    cplx* base;   // this thread's column (or its private dummy slot)
     int stride;     // W (columns interleaved) or 1 (dummy slot)
     int PL;
-    __device__ __forceinline__ float2& operator()(int f, int pos) const {
+    __device__ __forceinline__ cplx& operator()(int f, int pos) const {
         return base[(f * PL + lds_pad(pos)) * stride];
     }
 };
 
 // (bx, bz) <- G_hat (bx, bz) with G_hat = gscale (Gamma' - ga I)^-1 for the
 // real symmetric scaled Christoffel matrix Gamma' = [[gxx, gxz], [gxz, gzz]].
-__device__ __forceinline__ void green_mul(float2& bx, float2& bz, float gxx, float gzz, float gxz,
-                                          float2 ga, float gscale) {
-    const float2 mxx = make_float2(gxx - ga.x, -ga.y);
-    const float2 mzz = make_float2(gzz - ga.x, -ga.y);
-    float2 det = cmul(mxx, mzz);
+__device__ __forceinline__ void green_mul(cplx& bx, cplx& bz, real gxx, real gzz, real gxz,
+                                          cplx ga, real gscale) {
+    const cplx mxx = mkc(gxx - ga.x, -ga.y);
+    const cplx mzz = mkc(gzz - ga.x, -ga.y);
+    cplx det = cmul(mxx, mzz);
     det.x -= gxz * gxz;
-    const float s = gscale / (det.x * det.x + det.y * det.y);
-    const float2 inv = make_float2(det.x * s, -det.y * s);
-    const float2 gx = cmul(inv, bx), gz = cmul(inv, bz);   // inv b
-    const float2 ox = csub(cmul(mzz, gx), cscale(gz, gxz));
-    const float2 oz = csub(cmul(mxx, gz), cscale(gx, gxz));
+    const real s = gscale / (det.x * det.x + det.y * det.y);
+    const cplx inv = mkc(det.x * s, -det.y * s);
+    const cplx gx = cmul(inv, bx), gz = cmul(inv, bz);   // inv b
+    const cplx ox = csub(cmul(mzz, gx), cscale(gz, gxz));
+    const cplx oz = csub(cmul(mxx, gz), cscale(gx, gxz));
     bx = ox;
     bz = oz;
 }
@@ -216,13 +215,13 @@ __device__ __forceinline__ int fft_signed(int i, int n) { return (i < (n + 1) / 
 // LDS buffer and go through each pass one after the other; otherwise each
 // has its own buffer (twice the LDS, half the barriers).
 template <int N, int P, int MODE, bool SEQ>
-__global__ __launch_bounds__(512) void k_cols(float2* __restrict__ data, ProbDev pd, int W,
+__global__ __launch_bounds__(512) void k_cols(cplx* __restrict__ data, ProbDev pd, int W,
                                               const SysState* __restrict__ st,
-                                              const float2* __restrict__ tw) {
+                                              const cplx* __restrict__ tw) {
     using S = FftShape<N, P>;
     constexpr int T = S::T;
     constexpr int PL = PaddedLen<N>::value;
-    extern __shared__ float2 lds_dyn[];
+    extern __shared__ cplx lds_dyn[];
 
     const int nx = pd.nx;
     const int tid = threadIdx.x;
@@ -234,9 +233,9 @@ __global__ __launch_bounds__(512) void k_cols(float2* __restrict__ data, ProbDev
     if (st != nullptr && st[sys].status != ST_RUNNING) return;
     const bool active = t < T;
 
-    float2* base = data + (size_t)sys * 2 * N * nx + x0 + c;
+    cplx* base = data + (size_t)sys * 2 * N * nx + x0 + c;
     const size_t plane = (size_t)N * nx;
-    float2 v[2][P];
+    cplx v[2][P];
     if (active) {
 #pragma unroll
         for (int f = 0; f < 2; ++f)
@@ -246,7 +245,7 @@ __global__ __launch_bounds__(512) void k_cols(float2* __restrict__ data, ProbDev
 #pragma unroll
         for (int f = 0; f < 2; ++f)
 #pragma unroll
-            for (int m = 0; m < P; ++m) v[f][m] = make_float2(0.f, 0.f);
+            for (int m = 0; m < P; ++m) v[f][m] = mkc(0.f, 0.f);
     }
     ColLds lds{active ? lds_dyn + c : lds_dyn + (size_t)PL * W * (SEQ ? 1 : 2), active ? W : 1, PL};
     const int tt = active ? t : 0;
@@ -260,19 +259,19 @@ __global__ __launch_bounds__(512) void k_cols(float2* __restrict__ data, ProbDev
         const int ix = x0 + c;
         const int sx = fft_signed(ix, nx);
         const bool central = pd.symbol == 1;
-        const float kx = central ? sinpif(2.0f * (float)sx / (float)nx) / pd.dx : (float)sx * pd.dkx;
-        const float kxo = ((nx % 2) == 0 && ix == nx / 2) ? 0.f : kx;
-        const float kx2 = kx * kx;
-        const float axx = pd.gc11 * kx2, azz = pd.gc55 * kx2, axz = pd.gc1355 * kxo;
-        const float rdx = 1.0f / pd.dx;
+        const real kx = central ? rsinpi(2.0f * (real)sx / (real)nx) / pd.dx : (real)sx * pd.dkx;
+        const real kxo = ((nx % 2) == 0 && ix == nx / 2) ? 0.f : kx;
+        const real kx2 = kx * kx;
+        const real axx = pd.gc11 * kx2, azz = pd.gc55 * kx2, axz = pd.gc1355 * kxo;
+        const real rdx = 1.0f / pd.dx;
 #pragma unroll
         for (int m = 0; m < P; ++m) {
             const int iz = tt + T * m;
             const int sz = fft_signed(iz, N);
             // central symbol sin(2 pi iz / N) / dx from the twiddle table
             // (tw[iz] = exp(-2 pi i iz / N))
-            const float kz = central ? -tw[iz].y * rdx : (float)sz * pd.dkz;
-            const float kzo = ((N % 2) == 0 && iz == N / 2) ? 0.f : kz;
+            const real kz = central ? -tw[iz].y * rdx : (real)sz * pd.dkz;
+            const real kzo = ((N % 2) == 0 && iz == N / 2) ? 0.f : kz;
             green_mul(v[0][m], v[1][m], axx + pd.gc55 * kz * kz, azz + pd.gc33 * kz * kz, axz * kzo,
                       pd.ga, pd.gscale);
             __builtin_amdgcn_sched_barrier(0);   // one point at a time: bounded registers
@@ -284,7 +283,7 @@ __global__ __launch_bounds__(512) void k_cols(float2* __restrict__ data, ProbDev
         // opaque copy of the table pointer keeps the compiler from holding the
         // forward pass's twiddles in registers across the Green multiply.
         // Likewise for the LDS addresses, which are the same in both passes.
-        const float2* twi = tw;
+        const cplx* twi = tw;
         int ti = tt;
         ColLds ldi = lds;
         asm volatile("" : "+s"(twi));
@@ -312,13 +311,13 @@ inline hipError_t allow_lds(K kernel, size_t bytes) {
 }
 
 template <int N, int P, bool INV, int EPI>
-inline hipError_t rows_launch(const float2* in, float2* out, const float2* u, const float2* aux,
-                              double* part, int nrows, int rps, const SysState* st, const float2* tw,
+inline hipError_t rows_launch(const cplx* in, cplx* out, const cplx* u, const cplx* aux,
+                              double* part, int nrows, int rps, const SysState* st, const cplx* tw,
                               hipStream_t s, const GmEpi* ge = nullptr) {
     const GmEpi gz{nullptr, 0, 0, nullptr};
     const RowGeom g = row_geom(N, P, rps);
     const int blocks = (nrows + g.F - 1) / g.F;
-    const size_t lds = (size_t)(g.F + 1) * PaddedLen<N>::value * sizeof(float2);
+    const size_t lds = (size_t)(g.F + 1) * PaddedLen<N>::value * sizeof(cplx);
     hipError_t e = allow_lds(k_rows<N, P, INV, EPI>, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_rows<N, P, INV, EPI>), dim3(blocks), dim3(g.threads), lds, s, in, out, u, aux,
@@ -327,8 +326,8 @@ inline hipError_t rows_launch(const float2* in, float2* out, const float2* u, co
 }
 
 template <int N, int P, int MODE, bool SEQ>
-inline hipError_t cols_launch(float2* data, const ProbDev& pd, int W, const SysState* st,
-                              const float2* tw, hipStream_t s) {
+inline hipError_t cols_launch(cplx* data, const ProbDev& pd, int W, const SysState* st,
+                              const cplx* tw, hipStream_t s) {
     const ColGeom g = col_geom(N, pd.nx, ColCfg{P, W, SEQ ? 1 : 0});
     const int blocks = pd.nsys * (pd.nx / W);
     hipError_t e = allow_lds(k_cols<N, P, MODE, SEQ>, g.lds);
@@ -338,4 +337,4 @@ inline hipError_t cols_launch(float2* data, const ProbDev& pd, int W, const SysS
     return hipGetLastError();
 }
 
-}  // namespace fw
+FW_END

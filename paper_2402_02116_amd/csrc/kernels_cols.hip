@@ -3,20 +3,25 @@
 // transforms (2-D FFT entry point) in the default variant.
 #include "fft_kernels.h"
 
-namespace fw {
-
+FW_BEGIN
+#ifdef FW_C128
+#define FW_COL_VARIANTS(X)                                                                         \
+    X(16, 8) X(24, 12) X(32, 8) X(48, 12) X(64, 8) X(96, 12) X(128, 8) X(192, 12) X(256, 8)        \
+    X(384, 12) X(512, 8) X(768, 12) X(1024, 8) X(1536, 12) X(2048, 8)
+#else
 #define FW_COL_VARIANTS(X)                                                                        \
     X(16, 8) X(16, 16) X(24, 12) X(24, 24) X(32, 8) X(32, 16) X(48, 12) X(48, 24) X(64, 8) X(64, 16) \
     X(96, 12) X(96, 24) X(128, 8) X(128, 16) X(192, 12) X(192, 24) X(256, 8) X(256, 16) X(384, 12)  \
     X(384, 24) X(512, 8) X(512, 16) X(768, 12) X(768, 24) X(1024, 8) X(1024, 16) X(1536, 12)         \
     X(1536, 24) X(2048, 8) X(2048, 16)
+#endif
 
-hipError_t launch_cols(int mode, const ColCfg& c, float2* data, const ProbDev& pd, const SysState* st,
-                       const float2* tw, hipStream_t s) {
+hipError_t launch_cols(int mode, const ColCfg& c, cplx* data, const ProbDev& pd, const SysState* st,
+                       const cplx* tw, hipStream_t s) {
     const int n = pd.nz;
     if (!col_cfg_ok(n, pd.nx, c)) return hipErrorInvalidValue;
     if (mode != COL_GREEN && !(c.P == col_default(n, pd.nx).P && c.seq == 1)) return hipErrorInvalidValue;
-    const float2* t = tw + twiddle_offset(n);
+    const cplx* t = tw + twiddle_offset(n);
 #define FW_CASE(N, PP)                                                                          \
     if (n == N && c.P == PP) {                                                                  \
         if (mode == COL_GREEN)                                                                  \
@@ -33,4 +38,4 @@ hipError_t launch_cols(int mode, const ColCfg& c, float2* data, const ProbDev& p
     return hipErrorInvalidValue;
 }
 
-}  // namespace fw
+FW_END

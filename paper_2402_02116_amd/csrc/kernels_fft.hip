@@ -7,8 +7,7 @@
 #include "fft.h"
 #include "launch.h"
 
-namespace fw {
-
+FW_BEGIN
 // ------------------------------------------------------------ sizes ------
 #define FW_FOR_EACH_SIZE(X) \
     X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024) X(1536) X(2048)
@@ -19,10 +18,16 @@ static const int kSizes[] = {16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 76
 // passes), 12 for 3 * 2^k.  Column passes hold both field components per
 // thread, so they default to 8 (radix 8) to keep registers low and the
 // thread count high.  Each size also has one alternative per pass kind.
+// The complex128 build has the default variants only.
 int row_points_default(int n) { return (n % 3 == 0) ? 12 : 16; }
-static int row_points_alt(int n) { return (n % 3 == 0) ? 24 : 8; }
 static int col_points_default(int n) { return (n % 3 == 0) ? 12 : 8; }
+#ifdef FW_C128
+static int row_points_alt(int n) { return row_points_default(n); }
+static int col_points_alt(int n) { return col_points_default(n); }
+#else
+static int row_points_alt(int n) { return (n % 3 == 0) ? 24 : 8; }
 static int col_points_alt(int n) { return (n % 3 == 0) ? 24 : 16; }
+#endif
 
 bool fft_size_supported(int n) {
     for (int s : kSizes)
@@ -45,13 +50,13 @@ size_t twiddle_offset(int n) {
     return (size_t)-1;
 }
 
-void twiddle_table_fill(float2* host) {
+void twiddle_table_fill(cplx* host) {
     size_t off = 0;
     for (int s : kSizes) {
         for (int m = 0; m < s; ++m) {
             // exp(-2 pi i m / s); angle reduced in double
             const double a = -2.0 * 3.14159265358979323846 * (double)m / (double)s;
-            host[off + m] = make_float2((float)cos(a), (float)sin(a));
+            host[off + m] = mkc((real)cos(a), (real)sin(a));
         }
         off += (size_t)s;
     }
@@ -64,7 +69,7 @@ bool row_points_ok(int n, int P) {
 int row_candidates(int n, int* out) {
     int k = 0;
     out[k++] = row_points_default(n);
-    if (n % row_points_alt(n) == 0) out[k++] = row_points_alt(n);
+    if (row_points_alt(n) != out[0] && n % row_points_alt(n) == 0) out[k++] = row_points_alt(n);
     return k;
 }
 
@@ -89,7 +94,7 @@ ColGeom col_geom(int nz, int nx, const ColCfg& c) {
     ColGeom g;
     g.threads = ((c.W * T + 63) / 64) * 64;
     g.slots = c.W + (g.threads > c.W * T ? 1 : 0);   // idle threads need a private dummy slot
-    g.lds = (size_t)padded_len(nz) * g.slots * (c.seq ? 1 : 2) * sizeof(float2);
+    g.lds = (size_t)padded_len(nz) * g.slots * (c.seq ? 1 : 2) * sizeof(cplx);
     return g;
 }
 
@@ -114,12 +119,14 @@ ColCfg col_default(int nz, int nx) {
 int col_candidates(int nz, int nx, ColCfg* out, int cap) {
     int k = 0;
     const int ps[2] = {col_points_default(nz), col_points_alt(nz)};
-    for (int P : ps)
+    for (int i = 0; i < (ps[1] == ps[0] ? 1 : 2); ++i) {
+        const int P = ps[i];
         for (int seq = 1; seq >= 0; --seq)
             for (int W = 4; W <= 32; W *= 2) {
                 const ColCfg c{P, W, seq};
                 if (col_cfg_ok(nz, nx, c) && k < cap) out[k++] = c;
             }
+    }
     return k;
 }
-}  // namespace fw
+FW_END

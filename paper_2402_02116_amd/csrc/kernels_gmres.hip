@@ -13,8 +13,7 @@
 
 #include "launch.h"
 
-namespace fw {
-
+FW_BEGIN
 constexpr int kGmThreads = 256;
 constexpr int kGmEPT = 4;
 
@@ -78,10 +77,10 @@ __device__ void gm_begin(SysState& z, GmSys& g, double r2, double b2, double rto
 
 // ------------------------------------------------- Gram-Schmidt passes ----
 // Projection coefficients c_l = tot[2l] + i tot[2l+1] divided by n_l^2.
-__device__ __forceinline__ void load_coeffs(float2* c, const double* tot, const GmSys& g, int nv) {
+__device__ __forceinline__ void load_coeffs(cplx* c, const double* tot, const GmSys& g, int nv) {
     for (int l = threadIdx.x; l < nv; l += blockDim.x) {
         const double inv = 1.0 / g.n2[l];
-        c[l] = make_float2((float)(tot[2 * l] * inv), (float)(tot[2 * l + 1] * inv));
+        c[l] = mkc((real)(tot[2 * l] * inv), (real)(tot[2 * l + 1] * inv));
     }
     __syncthreads();
 }
@@ -163,7 +162,7 @@ __device__ void gm_hessenberg(SysState& z, GmSys& g, const double* tot1, const d
 // the epilogue's projections, pass 2: the re-orthogonalisation's).  With
 // `final`, also a partial ||w||^2 record per block.
 __global__ __launch_bounds__(kGmThreads) void k_gm_update(GmArgs a, int j, int pass, int final) {
-    __shared__ float2 c[kGmMax + 1];
+    __shared__ cplx c[kGmMax + 1];
     __shared__ double red[4 * 4];
     const int nb = gm_nb(a.n);
     const GmView vi = gm_idx(nb);
@@ -172,13 +171,13 @@ __global__ __launch_bounds__(kGmThreads) void k_gm_update(GmArgs a, int j, int p
     const double* tot = (pass == 1 ? a.tot1 : a.tot2) + (size_t)vi.sys * kGmRec;
     load_coeffs(c, tot, g, j + 1);
     const size_t off = (size_t)vi.sys * a.n;
-    float2* w = a.V + (size_t)(j + 1) * a.vstride + off;
+    cplx* w = a.V + (size_t)(j + 1) * a.vstride + off;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int e = 0; e < kGmEPT; ++e) {
         const int i = vi.i0 + e * kGmThreads + threadIdx.x;
         if (i < a.n) {
-            float2 x = w[i];
+            cplx x = w[i];
             for (int l = 0; l <= j; ++l) x = csub(x, cmul(c[l], a.V[(size_t)l * a.vstride + off + i]));
             w[i] = x;
             acc[0] += (double)x.x * x.x + (double)x.y * x.y;
@@ -197,12 +196,12 @@ __global__ __launch_bounds__(kGmThreads) void k_gm_dots(GmArgs a, int j) {
     const GmView vi = gm_idx(nb);
     if (a.st[vi.sys].status != ST_RUNNING) return;
     const size_t off = (size_t)vi.sys * a.n;
-    const float2* w = a.V + (size_t)(j + 1) * a.vstride + off;
-    float2 x[kGmEPT];
+    const cplx* w = a.V + (size_t)(j + 1) * a.vstride + off;
+    cplx x[kGmEPT];
 #pragma unroll
     for (int e = 0; e < kGmEPT; ++e) {
         const int i = vi.i0 + e * kGmThreads + threadIdx.x;
-        x[e] = (i < a.n) ? w[i] : make_float2(0.f, 0.f);
+        x[e] = (i < a.n) ? w[i] : mkc(0.f, 0.f);
     }
     double* rec = a.part + ((size_t)vi.sys * nb + vi.bi) * kGmRec;
     for (int l0 = 0; l0 <= j; l0 += 2) {
@@ -211,12 +210,12 @@ __global__ __launch_bounds__(kGmThreads) void k_gm_dots(GmArgs a, int j) {
         for (int k = 0; k < 2; ++k) {
             const int l = l0 + k;
             if (l > j) break;
-            const float2* v = a.V + (size_t)l * a.vstride + off;
+            const cplx* v = a.V + (size_t)l * a.vstride + off;
 #pragma unroll
             for (int e = 0; e < kGmEPT; ++e) {
                 const int i = vi.i0 + e * kGmThreads + threadIdx.x;
                 if (i < a.n) {
-                    const float2 b = v[i];
+                    const cplx b = v[i];
                     acc[2 * k] += (double)b.x * x[e].x + (double)b.y * x[e].y;
                     acc[2 * k + 1] += (double)b.x * x[e].y - (double)b.y * x[e].x;
                 }
@@ -276,21 +275,21 @@ __global__ void k_gm_solve(const SysState* __restrict__ st, GmSys* __restrict__ 
 }
 
 // x += sum_{l < k} (y_l / n_l) w_l for systems at the end of a cycle.
-__global__ __launch_bounds__(kGmThreads) void k_gm_xupdate(float2* __restrict__ x, GmArgs a) {
-    __shared__ float2 c[kGmMax];
+__global__ __launch_bounds__(kGmThreads) void k_gm_xupdate(cplx* __restrict__ x, GmArgs a) {
+    __shared__ cplx c[kGmMax];
     const int nb = gm_nb(a.n);
     const GmView vi = gm_idx(nb);
     if (a.st[vi.sys].status != ST_CYCLE_DONE) return;
     const GmSys& g = a.gs[vi.sys];
     const int k = g.j;
-    for (int l = threadIdx.x; l < k; l += blockDim.x) c[l] = make_float2((float)g.yre[l], (float)g.yim[l]);
+    for (int l = threadIdx.x; l < k; l += blockDim.x) c[l] = mkc((real)g.yre[l], (real)g.yim[l]);
     __syncthreads();
     const size_t off = (size_t)vi.sys * a.n;
 #pragma unroll
     for (int e = 0; e < kGmEPT; ++e) {
         const int i = vi.i0 + e * kGmThreads + threadIdx.x;
         if (i < a.n) {
-            float2 s = x[off + i];
+            cplx s = x[off + i];
             for (int l = 0; l < k; ++l) s = cadd(s, cmul(c[l], a.V[(size_t)l * a.vstride + off + i]));
             x[off + i] = s;
         }
@@ -348,7 +347,7 @@ hipError_t launch_gm_report(const SysState* st, int32_t* iters, double* relres, 
     return hipGetLastError();
 }
 
-hipError_t launch_gm_finish_cycle(float2* x, const GmArgs& a, hipStream_t s) {
+hipError_t launch_gm_finish_cycle(cplx* x, const GmArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_gm_solve, per_sys_grid(a.nsys), dim3(64), 0, s, a.st, a.gs, a.nsys);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -359,4 +358,4 @@ hipError_t launch_gm_finish_cycle(float2* x, const GmArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-}  // namespace fw
+FW_END

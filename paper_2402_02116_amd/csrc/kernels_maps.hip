@@ -4,38 +4,37 @@
 // maps, FP64 inner products and the CG updates with device-resident scalars.
 #include "launch.h"
 
-namespace fw {
-
+FW_BEGIN
 constexpr int kMapThreads = 256;
 
 // out[p][i] = m0[p] q[p][i]
-__global__ void k_map_scale(const float* __restrict__ q, float* __restrict__ out, MapScales m0,
+__global__ void k_map_scale(const real* __restrict__ q, real* __restrict__ out, MapScales m0,
                             int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int p = blockIdx.y;
-    if (i < n) out[(size_t)p * n + i] = (float)(m0.s[p] * (double)q[(size_t)p * n + i]);
+    if (i < n) out[(size_t)p * n + i] = (real)(m0.s[p] * (double)q[(size_t)p * n + i]);
 }
 
-hipError_t launch_map_scale(const float* q, float* out, const MapScales& m0, int n, hipStream_t s) {
+hipError_t launch_map_scale(const real* q, real* out, const MapScales& m0, int n, hipStream_t s) {
     hipLaunchKernelGGL(k_map_scale, dim3((n + kMapThreads - 1) / kMapThreads, 5), dim3(kMapThreads), 0, s,
                        q, out, m0, n);
     return hipGetLastError();
 }
 
 // Periodic, unscaled 5-point Laplacian of nmaps maps [nmaps][nz][nx].
-__global__ void k_laplacian(const float* __restrict__ q, float* __restrict__ out, int nx, int nz) {
+__global__ void k_laplacian(const real* __restrict__ q, real* __restrict__ out, int nx, int nz) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int p = blockIdx.y;
     if (i >= nx * nz) return;
     const int z = i / nx, x = i - z * nx;
-    const float* a = q + (size_t)p * nx * nz;
+    const real* a = q + (size_t)p * nx * nz;
     const int xp = x + 1 == nx ? 0 : x + 1, xm = x == 0 ? nx - 1 : x - 1;
     const int zp = z + 1 == nz ? 0 : z + 1, zm = z == 0 ? nz - 1 : z - 1;
     out[(size_t)p * nx * nz + i] = a[z * nx + xp] + a[z * nx + xm] + a[zp * nx + x] + a[zm * nx + x] -
                                    4.0f * a[i];
 }
 
-hipError_t launch_laplacian(const float* q, float* out, int nx, int nz, int nmaps, hipStream_t s) {
+hipError_t launch_laplacian(const real* q, real* out, int nx, int nz, int nmaps, hipStream_t s) {
     const int n = nx * nz;
     hipLaunchKernelGGL(k_laplacian, dim3((n + kMapThreads - 1) / kMapThreads, nmaps), dim3(kMapThreads), 0,
                        s, q, out, nx, nz);
@@ -43,18 +42,18 @@ hipError_t launch_laplacian(const float* q, float* out, int nx, int nz, int nmap
 }
 
 // out = c_j m0[p] Re(g[p]) + c_l reg[p]     (reg may be null: c_l ignored)
-__global__ void k_map_combine(const float2* __restrict__ g, const float* __restrict__ reg,
-                              float* __restrict__ out, MapScales m0, double cj, double cl, int n) {
+__global__ void k_map_combine(const cplx* __restrict__ g, const real* __restrict__ reg,
+                              real* __restrict__ out, MapScales m0, double cj, double cl, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int p = blockIdx.y;
     if (i >= n) return;
     const size_t k = (size_t)p * n + i;
     double v = cj * m0.s[p] * (double)g[k].x;
     if (reg) v += cl * (double)reg[k];
-    out[k] = (float)v;
+    out[k] = (real)v;
 }
 
-hipError_t launch_map_combine(const float2* g, const float* reg, float* out, const MapScales& m0,
+hipError_t launch_map_combine(const cplx* g, const real* reg, real* out, const MapScales& m0,
                               double cj, double cl, int n, hipStream_t s) {
     hipLaunchKernelGGL(k_map_combine, dim3((n + kMapThreads - 1) / kMapThreads, 5), dim3(kMapThreads), 0, s,
                        g, reg, out, m0, cj, cl, n);
@@ -64,7 +63,7 @@ hipError_t launch_map_combine(const float2* g, const float* reg, float* out, con
 // ------------------------------------------------------- FP64 reductions --
 // part[block] = sum over the block's elements of a[i] * b[i] (real) or
 // |a[i]|^2 (complex data).  Fixed-order, deterministic.
-__global__ __launch_bounds__(256) void k_dot_real(const float* __restrict__ a, const float* __restrict__ b,
+__global__ __launch_bounds__(256) void k_dot_real(const real* __restrict__ a, const real* __restrict__ b,
                                                   double* __restrict__ part, size_t n) {
     __shared__ double red[4 * 1];
     double acc[1] = {0.0};
@@ -74,7 +73,7 @@ __global__ __launch_bounds__(256) void k_dot_real(const float* __restrict__ a, c
     if (threadIdx.x == 0) part[blockIdx.x] = acc[0];
 }
 
-__global__ __launch_bounds__(256) void k_norm2_complex(const float2* __restrict__ a,
+__global__ __launch_bounds__(256) void k_norm2_complex(const cplx* __restrict__ a,
                                                        double* __restrict__ part, size_t n) {
     __shared__ double red[4 * 1];
     double acc[1] = {0.0};
@@ -95,14 +94,14 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__
     if (threadIdx.x == 0) *out = r[0];
 }
 
-hipError_t launch_dot_real(const float* a, const float* b, size_t n, double* part, double* out,
+hipError_t launch_dot_real(const real* a, const real* b, size_t n, double* part, double* out,
                            hipStream_t s) {
     hipLaunchKernelGGL(k_dot_real, dim3(kDotBlocks), dim3(256), 0, s, a, b, part, n);
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, part, kDotBlocks, out);
     return hipGetLastError();
 }
 
-hipError_t launch_norm2_complex(const float2* a, size_t n, double* part, double* out, hipStream_t s) {
+hipError_t launch_norm2_complex(const cplx* a, size_t n, double* part, double* out, hipStream_t s) {
     hipLaunchKernelGGL(k_norm2_complex, dim3(kDotBlocks), dim3(256), 0, s, a, part, n);
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, part, kDotBlocks, out);
     return hipGetLastError();
@@ -112,11 +111,11 @@ hipError_t launch_norm2_complex(const float2* a, size_t n, double* part, double*
 // Device scalars (doubles): sc[0] = rs (current <res, res>), sc[1] = <p, Ap>,
 // sc[2] = new <res, res>.  hist (may be null) receives sqrt(rs) per iteration.
 // x += alpha p; res -= alpha Ap with alpha = rs / <p, Ap>
-__global__ void k_cg_xr(float* __restrict__ x, float* __restrict__ res, const float* __restrict__ p,
-                        const float* __restrict__ Ap, const double* __restrict__ sc, size_t n) {
+__global__ void k_cg_xr(real* __restrict__ x, real* __restrict__ res, const real* __restrict__ p,
+                        const real* __restrict__ Ap, const double* __restrict__ sc, size_t n) {
     const double pap = sc[1];
     const double alpha = pap != 0.0 ? sc[0] / pap : 0.0;
-    const float af = (float)alpha;
+    const real af = (real)alpha;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
         x[i] += af * p[i];
         res[i] -= af * Ap[i];
@@ -126,10 +125,10 @@ __global__ void k_cg_xr(float* __restrict__ x, float* __restrict__ res, const fl
 // p = res + beta p with beta = rs_new / rs; then rs = rs_new (one thread of
 // block 0 after the block's update would race with other blocks, so the
 // scalar shift happens in k_cg_shift).
-__global__ void k_cg_p(float* __restrict__ p, const float* __restrict__ res, const double* __restrict__ sc,
+__global__ void k_cg_p(real* __restrict__ p, const real* __restrict__ res, const double* __restrict__ sc,
                        size_t n) {
     const double beta = sc[0] != 0.0 ? sc[2] / sc[0] : 0.0;
-    const float bf = (float)beta;
+    const real bf = (real)beta;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
         p[i] = res[i] + bf * p[i];
 }
@@ -141,13 +140,13 @@ __global__ void k_cg_shift(double* __restrict__ sc, double* __restrict__ hist, i
     }
 }
 
-hipError_t launch_cg_xr(float* x, float* res, const float* p, const float* Ap, const double* sc, size_t n,
+hipError_t launch_cg_xr(real* x, real* res, const real* p, const real* Ap, const double* sc, size_t n,
                         hipStream_t s) {
     hipLaunchKernelGGL(k_cg_xr, dim3(1024), dim3(256), 0, s, x, res, p, Ap, sc, n);
     return hipGetLastError();
 }
 
-hipError_t launch_cg_p(float* p, const float* res, const double* sc, size_t n, hipStream_t s) {
+hipError_t launch_cg_p(real* p, const real* res, const double* sc, size_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_cg_p, dim3(1024), dim3(256), 0, s, p, res, sc, n);
     return hipGetLastError();
 }
@@ -157,33 +156,33 @@ hipError_t launch_cg_shift(double* sc, double* hist, int it, hipStream_t s) {
     return hipGetLastError();
 }
 
-__global__ void k_copy_f(const float* __restrict__ a, float* __restrict__ b, size_t n) {
+__global__ void k_copy_f(const real* __restrict__ a, real* __restrict__ b, size_t n) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
         b[i] = a[i];
 }
-__global__ void k_zero_f(float* __restrict__ b, size_t n) {
+__global__ void k_zero_f(real* __restrict__ b, size_t n) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
         b[i] = 0.f;
 }
 
 // d -= r (complex data)
-__global__ void k_sub_complex(float2* __restrict__ d, const float2* __restrict__ r, size_t n) {
+__global__ void k_sub_complex(cplx* __restrict__ d, const cplx* __restrict__ r, size_t n) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
         d[i] = csub(d[i], r[i]);
 }
 
-hipError_t launch_sub_complex(float2* d, const float2* r, size_t n, hipStream_t s) {
+hipError_t launch_sub_complex(cplx* d, const cplx* r, size_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_sub_complex, dim3(256), dim3(256), 0, s, d, r, n);
     return hipGetLastError();
 }
 
-hipError_t launch_copy_f(const float* a, float* b, size_t n, hipStream_t s) {
+hipError_t launch_copy_f(const real* a, real* b, size_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_copy_f, dim3(1024), dim3(256), 0, s, a, b, n);
     return hipGetLastError();
 }
-hipError_t launch_zero_f(float* b, size_t n, hipStream_t s) {
+hipError_t launch_zero_f(real* b, size_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_zero_f, dim3(1024), dim3(256), 0, s, b, n);
     return hipGetLastError();
 }
 
-}  // namespace fw
+FW_END

@@ -2,20 +2,25 @@
 // forward store and all inverse epilogues.
 #include "fft_kernels.h"
 
-namespace fw {
-
+FW_BEGIN
 // (size, points per thread) pairs built: the default and the alternative of
-// each size.
+// each size (the default only in the complex128 build).
+#ifdef FW_C128
+#define FW_ROW_VARIANTS(X)                                                                           \
+    X(16, 16) X(24, 12) X(32, 16) X(48, 12) X(64, 16) X(96, 12) X(128, 16) X(192, 12) X(256, 16)     \
+    X(384, 12) X(512, 16) X(768, 12) X(1024, 16) X(1536, 12) X(2048, 16)
+#else
 #define FW_ROW_VARIANTS(X)                                                                          \
     X(16, 16) X(16, 8) X(24, 12) X(24, 24) X(32, 16) X(32, 8) X(48, 12) X(48, 24) X(64, 16) X(64, 8) \
     X(96, 12) X(96, 24) X(128, 16) X(128, 8) X(192, 12) X(192, 24) X(256, 16) X(256, 8) X(384, 12)  \
     X(384, 24) X(512, 16) X(512, 8) X(768, 12) X(768, 24) X(1024, 16) X(1024, 8) X(1536, 12)         \
     X(1536, 24) X(2048, 16) X(2048, 8)
+#endif
 
-hipError_t launch_rows_fwd(int n, int P, const float2* in, float2* out, int nrows, int rps,
-                           const SysState* st, const float2* tw, hipStream_t s) {
+hipError_t launch_rows_fwd(int n, int P, const cplx* in, cplx* out, int nrows, int rps,
+                           const SysState* st, const cplx* tw, hipStream_t s) {
     if (!row_points_ok(n, P)) return hipErrorInvalidValue;
-    const float2* t = tw + twiddle_offset(n);
+    const cplx* t = tw + twiddle_offset(n);
 #define FW_CASE(N, PP) \
     if (n == N && P == PP) \
         return rows_launch<N, PP, false, EPI_STORE>(in, out, nullptr, nullptr, nullptr, nrows, rps, st, t, s);
@@ -25,8 +30,8 @@ hipError_t launch_rows_fwd(int n, int P, const float2* in, float2* out, int nrow
 }
 
 template <int N, int P>
-static hipError_t rows_inv_np(int epi, const float2* in, const float2* u, const float2* aux, float2* out,
-                              double* part, int nrows, int rps, const SysState* st, const float2* tw,
+static hipError_t rows_inv_np(int epi, const cplx* in, const cplx* u, const cplx* aux, cplx* out,
+                              double* part, int nrows, int rps, const SysState* st, const cplx* tw,
                               hipStream_t s, const GmEpi* ge) {
     if ((epi == EPI_ARNOLDI || epi == EPI_GMRES_R0) && (!ge || !ge->part))
         return hipErrorInvalidValue;
@@ -41,11 +46,11 @@ static hipError_t rows_inv_np(int epi, const float2* in, const float2* u, const 
     }
 }
 
-hipError_t launch_rows_inv(int n, int P, int epi, const float2* in, const float2* u, const float2* aux,
-                           float2* out, double* part, int nrows, int rps, const SysState* st,
-                           const float2* tw, hipStream_t s, const GmEpi* ge) {
+hipError_t launch_rows_inv(int n, int P, int epi, const cplx* in, const cplx* u, const cplx* aux,
+                           cplx* out, double* part, int nrows, int rps, const SysState* st,
+                           const cplx* tw, hipStream_t s, const GmEpi* ge) {
     if (!row_points_ok(n, P)) return hipErrorInvalidValue;
-    const float2* t = tw + twiddle_offset(n);
+    const cplx* t = tw + twiddle_offset(n);
 #define FW_CASE(N, PP) \
     if (n == N && P == PP) return rows_inv_np<N, PP>(epi, in, u, aux, out, part, nrows, rps, st, t, s, ge);
     FW_ROW_VARIANTS(FW_CASE)
@@ -53,4 +58,4 @@ hipError_t launch_rows_inv(int n, int P, int epi, const float2* in, const float2
     return hipErrorInvalidValue;
 }
 
-}  // namespace fw
+FW_END

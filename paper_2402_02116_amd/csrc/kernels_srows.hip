@@ -11,30 +11,29 @@
 #include "bicg.h"
 #include "fft.h"
 
-namespace fw {
-
+FW_BEGIN
 namespace {
 
 __device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
 struct RowLdsF {
-    float2* p;
-    __device__ __forceinline__ float2& operator()(int, int pos) const { return p[lds_pad(pos)]; }
+    cplx* p;
+    __device__ __forceinline__ cplx& operator()(int, int pos) const { return p[lds_pad(pos)]; }
 };
 
 template <int N, int P, int VM>
-__global__ __launch_bounds__(256) void k_srows(const float2* __restrict__ u, const float2* __restrict__ a1,
-                                               const float2* __restrict__ a2, float2* __restrict__ wout,
-                                               float2* __restrict__ rhat, float2* __restrict__ out,
-                                               const float* __restrict__ maps, ProbDev pd, int F,
+__global__ __launch_bounds__(256) void k_srows(const cplx* __restrict__ u, const cplx* __restrict__ a1,
+                                               const cplx* __restrict__ a2, cplx* __restrict__ wout,
+                                               cplx* __restrict__ rhat, cplx* __restrict__ out,
+                                               const real* __restrict__ maps, ProbDev pd, int F,
                                                SysState* __restrict__ st, const double* __restrict__ part,
-                                               int np, const float2* __restrict__ tw,
-                                               const float2* __restrict__ a3, float2* __restrict__ xio,
-                                               float2* __restrict__ rout) {
+                                               int np, const cplx* __restrict__ tw,
+                                               const cplx* __restrict__ a3, cplx* __restrict__ xio,
+                                               cplx* __restrict__ rout) {
     using S = FftShape<N, P>;
     constexpr int T = S::T;
     constexpr int PL = PaddedLen<N>::value;
-    extern __shared__ float2 lds_dyn[];
+    extern __shared__ cplx lds_dyn[];
     __shared__ double red[4 * kPartialNV];
 
     const int nz = pd.nz;
@@ -56,7 +55,7 @@ __global__ __launch_bounds__(256) void k_srows(const float2* __restrict__ u, con
         }
     }
 
-    float2 c1 = make_float2(0.f, 0.f), c2 = make_float2(0.f, 0.f), c3 = make_float2(0.f, 0.f);
+    cplx c1 = mkc(0.f, 0.f), c2 = mkc(0.f, 0.f), c3 = mkc(0.f, 0.f);
     bool fresh = false;
     int step = SS_FULL;
     if constexpr (VM != VM_NONE) {
@@ -66,8 +65,8 @@ __global__ __launch_bounds__(256) void k_srows(const float2* __restrict__ u, con
     const size_t so = (size_t)sys * 2 * plane;
     // VM_PX on an own cell: r = s - omega t, x += alpha p_old + omega s
     auto close_iteration = [&](size_t gi) {
-        const float2 sv = u[so + gi], tv = a3[so + gi], pv = a1[so + gi];
-        const float2 rv = close_r(sv, tv, c2);
+        const cplx sv = u[so + gi], tv = a3[so + gi], pv = a1[so + gi];
+        const cplx rv = close_r(sv, tv, c2);
         st_wt(rout + so + gi, rv);
         st_wt(xio + so + gi, close_x(xio[so + gi], pv, sv, c3, c2));
         if (fresh) st_wt(rhat + so + gi, rv);
@@ -87,13 +86,13 @@ __global__ __launch_bounds__(256) void k_srows(const float2* __restrict__ u, con
     //    elements per thread at a time: every load of a batch is issued before
     //    its stores (out-of-range slots load element 0 and are dropped)
     const int HR = F + 4;
-    float2* su = lds_dyn;                           // [2][HR][N]
+    cplx* su = lds_dyn;                           // [2][HR][N]
     const int total = 2 * HR * N;
     constexpr int kB = VM == VM_PX ? 4 : 8;
     for (int i0 = threadIdx.x; i0 < total; i0 += kB * 256) {
         size_t gi[kB];
         bool ok[kB], own[kB];
-        float2 f[kB], sv[kB], pv[kB], rv[kB], xv[kB];
+        cplx f[kB], sv[kB], pv[kB], rv[kB], xv[kB];
 #pragma unroll
         for (int j = 0; j < kB; ++j) {
             const int idx = i0 + j * 256;
@@ -111,14 +110,14 @@ __global__ __launch_bounds__(256) void k_srows(const float2* __restrict__ u, con
             if constexpr (VM == VM_NONE) {
                 f[j] = u[g];
             } else if constexpr (VM == VM_P) {
-                const float2 r0 = u[g], p0 = a1[g], v0 = a2[g];
+                const cplx r0 = u[g], p0 = a1[g], v0 = a2[g];
                 f[j] = fresh ? r0 : cadd(r0, cmul(c1, csub(p0, cmul(c2, v0))));
             } else if constexpr (VM == VM_PX) {
                 sv[j] = u[g];
-                const float2 t0 = a3[g];
+                const cplx t0 = a3[g];
                 pv[j] = a1[g];
-                const float2 v0 = a2[g];
-                xv[j] = own[j] ? xio[g] : make_float2(0.f, 0.f);
+                const cplx v0 = a2[g];
+                xv[j] = own[j] ? xio[g] : mkc(0.f, 0.f);
                 rv[j] = close_r(sv[j], t0, c2);
                 f[j] = fresh ? rv[j] : cadd(rv[j], cmul(c1, csub(pv[j], cmul(c2, v0))));
             } else {
@@ -152,22 +151,22 @@ __global__ __launch_bounds__(256) void k_srows(const float2* __restrict__ u, con
     const int c = active ? q / F : 0;
     const int zl = active ? q - c * F : 0;
     const int z = z0 + zl;
-    const float sc = pd.inv4dx2;
-    const float* mc11 = maps;
-    const float* mc13 = maps + plane;
-    const float* mc33 = maps + 2 * plane;
-    const float* mc55 = maps + 3 * plane;
-    const float* mrho = maps + 4 * plane;
-    auto U = [&](int cc, int dz, int x) -> float2 { return su[(cc * HR + zl + 2 + dz) * N + wrapi(x, N)]; };
+    const real sc = pd.inv4dx2;
+    const real* mc11 = maps;
+    const real* mc13 = maps + plane;
+    const real* mc33 = maps + 2 * plane;
+    const real* mc55 = maps + 3 * plane;
+    const real* mrho = maps + 4 * plane;
+    auto U = [&](int cc, int dz, int x) -> cplx { return su[(cc * HR + zl + 2 + dz) * N + wrapi(x, N)]; };
     const size_t zr = (size_t)z * N, zu = (size_t)wrapi(z - 1, nz) * N, zd = (size_t)wrapi(z + 1, nz) * N;
     // the map values of kG points are loaded before any of them is used
     constexpr int kG = P % 8 == 0 ? 8 : (P % 6 == 0 ? 6 : 4);
     static_assert(P % kG == 0, "points per thread");
-    float2 v[1][P];
+    cplx v[1][P];
     if (active && c == 0) {
 #pragma unroll
       for (int m0 = 0; m0 < P; m0 += kG) {
-        float rh[kG], a11r[kG], a13r[kG], a11l[kG], a13l[kG], a55d[kG], a55u[kG];
+        real rh[kG], a11r[kG], a13r[kG], a11l[kG], a13l[kG], a55d[kG], a55u[kG];
 #pragma unroll
         for (int g = 0; g < kG; ++g) {
             const int m = g;
@@ -184,21 +183,21 @@ __global__ __launch_bounds__(256) void k_srows(const float2* __restrict__ u, con
         for (int m = 0; m < kG; ++m) {
             // sigma_1 at (z, x +- 1), sigma_5 at (z +- 1, x)
             const int x = t + T * (m0 + m);
-            const float2 exr = csub(U(0, 0, x + 2), U(0, 0, x)), ezr = csub(U(1, 1, x + 1), U(1, -1, x + 1));
-            const float2 exl = csub(U(0, 0, x), U(0, 0, x - 2)), ezl = csub(U(1, 1, x - 1), U(1, -1, x - 1));
-            const float2 s1r = make_float2(a11r[m] * exr.x + a13r[m] * ezr.x, a11r[m] * exr.y + a13r[m] * ezr.y);
-            const float2 s1l = make_float2(a11l[m] * exl.x + a13l[m] * ezl.x, a11l[m] * exl.y + a13l[m] * ezl.y);
-            const float2 exzd = cadd(csub(U(0, 2, x), U(0, 0, x)), csub(U(1, 1, x + 1), U(1, 1, x - 1)));
-            const float2 exzu = cadd(csub(U(0, 0, x), U(0, -2, x)), csub(U(1, -1, x + 1), U(1, -1, x - 1)));
-            const float2 dx1 = csub(s1r, s1l);
-            const float2 dz5 = csub(cscale(exzd, a55d[m]), cscale(exzu, a55u[m]));
+            const cplx exr = csub(U(0, 0, x + 2), U(0, 0, x)), ezr = csub(U(1, 1, x + 1), U(1, -1, x + 1));
+            const cplx exl = csub(U(0, 0, x), U(0, 0, x - 2)), ezl = csub(U(1, 1, x - 1), U(1, -1, x - 1));
+            const cplx s1r = mkc(a11r[m] * exr.x + a13r[m] * ezr.x, a11r[m] * exr.y + a13r[m] * ezr.y);
+            const cplx s1l = mkc(a11l[m] * exl.x + a13l[m] * ezl.x, a11l[m] * exl.y + a13l[m] * ezl.y);
+            const cplx exzd = cadd(csub(U(0, 2, x), U(0, 0, x)), csub(U(1, 1, x + 1), U(1, 1, x - 1)));
+            const cplx exzu = cadd(csub(U(0, 0, x), U(0, -2, x)), csub(U(1, -1, x + 1), U(1, -1, x - 1)));
+            const cplx dx1 = csub(s1r, s1l);
+            const cplx dz5 = csub(cscale(exzd, a55d[m]), cscale(exzu, a55u[m]));
             v[0][m0 + m] = cadd(cmul(cscale(pd.w2, rh[m]), U(0, 0, x)), cscale(cadd(dx1, dz5), sc));
         }
       }
     } else if (active) {
 #pragma unroll
       for (int m0 = 0; m0 < P; m0 += kG) {
-        float rh[kG], a13d[kG], a33d[kG], a13u[kG], a33u[kG], a55r[kG], a55l[kG];
+        real rh[kG], a13d[kG], a33d[kG], a13u[kG], a33u[kG], a55r[kG], a55l[kG];
 #pragma unroll
         for (int g = 0; g < kG; ++g) {
             const int m = g;
@@ -215,20 +214,20 @@ __global__ __launch_bounds__(256) void k_srows(const float2* __restrict__ u, con
         for (int m = 0; m < kG; ++m) {
             // sigma_5 at (z, x +- 1), sigma_3 at (z +- 1, x)
             const int x = t + T * (m0 + m);
-            const float2 exzr = cadd(csub(U(0, 1, x + 1), U(0, -1, x + 1)), csub(U(1, 0, x + 2), U(1, 0, x)));
-            const float2 exzl = cadd(csub(U(0, 1, x - 1), U(0, -1, x - 1)), csub(U(1, 0, x), U(1, 0, x - 2)));
-            const float2 exd = csub(U(0, 1, x + 1), U(0, 1, x - 1)), ezd = csub(U(1, 2, x), U(1, 0, x));
-            const float2 exu = csub(U(0, -1, x + 1), U(0, -1, x - 1)), ezu = csub(U(1, 0, x), U(1, -2, x));
-            const float2 s3d = make_float2(a13d[m] * exd.x + a33d[m] * ezd.x, a13d[m] * exd.y + a33d[m] * ezd.y);
-            const float2 s3u = make_float2(a13u[m] * exu.x + a33u[m] * ezu.x, a13u[m] * exu.y + a33u[m] * ezu.y);
-            const float2 dx5 = csub(cscale(exzr, a55r[m]), cscale(exzl, a55l[m]));
-            const float2 dz3 = csub(s3d, s3u);
+            const cplx exzr = cadd(csub(U(0, 1, x + 1), U(0, -1, x + 1)), csub(U(1, 0, x + 2), U(1, 0, x)));
+            const cplx exzl = cadd(csub(U(0, 1, x - 1), U(0, -1, x - 1)), csub(U(1, 0, x), U(1, 0, x - 2)));
+            const cplx exd = csub(U(0, 1, x + 1), U(0, 1, x - 1)), ezd = csub(U(1, 2, x), U(1, 0, x));
+            const cplx exu = csub(U(0, -1, x + 1), U(0, -1, x - 1)), ezu = csub(U(1, 0, x), U(1, -2, x));
+            const cplx s3d = mkc(a13d[m] * exd.x + a33d[m] * ezd.x, a13d[m] * exd.y + a33d[m] * ezd.y);
+            const cplx s3u = mkc(a13u[m] * exu.x + a33u[m] * ezu.x, a13u[m] * exu.y + a33u[m] * ezu.y);
+            const cplx dx5 = csub(cscale(exzr, a55r[m]), cscale(exzl, a55l[m]));
+            const cplx dz3 = csub(s3d, s3u);
             v[0][m0 + m] = cadd(cmul(cscale(pd.w2, rh[m]), U(1, 0, x)), cscale(cadd(dx5, dz3), sc));
         }
       }
     } else {
 #pragma unroll
-        for (int m = 0; m < P; ++m) v[0][m] = make_float2(0.f, 0.f);
+        for (int m = 0; m < P; ++m) v[0][m] = mkc(0.f, 0.f);
     }
     __syncthreads();   // the tile is read; its LDS now holds the transform's rows
 
@@ -236,7 +235,7 @@ __global__ __launch_bounds__(256) void k_srows(const float2* __restrict__ u, con
     RowLdsF lds{lds_dyn + (size_t)(active ? q : 2 * F) * PL};
     fft_run<N, P, false, 1>(v, t, tw, lds);
     if (active) {
-        float2* o = out + so + c * plane + zr;
+        cplx* o = out + so + c * plane + zr;
 #pragma unroll
         for (int m = 0; m < P; ++m) st_wt(o + t + T * m, v[0][m]);
     }
@@ -247,6 +246,10 @@ __global__ __launch_bounds__(256) void k_srows(const float2* __restrict__ u, con
 // Largest rows per block (a power of two <= 128 / T dividing nz) for n-point
 // rows with P points per thread; 0 when the fused kernel does not apply.
 int srows_rows(int nx, int nz, int P) {
+#ifdef FW_C128
+    (void)nx, (void)nz, (void)P;
+    return 0;   // the complex128 build keeps the stencil and the row pass apart
+#endif
     if (nx > kSrowsMaxN || nx % P != 0) return 0;
     const int T = nx / P;
     if (T > 128) return 0;
@@ -256,14 +259,14 @@ int srows_rows(int nx, int nz, int P) {
 }
 
 size_t srows_lds(int nx, int F) {
-    const size_t tile = (size_t)2 * (F + 4) * nx * sizeof(float2);
-    const size_t fft = (size_t)(2 * F + 1) * (nx + nx / 16 + 1) * sizeof(float2);
+    const size_t tile = (size_t)2 * (F + 4) * nx * sizeof(cplx);
+    const size_t fft = (size_t)(2 * F + 1) * (nx + nx / 16 + 1) * sizeof(cplx);
     return tile > fft ? tile : fft;
 }
 
 template <int N, int P, int VM>
-static hipError_t srows_launch(const StencilArgs& a, float2* out, const ProbDev& pd, SysState* st,
-                               const float2* tw, hipStream_t s) {
+static hipError_t srows_launch(const StencilArgs& a, cplx* out, const ProbDev& pd, SysState* st,
+                               const cplx* tw, hipStream_t s) {
     const int F = srows_rows(N, pd.nz, P);
     if (F == 0) return hipErrorInvalidValue;
     const size_t lds = srows_lds(N, F);
@@ -280,26 +283,30 @@ static hipError_t srows_launch(const StencilArgs& a, float2* out, const ProbDev&
 }
 
 template <int N, int P>
-static hipError_t srows_vm(int vm, const StencilArgs& a, float2* out, const ProbDev& pd, SysState* st,
-                           const float2* tw, hipStream_t s) {
+static hipError_t srows_vm(int vm, const StencilArgs& a, cplx* out, const ProbDev& pd, SysState* st,
+                           const cplx* tw, hipStream_t s) {
     if (vm == VM_NONE) return srows_launch<N, P, VM_NONE>(a, out, pd, st, tw, s);
     if (vm == VM_P) return srows_launch<N, P, VM_P>(a, out, pd, st, tw, s);
     if (vm == VM_PX) return srows_launch<N, P, VM_PX>(a, out, pd, st, tw, s);
     return srows_launch<N, P, VM_S>(a, out, pd, st, tw, s);
 }
 
+#ifdef FW_C128
+#define FW_SROWS_VARIANTS(X)
+#else
 #define FW_SROWS_VARIANTS(X)                                                                         \
     X(16, 16) X(16, 8) X(24, 12) X(24, 24) X(32, 16) X(32, 8) X(48, 12) X(48, 24) X(64, 16) X(64, 8) \
     X(96, 12) X(96, 24) X(128, 16) X(128, 8) X(192, 12) X(192, 24) X(256, 16) X(256, 8) X(384, 12)  \
     X(384, 24) X(512, 16) X(512, 8)
+#endif
 
-hipError_t launch_srows(int vm, int P, const StencilArgs& a, float2* out, const ProbDev& pd, SysState* st,
-                        const float2* tw, hipStream_t s) {
+hipError_t launch_srows(int vm, int P, const StencilArgs& a, cplx* out, const ProbDev& pd, SysState* st,
+                        const cplx* tw, hipStream_t s) {
     if (vm < 0 || vm > 3 || (vm != VM_NONE && !st) || ((vm == VM_P || vm == VM_PX) && !a.rhat) ||
         (vm == VM_PX && (!a.a3 || !a.xio || !a.rout)))
         return hipErrorInvalidValue;
     if (!row_points_ok(pd.nx, P) || srows_rows(pd.nx, pd.nz, P) == 0) return hipErrorInvalidValue;
-    const float2* t = tw + twiddle_offset(pd.nx);
+    const cplx* t = tw + twiddle_offset(pd.nx);
 #define FW_CASE(N, PP) \
     if (pd.nx == N && P == PP) return srows_vm<N, PP>(vm, a, out, pd, st, t, s);
     FW_SROWS_VARIANTS(FW_CASE)
@@ -307,4 +314,4 @@ hipError_t launch_srows(int vm, int P, const StencilArgs& a, float2* out, const 
     return hipErrorInvalidValue;
 }
 
-}  // namespace fw
+FW_END

@@ -9,8 +9,7 @@
 
 #include "bicg.h"
 
-namespace fw {
-
+FW_BEGIN
 constexpr int kVecThreads = 256;
 constexpr int kVecEPT = 4;   // complex elements per thread in vector kernels
 constexpr int kStallIters = 150;   // iterations without halving ||r|| before a restart
@@ -35,25 +34,25 @@ __device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >=
 // their halos.
 
 template <int TX, int TZ, int VM>
-__global__ __launch_bounds__(256) void k_body_force(const float2* __restrict__ u,
-                                                    const float2* __restrict__ a1,
-                                                    const float2* __restrict__ a2,
-                                                    float2* __restrict__ wout,
-                                                    float2* __restrict__ b,
-                                                    const float* __restrict__ maps, ProbDev pd,
+__global__ __launch_bounds__(256) void k_body_force(const cplx* __restrict__ u,
+                                                    const cplx* __restrict__ a1,
+                                                    const cplx* __restrict__ a2,
+                                                    cplx* __restrict__ wout,
+                                                    cplx* __restrict__ b,
+                                                    const real* __restrict__ maps, ProbDev pd,
                                                     int S, SysState* __restrict__ st,
                                                     const double* __restrict__ part, int np,
-                                                    float2* __restrict__ rhat,
-                                                    const float2* __restrict__ a3,
-                                                    float2* __restrict__ xio,
-                                                    float2* __restrict__ rout) {
+                                                    cplx* __restrict__ rhat,
+                                                    const cplx* __restrict__ a3,
+                                                    cplx* __restrict__ xio,
+                                                    cplx* __restrict__ rout) {
     static_assert(TX <= 64 && TZ % 4 == 0, "tile");
     constexpr int HX = TX + 4, HZ = TZ + 4, SX = TX + 2, SZ = TZ + 2;
     constexpr int KS = (SZ + 3) / 4;     // stress rows per thread
     constexpr int KB = TZ / 4;           // output rows per thread
     constexpr int KH = HZ / 4;           // displacement rows per thread
-    __shared__ float2 su[2][HZ][HX];
-    __shared__ float2 ss[3][SZ][SX];
+    __shared__ cplx su[2][HZ][HX];
+    __shared__ cplx ss[3][SZ][SX];
     __shared__ double red[4 * kPartialNV];
     const int nx = pd.nx, nz = pd.nz;
     const size_t plane = (size_t)nx * nz;
@@ -68,7 +67,7 @@ __global__ __launch_bounds__(256) void k_body_force(const float2* __restrict__ u
     const int hsx = (tx == 0) ? 0 : TX + 1;   // halo stress column of lanes 0 and 1
     const int hux = (tx < 2) ? tx : TX + tx;  // halo displacement column of lanes 0..3
 
-    float m_in[KS][4], m_h[KS][4], rho[KB];
+    real m_in[KS][4], m_h[KS][4], rho[KB];
 #pragma unroll
     for (int k = 0; k < KS; ++k) {
         const int sz = tg + 4 * k;
@@ -86,7 +85,7 @@ __global__ __launch_bounds__(256) void k_body_force(const float2* __restrict__ u
     for (int k = 0; k < KB; ++k)
         rho[k] = lane ? maps[4 * plane + (size_t)(z0 + tg + 4 * k) * nx + x0 + tx] : 0.f;
 
-    const float sc = pd.inv4dx2;
+    const real sc = pd.inv4dx2;
     for (int sys = sys0; sys < sys0 + S && sys < pd.nsys; ++sys) {
         if (st != nullptr) {   // uniform over the block
             const int stw = st[sys].status;
@@ -101,7 +100,7 @@ __global__ __launch_bounds__(256) void k_body_force(const float2* __restrict__ u
                 }
             }
         }
-        float2 c1 = make_float2(0.f, 0.f), c2 = make_float2(0.f, 0.f), c3 = make_float2(0.f, 0.f);
+        cplx c1 = mkc(0.f, 0.f), c2 = mkc(0.f, 0.f), c3 = mkc(0.f, 0.f);
         bool fresh = false;
         int step = SS_FULL;
         if constexpr (VM != VM_NONE) {
@@ -109,11 +108,11 @@ __global__ __launch_bounds__(256) void k_body_force(const float2* __restrict__ u
             if (step == SS_SKIP) continue;
         }
         const size_t so = (size_t)sys * 2 * plane;
-        float2* bs = b + so;
+        cplx* bs = b + so;
         // VM_PX on an own cell: r = s - omega t, x += alpha p_old + omega s
         auto close_iteration = [&](size_t gi) {
-            const float2 sv = u[so + gi], tv = a3[so + gi], pv = a1[so + gi];
-            const float2 rv = close_r(sv, tv, c2);
+            const cplx sv = u[so + gi], tv = a3[so + gi], pv = a1[so + gi];
+            const cplx rv = close_r(sv, tv, c2);
             st_wt(rout + so + gi, rv);
             st_wt(xio + so + gi, close_x(xio[so + gi], pv, sv, c3, c2));
             if (fresh) rhat[so + gi] = rv;
@@ -132,18 +131,18 @@ __global__ __launch_bounds__(256) void k_body_force(const float2* __restrict__ u
             }
         }
         // input field value at global index gi of this system (comp offset included)
-        auto field = [&](size_t gi) -> float2 {
+        auto field = [&](size_t gi) -> cplx {
             if constexpr (VM == VM_NONE) {
                 return u[so + gi];
             } else if constexpr (VM == VM_P) {
-                const float2 rv = u[so + gi];
+                const cplx rv = u[so + gi];
                 if (fresh) return rv;
-                const float2 pv = a1[so + gi], vv = a2[so + gi];
+                const cplx pv = a1[so + gi], vv = a2[so + gi];
                 return cadd(rv, cmul(c1, csub(pv, cmul(c2, vv))));
             } else if constexpr (VM == VM_PX) {
-                const float2 rv = close_r(u[so + gi], a3[so + gi], c2);
+                const cplx rv = close_r(u[so + gi], a3[so + gi], c2);
                 if (fresh) return rv;
-                const float2 pv = a1[so + gi], vv = a2[so + gi];
+                const cplx pv = a1[so + gi], vv = a2[so + gi];
                 return cadd(rv, cmul(c1, csub(pv, cmul(c2, vv))));
             } else {
                 return csub(u[so + gi], cmul(c1, a1[so + gi]));
@@ -155,7 +154,7 @@ __global__ __launch_bounds__(256) void k_body_force(const float2* __restrict__ u
             const int hz = tg + 4 * k;
             const size_t row = (size_t)wrap(z0 - 2 + hz, nz) * nx;
             if (lane) {
-                const float2 f0 = field(row + x0 + tx), f1 = field(plane + row + x0 + tx);
+                const cplx f0 = field(row + x0 + tx), f1 = field(plane + row + x0 + tx);
                 su[0][hz][tx + 2] = f0;
                 su[1][hz][tx + 2] = f1;
                 if constexpr (VM != VM_NONE) {
@@ -191,13 +190,13 @@ __global__ __launch_bounds__(256) void k_body_force(const float2* __restrict__ u
                     if (h == 0 ? lane : (tx < 2)) {
                         const int sx = (h == 0) ? tx + 1 : hsx;
                         const int hx = sx + 1;
-                        const float* m = (h == 0) ? m_in[k] : m_h[k];
-                        const float2 ex = csub(su[0][hz][hx + 1], su[0][hz][hx - 1]);
-                        const float2 ez = csub(su[1][hz + 1][hx], su[1][hz - 1][hx]);
-                        const float2 exz = cadd(csub(su[0][hz + 1][hx], su[0][hz - 1][hx]),
+                        const real* m = (h == 0) ? m_in[k] : m_h[k];
+                        const cplx ex = csub(su[0][hz][hx + 1], su[0][hz][hx - 1]);
+                        const cplx ez = csub(su[1][hz + 1][hx], su[1][hz - 1][hx]);
+                        const cplx exz = cadd(csub(su[0][hz + 1][hx], su[0][hz - 1][hx]),
                                                 csub(su[1][hz][hx + 1], su[1][hz][hx - 1]));
-                        ss[0][sz][sx] = make_float2(m[0] * ex.x + m[1] * ez.x, m[0] * ex.y + m[1] * ez.y);
-                        ss[1][sz][sx] = make_float2(m[1] * ex.x + m[2] * ez.x, m[1] * ex.y + m[2] * ez.y);
+                        ss[0][sz][sx] = mkc(m[0] * ex.x + m[1] * ez.x, m[0] * ex.y + m[1] * ez.y);
+                        ss[1][sz][sx] = mkc(m[1] * ex.x + m[2] * ez.x, m[1] * ex.y + m[2] * ez.y);
                         ss[2][sz][sx] = cscale(exz, m[3]);
                     }
                 }
@@ -209,11 +208,11 @@ __global__ __launch_bounds__(256) void k_body_force(const float2* __restrict__ u
             for (int k = 0; k < KB; ++k) {
                 const int lz = tg + 4 * k;
                 const int sz = lz + 1, sx = tx + 1;
-                const float2 dx1 = csub(ss[0][sz][sx + 1], ss[0][sz][sx - 1]);
-                const float2 dz5 = csub(ss[2][sz + 1][sx], ss[2][sz - 1][sx]);
-                const float2 dx5 = csub(ss[2][sz][sx + 1], ss[2][sz][sx - 1]);
-                const float2 dz3 = csub(ss[1][sz + 1][sx], ss[1][sz - 1][sx]);
-                const float2 wr = cscale(pd.w2, rho[k]);
+                const cplx dx1 = csub(ss[0][sz][sx + 1], ss[0][sz][sx - 1]);
+                const cplx dz5 = csub(ss[2][sz + 1][sx], ss[2][sz - 1][sx]);
+                const cplx dx5 = csub(ss[2][sz][sx + 1], ss[2][sz][sx - 1]);
+                const cplx dz3 = csub(ss[1][sz + 1][sx], ss[1][sz - 1][sx]);
+                const cplx wr = cscale(pd.w2, rho[k]);
                 const size_t gi = (size_t)(z0 + lz) * nx + x0 + tx;
                 st_wt(bs + gi, cadd(cmul(wr, su[0][lz + 2][tx + 2]), cscale(cadd(dx1, dz5), sc)));
                 st_wt(bs + plane + gi, cadd(cmul(wr, su[1][lz + 2][tx + 2]), cscale(cadd(dx5, dz3), sc)));
@@ -234,7 +233,11 @@ StCfg st_default() { return StCfg{STZ, 0}; }
 
 bool st_cfg_ok(int nx, int nz, const StCfg& c) {
     if (tile_x(nx) == 0) return false;
+#ifdef FW_C128
+    if (c.TZ != 4 && c.TZ != 8) return false;   // 16-row complex128 tiles exceed the static LDS limit
+#else
     if (c.TZ != 4 && c.TZ != 8 && c.TZ != 16) return false;
+#endif
     if (nz % c.TZ != 0) return false;
     return c.S == 0 || c.S == 1 || c.S == 2 || c.S == 4 || c.S == 8 || c.S == 16;
 }
@@ -280,7 +283,9 @@ template <int TX>
 static void body_force_tz(int vm, const StCfg& c, const StencilArgs& a, const ProbDev& pd, SysState* st,
                           hipStream_t s) {
     if (c.TZ == 4) body_force_vm<TX, 4>(vm, c, a, pd, st, s);
+#ifndef FW_C128
     else if (c.TZ == 16) body_force_vm<TX, 16>(vm, c, a, pd, st, s);
+#endif
     else body_force_vm<TX, 8>(vm, c, a, pd, st, s);
 }
 
@@ -300,7 +305,7 @@ hipError_t launch_stencil(int vm, const StCfg& c, const StencilArgs& a, const Pr
     return hipGetLastError();
 }
 
-hipError_t launch_body_force(const StCfg& c, const float2* u, float2* b, const float* maps,
+hipError_t launch_body_force(const StCfg& c, const cplx* u, cplx* b, const real* maps,
                              const ProbDev& pd, const SysState* st, hipStream_t s) {
     StencilArgs a{u, nullptr, nullptr, nullptr, b, maps, nullptr, 0};
     return launch_stencil(VM_NONE, c, a, pd, const_cast<SysState*>(st), s);
@@ -333,11 +338,11 @@ __device__ __forceinline__ VecIdx vec_idx(int nb) {
 
 // r = b (or r already holds b - A x0), x = 0 if zero_x, rhat = r, p = v = 0;
 // partials <rhat, r>, ||r||^2 and ||b||^2.
-__global__ __launch_bounds__(256) void k_bicg_init(const float2* __restrict__ b,
-                                                   const float2* r0,   // may alias r
-                                                   float2* __restrict__ x, float2* r,
-                                                   float2* __restrict__ rhat, float2* __restrict__ p,
-                                                   float2* __restrict__ v,
+__global__ __launch_bounds__(256) void k_bicg_init(const cplx* __restrict__ b,
+                                                   const cplx* r0,   // may alias r
+                                                   cplx* __restrict__ x, cplx* r,
+                                                   cplx* __restrict__ rhat, cplx* __restrict__ p,
+                                                   cplx* __restrict__ v,
                                                    double* __restrict__ partXR,
                                                    double* __restrict__ partB, int n, int nb,
                                                    int zero_x) {
@@ -349,13 +354,13 @@ __global__ __launch_bounds__(256) void k_bicg_init(const float2* __restrict__ b,
     for (int e = 0; e < kVecEPT; ++e) {
         const int i = vi.i0 + e * kVecThreads + threadIdx.x;
         if (i < n) {
-            const float2 bb = b[off + i];
-            const float2 rr = r0 ? r0[off + i] : bb;
-            if (zero_x) x[off + i] = make_float2(0.f, 0.f);
+            const cplx bb = b[off + i];
+            const cplx rr = r0 ? r0[off + i] : bb;
+            if (zero_x) x[off + i] = mkc(0.f, 0.f);
             r[off + i] = rr;
             rhat[off + i] = rr;
-            p[off + i] = make_float2(0.f, 0.f);
-            v[off + i] = make_float2(0.f, 0.f);
+            p[off + i] = mkc(0.f, 0.f);
+            v[off + i] = mkc(0.f, 0.f);
             const double q = (double)rr.x * rr.x + (double)rr.y * rr.y;
             acc[0] += q;
             acc[2] += q;
@@ -409,10 +414,10 @@ __global__ __launch_bounds__(256) void k_bicg_state_init(SysState* __restrict__ 
 // closing updates x += alpha p + omega s, r = s - omega t owed to a stopped
 // system.  A running system gets its stagnation bookkeeping only; its closing
 // updates are left to the next direction-update stencil.
-__global__ __launch_bounds__(256) void k_bicg_close(float2* __restrict__ x, float2* __restrict__ r,
-                                                    const float2* __restrict__ p,
-                                                    const float2* __restrict__ sv,
-                                                    const float2* __restrict__ t,
+__global__ __launch_bounds__(256) void k_bicg_close(cplx* __restrict__ x, cplx* __restrict__ r,
+                                                    const cplx* __restrict__ p,
+                                                    const cplx* __restrict__ sv,
+                                                    const cplx* __restrict__ t,
                                                     const double* __restrict__ partT, int npT,
                                                     SysState* __restrict__ st, int n, int nb) {
     __shared__ double red[4 * kPartialNV];
@@ -441,13 +446,13 @@ __global__ __launch_bounds__(256) void k_bicg_close(float2* __restrict__ x, floa
         return;
     }
     if (code != ST_NONFINITE) {
-        const float2 af = tof(dcomplex{z.alpha_re, z.alpha_im}), of = tof(o.omega);
+        const cplx af = toc(dcomplex{z.alpha_re, z.alpha_im}), of = toc(o.omega);
         const size_t off = (size_t)vi.sys * n;
 #pragma unroll
         for (int e = 0; e < kVecEPT; ++e) {
             const int i = vi.i0 + e * kVecThreads + threadIdx.x;
             if (i < n) {
-                const float2 svv = sv[off + i];
+                const cplx svv = sv[off + i];
                 st_wt(r + off + i, close_r(svv, t[off + i], of));
                 st_wt(x + off + i, close_x(x[off + i], p[off + i], svv, af, of));
             }
@@ -526,8 +531,8 @@ hipError_t launch_bicg_restart(SysState* st, int nsys, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_bicg_init(const float2* b, const float2* r0, float2* x, float2* r, float2* rhat,
-                            float2* p, float2* v, double* partXR, double* partB, int nsys, int n,
+hipError_t launch_bicg_init(const cplx* b, const cplx* r0, cplx* x, cplx* r, cplx* rhat,
+                            cplx* p, cplx* v, double* partXR, double* partB, int nsys, int n,
                             bool zero_x, hipStream_t s) {
     const int nb = vec_blocks_per_sys(n);
     hipLaunchKernelGGL(k_bicg_init, dim3(nsys * nb), dim3(kVecThreads), 0, s, b, r0, x, r, rhat, p,
@@ -542,7 +547,7 @@ hipError_t launch_bicg_state_init(SysState* st, const double* partXR, const doub
     return hipGetLastError();
 }
 
-hipError_t launch_bicg_close(float2* x, float2* r, const float2* p, const float2* sv, const float2* t,
+hipError_t launch_bicg_close(cplx* x, cplx* r, const cplx* p, const cplx* sv, const cplx* t,
                              const double* partT, int npT, SysState* st, int nsys, int n, hipStream_t s) {
     const int nb = vec_blocks_per_sys(n);
     hipLaunchKernelGGL(k_bicg_close, dim3(nsys * nb), dim3(kVecThreads), 0, s, x, r, p, sv, t, partT, npT, st, n,
@@ -569,15 +574,17 @@ __global__ __launch_bounds__(256) void k_zero(float4* __restrict__ dst, size_t n
         dst[i] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
-// n complex elements; n is even for every field of this library.
-hipError_t launch_copy(const float2* src, float2* dst, size_t n, hipStream_t s) {
-    const size_t n4 = n / 2;
+// n complex elements, moved as 16-byte words (n is even for every field of
+// this library).
+constexpr size_t kCplxPerWord = 16 / sizeof(cplx);
+hipError_t launch_copy(const cplx* src, cplx* dst, size_t n, hipStream_t s) {
+    const size_t n4 = n / kCplxPerWord;
     const int blocks = (int)std::min<size_t>((n4 + 255) / 256, 8192);
     hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(256), 0, s, (const float4*)src, (float4*)dst, n4);
     return hipGetLastError();
 }
-hipError_t launch_zero(float2* dst, size_t n, hipStream_t s) {
-    const size_t n4 = n / 2;
+hipError_t launch_zero(cplx* dst, size_t n, hipStream_t s) {
+    const size_t n4 = n / kCplxPerWord;
     const int blocks = (int)std::min<size_t>((n4 + 255) / 256, 8192);
     hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, s, (float4*)dst, n4);
     return hipGetLastError();
@@ -585,26 +592,26 @@ hipError_t launch_zero(float2* dst, size_t n, hipStream_t s) {
 
 // ---------------------------------------------------- sources, receivers --
 // f must be zero on entry: one force per system, F / dx^2 at (ix, iz).
-__global__ void k_point_sources(float2* __restrict__ f, const int32_t* __restrict__ ixz,
+__global__ void k_point_sources(cplx* __restrict__ f, const int32_t* __restrict__ ixz,
                                 const double* __restrict__ force, ProbDev pd) {
     const int sys = blockIdx.x * blockDim.x + threadIdx.x;
     if (sys >= pd.nsys) return;
     const size_t plane = (size_t)pd.nx * pd.nz;
     const int ix = ixz[2 * sys], iz = ixz[2 * sys + 1];
     const double inv = 1.0 / ((double)pd.dx * (double)pd.dx);
-    float2* fs = f + (size_t)sys * 2 * plane + (size_t)iz * pd.nx + ix;
-    fs[0] = make_float2((float)(force[2 * sys] * inv), 0.f);
-    fs[plane] = make_float2((float)(force[2 * sys + 1] * inv), 0.f);
+    cplx* fs = f + (size_t)sys * 2 * plane + (size_t)iz * pd.nx + ix;
+    fs[0] = mkc((real)(force[2 * sys] * inv), 0.f);
+    fs[plane] = mkc((real)(force[2 * sys + 1] * inv), 0.f);
 }
 
-hipError_t launch_point_sources(float2* f, const int32_t* src_ixz, const double* src_f,
+hipError_t launch_point_sources(cplx* f, const int32_t* src_ixz, const double* src_f,
                                 const ProbDev& pd, hipStream_t s) {
     hipLaunchKernelGGL(k_point_sources, dim3((pd.nsys + 63) / 64), dim3(64), 0, s, f, src_ixz, src_f, pd);
     return hipGetLastError();
 }
 
 // d[sys][rec][c] = w[sys][c][iz][ix]
-__global__ void k_gather(const float2* __restrict__ w, float2* __restrict__ d,
+__global__ void k_gather(const cplx* __restrict__ w, cplx* __restrict__ d,
                          const int32_t* __restrict__ rec, int nrec, ProbDev pd) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int total = pd.nsys * nrec * 2;
@@ -616,7 +623,7 @@ __global__ void k_gather(const float2* __restrict__ w, float2* __restrict__ d,
     d[i] = w[(size_t)sys * 2 * plane + c * plane + (size_t)rec[2 * rr + 1] * pd.nx + rec[2 * rr]];
 }
 
-hipError_t launch_gather(const float2* w, float2* d, const int32_t* rec_ixz, int nrec,
+hipError_t launch_gather(const cplx* w, cplx* d, const int32_t* rec_ixz, int nrec,
                          const ProbDev& pd, hipStream_t s) {
     const int total = pd.nsys * nrec * 2;
     hipLaunchKernelGGL(k_gather, dim3((total + 255) / 256), dim3(256), 0, s, w, d, rec_ixz, nrec, pd);
@@ -625,21 +632,21 @@ hipError_t launch_gather(const float2* w, float2* d, const int32_t* rec_ixz, int
 
 // f (zero on entry) += conj(d) at the receivers; one thread per (sys, c)
 // walks the receivers in order, so repeated receivers add deterministically.
-__global__ void k_scatter_conj(const float2* __restrict__ d, float2* __restrict__ f,
+__global__ void k_scatter_conj(const cplx* __restrict__ d, cplx* __restrict__ f,
                                const int32_t* __restrict__ rec, int nrec, ProbDev pd) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= pd.nsys * 2) return;
     const int sys = i >> 1, c = i & 1;
     const size_t plane = (size_t)pd.nx * pd.nz;
-    float2* fs = f + (size_t)sys * 2 * plane + c * plane;
+    cplx* fs = f + (size_t)sys * 2 * plane + c * plane;
     for (int r = 0; r < nrec; ++r) {
-        const float2 dv = d[((size_t)sys * nrec + r) * 2 + c];
+        const cplx dv = d[((size_t)sys * nrec + r) * 2 + c];
         const size_t gi = (size_t)rec[2 * r + 1] * pd.nx + rec[2 * r];
         fs[gi] = cadd(fs[gi], cconj(dv));
     }
 }
 
-hipError_t launch_scatter_conj(const float2* d, float2* f, const int32_t* rec_ixz, int nrec,
+hipError_t launch_scatter_conj(const cplx* d, cplx* f, const int32_t* rec_ixz, int nrec,
                                const ProbDev& pd, hipStream_t s) {
     const int total = pd.nsys * 2;
     hipLaunchKernelGGL(k_scatter_conj, dim3((total + 63) / 64), dim3(64), 0, s, d, f, rec_ixz, nrec, pd);
@@ -650,9 +657,9 @@ hipError_t launch_scatter_conj(const float2* d, float2* f, const int32_t* rec_ix
 // g_rho = conj(w~^2 sum_sys u^a . u^b); g_p = -conj(sum_sys eps^a . B^p eps^b),
 // with the 2-D B matrices of the maps (C11, C13, C33, C55):
 //   B11 -> e1 e1,  B13 -> e1 e3 + e3 e1,  B33 -> e3 e3,  B55 -> e5 e5.
-__global__ __launch_bounds__(256) void k_correlate(const float2* __restrict__ ua,
-                                                   const float2* __restrict__ ub,
-                                                   float2* __restrict__ g, ProbDev pd, int accumulate) {
+__global__ __launch_bounds__(256) void k_correlate(const cplx* __restrict__ ua,
+                                                   const cplx* __restrict__ ub,
+                                                   cplx* __restrict__ g, ProbDev pd, int accumulate) {
     const int nx = pd.nx, nz = pd.nz;
     const size_t plane = (size_t)nx * nz;
     const int cell = blockIdx.x * blockDim.x + threadIdx.x;
@@ -665,17 +672,17 @@ __global__ __launch_bounds__(256) void k_correlate(const float2* __restrict__ ua
     double rr = 0, ri = 0, a11r = 0, a11i = 0, a13r = 0, a13i = 0, a33r = 0, a33i = 0, a55r = 0,
            a55i = 0;
     for (int s = 0; s < pd.nsys; ++s) {
-        const float2* A = ua + (size_t)s * 2 * plane;
-        const float2* B = ub + (size_t)s * 2 * plane;
-        const float2 ax = A[ic], az = A[plane + ic], bx = B[ic], bz = B[plane + ic];
+        const cplx* A = ua + (size_t)s * 2 * plane;
+        const cplx* B = ub + (size_t)s * 2 * plane;
+        const cplx ax = A[ic], az = A[plane + ic], bx = B[ic], bz = B[plane + ic];
         rr += (double)ax.x * bx.x - (double)ax.y * bx.y + (double)az.x * bz.x - (double)az.y * bz.y;
         ri += (double)ax.x * bx.y + (double)ax.y * bx.x + (double)az.x * bz.y + (double)az.y * bz.x;
-        const float2 e1a = csub(A[ixp], A[ixm]);
-        const float2 e3a = csub(A[plane + izp], A[plane + izm]);
-        const float2 e5a = cadd(csub(A[izp], A[izm]), csub(A[plane + ixp], A[plane + ixm]));
-        const float2 e1b = csub(B[ixp], B[ixm]);
-        const float2 e3b = csub(B[plane + izp], B[plane + izm]);
-        const float2 e5b = cadd(csub(B[izp], B[izm]), csub(B[plane + ixp], B[plane + ixm]));
+        const cplx e1a = csub(A[ixp], A[ixm]);
+        const cplx e3a = csub(A[plane + izp], A[plane + izm]);
+        const cplx e5a = cadd(csub(A[izp], A[izm]), csub(A[plane + ixp], A[plane + ixm]));
+        const cplx e1b = csub(B[ixp], B[ixm]);
+        const cplx e3b = csub(B[plane + izp], B[plane + izm]);
+        const cplx e5b = cadd(csub(B[izp], B[izm]), csub(B[plane + ixp], B[plane + ixm]));
         a11r += (double)e1a.x * e1b.x - (double)e1a.y * e1b.y;
         a11i += (double)e1a.x * e1b.y + (double)e1a.y * e1b.x;
         a13r += (double)e1a.x * e3b.x - (double)e1a.y * e3b.y + (double)e3a.x * e1b.x - (double)e3a.y * e1b.y;
@@ -688,20 +695,20 @@ __global__ __launch_bounds__(256) void k_correlate(const float2* __restrict__ ua
     const double s = (double)pd.inv4dx2;
     const double wr = pd.w2.x, wi = pd.w2.y;
     // conj(w2 * rho) ; -conj(a) * s
-    float2 out[5];
-    out[0] = make_float2((float)(-a11r * s), (float)(a11i * s));
-    out[1] = make_float2((float)(-a13r * s), (float)(a13i * s));
-    out[2] = make_float2((float)(-a33r * s), (float)(a33i * s));
-    out[3] = make_float2((float)(-a55r * s), (float)(a55i * s));
-    out[4] = make_float2((float)(wr * rr - wi * ri), (float)(-(wr * ri + wi * rr)));
+    cplx out[5];
+    out[0] = mkc((real)(-a11r * s), (real)(a11i * s));
+    out[1] = mkc((real)(-a13r * s), (real)(a13i * s));
+    out[2] = mkc((real)(-a33r * s), (real)(a33i * s));
+    out[3] = mkc((real)(-a55r * s), (real)(a55i * s));
+    out[4] = mkc((real)(wr * rr - wi * ri), (real)(-(wr * ri + wi * rr)));
 #pragma unroll
     for (int p = 0; p < 5; ++p) {
-        float2* dst = g + (size_t)p * plane + ic;
+        cplx* dst = g + (size_t)p * plane + ic;
         *dst = accumulate ? cadd(*dst, out[p]) : out[p];
     }
 }
 
-hipError_t launch_correlate(const float2* ua, const float2* ub, float2* g, const ProbDev& pd,
+hipError_t launch_correlate(const cplx* ua, const cplx* ub, cplx* g, const ProbDev& pd,
                             bool accumulate, hipStream_t s) {
     const int cells = pd.nx * pd.nz;
     hipLaunchKernelGGL(k_correlate, dim3((cells + 255) / 256), dim3(256), 0, s, ua, ub, g, pd,
@@ -709,4 +716,4 @@ hipError_t launch_correlate(const float2* ua, const float2* ub, float2* g, const
     return hipGetLastError();
 }
 
-}  // namespace fw
+FW_END

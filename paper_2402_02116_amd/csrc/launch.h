@@ -6,8 +6,7 @@
 
 #include "common.h"
 
-namespace fw {
-
+FW_BEGIN
 // Epilogues of the inverse row transform that ends a convolution y = G0 conv b.
 enum RowEpilogue : int {
     EPI_STORE = 0,     // out = y
@@ -22,7 +21,7 @@ enum RowEpilogue : int {
 
 // Extra arguments of the GMRES epilogues (unused by the others).
 struct GmEpi {
-    const float2* V;   // basis vector 0, indexed like the transform's output
+    const cplx* V;   // basis vector 0, indexed like the transform's output
     size_t vstride;    // complex elements between basis vectors
     int nv;            // basis vectors to project on
     double* part;      // [sys][blocks][kGmRec] partial records
@@ -75,24 +74,24 @@ KernelCfg kernel_cfg_default(int nx, int nz);
 // packed back to back; offset of size n in complex elements.
 size_t twiddle_table_elems();
 size_t twiddle_offset(int n);
-void twiddle_table_fill(float2* host);
+void twiddle_table_fill(cplx* host);
 
 // Row transforms over nrows rows of length n (rows_per_sys rows per system;
 // a block never straddles systems).  st (may be null): systems whose status is
 // not RUNNING are skipped.
 // P is the points-per-thread variant (row_points_ok).
-hipError_t launch_rows_fwd(int n, int P, const float2* in, float2* out, int nrows, int rows_per_sys,
-                           const SysState* st, const float2* tw, hipStream_t s);
-hipError_t launch_rows_inv(int n, int P, int epi, const float2* in, const float2* u, const float2* aux,
-                           float2* out, double* partials, int nrows, int rows_per_sys,
-                           const SysState* st, const float2* tw, hipStream_t s, const GmEpi* ge = nullptr);
+hipError_t launch_rows_fwd(int n, int P, const cplx* in, cplx* out, int nrows, int rows_per_sys,
+                           const SysState* st, const cplx* tw, hipStream_t s);
+hipError_t launch_rows_inv(int n, int P, int epi, const cplx* in, const cplx* u, const cplx* aux,
+                           cplx* out, double* partials, int nrows, int rows_per_sys,
+                           const SysState* st, const cplx* tw, hipStream_t s, const GmEpi* ge = nullptr);
 // Column pass over [nsys][2][nz][nx] in place.  COL_FWD / COL_INV exist in
 // the default points-per-thread variant with shared LDS only.
-hipError_t launch_cols(int mode, const ColCfg& c, float2* data, const ProbDev& pd, const SysState* st,
-                       const float2* tw, hipStream_t s);
+hipError_t launch_cols(int mode, const ColCfg& c, cplx* data, const ProbDev& pd, const SysState* st,
+                       const cplx* tw, hipStream_t s);
 
 // Body force b = w~^2 drho u + div_h(dC : E_h u) of one problem.
-hipError_t launch_body_force(const StCfg& c, const float2* u, float2* b, const float* maps,
+hipError_t launch_body_force(const StCfg& c, const cplx* u, cplx* b, const real* maps,
                              const ProbDev& pd, const SysState* st, hipStream_t s);
 // Vector update fused into a stencil's load of its input field:
 //   VM_NONE: the input is u itself;
@@ -111,18 +110,18 @@ enum StencilVec : int { VM_NONE = 0, VM_P = 1, VM_S = 2, VM_PX = 3 };
 // a1 = p_old, a2 = v, a3 = t, xio = x, rout = r, wout = p_new, part = the
 // t-pass records]).
 struct StencilArgs {
-    const float2* u;
-    const float2* a1;
-    const float2* a2;
-    float2* wout;
-    float2* b;
-    const float* maps;
+    const cplx* u;
+    const cplx* a1;
+    const cplx* a2;
+    cplx* wout;
+    cplx* b;
+    const real* maps;
     const double* part;
     int np;
-    float2* rhat = nullptr;        // vm 1, 3: shadow residual, set to r when the iteration restarts
-    const float2* a3 = nullptr;    // vm 3: t
-    float2* xio = nullptr;         // vm 3: x (updated)
-    float2* rout = nullptr;        // vm 3: r (written)
+    cplx* rhat = nullptr;        // vm 1, 3: shadow residual, set to r when the iteration restarts
+    const cplx* a3 = nullptr;    // vm 3: t
+    cplx* xio = nullptr;         // vm 3: x (updated)
+    cplx* rout = nullptr;        // vm 3: r (written)
 };
 hipError_t launch_stencil(int vm, const StCfg& c, const StencilArgs& a, const ProbDev& pd, SysState* st,
                           hipStream_t s);
@@ -131,17 +130,17 @@ hipError_t launch_stencil(int vm, const StCfg& c, const StencilArgs& a, const Pr
 constexpr int kSrowsMaxN = 512;
 int srows_rows(int nx, int nz, int P);          // rows per block, 0 if unavailable
 size_t srows_lds(int nx, int F);
-hipError_t launch_srows(int vm, int P, const StencilArgs& a, float2* out, const ProbDev& pd, SysState* st,
-                        const float2* tw, hipStream_t s);
+hipError_t launch_srows(int vm, int P, const StencilArgs& a, cplx* out, const ProbDev& pd, SysState* st,
+                        const cplx* tw, hipStream_t s);
 
 // BiCGSTAB pieces (one problem; n = 2 nz nx complex per system).
 int vec_blocks_per_sys(int n);
-hipError_t launch_bicg_init(const float2* b, const float2* r0, float2* x, float2* r, float2* rhat,
-                            float2* p, float2* v, double* partXR, double* partB, int nsys, int n,
+hipError_t launch_bicg_init(const cplx* b, const cplx* r0, cplx* x, cplx* r, cplx* rhat,
+                            cplx* p, cplx* v, double* partXR, double* partB, int nsys, int n,
                             bool zero_x, hipStream_t s);
 hipError_t launch_bicg_state_init(SysState* st, const double* partXR, const double* partB,
                                   int nsys, int npart, double rtol, int maxit, hipStream_t s);
-hipError_t launch_bicg_close(float2* x, float2* r, const float2* p, const float2* sv, const float2* t,
+hipError_t launch_bicg_close(cplx* x, cplx* r, const cplx* p, const cplx* sv, const cplx* t,
                              const double* partT, int npT, SysState* st, int nsys, int n, hipStream_t s);
 hipError_t launch_bicg_restart_mark(SysState* st, const double* partTR, int npTR, int nsys, double limit2,
                                     int max_restarts, hipStream_t s);
@@ -151,7 +150,7 @@ hipError_t launch_bicg_finish(const SysState* st, const double* partTR, int npTR
 
 // Batched restarted GMRES (one problem).
 struct GmArgs {
-    float2* V;          // basis slot 0 of this problem (system 0)
+    cplx* V;          // basis slot 0 of this problem (system 0)
     size_t vstride;     // complex elements between basis slots
     GmSys* gs;          // per-system FP64 state
     SysState* st;       // per-system status / iteration count
@@ -174,37 +173,37 @@ hipError_t launch_gm_sum(const GmArgs& a, int mode, int nb, int j, bool cgs2, do
                          hipStream_t s);
 hipError_t launch_gm_update(const GmArgs& a, int j, int pass, bool final, hipStream_t s);
 hipError_t launch_gm_dots(const GmArgs& a, int j, hipStream_t s);
-hipError_t launch_gm_finish_cycle(float2* x, const GmArgs& a, hipStream_t s);
+hipError_t launch_gm_finish_cycle(cplx* x, const GmArgs& a, hipStream_t s);
 hipError_t launch_gm_report(const SysState* st, int32_t* iters, double* relres, int nsys, hipStream_t s);
 
 // Sources, receivers, correlation.
-hipError_t launch_point_sources(float2* f, const int32_t* src_ixz, const double* src_f,
+hipError_t launch_point_sources(cplx* f, const int32_t* src_ixz, const double* src_f,
                                 const ProbDev& pd, hipStream_t s);
-hipError_t launch_gather(const float2* w, float2* d, const int32_t* rec_ixz, int nrec,
+hipError_t launch_gather(const cplx* w, cplx* d, const int32_t* rec_ixz, int nrec,
                          const ProbDev& pd, hipStream_t s);
-hipError_t launch_scatter_conj(const float2* d, float2* f, const int32_t* rec_ixz, int nrec,
+hipError_t launch_scatter_conj(const cplx* d, cplx* f, const int32_t* rec_ixz, int nrec,
                                const ProbDev& pd, hipStream_t s);
-hipError_t launch_correlate(const float2* ua, const float2* ub, float2* g, const ProbDev& pd,
+hipError_t launch_correlate(const cplx* ua, const cplx* ub, cplx* g, const ProbDev& pd,
                             bool accumulate, hipStream_t s);
-hipError_t launch_copy(const float2* src, float2* dst, size_t n, hipStream_t s);
-hipError_t launch_zero(float2* dst, size_t n, hipStream_t s);
+hipError_t launch_copy(const cplx* src, cplx* dst, size_t n, hipStream_t s);
+hipError_t launch_zero(cplx* dst, size_t n, hipStream_t s);
 
 // Tikhonov-step model maps (5 maps of one grid).
 struct MapScales { double s[5]; };
-hipError_t launch_map_scale(const float* q, float* out, const MapScales& m0, int n, hipStream_t s);
-hipError_t launch_laplacian(const float* q, float* out, int nx, int nz, int nmaps, hipStream_t s);
-hipError_t launch_map_combine(const float2* g, const float* reg, float* out, const MapScales& m0,
+hipError_t launch_map_scale(const real* q, real* out, const MapScales& m0, int n, hipStream_t s);
+hipError_t launch_laplacian(const real* q, real* out, int nx, int nz, int nmaps, hipStream_t s);
+hipError_t launch_map_combine(const cplx* g, const real* reg, real* out, const MapScales& m0,
                               double cj, double cl, int n, hipStream_t s);
 constexpr int kDotPartials = 512;
-hipError_t launch_dot_real(const float* a, const float* b, size_t n, double* part, double* out,
+hipError_t launch_dot_real(const real* a, const real* b, size_t n, double* part, double* out,
                            hipStream_t s);
-hipError_t launch_norm2_complex(const float2* a, size_t n, double* part, double* out, hipStream_t s);
-hipError_t launch_cg_xr(float* x, float* res, const float* p, const float* Ap, const double* sc, size_t n,
+hipError_t launch_norm2_complex(const cplx* a, size_t n, double* part, double* out, hipStream_t s);
+hipError_t launch_cg_xr(real* x, real* res, const real* p, const real* Ap, const double* sc, size_t n,
                         hipStream_t s);
-hipError_t launch_cg_p(float* p, const float* res, const double* sc, size_t n, hipStream_t s);
+hipError_t launch_cg_p(real* p, const real* res, const double* sc, size_t n, hipStream_t s);
 hipError_t launch_cg_shift(double* sc, double* hist, int it, hipStream_t s);
-hipError_t launch_copy_f(const float* a, float* b, size_t n, hipStream_t s);
-hipError_t launch_zero_f(float* b, size_t n, hipStream_t s);
-hipError_t launch_sub_complex(float2* d, const float2* r, size_t n, hipStream_t s);
+hipError_t launch_copy_f(const real* a, real* b, size_t n, hipStream_t s);
+hipError_t launch_zero_f(real* b, size_t n, hipStream_t s);
+hipError_t launch_sub_complex(cplx* d, const cplx* r, size_t n, hipStream_t s);
 
-}  // namespace fw
+FW_END

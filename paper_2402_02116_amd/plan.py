@@ -5,9 +5,11 @@ libfwils.so.  PyTorch supplies device memory (the workspace and the fields)
 and the stream: each call enqueues on torch's current stream of the plan's
 device.
 
-Field tensors are flat complex64 CUDA tensors holding the plan-level field
+Field tensors are flat complex CUDA tensors holding the plan-level field
 (problems concatenated, each [nsys][2][nz][nx]); `view(t, i)` gives problem i
-as a [nsys, 2, nz, nx] view.
+as a [nsys, 2, nz, nx] view.  A plan is complex64 with float32 maps
+(precision "c64", the default) or complex128 with float64 maps ("c128", the
+FP64 reference of the same kernels); `cdtype` / `rdtype` are its types.
 """
 
 import ctypes
@@ -20,6 +22,8 @@ from . import _lib
 from ._lib import check
 
 SYMBOLS = {"spectral": _lib.FWILS_SYMBOL_SPECTRAL, "central": _lib.FWILS_SYMBOL_CENTRAL}
+PRECISIONS = {"c64": (_lib.FWILS_C64, torch.complex64, torch.float32),
+              "c128": (_lib.FWILS_C128, torch.complex128, torch.float64)}
 
 
 @dataclass
@@ -46,8 +50,12 @@ def _require_cuda(t, dtype, name):
 class Plan:
     """One or more (grid, frequency) problems solved together."""
 
-    def __init__(self, problems, device="cuda"):
+    def __init__(self, problems, device="cuda", precision="c64"):
         self.lib = _lib.load()
+        if precision not in PRECISIONS:
+            raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
+        self.precision = precision
+        prec, self.cdtype, self.rdtype = PRECISIONS[precision]
         if not torch.cuda.is_available():
             raise RuntimeError("fwils needs a ROCm GPU (torch.cuda.is_available() is False)")
         self.device = torch.device(device)
@@ -68,7 +76,7 @@ class Plan:
             sym = p.get("symbol", "spectral")
             arr[i].symbol = SYMBOLS[sym] if isinstance(sym, str) else int(sym)
         h = ctypes.c_void_p()
-        check(self.lib.fwils_plan_create(arr, n, _lib.FWILS_C64, ctypes.byref(h)), "fwils_plan_create")
+        check(self.lib.fwils_plan_create(arr, n, prec, ctypes.byref(h)), "fwils_plan_create")
         self._h = h
         size = ctypes.c_size_t()
         check(self.lib.fwils_workspace_size(h, ctypes.byref(size)), "fwils_workspace_size")
@@ -110,7 +118,7 @@ class Plan:
         check(self.lib.fwils_set_stream(self._h, ctypes.c_void_p(s)), "fwils_set_stream")
 
     def new_field(self):
-        return torch.zeros(self.field_elems, dtype=torch.complex64, device=self.device)
+        return torch.zeros(self.field_elems, dtype=self.cdtype, device=self.device)
 
     def view(self, t, i):
         p = self.problems[i]
@@ -120,11 +128,11 @@ class Plan:
     def pack(self, parts):
         """Concatenate per-problem [nsys, 2, nz, nx] arrays into a plan-level field."""
         flat = [torch.as_tensor(np.asarray(x) if not isinstance(x, torch.Tensor) else x)
-                .to(torch.complex64).reshape(-1) for x in parts]
+                .to(self.cdtype).reshape(-1) for x in parts]
         return torch.cat(flat).to(self.device).contiguous()
 
     def _field(self, t, name):
-        _require_cuda(t, torch.complex64, name)
+        _require_cuda(t, self.cdtype, name)
         if t.numel() != self.field_elems:
             raise ValueError(f"{name} has {t.numel()} elements, the plan's fields have {self.field_elems}")
         return t
@@ -140,7 +148,7 @@ class Plan:
     # ---------------------------------------------------------- the ABI ----
     def set_contrast(self, i, maps):
         p = self.problems[i]
-        m = torch.as_tensor(maps, dtype=torch.float32).to(self.device).contiguous()
+        m = torch.as_tensor(maps, dtype=self.rdtype).to(self.device).contiguous()
         if tuple(m.shape) != (5, p["nz"], p["nx"]):
             raise ValueError(f"maps must be [5, {p['nz']}, {p['nx']}]")
         self._bind_stream()
@@ -212,17 +220,17 @@ class Plan:
         return SolveResult(x, iters.cpu().numpy(), relres.cpu().numpy(), st)
 
     def frechet(self, ub, dm, rtol=1e-6, maxit=1000):
-        """J dm for every system; dm: list (one per problem) of float32 [5, nz, nx]."""
+        """J dm for every system; dm: list (one per problem) of rdtype [5, nz, nx]."""
         self._field(ub, "ub")
         dms = []
         for i, p in enumerate(self.problems):
             m = dm[i]
-            _require_cuda(m, torch.float32, f"dm[{i}]")
+            _require_cuda(m, self.rdtype, f"dm[{i}]")
             if tuple(m.shape) != (5, p["nz"], p["nx"]):
                 raise ValueError(f"dm[{i}] must be [5, {p['nz']}, {p['nx']}]")
             dms.append(m)
         arr = (ctypes.c_void_p * len(dms))(*[m.data_ptr() for m in dms])
-        d = torch.zeros(self.data_elems(), dtype=torch.complex64, device=self.device)
+        d = torch.zeros(self.data_elems(), dtype=self.cdtype, device=self.device)
         self._bind_stream()
         st = self.lib.fwils_frechet(self._h, _ptr(ub), arr, _ptr(d), float(rtol), int(maxit))
         if st != _lib.FWILS_OK:
@@ -230,16 +238,16 @@ class Plan:
         return d
 
     def adjoint(self, ub, r, rtol=1e-6, maxit=1000, g=None, accumulate=False):
-        """J* r: list (one per problem) of complex64 [5, nz, nx] maps."""
+        """J* r: list (one per problem) of cdtype [5, nz, nx] maps."""
         self._field(ub, "ub")
-        _require_cuda(r, torch.complex64, "r")
+        _require_cuda(r, self.cdtype, "r")
         if r.numel() != self.data_elems():
             raise ValueError(f"r must hold {self.data_elems()} complex values")
         if g is None:
-            g = [torch.zeros(5, p["nz"], p["nx"], dtype=torch.complex64, device=self.device)
+            g = [torch.zeros(5, p["nz"], p["nx"], dtype=self.cdtype, device=self.device)
                  for p in self.problems]
         for i, gi in enumerate(g):
-            _require_cuda(gi, torch.complex64, f"g[{i}]")
+            _require_cuda(gi, self.cdtype, f"g[{i}]")
         arr = (ctypes.c_void_p * len(g))(*[gi.data_ptr() for gi in g])
         self._bind_stream()
         st = self.lib.fwils_adjoint(self._h, _ptr(ub), _ptr(r), arr,
@@ -293,7 +301,7 @@ class Plan:
 
     def _maps(self, q, name):
         p = self.problems[0]
-        _require_cuda(q, torch.float32, name)
+        _require_cuda(q, self.rdtype, name)
         if tuple(q.shape) != (5, p["nz"], p["nx"]):
             raise ValueError(f"{name} must be [5, {p['nz']}, {p['nx']}]")
         return q
@@ -304,17 +312,17 @@ class Plan:
         return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
     def _data(self, r, name):
-        _require_cuda(r, torch.complex64, name)
+        _require_cuda(r, self.cdtype, name)
         if r.numel() != self.data_elems():
             raise ValueError(f"{name} must hold {self.data_elems()} complex values")
         return r
 
     def frechet_rel(self, ub, q, m0, rtol=1e-6, maxit=1000):
-        """d = J (m0 q) for relative maps q [5, nz, nx] (float32)."""
+        """d = J (m0 q) for relative maps q [5, nz, nx] (rdtype)."""
         self._field(ub, "ub")
         self._maps(q, "q")
         m, mp = self._m0(m0)
-        d = torch.zeros(self.data_elems(), dtype=torch.complex64, device=self.device)
+        d = torch.zeros(self.data_elems(), dtype=self.cdtype, device=self.device)
         self._bind_stream()
         st = self.lib.fwils_frechet_rel(self._h, _ptr(ub), _ptr(q), mp, _ptr(d), float(rtol), int(maxit))
         if st != _lib.FWILS_OK:
@@ -322,12 +330,12 @@ class Plan:
         return d
 
     def adjoint_rel(self, ub, r, m0, rtol=1e-6, maxit=1000):
-        """gq = m0 Re(J* r) summed over problems, float32 [5, nz, nx]."""
+        """gq = m0 Re(J* r) summed over problems, rdtype [5, nz, nx]."""
         self._field(ub, "ub")
         self._data(r, "r")
         m, mp = self._m0(m0)
         p = self.problems[0]
-        gq = torch.zeros(5, p["nz"], p["nx"], dtype=torch.float32, device=self.device)
+        gq = torch.zeros(5, p["nz"], p["nx"], dtype=self.rdtype, device=self.device)
         self._bind_stream()
         st = self.lib.fwils_adjoint_rel(self._h, _ptr(ub), _ptr(r), mp, _ptr(gq), float(rtol), int(maxit))
         if st != _lib.FWILS_OK:
@@ -363,7 +371,7 @@ class Plan:
         self._maps(q, "q")
         m, mp = self._m0(m0)
         out = torch.empty_like(q)
-        d = torch.zeros(self.data_elems(), dtype=torch.complex64, device=self.device)
+        d = torch.zeros(self.data_elems(), dtype=self.cdtype, device=self.device)
         self._bind_stream()
         st = self.lib.fwils_normal_apply(self._h, _ptr(ub), mp, float(rr), float(lam), self.REGS[reg],
                                          _ptr(q), _ptr(out), _ptr(d), float(rtol), int(maxit))
@@ -377,7 +385,7 @@ class Plan:
         self._data(r, "r")
         m, mp = self._m0(m0)
         p = self.problems[0]
-        q = torch.empty(5, p["nz"], p["nx"], dtype=torch.float32, device=self.device)
+        q = torch.empty(5, p["nz"], p["nx"], dtype=self.rdtype, device=self.device)
         d = torch.empty_like(r)
         hist = np.zeros(niter + 1, dtype=np.float64)
         self._bind_stream()
@@ -458,7 +466,7 @@ class Plan:
 
     def fft2(self, i, x, inverse=False, out=None):
         """2-D FFT (unnormalised) of every field of problem i; x: [nsys, 2, nz, nx]."""
-        _require_cuda(x, torch.complex64, "x")
+        _require_cuda(x, self.cdtype, "x")
         out = torch.empty_like(x) if out is None else out
         self._bind_stream()
         check(self.lib.fwils_fft2(self._h, i, _ptr(x), _ptr(out), 1 if inverse else 0), "fwils_fft2")

@@ -116,7 +116,29 @@ def test_plan_create_argument_errors(lib):
     arr = (_lib.FwilsProblem * 1)(_prob())
     assert lib.fwils_plan_create(arr, 0, 0, ctypes.byref(h)) == _lib.FWILS_EINVAL
     assert lib.fwils_plan_create(arr, 1, 0, None) == _lib.FWILS_EINVAL
-    assert lib.fwils_plan_create(arr, 1, 7, ctypes.byref(h)) == _lib.FWILS_EUNSUPPORTED
+    assert lib.fwils_plan_create(arr, 1, 7, ctypes.byref(h)) == _lib.FWILS_EINVAL
+    assert b"precision" in lib.fwils_last_error()
+
+
+@pytest.mark.parametrize("prec,csize", [(_lib.FWILS_C64, 8), (_lib.FWILS_C128, 16)])
+def test_both_precisions_create_plans_and_dispatch(lib, prec, csize):
+    """Each precision has its own library core; the public entry points route
+    a plan to the core that created it (workspace scales with the element size)."""
+    arr = (_lib.FwilsProblem * 1)(_prob(nx=64, nz=32, nsys=3))
+    h = ctypes.c_void_p()
+    assert lib.fwils_plan_create(arr, 1, prec, ctypes.byref(h)) == _lib.FWILS_OK and h.value
+    try:
+        fe, sz = ctypes.c_int64(), ctypes.c_size_t()
+        assert lib.fwils_field_elems(h, ctypes.byref(fe)) == 0 and fe.value == 3 * 2 * 64 * 32
+        assert lib.fwils_workspace_size(h, ctypes.byref(sz)) == 0
+        assert sz.value >= 9 * fe.value * csize
+        # errors raised inside either core reach the shared error text
+        assert lib.fwils_apply(h, ctypes.c_void_p(256), ctypes.c_void_p(512)) == _lib.FWILS_ENOMEM
+        assert b"workspace" in lib.fwils_last_error()
+    finally:
+        lib.fwils_plan_destroy(h)
+    assert lib.fwils_apply(None, ctypes.c_void_p(256), ctypes.c_void_p(512)) == _lib.FWILS_EINVAL
+    assert b"null plan" in lib.fwils_last_error()
 
 
 def test_plan_metadata_without_device(lib):
