@@ -65,10 +65,12 @@ def _kernel_source_hash():
 
 
 # kernel-name test of each pass (template arguments vary with the tuned variant)
-PASS_MATCH = [lambda n: (n.startswith("void fw::k_body_force<") or "k_srows<" in n) and ", 0>(" in n,
-              lambda n: n.startswith("void fw::k_rows<") and ", false, 0>" in n,
-              lambda n: n.startswith("void fw::k_cols<") and ", 0, " in n,
-              lambda n: n.startswith("void fw::k_rows<") and ", true, 1>" in n]
+# (the complex64 build's kernels live in namespace fw::c64)
+PASS_MATCH = [lambda n: (n.startswith("void fw::c64::k_body_force<") or "c64::(anonymous namespace)::k_srows<" in n)
+              and ", 0>(" in n,
+              lambda n: n.startswith("void fw::c64::k_rows<") and ", false, 0>" in n,
+              lambda n: n.startswith("void fw::c64::k_cols<") and ", 0, " in n,
+              lambda n: n.startswith("void fw::c64::k_rows<") and ", true, 1>" in n]
 
 
 def summarize_counters(fetch_csv, write_csv, cmd):
@@ -116,14 +118,14 @@ def _pass_instance(k, tuning, n=256):
     """Kernel instance of pass k on an n^2 grid under the plan's variants."""
     if k == 0:
         if tuning.get("fused_points"):
-            return f"fw::(anonymous namespace)::k_srows<{n}, {tuning['fused_points']}, 0>"
-        return f"fw::k_body_force<64, {tuning['stencil_rows']}, 0>"
+            return f"fw::c64::(anonymous namespace)::k_srows<{n}, {tuning['fused_points']}, 0>"
+        return f"fw::c64::k_body_force<64, {tuning['stencil_rows']}, 0>"
     if k == 1:
-        return f"fw::k_rows<{n}, {tuning['row_points']}, false, 0>"
+        return f"fw::c64::k_rows<{n}, {tuning['row_points']}, false, 0>"
     if k == 2:
         seq = "true" if tuning["col_shared"] else "false"
-        return f"fw::k_cols<{n}, {tuning['col_points']}, 0, {seq}>"
-    return f"fw::k_rows<{n}, {tuning['row_points']}, true, 1>"
+        return f"fw::c64::k_cols<{n}, {tuning['col_points']}, 0, {seq}>"
+    return f"fw::c64::k_rows<{n}, {tuning['row_points']}, true, 1>"
 
 
 def _traffic_from_profiles(kernel_pass, tuning):
@@ -229,10 +231,10 @@ def multigrid(a):
     return 0
 
 
-def _tik_plan(probs, rec, krylov, a):
+def _tik_plan(probs, rec, krylov, a, precision="c64"):
     from paper_2402_02116_amd.plan import Plan
     plan = Plan([dict(nx=p["nx"], nz=p["nz"], dx=p["dx"], c0=p["c0"], rho0=p["rho0"], freq_hz=p["freq_hz"],
-                      eta=p["eta"], nsys=p["nsys"]) for p in probs], device="cuda:0")
+                      eta=p["eta"], nsys=p["nsys"]) for p in probs], device="cuda:0", precision=precision)
     for i, p in enumerate(probs):
         plan.set_contrast(i, p["maps"])
         plan.set_receivers(i, rec)
@@ -288,34 +290,57 @@ def jacobian(a):
     return 0
 
 
+def _normal_step(w, a, precision, niters, rtol):
+    """Background solve, data r = J dq*, then CG runs of each length in `niters`
+    on one plan of the given precision: (times, q and history of the longest
+    run, background-solve time, autotune choice)."""
+    import torch
+    probs, rec = w["problems"], w["rec_ixz"]
+    plan, tuned = _tik_plan(probs, rec, a.krylov, a, precision)
+    src = sum((p["src_ixz"] for p in probs), [])
+    frc = sum((p["src_f"] for p in probs), [])
+    t0 = time.perf_counter()
+    ub = plan.solve(plan.incident(src, frc), rtol=rtol, maxit=3000).x
+    torch.cuda.synchronize()
+    t_ub = time.perf_counter() - t0
+    print(f"[bench] {precision} background solve of {len(src)} systems: {t_ub:.2f} s", file=sys.stderr, flush=True)
+    m0v = w["m0"].ravel()
+    r = plan.frechet_rel(ub, torch.as_tensor(w["dq_true"], dtype=plan.rdtype).cuda(), m0v, rtol=rtol)
+    times, q, hist = {}, None, None
+    for n in niters:
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        q, hist = plan.normal_cg(ub, r, m0v, niter=n, lam=w["lam"], reg=w["reg"], rtol=rtol)
+        torch.cuda.synchronize()
+        times[n] = time.perf_counter() - t
+        print(f"[bench] {precision} normal CG, {n} iteration(s): {times[n]:.2f} s, residual history {hist}",
+              file=sys.stderr, flush=True)
+    q = q.double().cpu()
+    del plan, ub, r
+    torch.cuda.empty_cache()
+    return times, q, hist, t_ub, tuned, len(src)
+
+
 def normal_cg(a):
     """Full linear DBI step: 1024^2 VTI at 5 m, 128 surface forces x (4, 7, 10) Hz =
     384 systems, 201 receivers; data r = J dq* (linearised about the smooth
     background); CG on the Tikhonov normal equation (L = I, lambda 1e-3).  Times
-    one CG iteration as the difference of 2 and 1 iterations."""
+    one CG iteration as the difference of 2 and 1 iterations.  With
+    --fp64-reference the same step (--cg-iters iterations) is run again in
+    complex128 on the GPU and the complex64 result's error against it reported."""
     import numpy as np
-    import torch
     import workloads as W
     w = W.vti1024_normal()
-    probs, rec = w["problems"], w["rec_ixz"]
-    plan, tuned = _tik_plan(probs, rec, a.krylov, a)
-    src = sum((p["src_ixz"] for p in probs), [])
-    frc = sum((p["src_f"] for p in probs), [])
-    t0 = time.perf_counter()
-    ub = plan.solve(plan.incident(src, frc), rtol=RTOL, maxit=2000).x
-    torch.cuda.synchronize()
-    t_ub = time.perf_counter() - t0
-    print(f"[bench] background solve of {len(src)} systems: {t_ub:.2f} s", file=sys.stderr, flush=True)
-    m0v = w["m0"].ravel()
-    r = plan.frechet_rel(ub, torch.as_tensor(w["dq_true"], dtype=torch.float32).cuda(), m0v, rtol=RTOL)
-    times = {}
-    for n in (1, 2):
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        _, hist = plan.normal_cg(ub, r, m0v, niter=n, lam=w["lam"], reg=w["reg"], rtol=RTOL)
-        torch.cuda.synchronize()
-        times[n] = time.perf_counter() - t
-        print(f"[bench] normal CG, {n} iteration(s): {times[n]:.2f} s, residual history {hist}",
+    nref = max(a.cg_iters, 2)
+    times, q64, hist64, t_ub, tuned, nsys = _normal_step(w, a, "c64", sorted({1, 2, nref}), RTOL)
+    ref = None
+    if a.fp64_reference:
+        _, q128, hist128, t_ub128, _, _ = _normal_step(w, a, "c128", [nref], 1e-10)
+        ref = dict(cg_iters=nref, rel_error_q=float(np.linalg.norm((q64 - q128).numpy()) /
+                                                    np.linalg.norm(q128.numpy())),
+                   rel_error_history=float(np.linalg.norm(hist64 - hist128) / np.linalg.norm(hist128)),
+                   s_background_solve_c128=round(t_ub128, 2), rtol_c128=1e-10)
+        print(f"[bench] complex64 vs complex128 GPU run after {nref} CG iterations: {ref}",
               file=sys.stderr, flush=True)
     it = times[2] - times[1]
     out = dict(metric=METRIC, value=round(1.0 / it, 4), unit="CG iterations/s", n_gpus=1, steps=1, warmup=0,
@@ -323,9 +348,9 @@ def normal_cg(a):
                dtype="c64", data="synthetic",
                config=dict(workload="1024x1024 VTI (dx 5 m), 128 surface forces x (4, 7, 10) Hz, 201 receivers: "
                                     "one CG iteration of the Tikhonov normal equation (L = I, lambda 1e-3)",
-                           nsys=int(len(src)), rtol=RTOL),
+                           nsys=int(nsys), rtol=RTOL),
                s_background_solve=round(t_ub, 2), s_cg_1=round(times[1], 2), s_cg_2=round(times[2], 2),
-               krylov=a.krylov, autotune=tuned)
+               krylov=a.krylov, autotune=tuned, fp64_gpu_reference=ref)
     print(json.dumps(out), flush=True)
     return 0
 
@@ -368,6 +393,9 @@ def main(argv=None):
     ap.add_argument("--cgs1", action="store_true", help="GMRES without the re-orthogonalisation pass")
     ap.add_argument("--cgs2", action="store_true", help="GMRES with the re-orthogonalisation pass")
     ap.add_argument("--workload", choices=["vti256x16", "multigrid", "jacobian", "normal"], default="vti256x16")
+    ap.add_argument("--fp64-reference", action="store_true",
+                    help="normal workload: rerun the step in complex128 and report the complex64 error")
+    ap.add_argument("--cg-iters", type=int, default=2, help="normal workload: CG iterations of the compared run")
     ap.add_argument("--passes-only", action="store_true",
                     help="only the per-pass kernel launches and the 1 GiB copy (for counter runs)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
