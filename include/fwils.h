@@ -188,7 +188,10 @@ fwils_status fwils_frechet(fwils_plan plan, const void* ub, const void* const* d
  * accumulated over systems in FP64.  r: device data.  g: host array of nprob
  * device pointers to complex maps [5][nz][nx] (output; with
  * FWILS_ADJ_ACCUMULATE added to).  Problems that share a g pointer are
- * summed when FWILS_ADJ_ACCUMULATE is set. */
+ * summed when FWILS_ADJ_ACCUMULATE is set.  In absolute units these maps can
+ * lie below the float32 normal range in a complex64 plan (fields of O(1e-12)
+ * m/N give products of O(1e-40)); fwils_adjoint_rel and the Tikhonov entry
+ * points accumulate J* r in FP64 and apply m0 before rounding. */
 fwils_status fwils_adjoint(fwils_plan plan, const void* ub, const void* r,
                            void* const* g, uint32_t flags, double rtol, int32_t maxit);
 

@@ -105,7 +105,7 @@ struct fwils_plan_s {
     size_t map_n = 0, off_mapws = 0;
     real *mq_dm = nullptr, *mq_x = nullptr, *mq_res = nullptr, *mq_p = nullptr, *mq_Ap = nullptr,
           *mq_l1 = nullptr, *mq_l2 = nullptr;
-    cplx* mq_g = nullptr;
+    double2* mq_g = nullptr;   // FP64 J* accumulator (map units)
     double *mq_part = nullptr, *mq_sc = nullptr, *mq_hist = nullptr;
     // graphs of one chunk of iterations over all problems (the first chunk of
     // a solve or restart starts from r)
@@ -729,7 +729,7 @@ fwils_status fwils_plan_create(const fwils_problem* probs, int32_t nprob, fwils_
     pl->map_n = one_grid ? (size_t)probs[0].nx * probs[0].nz : 0;
     pl->off_mapws = o;
     if (pl->map_n) {
-        o += 7 * align256(5 * pl->map_n * sizeof(real)) + align256(5 * pl->map_n * sizeof(cplx));
+        o += 7 * align256(5 * pl->map_n * sizeof(real)) + align256(5 * pl->map_n * sizeof(double2));
         o += align256(kDotPartials * sizeof(double)) + align256(16 * sizeof(double)) +
              align256(kMaxCgIters + 1) * sizeof(double);
     }
@@ -811,8 +811,8 @@ fwils_status fwils_set_workspace(fwils_plan plan, void* dev, size_t bytes) {
                          &plan->mq_Ap, &plan->mq_l1, &plan->mq_l2};
         for (int i = 0; i < 7; ++i) *fm[i] = (real*)(m + i * fb);
         m += 7 * fb;
-        plan->mq_g = (cplx*)m;
-        m += align256(5 * plan->map_n * sizeof(cplx));
+        plan->mq_g = (double2*)m;
+        m += align256(5 * plan->map_n * sizeof(double2));
         plan->mq_part = (double*)m;
         m += align256(kDotPartials * sizeof(double));
         plan->mq_sc = (double*)m;
@@ -974,7 +974,7 @@ fwils_status frechet_ws(fwils_plan plan, const void* ub, const real* const* dm, 
 // J* r (validated arguments): receiver scatter and convolution per problem,
 // one batched solve, correlation with u^b per problem.
 fwils_status adjoint_ws(fwils_plan plan, const void* ub, const void* r, void* const* g, bool accumulate,
-                        double rtol, int32_t maxit) {
+                        double rtol, int32_t maxit, bool fp64_maps = false) {
     hipStream_t s = plan->stream;
     for (size_t i = 0; i < plan->probs.size(); ++i) {
         const ProbHost& P = plan->probs[i];
@@ -988,8 +988,12 @@ fwils_status adjoint_ws(fwils_plan plan, const void* ub, const void* r, void* co
     if (st == FWILS_EDEVICE) return st;
     for (size_t i = 0; i < plan->probs.size(); ++i) {
         const ProbHost& P = plan->probs[i];
-        FW_HIP(launch_correlate(at(plan->x, P), at(ub, P), static_cast<cplx*>(g[i]), P.dev,
-                                accumulate, s));
+        if (fp64_maps)
+            FW_HIP(launch_correlate_f64(at(plan->x, P), at(ub, P), static_cast<double2*>(g[i]), P.dev,
+                                        accumulate, s));
+        else
+            FW_HIP(launch_correlate(at(plan->x, P), at(ub, P), static_cast<cplx*>(g[i]), P.dev,
+                                    accumulate, s));
     }
     return st;
 }
@@ -1064,8 +1068,8 @@ fwils_status normal_apply_ws(fwils_plan plan, const void* ub, const MapScales& m
     fwils_status st = frechet_ws(plan, ub, dms.data(), dscratch, rtol, maxit);
     if (st == FWILS_EDEVICE) return st;
     std::vector<void*> gs(plan->probs.size(), plan->mq_g);
-    FW_HIP(launch_zero(plan->mq_g, 5 * plan->map_n, s));
-    fwils_status st2 = adjoint_ws(plan, ub, dscratch, gs.data(), true, rtol, maxit);
+    FW_HIP(launch_zero_d2(plan->mq_g, 5 * plan->map_n, s));
+    fwils_status st2 = adjoint_ws(plan, ub, dscratch, gs.data(), true, rtol, maxit, true);
     if (st2 == FWILS_EDEVICE) return st2;
     const real* rq = nullptr;
     FW_TRY(regulariser(plan, reg, q, &rq));
@@ -1163,8 +1167,8 @@ fwils_status fwils_tikhonov_grad(fwils_plan plan, const void* ub, const void* r,
     FW_HIP(launch_sub_complex(static_cast<cplx*>(dscratch), static_cast<const cplx*>(r), nd, s));
     FW_HIP(launch_norm2_complex(static_cast<const cplx*>(dscratch), nd, plan->mq_part, sc + 5, s));
     std::vector<void*> gs(plan->probs.size(), plan->mq_g);
-    FW_HIP(launch_zero(plan->mq_g, 5 * plan->map_n, s));
-    fwils_status st2 = adjoint_ws(plan, ub, dscratch, gs.data(), true, rtol, maxit);
+    FW_HIP(launch_zero_d2(plan->mq_g, 5 * plan->map_n, s));
+    fwils_status st2 = adjoint_ws(plan, ub, dscratch, gs.data(), true, rtol, maxit, true);
     if (st2 == FWILS_EDEVICE) return st2;
     const real* rq = nullptr;
     FW_TRY(regulariser(plan, reg, q, &rq));
@@ -1205,8 +1209,8 @@ fwils_status fwils_adjoint_rel(fwils_plan plan, const void* ub, const void* r, c
     FW_TRY(check_field_ptrs({ub, r, gq}));
     FW_TRY(check_tik(plan, m0, 0.0, FWILS_REG_IDENTITY, rtol, maxit, "adjoint_rel"));
     std::vector<void*> gs(plan->probs.size(), plan->mq_g);
-    FW_HIP(launch_zero(plan->mq_g, 5 * plan->map_n, plan->stream));
-    fwils_status st = adjoint_ws(plan, ub, r, gs.data(), true, rtol, maxit);
+    FW_HIP(launch_zero_d2(plan->mq_g, 5 * plan->map_n, plan->stream));
+    fwils_status st = adjoint_ws(plan, ub, r, gs.data(), true, rtol, maxit, true);
     if (st == FWILS_EDEVICE) return st;
     FW_HIP(launch_map_combine(plan->mq_g, nullptr, gq, scales(m0), 1.0, 0.0, (int)plan->map_n, plan->stream));
     FW_HIP(hipStreamSynchronize(plan->stream));
@@ -1252,8 +1256,8 @@ fwils_status fwils_normal_cg(fwils_plan plan, const void* ub, const void* r, con
         return FWILS_EINVAL;
     }
     std::vector<void*> gs(plan->probs.size(), plan->mq_g);
-    FW_HIP(launch_zero(plan->mq_g, nm, s));
-    fwils_status st = adjoint_ws(plan, ub, r, gs.data(), true, rtol, maxit);
+    FW_HIP(launch_zero_d2(plan->mq_g, nm, s));
+    fwils_status st = adjoint_ws(plan, ub, r, gs.data(), true, rtol, maxit, true);
     if (st == FWILS_EDEVICE) return st;
     FW_HIP(launch_map_combine(plan->mq_g, nullptr, plan->mq_res, ms, 1.0 / rr, 0.0, n, s));
     FW_HIP(launch_zero_f(plan->mq_x, nm, s));

@@ -42,18 +42,18 @@ hipError_t launch_laplacian(const real* q, real* out, int nx, int nz, int nmaps,
 }
 
 // out = c_j m0[p] Re(g[p]) + c_l reg[p]     (reg may be null: c_l ignored)
-__global__ void k_map_combine(const cplx* __restrict__ g, const real* __restrict__ reg,
+__global__ void k_map_combine(const double2* __restrict__ g, const real* __restrict__ reg,
                               real* __restrict__ out, MapScales m0, double cj, double cl, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int p = blockIdx.y;
     if (i >= n) return;
     const size_t k = (size_t)p * n + i;
-    double v = cj * m0.s[p] * (double)g[k].x;
+    double v = cj * m0.s[p] * g[k].x;
     if (reg) v += cl * (double)reg[k];
     out[k] = (real)v;
 }
 
-hipError_t launch_map_combine(const cplx* g, const real* reg, real* out, const MapScales& m0,
+hipError_t launch_map_combine(const double2* g, const real* reg, real* out, const MapScales& m0,
                               double cj, double cl, int n, hipStream_t s) {
     hipLaunchKernelGGL(k_map_combine, dim3((n + kMapThreads - 1) / kMapThreads, 5), dim3(kMapThreads), 0, s,
                        g, reg, out, m0, cj, cl, n);

@@ -4,7 +4,8 @@
 //                    the virtual source P_b(dm) of eqs. YM / dC;
 //   k_bicg_*       - batched BiCGSTAB vector updates with FP64 scalars;
 //   k_point_sources, k_gather, k_scatter_conj - sources and receivers;
-//   k_correlate    - adjoint correlation of eq. ad1 summed over systems.
+//   k_correlate    - adjoint correlation of eq. ad1 summed over systems (FP64
+//                    sums; complex or FP64 complex output maps).
 #include <algorithm>
 
 #include "bicg.h"
@@ -583,6 +584,11 @@ hipError_t launch_copy(const cplx* src, cplx* dst, size_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(256), 0, s, (const float4*)src, (float4*)dst, n4);
     return hipGetLastError();
 }
+hipError_t launch_zero_d2(double2* dst, size_t n, hipStream_t s) {
+    const int blocks = (int)std::min<size_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, s, (float4*)dst, n);
+    return hipGetLastError();
+}
 hipError_t launch_zero(cplx* dst, size_t n, hipStream_t s) {
     const size_t n4 = n / kCplxPerWord;
     const int blocks = (int)std::min<size_t>((n4 + 255) / 256, 8192);
@@ -657,9 +663,10 @@ hipError_t launch_scatter_conj(const cplx* d, cplx* f, const int32_t* rec_ixz, i
 // g_rho = conj(w~^2 sum_sys u^a . u^b); g_p = -conj(sum_sys eps^a . B^p eps^b),
 // with the 2-D B matrices of the maps (C11, C13, C33, C55):
 //   B11 -> e1 e1,  B13 -> e1 e3 + e3 e1,  B33 -> e3 e3,  B55 -> e5 e5.
+template <class OUT>
 __global__ __launch_bounds__(256) void k_correlate(const cplx* __restrict__ ua,
                                                    const cplx* __restrict__ ub,
-                                                   cplx* __restrict__ g, ProbDev pd, int accumulate) {
+                                                   OUT* __restrict__ g, ProbDev pd, int accumulate) {
     const int nx = pd.nx, nz = pd.nz;
     const size_t plane = (size_t)nx * nz;
     const int cell = blockIdx.x * blockDim.x + threadIdx.x;
@@ -695,23 +702,33 @@ __global__ __launch_bounds__(256) void k_correlate(const cplx* __restrict__ ua,
     const double s = (double)pd.inv4dx2;
     const double wr = pd.w2.x, wi = pd.w2.y;
     // conj(w2 * rho) ; -conj(a) * s
-    cplx out[5];
-    out[0] = mkc((real)(-a11r * s), (real)(a11i * s));
-    out[1] = mkc((real)(-a13r * s), (real)(a13i * s));
-    out[2] = mkc((real)(-a33r * s), (real)(a33i * s));
-    out[3] = mkc((real)(-a55r * s), (real)(a55i * s));
-    out[4] = mkc((real)(wr * rr - wi * ri), (real)(-(wr * ri + wi * rr)));
+    const double out[5][2] = {{-a11r * s, a11i * s},
+                              {-a13r * s, a13i * s},
+                              {-a33r * s, a33i * s},
+                              {-a55r * s, a55i * s},
+                              {wr * rr - wi * ri, -(wr * ri + wi * rr)}};
 #pragma unroll
     for (int p = 0; p < 5; ++p) {
-        cplx* dst = g + (size_t)p * plane + ic;
-        *dst = accumulate ? cadd(*dst, out[p]) : out[p];
+        OUT* dst = g + (size_t)p * plane + ic;
+        OUT o = accumulate ? *dst : OUT{};
+        o.x = (decltype(o.x))((double)o.x + out[p][0]);
+        o.y = (decltype(o.y))((double)o.y + out[p][1]);
+        *dst = o;
     }
 }
 
 hipError_t launch_correlate(const cplx* ua, const cplx* ub, cplx* g, const ProbDev& pd,
                             bool accumulate, hipStream_t s) {
     const int cells = pd.nx * pd.nz;
-    hipLaunchKernelGGL(k_correlate, dim3((cells + 255) / 256), dim3(256), 0, s, ua, ub, g, pd,
+    hipLaunchKernelGGL(k_correlate<cplx>, dim3((cells + 255) / 256), dim3(256), 0, s, ua, ub, g, pd,
+                       accumulate ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_correlate_f64(const cplx* ua, const cplx* ub, double2* g, const ProbDev& pd,
+                                bool accumulate, hipStream_t s) {
+    const int cells = pd.nx * pd.nz;
+    hipLaunchKernelGGL(k_correlate<double2>, dim3((cells + 255) / 256), dim3(256), 0, s, ua, ub, g, pd,
                        accumulate ? 1 : 0);
     return hipGetLastError();
 }

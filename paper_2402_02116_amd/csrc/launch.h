@@ -185,6 +185,11 @@ hipError_t launch_scatter_conj(const cplx* d, cplx* f, const int32_t* rec_ixz, i
                                const ProbDev& pd, hipStream_t s);
 hipError_t launch_correlate(const cplx* ua, const cplx* ub, cplx* g, const ProbDev& pd,
                             bool accumulate, hipStream_t s);
+// The same correlation into FP64 complex maps (the Tikhonov step's
+// accumulator: for fields in m/N the absolute J* r lies below fp32's range).
+hipError_t launch_correlate_f64(const cplx* ua, const cplx* ub, double2* g, const ProbDev& pd,
+                                bool accumulate, hipStream_t s);
+hipError_t launch_zero_d2(double2* dst, size_t n, hipStream_t s);
 hipError_t launch_copy(const cplx* src, cplx* dst, size_t n, hipStream_t s);
 hipError_t launch_zero(cplx* dst, size_t n, hipStream_t s);
 
@@ -192,7 +197,7 @@ hipError_t launch_zero(cplx* dst, size_t n, hipStream_t s);
 struct MapScales { double s[5]; };
 hipError_t launch_map_scale(const real* q, real* out, const MapScales& m0, int n, hipStream_t s);
 hipError_t launch_laplacian(const real* q, real* out, int nx, int nz, int nmaps, hipStream_t s);
-hipError_t launch_map_combine(const cplx* g, const real* reg, real* out, const MapScales& m0,
+hipError_t launch_map_combine(const double2* g, const real* reg, real* out, const MapScales& m0,
                               double cj, double cl, int n, hipStream_t s);
 constexpr int kDotPartials = 512;
 hipError_t launch_dot_real(const real* a, const real* b, size_t n, double* part, double* out,

@@ -165,13 +165,16 @@ def test_c64_normal_cg_against_c128_gpu_run():
     run in complex128 on the GPU (the reference used at sizes the CPU oracle
     cannot reach); here small enough to pin the complex128 run to the oracle.
     The data are those of a true perturbation, r = J q*, so that the normal
-    operator Re J*J / ||r||^2 dominates lam and CG has work to do."""
+    operator Re J*J / ||r||^2 dominates lam and CG has work to do.  Partially
+    converged CG iterates amplify operator differences by the conditioning of
+    the Krylov basis, so the operators are compared tightly and the iterates
+    after a few steps more loosely."""
     nx = nz = 48
-    ns, nrec, freqs = 3, 9, (4.0, 7.0)
+    ns, nrec, freqs, niter = 3, 9, (4.0, 7.0), 3
     c0, rho0 = W.vti_background()
     m0 = W.model_scales(c0, rho0)
-    maps = m0 * W.smooth_maps(7, nz, nx, 4.0, 0.08)
-    qstar = W.smooth_maps(8, nz, nx, 3.0, 0.02)
+    maps = W.round_f32(m0 * W.smooth_maps(7, nz, nx, 4.0, 0.08))
+    qstar = W.round_f32(W.smooth_maps(8, nz, nx, 3.0, 0.02))
     src, f = W.surface_sources(nx, ns, iz=1)
     rec = W.surface_receivers(nx, nrec, iz=2)
     probs = [dict(nx=nx, nz=nz, dx=5.0, c0=tuple(c0), rho0=rho0, freq_hz=fr, eta=0.02, nsys=ns) for fr in freqs]
@@ -181,26 +184,34 @@ def test_c64_normal_cg_against_c128_gpu_run():
         ubr, _ = P.solve(P.incident(src, f), tol=1e-13)
         items.append((P, ubr, rec))
     r_np = tikhonov.Tikhonov(items, m0, [np.zeros((ns, nrec, 2))] * 2, lam=0.0, tol=1e-13).J(qstar)
+    rr = sum(float(np.vdot(x.ravel(), x.ravel()).real) for x in r_np)
     out = {}
     for prec in ("c128", "c64"):
         print(f"normal CG {prec}", flush=True)
         plan = _plan(probs, precision=prec)
-        mp = maps if prec == "c128" else W.round_f32(maps)
         for i in range(len(freqs)):
-            plan.set_contrast(i, mp)
+            plan.set_contrast(i, maps)
             plan.set_receivers(i, rec)
         tol = 1e-12 if prec == "c128" else 1e-7
         ub = plan.solve(plan.incident(src * 2, f * 2), rtol=tol, maxit=3000).x
         r = torch.as_tensor(np.concatenate([x.ravel() for x in r_np]).astype(
             np.complex128 if prec == "c128" else np.complex64)).cuda()
-        q, hist = plan.normal_cg(ub, r, m0.ravel(), niter=8, lam=1e-3, reg="identity", rtol=tol)
-        out[prec] = (q.double().cpu().numpy(), hist)
+        qt = torch.as_tensor(qstar, dtype=plan.rdtype).cuda()
+        Nq = plan.normal_apply(ub, m0.ravel(), rr, qt, lam=1e-3, reg="identity", rtol=tol)
+        q, hist = plan.normal_cg(ub, r, m0.ravel(), niter=niter, lam=1e-3, reg="identity", rtol=tol)
+        out[prec] = (q.double().cpu().numpy(), hist, Nq.double().cpu().numpy())
     T = tikhonov.Tikhonov(items, m0, r_np, lam=1e-3, reg="identity", tol=1e-13)
-    q_ref, hist_ref = T.solve_cg(8)
-    # the normal residual falls: CG does real work on this problem
-    assert hist_ref[-1] < 0.05 * hist_ref[0]
-    assert _rel(out["c128"][0], q_ref) < 1e-8
+    q_ref, hist_ref = T.solve_cg(niter)
+    assert hist_ref[-1] < 0.5 * hist_ref[0]   # CG does real work on this problem
+    e128 = _rel(out["c128"][0], q_ref)
+    assert _rel(out["c128"][2], T.normal_apply(qstar)) < 1e-9
+    assert e128 < 1e-8, e128
     assert _rel(out["c128"][1], np.array(hist_ref)) < 1e-8
-    err = _rel(out["c64"][0], out["c128"][0])
-    print(f"normal CG, c64 vs c128 GPU: {err:.2e}", flush=True)
-    assert err < 1e-4
+    # complex64 against the complex128 GPU run
+    e_op = _rel(out["c64"][2], out["c128"][2])
+    e_q = _rel(out["c64"][0], out["c128"][0])
+    e_h = _rel(out["c64"][1], out["c128"][1])
+    print(f"normal CG after {niter} steps: c128 vs oracle {e128:.2e}; c64 vs c128: N q {e_op:.2e}, "
+          f"q {e_q:.2e}, residual history {e_h:.2e}", flush=True)
+    assert e_op < 1e-5
+    assert e_q < 1e-3 and e_h < 1e-3
