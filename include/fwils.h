@@ -322,7 +322,8 @@ typedef struct {
     int32_t row_points;    /* row-transform points per thread (radix sequence) */
     int32_t col_points;    /* column-transform points per thread */
     int32_t col_width;     /* columns per column workgroup (power of two) */
-    int32_t col_shared;    /* 1: the two components share one LDS buffer */
+    int32_t col_shared;    /* 1: the two components share one LDS buffer;
+                              2: separate threads transform them          */
     int32_t stencil_rows;  /* contrast-stencil tile height: 4, 8 or 16 */
     int32_t stencil_sys;   /* systems per stencil workgroup, 0 = from the grid size */
     int32_t fused_points;  /* 0: contrast stencil and forward row transform as two

@@ -301,6 +301,77 @@ __global__ __launch_bounds__(512) void k_cols(cplx* __restrict__ data, ProbDev p
 }
 
 
+// The Green-multiply column pass with the two field components on separate
+// threads (twice the threads of k_cols, half the registers each): thread
+// (comp, t, c) transforms component comp of column c; after the forward
+// transform the components meet in LDS for the 2 x 2 Green multiply, and
+// each thread keeps the output of its own component.
+template <int N, int P>
+__global__ __launch_bounds__(512) void k_cols_split(cplx* __restrict__ data, ProbDev pd, int W,
+                                                     const SysState* __restrict__ st,
+                                                     const cplx* __restrict__ tw) {
+    using S = FftShape<N, P>;
+    constexpr int T = S::T;
+    constexpr int PL = PaddedLen<N>::value;
+    extern __shared__ cplx lds_dyn[];
+
+    const int nx = pd.nx;
+    const int tid = threadIdx.x;
+    const int wt = W * T;
+    const int comp = tid / wt;                 // blockDim.x == 2 W T
+    const int c = tid % W, t = (tid - comp * wt) / W;
+    const int ntile = nx / W;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int sys = blk / ntile;
+    const int x0 = (blk % ntile) * W;
+    if (st != nullptr && st[sys].status != ST_RUNNING) return;
+
+    const size_t plane = (size_t)N * nx;
+    cplx* base = data + (size_t)sys * 2 * plane + comp * plane + x0 + c;
+    cplx v[1][P];
+#pragma unroll
+    for (int m = 0; m < P; ++m) v[0][m] = base[(size_t)(t + T * m) * nx];
+    const ColLds own{lds_dyn + (size_t)comp * PL * W + c, W, PL};
+    const ColLds other{lds_dyn + (size_t)(1 - comp) * PL * W + c, W, PL};
+    fft_run<N, P, false, 1>(v, t, tw, own);
+
+    // exchange the transformed components through LDS
+    __syncthreads();   // the last transform exchange is read
+#pragma unroll
+    for (int m = 0; m < P; ++m) own(0, t + T * m) = v[0][m];
+    __syncthreads();
+    const int ix = x0 + c;
+    const int sx = fft_signed(ix, nx);
+    const bool central = pd.symbol == 1;
+    const real kx = central ? rsinpi(2.0f * (real)sx / (real)nx) / pd.dx : (real)sx * pd.dkx;
+    const real kxo = ((nx % 2) == 0 && ix == nx / 2) ? 0.f : kx;
+    const real kx2 = kx * kx;
+    const real axx = pd.gc11 * kx2, azz = pd.gc55 * kx2, axz = pd.gc1355 * kxo;
+    const real rdx = 1.0f / pd.dx;
+    // the partner's values first, into registers (a select between a register
+    // array element and an LDS address would force the array into memory)
+    cplx o[P];
+#pragma unroll
+    for (int m = 0; m < P; ++m) o[m] = other(0, t + T * m);
+#pragma unroll
+    for (int m = 0; m < P; ++m) {
+        const int iz = t + T * m;
+        const int sz = fft_signed(iz, N);
+        const real kz = central ? -tw[iz].y * rdx : (real)sz * pd.dkz;
+        const real kzo = ((N % 2) == 0 && iz == N / 2) ? 0.f : kz;
+        const cplx mine = v[0][m], theirs = o[m];
+        cplx bx = comp == 0 ? mine : theirs;
+        cplx bz = comp == 0 ? theirs : mine;
+        green_mul(bx, bz, axx + pd.gc55 * kz * kz, azz + pd.gc33 * kz * kz, axz * kzo, pd.ga, pd.gscale);
+        v[0][m] = comp == 0 ? bx : bz;
+        __builtin_amdgcn_sched_barrier(0);   // one point at a time: bounded registers
+    }
+    __syncthreads();   // every partner value is read before the inverse writes LDS
+    fft_run<N, P, true, 1>(v, t, tw, own);
+#pragma unroll
+    for (int m = 0; m < P; ++m) st_wt(base + (size_t)(t + T * m) * nx, v[0][m]);
+}
+
 // ----------------------------------------------------- launch helpers ----
 // Dynamic LDS above the default limit must be enabled once per kernel.
 template <class K>
@@ -322,6 +393,17 @@ inline hipError_t rows_launch(const cplx* in, cplx* out, const cplx* u, const cp
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_rows<N, P, INV, EPI>), dim3(blocks), dim3(g.threads), lds, s, in, out, u, aux,
                        part, nrows, rps, g.F, const_cast<SysState*>(st), tw, ge ? *ge : gz);
+    return hipGetLastError();
+}
+
+template <int N, int P>
+inline hipError_t cols_split_launch(cplx* data, const ProbDev& pd, int W, const SysState* st,
+                                    const cplx* tw, hipStream_t s) {
+    const ColGeom g = col_geom(N, pd.nx, ColCfg{P, W, 2});
+    const int blocks = pd.nsys * (pd.nx / W);
+    hipError_t e = allow_lds(k_cols_split<N, P>, g.lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_cols_split<N, P>), dim3(blocks), dim3(g.threads), g.lds, s, data, pd, W, st, tw);
     return hipGetLastError();
 }
 

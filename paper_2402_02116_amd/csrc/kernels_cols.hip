@@ -1,5 +1,5 @@
 // Column-pass launchers: the Green-multiply pass in every (size, points per
-// thread, LDS sharing) variant; the plain forward / inverse column
+// thread, LDS sharing or component split) variant; the plain forward / inverse column
 // transforms (2-D FFT entry point) in the default variant.
 #include "fft_kernels.h"
 
@@ -25,7 +25,8 @@ hipError_t launch_cols(int mode, const ColCfg& c, cplx* data, const ProbDev& pd,
 #define FW_CASE(N, PP)                                                                          \
     if (n == N && c.P == PP) {                                                                  \
         if (mode == COL_GREEN)                                                                  \
-            return c.seq ? cols_launch<N, PP, COL_GREEN, true>(data, pd, c.W, st, t, s)         \
+            return c.seq == 2 ? cols_split_launch<N, PP>(data, pd, c.W, st, t, s)               \
+                 : c.seq ? cols_launch<N, PP, COL_GREEN, true>(data, pd, c.W, st, t, s)          \
                          : cols_launch<N, PP, COL_GREEN, false>(data, pd, c.W, st, t, s);       \
         if constexpr (PP == ((N % 3 == 0) ? 12 : 8)) {                                         \
             if (mode == COL_FWD) return cols_launch<N, PP, COL_FWD, true>(data, pd, c.W, st, t, s); \

@@ -92,6 +92,12 @@ ColGeom col_geom(int nz, int nx, const ColCfg& c) {
     (void)nx;
     const int T = nz / c.P;
     ColGeom g;
+    if (c.seq == 2) {   // both components' columns in LDS, no idle threads
+        g.threads = 2 * c.W * T;
+        g.slots = c.W;
+        g.lds = (size_t)padded_len(nz) * c.W * 2 * sizeof(cplx);
+        return g;
+    }
     g.threads = ((c.W * T + 63) / 64) * 64;
     g.slots = c.W + (g.threads > c.W * T ? 1 : 0);   // idle threads need a private dummy slot
     g.lds = (size_t)padded_len(nz) * g.slots * (c.seq ? 1 : 2) * sizeof(cplx);
@@ -101,9 +107,10 @@ ColGeom col_geom(int nz, int nx, const ColCfg& c) {
 bool col_cfg_ok(int nz, int nx, const ColCfg& c) {
     if (!fft_size_supported(nz) || c.P <= 0 || nz % c.P != 0) return false;
     if (c.P != col_points_default(nz) && c.P != col_points_alt(nz)) return false;
-    if (c.seq != 0 && c.seq != 1) return false;
+    if (c.seq < 0 || c.seq > 2) return false;
     if (c.W < 1 || c.W > 64 || nx % c.W != 0 || (c.W & (c.W - 1)) != 0) return false;
     const ColGeom g = col_geom(nz, nx, c);
+    if (c.seq == 2) return g.threads % 64 == 0 && g.threads <= 512 && g.lds <= kMaxLds;
     return g.threads <= 512 && g.lds <= kMaxLds;
 }
 
@@ -121,7 +128,7 @@ int col_candidates(int nz, int nx, ColCfg* out, int cap) {
     const int ps[2] = {col_points_default(nz), col_points_alt(nz)};
     for (int i = 0; i < (ps[1] == ps[0] ? 1 : 2); ++i) {
         const int P = ps[i];
-        for (int seq = 1; seq >= 0; --seq)
+        for (int seq = 2; seq >= 0; --seq)
             for (int W = 4; W <= 32; W *= 2) {
                 const ColCfg c{P, W, seq};
                 if (col_cfg_ok(nz, nx, c) && k < cap) out[k++] = c;

@@ -38,7 +38,8 @@ constexpr size_t kMaxLds = 160 * 1024;   // LDS per workgroup on gfx950
 struct ColCfg {
     int P;     // points per thread
     int W;     // columns per block
-    int seq;   // 1: the two components share one LDS buffer
+    int seq;   // 1: the two components share one LDS buffer; 2: they are
+               // transformed by separate threads (Green pass only)
 };
 struct StCfg {
     int TZ;    // tile height (rows)
