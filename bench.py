@@ -69,8 +69,17 @@ def _kernel_source_hash():
 PASS_MATCH = [lambda n: (n.startswith("void fw::c64::k_body_force<") or "c64::(anonymous namespace)::k_srows<" in n)
               and ", 0>(" in n,
               lambda n: n.startswith("void fw::c64::k_rows<") and ", false, 0>" in n,
-              lambda n: n.startswith("void fw::c64::k_cols<") and ", 0, " in n,
+              lambda n: (n.startswith("void fw::c64::k_cols<") and ", 0, " in n)
+              or n.startswith("void fw::c64::k_cols_split<"),
               lambda n: n.startswith("void fw::c64::k_rows<") and ", true, 1>" in n]
+
+
+def _instance_name(kernel):
+    """'fw::c64::k_rows<256, 16, false, 0>' from the demangled name with its
+    parameter list (the namespace part may itself contain parentheses)."""
+    import re
+    m = re.match(r"(?:void )?(.*?>)\(", kernel)
+    return m.group(1) if m else kernel
 
 
 def summarize_counters(fetch_csv, write_csv, cmd):
@@ -102,7 +111,7 @@ def summarize_counters(fetch_csv, write_csv, cmd):
             if not match(n) or n not in write:
                 continue
             f, w = statistics.median(fetch[n]), statistics.median(write[n])
-            inst[n.split("(")[0].replace("void ", "")] = dict(
+            inst[_instance_name(n)] = dict(
                 fetch_kib=f, write_kib=w, launches=len(fetch[n]), hbm_bytes_per_launch=(f * sf + w * sw) * 1024.0)
         if inst:
             passes[str(k)] = dict(kernel=PASS_NAMES[k], instances=inst)
@@ -123,6 +132,8 @@ def _pass_instance(k, tuning, n=256):
     if k == 1:
         return f"fw::c64::k_rows<{n}, {tuning['row_points']}, false, 0>"
     if k == 2:
+        if tuning["col_shared"] == 2:
+            return f"fw::c64::k_cols_split<{n}, {tuning['col_points']}>"
         seq = "true" if tuning["col_shared"] else "false"
         return f"fw::c64::k_cols<{n}, {tuning['col_points']}, 0, {seq}>"
     return f"fw::c64::k_rows<{n}, {tuning['row_points']}, true, 1>"
