@@ -112,16 +112,16 @@ enum StencilStep : int { SS_SKIP = 0, SS_FULL = 1, SS_XONLY = 2 };
 // omega t, and a stopped system still receives its solution update
 // (SS_XONLY).  Returns SS_SKIP if the system stops (converged, limit,
 // breakdown) with nothing left to do; `writer` (one thread of one block per
-// system) records scalars and status.  Every thread of the block must call it
-// (block reduction).
-template <int VM>
+// system) records scalars and status.  Every thread of the block (NT threads)
+// must call it (block reduction); the totals do not depend on NT.
+template <int VM, int NT = 256>
 __device__ __forceinline__ int stencil_scalars(SysState* st, int sys, const double* part, int np, double* red,
                                                bool writer, cplx& c1, cplx& c2, cplx& c3, bool& fresh) {
     const SysState& z = st[sys];
     const int it = z.iter + 1;
     if constexpr (VM == VM_PX) {
         double q[kPartialNV];
-        sum_partials<kPartialNV, 256>(part + (size_t)sys * np * kPartialNV, np, q, red);
+        sum_partials<kPartialNV, NT, kPartialNV, 256>(part + (size_t)sys * np * kPartialNV, np, q, red);
         const OmegaStep o = omega_step(q);
         const dcomplex alpha{z.alpha_re, z.alpha_im};
         c2 = toc(o.omega);
@@ -156,7 +156,7 @@ __device__ __forceinline__ int stencil_scalars(SysState* st, int sys, const doub
         return SS_FULL;
     } else {
         double q[4];
-        sum_partials<4, 256>(part + (size_t)sys * np * kPartialNV, np, q, red);
+        sum_partials<4, NT, kPartialNV, 256>(part + (size_t)sys * np * kPartialNV, np, q, red);
         if constexpr (VM == VM_P) {
             if (bicg_stop(st, sys, q[2], writer)) return SS_SKIP;
             dcomplex rho_i{q[0], q[1]};

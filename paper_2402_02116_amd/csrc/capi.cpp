@@ -1509,8 +1509,11 @@ KernelCfg from_tuning(const fwils_tuning& t) {
 bool fuse_ok(const ProbHost& P, int fp) {
     if (fp == 0) return true;
     if (!row_points_ok(P.p.nx, fp)) return false;
-    const int F = srows_rows(P.p.nx, P.p.nz, fp);
-    return F > 0 && srows_lds(P.p.nx, F) <= kMaxLds;
+    for (int vm = VM_NONE; vm <= VM_PX; ++vm) {   // every mode the solver launches
+        const int F = srows_rows(P.p.nx, P.p.nz, fp, vm);
+        if (F == 0 || srows_lds(P.p.nx, F) > kMaxLds) return false;
+    }
+    return true;
 }
 
 bool cfg_ok(const ProbHost& P, const KernelCfg& k) {

@@ -160,14 +160,16 @@ __device__ __forceinline__ void block_allreduce(double (&acc)[NV], double* smem)
 
 // Sum the first NV doubles of np partial records (record i at
 // part[i * STRIDE]) in a fixed order; every thread of the block receives the
-// totals.
-template <int NV, int NT, int STRIDE = kPartialNV>
+// totals.  The first NR threads read the records (the others add zeros), so
+// blocks of any size NT >= NR get bit-identical totals.
+template <int NV, int NT, int STRIDE = kPartialNV, int NR = NT>
 __device__ __forceinline__ void sum_partials(const double* __restrict__ part, int np,
                                              double (&res)[NV], double* smem) {
     static_assert(NV <= STRIDE, "record too short");
+    static_assert(NR <= NT && NR % 64 == 0, "readers");
 #pragma unroll
     for (int k = 0; k < NV; ++k) res[k] = 0.0;
-    for (int i = threadIdx.x; i < np; i += NT) {
+    for (int i = threadIdx.x; threadIdx.x < NR && i < np; i += NR) {
 #pragma unroll
         for (int k = 0; k < NV; ++k) res[k] += part[(size_t)i * STRIDE + k];
     }

@@ -21,8 +21,8 @@ struct RowLdsF {
     __device__ __forceinline__ cplx& operator()(int, int pos) const { return p[lds_pad(pos)]; }
 };
 
-template <int N, int P, int VM>
-__global__ __launch_bounds__(256) void k_srows(const cplx* __restrict__ u, const cplx* __restrict__ a1,
+template <int N, int P, int VM, int NT>
+__global__ __launch_bounds__(NT) void k_srows(const cplx* __restrict__ u, const cplx* __restrict__ a1,
                                                const cplx* __restrict__ a2, cplx* __restrict__ wout,
                                                cplx* __restrict__ rhat, cplx* __restrict__ out,
                                                const real* __restrict__ maps, ProbDev pd, int F,
@@ -34,7 +34,7 @@ __global__ __launch_bounds__(256) void k_srows(const cplx* __restrict__ u, const
     constexpr int T = S::T;
     constexpr int PL = PaddedLen<N>::value;
     extern __shared__ cplx lds_dyn[];
-    __shared__ double red[4 * kPartialNV];
+    __shared__ double red[NT / 64 * kPartialNV];
 
     const int nz = pd.nz;
     const size_t plane = (size_t)N * nz;
@@ -59,7 +59,7 @@ __global__ __launch_bounds__(256) void k_srows(const cplx* __restrict__ u, const
     bool fresh = false;
     int step = SS_FULL;
     if constexpr (VM != VM_NONE) {
-        step = stencil_scalars<VM>(st, sys, part, np, red, z0 == 0 && threadIdx.x == 0, c1, c2, c3, fresh);
+        step = stencil_scalars<VM, NT>(st, sys, part, np, red, z0 == 0 && threadIdx.x == 0, c1, c2, c3, fresh);
         if (step == SS_SKIP) return;
     }
     const size_t so = (size_t)sys * 2 * plane;
@@ -89,13 +89,13 @@ __global__ __launch_bounds__(256) void k_srows(const cplx* __restrict__ u, const
     cplx* su = lds_dyn;                           // [2][HR][N]
     const int total = 2 * HR * N;
     constexpr int kB = VM == VM_PX ? 4 : 8;
-    for (int i0 = threadIdx.x; i0 < total; i0 += kB * 256) {
+    for (int i0 = threadIdx.x; i0 < total; i0 += kB * NT) {
         size_t gi[kB];
         bool ok[kB], own[kB];
         cplx f[kB], sv[kB], pv[kB], rv[kB], xv[kB];
 #pragma unroll
         for (int j = 0; j < kB; ++j) {
-            const int idx = i0 + j * 256;
+            const int idx = i0 + j * NT;
             ok[j] = idx < total;
             const int id = ok[j] ? idx : 0;
             const int c = id / (HR * N);
@@ -126,7 +126,7 @@ __global__ __launch_bounds__(256) void k_srows(const cplx* __restrict__ u, const
         }
 #pragma unroll
         for (int j = 0; j < kB; ++j)
-            if (ok[j]) su[i0 + j * 256] = f[j];
+            if (ok[j]) su[i0 + j * NT] = f[j];
         if constexpr (VM != VM_NONE) {
 #pragma unroll
             for (int j = 0; j < kB; ++j) {
@@ -243,17 +243,24 @@ __global__ __launch_bounds__(256) void k_srows(const cplx* __restrict__ u, const
 
 }  // namespace
 
-// Largest rows per block (a power of two <= 128 / T dividing nz) for n-point
-// rows with P points per thread; 0 when the fused kernel does not apply.
-int srows_rows(int nx, int nz, int P) {
+// Threads of the fused kernel: 512 (twice the rows per block, so a smaller
+// share of halo rows) for the heaviest input update, VM_PX, which reads four
+// vectors in the halo, where a thread's row segment is short enough; 256
+// otherwise (measured: no gain for the lighter modes).
+constexpr bool srows_wide(int nx, int P, int vm) { return vm == VM_PX && nx >= 256 && nx / P <= 32; }
+
+// Rows per block (a power of two <= threads / 2T dividing nz) for n-point
+// rows with P points per thread in stencil mode vm; 0 when the fused kernel
+// does not apply.
+int srows_rows(int nx, int nz, int P, int vm) {
 #ifdef FW_C128
-    (void)nx, (void)nz, (void)P;
+    (void)nx, (void)nz, (void)P, (void)vm;
     return 0;   // the complex128 build keeps the stencil and the row pass apart
 #endif
     if (nx > kSrowsMaxN || nx % P != 0) return 0;
     const int T = nx / P;
     if (T > 128) return 0;
-    int F = 128 / T;
+    int F = (srows_wide(nx, P, vm) ? 256 : 128) / T;
     while (F > 1 && nz % F != 0) F /= 2;
     return F;
 }
@@ -264,22 +271,29 @@ size_t srows_lds(int nx, int F) {
     return tile > fft ? tile : fft;
 }
 
-template <int N, int P, int VM>
-static hipError_t srows_launch(const StencilArgs& a, cplx* out, const ProbDev& pd, SysState* st,
-                               const cplx* tw, hipStream_t s) {
-    const int F = srows_rows(N, pd.nz, P);
+template <int N, int P, int VM, int NT>
+static hipError_t srows_launch_nt(const StencilArgs& a, cplx* out, const ProbDev& pd, SysState* st,
+                                  const cplx* tw, hipStream_t s) {
+    const int F = srows_rows(N, pd.nz, P, VM);
     if (F == 0) return hipErrorInvalidValue;
     const size_t lds = srows_lds(N, F);
     if (lds > kMaxLds) return hipErrorInvalidValue;
     if (lds > 65536) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_srows<N, P, VM>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_srows<N, P, VM, NT>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
     const int blocks = pd.nsys * (pd.nz / F);
-    hipLaunchKernelGGL((k_srows<N, P, VM>), dim3(blocks), dim3(256), lds, s, a.u, a.a1, a.a2, a.wout, a.rhat, out,
-                       a.maps, pd, F, st, a.part, a.np, tw, a.a3, a.xio, a.rout);
+    hipLaunchKernelGGL((k_srows<N, P, VM, NT>), dim3(blocks), dim3(NT), lds, s, a.u, a.a1, a.a2, a.wout, a.rhat,
+                       out, a.maps, pd, F, st, a.part, a.np, tw, a.a3, a.xio, a.rout);
     return hipGetLastError();
+}
+
+template <int N, int P, int VM>
+static hipError_t srows_launch(const StencilArgs& a, cplx* out, const ProbDev& pd, SysState* st,
+                               const cplx* tw, hipStream_t s) {
+    if constexpr (srows_wide(N, P, VM)) return srows_launch_nt<N, P, VM, 512>(a, out, pd, st, tw, s);
+    else return srows_launch_nt<N, P, VM, 256>(a, out, pd, st, tw, s);
 }
 
 template <int N, int P>
@@ -305,7 +319,7 @@ hipError_t launch_srows(int vm, int P, const StencilArgs& a, cplx* out, const Pr
     if (vm < 0 || vm > 3 || (vm != VM_NONE && !st) || ((vm == VM_P || vm == VM_PX) && !a.rhat) ||
         (vm == VM_PX && (!a.a3 || !a.xio || !a.rout)))
         return hipErrorInvalidValue;
-    if (!row_points_ok(pd.nx, P) || srows_rows(pd.nx, pd.nz, P) == 0) return hipErrorInvalidValue;
+    if (!row_points_ok(pd.nx, P) || srows_rows(pd.nx, pd.nz, P, vm) == 0) return hipErrorInvalidValue;
     const cplx* t = tw + twiddle_offset(pd.nx);
 #define FW_CASE(N, PP) \
     if (pd.nx == N && P == PP) return srows_vm<N, PP>(vm, a, out, pd, st, t, s);

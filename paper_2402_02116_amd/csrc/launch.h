@@ -129,7 +129,7 @@ hipError_t launch_stencil(int vm, const StCfg& c, const StencilArgs& a, const Pr
 // The stencil fused with the forward row transform: b (of the updated input,
 // vm as above, a.b unused) row-transformed into out.  Rows up to kSrowsMaxN.
 constexpr int kSrowsMaxN = 512;
-int srows_rows(int nx, int nz, int P);          // rows per block, 0 if unavailable
+int srows_rows(int nx, int nz, int P, int vm);  // rows per block in mode vm, 0 if unavailable
 size_t srows_lds(int nx, int F);
 hipError_t launch_srows(int vm, int P, const StencilArgs& a, cplx* out, const ProbDev& pd, SysState* st,
                         const cplx* tw, hipStream_t s);
