@@ -237,9 +237,39 @@ def multigrid(a):
                            cells_per_matvec=int(cells.sum())),
                time_to_1e6_ms=round(t_solve, 3), iters=[int(res.iters.min()), int(res.iters.max())],
                max_true_relres=float(res.relres.max()), autotune=tuning,
-               krylov=a.krylov if a.krylov == "bicgstab" else f"gmres({a.restart}, {'cgs1' if a.cgs1 else 'cgs2'})")
+               krylov=a.krylov if a.krylov == "bicgstab" else f"gmres({a.restart}, {'cgs1' if a.cgs1 else 'cgs2'})",
+               pass_rooflines=_pass_rooflines(plan))
     print(json.dumps(out), flush=True)
     return 0
+
+
+def _pass_rooflines(plan, reps=5):
+    """Per-pass kernel time (HIP events around back-to-back launches on the
+    plan's stream, all problems of the plan) and algorithmic HBM rate of one
+    matvec, as fractions of the 8 TB/s peak."""
+    import torch
+    u = torch.randn(plan.field_elems, dtype=plan.cdtype, device=plan.device)
+    Au = plan.new_field()
+    out = []
+    for k in range(4):
+        nbytes = 0.0
+        for i, p in enumerate(plan.problems):
+            cells, ns = p["nx"] * p["nz"], p["nsys"]
+            fused = plan.tuning(i)["fused_points"] != 0
+            if k == 1 and fused:
+                continue   # part of pass 0
+            nbytes += PASS_BYTES[k] * ns * cells + (MAP_BYTES_PER_CELL * cells if k == 0 else 0.0)
+        if nbytes == 0.0:
+            continue
+        for j in range(k):
+            plan.apply_pass(j, u, Au)
+        us = plan.time_pass(k, u, Au, reps)
+        gbs = nbytes / (us * 1e-6) / 1e9
+        out.append(dict(pass_=k, us=round(us, 1), gbs=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 3)))
+        print(f"[bench] pass {k}: {us:.1f} us, {gbs:.0f} GB/s algorithmic ({gbs / HBM_PEAK_GBS:.2f} of peak)",
+              file=sys.stderr, flush=True)
+    del u, Au
+    return [{("pass" if k == "pass_" else k): v for k, v in d.items()} for d in out]
 
 
 def _tik_plan(probs, rec, krylov, a, precision="c64"):
@@ -327,9 +357,11 @@ def _normal_step(w, a, precision, niters, rtol):
         print(f"[bench] {precision} normal CG, {n} iteration(s): {times[n]:.2f} s, residual history {hist}",
               file=sys.stderr, flush=True)
     q = q.double().cpu()
-    del plan, ub, r
+    del ub, r
+    rl = _pass_rooflines(plan) if precision == "c64" else None
+    del plan
     torch.cuda.empty_cache()
-    return times, q, hist, t_ub, tuned, len(src)
+    return times, q, hist, t_ub, tuned, len(src), rl
 
 
 def normal_cg(a):
@@ -343,10 +375,10 @@ def normal_cg(a):
     import workloads as W
     w = W.vti1024_normal()
     nref = max(a.cg_iters, 2)
-    times, q64, hist64, t_ub, tuned, nsys = _normal_step(w, a, "c64", sorted({1, 2, nref}), RTOL)
+    times, q64, hist64, t_ub, tuned, nsys, rooflines = _normal_step(w, a, "c64", sorted({1, 2, nref}), RTOL)
     ref = None
     if a.fp64_reference:
-        _, q128, hist128, t_ub128, _, _ = _normal_step(w, a, "c128", [nref], 1e-10)
+        _, q128, hist128, t_ub128, _, _, _ = _normal_step(w, a, "c128", [nref], 1e-10)
         ref = dict(cg_iters=nref, rel_error_q=float(np.linalg.norm((q64 - q128).numpy()) /
                                                     np.linalg.norm(q128.numpy())),
                    rel_error_history=float(np.linalg.norm(hist64 - hist128) / np.linalg.norm(hist128)),
@@ -361,7 +393,7 @@ def normal_cg(a):
                                     "one CG iteration of the Tikhonov normal equation (L = I, lambda 1e-3)",
                            nsys=int(nsys), rtol=RTOL),
                s_background_solve=round(t_ub, 2), s_cg_1=round(times[1], 2), s_cg_2=round(times[2], 2),
-               krylov=a.krylov, autotune=tuned, fp64_gpu_reference=ref)
+               krylov=a.krylov, autotune=tuned, fp64_gpu_reference=ref, pass_rooflines=rooflines)
     print(json.dumps(out), flush=True)
     return 0
 
