@@ -75,3 +75,31 @@ def test_autotune_then_solve_matches_oracle():
         uref, _ = P.solve(P.incident(src[k:k + p["nsys"]], f[k:k + p["nsys"]]), tol=1e-11)
         assert _rel(plan.view(res.x, i).cpu().numpy().astype(np.complex128), uref) < 1e-4
         k += p["nsys"]
+
+
+@pytest.mark.parametrize("nx,nz", [(256, 64), (384, 48)])
+def test_fused_solves_match_oracle_and_plain(nx, nz):
+    """Every fused stencil+rows variant through a whole BiCGSTAB solve (its
+    direction-update modes included, the 512-thread form of the closing mode
+    at these widths) against the oracle, and the batched solve bit-identical
+    to the per-source one under the same variant."""
+    from paper_2402_02116_amd.plan import Plan
+    p, maps = _case(nx, nz, 3, seed=11)
+    plan = Plan([p])
+    plan.set_contrast(0, maps)
+    src, f = W.surface_sources(nx, 3, iz=nz // 4)
+    u0 = plan.incident(src, f)
+    P = LSProblem(nx, nz, 8.0, p["c0"], p["rho0"], p["freq_hz"], 0.02, maps)
+    uref, _ = P.solve(P.incident(src, f), tol=1e-11)
+    cands = plan.tuning_candidates(0, "fuse")
+    assert cands
+    for c in cands:
+        plan.set_tuning(0, **c)
+        print(f"fused {nx}x{nz} points {c['fused_points']}", flush=True)
+        res = plan.solve(u0, rtol=1e-6, maxit=500)
+        assert res.status == 0 and np.all(res.relres <= 2e-6), (c, res.relres)
+        x = plan.view(res.x, 0).cpu().numpy().astype(np.complex128)
+        for k in range(3):
+            assert _rel(x[k], uref[k]) < 1e-4, (c, k)
+        plain = plan.solve(u0, rtol=1e-6, maxit=500, plain=True)
+        assert torch.equal(res.x, plain.x) and np.array_equal(res.iters, plain.iters), c
