@@ -26,11 +26,14 @@ problem    One (grid, background, contrast) problem with its solves, the
            Frechet operator (eqs. F, YM, F0, uY) and the adjoint (eqs. ad1, ua).
 tikhonov   Generalised Tikhonov objective, gradient and normal-equation CG
            (eqs. obj, norm).
+dbi        One frequency stage of the distorted-Born iteration: background
+           solve, normalised data error, normal-equation CG, model update,
+           self-adaptive lambda cooling and the stopping rule.
 dense      Explicit matrices for the pins: the dense Green's matrix from a
            direct DFT sum and the sparse discrete elastic operator (eq. Ewave).
 
 Parity pins for every function live in tests/test_oracle_*.py.
 """
 
-from . import media, green, operators, krylov, problem, tikhonov, dense  # noqa: F401
+from . import media, green, operators, krylov, problem, tikhonov, dbi, dense  # noqa: F401
 from .problem import LSProblem  # noqa: F401
