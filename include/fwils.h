@@ -68,7 +68,7 @@
 extern "C" {
 #endif
 
-#define FWILS_ABI_VERSION 5
+#define FWILS_ABI_VERSION 6
 
 typedef enum {
     FWILS_OK = 0,
@@ -273,6 +273,44 @@ fwils_status fwils_adjoint_rel(fwils_plan plan, const void* ub, const void* r, c
 /* out = L q: periodic unscaled 5-point Laplacian of the 5 maps [5][nz][nx]
  * (single-grid plans).  Self-adjoint, so it is also L^T q. */
 fwils_status fwils_laplacian(fwils_plan plan, const void* q, void* out);
+
+/* d = R u: every system's field sampled at its problem's receivers (the
+ * receiver operator of the data, eqs. du and F0).  u: device field; d:
+ * device complex [sum nsys][nrec][2] in the plan's data layout.  Every
+ * problem needs receivers.  Asynchronous on the plan's stream. */
+fwils_status fwils_receiver_data(fwils_plan plan, const void* u, void* d);
+
+/* Copies problem iprob's contrast maps (real [5][nz][nx], the layout and
+ * units of fwils_set_contrast) to the device buffer maps.  Asynchronous. */
+fwils_status fwils_get_contrast(fwils_plan plan, int32_t iprob, void* maps);
+
+/* ---- Distorted-Born iteration (the DBI loop around eqs. du, obj, norm) --
+ * One frequency stage of the inversion on a single-grid plan.  The plan's
+ * contrast is the background model m_b (shared by all its problems: set the
+ * same maps on each) and is updated in place.  Outer iteration k:
+ *   u^b = A_b^-1 u0 for the point forces src_ixz, src_f (as fwils_incident);
+ *     from k = 1 on, the solve starts from the previous model's u^b;
+ *   r = d_obs - R u^b;  eps_d[k] = ||r|| / ||d_obs|| (normalised data error);
+ *   stop if eps_d[k] < tol, eps_d[k] == 0 or k == max_outer;
+ *   lam_k = lam0 eps_d[k] / eps_d[0] (self-adaptive cooling; lam_0 = lam0);
+ *   q = niter CG iterations on eq. norm with lam_k (as fwils_normal_cg);
+ *   contrast_p += m0_p q_p on every problem (the background update).
+ * The paper's stage stops at eps_d < 1e-3 or after 10 iterations
+ * (tol = 1e-3, max_outer = 10).
+ * d_obs: device data (plan layout, non-zero); ub: device field, receives the
+ * final model's background fields; r: device data, receives their residual;
+ * q: device real [5][nz][nx], receives the last update (untouched without
+ * one); dscratch: device complex buffer of the data's size.  eps_hist: host
+ * double [max_outer + 1]; lam_hist: host double [max_outer] or NULL;
+ * updates (host, or NULL): the number of model updates made.
+ * niter 1..1000, max_outer 0..100, tol >= 0.  Returns the worst status of
+ * its solves (ENOCONV if any stopped at maxit); EBREAKDOWN if the data error
+ * became non-finite.  Synchronous. */
+fwils_status fwils_dbi_run(fwils_plan plan, const int32_t* src_ixz, const double* src_f,
+                           const void* d_obs, const double* m0, double lam0, int32_t reg,
+                           int32_t niter, double tol, int32_t max_outer, void* ub, void* r,
+                           void* q, void* dscratch, double* eps_hist, double* lam_hist,
+                           int32_t* updates, double rtol, int32_t maxit);
 
 /* 2-D FFT of every field of problem iprob with the library's own transform
  * kernels (unnormalised forward, exp(-i k.x); inverse with exp(+i k.x) and

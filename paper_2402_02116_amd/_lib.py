@@ -77,6 +77,12 @@ SIGNATURES = {
     "fwils_frechet_rel": (c_int32, [P, P, P, ctypes.POINTER(c_double), P, c_double, c_int32]),
     "fwils_adjoint_rel": (c_int32, [P, P, P, ctypes.POINTER(c_double), P, c_double, c_int32]),
     "fwils_laplacian": (c_int32, [P, P, P]),
+    "fwils_receiver_data": (c_int32, [P, P, P]),
+    "fwils_get_contrast": (c_int32, [P, c_int32, P]),
+    "fwils_dbi_run": (c_int32, [P, ctypes.POINTER(c_int32), ctypes.POINTER(c_double), P, ctypes.POINTER(c_double),
+                                c_double, c_int32, c_int32, c_double, c_int32, P, P, P, P,
+                                ctypes.POINTER(c_double), ctypes.POINTER(c_double), ctypes.POINTER(c_int32),
+                                c_double, c_int32]),
     "fwils_solve_stats": (c_int32, [P, ctypes.POINTER(c_int32), ctypes.POINTER(c_double)]),
     "fwils_solve_status": (c_int32, [P, ctypes.POINTER(c_int32)]),
     "fwils_autotune": (c_int32, [P, c_int32]),

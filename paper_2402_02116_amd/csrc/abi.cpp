@@ -64,6 +64,14 @@
        int32_t maxit),                                                                                     \
       (plan, ub, r, m0, gq, rtol, maxit))                                                                  \
     X(fwils_status, laplacian, (fwils_plan plan, const void* q, void* out), (plan, q, out))              \
+    X(fwils_status, receiver_data, (fwils_plan plan, const void* u, void* d), (plan, u, d))              \
+    X(fwils_status, get_contrast, (fwils_plan plan, int32_t iprob, void* maps), (plan, iprob, maps))     \
+    X(fwils_status, dbi_run,                                                                               \
+      (fwils_plan plan, const int32_t* src_ixz, const double* src_f, const void* d_obs, const double* m0, \
+       double lam0, int32_t reg, int32_t niter, double tol, int32_t max_outer, void* ub, void* r, void* q, \
+       void* dscratch, double* eps_hist, double* lam_hist, int32_t* updates, double rtol, int32_t maxit),  \
+      (plan, src_ixz, src_f, d_obs, m0, lam0, reg, niter, tol, max_outer, ub, r, q, dscratch, eps_hist,   \
+       lam_hist, updates, rtol, maxit))                                                                    \
     X(fwils_status, fft2, (fwils_plan plan, int32_t iprob, const void* in, void* out, int32_t inverse),  \
       (plan, iprob, in, out, inverse))                                                                     \
     X(fwils_status, gmres_workspace_size, (fwils_plan plan, int32_t restart, size_t* bytes),             \

@@ -60,6 +60,7 @@ constexpr int kNumVec = 10;           // field-sized workspace vectors
 constexpr int kMaxRestarts = 3;       // restarts from the true residual per solve
 constexpr double kTrueResFactor = 2.0; // restart when ||b - A x|| > 2 rtol ||b||
 constexpr int kMaxCgIters = 1000;
+constexpr int kMaxDbiUpdates = 100;
 constexpr double kCgFloor = 1e-30;    // normal CG stops when ||res||^2 <= kCgFloor ||res_0||^2
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -631,6 +632,44 @@ fwils_status solve_ws(fwils_plan pl, const cplx* b, bool use_x0, double rtol, in
     return bicg_solve_ws(pl, b, use_x0, rtol, maxit, iters, relres, flags);
 }
 
+// Checks the point forces (one per system, host arrays as fwils_incident
+// takes them) and copies them to the plan's device arrays.
+fwils_status upload_sources(fwils_plan plan, const int32_t* src_ixz, const double* src_f, const char* what) {
+    if (!src_ixz || !src_f) {
+        set_error("%s: null source pointer", what);
+        return FWILS_EINVAL;
+    }
+    for (const ProbHost& P : plan->probs) {
+        for (int sy = 0; sy < P.p.nsys; ++sy) {
+            const size_t k = P.sys_off + sy;
+            const int ix = src_ixz[2 * k], iz = src_ixz[2 * k + 1];
+            if (ix < 0 || ix >= P.p.nx || iz < 0 || iz >= P.p.nz || !std::isfinite(src_f[2 * k]) ||
+                !std::isfinite(src_f[2 * k + 1])) {
+                set_error("%s: source %zu at (%d, %d) outside the grid or non-finite force", what, k, ix, iz);
+                return FWILS_EINVAL;
+            }
+        }
+    }
+    FW_HIP(hipStreamSynchronize(plan->stream));
+    FW_HIP(hipMemcpy(plan->src_i, src_ixz, plan->total_sys * 2 * sizeof(int32_t), hipMemcpyHostToDevice));
+    FW_HIP(hipMemcpy(plan->src_f, src_f, plan->total_sys * 2 * sizeof(double), hipMemcpyHostToDevice));
+    return FWILS_OK;
+}
+
+// u0 = G0 conv s for the uploaded point forces (eq. u0); f: a field-sized
+// buffer for the discrete sources, distinct from out and from tmp.
+hipError_t incident_ws(fwils_plan plan, cplx* f, cplx* out) {
+    for (const ProbHost& P : plan->probs) {
+        hipError_t e = launch_zero(at(f, P), (size_t)P.p.nsys * P.n_per_sys, plan->stream);
+        if (e == hipSuccess)
+            e = launch_point_sources(at(f, P), plan->src_i + 2 * P.sys_off, plan->src_f + 2 * P.sys_off, P.dev,
+                                     plan->stream);
+        if (e == hipSuccess) e = conv_problem(plan, P, at(f, P), at(out, P));
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 fwils_status check_field_ptrs(std::initializer_list<const void*> ptrs) {
     for (const void* q : ptrs)
         if (!q) {
@@ -718,8 +757,8 @@ fwils_status fwils_plan_create(const fwils_problem* probs, int32_t nprob, fwils_
     o = align256(o + pl->maps_floats * sizeof(real));
     pl->off_rec = o;
     o = align256(o + (size_t)nprob * kMaxRec * 2 * sizeof(int32_t));
-    pl->off_src = o;
-    o = align256(o + pl->total_sys * 2 * (sizeof(int32_t) + sizeof(double)));
+    pl->off_src = o;   // source cells, then (256-byte aligned) source forces
+    o = align256(o + align256(pl->total_sys * 2 * sizeof(int32_t)) + pl->total_sys * 2 * sizeof(double));
     pl->off_vec = o;
     o += kNumVec * align256(pl->total_field * sizeof(cplx));
     bool one_grid = true;
@@ -870,31 +909,12 @@ fwils_status fwils_set_receivers(fwils_plan plan, int32_t iprob, const int32_t* 
 
 fwils_status fwils_incident(fwils_plan plan, const int32_t* src_ixz, const double* src_f, void* u0) {
     FW_TRY(check_plan(plan));
-    if (!src_ixz || !src_f || !u0) {
+    if (!u0) {
         set_error("incident: null pointer");
         return FWILS_EINVAL;
     }
-    for (const ProbHost& P : plan->probs) {
-        for (int sy = 0; sy < P.p.nsys; ++sy) {
-            const size_t k = P.sys_off + sy;
-            const int ix = src_ixz[2 * k], iz = src_ixz[2 * k + 1];
-            if (ix < 0 || ix >= P.p.nx || iz < 0 || iz >= P.p.nz || !std::isfinite(src_f[2 * k]) ||
-                !std::isfinite(src_f[2 * k + 1])) {
-                set_error("incident: source %zu at (%d, %d) outside the grid or non-finite force", k, ix, iz);
-                return FWILS_EINVAL;
-            }
-        }
-    }
-    hipStream_t s = plan->stream;
-    FW_HIP(hipStreamSynchronize(s));
-    FW_HIP(hipMemcpy(plan->src_i, src_ixz, plan->total_sys * 2 * sizeof(int32_t), hipMemcpyHostToDevice));
-    FW_HIP(hipMemcpy(plan->src_f, src_f, plan->total_sys * 2 * sizeof(double), hipMemcpyHostToDevice));
-    for (const ProbHost& P : plan->probs) {
-        cplx* f = at(plan->rhs, P);
-        FW_HIP(launch_zero(f, (size_t)P.p.nsys * P.n_per_sys, s));
-        FW_HIP(launch_point_sources(f, plan->src_i + 2 * P.sys_off, plan->src_f + 2 * P.sys_off, P.dev, s));
-        FW_HIP(conv_problem(plan, P, f, static_cast<cplx*>(u0) + P.field_off));
-    }
+    FW_TRY(upload_sources(plan, src_ixz, src_f, "incident"));
+    FW_HIP(incident_ws(plan, plan->rhs, static_cast<cplx*>(u0)));
     return FWILS_OK;
 }
 
@@ -1083,6 +1103,67 @@ MapScales scales(const double* m0) {
     return m;
 }
 
+// niter CG iterations on eq. norm from q = 0 (validated arguments); hist:
+// host [niter + 1] or NULL.
+fwils_status normal_cg_ws(fwils_plan plan, const void* ub, const void* r, const MapScales& ms, double lam,
+                          int32_t reg, int32_t niter, real* q, double* hist, void* dscratch, double rtol,
+                          int32_t maxit) {
+    hipStream_t s = plan->stream;
+    const int n = (int)plan->map_n;
+    const size_t nm = 5 * plan->map_n;
+    double* sc = plan->mq_sc;
+    // rr and the right-hand side m0 Re J* r / rr
+    FW_HIP(launch_norm2_complex(static_cast<const cplx*>(r), data_elems(plan), plan->mq_part, sc + 4, s));
+    double rr = 0;
+    FW_HIP(hipMemcpyAsync(&rr, sc + 4, sizeof(double), hipMemcpyDeviceToHost, s));
+    FW_HIP(hipStreamSynchronize(s));
+    if (!(rr > 0)) {
+        set_error("normal_cg: ||r|| is zero");
+        return FWILS_EINVAL;
+    }
+    std::vector<void*> gs(plan->probs.size(), plan->mq_g);
+    FW_HIP(launch_zero_d2(plan->mq_g, nm, s));
+    fwils_status st = adjoint_ws(plan, ub, r, gs.data(), true, rtol, maxit, true);
+    if (st == FWILS_EDEVICE) return st;
+    FW_HIP(launch_map_combine(plan->mq_g, nullptr, plan->mq_res, ms, 1.0 / rr, 0.0, n, s));
+    FW_HIP(launch_zero_f(plan->mq_x, nm, s));
+    FW_HIP(launch_copy_f(plan->mq_res, plan->mq_p, nm, s));
+    FW_HIP(launch_dot_real(plan->mq_res, plan->mq_res, nm, plan->mq_part, sc + 2, s));
+    FW_HIP(launch_cg_shift(sc, plan->mq_hist, 0, s));
+    double rs0 = 0.0;
+    FW_HIP(hipMemcpyAsync(&rs0, sc + 2, sizeof(double), hipMemcpyDeviceToHost, s));
+    FW_HIP(hipStreamSynchronize(s));
+    int done = niter;   // iterations run: fewer once the residual is at the floor
+    for (int it = 0; it < niter; ++it) {
+        fwils_status sa = normal_apply_ws(plan, ub, ms, rr, lam, reg, plan->mq_p, plan->mq_Ap, dscratch,
+                                          rtol, maxit);
+        if (sa == FWILS_EDEVICE) return sa;
+        st = worst(st, sa);
+        FW_HIP(launch_dot_real(plan->mq_p, plan->mq_Ap, nm, plan->mq_part, sc + 1, s));
+        FW_HIP(launch_cg_xr(plan->mq_x, plan->mq_res, plan->mq_p, plan->mq_Ap, sc, nm, s));
+        FW_HIP(launch_dot_real(plan->mq_res, plan->mq_res, nm, plan->mq_part, sc + 2, s));
+        FW_HIP(launch_cg_p(plan->mq_p, plan->mq_res, sc, nm, s));
+        FW_HIP(launch_cg_shift(sc, plan->mq_hist, it + 1, s));
+        // converged to working precision: further iterations would only push
+        // the direction vectors towards underflow
+        double rs = 0.0;
+        FW_HIP(hipMemcpyAsync(&rs, sc + 2, sizeof(double), hipMemcpyDeviceToHost, s));
+        FW_HIP(hipStreamSynchronize(s));
+        if (!(rs > kCgFloor * rs0)) {
+            done = it + 1;
+            break;
+        }
+    }
+    FW_HIP(launch_copy_f(plan->mq_x, q, nm, s));
+    if (hist)
+        FW_HIP(hipMemcpyAsync(hist, plan->mq_hist, (size_t)(done + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+    FW_HIP(hipStreamSynchronize(s));
+    if (hist)
+        for (int i = done + 1; i <= niter; ++i) hist[i] = hist[done];
+    return st;
+}
+
+
 }  // namespace
 
 extern "C" {
@@ -1241,59 +1322,107 @@ fwils_status fwils_normal_cg(fwils_plan plan, const void* ub, const void* r, con
         set_error("normal_cg: niter must be 1..%d", kMaxCgIters);
         return FWILS_EINVAL;
     }
-    hipStream_t s = plan->stream;
-    const MapScales ms = scales(m0);
-    const int n = (int)plan->map_n;
-    const size_t nm = 5 * plan->map_n;
-    double* sc = plan->mq_sc;
-    // rr and the right-hand side m0 Re J* r / rr
-    FW_HIP(launch_norm2_complex(static_cast<const cplx*>(r), data_elems(plan), plan->mq_part, sc + 4, s));
-    double rr = 0;
-    FW_HIP(hipMemcpyAsync(&rr, sc + 4, sizeof(double), hipMemcpyDeviceToHost, s));
-    FW_HIP(hipStreamSynchronize(s));
-    if (!(rr > 0)) {
-        set_error("normal_cg: ||r|| is zero");
-        return FWILS_EINVAL;
-    }
-    std::vector<void*> gs(plan->probs.size(), plan->mq_g);
-    FW_HIP(launch_zero_d2(plan->mq_g, nm, s));
-    fwils_status st = adjoint_ws(plan, ub, r, gs.data(), true, rtol, maxit, true);
-    if (st == FWILS_EDEVICE) return st;
-    FW_HIP(launch_map_combine(plan->mq_g, nullptr, plan->mq_res, ms, 1.0 / rr, 0.0, n, s));
-    FW_HIP(launch_zero_f(plan->mq_x, nm, s));
-    FW_HIP(launch_copy_f(plan->mq_res, plan->mq_p, nm, s));
-    FW_HIP(launch_dot_real(plan->mq_res, plan->mq_res, nm, plan->mq_part, sc + 2, s));
-    FW_HIP(launch_cg_shift(sc, plan->mq_hist, 0, s));
-    double rs0 = 0.0;
-    FW_HIP(hipMemcpyAsync(&rs0, sc + 2, sizeof(double), hipMemcpyDeviceToHost, s));
-    FW_HIP(hipStreamSynchronize(s));
-    int done = niter;   // iterations run: fewer once the residual is at the floor
-    for (int it = 0; it < niter; ++it) {
-        fwils_status sa = normal_apply_ws(plan, ub, ms, rr, lam, reg, plan->mq_p, plan->mq_Ap, dscratch,
-                                          rtol, maxit);
-        if (sa == FWILS_EDEVICE) return sa;
-        st = worst(st, sa);
-        FW_HIP(launch_dot_real(plan->mq_p, plan->mq_Ap, nm, plan->mq_part, sc + 1, s));
-        FW_HIP(launch_cg_xr(plan->mq_x, plan->mq_res, plan->mq_p, plan->mq_Ap, sc, nm, s));
-        FW_HIP(launch_dot_real(plan->mq_res, plan->mq_res, nm, plan->mq_part, sc + 2, s));
-        FW_HIP(launch_cg_p(plan->mq_p, plan->mq_res, sc, nm, s));
-        FW_HIP(launch_cg_shift(sc, plan->mq_hist, it + 1, s));
-        // converged to working precision: further iterations would only push
-        // the direction vectors towards underflow
-        double rs = 0.0;
-        FW_HIP(hipMemcpyAsync(&rs, sc + 2, sizeof(double), hipMemcpyDeviceToHost, s));
-        FW_HIP(hipStreamSynchronize(s));
-        if (!(rs > kCgFloor * rs0)) {
-            done = it + 1;
-            break;
+    return normal_cg_ws(plan, ub, r, scales(m0), lam, reg, niter, q, hist, dscratch, rtol, maxit);
+}
+
+fwils_status fwils_receiver_data(fwils_plan plan, const void* u, void* d) {
+    FW_TRY(check_plan(plan));
+    FW_TRY(check_field_ptrs({u, d}));
+    for (size_t i = 0; i < plan->probs.size(); ++i) {
+        const ProbHost& P = plan->probs[i];
+        if (P.nrec < 1) {
+            set_error("receiver_data: problem %zu has no receivers", i);
+            return FWILS_EINVAL;
         }
     }
-    FW_HIP(launch_copy_f(plan->mq_x, q, nm, s));
-    if (hist)
-        FW_HIP(hipMemcpyAsync(hist, plan->mq_hist, (size_t)(done + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+    for (size_t i = 0; i < plan->probs.size(); ++i) {
+        const ProbHost& P = plan->probs[i];
+        FW_HIP(launch_gather(at(u, P), static_cast<cplx*>(d) + P.data_off, plan->rec + i * kMaxRec * 2, P.nrec,
+                             P.dev, plan->stream));
+    }
+    return FWILS_OK;
+}
+
+fwils_status fwils_get_contrast(fwils_plan plan, int32_t iprob, void* maps) {
+    FW_TRY(check_plan(plan));
+    if (iprob < 0 || iprob >= (int)plan->probs.size() || !maps) {
+        set_error("get_contrast: bad problem index or null maps");
+        return FWILS_EINVAL;
+    }
+    const ProbHost& P = plan->probs[iprob];
+    FW_HIP(hipMemcpyAsync(maps, maps_at(plan, P), (size_t)5 * P.p.nz * P.p.nx * sizeof(real),
+                          hipMemcpyDeviceToDevice, plan->stream));
+    return FWILS_OK;
+}
+
+fwils_status fwils_dbi_run(fwils_plan plan, const int32_t* src_ixz, const double* src_f, const void* d_obs_,
+                           const double* m0, double lam0, int32_t reg, int32_t niter, double tol,
+                           int32_t max_outer, void* ub_, void* r_, void* q_, void* dscratch, double* eps_hist,
+                           double* lam_hist, int32_t* updates, double rtol, int32_t maxit) {
+    const cplx* d_obs = static_cast<const cplx*>(d_obs_);
+    cplx* ub = static_cast<cplx*>(ub_);
+    cplx* r = static_cast<cplx*>(r_);
+    real* q = static_cast<real*>(q_);
+    FW_TRY(check_plan(plan));
+    FW_TRY(check_field_ptrs({d_obs, ub, r, q, dscratch, eps_hist}));
+    FW_TRY(check_tik(plan, m0, lam0, reg, rtol, maxit, "dbi_run"));
+    if (niter < 1 || niter > kMaxCgIters || max_outer < 0 || max_outer > kMaxDbiUpdates || !(tol >= 0)) {
+        set_error("dbi_run: need niter 1..%d, max_outer 0..%d and tol >= 0", kMaxCgIters, kMaxDbiUpdates);
+        return FWILS_EINVAL;
+    }
+    FW_TRY(upload_sources(plan, src_ixz, src_f, "dbi_run"));
+    hipStream_t s = plan->stream;
+    const MapScales ms = scales(m0);
+    const size_t nd = data_elems(plan);
+    double* sc = plan->mq_sc;
+    double dd = 0.0;
+    FW_HIP(launch_norm2_complex(d_obs, nd, plan->mq_part, sc + 9, s));
+    FW_HIP(hipMemcpyAsync(&dd, sc + 9, sizeof(double), hipMemcpyDeviceToHost, s));
     FW_HIP(hipStreamSynchronize(s));
-    if (hist)
-        for (int i = done + 1; i <= niter; ++i) hist[i] = hist[done];
+    if (!(dd > 0) || !std::isfinite(dd)) {
+        set_error("dbi_run: d_obs must be non-zero and finite");
+        return FWILS_EINVAL;
+    }
+    fwils_status st = FWILS_OK;
+    int made = 0;
+    for (int k = 0;; ++k) {
+        // background fields of the current model, warm-started from the
+        // previous model's fields after the first update
+        FW_HIP(incident_ws(plan, plan->s, plan->rhs));
+        if (k > 0) FW_HIP(launch_copy(ub, plan->x, plan->total_field, s));
+        const fwils_status ss = solve_ws(plan, plan->rhs, k > 0, rtol, maxit, nullptr, nullptr, 0);
+        if (ss == FWILS_EDEVICE) return ss;
+        st = worst(st, ss);
+        FW_HIP(launch_copy(plan->x, ub, plan->total_field, s));
+        // r = d_obs - R u^b and the normalised data error
+        for (size_t i = 0; i < plan->probs.size(); ++i) {
+            const ProbHost& P = plan->probs[i];
+            FW_HIP(launch_gather(at(ub, P), r + P.data_off, plan->rec + i * kMaxRec * 2, P.nrec, P.dev, s));
+        }
+        FW_HIP(launch_data_residual(r, d_obs, nd, s));
+        double rr = 0.0;
+        FW_HIP(launch_norm2_complex(r, nd, plan->mq_part, sc + 8, s));
+        FW_HIP(hipMemcpyAsync(&rr, sc + 8, sizeof(double), hipMemcpyDeviceToHost, s));
+        FW_HIP(hipStreamSynchronize(s));
+        const double eps = std::sqrt(rr / dd);
+        if (!std::isfinite(eps)) {
+            set_error("dbi_run: non-finite data error after %d updates", made);
+            if (updates) *updates = made;
+            return FWILS_EBREAKDOWN;
+        }
+        eps_hist[k] = eps;
+        if (eps < tol || eps == 0.0 || k == max_outer) break;
+        // self-adaptive cooling: lambda follows the data error
+        const double lam = lam0 * eps / eps_hist[0];
+        if (lam_hist) lam_hist[k] = lam;
+        const fwils_status sq = normal_cg_ws(plan, ub, r, ms, lam, reg, niter, q, nullptr, dscratch, rtol, maxit);
+        if (sq == FWILS_EDEVICE || sq == FWILS_EINVAL) return sq;
+        st = worst(st, sq);
+        for (const ProbHost& P : plan->probs) FW_HIP(launch_map_update(maps_at(plan, P), q, ms, (int)plan->map_n, s));
+        ++made;
+    }
+    FW_HIP(hipStreamSynchronize(s));
+    if (updates) *updates = made;
     return st;
 }
 

@@ -35,6 +35,9 @@
 #define fwils_frechet_rel FW_CORE(fwils_frechet_rel)
 #define fwils_adjoint_rel FW_CORE(fwils_adjoint_rel)
 #define fwils_laplacian FW_CORE(fwils_laplacian)
+#define fwils_receiver_data FW_CORE(fwils_receiver_data)
+#define fwils_get_contrast FW_CORE(fwils_get_contrast)
+#define fwils_dbi_run FW_CORE(fwils_dbi_run)
 #define fwils_fft2 FW_CORE(fwils_fft2)
 #define fwils_gmres_workspace_size FW_CORE(fwils_gmres_workspace_size)
 #define fwils_set_krylov FW_CORE(fwils_set_krylov)

@@ -1,7 +1,8 @@
 // Model-map kernels of the generalised Tikhonov step (eqs. obj, norm):
 // relative maps q [5][nz][nx] (fp32), dm = m0 q, the periodic 5-point
 // Laplacian, the combination of J* output into gradient / normal-operator
-// maps, FP64 inner products and the CG updates with device-resident scalars.
+// maps, FP64 inner products and the CG updates with device-resident scalars;
+// the data residual and background update of the distorted-Born loop.
 #include "launch.h"
 
 FW_BEGIN
@@ -173,6 +174,34 @@ __global__ void k_sub_complex(cplx* __restrict__ d, const cplx* __restrict__ r, 
 
 hipError_t launch_sub_complex(cplx* d, const cplx* r, size_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_sub_complex, dim3(256), dim3(256), 0, s, d, r, n);
+    return hipGetLastError();
+}
+
+// r = d_obs - r: the data residual of a DBI step from the gathered R u^b
+__global__ void k_data_residual(cplx* __restrict__ r, const cplx* __restrict__ d_obs, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        r[i] = csub(d_obs[i], r[i]);
+}
+
+hipError_t launch_data_residual(cplx* r, const cplx* d_obs, size_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_data_residual, dim3(256), dim3(256), 0, s, r, d_obs, n);
+    return hipGetLastError();
+}
+
+// maps[p][i] += m0[p] q[p][i] (the DBI background update, in FP64 before
+// rounding to the map precision)
+__global__ void k_map_update(real* __restrict__ maps, const real* __restrict__ q, MapScales m0, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int p = blockIdx.y;
+    if (i < n) {
+        const size_t k = (size_t)p * n + i;
+        maps[k] = (real)((double)maps[k] + m0.s[p] * (double)q[k]);
+    }
+}
+
+hipError_t launch_map_update(real* maps, const real* q, const MapScales& m0, int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_map_update, dim3((n + kMapThreads - 1) / kMapThreads, 5), dim3(kMapThreads), 0, s,
+                       maps, q, m0, n);
     return hipGetLastError();
 }
 

@@ -211,5 +211,7 @@ hipError_t launch_cg_shift(double* sc, double* hist, int it, hipStream_t s);
 hipError_t launch_copy_f(const real* a, real* b, size_t n, hipStream_t s);
 hipError_t launch_zero_f(real* b, size_t n, hipStream_t s);
 hipError_t launch_sub_complex(cplx* d, const cplx* r, size_t n, hipStream_t s);
+hipError_t launch_data_residual(cplx* r, const cplx* d_obs, size_t n, hipStream_t s);
+hipError_t launch_map_update(real* maps, const real* q, const MapScales& m0, int n, hipStream_t s);
 
 FW_END

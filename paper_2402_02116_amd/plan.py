@@ -396,6 +396,57 @@ class Plan:
             check(st, "fwils_normal_cg")
         return q, hist
 
+    def receiver_data(self, u, out=None):
+        """d = R u: the fields sampled at every problem's receivers (plan data layout)."""
+        self._field(u, "u")
+        d = torch.empty(self.data_elems(), dtype=self.cdtype, device=self.device) if out is None \
+            else self._data(out, "out")
+        self._bind_stream()
+        check(self.lib.fwils_receiver_data(self._h, _ptr(u), _ptr(d)), "fwils_receiver_data")
+        return d
+
+    def get_contrast(self, i):
+        """Problem i's current contrast maps [5, nz, nx] (rdtype)."""
+        p = self.problems[i]
+        m = torch.empty(5, p["nz"], p["nx"], dtype=self.rdtype, device=self.device)
+        self._bind_stream()
+        check(self.lib.fwils_get_contrast(self._h, i, _ptr(m)), "fwils_get_contrast")
+        torch.cuda.current_stream(self.device).synchronize()
+        return m
+
+    def dbi_run(self, src_ixz, src_f, d_obs, m0, lam0=1e-3, niter=10, reg="identity", tol=1e-3,
+                max_outer=10, rtol=1e-6, maxit=1000):
+        """One frequency stage of the distorted-Born inversion (fwils_dbi_run):
+        updates the plan's contrast in place and returns a dict with the data
+        error history eps_d, the cooled lambdas, the number of updates, the
+        final background fields ub, their residual r, the last update q and
+        the status of the worst solve."""
+        s = np.ascontiguousarray(np.asarray(src_ixz, dtype=np.int32).reshape(-1, 2))
+        f = np.ascontiguousarray(np.asarray(src_f, dtype=np.float64).reshape(-1, 2))
+        if s.shape[0] != self.total_sys or f.shape[0] != self.total_sys:
+            raise ValueError(f"need {self.total_sys} sources and forces")
+        self._data(d_obs, "d_obs")
+        m, mp = self._m0(m0)
+        p = self.problems[0]
+        ub = self.new_field()
+        r = torch.empty_like(d_obs)
+        d = torch.empty_like(d_obs)
+        q = torch.zeros(5, p["nz"], p["nx"], dtype=self.rdtype, device=self.device)
+        eps = np.full(max_outer + 1, np.nan)
+        lam = np.full(max(max_outer, 1), np.nan)
+        upd = ctypes.c_int32(0)
+        dbl = ctypes.POINTER(ctypes.c_double)
+        self._bind_stream()
+        st = self.lib.fwils_dbi_run(self._h, s.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                    f.ctypes.data_as(dbl), _ptr(d_obs), mp, float(lam0), self.REGS[reg],
+                                    int(niter), float(tol), int(max_outer), _ptr(ub), _ptr(r), _ptr(q), _ptr(d),
+                                    eps.ctypes.data_as(dbl), lam.ctypes.data_as(dbl), ctypes.byref(upd),
+                                    float(rtol), int(maxit))
+        if st not in (_lib.FWILS_OK, _lib.FWILS_ENOCONV):
+            check(st, "fwils_dbi_run")
+        n = int(upd.value)
+        return dict(eps=eps[:n + 1].tolist(), lam=lam[:n].tolist(), updates=n, ub=ub, r=r, q=q, status=st)
+
     # ------------------------------------------------- Krylov method ----
     def set_krylov(self, method="bicgstab", restart=20, cgs2=True):
         """Krylov method of every solve of this plan: 'bicgstab' (default) or

@@ -162,6 +162,13 @@ def test_plan_metadata_without_device(lib):
         assert lib.fwils_set_workspace(h, ctypes.c_void_p(256), sz.value - 1) == _lib.FWILS_ENOMEM
         assert lib.fwils_set_workspace(h, ctypes.c_void_p(257), sz.value) == _lib.FWILS_ENOMEM
         assert lib.fwils_set_stream(h, None) == _lib.FWILS_OK
+        v = ctypes.c_void_p(256)
+        assert lib.fwils_receiver_data(h, v, v) == _lib.FWILS_ENOMEM
+        assert lib.fwils_get_contrast(h, 0, v) == _lib.FWILS_ENOMEM
+        m0 = (ctypes.c_double * 5)(1, 1, 1, 1, 1)
+        eps = (ctypes.c_double * 11)()
+        assert lib.fwils_dbi_run(h, None, None, v, m0, 1e-3, 0, 5, 1e-3, 10, v, v, v, v, eps, None, None,
+                                 1e-6, 100) == _lib.FWILS_ENOMEM
     finally:
         lib.fwils_plan_destroy(h)
 
@@ -169,6 +176,10 @@ def test_plan_metadata_without_device(lib):
 def test_null_plan_is_rejected(lib):
     assert lib.fwils_apply(None, None, None) == _lib.FWILS_EINVAL
     assert lib.fwils_solve(None, None, None, 1e-6, 10, None, None, 0) == _lib.FWILS_EINVAL
+    assert lib.fwils_receiver_data(None, None, None) == _lib.FWILS_EINVAL
+    assert lib.fwils_get_contrast(None, 0, None) == _lib.FWILS_EINVAL
+    assert lib.fwils_dbi_run(None, None, None, None, None, 0.0, 0, 1, 0.0, 1, None, None, None, None, None,
+                             None, None, 1e-6, 10) == _lib.FWILS_EINVAL
     lib.fwils_plan_destroy(None)
 
 

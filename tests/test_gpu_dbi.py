@@ -1,0 +1,127 @@
+"""GPU parity of the distorted-Born inversion stage (fwils_dbi_run: background
+solve, normalised data error, normal-equation CG, background update and
+self-adaptive lambda cooling) and of the receiver gather and contrast copy it
+builds on, against the complex128 oracle's DBI stage on the same seeded
+inputs, in both library precisions."""
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import LSProblem, dbi, operators
+
+pytestmark = pytest.mark.gpu
+
+NX, NZ, DX, FREQS = 32, 16, 10.0, (20.0, 28.0)
+NSYS = 2
+SRC = [(3, 1), (22, 2)]
+SRC_F = [(0.0, 1.0), (1.0, 0.0)]
+REC = [(ix, 2) for ix in range(0, NX, 2)] + [(ix, 11) for ix in range(1, NX, 4)]
+LAM0, NITER, MAX_OUTER = 1.0, 4, 2
+
+
+def _rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+@pytest.fixture(scope="module")
+def case():
+    c0, rho0 = W.vti_background()
+    m0 = W.model_scales(c0, rho0)
+    m0b = m0.reshape(5, 1, 1)
+    c_true = W.round_f32(m0b * W.smooth_maps(21, NZ, NX, 2.0, 0.03))
+    c_start = W.round_f32(m0b * W.smooth_maps(22, NZ, NX, 2.0, 0.01))
+    probs = [dict(nx=NX, nz=NZ, dx=DX, c0=tuple(c0), rho0=rho0, freq_hz=f, eta=0.02, nsys=NSYS) for f in FREQS]
+    items = []
+    for f in FREQS:
+        P = LSProblem(NX, NZ, DX, c0, rho0, f, 0.02, c_true)
+        u, _ = P.solve(P.incident(SRC, SRC_F), tol=1e-13)
+        items.append([P, SRC, SRC_F, REC, W.round_f32(operators.sample(u, REC))])
+    c_ref, eps_ref, lam_ref, q_ref = dbi.dbi_stage(items, c_start, m0, LAM0, NITER, tol=0.0,
+                                                   max_outer=MAX_OUTER, solve_tol=1e-13)
+    return dict(probs=probs, items=items, m0=m0, c_start=c_start, c_true=c_true, c_ref=c_ref,
+                eps_ref=eps_ref, lam_ref=lam_ref, q_ref=q_ref)
+
+
+def _plan(case, precision):
+    from paper_2402_02116_amd.plan import Plan
+    plan = Plan(case["probs"], precision=precision)
+    for i in range(len(FREQS)):
+        plan.set_contrast(i, case["c_start"])
+        plan.set_receivers(i, REC)
+    return plan
+
+
+def _d_obs(plan, case):
+    d = np.concatenate([it[4].ravel() for it in case["items"]])
+    return torch.as_tensor(d.astype(np.complex128 if plan.precision == "c128" else np.complex64)).cuda()
+
+
+@pytest.mark.parametrize("precision,tol_eps,tol_model", [("c128", 1e-9, 1e-8), ("c64", 1e-5, 1e-4)])
+def test_dbi_stage_matches_oracle(case, precision, tol_eps, tol_model):
+    """Two updates of a two-frequency stage from a 1 % start towards a 3 %
+    model: data-error history, lambdas, last update and final contrast."""
+    print(f"dbi stage {precision}", flush=True)
+    plan = _plan(case, precision)
+    rtol = 1e-12 if precision == "c128" else 1e-7
+    out = plan.dbi_run(SRC * len(FREQS), SRC_F * len(FREQS), _d_obs(plan, case), case["m0"], lam0=LAM0,
+                       niter=NITER, tol=0.0, max_outer=MAX_OUTER, rtol=rtol, maxit=2000)
+    assert out["status"] == 0 and out["updates"] == MAX_OUTER
+    e_eps = _rel(out["eps"], case["eps_ref"])
+    e_lam = _rel(out["lam"], case["lam_ref"])
+    c = plan.get_contrast(0).cpu().numpy().astype(np.float64)
+    step, step_ref = c - case["c_start"], case["c_ref"] - case["c_start"]
+    e_step = _rel(step, step_ref)
+    e_q = _rel(out["q"].cpu().numpy(), case["q_ref"])
+    print(f"  eps {out['eps']} vs {case['eps_ref']}: {e_eps:.2e}; lam {e_lam:.2e}; "
+          f"model step {e_step:.2e}; last q {e_q:.2e}", flush=True)
+    assert e_eps < tol_eps and e_lam < tol_eps
+    assert e_step < tol_model and e_q < tol_model
+    # every problem carries the same updated model
+    assert torch.equal(plan.get_contrast(1), plan.get_contrast(0))
+    # the data error falls and the final residual is the last eps
+    assert out["eps"][-1] < out["eps"][0]
+    r = out["r"].cpu().numpy()
+    d = np.concatenate([it[4].ravel() for it in case["items"]])
+    assert abs(np.linalg.norm(r) / np.linalg.norm(d) - out["eps"][-1]) < 1e-6 * out["eps"][-1]
+
+
+def test_receiver_data_and_contrast_copy_are_exact(case):
+    plan = _plan(case, "c64")
+    assert np.array_equal(plan.get_contrast(1).cpu().numpy(), case["c_start"].astype(np.float32))
+    u = plan.solve(plan.incident(SRC * len(FREQS), SRC_F * len(FREQS)), rtol=1e-6).x
+    d = plan.receiver_data(u)
+    for i in range(len(FREQS)):
+        ref = operators.sample(plan.view(u, i).cpu().numpy(), REC)
+        assert np.array_equal(plan.data_view(d, i).cpu().numpy(), ref)
+
+
+def test_exactly_fitted_data_stop_without_update(case):
+    """d_obs = R u^b of the starting model, computed by the same kernels:
+    eps_d is exactly zero, no update is made and the contrast is unchanged."""
+    plan = _plan(case, "c64")
+    u = plan.solve(plan.incident(SRC * len(FREQS), SRC_F * len(FREQS)), rtol=1e-6, maxit=2000).x
+    d_fit = plan.receiver_data(u)
+    out = plan.dbi_run(SRC * len(FREQS), SRC_F * len(FREQS), d_fit, case["m0"], lam0=LAM0, niter=NITER,
+                       tol=1e-3, max_outer=10, rtol=1e-6, maxit=2000)
+    assert out["updates"] == 0 and out["eps"] == [0.0] and out["lam"] == []
+    assert np.array_equal(plan.get_contrast(0).cpu().numpy(), case["c_start"].astype(np.float32))
+    assert torch.equal(out["ub"], u)
+
+
+def test_stopping_rule_and_argument_errors(case):
+    from paper_2402_02116_amd._lib import FwilsError
+    plan = _plan(case, "c64")
+    d = _d_obs(plan, case)
+    # a loose tolerance ends the stage as soon as the misfit is below it
+    out = plan.dbi_run(SRC * len(FREQS), SRC_F * len(FREQS), d, case["m0"], lam0=LAM0, niter=NITER, tol=0.5,
+                       max_outer=10, rtol=1e-6)
+    assert out["updates"] == 0 and out["eps"][0] < 0.5
+    with pytest.raises(FwilsError):
+        plan.dbi_run(SRC * len(FREQS), SRC_F * len(FREQS), torch.zeros_like(d), case["m0"], max_outer=2)
+    with pytest.raises(FwilsError):
+        plan.dbi_run(SRC * len(FREQS), SRC_F * len(FREQS), d, case["m0"], niter=0)
+    with pytest.raises(FwilsError):
+        plan.dbi_run([(NX, 0)] * (NSYS * len(FREQS)), SRC_F * len(FREQS), d, case["m0"])
