@@ -422,6 +422,70 @@ def cpu_baseline(c, rec, dm, r, nsample):
                        f"J, J*), complex128 numpy/scipy, {mv} matvecs in {dt:.1f} s")
 
 
+def dbi_inversion(a):
+    """Distorted-Born inversion shaped like the paper's 2-D VTI reservoir
+    example: 192 x 48 cells of 20 m, 48 surface forces, 96 receivers, nine
+    frequencies 3..19 Hz inverted one after the other, each stage stopping at
+    eps_d < 1e-3 or after 10 updates, --dbi-cg CG iterations per update
+    (lambda0 --dbi-lambda, self-adaptive cooling).  Observed data come from
+    forward solves in the true model (before the timed region); the timed
+    region is the whole sequential inversion from the smoothed model."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2402_02116_amd.dbi import invert_sequential
+    from paper_2402_02116_amd.plan import Plan
+    w = W.reservoir_dbi()
+    nsrc = len(w["src_ixz"])
+    plans, d_obs, tuned = [], [], None
+    for f in w["freqs"]:
+        plan = Plan([dict(nx=w["nx"], nz=w["nz"], dx=w["dx"], c0=w["c0"], rho0=w["rho0"], freq_hz=f,
+                          eta=w["eta"], nsys=nsrc)], device="cuda:0")
+        plan.set_receivers(0, w["rec"])
+        if a.krylov == "gmres":
+            plan.set_krylov("gmres", restart=a.restart, cgs2=not a.cgs1)
+        if not a.no_autotune:   # one grid: the first plan's choice serves every frequency
+            if tuned is None:
+                tuned = plan.autotune(reps=5)
+            else:
+                plan.set_tuning(0, **{k: v for k, v in tuned[0].items() if k != "time_us"})
+        plan.set_contrast(0, w["c_true"])
+        u = plan.solve(plan.incident(w["src_ixz"], w["src_f"]), rtol=1e-7, maxit=5000).x
+        d_obs.append(plan.receiver_data(u))
+        plans.append(plan)
+    torch.cuda.synchronize()
+    print(f"[bench] dbi: observed data at {len(plans)} frequencies", file=sys.stderr, flush=True)
+    t = time.perf_counter()
+    c, stages = invert_sequential(plans, w["src_ixz"], w["src_f"], d_obs, w["c_start"], w["m0"],
+                                  lam0=a.dbi_lambda, niter=a.dbi_cg, tol=1e-3, max_outer=10, rtol=RTOL,
+                                  maxit=5000)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t
+    for st in stages:
+        print(f"[bench] dbi {st['freq_hz']:4.1f} Hz: {st['updates']} updates, eps_d {st['eps'][0]:.4f} -> "
+              f"{st['eps'][-1]:.4f}", file=sys.stderr, flush=True)
+    c = c.double().cpu().numpy()
+    m0 = w["m0"].reshape(5, 1, 1)
+    m_true, m_start, m_end = m0 + w["c_true"], m0 + w["c_start"], m0 + c
+    eps_m = [float(np.linalg.norm(m[p] - m_true[p]) / np.linalg.norm(m_true[p])) for m in (m_start, m_end)
+             for p in range(5)]
+    updates = sum(st["updates"] for st in stages)
+    out = dict(metric=METRIC, value=round(updates / secs, 3), unit="DBI updates/s", n_gpus=1, steps=1, warmup=0,
+               ms_per_step=round(secs * 1e3, 1), higher_is_better=True, scaling="weak", vs_baseline=None,
+               dtype="c64", data="synthetic",
+               config=dict(workload="192x48 VTI (dx 20 m), random-layered true model, smoothed start, "
+                                    "48 surface forces, 96 receivers, 3..19 Hz sequential DBI "
+                                    "(eps_d < 1e-3 or 10 updates per frequency)",
+                           nsys=nsrc, cg_iters=a.dbi_cg, lambda0=a.dbi_lambda, rtol=RTOL),
+               updates=updates, s_total=round(secs, 2), ms_per_update=round(secs * 1e3 / max(updates, 1), 1),
+               stages=[dict(freq_hz=st["freq_hz"], updates=st["updates"], eps_first=round(st["eps"][0], 5),
+                            eps_last=round(st["eps"][-1], 5)) for st in stages],
+               eps_m_start=[round(x, 5) for x in eps_m[:5]], eps_m_end=[round(x, 5) for x in eps_m[5:]],
+               krylov=a.krylov, autotune=tuned)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -437,7 +501,10 @@ def main(argv=None):
     ap.add_argument("--restart", type=int, default=32, help="GMRES restart length (<= 32)")
     ap.add_argument("--cgs1", action="store_true", help="GMRES without the re-orthogonalisation pass")
     ap.add_argument("--cgs2", action="store_true", help="GMRES with the re-orthogonalisation pass")
-    ap.add_argument("--workload", choices=["vti256x16", "multigrid", "jacobian", "normal"], default="vti256x16")
+    ap.add_argument("--workload", choices=["vti256x16", "multigrid", "jacobian", "normal", "dbi"],
+                    default="vti256x16")
+    ap.add_argument("--dbi-cg", type=int, default=10, help="dbi workload: CG iterations per model update")
+    ap.add_argument("--dbi-lambda", type=float, default=1e-2, help="dbi workload: initial lambda")
     ap.add_argument("--fp64-reference", action="store_true",
                     help="normal workload: rerun the step in complex128 and report the complex64 error")
     ap.add_argument("--cg-iters", type=int, default=2, help="normal workload: CG iterations of the compared run")
@@ -460,7 +527,7 @@ def main(argv=None):
 
     torch.cuda.set_device(0)
     if a.krylov == "auto":
-        a.krylov = "gmres" if a.workload == "multigrid" else "bicgstab"
+        a.krylov = "gmres" if a.workload in ("multigrid", "dbi") else "bicgstab"
         a.cgs1 = a.cgs1 or not a.cgs2
     elif a.cgs2:
         a.cgs1 = False
@@ -470,6 +537,8 @@ def main(argv=None):
         return jacobian(a)
     if a.workload == "normal":
         return normal_cg(a)
+    if a.workload == "dbi":
+        return dbi_inversion(a)
     c, rec, dm_np, r_np = build_workload()
     nx, nz, ns = c["nx"], c["nz"], c["nsys"]
     cells = nx * nz

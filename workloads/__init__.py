@@ -208,3 +208,23 @@ def vti1024_normal(n=1024, dx=5.0, nsrc=128, nrec=201, freqs=(4.0, 7.0, 10.0)):
     dq_true = round_f32(smooth_maps(8, n, n, 10, 0.02))
     return dict(problems=probs, rec_ixz=rec, dq_true=dq_true, lam=1e-3, reg="identity",
                 m0=model_scales(c0, rho0), cg_iters=20)
+
+
+def reservoir_dbi(nx=192, nz=48, dx=20.0, nsrc=48, nrec=96, freqs=(3.0, 5.0, 7.0, 9.0, 11.0, 13.0, 15.0, 17.0, 19.0),
+                  seed=9, smooth=15.0):
+    """Stand-in for the paper's 2-D VTI reservoir inversion (its model is not
+    available): a VTI background with random-layered perturbations of all five
+    parameters (seed 9: layer offsets within 10 %, 2 % smooth noise) on 192 x 48
+    cells of 20 m (the 2^a 3^b grid nearest the example's 180 x 45), the
+    starting model its periodic Gaussian smoothing with sigma 15 cells, 48
+    vertical surface forces, 96 surface receivers and nine frequencies from
+    3 to 19 Hz, inverted one after the other."""
+    c0, rho0 = vti_background()
+    m0 = model_scales(c0, rho0)
+    q_true = random_layered(seed, nz, nx, nlayers=6, offset=0.10, std=0.02, ell=6)
+    q_start = scipy.ndimage.gaussian_filter(q_true, sigma=(0, smooth, smooth), mode="wrap")
+    src_ixz, src_f = surface_sources(nx, nsrc, iz=1)
+    rec = surface_receivers(nx, nrec, iz=1)
+    return dict(nx=nx, nz=nz, dx=dx, c0=c0, rho0=rho0, eta=0.02, freqs=tuple(freqs), m0=m0.ravel(),
+                c_true=round_f32(m0 * q_true), c_start=round_f32(m0 * q_start), src_ixz=src_ixz, src_f=src_f,
+                rec=rec)
