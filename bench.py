@@ -137,7 +137,8 @@ def _pass_instance(k, tuning, n=256):
         if tuning["col_shared"] == 2:
             return f"fw::c64::k_cols_split<{n}, {tuning['col_points']}>"
         seq = "true" if tuning["col_shared"] else "false"
-        return f"fw::c64::k_cols<{n}, {tuning['col_points']}, 0, {seq}>"
+        nt = 1024 if tuning["col_shared"] == 3 else 512
+        return f"fw::c64::k_cols<{n}, {tuning['col_points']}, 0, {seq}, {nt}>"
     return f"fw::c64::k_rows<{n}, {tuning['row_points']}, true, 1>"
 
 

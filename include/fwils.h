@@ -361,7 +361,10 @@ typedef struct {
     int32_t col_points;    /* column-transform points per thread */
     int32_t col_width;     /* columns per column workgroup (power of two) */
     int32_t col_shared;    /* 1: the two components share one LDS buffer;
-                              2: separate threads transform them          */
+                              2: separate threads transform them;
+                              3: as 1 in blocks of up to 1024 threads
+                                 (complex64, power-of-two columns of 512 or
+                                 more points, col_points 8)              */
     int32_t stencil_rows;  /* contrast-stencil tile height: 4, 8 or 16 */
     int32_t stencil_sys;   /* systems per stencil workgroup, 0 = from the grid size */
     int32_t fused_points;  /* 0: contrast stencil and forward row transform as two

@@ -56,7 +56,7 @@ void set_error(const char* fmt, ...) {
 
 constexpr int kMaxRec = 65536;
 constexpr int kChunkIters = 4;        // iterations per graph chunk (even: p buffers alternate)
-constexpr int kNumVec = 10;           // field-sized workspace vectors
+constexpr int kNumVec = 11;           // field-sized workspace vectors
 constexpr int kMaxRestarts = 3;       // restarts from the true residual per solve
 constexpr double kTrueResFactor = 2.0; // restart when ||b - A x|| > 2 rtol ||b||
 constexpr int kMaxCgIters = 1000;
@@ -102,6 +102,7 @@ struct fwils_plan_s {
     double* src_f = nullptr;
     cplx *x = nullptr, *r = nullptr, *rhat = nullptr, *p = nullptr, *p2 = nullptr, *v = nullptr,
            *s = nullptr, *t = nullptr, *tmp = nullptr, *rhs = nullptr;
+    cplx* tmp2 = nullptr;   // the separate contrast stencil's output (input of the forward rows)
     // model-map scratch of the Tikhonov step (single-grid plans only)
     size_t map_n = 0, off_mapws = 0;
     real *mq_dm = nullptr, *mq_x = nullptr, *mq_res = nullptr, *mq_p = nullptr, *mq_Ap = nullptr,
@@ -139,6 +140,7 @@ ProbDev make_dev(const fwils_problem& p) {
     d.nz = p.nz;
     d.nsys = p.nsys;
     d.symbol = p.symbol;
+    d.tile_sh = 0;   // set with the column variant (col_tile_shift)
     d.inv4dx2 = (real)(1.0 / (4.0 * p.dx * p.dx));
     d.w2 = mkc((real)w2r, (real)w2i);
     d.gc11 = (real)(p.c0[0] / rw2);
@@ -180,11 +182,12 @@ inline real* maps_at(fwils_plan pl, const ProbHost& P) { return pl->maps + P.map
 hipError_t conv_problem(fwils_plan pl, const ProbHost& P, const cplx* f, cplx* out) {
     const int rows = P.p.nsys * 2 * P.p.nz;
     cplx* tmp = at(pl->tmp, P);
-    hipError_t e = launch_rows_fwd(P.p.nx, P.cfg.row_p, f, tmp, rows, 2 * P.p.nz, nullptr, pl->tw, pl->stream);
+    hipError_t e = launch_rows_fwd(P.p.nx, P.cfg.row_p, f, tmp, rows, 2 * P.p.nz, tile_rows(P.dev), nullptr, pl->tw,
+                                   pl->stream);
     if (e == hipSuccess) e = launch_cols(COL_GREEN, P.cfg.col, tmp, P.dev, nullptr, pl->tw, pl->stream);
     if (e == hipSuccess)
         e = launch_rows_inv(P.p.nx, P.cfg.row_p, EPI_STORE, tmp, nullptr, nullptr, out, nullptr, rows,
-                            2 * P.p.nz, nullptr, pl->tw, pl->stream);
+                            2 * P.p.nz, tile_rows(P.dev), nullptr, pl->tw, pl->stream);
     return e;
 }
 
@@ -199,13 +202,15 @@ hipError_t matvec(fwils_plan pl, const ProbHost& P, const ProbDev& d, const cplx
     if (k.fuse_p) {
         const StencilArgs a{u, nullptr, nullptr, nullptr, nullptr, maps, nullptr, 0};
         e = launch_srows(0, k.fuse_p, a, tmp, d, const_cast<SysState*>(st), pl->tw, s);
-    } else {
-        e = launch_body_force(k.st, u, tmp, maps, d, st, s);
-        if (e == hipSuccess) e = launch_rows_fwd(d.nx, k.row_p, tmp, tmp, rows, 2 * d.nz, st, pl->tw, s);
+    } else {   // the stencil into tmp2 (same views as tmp), then the rows into tmp
+        cplx* tmp2 = pl->tmp2 + (tmp - pl->tmp);
+        e = launch_body_force(k.st, u, tmp2, maps, d, st, s);
+        if (e == hipSuccess) e = launch_rows_fwd(d.nx, k.row_p, tmp2, tmp, rows, 2 * d.nz, tile_rows(d), st, pl->tw, s);
     }
     if (e == hipSuccess) e = launch_cols(COL_GREEN, k.col, tmp, d, st, pl->tw, s);
     if (e == hipSuccess)
-        e = launch_rows_inv(d.nx, k.row_p, epi, tmp, u, aux, out, part, rows, 2 * d.nz, st, pl->tw, s, ge);
+        e = launch_rows_inv(d.nx, k.row_p, epi, tmp, u, aux, out, part, rows, 2 * d.nz, tile_rows(d), st, pl->tw, s,
+                            ge);
     return e;
 }
 
@@ -264,19 +269,24 @@ hipError_t bicg_iteration(fwils_plan pl, const ProbHost& P, const SysView& V, in
     // (one fused kernel, or two)
     auto stencil_rows = [&](int vm, const StencilArgs& a) -> hipError_t {
         if (k.fuse_p) return launch_srows(vm, k.fuse_p, a, tmp, V.d, st, pl->tw, s);
-        hipError_t r = launch_stencil(vm, k.st, a, V.d, st, s);
-        if (r == hipSuccess) r = launch_rows_fwd(V.d.nx, k.row_p, tmp, tmp, rows, 2 * V.d.nz, st, pl->tw, s);
+        StencilArgs a2 = a;   // the separate stencil writes tmp2, the rows read it
+        a2.b = pl->tmp2 + V.foff;
+        hipError_t r = launch_stencil(vm, k.st, a2, V.d, st, s);
+        if (r == hipSuccess)
+            r = launch_rows_fwd(V.d.nx, k.row_p, a2.b, tmp, rows, 2 * V.d.nz, tile_rows(V.d), st, pl->tw, s);
         return r;
     };
     hipError_t e = stencil_rows(first ? VM_P : VM_PX, ap);
     if (e == hipSuccess) e = launch_cols(COL_GREEN, k.col, tmp, V.d, st, pl->tw, s);
     if (e == hipSuccess)
-        e = launch_rows_inv(V.d.nx, k.row_p, EPI_BICG_V, tmp, pnew, rh, v, pV, rows, 2 * V.d.nz, st, pl->tw, s);
+        e = launch_rows_inv(V.d.nx, k.row_p, EPI_BICG_V, tmp, pnew, rh, v, pV, rows, 2 * V.d.nz, tile_rows(V.d), st,
+                            pl->tw, s);
     const StencilArgs as{r, v, nullptr, sv, tmp, maps, pV, P.np_rows};
     if (e == hipSuccess) e = stencil_rows(VM_S, as);
     if (e == hipSuccess) e = launch_cols(COL_GREEN, k.col, tmp, V.d, st, pl->tw, s);
     if (e == hipSuccess)
-        e = launch_rows_inv(V.d.nx, k.row_p, EPI_BICG_T, tmp, sv, rh, t, pT, rows, 2 * V.d.nz, st, pl->tw, s);
+        e = launch_rows_inv(V.d.nx, k.row_p, EPI_BICG_T, tmp, sv, rh, t, pT, rows, 2 * V.d.nz, tile_rows(V.d), st,
+                            pl->tw, s);
     return e;
 }
 
@@ -726,6 +736,7 @@ fwils_status fwils_plan_create(const fwils_problem* probs, int32_t nprob, fwils_
         P.data_off = 0;
         P.nrec = 0;
         P.cfg = kernel_cfg_default(P.p.nx, P.p.nz);
+        P.dev.tile_sh = col_tile_shift(P.p.nx, P.cfg.col.W);
         P.tuned_us[0] = P.tuned_us[1] = P.tuned_us[2] = P.tuned_us[3] = 0.f;
         P.np_rows = row_geom(P.p.nx, P.cfg.row_p, 2 * P.p.nz).blocks_per_sys;
         P.np_vec = vec_blocks_per_sys((int)P.n_per_sys);
@@ -840,7 +851,7 @@ fwils_status fwils_set_workspace(fwils_plan plan, void* dev, size_t bytes) {
     plan->src_i = (int32_t*)(w + plan->off_src);
     plan->src_f = (double*)(w + plan->off_src + align256(plan->total_sys * 2 * sizeof(int32_t)));
     cplx** vecs[kNumVec] = {&plan->x, &plan->r, &plan->rhat, &plan->p, &plan->p2,
-                              &plan->v, &plan->s, &plan->t, &plan->tmp, &plan->rhs};
+                              &plan->v, &plan->s, &plan->t, &plan->tmp, &plan->rhs, &plan->tmp2};
     const size_t vb = align256(plan->total_field * sizeof(cplx));
     for (int i = 0; i < kNumVec; ++i) *vecs[i] = (cplx*)(w + plan->off_vec + i * vb);
     if (plan->map_n) {
@@ -1442,17 +1453,18 @@ fwils_status fwils_apply_pass(fwils_plan plan, int32_t pass, const void* u, void
                     const StencilArgs a{at(u, P), nullptr, nullptr, nullptr, nullptr, maps_at(plan, P), nullptr, 0};
                     FW_HIP(launch_srows(0, P.cfg.fuse_p, a, tmp, P.dev, nullptr, plan->tw, s));
                 } else {
-                    FW_HIP(launch_body_force(P.cfg.st, at(u, P), tmp, maps_at(plan, P), P.dev, nullptr, s));
+                    FW_HIP(launch_body_force(P.cfg.st, at(u, P), at(plan->tmp2, P), maps_at(plan, P), P.dev, nullptr, s));
                 }
                 break;
             case 1:   // part of pass 0 when the stencil and the rows are fused
                 if (!P.cfg.fuse_p)
-                    FW_HIP(launch_rows_fwd(P.p.nx, P.cfg.row_p, tmp, tmp, rows, 2 * P.p.nz, nullptr, plan->tw, s));
+                    FW_HIP(launch_rows_fwd(P.p.nx, P.cfg.row_p, at(plan->tmp2, P), tmp, rows, 2 * P.p.nz,
+                                           tile_rows(P.dev), nullptr, plan->tw, s));
                 break;
             case 2: FW_HIP(launch_cols(COL_GREEN, P.cfg.col, tmp, P.dev, nullptr, plan->tw, s)); break;
             default:
                 FW_HIP(launch_rows_inv(P.p.nx, P.cfg.row_p, EPI_APPLY, tmp, at(u, P), nullptr,
-                                       static_cast<cplx*>(Au) + P.field_off, nullptr, rows, 2 * P.p.nz,
+                                       static_cast<cplx*>(Au) + P.field_off, nullptr, rows, 2 * P.p.nz, tile_rows(P.dev),
                                        nullptr, plan->tw, s));
         }
     }
@@ -1652,6 +1664,7 @@ bool cfg_ok(const ProbHost& P, const KernelCfg& k) {
 
 void apply_cfg(fwils_plan pl, ProbHost& P, const KernelCfg& k) {
     P.cfg = k;
+    P.dev.tile_sh = col_tile_shift(P.p.nx, k.col.W);   // the spectrum follows the column blocks
     P.np_rows = row_geom(P.p.nx, k.row_p, 2 * P.p.nz).blocks_per_sys;
     drop_graphs(pl);
 }
@@ -1706,19 +1719,25 @@ hipError_t tune_launch(fwils_plan pl, const ProbHost& P, int kind, const KernelC
     cplx* u = at(pl->x, P);
     cplx* tmp = at(pl->tmp, P);
     if (kind == FWILS_TUNE_STENCIL) return launch_body_force(k.st, u, tmp, maps_at(pl, P), P.dev, nullptr, pl->stream);
+    cplx* tmp2 = at(pl->tmp2, P);
     if (kind == FWILS_TUNE_ROWS)
-        return launch_rows_fwd(P.p.nx, k.row_p, tmp, tmp, rows, 2 * P.p.nz, nullptr, pl->tw, pl->stream);
+        return launch_rows_fwd(P.p.nx, k.row_p, tmp2, tmp, rows, 2 * P.p.nz, tile_rows(P.dev), nullptr, pl->tw,
+                               pl->stream);
     if (kind == FWILS_TUNE_FUSE) {
         // the stencil and the forward rows, fused or as two kernels
         if (k.fuse_p) {
             const StencilArgs a{u, nullptr, nullptr, nullptr, nullptr, maps_at(pl, P), nullptr, 0};
             return launch_srows(0, k.fuse_p, a, tmp, P.dev, nullptr, pl->tw, pl->stream);
         }
-        hipError_t e = launch_body_force(k.st, u, tmp, maps_at(pl, P), P.dev, nullptr, pl->stream);
-        if (e == hipSuccess) e = launch_rows_fwd(P.p.nx, k.row_p, tmp, tmp, rows, 2 * P.p.nz, nullptr, pl->tw, pl->stream);
+        hipError_t e = launch_body_force(k.st, u, tmp2, maps_at(pl, P), P.dev, nullptr, pl->stream);
+        if (e == hipSuccess)
+            e = launch_rows_fwd(P.p.nx, k.row_p, tmp2, tmp, rows, 2 * P.p.nz, tile_rows(P.dev), nullptr, pl->tw,
+                                pl->stream);
         return e;
     }
-    return launch_cols(COL_GREEN, k.col, tmp, P.dev, nullptr, pl->tw, pl->stream);
+    ProbDev d = P.dev;   // a column candidate reads the spectrum tiled for its own blocks
+    d.tile_sh = col_tile_shift(P.p.nx, k.col.W);
+    return launch_cols(COL_GREEN, k.col, tmp, d, nullptr, pl->tw, pl->stream);
 }
 
 }  // namespace
@@ -1751,6 +1770,7 @@ fwils_status fwils_autotune(fwils_plan plan, int32_t reps) {
             float tbest = 0.f;
             if (kind == FWILS_TUNE_FUSE) best.fuse_p = 0;
             P.cfg = best;   // later kinds are timed with the earlier choices
+            P.dev.tile_sh = col_tile_shift(P.p.nx, best.col.W);
             for (const KernelCfg& k : candidates(P, kind)) {
                 float ms = 0.f;
                 he = tune_launch(plan, P, kind, k);   // warm-up (and first-use set-up)
@@ -1845,15 +1865,16 @@ fwils_status fwils_fft2(fwils_plan plan, int32_t iprob, const void* in, void* ou
     const cplx* src = static_cast<const cplx*>(in);
     cplx* dst = static_cast<cplx*>(out);
     hipStream_t s = plan->stream;
+    ProbDev nat = P.dev;   // the transform itself: row-major in and out
+    nat.tile_sh = 0;
     if (!inverse) {
-        FW_HIP(launch_rows_fwd(P.p.nx, row_points_default(P.p.nx), src, dst, rows, 2 * P.p.nz, nullptr,
+        FW_HIP(launch_rows_fwd(P.p.nx, row_points_default(P.p.nx), src, dst, rows, 2 * P.p.nz, SpecLayout{}, nullptr,
                                plan->tw, s));
-        FW_HIP(launch_cols(COL_FWD, col_default(P.p.nz, P.p.nx), dst, P.dev, nullptr, plan->tw, s));
+        FW_HIP(launch_cols(COL_FWD, col_default(P.p.nz, P.p.nx), dst, nat, nullptr, plan->tw, s));
     } else {
         FW_HIP(launch_rows_inv(P.p.nx, row_points_default(P.p.nx), EPI_STORE, src, nullptr, nullptr, dst,
-                               nullptr, rows, 2 * P.p.nz,
-                               nullptr, plan->tw, s));
-        FW_HIP(launch_cols(COL_INV, col_default(P.p.nz, P.p.nx), dst, P.dev, nullptr, plan->tw, s));
+                               nullptr, rows, 2 * P.p.nz, SpecLayout{}, nullptr, plan->tw, s));
+        FW_HIP(launch_cols(COL_INV, col_default(P.p.nz, P.p.nx), dst, nat, nullptr, plan->tw, s));
     }
     return FWILS_OK;
 }

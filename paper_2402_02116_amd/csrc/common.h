@@ -76,8 +76,21 @@ __device__ __forceinline__ void st_wt(cplx* p, cplx v) {
 
 // --------------------------------------------------------- problem consts --
 // Per-problem constants, passed by value to every kernel of that problem.
+// The spectrum between the row and the column passes of a convolution may be
+// stored in column tiles as wide as a column block: each [nz][nx] plane as
+// [nx / w][nz][w] (w = 2^sh), so that a column block reads and writes one
+// contiguous run of memory instead of short segments of long rows.
+
+// Offset of element (z, x) inside one spectrum plane: tiled when tile_nz (the
+// plane's nz) is non-zero, row-major otherwise.
+__host__ __device__ __forceinline__ size_t spec_off(int z, int x, int nx, int tile_nz, int sh) {
+    return tile_nz ? ((size_t)(x >> sh) * tile_nz << sh) + ((size_t)z << sh) + (x & ((1 << sh) - 1))
+                   : (size_t)z * nx + x;
+}
+
 struct ProbDev {
     int nx, nz, nsys, symbol;
+    int tile_sh;          // the convolution's spectrum: tiles of 2^tile_sh columns, 0 = row-major
     real inv4dx2;         // 1 / (4 dx^2): both central differences of the stencil
     cplx w2;              // w~^2 = (2 pi f (1 + i eta))^2
     // Green's symbol in units of rho0 w^2 (w real): Gamma' = Gamma / (rho0 w^2)

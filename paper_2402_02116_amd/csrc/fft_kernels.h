@@ -45,14 +45,16 @@ struct RowLds {
 };
 
 // Row transforms of F rows per block, P points per thread (T = N / P threads
-// per row).  `in` and `out` may be the same array (in-place forward pass):
+// per row).  The spectrum side (the forward pass's output, the inverse pass's
+// input) is in tiles of 2^tile_sh columns when tile_nz (= nz) is non-zero.  `in` and `out`
+// may be the same array only with row-major spectra (in-place forward pass):
 // every block reads all of its rows before its barriers and writes them after.
 template <int N, int P, bool INV, int EPI>
 __global__ __launch_bounds__(256) void k_rows(const cplx* in, cplx* out,
                                               const cplx* __restrict__ u,
                                               const cplx* __restrict__ aux,
                                               double* __restrict__ partials, int nrows,
-                                              int rows_per_sys, int F,
+                                              int rows_per_sys, int F, int tile_nz, int tile_sh,
                                               SysState* __restrict__ st,
                                               const cplx* __restrict__ tw, GmEpi ge) {
     using S = FftShape<N, P>;
@@ -69,11 +71,26 @@ __global__ __launch_bounds__(256) void k_rows(const cplx* in, cplx* out,
     const int row = row0 + q;
     const bool active = (q < F) && (row < nrows);
 
+    // spectrum positions of this row's points (tiled layout: plane, row in plane)
+    size_t sbase = (size_t)row * N;
+    int srow = 0;
+    const bool tiled = tile_nz != 0;
+    if (tiled) {
+        srow = row % tile_nz;
+        sbase = (size_t)(row / tile_nz) * tile_nz * N;
+    }
+    auto spos = [&](int x) -> size_t { return sbase + (tiled ? spec_off(srow, x, N, tile_nz, tile_sh) : (size_t)x); };
+
     cplx v[1][P];
     if (active) {
-        const cplx* src = in + (size_t)row * N;
+        if constexpr (INV) {
 #pragma unroll
-        for (int m = 0; m < P; ++m) v[0][m] = src[t + T * m];
+            for (int m = 0; m < P; ++m) v[0][m] = in[spos(t + T * m)];
+        } else {
+            const cplx* src = in + (size_t)row * N;
+#pragma unroll
+            for (int m = 0; m < P; ++m) v[0][m] = src[t + T * m];
+        }
     } else {
 #pragma unroll
         for (int m = 0; m < P; ++m) v[0][m] = mkc(0.f, 0.f);
@@ -90,7 +107,7 @@ __global__ __launch_bounds__(256) void k_rows(const cplx* in, cplx* out,
             const size_t i = base + t + T * m;
             const cplx y = v[0][m];
             if constexpr (EPI == EPI_STORE) {
-                st_wt(out + i, y);
+                st_wt(out + (INV ? i : spos(t + T * m)), y);
             } else {
                 const cplx uu = u[i];
                 const cplx o = csub(uu, y);
@@ -213,9 +230,10 @@ __device__ __forceinline__ int fft_signed(int i, int n) { return (i < (n + 1) / 
 // Column transforms (with the Green multiply in COL_GREEN mode) of W columns
 // per block, P points per thread.  SEQ: the two field components share one
 // LDS buffer and go through each pass one after the other; otherwise each
-// has its own buffer (twice the LDS, half the barriers).
-template <int N, int P, int MODE, bool SEQ>
-__global__ __launch_bounds__(512) void k_cols(cplx* __restrict__ data, ProbDev pd, int W,
+// has its own buffer (twice the LDS, half the barriers).  NT: the block-size
+// bound (1024 lets long columns use 16-column, 128-byte row segments).
+template <int N, int P, int MODE, bool SEQ, int NT = 512>
+__global__ __launch_bounds__(NT) void k_cols(cplx* __restrict__ data, ProbDev pd, int W,
                                               const SysState* __restrict__ st,
                                               const cplx* __restrict__ tw) {
     using S = FftShape<N, P>;
@@ -233,14 +251,16 @@ __global__ __launch_bounds__(512) void k_cols(cplx* __restrict__ data, ProbDev p
     if (st != nullptr && st[sys].status != ST_RUNNING) return;
     const bool active = t < T;
 
-    cplx* base = data + (size_t)sys * 2 * N * nx + x0 + c;
+    // column x0 + c: row-major (stride nx) or column-tiled (stride: the tile width)
+    const int cs = pd.tile_sh ? (1 << pd.tile_sh) : nx;
+    cplx* base = data + (size_t)sys * 2 * N * nx + spec_off(0, x0 + c, nx, pd.tile_sh ? N : 0, pd.tile_sh);
     const size_t plane = (size_t)N * nx;
     cplx v[2][P];
     if (active) {
 #pragma unroll
         for (int f = 0; f < 2; ++f)
 #pragma unroll
-            for (int m = 0; m < P; ++m) v[f][m] = base[f * plane + (size_t)(t + T * m) * nx];
+            for (int m = 0; m < P; ++m) v[f][m] = base[f * plane + (size_t)(t + T * m) * cs];
     } else {
 #pragma unroll
         for (int f = 0; f < 2; ++f)
@@ -296,7 +316,7 @@ __global__ __launch_bounds__(512) void k_cols(cplx* __restrict__ data, ProbDev p
 #pragma unroll
         for (int f = 0; f < 2; ++f)
 #pragma unroll
-            for (int m = 0; m < P; ++m) st_wt(base + f * plane + (size_t)(t + T * m) * nx, v[f][m]);
+            for (int m = 0; m < P; ++m) st_wt(base + f * plane + (size_t)(t + T * m) * cs, v[f][m]);
     }
 }
 
@@ -327,10 +347,11 @@ __global__ __launch_bounds__(512) void k_cols_split(cplx* __restrict__ data, Pro
     if (st != nullptr && st[sys].status != ST_RUNNING) return;
 
     const size_t plane = (size_t)N * nx;
-    cplx* base = data + (size_t)sys * 2 * plane + comp * plane + x0 + c;
+    const int cs = pd.tile_sh ? (1 << pd.tile_sh) : nx;   // column stride: row-major or column-tiled
+    cplx* base = data + (size_t)sys * 2 * plane + comp * plane + spec_off(0, x0 + c, nx, pd.tile_sh ? N : 0, pd.tile_sh);
     cplx v[1][P];
 #pragma unroll
-    for (int m = 0; m < P; ++m) v[0][m] = base[(size_t)(t + T * m) * nx];
+    for (int m = 0; m < P; ++m) v[0][m] = base[(size_t)(t + T * m) * cs];
     const ColLds own{lds_dyn + (size_t)comp * PL * W + c, W, PL};
     const ColLds other{lds_dyn + (size_t)(1 - comp) * PL * W + c, W, PL};
     fft_run<N, P, false, 1>(v, t, tw, own);
@@ -369,7 +390,7 @@ __global__ __launch_bounds__(512) void k_cols_split(cplx* __restrict__ data, Pro
     __syncthreads();   // every partner value is read before the inverse writes LDS
     fft_run<N, P, true, 1>(v, t, tw, own);
 #pragma unroll
-    for (int m = 0; m < P; ++m) st_wt(base + (size_t)(t + T * m) * nx, v[0][m]);
+    for (int m = 0; m < P; ++m) st_wt(base + (size_t)(t + T * m) * cs, v[0][m]);
 }
 
 // ----------------------------------------------------- launch helpers ----
@@ -383,8 +404,10 @@ inline hipError_t allow_lds(K kernel, size_t bytes) {
 
 template <int N, int P, bool INV, int EPI>
 inline hipError_t rows_launch(const cplx* in, cplx* out, const cplx* u, const cplx* aux,
-                              double* part, int nrows, int rps, const SysState* st, const cplx* tw,
-                              hipStream_t s, const GmEpi* ge = nullptr) {
+                              double* part, int nrows, int rps, SpecLayout lay, const SysState* st,
+                              const cplx* tw, hipStream_t s, const GmEpi* ge = nullptr) {
+    if (lay.nz && (lay.sh < 1 || N % (1 << lay.sh) != 0 || in == out || rps != 2 * lay.nz))
+        return hipErrorInvalidValue;
     const GmEpi gz{nullptr, 0, 0, nullptr};
     const RowGeom g = row_geom(N, P, rps);
     const int blocks = (nrows + g.F - 1) / g.F;
@@ -392,7 +415,7 @@ inline hipError_t rows_launch(const cplx* in, cplx* out, const cplx* u, const cp
     hipError_t e = allow_lds(k_rows<N, P, INV, EPI>, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_rows<N, P, INV, EPI>), dim3(blocks), dim3(g.threads), lds, s, in, out, u, aux,
-                       part, nrows, rps, g.F, const_cast<SysState*>(st), tw, ge ? *ge : gz);
+                       part, nrows, rps, g.F, lay.nz, lay.sh, const_cast<SysState*>(st), tw, ge ? *ge : gz);
     return hipGetLastError();
 }
 
@@ -407,14 +430,15 @@ inline hipError_t cols_split_launch(cplx* data, const ProbDev& pd, int W, const 
     return hipGetLastError();
 }
 
-template <int N, int P, int MODE, bool SEQ>
+template <int N, int P, int MODE, bool SEQ, int NT = 512>
 inline hipError_t cols_launch(cplx* data, const ProbDev& pd, int W, const SysState* st,
                               const cplx* tw, hipStream_t s) {
-    const ColGeom g = col_geom(N, pd.nx, ColCfg{P, W, SEQ ? 1 : 0});
+    const ColGeom g = col_geom(N, pd.nx, ColCfg{P, W, NT > 512 ? 3 : SEQ ? 1 : 0});
+    if (g.threads > NT) return hipErrorInvalidValue;
     const int blocks = pd.nsys * (pd.nx / W);
-    hipError_t e = allow_lds(k_cols<N, P, MODE, SEQ>, g.lds);
+    hipError_t e = allow_lds(k_cols<N, P, MODE, SEQ, NT>, g.lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_cols<N, P, MODE, SEQ>), dim3(blocks), dim3(g.threads), g.lds, s, data, pd, W,
+    hipLaunchKernelGGL((k_cols<N, P, MODE, SEQ, NT>), dim3(blocks), dim3(g.threads), g.lds, s, data, pd, W,
                        st, tw);
     return hipGetLastError();
 }

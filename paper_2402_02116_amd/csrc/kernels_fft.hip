@@ -29,6 +29,19 @@ static int row_points_alt(int n) { return (n % 3 == 0) ? 24 : 8; }
 static int col_points_alt(int n) { return (n % 3 == 0) ? 24 : 16; }
 #endif
 
+// The 1024-thread shared-buffer column pass exists for long power-of-two
+// columns with 8 points per thread only (complex64): more points per thread
+// exceed the 128 registers of a 1024-thread block and spill.
+static bool cols_wide_built(int n, int P) {
+#ifdef FW_C128
+    (void)n;
+    (void)P;
+    return false;
+#else
+    return n >= 512 && n % 3 != 0 && P == 8;
+#endif
+}
+
 bool fft_size_supported(int n) {
     for (int s : kSizes)
         if (s == n) return true;
@@ -92,6 +105,7 @@ ColGeom col_geom(int nz, int nx, const ColCfg& c) {
     (void)nx;
     const int T = nz / c.P;
     ColGeom g;
+    // seq 3: the shared-buffer pass (seq 1) in blocks of up to 1024 threads
     if (c.seq == 2) {   // both components' columns in LDS, no idle threads
         g.threads = 2 * c.W * T;
         g.slots = c.W;
@@ -107,10 +121,11 @@ ColGeom col_geom(int nz, int nx, const ColCfg& c) {
 bool col_cfg_ok(int nz, int nx, const ColCfg& c) {
     if (!fft_size_supported(nz) || c.P <= 0 || nz % c.P != 0) return false;
     if (c.P != col_points_default(nz) && c.P != col_points_alt(nz)) return false;
-    if (c.seq < 0 || c.seq > 2) return false;
+    if (c.seq < 0 || c.seq > 3) return false;
     if (c.W < 1 || c.W > 64 || nx % c.W != 0 || (c.W & (c.W - 1)) != 0) return false;
     const ColGeom g = col_geom(nz, nx, c);
     if (c.seq == 2) return g.threads % 64 == 0 && g.threads <= 512 && g.lds <= kMaxLds;
+    if (c.seq == 3) return cols_wide_built(nz, c.P) && g.threads > 512 && g.threads <= 1024 && g.lds <= kMaxLds;
     return g.threads <= 512 && g.lds <= kMaxLds;
 }
 
@@ -128,7 +143,7 @@ int col_candidates(int nz, int nx, ColCfg* out, int cap) {
     const int ps[2] = {col_points_default(nz), col_points_alt(nz)};
     for (int i = 0; i < (ps[1] == ps[0] ? 1 : 2); ++i) {
         const int P = ps[i];
-        for (int seq = 2; seq >= 0; --seq)
+        for (int seq = 3; seq >= 0; --seq)
             for (int W = 4; W <= 32; W *= 2) {
                 const ColCfg c{P, W, seq};
                 if (col_cfg_ok(nz, nx, c) && k < cap) out[k++] = c;

@@ -17,13 +17,13 @@ FW_BEGIN
     X(1536, 24) X(2048, 16) X(2048, 8)
 #endif
 
-hipError_t launch_rows_fwd(int n, int P, const cplx* in, cplx* out, int nrows, int rps,
+hipError_t launch_rows_fwd(int n, int P, const cplx* in, cplx* out, int nrows, int rps, SpecLayout lay,
                            const SysState* st, const cplx* tw, hipStream_t s) {
     if (!row_points_ok(n, P)) return hipErrorInvalidValue;
     const cplx* t = tw + twiddle_offset(n);
 #define FW_CASE(N, PP) \
     if (n == N && P == PP) \
-        return rows_launch<N, PP, false, EPI_STORE>(in, out, nullptr, nullptr, nullptr, nrows, rps, st, t, s);
+        return rows_launch<N, PP, false, EPI_STORE>(in, out, nullptr, nullptr, nullptr, nrows, rps, lay, st, t, s);
     FW_ROW_VARIANTS(FW_CASE)
 #undef FW_CASE
     return hipErrorInvalidValue;
@@ -31,14 +31,14 @@ hipError_t launch_rows_fwd(int n, int P, const cplx* in, cplx* out, int nrows, i
 
 template <int N, int P>
 static hipError_t rows_inv_np(int epi, const cplx* in, const cplx* u, const cplx* aux, cplx* out,
-                              double* part, int nrows, int rps, const SysState* st, const cplx* tw,
-                              hipStream_t s, const GmEpi* ge) {
+                              double* part, int nrows, int rps, SpecLayout lay, const SysState* st,
+                              const cplx* tw, hipStream_t s, const GmEpi* ge) {
     if ((epi == EPI_ARNOLDI || epi == EPI_GMRES_R0) && (!ge || !ge->part))
         return hipErrorInvalidValue;
     if (epi == EPI_ARNOLDI && (!ge->V || ge->nv < 1 || ge->nv > kGmMax + 1)) return hipErrorInvalidValue;
     switch (epi) {
 #define FW_EPI(E) \
-    case E: return rows_launch<N, P, true, E>(in, out, u, aux, part, nrows, rps, st, tw, s, ge);
+    case E: return rows_launch<N, P, true, E>(in, out, u, aux, part, nrows, rps, lay, st, tw, s, ge);
         FW_EPI(EPI_STORE) FW_EPI(EPI_APPLY) FW_EPI(EPI_BICG_V) FW_EPI(EPI_BICG_T) FW_EPI(EPI_TRUERES)
         FW_EPI(EPI_ARNOLDI) FW_EPI(EPI_GMRES_R0)
 #undef FW_EPI
@@ -47,12 +47,12 @@ static hipError_t rows_inv_np(int epi, const cplx* in, const cplx* u, const cplx
 }
 
 hipError_t launch_rows_inv(int n, int P, int epi, const cplx* in, const cplx* u, const cplx* aux,
-                           cplx* out, double* part, int nrows, int rps, const SysState* st,
+                           cplx* out, double* part, int nrows, int rps, SpecLayout lay, const SysState* st,
                            const cplx* tw, hipStream_t s, const GmEpi* ge) {
     if (!row_points_ok(n, P)) return hipErrorInvalidValue;
     const cplx* t = tw + twiddle_offset(n);
 #define FW_CASE(N, PP) \
-    if (n == N && P == PP) return rows_inv_np<N, PP>(epi, in, u, aux, out, part, nrows, rps, st, t, s, ge);
+    if (n == N && P == PP) return rows_inv_np<N, PP>(epi, in, u, aux, out, part, nrows, rps, lay, st, t, s, ge);
     FW_ROW_VARIANTS(FW_CASE)
 #undef FW_CASE
     return hipErrorInvalidValue;

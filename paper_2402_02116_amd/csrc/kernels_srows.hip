@@ -234,10 +234,11 @@ __global__ __launch_bounds__(NT) void k_srows(const cplx* __restrict__ u, const 
     // 3. forward row transforms (idle threads work in a dummy slot)
     RowLdsF lds{lds_dyn + (size_t)(active ? q : 2 * F) * PL};
     fft_run<N, P, false, 1>(v, t, tw, lds);
-    if (active) {
-        cplx* o = out + so + c * plane + zr;
+    if (active) {   // the spectrum: row-major or column-tiled
+        cplx* o = out + so + c * plane;
+        const int tnz = pd.tile_sh ? nz : 0;
 #pragma unroll
-        for (int m = 0; m < P; ++m) st_wt(o + t + T * m, v[0][m]);
+        for (int m = 0; m < P; ++m) st_wt(o + spec_off(z, t + T * m, N, tnz, pd.tile_sh), v[0][m]);
     }
 }
 

@@ -80,14 +80,30 @@ void twiddle_table_fill(cplx* host);
 // Row transforms over nrows rows of length n (rows_per_sys rows per system;
 // a block never straddles systems).  st (may be null): systems whose status is
 // not RUNNING are skipped.
-// P is the points-per-thread variant (row_points_ok).
-hipError_t launch_rows_fwd(int n, int P, const cplx* in, cplx* out, int nrows, int rows_per_sys,
+// P is the points-per-thread variant (row_points_ok).  lay: the layout of
+// the spectrum side (the forward pass's output, the inverse pass's input):
+// row-major (nz = 0) or tiles of 2^sh columns (needs distinct in / out).
+struct SpecLayout {
+    int nz = 0, sh = 0;
+};
+hipError_t launch_rows_fwd(int n, int P, const cplx* in, cplx* out, int nrows, int rows_per_sys, SpecLayout lay,
                            const SysState* st, const cplx* tw, hipStream_t s);
 hipError_t launch_rows_inv(int n, int P, int epi, const cplx* in, const cplx* u, const cplx* aux,
-                           cplx* out, double* partials, int nrows, int rows_per_sys,
+                           cplx* out, double* partials, int nrows, int rows_per_sys, SpecLayout lay,
                            const SysState* st, const cplx* tw, hipStream_t s, const GmEpi* ge = nullptr);
-// Column pass over [nsys][2][nz][nx] in place.  COL_FWD / COL_INV exist in
-// the default points-per-thread variant with shared LDS only.
+// The spectrum layout of problem d's convolutions.
+inline SpecLayout tile_rows(const ProbDev& d) { return d.tile_sh ? SpecLayout{d.nz, d.tile_sh} : SpecLayout{}; }
+// Column-tile shift for a column pass of W-column blocks on rows of nx points:
+// tiles as wide as the block (8 to 32 columns), row-major for narrower blocks.
+inline int col_tile_shift(int nx, int W) {
+    if (W < 8 || nx % W != 0 || (W & (W - 1)) != 0) return 0;
+    int sh = 0;
+    while ((1 << sh) < W) ++sh;
+    return sh;
+}
+// Column pass over [nsys][2][nz][nx] in place (column-tiled when pd.tile_sh).
+// COL_FWD / COL_INV exist in the default points-per-thread variant with
+// shared LDS only.
 hipError_t launch_cols(int mode, const ColCfg& c, cplx* data, const ProbDev& pd, const SysState* st,
                        const cplx* tw, hipStream_t s);
 
