@@ -370,9 +370,11 @@ typedef struct {
     int32_t fused_points;  /* 0: contrast stencil and forward row transform as two
                               kernels; else one fused kernel with this many points
                               per thread (rows of at most 512 points) */
-    float time_us[4];      /* autotuner's time of the chosen stencil, row, column and
-                              stencil + row kernels over all systems of the problem
-                              (0 if not tuned) */
+    float time_us[4];      /* autotuner's time over all systems of the problem of the
+                              chosen stencil, forward row pass, column variant (with
+                              the forward and inverse row passes on the spectrum
+                              layout it sets: tiles as wide as its blocks) and
+                              stencil + row kernels (0 if not tuned) */
 } fwils_tuning;
 
 #define FWILS_TUNE_STENCIL 0

@@ -1735,9 +1735,18 @@ hipError_t tune_launch(fwils_plan pl, const ProbHost& P, int kind, const KernelC
                                 pl->stream);
         return e;
     }
-    ProbDev d = P.dev;   // a column candidate reads the spectrum tiled for its own blocks
+    // A column variant also fixes the spectrum layout (tiles as wide as its
+    // blocks) that both row passes write and read: it is timed with them, as
+    // the three passes of one convolution.
+    ProbDev d = P.dev;
     d.tile_sh = col_tile_shift(P.p.nx, k.col.W);
-    return launch_cols(COL_GREEN, k.col, tmp, d, nullptr, pl->tw, pl->stream);
+    hipError_t e = launch_rows_fwd(P.p.nx, k.row_p, tmp2, tmp, rows, 2 * P.p.nz, tile_rows(d), nullptr, pl->tw,
+                                   pl->stream);
+    if (e == hipSuccess) e = launch_cols(COL_GREEN, k.col, tmp, d, nullptr, pl->tw, pl->stream);
+    if (e == hipSuccess)
+        e = launch_rows_inv(P.p.nx, k.row_p, EPI_STORE, tmp, nullptr, nullptr, tmp2, nullptr, rows, 2 * P.p.nz,
+                            tile_rows(d), nullptr, pl->tw, pl->stream);
+    return e;
 }
 
 }  // namespace

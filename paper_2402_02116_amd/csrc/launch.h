@@ -94,9 +94,9 @@ hipError_t launch_rows_inv(int n, int P, int epi, const cplx* in, const cplx* u,
 // The spectrum layout of problem d's convolutions.
 inline SpecLayout tile_rows(const ProbDev& d) { return d.tile_sh ? SpecLayout{d.nz, d.tile_sh} : SpecLayout{}; }
 // Column-tile shift for a column pass of W-column blocks on rows of nx points:
-// tiles as wide as the block (8 to 32 columns), row-major for narrower blocks.
+// tiles as wide as the block (4 to 32 columns), row-major for narrower blocks.
 inline int col_tile_shift(int nx, int W) {
-    if (W < 8 || nx % W != 0 || (W & (W - 1)) != 0) return 0;
+    if (W < 4 || nx % W != 0 || (W & (W - 1)) != 0) return 0;
     int sh = 0;
     while ((1 << sh) < W) ++sh;
     return sh;
