@@ -497,8 +497,9 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the built-in kernel variants")
     ap.add_argument("--krylov", choices=["auto", "bicgstab", "gmres"], default="auto",
-                    help="auto: BiCGSTAB for the 256^2 workload (few iterations), GMRES(32) with one "
-                         "Gram-Schmidt pass for the four-grid workload (hard 12 Hz systems)")
+                    help="auto: GMRES(32) with one Gram-Schmidt pass for the four-grid workload (hard "
+                         "12 Hz systems), BiCGSTAB for the others (1.7x faster than GMRES on the dbi "
+                         "workload, whose small systems make the Arnoldi projections dominate)")
     ap.add_argument("--restart", type=int, default=32, help="GMRES restart length (<= 32)")
     ap.add_argument("--cgs1", action="store_true", help="GMRES without the re-orthogonalisation pass")
     ap.add_argument("--cgs2", action="store_true", help="GMRES with the re-orthogonalisation pass")
@@ -528,7 +529,7 @@ def main(argv=None):
 
     torch.cuda.set_device(0)
     if a.krylov == "auto":
-        a.krylov = "gmres" if a.workload in ("multigrid", "dbi") else "bicgstab"
+        a.krylov = "gmres" if a.workload == "multigrid" else "bicgstab"
         a.cgs1 = a.cgs1 or not a.cgs2
     elif a.cgs2:
         a.cgs1 = False
