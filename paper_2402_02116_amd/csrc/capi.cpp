@@ -742,7 +742,7 @@ fwils_status fwils_plan_create(const fwils_problem* probs, int32_t nprob, fwils_
         P.np_vec = vec_blocks_per_sys((int)P.n_per_sys);
         pl->max_np = std::max(pl->max_np, P.np_vec);
         {   // partial buffers fit every row-transform variant
-            int cand[2];
+            int cand[3];
             const int nc = row_candidates(P.p.nx, cand);
             for (int c = 0; c < nc; ++c)
                 pl->max_np = std::max(pl->max_np, row_geom(P.p.nx, cand[c], 2 * P.p.nz).blocks_per_sys);
@@ -1543,7 +1543,7 @@ GmLayout gm_layout(fwils_plan pl, int m) {
     GmLayout L;
     L.maxnb = 0;
     for (const ProbHost& P : pl->probs) {
-        int cand[2];
+        int cand[3];
         const int nc = row_candidates(P.p.nx, cand);
         for (int c = 0; c < nc; ++c)
             L.maxnb = std::max(L.maxnb, (size_t)row_geom(P.p.nx, cand[c], 2 * P.p.nz).blocks_per_sys);
@@ -1682,7 +1682,7 @@ std::vector<KernelCfg> candidates(const ProbHost& P, int kind) {
             out.push_back(k);
         }
     } else if (kind == FWILS_TUNE_ROWS) {
-        int c[2];
+        int c[3];
         const int n = row_candidates(P.p.nx, c);
         for (int i = 0; i < n; ++i) {
             KernelCfg k = P.cfg;
@@ -1701,7 +1701,7 @@ std::vector<KernelCfg> candidates(const ProbHost& P, int kind) {
         KernelCfg k = P.cfg;
         k.fuse_p = 0;
         out.push_back(k);
-        int c[2];
+        int c[3];
         const int n = row_candidates(P.p.nx, c);
         for (int i = 0; i < n; ++i) {
             if (!fuse_ok(P, c[i])) continue;

@@ -10,8 +10,8 @@
 // is therefore loaded from and stored to global memory in coalesced
 // t-fastest order, and only the passes in between go through LDS.
 //
-// The radix sequence is chosen at compile time from {16, 8, 4, 2, 3}; every
-// radix must divide P.  Twiddles come from a length-N table
+// The radix sequence is chosen at compile time from {32, 16, 8, 4, 2, 3};
+// every radix must divide P.  Twiddles come from a length-N table
 // tw[m] = exp(-2 pi i m / N) (double-rounded on the host); the inverse uses
 // conjugates.  No normalisation is applied in either direction.
 #pragma once
@@ -26,11 +26,11 @@ struct RadixPlan {
 
 constexpr RadixPlan radix_plan(int N, int P) {
     RadixPlan pl{0, {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0}};
-    const int cand[5] = {16, 8, 4, 2, 3};
+    const int cand[6] = {32, 16, 8, 4, 2, 3};
     int rem = N;
     while (rem > 1) {
         int pick = 0;
-        for (int i = 0; i < 5; ++i) {
+        for (int i = 0; i < 6; ++i) {
             if (P % cand[i] == 0 && rem % cand[i] == 0) { pick = cand[i]; break; }
         }
         if (pick == 0 || pl.np == 16) { pl.np = -1; return pl; }
@@ -148,6 +148,52 @@ __device__ __forceinline__ void dft16(cplx (&x)[16]) {
     for (int k = 0; k < 16; ++k) x[k] = y[k];
 }
 
+// multiply by W_32^e for compile-time e (odd e from cos(k pi / 16), k = 1..7)
+template <bool INV, int E>
+__device__ __forceinline__ cplx twc32(cplx z) {
+    constexpr int e = ((E % 32) + 32) % 32;
+    if constexpr (e % 2 == 0) {
+        return twc<INV, 16, e / 2>(z);
+    } else {
+        // cos(2 pi q / 32) for q = 0..8
+        constexpr double K[9] = {1.0, 0.980785280403230449126, 0.923879532511286756128,
+                                 0.831469612302545237079, 0.707106781186547524401, 0.555570233019602224743,
+                                 0.382683432365089771729, 0.195090322016128267848, 0.0};
+        // cos and sin of 2 pi e / 32 from the first octant by symmetry
+        constexpr int q = e % 8, o = e / 8;   // e = 8 o + q, 0 < q < 8
+        constexpr double c0 = K[q], s0 = K[8 - q];
+        constexpr double cc = o == 0 ? c0 : o == 1 ? -s0 : o == 2 ? -c0 : s0;
+        constexpr double ss = o == 0 ? s0 : o == 1 ? c0 : o == 2 ? -s0 : -c0;
+        constexpr real c = (real)cc;
+        constexpr real sn = INV ? (real)ss : -(real)ss;   // W = c + i sn
+        return mkc(z.x * c - z.y * sn, z.x * sn + z.y * c);
+    }
+}
+
+template <int K, bool INV>
+__device__ __forceinline__ void dft32_combine(cplx (&x)[32], const cplx (&e)[16], const cplx (&o)[16]) {
+    if constexpr (K < 16) {
+        const cplx t = twc32<INV, K>(o[K]);
+        x[K] = cadd(e[K], t);
+        x[K + 16] = csub(e[K], t);
+        dft32_combine<K + 1, INV>(x, e, o);
+    }
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft32(cplx (&x)[32]) {
+    // even / odd 16-point halves, then X[k] = E[k] +- W32^k O[k]
+    cplx e[16], o[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        e[i] = x[2 * i];
+        o[i] = x[2 * i + 1];
+    }
+    dft16<INV>(e);
+    dft16<INV>(o);
+    dft32_combine<0, INV>(x, e, o);
+}
+
 template <bool INV>
 __device__ __forceinline__ void dft3(cplx& x0, cplx& x1, cplx& x2) {
     const real h = (real)0.86602540378443864676;   // sqrt(3) / 2
@@ -166,13 +212,15 @@ __device__ __forceinline__ void dft(cplx (&x)[R]) {
     else if constexpr (R == 4) dft4<INV>(x[0], x[1], x[2], x[3]);
     else if constexpr (R == 8) dft8<INV>(x);
     else if constexpr (R == 16) dft16<INV>(x);
+    else if constexpr (R == 32) dft32<INV>(x);
     else static_assert(R == 2, "unsupported radix");
 }
 
 // --------------------------------------------------------------- twiddles --
 // w[r] = W^(r e) for r = 1..R-1, where W^e = tw[e] (forward; conjugated for
-// the inverse).  Only W^e and, for R >= 8, W^(4e) are read from the table; the
-// other powers are products of at most four factors (a few ulp).
+// the inverse).  Only W^e, for R >= 8 W^(4e) and for R = 32 W^(16e) are read
+// from the table; the other powers are products of at most five factors (a
+// few ulp).
 template <int R, bool INV>
 __device__ __forceinline__ void twiddles(cplx (&w)[R], const cplx* __restrict__ tw, int e) {
     cplx w1 = tw[e];
@@ -187,7 +235,7 @@ __device__ __forceinline__ void twiddles(cplx (&w)[R], const cplx* __restrict__ 
 #pragma unroll
         for (int r = 5; r < 8; ++r) w[r] = cmul(w4, w[r - 4]);
     }
-    if constexpr (R == 16) {
+    if constexpr (R >= 16) {
         const cplx w8 = cmul(w[4], w[4]);
         const cplx w12 = cmul(w8, w[4]);
         w[8] = w8;
@@ -197,6 +245,13 @@ __device__ __forceinline__ void twiddles(cplx (&w)[R], const cplx* __restrict__ 
             w[8 + r] = cmul(w8, w[r]);
             w[12 + r] = cmul(w12, w[r]);
         }
+    }
+    if constexpr (R == 32) {
+        cplx w16 = tw[16 * e];
+        if (INV) w16 = cconj(w16);
+        w[16] = w16;
+#pragma unroll
+        for (int r = 1; r < 16; ++r) w[16 + r] = cmul(w16, w[r]);
     }
 }
 

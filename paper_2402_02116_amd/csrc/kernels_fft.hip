@@ -24,9 +24,15 @@ static int col_points_default(int n) { return (n % 3 == 0) ? 12 : 8; }
 #ifdef FW_C128
 static int row_points_alt(int n) { return row_points_default(n); }
 static int col_points_alt(int n) { return col_points_default(n); }
+static int points_radix32(int) { return 0; }
 #else
 static int row_points_alt(int n) { return (n % 3 == 0) ? 24 : 8; }
 static int col_points_alt(int n) { return (n % 3 == 0) ? 24 : 16; }
+// A third row-pass variant for 512- and 1024-point rows: 32 points per
+// thread, radix-32 passes (32 x 32 at 1024 points: one LDS exchange per
+// direction instead of two).  Column passes hold both field components (or
+// twice the threads) and spill at 32 points, so they have none.
+static int points_radix32(int n) { return (n == 512 || n == 1024) ? 32 : 0; }
 #endif
 
 // The 1024-thread shared-buffer column pass exists for long power-of-two
@@ -76,13 +82,15 @@ void twiddle_table_fill(cplx* host) {
 }
 
 bool row_points_ok(int n, int P) {
-    return fft_size_supported(n) && (P == row_points_default(n) || P == row_points_alt(n)) && n % P == 0;
+    return fft_size_supported(n) && n % P == 0 &&
+           (P == row_points_default(n) || P == row_points_alt(n) || P == points_radix32(n));
 }
 
 int row_candidates(int n, int* out) {
     int k = 0;
     out[k++] = row_points_default(n);
     if (row_points_alt(n) != out[0] && n % row_points_alt(n) == 0) out[k++] = row_points_alt(n);
+    if (points_radix32(n)) out[k++] = points_radix32(n);
     return k;
 }
 

@@ -14,7 +14,7 @@ FW_BEGIN
     X(16, 16) X(16, 8) X(24, 12) X(24, 24) X(32, 16) X(32, 8) X(48, 12) X(48, 24) X(64, 16) X(64, 8) \
     X(96, 12) X(96, 24) X(128, 16) X(128, 8) X(192, 12) X(192, 24) X(256, 16) X(256, 8) X(384, 12)  \
     X(384, 24) X(512, 16) X(512, 8) X(768, 12) X(768, 24) X(1024, 16) X(1024, 8) X(1536, 12)         \
-    X(1536, 24) X(2048, 16) X(2048, 8)
+    X(1536, 24) X(2048, 16) X(2048, 8) X(512, 32) X(1024, 32)
 #endif
 
 hipError_t launch_rows_fwd(int n, int P, const cplx* in, cplx* out, int nrows, int rps, SpecLayout lay,

@@ -258,7 +258,7 @@ int srows_rows(int nx, int nz, int P, int vm) {
     (void)nx, (void)nz, (void)P, (void)vm;
     return 0;   // the complex128 build keeps the stencil and the row pass apart
 #endif
-    if (nx > kSrowsMaxN || nx % P != 0) return 0;
+    if (nx > kSrowsMaxN || nx % P != 0 || P > 24) return 0;   // no fused radix-32 variant
     const int T = nx / P;
     if (T > 128) return 0;
     int F = (srows_wide(nx, P, vm) ? 256 : 128) / T;

@@ -62,7 +62,7 @@ ColGeom col_geom(int nz, int nx, const ColCfg& c);
 // Variants: defaults, validity, and the candidate lists of the autotuner.
 int row_points_default(int n);
 bool row_points_ok(int n, int P);
-int row_candidates(int n, int* out);          // at most 2
+int row_candidates(int n, int* out);          // at most 3
 ColCfg col_default(int nz, int nx);
 bool col_cfg_ok(int nz, int nx, const ColCfg& c);
 int col_candidates(int nz, int nx, ColCfg* out, int cap);
