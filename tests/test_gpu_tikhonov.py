@@ -108,3 +108,32 @@ def test_normal_cg_matches_oracle(case):
     assert _rel(hist, np.array(hist_o)) < 1e-3
     assert _rel(q.cpu().numpy(), qo) < 1e-3
     assert hist[-1] < hist[0]
+
+
+def test_adjoint_identity_at_full_size_512():
+    """Re <r, J (m0 q)> = <m0 Re J* r, q> on the 512^2 workload (32 forces x two
+    frequencies = 64 systems, 101 receivers), in the launch configuration the
+    bench times: the property that pins J and J* against each other at the
+    size the CPU oracle cannot reach."""
+    from paper_2402_02116_amd.plan import Plan
+    w = W.vti512_jacobian()
+    probs, rec = w["problems"], w["rec_ixz"]
+    print("adjoint identity 512^2 x 64 systems", flush=True)
+    plan = Plan([dict(nx=p["nx"], nz=p["nz"], dx=p["dx"], c0=p["c0"], rho0=p["rho0"], freq_hz=p["freq_hz"],
+                      eta=p["eta"], nsys=p["nsys"]) for p in probs])
+    for i, p in enumerate(probs):
+        plan.set_contrast(i, p["maps"])
+        plan.set_receivers(i, rec)
+    plan.autotune(reps=3)
+    src = sum((p["src_ixz"] for p in probs), [])
+    frc = sum((p["src_f"] for p in probs), [])
+    ub = plan.solve(plan.incident(src, frc), rtol=1e-6, maxit=2000).x
+    m0v = w["m0"].ravel()
+    q = torch.as_tensor(w["dq"], dtype=torch.float32).cuda()
+    r = torch.as_tensor(np.concatenate([x.ravel() for x in w["r"]]).astype(np.complex64)).cuda()
+    d = plan.frechet_rel(ub, q, m0v, rtol=1e-7).cpu().numpy().astype(np.complex128)
+    gq = plan.adjoint_rel(ub, r, m0v, rtol=1e-7).cpu().numpy().astype(np.float64)
+    lhs = float(np.vdot(r.cpu().numpy().astype(np.complex128), d).real)
+    rhs = float(np.sum(gq * w["dq"]))
+    print(f"  <r, J q> = {lhs:.6e}, <J* r, q> = {rhs:.6e}", flush=True)
+    assert abs(lhs - rhs) <= 1e-4 * abs(lhs)
