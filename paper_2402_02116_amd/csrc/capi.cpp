@@ -373,15 +373,9 @@ fwils_status bicg_solve_ws(fwils_plan pl, const cplx* b, bool use_x0, double rto
                                       part_at(pl->partB, pl, P), P.p.nsys, P.np_vec, rtol, maxit, s));
     }
     const size_t nst = pl->total_sys;
-    auto all_done = [&](bool& done) -> fwils_status {
-        FW_HIP(hipMemcpyAsync(pl->host_state, pl->state, nst * sizeof(SysState), hipMemcpyDeviceToHost, s));
-        FW_HIP(hipStreamSynchronize(s));
-        done = true;
-        for (size_t i = 0; i < nst; ++i)
-            if (pl->host_state[i].status == ST_RUNNING) done = false;
-        return FWILS_OK;
-    };
-    auto iterate = [&]() -> fwils_status {
+    // known: pl->host_state holds the current states (else the first chunk is
+    // queued without a look: its kernels exit at once for stopped systems)
+    auto iterate = [&](bool known) -> fwils_status {
         if (flags & FWILS_SOLVE_PLAIN) {
             // per-source loop, host-synchronous check after every iteration
             for (const ProbHost& P : pl->probs) {
@@ -402,8 +396,12 @@ fwils_status bicg_solve_ws(fwils_plan pl, const cplx* b, bool use_x0, double rto
         }
         const int max_chunks = maxit / kChunkIters + 2;
         bool done = false;
-        FW_TRY(all_done(done));
-        if (done) return FWILS_OK;
+        if (known) {
+            done = true;
+            for (size_t i = 0; i < nst; ++i)
+                if (pl->host_state[i].status == ST_RUNNING) done = false;
+            if (done) return FWILS_OK;
+        }
         if (!(flags & FWILS_SOLVE_NOGRAPH)) FW_TRY(build_chunk_graphs(pl));
         // Chunk c + 1 is queued before the state after chunk c is inspected, so
         // the device does not wait for the host between chunks; a chunk queued
@@ -423,7 +421,7 @@ fwils_status bicg_solve_ws(fwils_plan pl, const cplx* b, bool use_x0, double rto
             return FWILS_OK;
         };
         std::vector<double> prev(nst);
-        for (size_t i = 0; i < nst; ++i) prev[i] = pl->host_state[i].rnorm2;
+        for (size_t i = 0; i < nst; ++i) prev[i] = known ? pl->host_state[i].rnorm2 : 0.0;
         int launched = 0;
         bool last_likely = false;
         FW_TRY(launch(0));
@@ -457,9 +455,14 @@ fwils_status bicg_solve_ws(fwils_plan pl, const cplx* b, bool use_x0, double rto
     // recursive residual drifted (bounded number of restarts per system).
     const double limit2 = (kTrueResFactor * rtol) * (kTrueResFactor * rtol);
     for (int round = 0;; ++round) {
-        FW_HIP(hipMemcpyAsync(pl->host_state, pl->state, nst * sizeof(SysState), hipMemcpyDeviceToHost, s));
-        FW_HIP(hipStreamSynchronize(s));
-        FW_TRY(iterate());
+        // the plain loop reads every system's state first; the batched one
+        // starts the first round without a host round trip
+        const bool look = round > 0 || (flags & FWILS_SOLVE_PLAIN);
+        if (look) {
+            FW_HIP(hipMemcpyAsync(pl->host_state, pl->state, nst * sizeof(SysState), hipMemcpyDeviceToHost, s));
+            FW_HIP(hipStreamSynchronize(s));
+        }
+        FW_TRY(iterate(look));
         for (const ProbHost& P : pl->probs)
             FW_HIP(matvec(pl, P, P.dev, at(pl->x, P), at(pl->tmp, P), maps_at(pl, P), EPI_TRUERES,
                           b + P.field_off, at(pl->r, P), part_at(pl->partT, pl, P), nullptr, s));
