@@ -120,6 +120,10 @@ class Plan:
     def new_field(self):
         return torch.zeros(self.field_elems, dtype=self.cdtype, device=self.device)
 
+    def _out_field(self):
+        # an output the library writes in full (no fill kernel before the call)
+        return torch.empty(self.field_elems, dtype=self.cdtype, device=self.device)
+
     def view(self, t, i):
         p = self.problems[i]
         n = p["nsys"] * 2 * p["nz"] * p["nx"]
@@ -167,7 +171,7 @@ class Plan:
         f = np.ascontiguousarray(np.asarray(src_f, dtype=np.float64).reshape(-1, 2))
         if s.shape[0] != self.total_sys or f.shape[0] != self.total_sys:
             raise ValueError(f"need {self.total_sys} sources and forces")
-        u0 = self.new_field()
+        u0 = self._out_field()
         self._bind_stream()
         check(self.lib.fwils_incident(self._h, s.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                                       f.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _ptr(u0)),
@@ -205,13 +209,13 @@ class Plan:
             x = self._field(x0, "x0").clone() if out is None else out.copy_(x0)
             flags |= _lib.FWILS_SOLVE_X0
         else:
-            x = self.new_field() if out is None else self._field(out, "out")
+            x = self._out_field() if out is None else self._field(out, "out")
         if plain:
             flags |= _lib.FWILS_SOLVE_PLAIN
         if not graph:
             flags |= _lib.FWILS_SOLVE_NOGRAPH
-        iters = torch.zeros(self.total_sys, dtype=torch.int32, device=self.device)
-        relres = torch.zeros(self.total_sys, dtype=torch.float64, device=self.device)
+        iters = torch.empty(self.total_sys, dtype=torch.int32, device=self.device)
+        relres = torch.empty(self.total_sys, dtype=torch.float64, device=self.device)
         self._bind_stream()
         st = self.lib.fwils_solve(self._h, _ptr(rhs), _ptr(x), float(rtol), int(maxit),
                                   _ptr(iters), _ptr(relres), flags)
@@ -230,7 +234,7 @@ class Plan:
                 raise ValueError(f"dm[{i}] must be [5, {p['nz']}, {p['nx']}]")
             dms.append(m)
         arr = (ctypes.c_void_p * len(dms))(*[m.data_ptr() for m in dms])
-        d = torch.zeros(self.data_elems(), dtype=self.cdtype, device=self.device)
+        d = torch.empty(self.data_elems(), dtype=self.cdtype, device=self.device)
         self._bind_stream()
         st = self.lib.fwils_frechet(self._h, _ptr(ub), arr, _ptr(d), float(rtol), int(maxit))
         if st != _lib.FWILS_OK:
@@ -244,7 +248,9 @@ class Plan:
         if r.numel() != self.data_elems():
             raise ValueError(f"r must hold {self.data_elems()} complex values")
         if g is None:
-            g = [torch.zeros(5, p["nz"], p["nx"], dtype=self.cdtype, device=self.device)
+            if accumulate:
+                raise ValueError("accumulate needs the g maps to add to")
+            g = [torch.empty(5, p["nz"], p["nx"], dtype=self.cdtype, device=self.device)
                  for p in self.problems]
         for i, gi in enumerate(g):
             _require_cuda(gi, self.cdtype, f"g[{i}]")
