@@ -139,7 +139,7 @@ def _pass_instance(k, tuning, n=256):
         seq = "true" if tuning["col_shared"] else "false"
         nt = 1024 if tuning["col_shared"] == 3 else 512
         return f"fw::c64::k_cols<{n}, {tuning['col_points']}, 0, {seq}, {nt}>"
-    return f"fw::c64::k_rows<{n}, {tuning['row_points']}, true, 1>"
+    return f"fw::c64::k_rows<{n}, {tuning.get('row_points_inv') or tuning['row_points']}, true, 1>"
 
 
 def _traffic_from_profiles(kernel_pass, tuning):

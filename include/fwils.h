@@ -68,7 +68,7 @@
 extern "C" {
 #endif
 
-#define FWILS_ABI_VERSION 6
+#define FWILS_ABI_VERSION 7
 
 typedef enum {
     FWILS_OK = 0,
@@ -370,6 +370,9 @@ typedef struct {
     int32_t fused_points;  /* 0: contrast stencil and forward row transform as two
                               kernels; else one fused kernel with this many points
                               per thread (rows of at most 512 points) */
+    int32_t row_points_inv; /* inverse row-transform points per thread (its Krylov
+                              epilogues hold more registers, so it is tuned on its
+                              own); 0 in fwils_set_tuning: the same as row_points */
     float time_us[4];      /* autotuner's time over all systems of the problem of the
                               chosen stencil, forward row pass, column variant (with
                               the forward and inverse row passes on the spectrum

@@ -33,10 +33,10 @@ class FwilsProblem(ctypes.Structure):
 class FwilsTuning(ctypes.Structure):
     _fields_ = [("row_points", c_int32), ("col_points", c_int32), ("col_width", c_int32),
                 ("col_shared", c_int32), ("stencil_rows", c_int32), ("stencil_sys", c_int32),
-                ("fused_points", c_int32), ("time_us", ctypes.c_float * 4)]
+                ("fused_points", c_int32), ("row_points_inv", c_int32), ("time_us", ctypes.c_float * 4)]
 
     FIELDS = ("row_points", "col_points", "col_width", "col_shared", "stencil_rows", "stencil_sys",
-              "fused_points")
+              "fused_points", "row_points_inv")
 
     def to_dict(self):
         d = {k: int(getattr(self, k)) for k in self.FIELDS}

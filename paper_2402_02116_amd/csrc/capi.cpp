@@ -186,7 +186,7 @@ hipError_t conv_problem(fwils_plan pl, const ProbHost& P, const cplx* f, cplx* o
                                    pl->stream);
     if (e == hipSuccess) e = launch_cols(COL_GREEN, P.cfg.col, tmp, P.dev, nullptr, pl->tw, pl->stream);
     if (e == hipSuccess)
-        e = launch_rows_inv(P.p.nx, P.cfg.row_p, EPI_STORE, tmp, nullptr, nullptr, out, nullptr, rows,
+        e = launch_rows_inv(P.p.nx, P.cfg.row_pi, EPI_STORE, tmp, nullptr, nullptr, out, nullptr, rows,
                             2 * P.p.nz, tile_rows(P.dev), nullptr, pl->tw, pl->stream);
     return e;
 }
@@ -209,7 +209,7 @@ hipError_t matvec(fwils_plan pl, const ProbHost& P, const ProbDev& d, const cplx
     }
     if (e == hipSuccess) e = launch_cols(COL_GREEN, k.col, tmp, d, st, pl->tw, s);
     if (e == hipSuccess)
-        e = launch_rows_inv(d.nx, k.row_p, epi, tmp, u, aux, out, part, rows, 2 * d.nz, tile_rows(d), st, pl->tw, s,
+        e = launch_rows_inv(d.nx, k.row_pi, epi, tmp, u, aux, out, part, rows, 2 * d.nz, tile_rows(d), st, pl->tw, s,
                             ge);
     return e;
 }
@@ -279,13 +279,13 @@ hipError_t bicg_iteration(fwils_plan pl, const ProbHost& P, const SysView& V, in
     hipError_t e = stencil_rows(first ? VM_P : VM_PX, ap);
     if (e == hipSuccess) e = launch_cols(COL_GREEN, k.col, tmp, V.d, st, pl->tw, s);
     if (e == hipSuccess)
-        e = launch_rows_inv(V.d.nx, k.row_p, EPI_BICG_V, tmp, pnew, rh, v, pV, rows, 2 * V.d.nz, tile_rows(V.d), st,
+        e = launch_rows_inv(V.d.nx, k.row_pi, EPI_BICG_V, tmp, pnew, rh, v, pV, rows, 2 * V.d.nz, tile_rows(V.d), st,
                             pl->tw, s);
     const StencilArgs as{r, v, nullptr, sv, tmp, maps, pV, P.np_rows};
     if (e == hipSuccess) e = stencil_rows(VM_S, as);
     if (e == hipSuccess) e = launch_cols(COL_GREEN, k.col, tmp, V.d, st, pl->tw, s);
     if (e == hipSuccess)
-        e = launch_rows_inv(V.d.nx, k.row_p, EPI_BICG_T, tmp, sv, rh, t, pT, rows, 2 * V.d.nz, tile_rows(V.d), st,
+        e = launch_rows_inv(V.d.nx, k.row_pi, EPI_BICG_T, tmp, sv, rh, t, pT, rows, 2 * V.d.nz, tile_rows(V.d), st,
                             pl->tw, s);
     return e;
 }
@@ -741,7 +741,7 @@ fwils_status fwils_plan_create(const fwils_problem* probs, int32_t nprob, fwils_
         P.cfg = kernel_cfg_default(P.p.nx, P.p.nz);
         P.dev.tile_sh = col_tile_shift(P.p.nx, P.cfg.col.W);
         P.tuned_us[0] = P.tuned_us[1] = P.tuned_us[2] = P.tuned_us[3] = 0.f;
-        P.np_rows = row_geom(P.p.nx, P.cfg.row_p, 2 * P.p.nz).blocks_per_sys;
+        P.np_rows = row_geom(P.p.nx, P.cfg.row_pi, 2 * P.p.nz).blocks_per_sys;   // the inverse pass's partials
         P.np_vec = vec_blocks_per_sys((int)P.n_per_sys);
         pl->max_np = std::max(pl->max_np, P.np_vec);
         {   // partial buffers fit every row-transform variant
@@ -1466,7 +1466,7 @@ fwils_status fwils_apply_pass(fwils_plan plan, int32_t pass, const void* u, void
                 break;
             case 2: FW_HIP(launch_cols(COL_GREEN, P.cfg.col, tmp, P.dev, nullptr, plan->tw, s)); break;
             default:
-                FW_HIP(launch_rows_inv(P.p.nx, P.cfg.row_p, EPI_APPLY, tmp, at(u, P), nullptr,
+                FW_HIP(launch_rows_inv(P.p.nx, P.cfg.row_pi, EPI_APPLY, tmp, at(u, P), nullptr,
                                        static_cast<cplx*>(Au) + P.field_off, nullptr, rows, 2 * P.p.nz, tile_rows(P.dev),
                                        nullptr, plan->tw, s));
         }
@@ -1631,6 +1631,7 @@ namespace {
 fwils_tuning to_tuning(const ProbHost& P) {
     fwils_tuning t;
     t.row_points = P.cfg.row_p;
+    t.row_points_inv = P.cfg.row_pi;
     t.col_points = P.cfg.col.P;
     t.col_width = P.cfg.col.W;
     t.col_shared = P.cfg.col.seq;
@@ -1644,6 +1645,7 @@ fwils_tuning to_tuning(const ProbHost& P) {
 KernelCfg from_tuning(const fwils_tuning& t) {
     KernelCfg k;
     k.row_p = t.row_points;
+    k.row_pi = t.row_points_inv ? t.row_points_inv : t.row_points;
     k.col = ColCfg{t.col_points, t.col_width, t.col_shared};
     k.st = StCfg{t.stencil_rows, t.stencil_sys};
     k.fuse_p = t.fused_points;
@@ -1661,14 +1663,14 @@ bool fuse_ok(const ProbHost& P, int fp) {
 }
 
 bool cfg_ok(const ProbHost& P, const KernelCfg& k) {
-    return row_points_ok(P.p.nx, k.row_p) && col_cfg_ok(P.p.nz, P.p.nx, k.col) &&
+    return row_points_ok(P.p.nx, k.row_p) && row_points_ok(P.p.nx, k.row_pi) && col_cfg_ok(P.p.nz, P.p.nx, k.col) &&
            st_cfg_ok(P.p.nx, P.p.nz, k.st) && fuse_ok(P, k.fuse_p);
 }
 
 void apply_cfg(fwils_plan pl, ProbHost& P, const KernelCfg& k) {
     P.cfg = k;
     P.dev.tile_sh = col_tile_shift(P.p.nx, k.col.W);   // the spectrum follows the column blocks
-    P.np_rows = row_geom(P.p.nx, k.row_p, 2 * P.p.nz).blocks_per_sys;
+    P.np_rows = row_geom(P.p.nx, k.row_pi, 2 * P.p.nz).blocks_per_sys;
     drop_graphs(pl);
 }
 
@@ -1689,7 +1691,7 @@ std::vector<KernelCfg> candidates(const ProbHost& P, int kind) {
         const int n = row_candidates(P.p.nx, c);
         for (int i = 0; i < n; ++i) {
             KernelCfg k = P.cfg;
-            k.row_p = c[i];
+            k.row_p = k.row_pi = c[i];   // both row passes in this variant
             out.push_back(k);
         }
     } else if (kind == FWILS_TUNE_COLS) {
@@ -1715,12 +1717,20 @@ std::vector<KernelCfg> candidates(const ProbHost& P, int kind) {
     return out;
 }
 
+// The inverse row pass as an extra timing kind of the autotuner (with the
+// Krylov v-epilogue: an input field, r^ and two-sum partial records).
+constexpr int kTuneRowsInv = 100;
+
 // One launch of the kernel of the given kind, variant k, over all systems of
 // problem P (fields from the workspace vectors; every system active).
 hipError_t tune_launch(fwils_plan pl, const ProbHost& P, int kind, const KernelCfg& k) {
     const int rows = P.p.nsys * 2 * P.p.nz;
     cplx* u = at(pl->x, P);
     cplx* tmp = at(pl->tmp, P);
+    if (kind == kTuneRowsInv)
+        return launch_rows_inv(P.p.nx, k.row_pi, EPI_BICG_V, tmp, u, at(pl->rhat, P), at(pl->v, P),
+                               part_at(pl->partV, pl, P), rows, 2 * P.p.nz, tile_rows(P.dev), nullptr, pl->tw,
+                               pl->stream);
     if (kind == FWILS_TUNE_STENCIL) return launch_body_force(k.st, u, tmp, maps_at(pl, P), P.dev, nullptr, pl->stream);
     cplx* tmp2 = at(pl->tmp2, P);
     if (kind == FWILS_TUNE_ROWS)
@@ -1747,7 +1757,7 @@ hipError_t tune_launch(fwils_plan pl, const ProbHost& P, int kind, const KernelC
                                    pl->stream);
     if (e == hipSuccess) e = launch_cols(COL_GREEN, k.col, tmp, d, nullptr, pl->tw, pl->stream);
     if (e == hipSuccess)
-        e = launch_rows_inv(P.p.nx, k.row_p, EPI_STORE, tmp, nullptr, nullptr, tmp2, nullptr, rows, 2 * P.p.nz,
+        e = launch_rows_inv(P.p.nx, k.row_pi, EPI_STORE, tmp, nullptr, nullptr, tmp2, nullptr, rows, 2 * P.p.nz,
                             tile_rows(d), nullptr, pl->tw, pl->stream);
     return e;
 }
@@ -1783,26 +1793,38 @@ fwils_status fwils_autotune(fwils_plan plan, int32_t reps) {
             if (kind == FWILS_TUNE_FUSE) best.fuse_p = 0;
             P.cfg = best;   // later kinds are timed with the earlier choices
             P.dev.tile_sh = col_tile_shift(P.p.nx, best.col.W);
-            for (const KernelCfg& k : candidates(P, kind)) {
+            float tbest_inv = 0.f;
+            auto time_us = [&](int knd, const KernelCfg& k, float& us) -> hipError_t {
                 float ms = 0.f;
-                he = tune_launch(plan, P, kind, k);   // warm-up (and first-use set-up)
-                if (he == hipSuccess) he = hipEventRecord(e0, s);
-                for (int r = 0; r < reps && he == hipSuccess; ++r) he = tune_launch(plan, P, kind, k);
-                if (he == hipSuccess) he = hipEventRecord(e1, s);
-                if (he == hipSuccess) he = hipEventSynchronize(e1);
-                if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+                hipError_t e = tune_launch(plan, P, knd, k);   // warm-up (and first-use set-up)
+                if (e == hipSuccess) e = hipEventRecord(e0, s);
+                for (int r = 0; r < reps && e == hipSuccess; ++r) e = tune_launch(plan, P, knd, k);
+                if (e == hipSuccess) e = hipEventRecord(e1, s);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                us = ms * 1e3f / (float)reps;
+                return e;
+            };
+            for (const KernelCfg& k : candidates(P, kind)) {
+                float us = 0.f, us_inv = 0.f;
+                he = time_us(kind, k, us);
+                // the row variant is chosen for each direction on its own
+                if (he == hipSuccess && kind == FWILS_TUNE_ROWS) he = time_us(kTuneRowsInv, k, us_inv);
                 if (he != hipSuccess) {
                     set_error("autotune: %s", hipGetErrorString(he));
                     st = FWILS_EDEVICE;
                     break;
                 }
-                const float us = ms * 1e3f / (float)reps;
                 if (tbest == 0.f || us < tbest) {
                     tbest = us;
                     if (kind == FWILS_TUNE_STENCIL) best.st = k.st;
                     else if (kind == FWILS_TUNE_ROWS) best.row_p = k.row_p;
                     else if (kind == FWILS_TUNE_COLS) best.col = k.col;
                     else best.fuse_p = k.fuse_p;
+                }
+                if (kind == FWILS_TUNE_ROWS && (tbest_inv == 0.f || us_inv < tbest_inv)) {
+                    tbest_inv = us_inv;
+                    best.row_pi = k.row_pi;
                 }
             }
             best_us[kind] = tbest;

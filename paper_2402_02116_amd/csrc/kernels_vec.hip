@@ -315,6 +315,7 @@ hipError_t launch_body_force(const StCfg& c, const cplx* u, cplx* b, const real*
 KernelCfg kernel_cfg_default(int nx, int nz) {
     KernelCfg k;
     k.row_p = row_points_default(nx);
+    k.row_pi = k.row_p;
     k.col = col_default(nz, nx);
     k.st = st_default();
     k.fuse_p = 0;

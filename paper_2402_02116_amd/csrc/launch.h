@@ -46,7 +46,8 @@ struct StCfg {
     int S;     // systems per block, 0 = chosen from the grid size
 };
 struct KernelCfg {
-    int row_p;   // row-transform points per thread
+    int row_p;   // forward row-transform points per thread
+    int row_pi;  // inverse row-transform points per thread (its epilogues hold more registers)
     ColCfg col;
     StCfg st;
     int fuse_p;  // 0: separate stencil and forward row pass; else the fused
