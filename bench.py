@@ -83,7 +83,7 @@ def _instance_name(kernel):
     return m.group(1) if m else kernel
 
 
-def summarize_counters(fetch_csv, write_csv, cmd):
+def summarize_counters(fetch_csv, write_csv, cmd, out_path=None):
     """profiles/counters_vti256x16.json from two rocprofv3 --pmc runs of
     `bench.py --passes-only` (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch).
     Each counter is scaled by what it reads for the 1 GiB device copy that the
@@ -118,7 +118,7 @@ def summarize_counters(fetch_csv, write_csv, cmd):
             passes[str(k)] = dict(kernel=PASS_NAMES[k], instances=inst)
     out = dict(source_hash=_kernel_source_hash(), command=cmd, fetch_scale=sf, write_scale=sw,
                copy_fetch_kib=copy_f, copy_write_kib=copy_w, passes=passes)
-    with open(COUNTERS, "w") as fh:
+    with open(out_path or COUNTERS, "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(out, indent=1))
     return 0
@@ -377,6 +377,19 @@ def normal_cg(a):
     import numpy as np
     import workloads as W
     w = W.vti1024_normal()
+    if a.passes_only:
+        # counter runs: the tuned passes of every problem, then the 1 GiB
+        # device copy the counters are scaled by
+        import torch
+        plan, tuned = _tik_plan(w["problems"], w["rec_ixz"], a.krylov, a, "c64")
+        rl = _pass_rooflines(plan, reps=a.reps)
+        src = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps(dict(passes_only=True, pass_rooflines=rl, tuning=tuned)), flush=True)
+        return 0
     nref = max(a.cg_iters, 2)
     times, q64, hist64, t_ub, tuned, nsys, rooflines = _normal_step(w, a, "c64", sorted({1, 2, nref}), RTOL)
     ref = None
@@ -515,9 +528,11 @@ def main(argv=None):
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/counters_vti256x16.json from two rocprofv3 --pmc runs")
     ap.add_argument("--counter-command", default="", help="the rocprofv3 command, recorded in the summary")
+    ap.add_argument("--counters-out", default=None, help="summary file (default profiles/counters_vti256x16.json)")
     a = ap.parse_args(argv)
     if a.summarize_counters:
-        return summarize_counters(a.summarize_counters[0], a.summarize_counters[1], a.counter_command)
+        return summarize_counters(a.summarize_counters[0], a.summarize_counters[1], a.counter_command,
+                                  a.counters_out)
     if a.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported (the path shards "
               f"independent (source, frequency) systems across GPUs, one process per GPU)", file=sys.stderr)
