@@ -49,6 +49,13 @@ PASS_BYTES = [32.0, 32.0, 32.0, 48.0]
 # u in, the row-transformed b out (plus the maps)
 FUSED_NAME = "k_srows (contrast stencil fused with the forward row FFT)"
 MAP_BYTES_PER_CELL = 20.0
+# algorithmic HBM bytes per cell-system of one batched BiCGSTAB iteration:
+# direction-update stencil (reads s, t, p_old, v, x; writes p, r, x and the
+# row-transformed b: 144 B), s-update stencil (reads r, v; writes s, b: 64 B),
+# two column passes (2 x 32 B), two inverse row passes with the v / t
+# epilogues (read the spectrum, the field and r^; write v or t: 2 x 64 B);
+# 64 B more when the stencils and the forward rows are separate kernels
+ITER_BYTES_FUSED, ITER_BYTES_SPLIT = 400.0, 464.0
 
 
 CSRC = os.path.join(ROOT, "paper_2402_02116_amd", "csrc")
@@ -697,6 +704,15 @@ def main(argv=None):
                               pass_gbs=[round(g, 1) for g in gbs], copy_gbs=round(copy_gbs, 1),
                               tuning=plan.tuning(0))), flush=True)
         return 0
+    # the batched solve as a whole: algorithmic bytes of its BiCGSTAB iterations
+    # (every system's own count) over its wall time, set-up and checks included
+    solve_bw = None
+    if a.krylov == "bicgstab":
+        per = ITER_BYTES_FUSED if plan.tuning(0)["fused_points"] else ITER_BYTES_SPLIT
+        sbytes = float(np.sum(tbr.iters)) * per * cells
+        sgbs = sbytes / (tb[len(tb) // 2] * 1e-3) / 1e9
+        solve_bw = dict(bytes=sbytes, ms=round(tb[len(tb) // 2], 3), gbs=round(sgbs, 1),
+                        frac=round(sgbs / HBM_PEAK_GBS, 4), bytes_per_iteration_per_cell=per)
     roof = dict(bound="hbm", kernel=names[dom], achieved=round(gbs[dom], 1), peak=HBM_PEAK_GBS,
                 unit="GB/s", frac=round(gbs[dom] / HBM_PEAK_GBS, 4),
                 traffic=None if traffic is None else round(traffic, 1),
@@ -714,6 +730,7 @@ def main(argv=None):
                                    speedup=round(tp[len(tp) // 2] / tb[len(tb) // 2], 2),
                                    iters=[int(tbr.iters.min()), int(tbr.iters.max())],
                                    max_true_relres=float(tbr.relres.max()), identical=same),
+               solve_bandwidth=solve_bw,
                copy_gbs=round(copy_gbs, 1), autotune=tuning,
                matvec=dict(gpoints_s=round(matvec_gps, 3), us=round(t_apply * 1e3, 3),
                            kernels=names, pass_us=[round(t * 1e3, 3) for t in t_pass],
