@@ -167,6 +167,45 @@ def test_solve_rectangular_vti_matches_oracle(nx, nz, nsys):
         assert _rel(u[k], uref[k]) < FIELD_TOL
 
 
+@pytest.mark.parametrize("nx,nz", [(2048, 16), (16, 2048)])
+def test_solve_at_the_extreme_grid_shapes(nx, nz):
+    """The longest supported rows and columns (2048 points) against the
+    oracle, with the autotuner's choice of variants."""
+    p, maps = _vti_case(nx, nz, 2, amp=0.08, seed=17)
+    print(f"extreme shape {nx}x{nz}", flush=True)
+    plan = _plan([p])
+    plan.set_contrast(0, maps)
+    plan.autotune(reps=2)
+    src = [(nx // 3, nz // 3), (2 * nx // 3, 2 * nz // 3)]
+    f = [(0.0, 1.0), (1.0, 0.0)]
+    res = plan.solve(plan.incident(src, f), rtol=1e-7, maxit=1000)
+    assert res.status == 0
+    P = _oracle(p, maps)
+    uref, _ = P.solve(P.incident(src, f), tol=1e-11)
+    u = _to_np(plan.view(res.x, 0))
+    for k in range(2):
+        assert _rel(u[k], uref[k]) < FIELD_TOL
+
+
+def test_many_systems_on_a_small_grid():
+    """256 systems of 32 x 32 (blocks, partial records and graph chunks at
+    a large batch): every system converges; a sample matches the oracle."""
+    nsys = 256
+    p, maps = _vti_case(32, 32, nsys, amp=0.1, seed=19)
+    plan = _plan([p])
+    plan.set_contrast(0, maps)
+    src = [(s % 32, (s // 32) % 32) for s in range(nsys)]
+    f = [(float(np.cos(s)), float(np.sin(s))) for s in range(nsys)]
+    res = plan.solve(plan.incident(src, f), rtol=1e-6, maxit=500)
+    assert res.status == 0 and np.all(res.relres < 2e-6)
+    P = _oracle(p, maps)
+    pick = [0, 97, 255]
+    uref, _ = P.solve(P.incident([src[k] for k in pick], [f[k] for k in pick]), tol=1e-11)
+    u = _to_np(plan.view(res.x, 0))
+    for i, k in enumerate(pick):
+        assert _rel(u[k], uref[i]) < FIELD_TOL
+
+
 def test_solve_vti256_full_size_sampled():
     """256^2 VTI, 16 sources, 5 Hz at full size, batched c64 to 1e-6:
     every true residual <= 2e-6; three of the systems against the oracle."""
