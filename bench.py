@@ -443,25 +443,21 @@ def cpu_baseline(c, rec, dm, r, nsample):
                        f"J, J*), complex128 numpy/scipy, {mv} matvecs in {dt:.1f} s")
 
 
-def dbi_inversion(a):
-    """Distorted-Born inversion shaped like the paper's 2-D VTI reservoir
-    example: 192 x 48 cells of 20 m, 48 surface forces, 96 receivers, nine
-    frequencies 3..19 Hz inverted one after the other, each stage stopping at
-    eps_d < 1e-3 or after 10 updates, --dbi-cg CG iterations per update
-    (lambda0 --dbi-lambda, self-adaptive cooling).  Observed data come from
-    forward solves in the true model (before the timed region); the timed
-    region is the whole sequential inversion from the smoothed model."""
+def _dbi_run(a, w, precision):
+    """The sequential inversion of workload w in one precision: (final contrast
+    as float64 numpy, per-stage records, seconds of the timed inversion,
+    autotune choice).  Observed data come from forward solves in the true
+    model in complex64 (both precisions invert the same data values)."""
     import numpy as np
     import torch
-    import workloads as W
     from paper_2402_02116_amd.dbi import invert_sequential
     from paper_2402_02116_amd.plan import Plan
-    w = W.reservoir_dbi()
     nsrc = len(w["src_ixz"])
     plans, d_obs, tuned = [], [], None
     for f in w["freqs"]:
-        plan = Plan([dict(nx=w["nx"], nz=w["nz"], dx=w["dx"], c0=w["c0"], rho0=w["rho0"], freq_hz=f,
-                          eta=w["eta"], nsys=nsrc)], device="cuda:0")
+        mk = lambda prec: Plan([dict(nx=w["nx"], nz=w["nz"], dx=w["dx"], c0=w["c0"], rho0=w["rho0"],
+                                     freq_hz=f, eta=w["eta"], nsys=nsrc)], device="cuda:0", precision=prec)
+        plan = mk(precision)
         plan.set_receivers(0, w["rec"])
         if a.krylov == "gmres":
             plan.set_krylov("gmres", restart=a.restart, cgs2=not a.cgs1)
@@ -470,27 +466,60 @@ def dbi_inversion(a):
                 tuned = plan.autotune(reps=5)
             else:
                 plan.set_tuning(0, **{k: v for k, v in tuned[0].items() if k != "time_us"})
-        plan.set_contrast(0, w["c_true"])
-        u = plan.solve(plan.incident(w["src_ixz"], w["src_f"]), rtol=1e-7, maxit=5000).x
-        d_obs.append(plan.receiver_data(u))
+        fwd = plan if precision == "c64" else mk("c64")
+        if fwd is not plan:
+            fwd.set_receivers(0, w["rec"])
+        fwd.set_contrast(0, w["c_true"])
+        u = fwd.solve(fwd.incident(w["src_ixz"], w["src_f"]), rtol=1e-7, maxit=5000).x
+        d_obs.append(fwd.receiver_data(u).to(plan.cdtype))
+        del u, fwd
         plans.append(plan)
     torch.cuda.synchronize()
-    print(f"[bench] dbi: observed data at {len(plans)} frequencies", file=sys.stderr, flush=True)
+    print(f"[bench] dbi ({precision}): observed data at {len(plans)} frequencies", file=sys.stderr, flush=True)
     t = time.perf_counter()
     c, stages = invert_sequential(plans, w["src_ixz"], w["src_f"], d_obs, w["c_start"], w["m0"],
-                                  lam0=a.dbi_lambda, niter=a.dbi_cg, tol=1e-3, max_outer=10, rtol=RTOL,
-                                  maxit=5000)
+                                  lam0=a.dbi_lambda, niter=a.dbi_cg, tol=1e-3, max_outer=10,
+                                  rtol=RTOL if precision == "c64" else 1e-10, maxit=5000)
     torch.cuda.synchronize()
     secs = time.perf_counter() - t
     for st in stages:
-        print(f"[bench] dbi {st['freq_hz']:4.1f} Hz: {st['updates']} updates, eps_d {st['eps'][0]:.4f} -> "
+        print(f"[bench] dbi {precision} {st['freq_hz']:4.1f} Hz: {st['updates']} updates, eps_d {st['eps'][0]:.4f} -> "
               f"{st['eps'][-1]:.4f}", file=sys.stderr, flush=True)
     c = c.double().cpu().numpy()
+    del plans, d_obs
+    torch.cuda.empty_cache()
+    return c, stages, secs, tuned
+
+
+def dbi_inversion(a):
+    """Distorted-Born inversion shaped like the paper's 2-D VTI reservoir
+    example: 192 x 48 cells of 20 m, 48 surface forces, 96 receivers, nine
+    frequencies 3..19 Hz inverted one after the other, each stage stopping at
+    eps_d < 1e-3 or after 10 updates, --dbi-cg CG iterations per update
+    (lambda0 --dbi-lambda, self-adaptive cooling).  Observed data come from
+    forward solves in the true model (before the timed region); the timed
+    region is the whole sequential inversion from the smoothed model.  With
+    --fp64-reference the inversion is repeated in complex128 and the
+    complex64 model's error against it reported."""
+    import numpy as np
+    import workloads as W
+    w = W.reservoir_dbi()
+    nsrc = len(w["src_ixz"])
+    c, stages, secs, tuned = _dbi_run(a, w, "c64")
     m0 = w["m0"].reshape(5, 1, 1)
     m_true, m_start, m_end = m0 + w["c_true"], m0 + w["c_start"], m0 + c
     eps_m = [float(np.linalg.norm(m[p] - m_true[p]) / np.linalg.norm(m_true[p])) for m in (m_start, m_end)
              for p in range(5)]
     updates = sum(st["updates"] for st in stages)
+    ref = None
+    if a.fp64_reference:
+        c128, st128, secs128, _ = _dbi_run(a, w, "c128")
+        ref = dict(s_total_c128=round(secs128, 2), updates_c128=sum(st["updates"] for st in st128),
+                   rel_error_model=[round(float(np.linalg.norm(c[p] - c128[p]) / np.linalg.norm(m0[p] + c128[p])), 9)
+                                    for p in range(5)],
+                   rel_error_contrast=float(np.linalg.norm(c - c128) / np.linalg.norm(c128)),
+                   eps_last_c128=[round(st["eps"][-1], 6) for st in st128], rtol_c128=1e-10)
+        print(f"[bench] dbi complex64 vs complex128: {ref}", file=sys.stderr, flush=True)
     out = dict(metric=METRIC, value=round(updates / secs, 3), unit="DBI updates/s", n_gpus=1, steps=1, warmup=0,
                ms_per_step=round(secs * 1e3, 1), higher_is_better=True, scaling="weak", vs_baseline=None,
                dtype="c64", data="synthetic",
@@ -502,7 +531,7 @@ def dbi_inversion(a):
                stages=[dict(freq_hz=st["freq_hz"], updates=st["updates"], eps_first=round(st["eps"][0], 5),
                             eps_last=round(st["eps"][-1], 5)) for st in stages],
                eps_m_start=[round(x, 5) for x in eps_m[:5]], eps_m_end=[round(x, 5) for x in eps_m[5:]],
-               krylov=a.krylov, autotune=tuned)
+               krylov=a.krylov, autotune=tuned, fp64_gpu_reference=ref)
     print(json.dumps(out), flush=True)
     return 0
 
@@ -528,7 +557,7 @@ def main(argv=None):
     ap.add_argument("--dbi-cg", type=int, default=10, help="dbi workload: CG iterations per model update")
     ap.add_argument("--dbi-lambda", type=float, default=1e-2, help="dbi workload: initial lambda")
     ap.add_argument("--fp64-reference", action="store_true",
-                    help="normal workload: rerun the step in complex128 and report the complex64 error")
+                    help="normal / dbi workloads: rerun in complex128 on the GPU and report the complex64 error")
     ap.add_argument("--cg-iters", type=int, default=2, help="normal workload: CG iterations of the compared run")
     ap.add_argument("--passes-only", action="store_true",
                     help="only the per-pass kernel launches and the 1 GiB copy (for counter runs)")
