@@ -259,7 +259,9 @@ template <int TX, int TZ, int VM>
 static void body_force_launch(const StCfg& c, const StencilArgs& a, const ProbDev& pd, SysState* st,
                               hipStream_t s) {
     const int ntiles = (pd.nx / TX) * (pd.nz / TZ);
-    int S = c.S;
+    // the solver's update modes carry two to five vectors per system and take
+    // the automatic count (the tuned count is timed in the plain mode)
+    int S = VM == VM_NONE ? c.S : 0;
     if (S == 0) {
         // several systems per block once there are plenty of blocks
         S = 1;
