@@ -17,7 +17,9 @@ divided by the step's wall time (G cell-systems per second).
 Also reported: the isolated batched matvec rate, time-to-1e-6 of the batched
 solve against the plain per-source solve (same kernels, nsys = 1, host check
 every iteration), the per-pass kernel times, the roofline of the dominant
-kernel and the CPU oracle timed on a bounded sample of the same step.
+kernel (the BiCGSTAB direction-update mode of the fused stencil + row FFT,
+timed with every system running) and the CPU oracle timed on a bounded sample
+of the same step.
 """
 
 import argparse
@@ -56,6 +58,12 @@ MAP_BYTES_PER_CELL = 20.0
 # epilogues (read the spectrum, the field and r^; write v or t: 2 x 64 B);
 # 64 B more when the stencils and the forward rows are separate kernels
 ITER_BYTES_FUSED, ITER_BYTES_SPLIT = 400.0, 464.0
+# the direction-update mode of the fused kernel alone (the largest kernel of a
+# BiCGSTAB iteration): 144 B per cell-system plus the maps
+PX_BYTES = 144.0
+PX_NAME = ("k_srows, direction-update mode (previous iteration's r / x updates and p = r + beta (p - omega v) "
+           "fused into the contrast stencil and the forward row FFT)")
+PX_PASS = 4   # its entry in the counter summary
 
 
 CSRC = os.path.join(ROOT, "paper_2402_02116_amd", "csrc")
@@ -79,7 +87,8 @@ PASS_MATCH = [lambda n: (n.startswith("void fw::c64::k_body_force<") and ", 0>("
               lambda n: n.startswith("void fw::c64::k_rows<") and ", false, 0>" in n,
               lambda n: (n.startswith("void fw::c64::k_cols<") and ", 0, " in n)
               or n.startswith("void fw::c64::k_cols_split<"),
-              lambda n: n.startswith("void fw::c64::k_rows<") and ", true, 1>" in n]
+              lambda n: n.startswith("void fw::c64::k_rows<") and ", true, 1>" in n,
+              lambda n: re.search(r"c64::\(anonymous namespace\)::k_srows<\d+, \d+, 3, \d+>\(", n) is not None]
 
 
 def _instance_name(kernel):
@@ -118,11 +127,17 @@ def summarize_counters(fetch_csv, write_csv, cmd, out_path=None):
         for n in fetch:
             if not match(n) or n not in write:
                 continue
-            f, w = statistics.median(fetch[n]), statistics.median(write[n])
+            fv, wv = fetch[n], write[n]
+            if k == PX_PASS:
+                # the timed launches run every system; a solve's launches after
+                # its systems stopped exit early and are left out
+                fv = [x for x in fv if x >= 0.5 * max(fv)]
+                wv = [x for x in wv if x >= 0.5 * max(wv)]
+            f, w = statistics.median(fv), statistics.median(wv)
             inst[_instance_name(n)] = dict(
-                fetch_kib=f, write_kib=w, launches=len(fetch[n]), hbm_bytes_per_launch=(f * sf + w * sw) * 1024.0)
+                fetch_kib=f, write_kib=w, launches=len(fv), hbm_bytes_per_launch=(f * sf + w * sw) * 1024.0)
         if inst:
-            passes[str(k)] = dict(kernel=PASS_NAMES[k], instances=inst)
+            passes[str(k)] = dict(kernel=PX_NAME if k == PX_PASS else PASS_NAMES[k], instances=inst)
     out = dict(source_hash=_kernel_source_hash(), command=cmd, fetch_scale=sf, write_scale=sw,
                copy_fetch_kib=copy_f, copy_write_kib=copy_w, passes=passes)
     with open(out_path or COUNTERS, "w") as fh:
@@ -133,6 +148,10 @@ def summarize_counters(fetch_csv, write_csv, cmd, out_path=None):
 
 def _pass_instance(k, tuning, n=256):
     """Kernel instance of pass k on an n^2 grid under the plan's variants."""
+    if k == PX_PASS:
+        # 512 threads while a thread's row segment is at most 32 points long
+        p = tuning["fused_points"]
+        return f"fw::c64::(anonymous namespace)::k_srows<{n}, {p}, 3, {512 if n >= 256 and n // p <= 32 else 256}>"
     if k == 0:
         if tuning.get("fused_points"):
             # the plain mode always runs the 256-thread form
@@ -691,11 +710,25 @@ def main(argv=None):
     bytes_per_launch = [PASS_BYTES[k] * ns * cells + (MAP_BYTES_PER_CELL * cells if k == 0 else 0.0)
                         for k in passes]
     gbs = [bytes_per_launch[i] / (t_pass[i] * 1e-3) / 1e9 for i in range(len(passes))]
-    # the roofline is stated for the contrast-stencil pass (fused with the
-    # forward rows when tuned so): its kernel family (matvec, p-update and
-    # s-update modes) takes the largest share of the step's kernel time
-    dom = 0
-    traffic = _traffic_from_profiles(passes[dom], plan.tuning(0))
+    # the direction-update mode of the fused kernel, the largest kernel of a
+    # BiCGSTAB iteration and of the step: every system running, continuing
+    # from the state of a solve stopped after a few iterations
+    t_px = px_bytes = None
+    if fused and a.krylov == "bicgstab":
+        plan.solve(plan.incident(c["src_ixz"], c["src_f"]), rtol=1e-12, maxit=8)
+        t_px = plan.time_krylov_pass(a.reps) * 1e-3   # ms per launch
+        px_bytes = PX_BYTES * ns * cells + MAP_BYTES_PER_CELL * cells
+        print(f"[bench] direction-update pass {PX_NAME.split(',')[0]}: {t_px * 1e3:.2f} us/launch, "
+              f"{px_bytes / (t_px * 1e-3) / 1e9:.0f} GB/s algorithmic", file=sys.stderr, flush=True)
+    # the roofline is stated for that kernel (for the matvec's stencil pass
+    # when the stencil and the rows run apart, or under GMRES)
+    if t_px is not None:
+        roof_name, roof_bytes, roof_ms = PX_NAME, px_bytes, t_px
+        traffic = _traffic_from_profiles(PX_PASS, plan.tuning(0))
+    else:
+        roof_name, roof_bytes, roof_ms = names[0], bytes_per_launch[0], t_pass[0]
+        traffic = _traffic_from_profiles(passes[0], plan.tuning(0))
+    roof_gbs = roof_bytes / (roof_ms * 1e-3) / 1e9
     for i, k in enumerate(passes):
         print(f"[bench] pass {k} {names[i]}: {t_pass[i] * 1e3:.2f} us/launch, "
               f"{gbs[i]:.0f} GB/s algorithmic", file=sys.stderr, flush=True)
@@ -727,6 +760,10 @@ def main(argv=None):
                     plan.apply_pass(j, u, Au)
                 for _ in range(a.reps):
                     plan.apply_pass(k, u, Au)
+                if kind == "fuse" and a.krylov == "bicgstab":
+                    # the direction-update mode of this fused variant
+                    plan.solve(plan.incident(c["src_ixz"], c["src_f"]), rtol=1e-12, maxit=8)
+                    plan.time_krylov_pass(a.reps)
         plan.set_tuning(0, **{f: chosen[f] for f in chosen if f != "time_us"})
         torch.cuda.synchronize()
         print(json.dumps(dict(passes_only=True, pass_us=[round(t * 1e3, 3) for t in t_pass],
@@ -742,10 +779,10 @@ def main(argv=None):
         sgbs = sbytes / (tb[len(tb) // 2] * 1e-3) / 1e9
         solve_bw = dict(bytes=sbytes, ms=round(tb[len(tb) // 2], 3), gbs=round(sgbs, 1),
                         frac=round(sgbs / HBM_PEAK_GBS, 4), bytes_per_iteration_per_cell=per)
-    roof = dict(bound="hbm", kernel=names[dom], achieved=round(gbs[dom], 1), peak=HBM_PEAK_GBS,
-                unit="GB/s", frac=round(gbs[dom] / HBM_PEAK_GBS, 4),
+    roof = dict(bound="hbm", kernel=roof_name, achieved=round(roof_gbs, 1), peak=HBM_PEAK_GBS,
+                unit="GB/s", frac=round(roof_gbs / HBM_PEAK_GBS, 4),
                 traffic=None if traffic is None else round(traffic, 1),
-                bytes_per_launch=bytes_per_launch[dom], avg_launch_us=round(t_pass[dom] * 1e3, 3))
+                bytes_per_launch=roof_bytes, avg_launch_us=round(roof_ms * 1e3, 3))
     out = dict(metric=METRIC, value=round(value, 3), unit="GPoints/s", n_gpus=1, steps=a.steps,
                warmup=a.warmup, ms_per_step=round(ms_step, 4), higher_is_better=True, scaling="weak",
                vs_baseline=None, dtype="c64", data="synthetic",

@@ -209,6 +209,20 @@ fwils_status fwils_apply_pass(fwils_plan plan, int32_t pass, const void* u, void
  * fwils_apply_pass over reps (1..10000) back-to-back launches, measured with
  * HIP events on the plan's stream after one warm-up launch.  Synchronous. */
 fwils_status fwils_time_pass(fwils_plan plan, int32_t pass, const void* u, void* Au, int32_t reps, float* us);
+/* Average duration in microseconds (*us, host) of the BiCGSTAB iteration's
+ * direction-update pass with every system of the plan running: the contrast
+ * stencil whose input update closes the previous iteration (r = s - omega t,
+ * x += alpha p_old + omega s) and forms p = r + beta (p_old - omega v), with
+ * the forward row transforms (one kernel when fused).  It continues from the
+ * state of this plan's most recent solve, which must be a BiCGSTAB solve that
+ * completed at least one iteration on every system (e.g. one stopped by maxit),
+ * with the stop tests switched off: one warm-up launch, then reps (1..10000)
+ * back-to-back launches between HIP events on the plan's stream (each takes
+ * the same decisions).  The solver's per-system state is restored afterwards; the
+ * workspace's Krylov vectors are left changed (every solve initialises them).
+ * FWILS_EINVAL for a GMRES plan, when the last solve was not such a solve, or
+ * if some system stopped running during the timed launches.  Synchronous. */
+fwils_status fwils_time_krylov_pass(fwils_plan plan, int32_t reps, float* us);
 
 /* Per-system results of the most recent Krylov solve of this plan (from
  * fwils_solve, fwils_frechet or fwils_adjoint): completed iterations and the

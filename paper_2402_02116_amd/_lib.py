@@ -68,6 +68,7 @@ SIGNATURES = {
     "fwils_fft2": (c_int32, [P, c_int32, P, P, c_int32]),
     "fwils_apply_pass": (c_int32, [P, c_int32, P, P]),
     "fwils_time_pass": (c_int32, [P, c_int32, P, P, c_int32, ctypes.POINTER(ctypes.c_float)]),
+    "fwils_time_krylov_pass": (c_int32, [P, c_int32, ctypes.POINTER(ctypes.c_float)]),
     "fwils_tikhonov_grad": (c_int32, [P, P, P, ctypes.POINTER(c_double), c_double, c_int32, P, P,
                                       ctypes.POINTER(c_double), P, c_double, c_int32]),
     "fwils_normal_apply": (c_int32, [P, P, ctypes.POINTER(c_double), c_double, c_double, c_int32, P, P, P,

@@ -41,6 +41,7 @@
     X(fwils_status, time_pass,                                                                             \
       (fwils_plan plan, int32_t pass, const void* u, void* Au, int32_t reps, float* us),                  \
       (plan, pass, u, Au, reps, us))                                                                       \
+    X(fwils_status, time_krylov_pass, (fwils_plan plan, int32_t reps, float* us), (plan, reps, us))       \
     X(fwils_status, solve_stats, (fwils_plan plan, int32_t* iters, double* relres), (plan, iters, relres)) \
     X(fwils_status, solve_status, (fwils_plan plan, int32_t* status), (plan, status))                    \
     X(fwils_status, tikhonov_grad,                                                                         \

@@ -114,6 +114,7 @@ struct fwils_plan_s {
     hipGraphExec_t chunk = nullptr, chunk_first = nullptr;
     // Krylov method; GMRES state lives in a caller-provided workspace
     int krylov = FWILS_KRYLOV_BICGSTAB;
+    bool bicg_state = false;   // the workspace holds the state of a finished BiCGSTAB solve
     int gm_m = 0;
     bool gm_cgs2 = true;
     size_t gm_maxnb = 0;
@@ -245,9 +246,10 @@ SysView make_view(fwils_plan pl, const ProbHost& P, int s0, int ns) {
 // iteration's closing updates r = s - omega t, x += alpha p_old + omega s
 // (decided from the t-pass records, so a system that stops there gets only
 // those); the second takes s = r - alpha v.  p alternates between two buffers
-// with the iteration parity.
+// with the iteration parity.  px_only: the direction-update stencil pass
+// alone (a timing aid; needs !first).
 hipError_t bicg_iteration(fwils_plan pl, const ProbHost& P, const SysView& V, int parity, bool first,
-                          hipStream_t s) {
+                          hipStream_t s, bool px_only = false) {
     const int ns = V.d.nsys;
     const int rows = ns * 2 * V.d.nz;
     cplx *x = pl->x + V.foff, *r = pl->r + V.foff, *rh = pl->rhat + V.foff, *v = pl->v + V.foff,
@@ -277,6 +279,7 @@ hipError_t bicg_iteration(fwils_plan pl, const ProbHost& P, const SysView& V, in
         return r;
     };
     hipError_t e = stencil_rows(first ? VM_P : VM_PX, ap);
+    if (px_only) return e;
     if (e == hipSuccess) e = launch_cols(COL_GREEN, k.col, tmp, V.d, st, pl->tw, s);
     if (e == hipSuccess)
         e = launch_rows_inv(V.d.nx, k.row_pi, EPI_BICG_V, tmp, pnew, rh, v, pV, rows, 2 * V.d.nz, tile_rows(V.d), st,
@@ -288,6 +291,15 @@ hipError_t bicg_iteration(fwils_plan pl, const ProbHost& P, const SysView& V, in
         e = launch_rows_inv(V.d.nx, k.row_pi, EPI_BICG_T, tmp, sv, rh, t, pT, rows, 2 * V.d.nz, tile_rows(V.d), st,
                             pl->tw, s);
     return e;
+}
+
+// The t pass of an iteration alone: t = s - G0*b(s) from the spectrum in the
+// scratch field, with its dot-product records (a timing aid).
+hipError_t bicg_t_pass(fwils_plan pl, const ProbHost& P, const SysView& V, hipStream_t s) {
+    const int rows = V.d.nsys * 2 * V.d.nz;
+    return launch_rows_inv(V.d.nx, P.cfg.row_pi, EPI_BICG_T, pl->tmp + V.foff, pl->s + V.foff, pl->rhat + V.foff,
+                           pl->t + V.foff, pl->partT + V.poff_row, rows, 2 * V.d.nz, tile_rows(V.d),
+                           pl->state + V.soff, pl->tw, s);
 }
 
 // The end-of-chunk close kernel after an iteration of the given parity.
@@ -491,6 +503,7 @@ fwils_status bicg_solve_ws(fwils_plan pl, const cplx* b, bool use_x0, double rto
                                   iters ? iters + P.sys_off : nullptr, relres ? relres + P.sys_off : nullptr, s));
     FW_HIP(hipMemcpyAsync(pl->host_state, pl->state, nst * sizeof(SysState), hipMemcpyDeviceToHost, s));
     FW_HIP(hipStreamSynchronize(s));
+    pl->bicg_state = true;
     bool noconv = false, brk = false;
     for (size_t i = 0; i < nst; ++i) {
         const int stt = st_code(pl->host_state[i].status);
@@ -641,6 +654,7 @@ fwils_status gm_solve_ws(fwils_plan pl, const cplx* b, bool use_x0, double rtol,
 
 fwils_status solve_ws(fwils_plan pl, const cplx* b, bool use_x0, double rtol, int maxit, int32_t* iters,
                       double* relres, uint32_t flags) {
+    pl->bicg_state = false;
     if (pl->krylov == FWILS_KRYLOV_GMRES) return gm_solve_ws(pl, b, use_x0, rtol, maxit, iters, relres, flags);
     return bicg_solve_ws(pl, b, use_x0, rtol, maxit, iters, relres, flags);
 }
@@ -834,6 +848,7 @@ fwils_status fwils_set_workspace(fwils_plan plan, void* dev, size_t bytes) {
         return FWILS_ENOMEM;
     }
     drop_graphs(plan);
+    plan->bicg_state = false;
     if (!plan->host_state) {
         FW_HIP(hipHostMalloc((void**)&plan->host_state, plan->total_sys * sizeof(SysState),
                              hipHostMallocDefault));
@@ -1498,6 +1513,86 @@ fwils_status fwils_time_pass(fwils_plan plan, int32_t pass, const void* u, void*
         return FWILS_EDEVICE;
     }
     *us = ms * 1e3f / (float)reps;
+    return FWILS_OK;
+}
+
+fwils_status fwils_time_krylov_pass(fwils_plan plan, int32_t reps, float* us) {
+    FW_TRY(check_plan(plan));
+    if (!us || reps < 1 || reps > 10000) {
+        set_error("time_krylov_pass: need reps 1..10000 and an output");
+        return FWILS_EINVAL;
+    }
+    if (plan->krylov != FWILS_KRYLOV_BICGSTAB || !plan->bicg_state) {
+        set_error("time_krylov_pass: needs a BiCGSTAB plan whose last solve was a finished BiCGSTAB solve");
+        return FWILS_EINVAL;
+    }
+    hipStream_t s = plan->stream;
+    const size_t nst = plan->total_sys;
+    SysState* orig = plan->host_pipe;          // the solver's pinned staging, idle here
+    SysState* run = plan->host_pipe + nst;
+    FW_HIP(hipMemcpyAsync(orig, plan->state, nst * sizeof(SysState), hipMemcpyDeviceToHost, s));
+    FW_HIP(hipStreamSynchronize(s));
+    for (size_t i = 0; i < nst; ++i) {
+        if (orig[i].iter < 1 || !(orig[i].bnorm2 > 0.0) || !(orig[i].bnorm2 < 1e300)) {
+            set_error("time_krylov_pass: system %zu has no completed BiCGSTAB iteration to continue from", i);
+            return FWILS_EINVAL;
+        }
+        // every system keeps running: no convergence test, no iteration limit,
+        // no restart with a fresh shadow residual
+        run[i] = orig[i];
+        run[i].status = ST_RUNNING;
+        run[i].tol2 = 0.0;
+        run[i].maxit = orig[i].iter + 1000000;
+        run[i].fresh_at = 0;
+    }
+    // the records the pass reads (those of the last t pass; the solve's final
+    // residual check reuses their buffer) are made again from s and t
+    FW_HIP(hipMemcpyAsync(plan->state, run, nst * sizeof(SysState), hipMemcpyHostToDevice, s));
+    for (const ProbHost& P : plan->probs) FW_HIP(bicg_t_pass(plan, P, make_view(plan, P, 0, P.p.nsys), s));
+    // Back-to-back launches take the same decisions: a launch writes rho into
+    // the slot of its own iteration parity and reads the other one, takes
+    // omega from the t-pass records, which it does not write, and leaves the
+    // iteration count alone; only x keeps accumulating its update.
+    auto launch_all = [&]() -> hipError_t {
+        for (const ProbHost& P : plan->probs) {
+            const hipError_t e = bicg_iteration(plan, P, make_view(plan, P, 0, P.p.nsys), 0, false, s, true);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    hipEvent_t e0, e1;
+    FW_HIP(hipEventCreate(&e0));
+    FW_HIP(hipEventCreate(&e1));
+    hipError_t he = launch_all();   // warm-up
+    if (he == hipSuccess) he = hipEventRecord(e0, s);
+    for (int r = 0; r < reps && he == hipSuccess; ++r) he = launch_all();
+    if (he == hipSuccess) he = hipEventRecord(e1, s);
+    if (he == hipSuccess) he = hipEventSynchronize(e1);
+    float total_ms = 0.f;
+    if (he == hipSuccess) he = hipEventElapsedTime(&total_ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    // the last launch must have found every system running (else some blocks
+    // skipped their work); then the solver's state goes back as it was
+    bool all_ran = false;
+    if (he == hipSuccess) he = hipMemcpyAsync(run, plan->state, nst * sizeof(SysState), hipMemcpyDeviceToHost, s);
+    if (he == hipSuccess) he = hipStreamSynchronize(s);
+    if (he == hipSuccess) {
+        all_ran = true;
+        for (size_t i = 0; i < nst; ++i)
+            if (run[i].status != ST_RUNNING) all_ran = false;
+        he = hipMemcpyAsync(plan->state, orig, nst * sizeof(SysState), hipMemcpyHostToDevice, s);
+    }
+    if (he == hipSuccess) he = hipStreamSynchronize(s);
+    if (he != hipSuccess) {
+        set_error("time_krylov_pass: %s", hipGetErrorString(he));
+        return FWILS_EDEVICE;
+    }
+    if (!all_ran) {
+        set_error("time_krylov_pass: a system left the running state during the timed launches");
+        return FWILS_EINVAL;
+    }
+    *us = total_ms * 1e3f / (float)reps;
     return FWILS_OK;
 }
 

@@ -27,6 +27,7 @@
 #define fwils_adjoint FW_CORE(fwils_adjoint)
 #define fwils_apply_pass FW_CORE(fwils_apply_pass)
 #define fwils_time_pass FW_CORE(fwils_time_pass)
+#define fwils_time_krylov_pass FW_CORE(fwils_time_krylov_pass)
 #define fwils_solve_stats FW_CORE(fwils_solve_stats)
 #define fwils_solve_status FW_CORE(fwils_solve_status)
 #define fwils_tikhonov_grad FW_CORE(fwils_tikhonov_grad)

@@ -284,6 +284,14 @@ class Plan:
               "fwils_time_pass")
         return us.value
 
+    def time_krylov_pass(self, reps=50):
+        """Average duration (us) of the BiCGSTAB direction-update stencil pass
+        with every system running, continuing from the last solve's state."""
+        us = ctypes.c_float()
+        self._bind_stream()
+        check(self.lib.fwils_time_krylov_pass(self._h, int(reps), ctypes.byref(us)), "fwils_time_krylov_pass")
+        return us.value
+
     def solve_stats(self):
         """(iters, recursive relres) of the last Krylov solve, per system."""
         it = np.zeros(self.total_sys, dtype=np.int32)
