@@ -28,3 +28,37 @@ def test_counter_summary_keys_match_the_kernel_names():
     name = ("void fw::c64::k_rows<256, 8, true, 1>(HIP_vector_type<float, 2u> const*, int)")
     assert bench._instance_name(name) == "fw::c64::k_rows<256, 8, true, 1>"
     assert bench.PASS_MATCH[3](name) and not bench.PASS_MATCH[1](name)
+    # the direction-update mode of the fused kernel (the roofline kernel)
+    px = bench._pass_instance(bench.PX_PASS, t)
+    assert px == "fw::c64::(anonymous namespace)::k_srows<256, 16, 3, 512>"
+    assert bench._pass_instance(bench.PX_PASS, dict(t, fused_points=8)).endswith("k_srows<256, 8, 3, 512>")
+    full = "void " + px + "(HIP_vector_type<float, 2u> const*, int)"
+    assert bench.PASS_MATCH[bench.PX_PASS](full) and not bench.PASS_MATCH[0](full)
+    assert bench._instance_name(full) == px
+
+
+def test_counter_summary_keeps_full_direction_update_launches(tmp_path):
+    """The summary scales both counters by the 1 GiB copy and, for the
+    direction-update pass, keeps only launches in which every system worked."""
+    sys.path.insert(0, ROOT)
+    import bench
+    px = "void fw::c64::(anonymous namespace)::k_srows<256, 16, 3, 512>(int)"
+    mv = "void fw::c64::k_rows<256, 8, true, 1>(int)"
+    cp = "__amd_rocclr_copyBuffer"
+    rows = {"FETCH_SIZE": [(cp, 524288.0), (px, 100.0), (px, 100.0), (px, 2.0), (mv, 10.0), (mv, 30.0)],
+            "WRITE_SIZE": [(cp, 1048576.0), (px, 50.0), (px, 50.0), (px, 1.0), (mv, 5.0), (mv, 5.0)]}
+    paths = []
+    for counter, recs in rows.items():
+        path = tmp_path / f"{counter}.csv"
+        lines = ["Kernel_Name,Counter_Name,Counter_Value"] + [f'"{n}",{counter},{v}' for n, v in recs]
+        path.write_text("\n".join(lines) + "\n")
+        paths.append(str(path))
+    out = tmp_path / "summary.json"
+    bench.summarize_counters(paths[0], paths[1], "test", str(out))
+    import json
+    d = json.loads(out.read_text())
+    assert d["fetch_scale"] == 2.0 and d["write_scale"] == 1.0
+    e = d["passes"][str(bench.PX_PASS)]["instances"]["fw::c64::(anonymous namespace)::k_srows<256, 16, 3, 512>"]
+    assert e["launches"] == 2 and e["hbm_bytes_per_launch"] == (100.0 * 2.0 + 50.0) * 1024.0
+    m = d["passes"]["3"]["instances"]["fw::c64::k_rows<256, 8, true, 1>"]
+    assert m["launches"] == 2 and m["hbm_bytes_per_launch"] == (20.0 * 2.0 + 5.0) * 1024.0
