@@ -68,7 +68,7 @@
 extern "C" {
 #endif
 
-#define FWILS_ABI_VERSION 7
+#define FWILS_ABI_VERSION 8
 
 typedef enum {
     FWILS_OK = 0,
@@ -111,6 +111,10 @@ typedef struct fwils_plan_s* fwils_plan;
                                       convergence check every iteration (the
                                       plain baseline; same kernels, nsys = 1)  */
 #define FWILS_SOLVE_NOGRAPH  0x4u  /* batched, but launched without HIP graphs */
+#define FWILS_SOLVE_SCATTERED 0x8u /* x receives u - rhs instead of u: with
+                                      rhs = u0 (fwils_incident) this is the
+                                      scattered field u_s = u - u0 of eq.
+                                      delu's decomposition u = u0 + u_s */
 
 /* Adjoint flags. */
 #define FWILS_ADJ_ACCUMULATE 0x1u  /* add into g instead of overwriting        */
@@ -161,7 +165,9 @@ fwils_status fwils_apply(fwils_plan plan, const void* u, void* Au);
  * BiCGSTAB unless fwils_set_krylov chose GMRES), vectors of the plan's
  * precision and FP64 inner products.  Stops each system when its recursive residual
  * satisfies ||r|| <= rtol ||rhs||, or after maxit iterations.  rhs, x:
- * device fields (x is output, and input with FWILS_SOLVE_X0).  iters (int32)
+ * device fields (x is output, and input with FWILS_SOLVE_X0; with
+ * FWILS_SOLVE_SCATTERED the output is the solution minus rhs, formed on the
+ * device; x may then alias rhs).  iters (int32)
  * and relres (double, TRUE residual ||rhs - A x|| / ||rhs||) are device
  * arrays [sum nsys] or NULL.  Returns FWILS_ENOCONV if any system stopped at
  * maxit and FWILS_EBREAKDOWN if any broke down; x is written in all cases.
@@ -186,12 +192,12 @@ fwils_status fwils_frechet(fwils_plan plan, const void* ub, const void* const* d
  *   g_rho = sum_sys conj( w~^2 u^a . u^b ),
  *   g_p   = - sum_sys conj( (E_h u^a)^T B^(p) (E_h u^b) ),  p = C11, C13, C33, C55,
  * accumulated over systems in FP64.  r: device data.  g: host array of nprob
- * device pointers to complex maps [5][nz][nx] (output; with
- * FWILS_ADJ_ACCUMULATE added to).  Problems that share a g pointer are
- * summed when FWILS_ADJ_ACCUMULATE is set.  In absolute units these maps can
- * lie below the float32 normal range in a complex64 plan (fields of O(1e-12)
- * m/N give products of O(1e-40)); fwils_adjoint_rel and the Tikhonov entry
- * points accumulate J* r in FP64 and apply m0 before rounding. */
+ * device pointers to complex128 maps [5][nz][nx] in BOTH precisions (output;
+ * with FWILS_ADJ_ACCUMULATE added to).  Problems that share a g pointer are
+ * summed when FWILS_ADJ_ACCUMULATE is set.  The maps are FP64 because in
+ * absolute units their values lie far below the float32 normal range (fields
+ * of O(1e-12) m/N give products of O(1e-40)); fwils_adjoint_rel gives the
+ * same operator in relative units of the plan's real type. */
 fwils_status fwils_adjoint(fwils_plan plan, const void* ub, const void* r,
                            void* const* g, uint32_t flags, double rtol, int32_t maxit);
 

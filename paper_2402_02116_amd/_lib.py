@@ -19,7 +19,7 @@ FWILS_OK, FWILS_EINVAL, FWILS_ENOMEM, FWILS_EDEVICE, FWILS_ENOCONV, FWILS_EBREAK
 FWILS_C64 = 0
 FWILS_C128 = 1
 FWILS_SYMBOL_SPECTRAL, FWILS_SYMBOL_CENTRAL = 0, 1
-FWILS_SOLVE_X0, FWILS_SOLVE_PLAIN, FWILS_SOLVE_NOGRAPH = 0x1, 0x2, 0x4
+FWILS_SOLVE_X0, FWILS_SOLVE_PLAIN, FWILS_SOLVE_NOGRAPH, FWILS_SOLVE_SCATTERED = 0x1, 0x2, 0x4, 0x8
 FWILS_ADJ_ACCUMULATE = 0x1
 FWILS_REG_IDENTITY, FWILS_REG_LAPLACIAN = 0, 1
 

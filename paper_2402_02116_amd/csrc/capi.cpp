@@ -194,9 +194,11 @@ hipError_t conv_problem(fwils_plan pl, const ProbHost& P, const cplx* f, cplx* o
 
 // One LS matvec with an epilogue, for nsys systems starting at the given
 // views (used both batched and per system).
+// tmp2: the separate stencil's output; null = the workspace vector at
+// tmp's offset (tmp is then a view of the workspace's FFT scratch).
 hipError_t matvec(fwils_plan pl, const ProbHost& P, const ProbDev& d, const cplx* u, cplx* tmp,
                   const real* maps, int epi, const cplx* aux, cplx* out, double* part,
-                  const SysState* st, hipStream_t s, const GmEpi* ge = nullptr) {
+                  const SysState* st, hipStream_t s, const GmEpi* ge = nullptr, cplx* tmp2 = nullptr) {
     const int rows = d.nsys * 2 * d.nz;
     const KernelCfg& k = P.cfg;
     hipError_t e = hipSuccess;
@@ -204,7 +206,7 @@ hipError_t matvec(fwils_plan pl, const ProbHost& P, const ProbDev& d, const cplx
         const StencilArgs a{u, nullptr, nullptr, nullptr, nullptr, maps, nullptr, 0};
         e = launch_srows(0, k.fuse_p, a, tmp, d, const_cast<SysState*>(st), pl->tw, s);
     } else {   // the stencil into tmp2 (same views as tmp), then the rows into tmp
-        cplx* tmp2 = pl->tmp2 + (tmp - pl->tmp);
+        if (!tmp2) tmp2 = pl->tmp2 + (tmp - pl->tmp);
         e = launch_body_force(k.st, u, tmp2, maps, d, st, s);
         if (e == hipSuccess) e = launch_rows_fwd(d.nx, k.row_p, tmp2, tmp, rows, 2 * d.nz, tile_rows(d), st, pl->tw, s);
     }
@@ -981,7 +983,8 @@ fwils_status fwils_solve(fwils_plan plan, const void* rhs, void* x, double rtol,
                          int32_t* iters, double* relres, uint32_t flags) {
     FW_TRY(check_plan(plan));
     FW_TRY(check_field_ptrs({rhs, x}));
-    if (!(rtol > 0) || maxit < 1 || (flags & ~(FWILS_SOLVE_X0 | FWILS_SOLVE_PLAIN | FWILS_SOLVE_NOGRAPH))) {
+    if (!(rtol > 0) || maxit < 1 ||
+        (flags & ~(FWILS_SOLVE_X0 | FWILS_SOLVE_PLAIN | FWILS_SOLVE_NOGRAPH | FWILS_SOLVE_SCATTERED))) {
         set_error("solve: need rtol > 0, maxit >= 1 and known flags");
         return FWILS_EINVAL;
     }
@@ -990,7 +993,10 @@ fwils_status fwils_solve(fwils_plan plan, const void* rhs, void* x, double rtol,
     if (x0) FW_HIP(launch_copy(static_cast<const cplx*>(x), plan->x, plan->total_field, s));
     fwils_status st = solve_ws(plan, static_cast<const cplx*>(rhs), x0, rtol, maxit, iters, relres, flags);
     if (st == FWILS_EDEVICE) return st;
-    FW_HIP(launch_copy(plan->x, static_cast<cplx*>(x), plan->total_field, s));
+    if (flags & FWILS_SOLVE_SCATTERED)   // u_s = u - u0 (eq. delu), elementwise, so x may alias rhs
+        FW_HIP(launch_diff(plan->x, static_cast<const cplx*>(rhs), static_cast<cplx*>(x), plan->total_field, s));
+    else
+        FW_HIP(launch_copy(plan->x, static_cast<cplx*>(x), plan->total_field, s));
     FW_HIP(hipStreamSynchronize(s));
     return st;
 }
@@ -1230,7 +1236,9 @@ fwils_status fwils_adjoint(fwils_plan plan, const void* ub, const void* r, void*
         set_error("adjoint: unknown flags");
         return FWILS_EINVAL;
     }
-    fwils_status st = adjoint_ws(plan, ub, r, g, (flags & FWILS_ADJ_ACCUMULATE) != 0, rtol, maxit);
+    // complex128 maps in both precisions: absolute-unit products lie below
+    // the float32 normal range at physical field scales
+    fwils_status st = adjoint_ws(plan, ub, r, g, (flags & FWILS_ADJ_ACCUMULATE) != 0, rtol, maxit, true);
     if (st == FWILS_EDEVICE) return st;
     FW_HIP(hipStreamSynchronize(plan->stream));
     return st;

@@ -587,6 +587,16 @@ hipError_t launch_copy(const cplx* src, cplx* dst, size_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(256), 0, s, (const float4*)src, (float4*)dst, n4);
     return hipGetLastError();
 }
+// out = a - b over n complex elements (out may alias a or b).
+__global__ __launch_bounds__(256) void k_diff(const cplx* __restrict__ a, const cplx* b, cplx* out, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        out[i] = csub(a[i], b[i]);
+}
+hipError_t launch_diff(const cplx* a, const cplx* b, cplx* out, size_t n, hipStream_t s) {
+    const int blocks = (int)std::min<size_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_diff, dim3(blocks), dim3(256), 0, s, a, b, out, n);
+    return hipGetLastError();
+}
 hipError_t launch_zero_d2(double2* dst, size_t n, hipStream_t s) {
     const int blocks = (int)std::min<size_t>((n + 255) / 256, 8192);
     hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, s, (float4*)dst, n);

@@ -209,6 +209,7 @@ hipError_t launch_correlate_f64(const cplx* ua, const cplx* ub, double2* g, cons
                                 bool accumulate, hipStream_t s);
 hipError_t launch_zero_d2(double2* dst, size_t n, hipStream_t s);
 hipError_t launch_copy(const cplx* src, cplx* dst, size_t n, hipStream_t s);
+hipError_t launch_diff(const cplx* a, const cplx* b, cplx* out, size_t n, hipStream_t s);
 hipError_t launch_zero(cplx* dst, size_t n, hipStream_t s);
 
 // Tikhonov-step model maps (5 maps of one grid).

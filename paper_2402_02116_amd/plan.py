@@ -200,9 +200,11 @@ class Plan:
         return out
 
     def solve(self, rhs, x0=None, rtol=1e-6, maxit=1000, plain=False, graph=True, out=None,
-              strict=False):
+              strict=False, scattered=False):
         """Krylov solve of A x = rhs with the plan's method (set_krylov); returns
-        SolveResult (iters, true relres)."""
+        SolveResult (iters, true relres).  scattered=True: x is the solution
+        minus rhs (the scattered field u - u0 when rhs = u0), formed by the
+        library."""
         self._field(rhs, "rhs")
         flags = 0
         if x0 is not None:
@@ -214,6 +216,8 @@ class Plan:
             flags |= _lib.FWILS_SOLVE_PLAIN
         if not graph:
             flags |= _lib.FWILS_SOLVE_NOGRAPH
+        if scattered:
+            flags |= _lib.FWILS_SOLVE_SCATTERED
         iters = torch.empty(self.total_sys, dtype=torch.int32, device=self.device)
         relres = torch.empty(self.total_sys, dtype=torch.float64, device=self.device)
         self._bind_stream()
@@ -242,7 +246,8 @@ class Plan:
         return d
 
     def adjoint(self, ub, r, rtol=1e-6, maxit=1000, g=None, accumulate=False):
-        """J* r: list (one per problem) of cdtype [5, nz, nx] maps."""
+        """J* r: list (one per problem) of complex128 [5, nz, nx] maps (FP64 in
+        both precisions: absolute-unit values lie below the float32 range)."""
         self._field(ub, "ub")
         _require_cuda(r, self.cdtype, "r")
         if r.numel() != self.data_elems():
@@ -250,10 +255,12 @@ class Plan:
         if g is None:
             if accumulate:
                 raise ValueError("accumulate needs the g maps to add to")
-            g = [torch.empty(5, p["nz"], p["nx"], dtype=self.cdtype, device=self.device)
+            g = [torch.empty(5, p["nz"], p["nx"], dtype=torch.complex128, device=self.device)
                  for p in self.problems]
-        for i, gi in enumerate(g):
-            _require_cuda(gi, self.cdtype, f"g[{i}]")
+        for i, (gi, p) in enumerate(zip(g, self.problems)):
+            _require_cuda(gi, torch.complex128, f"g[{i}]")
+            if tuple(gi.shape) != (5, p["nz"], p["nx"]):
+                raise ValueError(f"g[{i}] must be [5, {p['nz']}, {p['nx']}]")
         arr = (ctypes.c_void_p * len(g))(*[gi.data_ptr() for gi in g])
         self._bind_stream()
         st = self.lib.fwils_adjoint(self._h, _ptr(ub), _ptr(r), arr,

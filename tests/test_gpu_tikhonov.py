@@ -127,7 +127,9 @@ def test_adjoint_identity_at_full_size_512():
     plan.autotune(reps=3)
     src = sum((p["src_ixz"] for p in probs), [])
     frc = sum((p["src_f"] for p in probs), [])
-    ub = plan.solve(plan.incident(src, frc), rtol=1e-6, maxit=2000).x
+    bg = plan.solve(plan.incident(src, frc), rtol=1e-6, maxit=2000)
+    assert bg.status == 0 and np.all(bg.relres <= 2e-6), (bg.status, bg.relres.max())
+    ub = bg.x
     m0v = w["m0"].ravel()
     q = torch.as_tensor(w["dq"], dtype=torch.float32).cuda()
     r = torch.as_tensor(np.concatenate([x.ravel() for x in w["r"]]).astype(np.complex64)).cuda()

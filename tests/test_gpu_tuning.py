@@ -27,8 +27,10 @@ def _case(nx, nz, nsys, seed=5):
 
 
 # (1024, 32): the radix-32 row variant; (64, 1024): the 1024-thread column
-# variant and the longest columns of the shared / split variants
-@pytest.mark.parametrize("nx,nz", [(96, 64), (64, 96), (256, 384), (1024, 32), (64, 1024)])
+# variant and the longest columns of the shared / split variants; (512, 64):
+# the 512-point rows (radix-32, 16- and 8-point variants) and the fused
+# stencil + rows kernels of that width, which the 512^2 workload runs
+@pytest.mark.parametrize("nx,nz", [(96, 64), (64, 96), (256, 384), (1024, 32), (64, 1024), (512, 64)])
 def test_every_variant_matches_oracle(nx, nz):
     from paper_2402_02116_amd.plan import Plan
     p, maps = _case(nx, nz, 2)
@@ -80,12 +82,14 @@ def test_autotune_then_solve_matches_oracle():
         k += p["nsys"]
 
 
-@pytest.mark.parametrize("nx,nz", [(256, 64), (384, 48)])
+@pytest.mark.parametrize("nx,nz", [(256, 64), (384, 48), (512, 48)])
 def test_fused_solves_match_oracle_and_plain(nx, nz):
-    """Every fused stencil+rows variant through a whole BiCGSTAB solve (its
-    direction-update modes included, the 512-thread form of the closing mode
-    at these widths) against the oracle, and the batched solve bit-identical
-    to the per-source one under the same variant."""
+    """Every fused stencil+rows variant (and the separate stencil) through a
+    whole BiCGSTAB solve, its direction-update modes included (the 512-thread
+    form of the closing mode where it exists), with every row-transform
+    variant in both row passes (so every Krylov epilogue of the inverse rows
+    runs in each radix sequence), against the oracle; and the batched solve
+    bit-identical to the per-source one under the same variants."""
     from paper_2402_02116_amd.plan import Plan
     p, maps = _case(nx, nz, 3, seed=11)
     plan = Plan([p])
@@ -94,15 +98,21 @@ def test_fused_solves_match_oracle_and_plain(nx, nz):
     u0 = plan.incident(src, f)
     P = LSProblem(nx, nz, 8.0, p["c0"], p["rho0"], p["freq_hz"], 0.02, maps)
     uref, _ = P.solve(P.incident(src, f), tol=1e-11)
-    cands = plan.tuning_candidates(0, "fuse")
-    assert cands
-    for c in cands:
-        plan.set_tuning(0, **c)
-        print(f"fused {nx}x{nz} points {c['fused_points']}", flush=True)
-        res = plan.solve(u0, rtol=1e-6, maxit=500)
-        assert res.status == 0 and np.all(res.relres <= 2e-6), (c, res.relres)
-        x = plan.view(res.x, 0).cpu().numpy().astype(np.complex128)
-        for k in range(3):
-            assert _rel(x[k], uref[k]) < 1e-4, (c, k)
-        plain = plan.solve(u0, rtol=1e-6, maxit=500, plain=True)
-        assert torch.equal(res.x, plain.x) and np.array_equal(res.iters, plain.iters), c
+    fuse = plan.tuning_candidates(0, "fuse")
+    rows = [r["row_points"] for r in plan.tuning_candidates(0, "rows")]
+    assert len(fuse) >= 2 and len(rows) >= 2
+    worst = 0.0
+    for c in fuse:
+        for rp in rows:
+            plan.set_tuning(0, **dict(c, row_points=rp, row_points_inv=rp))
+            print(f"{nx}x{nz}: fused points {c['fused_points']}, row points {rp}", flush=True)
+            res = plan.solve(u0, rtol=1e-6, maxit=500)
+            assert res.status == 0 and np.all(res.relres <= 2e-6), (c, rp, res.relres)
+            x = plan.view(res.x, 0).cpu().numpy().astype(np.complex128)
+            for k in range(3):
+                err = _rel(x[k], uref[k])
+                worst = max(worst, err)
+                assert err < 1e-4, (c, rp, k, err)
+            plain = plan.solve(u0, rtol=1e-6, maxit=500, plain=True)
+            assert torch.equal(res.x, plain.x) and np.array_equal(res.iters, plain.iters), (c, rp)
+    print(f"{nx}x{nz}: {len(fuse) * len(rows)} solves, worst field error {worst:.2e}", flush=True)
