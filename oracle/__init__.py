@@ -31,9 +31,15 @@ dbi        One frequency stage of the distorted-Born iteration: background
            self-adaptive lambda cooling and the stopping rule.
 dense      Explicit matrices for the pins: the dense Green's matrix from a
            direct DFT sum and the sparse discrete elastic operator (eq. Ewave).
+elastic3d  The 3-D, generally anisotropic form: 21-constant stiffness and
+           its B matrices (eq. dC), the VTI set with C66 (App. C), the 3x3
+           Christoffel inverse, 6-strain stencils, one LS problem with its
+           solves, J and J*.
+dense3d    Explicit 3-D matrices for its pins (direct-DFT Green's matrix,
+           Kronecker-assembled E_h, the discrete 3-D eq. Ewave).
 
 Parity pins for every function live in tests/test_oracle_*.py.
 """
 
-from . import media, green, operators, krylov, problem, tikhonov, dbi, dense  # noqa: F401
+from . import media, green, operators, krylov, problem, tikhonov, dbi, dense, elastic3d, dense3d  # noqa: F401
 from .problem import LSProblem  # noqa: F401
