@@ -161,6 +161,21 @@ fwils_status fwils_convolve(fwils_plan plan, const void* f, void* out);
  * fields, must not alias. */
 fwils_status fwils_apply(fwils_plan plan, const void* u, void* Au);
 
+/* fwils_apply for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid allocation): the
+ * same kernels and result as fwils_apply, with the FFT scratch field and the
+ * separate stencil's output in a static device array of the library (64 MiB
+ * per GPU and precision build, held until the process ends) instead of the
+ * workspace's two scratch vectors.  Allocates nothing (no hipMalloc / free).
+ * Needs 2 * align256(field bytes) <= 64 MiB: fields of at most 4 Mi complex
+ * elements (complex64) or 2 Mi (complex128); FWILS_EINVAL beyond that, or if
+ * the current device is not the plan's workspace's device.  The plan's
+ * workspace still holds its constant tables and contrast.  Every call on one
+ * GPU shares that GPU's array: calls that overlap in time on one GPU (other
+ * streams, other plans, other threads) race and must be serialised by the
+ * caller.  Nothing in the array needs clearing between calls. */
+fwils_status fwils_apply_noalloc(fwils_plan plan, const void* u, void* Au);
+
 /* Solve A x = rhs for every system by the plan's Krylov method (eq. axb;
  * BiCGSTAB unless fwils_set_krylov chose GMRES), vectors of the plan's
  * precision and FP64 inner products.  Stops each system when its recursive residual

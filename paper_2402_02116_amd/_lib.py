@@ -62,6 +62,7 @@ SIGNATURES = {
     "fwils_body_force": (c_int32, [P, P, P]),
     "fwils_convolve": (c_int32, [P, P, P]),
     "fwils_apply": (c_int32, [P, P, P]),
+    "fwils_apply_noalloc": (c_int32, [P, P, P]),
     "fwils_solve": (c_int32, [P, P, P, c_double, c_int32, P, P, c_uint32]),
     "fwils_frechet": (c_int32, [P, P, ctypes.POINTER(c_void_p), P, c_double, c_int32]),
     "fwils_adjoint": (c_int32, [P, P, P, ctypes.POINTER(c_void_p), c_uint32, c_double, c_int32]),

@@ -25,6 +25,7 @@
     X(fwils_status, body_force, (fwils_plan plan, const void* u, void* b), (plan, u, b))                 \
     X(fwils_status, convolve, (fwils_plan plan, const void* f, void* out), (plan, f, out))               \
     X(fwils_status, apply, (fwils_plan plan, const void* u, void* Au), (plan, u, Au))                    \
+    X(fwils_status, apply_noalloc, (fwils_plan plan, const void* u, void* Au), (plan, u, Au))            \
     X(fwils_status, solve,                                                                                 \
       (fwils_plan plan, const void* rhs, void* x, double rtol, int32_t maxit, int32_t* iters,            \
        double* relres, uint32_t flags),                                                                    \

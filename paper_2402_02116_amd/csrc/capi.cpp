@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -976,6 +977,81 @@ fwils_status fwils_apply(fwils_plan plan, const void* u, void* Au) {
     for (const ProbHost& P : plan->probs)
         FW_HIP(matvec(plan, P, P.dev, at(u, P), at(plan->tmp, P), maps_at(plan, P), EPI_APPLY, nullptr,
                       static_cast<cplx*>(Au) + P.field_off, nullptr, nullptr, plan->stream));
+    return FWILS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Scratch of fwils_apply_noalloc: the column-tiled FFT scratch field and the
+// separate contrast stencil's output, in place of the two workspace vectors
+// fwils_apply uses.  Every GPU the library runs on holds one copy (per
+// precision build) for the life of the process.
+constexpr size_t kNoAllocBytes = (size_t)64 << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device dev, which must be current; looked
+// up once per device.  In host code the array's own name is not a device
+// address: only the looked-up pointer is ever handed to kernels.
+fwils_status noalloc_scratch(int dev, void** out) {
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("apply_noalloc: device %d beyond the %d this build tracks", dev, kMaxDevices);
+        return FWILS_EINVAL;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        FW_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) {
+            set_error("apply_noalloc: no device address for the static scratch on device %d", dev);
+            return FWILS_EDEVICE;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return FWILS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fwils_status fwils_apply_noalloc(fwils_plan plan, const void* u, void* Au) {
+    FW_TRY(check_plan(plan));
+    FW_TRY(check_field_ptrs({u, Au}));
+    if (u == Au) {
+        set_error("apply_noalloc: u and Au must not alias");
+        return FWILS_EINVAL;
+    }
+    const size_t fb = align256(plan->total_field * sizeof(cplx));
+    if (2 * fb > kNoAllocBytes) {
+        set_error("apply_noalloc: the plan's fields (%zu complex elements) need %zu bytes of scratch; "
+                  "the static scratch holds %zu (fields of at most %zu complex elements)",
+                  plan->total_field, 2 * fb, kNoAllocBytes, kNoAllocBytes / 2 / sizeof(cplx));
+        return FWILS_EINVAL;
+    }
+    int dev = -1;
+    FW_HIP(hipGetDevice(&dev));
+    hipPointerAttribute_t attr;
+    FW_HIP(hipPointerGetAttributes(&attr, plan->ws));
+    if (attr.device != dev) {
+        set_error("apply_noalloc: the plan's workspace is on device %d, device %d is current", attr.device, dev);
+        return FWILS_EINVAL;
+    }
+    void* base = nullptr;
+    FW_TRY(noalloc_scratch(dev, &base));
+    cplx* tmp = static_cast<cplx*>(base);
+    cplx* tmp2 = reinterpret_cast<cplx*>(static_cast<char*>(base) + fb);
+    // the scratch is written in full before it is read: nothing to clear
+    for (const ProbHost& P : plan->probs)
+        FW_HIP(matvec(plan, P, P.dev, at(u, P), tmp + P.field_off, maps_at(plan, P), EPI_APPLY, nullptr,
+                      static_cast<cplx*>(Au) + P.field_off, nullptr, nullptr, plan->stream, nullptr,
+                      tmp2 + P.field_off));
     return FWILS_OK;
 }
 

@@ -22,6 +22,7 @@
 #define fwils_body_force FW_CORE(fwils_body_force)
 #define fwils_convolve FW_CORE(fwils_convolve)
 #define fwils_apply FW_CORE(fwils_apply)
+#define fwils_apply_noalloc FW_CORE(fwils_apply_noalloc)
 #define fwils_solve FW_CORE(fwils_solve)
 #define fwils_frechet FW_CORE(fwils_frechet)
 #define fwils_adjoint FW_CORE(fwils_adjoint)

@@ -199,6 +199,15 @@ class Plan:
         check(self.lib.fwils_apply(self._h, _ptr(u), _ptr(out)), "fwils_apply")
         return out
 
+    def apply_noalloc(self, u, out=None):
+        """apply() with the library's static scratch instead of the workspace's
+        (fwils_apply_noalloc: no device allocation inside the call)."""
+        self._field(u, "u")
+        out = self.new_field() if out is None else self._field(out, "out")
+        self._bind_stream()
+        check(self.lib.fwils_apply_noalloc(self._h, _ptr(u), _ptr(out)), "fwils_apply_noalloc")
+        return out
+
     def solve(self, rhs, x0=None, rtol=1e-6, maxit=1000, plain=False, graph=True, out=None,
               strict=False, scattered=False):
         """Krylov solve of A x = rhs with the plan's method (set_krylov); returns
