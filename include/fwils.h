@@ -103,6 +103,39 @@ typedef struct {
     int32_t symbol;      /* fwils_symbol                                    */
 } fwils_problem;
 
+/* One 3-D (grid, frequency) problem with a general anisotropic background
+ * (the 21 elastic constants of the abbreviated subscript section; eq. decom)
+ * and a contrast in one of two parametrisations (eq. dC):
+ *   FWILS_PARAMS_VTI:     maps [6][nz][ny][nx] = (dC11, dC13, dC33, dC55, dC66,
+ *                         drho) with App. C's B matrices (dC12 = dC11 - 2 dC66,
+ *                         dC22 = dC11, dC23 = dC13, dC44 = dC55);
+ *   FWILS_PARAMS_GENERAL: maps [22][nz][ny][nx] = the 21 constants of the upper
+ *                         triangle of the 6 x 6 matrix in row-major order (C11,
+ *                         C12, ..., C16, C22, ..., C66), then drho.
+ * Fields of a 3-D plan are complex [nsys][3][nz][ny][nx] (u_x, u_y, u_z);
+ * sources, forces and receivers are [n][3] as (ix, iy, iz) and (fx, fy, fz),
+ * a point force F is F / dx^3 at its cell; data are [nsys][nrec][3].  The
+ * operator is eq. A with the six-strain Voigt stencil, G_hat(k) the inverse of
+ * the damped 3 x 3 Christoffel matrix of the background (products of two
+ * different wavenumber components use k = 0 at an even axis's Nyquist
+ * index).  Axis lengths 2^a 3^b 5^c from 16 to 256 (16, 20, 24, 32, 40, 48,
+ * 64, 80, 96, 128, 160, 192, 256); ny = 1 gives the 2-D plane with all three
+ * displacement components (d/dy = 0). */
+#define FWILS_PARAMS_VTI 0
+#define FWILS_PARAMS_GENERAL 1
+typedef struct {
+    int32_t nx, ny, nz;  /* cells per axis                                  */
+    double  dx;          /* cell size (m), all axes                         */
+    double  c0[21];      /* background C11, C12, ..., C16, C22, ..., C66 (Pa);
+                            the 6 x 6 matrix must be positive definite       */
+    double  rho0;        /* background density (kg/m^3)                     */
+    double  freq_hz;     /* frequency f (Hz)                                */
+    double  damping;     /* eta in w~ = 2 pi f (1 + i eta); eta > 0         */
+    int32_t nsys;        /* systems (sources) on this problem, >= 1         */
+    int32_t symbol;      /* fwils_symbol                                    */
+    int32_t params;      /* FWILS_PARAMS_VTI or FWILS_PARAMS_GENERAL        */
+} fwils_problem3;
+
 typedef struct fwils_plan_s* fwils_plan;
 
 /* Solve flags. */
@@ -124,6 +157,16 @@ typedef struct fwils_plan_s* fwils_plan;
 fwils_status fwils_plan_create(const fwils_problem* probs, int32_t nprob,
                                fwils_precision prec, fwils_plan* out);
 void fwils_plan_destroy(fwils_plan plan);
+/* A plan of 3-D problems (all problems of a plan are 2-D or all 3-D).  The
+ * same entry points apply to it with the 3-D layouts above: workspace,
+ * stream, contrast, receivers, incident, body force, convolve, apply,
+ * apply_noalloc, solve (BiCGSTAB or GMRES), frechet, adjoint (complex128 maps
+ * [nmaps][nz][ny][nx]), receiver_data, get_contrast, field_elems, solve
+ * statistics and fft2 (the 3-D transform).  The Tikhonov, DBI, tuning and
+ * pass-timing entry points return FWILS_EUNSUPPORTED for it; fwils_autotune
+ * leaves its problems unchanged. */
+fwils_status fwils_plan_create3(const fwils_problem3* probs, int32_t nprob, fwils_precision prec,
+                                fwils_plan* out);
 
 /* Bytes of device workspace the plan needs (256-byte aligned start). */
 fwils_status fwils_workspace_size(fwils_plan plan, size_t* bytes);

@@ -30,6 +30,15 @@ class FwilsProblem(ctypes.Structure):
                 ("nsys", c_int32), ("symbol", c_int32)]
 
 
+class FwilsProblem3(ctypes.Structure):
+    _fields_ = [("nx", c_int32), ("ny", c_int32), ("nz", c_int32), ("dx", c_double), ("c0", c_double * 21),
+                ("rho0", c_double), ("freq_hz", c_double), ("damping", c_double), ("nsys", c_int32),
+                ("symbol", c_int32), ("params", c_int32)]
+
+
+FWILS_PARAMS_VTI, FWILS_PARAMS_GENERAL = 0, 1
+
+
 class FwilsTuning(ctypes.Structure):
     _fields_ = [("row_points", c_int32), ("col_points", c_int32), ("col_width", c_int32),
                 ("col_shared", c_int32), ("stencil_rows", c_int32), ("stencil_sys", c_int32),
@@ -51,6 +60,7 @@ FWILS_GMRES_CGS1 = 0x1
 P = c_void_p
 SIGNATURES = {
     "fwils_plan_create": (c_int32, [ctypes.POINTER(FwilsProblem), c_int32, c_int32, ctypes.POINTER(c_void_p)]),
+    "fwils_plan_create3": (c_int32, [ctypes.POINTER(FwilsProblem3), c_int32, c_int32, ctypes.POINTER(c_void_p)]),
     "fwils_plan_destroy": (None, [P]),
     "fwils_workspace_size": (c_int32, [P, ctypes.POINTER(c_size_t)]),
     "fwils_set_workspace": (c_int32, [P, P, c_size_t]),

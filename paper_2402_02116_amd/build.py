@@ -22,7 +22,7 @@ LIB = os.path.join(HERE, "libfwils.so")
 # The core (kernels and capi.cpp) is compiled once per precision: complex64
 # and, with -DFW_C128, complex128; abi.cpp (the public entry points) once.
 CORE = ["kernels_rows.hip", "kernels_cols.hip", "kernels_fft.hip", "kernels_vec.hip", "kernels_maps.hip",
-        "kernels_gmres.hip", "kernels_srows.hip", "capi.cpp"]
+        "kernels_gmres.hip", "kernels_srows.hip", "kernels_3d.hip", "capi.cpp"]
 UNITS = [(s, "c64") for s in CORE] + [(s, "c128") for s in CORE] + [("abi.cpp", None)]
 SOURCES = CORE + ["abi.cpp"]
 
@@ -63,7 +63,7 @@ def build(jobs=None, verbose=False):
     os.makedirs(BUILD, exist_ok=True)
     jobs = jobs or min(len(UNITS), os.cpu_count() or 1)
     # longest units first
-    order = sorted(UNITS, key=lambda u: (u[0] not in ("kernels_rows.hip", "kernels_cols.hip",
+    order = sorted(UNITS, key=lambda u: (u[0] not in ("kernels_rows.hip", "kernels_cols.hip", "kernels_3d.hip",
                                                      "kernels_srows.hip", "kernels_vec.hip"), u[1] != "c64"))
     with concurrent.futures.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(lambda u: _compile(u, verbose), order))

@@ -96,6 +96,10 @@ fwils_status fwils_plan_create_c64(const fwils_problem* probs, int32_t nprob, fw
                                    fwils_plan* out);
 fwils_status fwils_plan_create_c128(const fwils_problem* probs, int32_t nprob, fwils_precision prec,
                                     fwils_plan* out);
+fwils_status fwils_plan_create3_c64(const fwils_problem3* probs, int32_t nprob, fwils_precision prec,
+                                    fwils_plan* out);
+fwils_status fwils_plan_create3_c128(const fwils_problem3* probs, int32_t nprob, fwils_precision prec,
+                                     fwils_plan* out);
 void fwils_plan_destroy_c64(fwils_plan plan);
 void fwils_plan_destroy_c128(fwils_plan plan);
 }
@@ -138,6 +142,14 @@ fwils_status fwils_plan_create(const fwils_problem* probs, int32_t nprob, fwils_
     if (prec == FWILS_C64) return fwils_plan_create_c64(probs, nprob, prec, out);
     if (prec == FWILS_C128) return fwils_plan_create_c128(probs, nprob, prec, out);
     set_error("plan_create: unknown precision");
+    return FWILS_EINVAL;
+}
+
+fwils_status fwils_plan_create3(const fwils_problem3* probs, int32_t nprob, fwils_precision prec,
+                                fwils_plan* out) {
+    if (prec == FWILS_C64) return fwils_plan_create3_c64(probs, nprob, prec, out);
+    if (prec == FWILS_C128) return fwils_plan_create3_c128(probs, nprob, prec, out);
+    set_error("plan_create3: unknown precision");
     return FWILS_EINVAL;
 }
 

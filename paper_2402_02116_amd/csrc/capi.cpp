@@ -79,6 +79,12 @@ struct ProbHost {
     int np_vec;           // partial records per system from vector kernels
     KernelCfg cfg;        // kernel variants (defaults, the autotuner's or the caller's)
     float tuned_us[4];    // autotune: stencil, row, column, stencil + rows time of the choice
+    // dimensions of the field (2-D: ny = 1, two components, five maps)
+    bool d3 = false;      // a 3-D problem (fwils_plan_create3)
+    int ny = 1, ncomp = 2, nmaps = 5;
+    int rps = 0;          // rows of nx points per system: ncomp nz ny
+    size_t cells = 0;     // nx ny nz
+    ProbDev3 dev3{};      // 3-D kernel constants
 };
 
 }  // namespace
@@ -86,6 +92,8 @@ struct ProbHost {
 struct fwils_plan_s {
     int32_t prec = kPrec;   // first member in both precisions: read by the dispatch
     std::vector<ProbHost> probs;
+    bool d3 = false;        // a plan of 3-D problems
+    int cstride = 2;        // ints per source / receiver cell index, doubles per force
     size_t total_field = 0, total_sys = 0, maps_floats = 0;
     int max_np = 0;
     hipStream_t stream = nullptr;
@@ -169,6 +177,15 @@ fwils_status check_plan(fwils_plan plan, bool need_ws = true) {
     return FWILS_OK;
 }
 
+// FWILS_EUNSUPPORTED for a plan of 3-D problems (entry points of the 2-D path only).
+fwils_status only_2d(fwils_plan plan, const char* what) {
+    if (plan && plan->d3) {
+        set_error("%s: not available for 3-D plans", what);
+        return FWILS_EUNSUPPORTED;
+    }
+    return FWILS_OK;
+}
+
 // Views of the plan-level vectors for problem i.
 inline cplx* at(cplx* base, const ProbHost& P) { return base + P.field_off; }
 inline const cplx* at(const void* base, const ProbHost& P) {
@@ -180,16 +197,44 @@ inline double* part_at(double* base, fwils_plan pl, const ProbHost& P) {
 }
 inline real* maps_at(fwils_plan pl, const ProbHost& P) { return pl->maps + P.map_off; }
 
+// The kernel constants of a 3-D problem for a view of d.nsys systems.
+inline ProbDev3 view3(const ProbHost& P, const ProbDev& d) {
+    ProbDev3 d3 = P.dev3;
+    d3.nsys = d.nsys;
+    return d3;
+}
+
+// The part of a convolution between the forward and the inverse x (row)
+// transforms, in place on the spectrum tmp: 2-D, the column pass with the
+// Green multiply; 3-D, the y transforms around the z pass with the 3 x 3
+// Green multiply.  d: the view (its nsys systems from tmp on).
+hipError_t spectral(fwils_plan pl, const ProbHost& P, const ProbDev& d, cplx* tmp, const SysState* st, hipStream_t s) {
+    if (!P.d3) return launch_cols(COL_GREEN, P.cfg.col, tmp, d, st, pl->tw, s);
+    const ProbDev3 d3 = view3(P, d);
+    const int nx = d3.nx, ny = d3.ny, nz = d3.nz;
+    hipError_t e = hipSuccess;
+    if (ny > 1) e = launch_axis3(AX_FWD, ny, tmp, nx, d3.nsys * 3 * nz, 3 * nz, st, pl->tw, d3, s);
+    if (e == hipSuccess) e = launch_axis3(AX_GREEN, nz, tmp, nx * ny, d3.nsys, 1, st, pl->tw, d3, s);
+    if (e == hipSuccess && ny > 1) e = launch_axis3(AX_INV, ny, tmp, nx, d3.nsys * 3 * nz, 3 * nz, st, pl->tw, d3, s);
+    return e;
+}
+
+// The contrast stencil of either dimension (vector update vm, a.b the output).
+hipError_t stencil_any(const ProbHost& P, const ProbDev& d, int vm, const StencilArgs& a, SysState* st, hipStream_t s) {
+    if (P.d3) return launch_stencil3(vm, a, view3(P, d), st, s);
+    return launch_stencil(vm, P.cfg.st, a, d, st, s);
+}
+
 // y = G0 conv f for problem P (f read, out written; tmp is scratch).
 hipError_t conv_problem(fwils_plan pl, const ProbHost& P, const cplx* f, cplx* out) {
-    const int rows = P.p.nsys * 2 * P.p.nz;
+    const int rows = P.p.nsys * P.rps;
     cplx* tmp = at(pl->tmp, P);
-    hipError_t e = launch_rows_fwd(P.p.nx, P.cfg.row_p, f, tmp, rows, 2 * P.p.nz, tile_rows(P.dev), nullptr, pl->tw,
+    hipError_t e = launch_rows_fwd(P.p.nx, P.cfg.row_p, f, tmp, rows, P.rps, tile_rows(P.dev), nullptr, pl->tw,
                                    pl->stream);
-    if (e == hipSuccess) e = launch_cols(COL_GREEN, P.cfg.col, tmp, P.dev, nullptr, pl->tw, pl->stream);
+    if (e == hipSuccess) e = spectral(pl, P, P.dev, tmp, nullptr, pl->stream);
     if (e == hipSuccess)
         e = launch_rows_inv(P.p.nx, P.cfg.row_pi, EPI_STORE, tmp, nullptr, nullptr, out, nullptr, rows,
-                            2 * P.p.nz, tile_rows(P.dev), nullptr, pl->tw, pl->stream);
+                            P.rps, tile_rows(P.dev), nullptr, pl->tw, pl->stream);
     return e;
 }
 
@@ -200,7 +245,7 @@ hipError_t conv_problem(fwils_plan pl, const ProbHost& P, const cplx* f, cplx* o
 hipError_t matvec(fwils_plan pl, const ProbHost& P, const ProbDev& d, const cplx* u, cplx* tmp,
                   const real* maps, int epi, const cplx* aux, cplx* out, double* part,
                   const SysState* st, hipStream_t s, const GmEpi* ge = nullptr, cplx* tmp2 = nullptr) {
-    const int rows = d.nsys * 2 * d.nz;
+    const int rows = d.nsys * P.rps;
     const KernelCfg& k = P.cfg;
     hipError_t e = hipSuccess;
     if (k.fuse_p) {
@@ -208,12 +253,13 @@ hipError_t matvec(fwils_plan pl, const ProbHost& P, const ProbDev& d, const cplx
         e = launch_srows(0, k.fuse_p, a, tmp, d, const_cast<SysState*>(st), pl->tw, s);
     } else {   // the stencil into tmp2 (same views as tmp), then the rows into tmp
         if (!tmp2) tmp2 = pl->tmp2 + (tmp - pl->tmp);
-        e = launch_body_force(k.st, u, tmp2, maps, d, st, s);
-        if (e == hipSuccess) e = launch_rows_fwd(d.nx, k.row_p, tmp2, tmp, rows, 2 * d.nz, tile_rows(d), st, pl->tw, s);
+        const StencilArgs a{u, nullptr, nullptr, nullptr, tmp2, maps, nullptr, 0};
+        e = stencil_any(P, d, VM_NONE, a, const_cast<SysState*>(st), s);
+        if (e == hipSuccess) e = launch_rows_fwd(d.nx, k.row_p, tmp2, tmp, rows, P.rps, tile_rows(d), st, pl->tw, s);
     }
-    if (e == hipSuccess) e = launch_cols(COL_GREEN, k.col, tmp, d, st, pl->tw, s);
+    if (e == hipSuccess) e = spectral(pl, P, d, tmp, st, s);
     if (e == hipSuccess)
-        e = launch_rows_inv(d.nx, k.row_pi, epi, tmp, u, aux, out, part, rows, 2 * d.nz, tile_rows(d), st, pl->tw, s,
+        e = launch_rows_inv(d.nx, k.row_pi, epi, tmp, u, aux, out, part, rows, P.rps, tile_rows(d), st, pl->tw, s,
                             ge);
     return e;
 }
@@ -254,7 +300,7 @@ SysView make_view(fwils_plan pl, const ProbHost& P, int s0, int ns) {
 hipError_t bicg_iteration(fwils_plan pl, const ProbHost& P, const SysView& V, int parity, bool first,
                           hipStream_t s, bool px_only = false) {
     const int ns = V.d.nsys;
-    const int rows = ns * 2 * V.d.nz;
+    const int rows = ns * P.rps;
     cplx *x = pl->x + V.foff, *r = pl->r + V.foff, *rh = pl->rhat + V.foff, *v = pl->v + V.foff,
            *sv = pl->s + V.foff, *t = pl->t + V.foff, *tmp = pl->tmp + V.foff;
     cplx* pold = (parity ? pl->p2 : pl->p) + V.foff;
@@ -276,22 +322,22 @@ hipError_t bicg_iteration(fwils_plan pl, const ProbHost& P, const SysView& V, in
         if (k.fuse_p) return launch_srows(vm, k.fuse_p, a, tmp, V.d, st, pl->tw, s);
         StencilArgs a2 = a;   // the separate stencil writes tmp2, the rows read it
         a2.b = pl->tmp2 + V.foff;
-        hipError_t r = launch_stencil(vm, k.st, a2, V.d, st, s);
+        hipError_t r = stencil_any(P, V.d, vm, a2, st, s);
         if (r == hipSuccess)
-            r = launch_rows_fwd(V.d.nx, k.row_p, a2.b, tmp, rows, 2 * V.d.nz, tile_rows(V.d), st, pl->tw, s);
+            r = launch_rows_fwd(V.d.nx, k.row_p, a2.b, tmp, rows, P.rps, tile_rows(V.d), st, pl->tw, s);
         return r;
     };
     hipError_t e = stencil_rows(first ? VM_P : VM_PX, ap);
     if (px_only) return e;
-    if (e == hipSuccess) e = launch_cols(COL_GREEN, k.col, tmp, V.d, st, pl->tw, s);
+    if (e == hipSuccess) e = spectral(pl, P, V.d, tmp, st, s);
     if (e == hipSuccess)
-        e = launch_rows_inv(V.d.nx, k.row_pi, EPI_BICG_V, tmp, pnew, rh, v, pV, rows, 2 * V.d.nz, tile_rows(V.d), st,
+        e = launch_rows_inv(V.d.nx, k.row_pi, EPI_BICG_V, tmp, pnew, rh, v, pV, rows, P.rps, tile_rows(V.d), st,
                             pl->tw, s);
     const StencilArgs as{r, v, nullptr, sv, tmp, maps, pV, P.np_rows};
     if (e == hipSuccess) e = stencil_rows(VM_S, as);
-    if (e == hipSuccess) e = launch_cols(COL_GREEN, k.col, tmp, V.d, st, pl->tw, s);
+    if (e == hipSuccess) e = spectral(pl, P, V.d, tmp, st, s);
     if (e == hipSuccess)
-        e = launch_rows_inv(V.d.nx, k.row_pi, EPI_BICG_T, tmp, sv, rh, t, pT, rows, 2 * V.d.nz, tile_rows(V.d), st,
+        e = launch_rows_inv(V.d.nx, k.row_pi, EPI_BICG_T, tmp, sv, rh, t, pT, rows, P.rps, tile_rows(V.d), st,
                             pl->tw, s);
     return e;
 }
@@ -299,9 +345,9 @@ hipError_t bicg_iteration(fwils_plan pl, const ProbHost& P, const SysView& V, in
 // The t pass of an iteration alone: t = s - G0*b(s) from the spectrum in the
 // scratch field, with its dot-product records (a timing aid).
 hipError_t bicg_t_pass(fwils_plan pl, const ProbHost& P, const SysView& V, hipStream_t s) {
-    const int rows = V.d.nsys * 2 * V.d.nz;
+    const int rows = V.d.nsys * P.rps;
     return launch_rows_inv(V.d.nx, P.cfg.row_pi, EPI_BICG_T, pl->tmp + V.foff, pl->s + V.foff, pl->rhat + V.foff,
-                           pl->t + V.foff, pl->partT + V.poff_row, rows, 2 * V.d.nz, tile_rows(V.d),
+                           pl->t + V.foff, pl->partT + V.poff_row, rows, P.rps, tile_rows(V.d),
                            pl->state + V.soff, pl->tw, s);
 }
 
@@ -669,20 +715,22 @@ fwils_status upload_sources(fwils_plan plan, const int32_t* src_ixz, const doubl
         set_error("%s: null source pointer", what);
         return FWILS_EINVAL;
     }
+    const int cs = plan->cstride;
     for (const ProbHost& P : plan->probs) {
         for (int sy = 0; sy < P.p.nsys; ++sy) {
             const size_t k = P.sys_off + sy;
-            const int ix = src_ixz[2 * k], iz = src_ixz[2 * k + 1];
-            if (ix < 0 || ix >= P.p.nx || iz < 0 || iz >= P.p.nz || !std::isfinite(src_f[2 * k]) ||
-                !std::isfinite(src_f[2 * k + 1])) {
-                set_error("%s: source %zu at (%d, %d) outside the grid or non-finite force", what, k, ix, iz);
+            const int ix = src_ixz[cs * k], iz = src_ixz[cs * k + cs - 1], iy = cs == 3 ? src_ixz[cs * k + 1] : 0;
+            bool finite = true;
+            for (int c = 0; c < cs; ++c) finite = finite && std::isfinite(src_f[cs * k + c]);
+            if (ix < 0 || ix >= P.p.nx || iz < 0 || iz >= P.p.nz || iy < 0 || iy >= P.ny || !finite) {
+                set_error("%s: source %zu at (%d, %d, %d) outside the grid or non-finite force", what, k, ix, iy, iz);
                 return FWILS_EINVAL;
             }
         }
     }
     FW_HIP(hipStreamSynchronize(plan->stream));
-    FW_HIP(hipMemcpy(plan->src_i, src_ixz, plan->total_sys * 2 * sizeof(int32_t), hipMemcpyHostToDevice));
-    FW_HIP(hipMemcpy(plan->src_f, src_f, plan->total_sys * 2 * sizeof(double), hipMemcpyHostToDevice));
+    FW_HIP(hipMemcpy(plan->src_i, src_ixz, plan->total_sys * cs * sizeof(int32_t), hipMemcpyHostToDevice));
+    FW_HIP(hipMemcpy(plan->src_f, src_f, plan->total_sys * cs * sizeof(double), hipMemcpyHostToDevice));
     return FWILS_OK;
 }
 
@@ -691,9 +739,12 @@ fwils_status upload_sources(fwils_plan plan, const int32_t* src_ixz, const doubl
 hipError_t incident_ws(fwils_plan plan, cplx* f, cplx* out) {
     for (const ProbHost& P : plan->probs) {
         hipError_t e = launch_zero(at(f, P), (size_t)P.p.nsys * P.n_per_sys, plan->stream);
+        const int cs = plan->cstride;
         if (e == hipSuccess)
-            e = launch_point_sources(at(f, P), plan->src_i + 2 * P.sys_off, plan->src_f + 2 * P.sys_off, P.dev,
-                                     plan->stream);
+            e = P.d3 ? launch_point_sources3(at(f, P), plan->src_i + cs * P.sys_off, plan->src_f + cs * P.sys_off,
+                                             P.dev3, plan->stream)
+                     : launch_point_sources(at(f, P), plan->src_i + cs * P.sys_off, plan->src_f + cs * P.sys_off,
+                                            P.dev, plan->stream);
         if (e == hipSuccess) e = conv_problem(plan, P, at(f, P), at(out, P));
         if (e != hipSuccess) return e;
     }
@@ -707,6 +758,136 @@ fwils_status check_field_ptrs(std::initializer_list<const void*> ptrs) {
             return FWILS_EINVAL;
         }
     return FWILS_OK;
+}
+
+// Offsets of every problem in the plan-level vectors, partial-record sizes
+// and the workspace layout, from the problems' dimensions and variants.
+void layout_plan(fwils_plan pl) {
+    size_t foff = 0, soff = 0, moff = 0;
+    pl->max_np = 0;
+    for (ProbHost& P : pl->probs) {
+        P.n_per_sys = (size_t)P.ncomp * P.cells;
+        P.field_off = foff;
+        P.sys_off = soff;
+        P.map_off = moff;
+        P.data_off = 0;
+        P.nrec = 0;
+        P.tuned_us[0] = P.tuned_us[1] = P.tuned_us[2] = P.tuned_us[3] = 0.f;
+        P.np_rows = row_geom(P.p.nx, P.cfg.row_pi, P.rps).blocks_per_sys;   // the inverse pass's partials
+        P.np_vec = vec_blocks_per_sys((int)P.n_per_sys);
+        pl->max_np = std::max(pl->max_np, P.np_vec);
+        {   // partial buffers fit every row-transform variant
+            int cand[3];
+            const int nc = row_candidates(P.p.nx, cand);
+            for (int c = 0; c < nc; ++c)
+                pl->max_np = std::max(pl->max_np, row_geom(P.p.nx, cand[c], P.rps).blocks_per_sys);
+        }
+        foff += (size_t)P.p.nsys * P.n_per_sys;
+        soff += (size_t)P.p.nsys;
+        moff += (size_t)P.nmaps * P.cells;
+    }
+    const int nprob = (int)pl->probs.size();
+    pl->total_field = foff;
+    pl->total_sys = soff;
+    pl->maps_floats = moff;
+    // workspace layout
+    size_t o = 0;
+    pl->off_tw = o;
+    o = align256(o + twiddle_table_elems() * sizeof(cplx));
+    pl->off_state = o;
+    o = align256(o + pl->total_sys * sizeof(SysState));
+    pl->off_part = o;
+    pl->part_bytes = align256(pl->total_sys * (size_t)pl->max_np * kPartialNV * sizeof(double));
+    o += 4 * pl->part_bytes;
+    pl->off_maps = o;
+    o = align256(o + pl->maps_floats * sizeof(real));
+    pl->off_rec = o;
+    o = align256(o + (size_t)nprob * kMaxRec * 3 * sizeof(int32_t));
+    pl->off_src = o;   // source cells, then (256-byte aligned) source forces
+    o = align256(o + align256(pl->total_sys * 3 * sizeof(int32_t)) + pl->total_sys * 3 * sizeof(double));
+    pl->off_vec = o;
+    o += kNumVec * align256(pl->total_field * sizeof(cplx));
+    // the Tikhonov step's model-map scratch: single-grid 2-D plans
+    bool one_grid = !pl->d3;
+    for (int i = 1; i < nprob; ++i)
+        one_grid = one_grid && pl->probs[i].p.nx == pl->probs[0].p.nx && pl->probs[i].p.nz == pl->probs[0].p.nz &&
+                   pl->probs[i].p.dx == pl->probs[0].p.dx;
+    pl->map_n = one_grid ? (size_t)pl->probs[0].p.nx * pl->probs[0].p.nz : 0;
+    pl->off_mapws = o;
+    if (pl->map_n) {
+        o += 7 * align256(5 * pl->map_n * sizeof(real)) + align256(5 * pl->map_n * sizeof(double2));
+        o += align256(kDotPartials * sizeof(double)) + align256(16 * sizeof(double)) +
+             align256(kMaxCgIters + 1) * sizeof(double);
+    }
+    pl->ws_bytes = o;
+}
+
+// Kernel constants of a 3-D problem.  The scaled Christoffel coefficients
+// come from the general 4-index tensor C_ijkl = C[V(i,j)][V(k,l)]:
+// Gamma_ik = sum_jl C_ijkl k_j k_l, so the coefficient of the monomial
+// k_j k_l (j <= l) in entry (i, k) is C_ijkj for j = l and C_ijkl + C_ilkj
+// otherwise, divided by rho0 w^2 (w real).
+ProbDev3 make_dev3(const fwils_problem3& p) {
+    ProbDev3 d{};
+    const double w = 2.0 * M_PI * p.freq_hz, eta = p.damping;
+    const double rw2 = p.rho0 * w * w;
+    d.nx = p.nx;
+    d.ny = p.ny;
+    d.nz = p.nz;
+    d.nsys = p.nsys;
+    d.params = p.params == FWILS_PARAMS_GENERAL ? kParamsGeneral : kParamsVti;
+    d.symbol = p.symbol;
+    d.inv4dx2 = (real)(1.0 / (4.0 * p.dx * p.dx));
+    d.w2 = mkc((real)(w * w * (1.0 - eta * eta)), (real)(w * w * 2.0 * eta));
+    d.dx = (real)p.dx;
+    double C[6][6];
+    int q = 0;
+    for (int i = 0; i < 6; ++i)
+        for (int j = i; j < 6; ++j) {
+            C[i][j] = C[j][i] = p.c0[q];
+            ++q;
+        }
+    const int V[3][3] = {{0, 5, 4}, {5, 1, 3}, {4, 3, 2}};   // Voigt index of (i, j)
+    const int pr[6][2] = {{0, 0}, {1, 1}, {2, 2}, {1, 2}, {0, 2}, {0, 1}};
+    for (int a = 0; a < 6; ++a) {
+        const int i = pr[a][0], k = pr[a][1];
+        for (int b = 0; b < 6; ++b) {
+            const int j = pr[b][0], l = pr[b][1];
+            double c = C[V[i][j]][V[k][l]];
+            if (j != l) c += C[V[i][l]][V[k][j]];
+            d.gq[a][b] = (real)(c / rw2);
+        }
+    }
+    d.ga = mkc((real)(1.0 - eta * eta), (real)(2.0 * eta));
+    d.gscale = (real)(1.0 / (rw2 * (double)p.nx * (double)p.ny * (double)p.nz));
+    d.dk[0] = (real)(2.0 * M_PI / (p.nx * p.dx));
+    d.dk[1] = (real)(2.0 * M_PI / (p.ny * p.dx));
+    d.dk[2] = (real)(2.0 * M_PI / (p.nz * p.dx));
+    return d;
+}
+
+// Whether a symmetric 6 x 6 matrix (21 constants) is positive definite
+// (Cholesky in double).
+bool spd21(const double* c21) {
+    double A[6][6];
+    int q = 0;
+    for (int i = 0; i < 6; ++i)
+        for (int j = i; j < 6; ++j) {
+            A[i][j] = A[j][i] = c21[q];
+            ++q;
+        }
+    for (int j = 0; j < 6; ++j) {
+        double d = A[j][j];
+        for (int k = 0; k < j; ++k) d -= A[j][k] * A[j][k];
+        if (!(d > 0.0)) return false;
+        A[j][j] = std::sqrt(d);
+        for (int i = j + 1; i < 6; ++i) {
+            double v = A[i][j];
+            for (int k = 0; k < j; ++k) v -= A[i][k] * A[j][k];
+            A[i][j] = v / A[j][j];
+        }
+    }
+    return true;
 }
 
 }  // namespace
@@ -744,66 +925,102 @@ fwils_status fwils_plan_create(const fwils_problem* probs, int32_t nprob, fwils_
         }
     }
     fwils_plan pl = new fwils_plan_s();
-    size_t foff = 0, soff = 0, moff = 0;
     for (int i = 0; i < nprob; ++i) {
         ProbHost P;
         P.p = probs[i];
         P.dev = make_dev(P.p);
-        P.n_per_sys = (size_t)2 * P.p.nz * P.p.nx;
-        P.field_off = foff;
-        P.sys_off = soff;
-        P.map_off = moff;
-        P.data_off = 0;
-        P.nrec = 0;
+        P.ny = 1;
+        P.ncomp = 2;
+        P.nmaps = 5;
+        P.cells = (size_t)P.p.nz * P.p.nx;
+        P.rps = 2 * P.p.nz;
         P.cfg = kernel_cfg_default(P.p.nx, P.p.nz);
         P.dev.tile_sh = col_tile_shift(P.p.nx, P.cfg.col.W);
-        P.tuned_us[0] = P.tuned_us[1] = P.tuned_us[2] = P.tuned_us[3] = 0.f;
-        P.np_rows = row_geom(P.p.nx, P.cfg.row_pi, 2 * P.p.nz).blocks_per_sys;   // the inverse pass's partials
-        P.np_vec = vec_blocks_per_sys((int)P.n_per_sys);
-        pl->max_np = std::max(pl->max_np, P.np_vec);
-        {   // partial buffers fit every row-transform variant
-            int cand[3];
-            const int nc = row_candidates(P.p.nx, cand);
-            for (int c = 0; c < nc; ++c)
-                pl->max_np = std::max(pl->max_np, row_geom(P.p.nx, cand[c], 2 * P.p.nz).blocks_per_sys);
-        }
-        foff += (size_t)P.p.nsys * P.n_per_sys;
-        soff += (size_t)P.p.nsys;
-        moff += (size_t)5 * P.p.nz * P.p.nx;
         pl->probs.push_back(P);
     }
-    pl->total_field = foff;
-    pl->total_sys = soff;
-    pl->maps_floats = moff;
-    // workspace layout
-    size_t o = 0;
-    pl->off_tw = o;
-    o = align256(o + twiddle_table_elems() * sizeof(cplx));
-    pl->off_state = o;
-    o = align256(o + pl->total_sys * sizeof(SysState));
-    pl->off_part = o;
-    pl->part_bytes = align256(pl->total_sys * (size_t)pl->max_np * kPartialNV * sizeof(double));
-    o += 4 * pl->part_bytes;
-    pl->off_maps = o;
-    o = align256(o + pl->maps_floats * sizeof(real));
-    pl->off_rec = o;
-    o = align256(o + (size_t)nprob * kMaxRec * 2 * sizeof(int32_t));
-    pl->off_src = o;   // source cells, then (256-byte aligned) source forces
-    o = align256(o + align256(pl->total_sys * 2 * sizeof(int32_t)) + pl->total_sys * 2 * sizeof(double));
-    pl->off_vec = o;
-    o += kNumVec * align256(pl->total_field * sizeof(cplx));
-    bool one_grid = true;
-    for (int i = 1; i < nprob; ++i)
-        one_grid = one_grid && probs[i].nx == probs[0].nx && probs[i].nz == probs[0].nz &&
-                   probs[i].dx == probs[0].dx;
-    pl->map_n = one_grid ? (size_t)probs[0].nx * probs[0].nz : 0;
-    pl->off_mapws = o;
-    if (pl->map_n) {
-        o += 7 * align256(5 * pl->map_n * sizeof(real)) + align256(5 * pl->map_n * sizeof(double2));
-        o += align256(kDotPartials * sizeof(double)) + align256(16 * sizeof(double)) +
-             align256(kMaxCgIters + 1) * sizeof(double);
+    layout_plan(pl);
+    *out = pl;
+    return FWILS_OK;
+}
+
+fwils_status fwils_plan_create3(const fwils_problem3* probs, int32_t nprob, fwils_precision prec,
+                                fwils_plan* out) {
+    if (!out || !probs || nprob < 1 || nprob > 64) {
+        set_error("plan_create3: need 1..64 problems and an output pointer");
+        return FWILS_EINVAL;
     }
-    pl->ws_bytes = o;
+    if (prec != kPrec) {
+        set_error("plan_create3: precision %d reached the wrong library core", (int)prec);
+        return FWILS_EINVAL;
+    }
+    for (int i = 0; i < nprob; ++i) {
+        const fwils_problem3& p = probs[i];
+        if (!axis3_size_supported(p.nx) || !axis3_size_supported(p.nz) ||
+            !(p.ny == 1 || axis3_size_supported(p.ny))) {
+            set_error("problem %d: %d x %d x %d not supported (each axis 2^a 3^b 5^c in 16..256, or ny = 1)", i, p.nx,
+                      p.ny, p.nz);
+            return FWILS_EINVAL;
+        }
+        if (!(p.dx > 0) || !(p.rho0 > 0) || !(p.freq_hz > 0) || !(p.damping > 0)) {
+            set_error("problem %d: dx, rho0, freq_hz and damping must be > 0", i);
+            return FWILS_EINVAL;
+        }
+        bool finite = true;
+        for (int k = 0; k < 21; ++k) finite = finite && std::isfinite(p.c0[k]);
+        if (!finite || !spd21(p.c0)) {
+            set_error("problem %d: the background stiffness must be finite and positive definite", i);
+            return FWILS_EINVAL;
+        }
+        if (p.params != FWILS_PARAMS_VTI && p.params != FWILS_PARAMS_GENERAL) {
+            set_error("problem %d: unknown params %d", i, p.params);
+            return FWILS_EINVAL;
+        }
+        if (p.symbol != FWILS_SYMBOL_SPECTRAL && p.symbol != FWILS_SYMBOL_CENTRAL) {
+            set_error("problem %d: unknown symbol %d", i, p.symbol);
+            return FWILS_EINVAL;
+        }
+        const long long cells = (long long)p.nx * p.ny * p.nz;
+        if (p.nsys < 1 || (long long)p.nsys * 3 * cells > (1LL << 31) * 4 || (long long)p.nsys * 3 * p.nz * p.ny > (1LL << 30)) {
+            set_error("problem %d: nsys=%d out of range", i, p.nsys);
+            return FWILS_EINVAL;
+        }
+    }
+    fwils_plan pl = new fwils_plan_s();
+    pl->d3 = true;
+    pl->cstride = 3;
+    for (int i = 0; i < nprob; ++i) {
+        const fwils_problem3& q = probs[i];
+        ProbHost P;
+        P.p = fwils_problem{};
+        P.p.nx = q.nx;
+        P.p.nz = q.nz;
+        P.p.dx = q.dx;
+        P.p.rho0 = q.rho0;
+        P.p.freq_hz = q.freq_hz;
+        P.p.damping = q.damping;
+        P.p.nsys = q.nsys;
+        P.p.symbol = q.symbol;
+        P.dev = ProbDev{};
+        P.dev.nx = q.nx;
+        P.dev.nz = q.nz;
+        P.dev.nsys = q.nsys;
+        P.dev.symbol = q.symbol;
+        P.dev.tile_sh = 0;   // row-major spectra
+        P.dev.dx = (real)q.dx;
+        P.dev3 = make_dev3(q);
+        P.d3 = true;
+        P.ny = q.ny;
+        P.ncomp = 3;
+        P.nmaps = q.params == FWILS_PARAMS_GENERAL ? 22 : 6;
+        P.cells = (size_t)q.nx * q.ny * q.nz;
+        P.rps = 3 * q.nz * q.ny;
+        P.cfg.row_p = P.cfg.row_pi = row_points_default(q.nx);
+        P.cfg.col = ColCfg{0, 0, 0};
+        P.cfg.st = st_default();
+        P.cfg.fuse_p = 0;
+        pl->probs.push_back(P);
+    }
+    layout_plan(pl);
     *out = pl;
     return FWILS_OK;
 }
@@ -870,7 +1087,8 @@ fwils_status fwils_set_workspace(fwils_plan plan, void* dev, size_t bytes) {
     plan->maps = (real*)(w + plan->off_maps);
     plan->rec = (int32_t*)(w + plan->off_rec);
     plan->src_i = (int32_t*)(w + plan->off_src);
-    plan->src_f = (double*)(w + plan->off_src + align256(plan->total_sys * 2 * sizeof(int32_t)));
+    // the forces follow the cells at the offset the layout reserves (three ints per system)
+    plan->src_f = (double*)(w + plan->off_src + align256(plan->total_sys * 3 * sizeof(int32_t)));
     cplx** vecs[kNumVec] = {&plan->x, &plan->r, &plan->rhat, &plan->p, &plan->p2,
                               &plan->v, &plan->s, &plan->t, &plan->tmp, &plan->rhs, &plan->tmp2};
     const size_t vb = align256(plan->total_field * sizeof(cplx));
@@ -907,7 +1125,7 @@ fwils_status fwils_set_contrast(fwils_plan plan, int32_t iprob, const void* maps
         return FWILS_EINVAL;
     }
     const ProbHost& P = plan->probs[iprob];
-    FW_HIP(hipMemcpyAsync(maps_at(plan, P), maps, (size_t)5 * P.p.nz * P.p.nx * sizeof(real),
+    FW_HIP(hipMemcpyAsync(maps_at(plan, P), maps, (size_t)P.nmaps * P.cells * sizeof(real),
                           hipMemcpyDeviceToDevice, plan->stream));
     return FWILS_OK;
 }
@@ -919,22 +1137,23 @@ fwils_status fwils_set_receivers(fwils_plan plan, int32_t iprob, const int32_t* 
         return FWILS_EINVAL;
     }
     ProbHost& P = plan->probs[iprob];
+    const int cs = plan->cstride;
     for (int r = 0; r < nrec; ++r) {
-        if (rec_ixz[2 * r] < 0 || rec_ixz[2 * r] >= P.p.nx || rec_ixz[2 * r + 1] < 0 ||
-            rec_ixz[2 * r + 1] >= P.p.nz) {
-            set_error("set_receivers: receiver %d at (%d, %d) outside the %dx%d grid", r, rec_ixz[2 * r],
-                      rec_ixz[2 * r + 1], P.p.nx, P.p.nz);
+        const int ix = rec_ixz[cs * r], iz = rec_ixz[cs * r + cs - 1], iy = cs == 3 ? rec_ixz[cs * r + 1] : 0;
+        if (ix < 0 || ix >= P.p.nx || iy < 0 || iy >= P.ny || iz < 0 || iz >= P.p.nz) {
+            set_error("set_receivers: receiver %d at (%d, %d, %d) outside the %dx%dx%d grid", r, ix, iy, iz, P.p.nx,
+                      P.ny, P.p.nz);
             return FWILS_EINVAL;
         }
     }
     FW_HIP(hipStreamSynchronize(plan->stream));
-    FW_HIP(hipMemcpy(plan->rec + (size_t)iprob * kMaxRec * 2, rec_ixz, (size_t)nrec * 2 * sizeof(int32_t),
+    FW_HIP(hipMemcpy(plan->rec + (size_t)iprob * kMaxRec * 3, rec_ixz, (size_t)nrec * cs * sizeof(int32_t),
                      hipMemcpyHostToDevice));
     P.nrec = nrec;
     size_t doff = 0;
     for (ProbHost& Q : plan->probs) {
         Q.data_off = doff;
-        doff += (size_t)Q.p.nsys * Q.nrec * 2;
+        doff += (size_t)Q.p.nsys * Q.nrec * Q.ncomp;
     }
     return FWILS_OK;
 }
@@ -953,9 +1172,11 @@ fwils_status fwils_incident(fwils_plan plan, const int32_t* src_ixz, const doubl
 fwils_status fwils_body_force(fwils_plan plan, const void* u, void* b) {
     FW_TRY(check_plan(plan));
     FW_TRY(check_field_ptrs({u, b}));
-    for (const ProbHost& P : plan->probs)
-        FW_HIP(launch_body_force(P.cfg.st, at(u, P), static_cast<cplx*>(b) + P.field_off, maps_at(plan, P), P.dev,
-                                 nullptr, plan->stream));
+    for (const ProbHost& P : plan->probs) {
+        const StencilArgs a{at(u, P), nullptr, nullptr, nullptr, static_cast<cplx*>(b) + P.field_off,
+                            maps_at(plan, P), nullptr, 0};
+        FW_HIP(stencil_any(P, P.dev, VM_NONE, a, nullptr, plan->stream));
+    }
     return FWILS_OK;
 }
 
@@ -1081,6 +1302,13 @@ fwils_status fwils_solve(fwils_plan plan, const void* rhs, void* x, double rtol,
 
 namespace {
 
+// d = R w for problem i (either dimension).
+hipError_t gather_any(fwils_plan plan, size_t i, const cplx* w, cplx* d, hipStream_t s) {
+    const ProbHost& P = plan->probs[i];
+    const int32_t* rec = plan->rec + i * kMaxRec * 3;
+    return P.d3 ? launch_gather3(w, d, rec, P.nrec, P.dev3, s) : launch_gather(w, d, rec, P.nrec, P.dev, s);
+}
+
 // J dm (validated arguments): one virtual source, one convolution and one
 // gather per problem around one batched solve.
 fwils_status frechet_ws(fwils_plan plan, const void* ub, const real* const* dm, void* d, double rtol,
@@ -1089,15 +1317,15 @@ fwils_status frechet_ws(fwils_plan plan, const void* ub, const real* const* dm, 
     for (size_t i = 0; i < plan->probs.size(); ++i) {
         const ProbHost& P = plan->probs[i];
         // virtual source P_b(dm): the contrast stencil applied to u^b with dm
-        FW_HIP(launch_body_force(P.cfg.st, at(ub, P), at(plan->s, P), dm[i], P.dev, nullptr, s));
+        const StencilArgs a{at(ub, P), nullptr, nullptr, nullptr, at(plan->s, P), dm[i], nullptr, 0};
+        FW_HIP(stencil_any(P, P.dev, VM_NONE, a, nullptr, s));
         FW_HIP(conv_problem(plan, P, at(plan->s, P), at(plan->rhs, P)));
     }
     fwils_status st = solve_ws(plan, plan->rhs, false, rtol, maxit, nullptr, nullptr, 0);
     if (st == FWILS_EDEVICE) return st;
     for (size_t i = 0; i < plan->probs.size(); ++i) {
         const ProbHost& P = plan->probs[i];
-        FW_HIP(launch_gather(at(plan->x, P), static_cast<cplx*>(d) + P.data_off,
-                             plan->rec + i * kMaxRec * 2, P.nrec, P.dev, s));
+        FW_HIP(gather_any(plan, i, at(plan->x, P), static_cast<cplx*>(d) + P.data_off, s));
     }
     return st;
 }
@@ -1111,15 +1339,21 @@ fwils_status adjoint_ws(fwils_plan plan, const void* ub, const void* r, void* co
         const ProbHost& P = plan->probs[i];
         cplx* f = at(plan->s, P);
         FW_HIP(launch_zero(f, (size_t)P.p.nsys * P.n_per_sys, s));
-        FW_HIP(launch_scatter_conj(static_cast<const cplx*>(r) + P.data_off, f,
-                                   plan->rec + i * kMaxRec * 2, P.nrec, P.dev, s));
+        if (P.d3)
+            FW_HIP(launch_scatter_conj3(static_cast<const cplx*>(r) + P.data_off, f, plan->rec + i * kMaxRec * 3,
+                                        P.nrec, P.dev3, s));
+        else
+            FW_HIP(launch_scatter_conj(static_cast<const cplx*>(r) + P.data_off, f, plan->rec + i * kMaxRec * 3,
+                                       P.nrec, P.dev, s));
         FW_HIP(conv_problem(plan, P, f, at(plan->rhs, P)));
     }
     fwils_status st = solve_ws(plan, plan->rhs, false, rtol, maxit, nullptr, nullptr, 0);
     if (st == FWILS_EDEVICE) return st;
     for (size_t i = 0; i < plan->probs.size(); ++i) {
         const ProbHost& P = plan->probs[i];
-        if (fp64_maps)
+        if (P.d3)
+            FW_HIP(launch_correlate3(at(plan->x, P), at(ub, P), static_cast<double2*>(g[i]), P.dev3, accumulate, s));
+        else if (fp64_maps)
             FW_HIP(launch_correlate_f64(at(plan->x, P), at(ub, P), static_cast<double2*>(g[i]), P.dev,
                                         accumulate, s));
         else
@@ -1171,7 +1405,7 @@ fwils_status check_tik(fwils_plan plan, const double* m0, double lam, int32_t re
 
 size_t data_elems(fwils_plan plan) {
     size_t n = 0;
-    for (const ProbHost& P : plan->probs) n += (size_t)P.p.nsys * P.nrec * 2;
+    for (const ProbHost& P : plan->probs) n += (size_t)P.p.nsys * P.nrec * P.ncomp;
     return n;
 }
 
@@ -1323,6 +1557,7 @@ fwils_status fwils_adjoint(fwils_plan plan, const void* ub, const void* r, void*
 fwils_status fwils_normal_apply(fwils_plan plan, const void* ub, const double* m0, double rr, double lam,
                                 int32_t reg, const void* q_in_, void* q_out_, void* dscratch, double rtol,
                                 int32_t maxit) {
+    FW_TRY(only_2d(plan, "normal_apply"));
     const real* q_in = static_cast<const real*>(q_in_);
     real* q_out = static_cast<real*>(q_out_);
     FW_TRY(check_plan(plan));
@@ -1341,6 +1576,7 @@ fwils_status fwils_normal_apply(fwils_plan plan, const void* ub, const double* m
 fwils_status fwils_tikhonov_grad(fwils_plan plan, const void* ub, const void* r, const double* m0, double lam,
                                  int32_t reg, const void* q_, void* grad_, double* fval, void* dscratch,
                                  double rtol, int32_t maxit) {
+    FW_TRY(only_2d(plan, "tikhonov_grad"));
     const real* q = static_cast<const real*>(q_);
     real* grad = static_cast<real*>(grad_);
     FW_TRY(check_plan(plan));
@@ -1384,6 +1620,7 @@ fwils_status fwils_tikhonov_grad(fwils_plan plan, const void* ub, const void* r,
 
 fwils_status fwils_frechet_rel(fwils_plan plan, const void* ub, const void* q_, const double* m0, void* d,
                                double rtol, int32_t maxit) {
+    FW_TRY(only_2d(plan, "frechet_rel"));
     const real* q = static_cast<const real*>(q_);
     FW_TRY(check_plan(plan));
     FW_TRY(check_field_ptrs({ub, q, d}));
@@ -1398,6 +1635,7 @@ fwils_status fwils_frechet_rel(fwils_plan plan, const void* ub, const void* q_, 
 
 fwils_status fwils_adjoint_rel(fwils_plan plan, const void* ub, const void* r, const double* m0, void* gq_,
                                double rtol, int32_t maxit) {
+    FW_TRY(only_2d(plan, "adjoint_rel"));
     real* gq = static_cast<real*>(gq_);
     FW_TRY(check_plan(plan));
     FW_TRY(check_field_ptrs({ub, r, gq}));
@@ -1412,6 +1650,7 @@ fwils_status fwils_adjoint_rel(fwils_plan plan, const void* ub, const void* r, c
 }
 
 fwils_status fwils_laplacian(fwils_plan plan, const void* q_, void* out_) {
+    FW_TRY(only_2d(plan, "laplacian"));
     const real* q = static_cast<const real*>(q_);
     real* out = static_cast<real*>(out_);
     FW_TRY(check_plan(plan));
@@ -1427,6 +1666,7 @@ fwils_status fwils_laplacian(fwils_plan plan, const void* q_, void* out_) {
 fwils_status fwils_normal_cg(fwils_plan plan, const void* ub, const void* r, const double* m0, double lam,
                              int32_t reg, int32_t niter, void* q_, double* hist, void* dscratch, double rtol,
                              int32_t maxit) {
+    FW_TRY(only_2d(plan, "normal_cg"));
     real* q = static_cast<real*>(q_);
     FW_TRY(check_plan(plan));
     FW_TRY(check_field_ptrs({ub, r, q, dscratch}));
@@ -1450,8 +1690,7 @@ fwils_status fwils_receiver_data(fwils_plan plan, const void* u, void* d) {
     }
     for (size_t i = 0; i < plan->probs.size(); ++i) {
         const ProbHost& P = plan->probs[i];
-        FW_HIP(launch_gather(at(u, P), static_cast<cplx*>(d) + P.data_off, plan->rec + i * kMaxRec * 2, P.nrec,
-                             P.dev, plan->stream));
+        FW_HIP(gather_any(plan, i, at(u, P), static_cast<cplx*>(d) + P.data_off, plan->stream));
     }
     return FWILS_OK;
 }
@@ -1463,7 +1702,7 @@ fwils_status fwils_get_contrast(fwils_plan plan, int32_t iprob, void* maps) {
         return FWILS_EINVAL;
     }
     const ProbHost& P = plan->probs[iprob];
-    FW_HIP(hipMemcpyAsync(maps, maps_at(plan, P), (size_t)5 * P.p.nz * P.p.nx * sizeof(real),
+    FW_HIP(hipMemcpyAsync(maps, maps_at(plan, P), (size_t)P.nmaps * P.cells * sizeof(real),
                           hipMemcpyDeviceToDevice, plan->stream));
     return FWILS_OK;
 }
@@ -1472,6 +1711,7 @@ fwils_status fwils_dbi_run(fwils_plan plan, const int32_t* src_ixz, const double
                            const double* m0, double lam0, int32_t reg, int32_t niter, double tol,
                            int32_t max_outer, void* ub_, void* r_, void* q_, void* dscratch, double* eps_hist,
                            double* lam_hist, int32_t* updates, double rtol, int32_t maxit) {
+    FW_TRY(only_2d(plan, "dbi_run"));
     const cplx* d_obs = static_cast<const cplx*>(d_obs_);
     cplx* ub = static_cast<cplx*>(ub_);
     cplx* r = static_cast<cplx*>(r_);
@@ -1510,7 +1750,7 @@ fwils_status fwils_dbi_run(fwils_plan plan, const int32_t* src_ixz, const double
         // r = d_obs - R u^b and the normalised data error
         for (size_t i = 0; i < plan->probs.size(); ++i) {
             const ProbHost& P = plan->probs[i];
-            FW_HIP(launch_gather(at(ub, P), r + P.data_off, plan->rec + i * kMaxRec * 2, P.nrec, P.dev, s));
+            FW_HIP(launch_gather(at(ub, P), r + P.data_off, plan->rec + i * kMaxRec * 3, P.nrec, P.dev, s));
         }
         FW_HIP(launch_data_residual(r, d_obs, nd, s));
         double rr = 0.0;
@@ -1540,6 +1780,7 @@ fwils_status fwils_dbi_run(fwils_plan plan, const int32_t* src_ixz, const double
 }
 
 fwils_status fwils_apply_pass(fwils_plan plan, int32_t pass, const void* u, void* Au) {
+    FW_TRY(only_2d(plan, "apply_pass"));
     FW_TRY(check_plan(plan));
     if (pass < 0 || pass > 3 || ((pass == 0 || pass == 3) && !u) || (pass == 3 && (!Au || u == Au))) {
         set_error("apply_pass: pass must be 0..3 with u (passes 0, 3) and a distinct Au (pass 3)");
@@ -1574,6 +1815,7 @@ fwils_status fwils_apply_pass(fwils_plan plan, int32_t pass, const void* u, void
 }
 
 fwils_status fwils_time_pass(fwils_plan plan, int32_t pass, const void* u, void* Au, int32_t reps, float* us) {
+    FW_TRY(only_2d(plan, "time_pass"));
     if (!us || reps < 1 || reps > 10000) {
         set_error("time_pass: need reps 1..10000 and an output");
         return FWILS_EINVAL;
@@ -1601,6 +1843,7 @@ fwils_status fwils_time_pass(fwils_plan plan, int32_t pass, const void* u, void*
 }
 
 fwils_status fwils_time_krylov_pass(fwils_plan plan, int32_t reps, float* us) {
+    FW_TRY(only_2d(plan, "time_krylov_pass"));
     FW_TRY(check_plan(plan));
     if (!us || reps < 1 || reps > 10000) {
         set_error("time_krylov_pass: need reps 1..10000 and an output");
@@ -1728,7 +1971,7 @@ GmLayout gm_layout(fwils_plan pl, int m) {
         int cand[3];
         const int nc = row_candidates(P.p.nx, cand);
         for (int c = 0; c < nc; ++c)
-            L.maxnb = std::max(L.maxnb, (size_t)row_geom(P.p.nx, cand[c], 2 * P.p.nz).blocks_per_sys);
+            L.maxnb = std::max(L.maxnb, (size_t)row_geom(P.p.nx, cand[c], P.rps).blocks_per_sys);
         L.maxnb = std::max(L.maxnb, (size_t)gm_blocks_per_sys((int)P.n_per_sys));
     }
     size_t o = 0;
@@ -1946,6 +2189,7 @@ hipError_t tune_launch(fwils_plan pl, const ProbHost& P, int kind, const KernelC
 extern "C" {
 
 fwils_status fwils_autotune(fwils_plan plan, int32_t reps) {
+    if (plan && plan->d3) return check_plan(plan);   // 3-D problems: one variant per kernel
     FW_TRY(check_plan(plan));
     if (reps < 1 || reps > 1000) {
         set_error("autotune: reps must be 1..1000");
@@ -2018,6 +2262,7 @@ fwils_status fwils_autotune(fwils_plan plan, int32_t reps) {
 }
 
 fwils_status fwils_get_tuning(fwils_plan plan, int32_t iprob, fwils_tuning* out) {
+    FW_TRY(only_2d(plan, "get_tuning"));
     FW_TRY(check_plan(plan, false));
     if (!out || iprob < 0 || iprob >= (int)plan->probs.size()) {
         set_error("get_tuning: bad problem index or null output");
@@ -2028,6 +2273,7 @@ fwils_status fwils_get_tuning(fwils_plan plan, int32_t iprob, fwils_tuning* out)
 }
 
 fwils_status fwils_set_tuning(fwils_plan plan, int32_t iprob, const fwils_tuning* t) {
+    FW_TRY(only_2d(plan, "set_tuning"));
     FW_TRY(check_plan(plan, false));
     if (!t || iprob < 0 || iprob >= (int)plan->probs.size()) {
         set_error("set_tuning: bad problem index or null input");
@@ -2048,6 +2294,7 @@ fwils_status fwils_set_tuning(fwils_plan plan, int32_t iprob, const fwils_tuning
 
 fwils_status fwils_tuning_candidates(fwils_plan plan, int32_t iprob, int32_t kind, fwils_tuning* out,
                                      int32_t cap, int32_t* count) {
+    FW_TRY(only_2d(plan, "tuning_candidates"));
     FW_TRY(check_plan(plan, false));
     if (!count || iprob < 0 || iprob >= (int)plan->probs.size() || kind < 0 || kind > 3 || cap < 0 ||
         (cap > 0 && !out)) {
@@ -2074,10 +2321,24 @@ fwils_status fwils_fft2(fwils_plan plan, int32_t iprob, const void* in, void* ou
         return FWILS_EINVAL;
     }
     const ProbHost& P = plan->probs[iprob];
-    const int rows = P.p.nsys * 2 * P.p.nz;
+    const int rows = P.p.nsys * P.rps;
     const cplx* src = static_cast<const cplx*>(in);
     cplx* dst = static_cast<cplx*>(out);
     hipStream_t s = plan->stream;
+    if (P.d3) {   // x rows, then the y and z axes in place (unnormalised, separable)
+        const ProbDev3& d = P.dev3;
+        const int nx = d.nx, ny = d.ny, nz = d.nz, ns = P.p.nsys;
+        const int px = row_points_default(nx);
+        if (!inverse)
+            FW_HIP(launch_rows_fwd(nx, px, src, dst, rows, P.rps, SpecLayout{}, nullptr, plan->tw, s));
+        else
+            FW_HIP(launch_rows_inv(nx, px, EPI_STORE, src, nullptr, nullptr, dst, nullptr, rows, P.rps, SpecLayout{},
+                                   nullptr, plan->tw, s));
+        const int mode = inverse ? AX_INV : AX_FWD;
+        if (ny > 1) FW_HIP(launch_axis3(mode, ny, dst, nx, ns * 3 * nz, 3 * nz, nullptr, plan->tw, d, s));
+        FW_HIP(launch_axis3(mode, nz, dst, nx * ny, ns * 3, 3, nullptr, plan->tw, d, s));
+        return FWILS_OK;
+    }
     ProbDev nat = P.dev;   // the transform itself: row-major in and out
     nat.tile_sh = 0;
     if (!inverse) {

@@ -10,7 +10,7 @@
 // is therefore loaded from and stored to global memory in coalesced
 // t-fastest order, and only the passes in between go through LDS.
 //
-// The radix sequence is chosen at compile time from {32, 16, 8, 4, 2, 3};
+// The radix sequence is chosen at compile time from {32, 16, 8, 4, 2, 3, 5};
 // every radix must divide P.  Twiddles come from a length-N table
 // tw[m] = exp(-2 pi i m / N) (double-rounded on the host); the inverse uses
 // conjugates.  No normalisation is applied in either direction.
@@ -26,11 +26,11 @@ struct RadixPlan {
 
 constexpr RadixPlan radix_plan(int N, int P) {
     RadixPlan pl{0, {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0}};
-    const int cand[6] = {32, 16, 8, 4, 2, 3};
+    const int cand[7] = {32, 16, 8, 4, 2, 3, 5};
     int rem = N;
     while (rem > 1) {
         int pick = 0;
-        for (int i = 0; i < 6; ++i) {
+        for (int i = 0; i < 7; ++i) {
             if (P % cand[i] == 0 && rem % cand[i] == 0) { pick = cand[i]; break; }
         }
         if (pick == 0 || pl.np == 16) { pl.np = -1; return pl; }
@@ -205,10 +205,32 @@ __device__ __forceinline__ void dft3(cplx& x0, cplx& x1, cplx& x2) {
     x2 = csub(m, d);
 }
 
+// 5-point DFT from the even / odd sums of the conjugate pairs (1, 4) and
+// (2, 3): X_1,4 = x0 + c1 t1 + c2 t2 -+ i (s1 d1 + s2 d2) and
+// X_2,3 = x0 + c2 t1 + c1 t2 -+ i (s2 d1 - s1 d2) for the forward sign, with
+// c_k = cos(2 pi k / 5), s_k = sin(2 pi k / 5), t = sums, d = differences.
+template <bool INV>
+__device__ __forceinline__ void dft5(cplx& x0, cplx& x1, cplx& x2, cplx& x3, cplx& x4) {
+    const real c1 = (real)0.30901699437494742410, c2 = (real)-0.80901699437494742410;
+    const real s1 = (real)0.95105651629515357212, s2 = (real)0.58778525229247312917;
+    const cplx t1 = cadd(x1, x4), t2 = cadd(x2, x3);
+    const cplx d1 = csub(x1, x4), d2 = csub(x2, x3);
+    const cplx a1 = mkc(x0.x + c1 * t1.x + c2 * t2.x, x0.y + c1 * t1.y + c2 * t2.y);
+    const cplx a2 = mkc(x0.x + c2 * t1.x + c1 * t2.x, x0.y + c2 * t1.y + c1 * t2.y);
+    const cplx b1 = mul_mi<INV>(mkc(s1 * d1.x + s2 * d2.x, s1 * d1.y + s2 * d2.y));
+    const cplx b2 = mul_mi<INV>(mkc(s2 * d1.x - s1 * d2.x, s2 * d1.y - s1 * d2.y));
+    x0 = cadd(x0, cadd(t1, t2));
+    x1 = cadd(a1, b1);
+    x4 = csub(a1, b1);
+    x2 = cadd(a2, b2);
+    x3 = csub(a2, b2);
+}
+
 template <int R, bool INV>
 __device__ __forceinline__ void dft(cplx (&x)[R]) {
     if constexpr (R == 2) dft2<INV>(x[0], x[1]);
     else if constexpr (R == 3) dft3<INV>(x[0], x[1], x[2]);
+    else if constexpr (R == 5) dft5<INV>(x[0], x[1], x[2], x[3], x[4]);
     else if constexpr (R == 4) dft4<INV>(x[0], x[1], x[2], x[3]);
     else if constexpr (R == 8) dft8<INV>(x);
     else if constexpr (R == 16) dft16<INV>(x);
@@ -228,6 +250,7 @@ __device__ __forceinline__ void twiddles(cplx (&w)[R], const cplx* __restrict__ 
     w[1] = w1;
     if constexpr (R >= 3) w[2] = cmul(w1, w1);
     if constexpr (R >= 4) w[3] = cmul(w[2], w1);
+    if constexpr (R == 5) w[4] = cmul(w[3], w1);
     if constexpr (R >= 8) {
         cplx w4 = tw[4 * e];
         if (INV) w4 = cconj(w4);

@@ -13,20 +13,23 @@ FW_BEGIN
     X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024) X(1536) X(2048)
 
 static const int kSizes[] = {16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048};
+// Twiddle tables: the 2-D sizes, then the 5 * 2^k axis lengths of 3-D grids.
+static const int kTwSizes[] = {16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048,
+                               20, 40, 80, 160};
 
 // Default points per thread.  Row passes: 16 for powers of two (radix-16
 // passes), 12 for 3 * 2^k.  Column passes hold both field components per
 // thread, so they default to 8 (radix 8) to keep registers low and the
 // thread count high.  Each size also has one alternative per pass kind.
 // The complex128 build has the default variants only.
-int row_points_default(int n) { return (n % 3 == 0) ? 12 : 16; }
+int row_points_default(int n) { return (n % 5 == 0) ? (n <= 40 ? 10 : 20) : (n % 3 == 0) ? 12 : 16; }
 static int col_points_default(int n) { return (n % 3 == 0) ? 12 : 8; }
 #ifdef FW_C128
 static int row_points_alt(int n) { return row_points_default(n); }
 static int col_points_alt(int n) { return col_points_default(n); }
 static int points_radix32(int) { return 0; }
 #else
-static int row_points_alt(int n) { return (n % 3 == 0) ? 24 : 8; }
+static int row_points_alt(int n) { return (n % 5 == 0) ? row_points_default(n) : (n % 3 == 0) ? 24 : 8; }
 static int col_points_alt(int n) { return (n % 3 == 0) ? 24 : 16; }
 // A third row-pass variant for 512- and 1024-point rows: 32 points per
 // thread, radix-32 passes (32 x 32 at 1024 points: one LDS exchange per
@@ -56,13 +59,13 @@ bool fft_size_supported(int n) {
 
 size_t twiddle_table_elems() {
     size_t t = 0;
-    for (int s : kSizes) t += (size_t)s;
+    for (int s : kTwSizes) t += (size_t)s;
     return t;
 }
 
 size_t twiddle_offset(int n) {
     size_t t = 0;
-    for (int s : kSizes) {
+    for (int s : kTwSizes) {
         if (s == n) return t;
         t += (size_t)s;
     }
@@ -71,7 +74,7 @@ size_t twiddle_offset(int n) {
 
 void twiddle_table_fill(cplx* host) {
     size_t off = 0;
-    for (int s : kSizes) {
+    for (int s : kTwSizes) {
         for (int m = 0; m < s; ++m) {
             // exp(-2 pi i m / s); angle reduced in double
             const double a = -2.0 * 3.14159265358979323846 * (double)m / (double)s;
@@ -82,7 +85,7 @@ void twiddle_table_fill(cplx* host) {
 }
 
 bool row_points_ok(int n, int P) {
-    return fft_size_supported(n) && n % P == 0 &&
+    return (fft_size_supported(n) || axis3_size_supported(n)) && n % P == 0 &&
            (P == row_points_default(n) || P == row_points_alt(n) || P == points_radix32(n));
 }
 

@@ -151,6 +151,48 @@ size_t srows_lds(int nx, int F);
 hipError_t launch_srows(int vm, int P, const StencilArgs& a, cplx* out, const ProbDev& pd, SysState* st,
                         const cplx* tw, hipStream_t s);
 
+// ------------------------------------------------------------- 3-D ------
+// A 3-D problem: fields [nsys][3][nz][ny][nx] (u_x, u_y, u_z), a general
+// background given by its 21 Voigt constants, and the contrast as VTI maps
+// [6][nz][ny][nx] (dC11, dC13, dC33, dC55, dC66, drho) or general maps
+// [22][nz][ny][nx] (the 21 constants of the upper triangle of the 6 x 6
+// matrix in row-major order, then drho).
+constexpr int kParamsVti = 0;
+constexpr int kParamsGeneral = 1;
+struct ProbDev3 {
+    int nx, ny, nz, nsys;
+    int params;           // kParamsVti or kParamsGeneral
+    int symbol;           // 0 spectral, 1 central-difference wavenumbers
+    real inv4dx2;         // 1 / (4 dx^2)
+    cplx w2;              // w~^2
+    real dx;
+    // Green's symbol in units of rho0 w^2 (w real): the scaled Christoffel
+    // entry Gamma'_p, p in (xx, yy, zz, yz, xz, xy), is sum_q gq[p][q] mono_q
+    // with mono = (kx^2, ky^2, kz^2, ky kz, kx kz, kx ky)
+    real gq[6][6];
+    cplx ga;              // (1 + i eta)^2
+    real gscale;          // 1 / (rho0 w^2 nx ny nz)
+    real dk[3];           // 2 pi / (n dx) per axis
+};
+enum AxisMode : int { AX_FWD = 0, AX_INV = 1, AX_GREEN = 2 };
+bool axis3_size_supported(int n);   // 3-D axis lengths: 2^a 3^b 5^c from 16 to 256 (see kernels_3d.hip)
+int axis_points(int n);
+// Contrast stencil of a 3-D problem with the vector update of StencilArgs.
+hipError_t launch_stencil3(int vm, const StencilArgs& a, const ProbDev3& pd, SysState* st, hipStream_t s);
+// Strided-axis transforms in place: [nslab][n][S] (AX_FWD / AX_INV; system of
+// a slab = slab / slabs_per_sys) or [nsys][3][n][S] (AX_GREEN, nslab = nsys,
+// the z pass with the 3 x 3 Green multiply and the 1 / (nx ny nz) scale).
+hipError_t launch_axis3(int mode, int n, cplx* data, int S, int nslab, int slabs_per_sys, const SysState* st,
+                        const cplx* tw, const ProbDev3& pd, hipStream_t s);
+hipError_t launch_point_sources3(cplx* f, const int32_t* src_ixyz, const double* src_f, const ProbDev3& pd,
+                                 hipStream_t s);
+hipError_t launch_gather3(const cplx* w, cplx* d, const int32_t* rec, int nrec, const ProbDev3& pd, hipStream_t s);
+hipError_t launch_scatter_conj3(const cplx* d, cplx* f, const int32_t* rec, int nrec, const ProbDev3& pd,
+                                hipStream_t s);
+// J* correlation of eq. ad1 into FP64 complex maps [NS + 1][nz][ny][nx].
+hipError_t launch_correlate3(const cplx* ua, const cplx* ub, double2* g, const ProbDev3& pd, bool accumulate,
+                             hipStream_t s);
+
 // BiCGSTAB pieces (one problem; n = 2 nz nx complex per system).
 int vec_blocks_per_sys(int n);
 hipError_t launch_bicg_init(const cplx* b, const cplx* r0, cplx* x, cplx* r, cplx* rhat,

@@ -77,6 +77,15 @@ class Plan:
             arr[i].symbol = SYMBOLS[sym] if isinstance(sym, str) else int(sym)
         h = ctypes.c_void_p()
         check(self.lib.fwils_plan_create(arr, n, prec, ctypes.byref(h)), "fwils_plan_create")
+        self._attach(h)
+
+    def _sys_elems(self, p):
+        """Complex elements of one system's field."""
+        return 2 * p["nz"] * p["nx"]
+
+    def _attach(self, h):
+        """Workspace, stream and the plan-level offsets of a created plan."""
+        n = len(self.problems)
         self._h = h
         size = ctypes.c_size_t()
         check(self.lib.fwils_workspace_size(h, ctypes.byref(size)), "fwils_workspace_size")
@@ -97,7 +106,7 @@ class Plan:
         for p in self.problems:
             self.offsets.append(o)
             self.sys_offsets.append(so)
-            o += p["nsys"] * 2 * p["nz"] * p["nx"]
+            o += p["nsys"] * self._sys_elems(p)
             so += p["nsys"]
         self.total_sys = so
         self.nrec = [0] * n
@@ -126,8 +135,11 @@ class Plan:
 
     def view(self, t, i):
         p = self.problems[i]
-        n = p["nsys"] * 2 * p["nz"] * p["nx"]
-        return t[self.offsets[i]:self.offsets[i] + n].view(p["nsys"], 2, p["nz"], p["nx"])
+        n = p["nsys"] * self._sys_elems(p)
+        return t[self.offsets[i]:self.offsets[i] + n].view(p["nsys"], *self._field_shape(p))
+
+    def _field_shape(self, p):
+        return (2, p["nz"], p["nx"])
 
     def pack(self, parts):
         """Concatenate per-problem [nsys, 2, nz, nx] arrays into a plan-level field."""
@@ -547,6 +559,156 @@ class Plan:
 
     def fft2(self, i, x, inverse=False, out=None):
         """2-D FFT (unnormalised) of every field of problem i; x: [nsys, 2, nz, nx]."""
+        _require_cuda(x, self.cdtype, "x")
+        out = torch.empty_like(x) if out is None else out
+        self._bind_stream()
+        check(self.lib.fwils_fft2(self._h, i, _ptr(x), _ptr(out), 1 if inverse else 0), "fwils_fft2")
+        return out
+
+
+class Plan3(Plan):
+    """One or more 3-D problems with a general anisotropic background
+    (fwils_plan_create3).  A problem dict holds nx, ny, nz, dx, c0 (the 21
+    constants of the 6 x 6 stiffness, upper triangle row by row, or a 6 x 6
+    array), rho0, freq_hz, nsys, and optionally eta / damping, symbol and
+    params ('vti': maps C11, C13, C33, C55, C66, rho; 'general': the 21
+    constants and rho).  Fields are [nsys, 3, nz, ny, nx]; sources and
+    receivers (ix, iy, iz); forces (fx, fy, fz); data [nsys, nrec, 3]."""
+
+    PARAMS = {"vti": _lib.FWILS_PARAMS_VTI, "general": _lib.FWILS_PARAMS_GENERAL}
+    NMAPS = {"vti": 6, "general": 22}
+
+    def __init__(self, problems, device="cuda", precision="c64"):
+        self.lib = _lib.load()
+        if precision not in PRECISIONS:
+            raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
+        self.precision = precision
+        prec, self.cdtype, self.rdtype = PRECISIONS[precision]
+        if not torch.cuda.is_available():
+            raise RuntimeError("fwils needs a ROCm GPU (torch.cuda.is_available() is False)")
+        self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self.problems = [dict(p) for p in problems]
+        n = len(self.problems)
+        arr = (_lib.FwilsProblem3 * n)()
+        for i, p in enumerate(self.problems):
+            p.setdefault("params", "vti")
+            arr[i].nx, arr[i].ny, arr[i].nz = int(p["nx"]), int(p["ny"]), int(p["nz"])
+            arr[i].dx = float(p["dx"])
+            c0 = np.asarray(p["c0"], dtype=np.float64)
+            if c0.shape == (6, 6):
+                c0 = c0[np.triu_indices(6)]
+            if c0.shape != (21,):
+                raise ValueError("c0 must hold 21 constants or be a 6 x 6 matrix")
+            for k in range(21):
+                arr[i].c0[k] = float(c0[k])
+            arr[i].rho0 = float(p["rho0"])
+            arr[i].freq_hz = float(p["freq_hz"])
+            arr[i].damping = float(p.get("eta", p.get("damping", 0.02)))
+            arr[i].nsys = int(p["nsys"])
+            sym = p.get("symbol", "spectral")
+            arr[i].symbol = SYMBOLS[sym] if isinstance(sym, str) else int(sym)
+            arr[i].params = self.PARAMS[p["params"]]
+        h = ctypes.c_void_p()
+        check(self.lib.fwils_plan_create3(arr, n, prec, ctypes.byref(h)), "fwils_plan_create3")
+        self._attach(h)
+
+    def _sys_elems(self, p):
+        return 3 * p["nz"] * p["ny"] * p["nx"]
+
+    def _field_shape(self, p):
+        return (3, p["nz"], p["ny"], p["nx"])
+
+    def nmaps(self, i):
+        return self.NMAPS[self.problems[i]["params"]]
+
+    def _map_shape(self, i):
+        p = self.problems[i]
+        return (self.nmaps(i), p["nz"], p["ny"], p["nx"])
+
+    def set_contrast(self, i, maps):
+        m = torch.as_tensor(maps, dtype=self.rdtype).to(self.device).contiguous()
+        if tuple(m.shape) != self._map_shape(i):
+            raise ValueError(f"maps must be {list(self._map_shape(i))}")
+        self._bind_stream()
+        check(self.lib.fwils_set_contrast(self._h, i, _ptr(m)), "fwils_set_contrast")
+        torch.cuda.current_stream(self.device).synchronize()
+
+    def get_contrast(self, i):
+        m = torch.empty(self._map_shape(i), dtype=self.rdtype, device=self.device)
+        self._bind_stream()
+        check(self.lib.fwils_get_contrast(self._h, i, _ptr(m)), "fwils_get_contrast")
+        torch.cuda.current_stream(self.device).synchronize()
+        return m
+
+    def set_receivers(self, i, rec_ixyz):
+        r = np.ascontiguousarray(np.asarray(rec_ixyz, dtype=np.int32).reshape(-1, 3))
+        self._bind_stream()
+        check(self.lib.fwils_set_receivers(self._h, i, r.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                           r.shape[0]), "fwils_set_receivers")
+        self.nrec[i] = r.shape[0]
+
+    def incident(self, src_ixyz, src_f):
+        s = np.ascontiguousarray(np.asarray(src_ixyz, dtype=np.int32).reshape(-1, 3))
+        f = np.ascontiguousarray(np.asarray(src_f, dtype=np.float64).reshape(-1, 3))
+        if s.shape[0] != self.total_sys or f.shape[0] != self.total_sys:
+            raise ValueError(f"need {self.total_sys} sources and forces")
+        u0 = self._out_field()
+        self._bind_stream()
+        check(self.lib.fwils_incident(self._h, s.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                      f.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _ptr(u0)),
+              "fwils_incident")
+        return u0
+
+    def data_elems(self):
+        return sum(p["nsys"] * nr * 3 for p, nr in zip(self.problems, self.nrec))
+
+    def data_view(self, d, i):
+        p = self.problems[i]
+        off = sum(q["nsys"] * nr * 3 for q, nr in zip(self.problems[:i], self.nrec[:i]))
+        return d[off:off + p["nsys"] * self.nrec[i] * 3].view(p["nsys"], self.nrec[i], 3)
+
+    def frechet(self, ub, dm, rtol=1e-6, maxit=1000):
+        """J dm for every system; dm: list (one per problem) of rdtype [nmaps, nz, ny, nx]."""
+        self._field(ub, "ub")
+        for i, m in enumerate(dm):
+            _require_cuda(m, self.rdtype, f"dm[{i}]")
+            if tuple(m.shape) != self._map_shape(i):
+                raise ValueError(f"dm[{i}] must be {list(self._map_shape(i))}")
+        arr = (ctypes.c_void_p * len(dm))(*[m.data_ptr() for m in dm])
+        d = torch.empty(self.data_elems(), dtype=self.cdtype, device=self.device)
+        self._bind_stream()
+        st = self.lib.fwils_frechet(self._h, _ptr(ub), arr, _ptr(d), float(rtol), int(maxit))
+        if st != _lib.FWILS_OK:
+            check(st, "fwils_frechet")
+        return d
+
+    def adjoint(self, ub, r, rtol=1e-6, maxit=1000, g=None, accumulate=False):
+        """J* r: list (one per problem) of complex128 [nmaps, nz, ny, nx] maps."""
+        self._field(ub, "ub")
+        _require_cuda(r, self.cdtype, "r")
+        if r.numel() != self.data_elems():
+            raise ValueError(f"r must hold {self.data_elems()} complex values")
+        if g is None:
+            if accumulate:
+                raise ValueError("accumulate needs the g maps to add to")
+            g = [torch.empty(self._map_shape(i), dtype=torch.complex128, device=self.device)
+                 for i in range(len(self.problems))]
+        for i, gi in enumerate(g):
+            _require_cuda(gi, torch.complex128, f"g[{i}]")
+            if tuple(gi.shape) != self._map_shape(i):
+                raise ValueError(f"g[{i}] must be {list(self._map_shape(i))}")
+        arr = (ctypes.c_void_p * len(g))(*[gi.data_ptr() for gi in g])
+        self._bind_stream()
+        st = self.lib.fwils_adjoint(self._h, _ptr(ub), _ptr(r), arr,
+                                    _lib.FWILS_ADJ_ACCUMULATE if accumulate else 0, float(rtol), int(maxit))
+        if st != _lib.FWILS_OK:
+            check(st, "fwils_adjoint")
+        return g
+
+    def fft3(self, i, x, inverse=False, out=None):
+        """3-D FFT (unnormalised) of every field of problem i; x: [nsys, 3, nz, ny, nx]."""
         _require_cuda(x, self.cdtype, "x")
         out = torch.empty_like(x) if out is None else out
         self._bind_stream()

@@ -27,7 +27,7 @@ def test_core_rename_list_matches_header():
 def test_dispatch_list_matches_header():
     abi = (CSRC / "abi.cpp").read_text()
     forwarded = {"fwils_" + n for n in re.findall(r"^\s*X\(\w+, (\w+),", abi, re.M)}
-    defined = forwarded | {"fwils_plan_create", "fwils_plan_destroy"} | SHIM_ONLY
+    defined = forwarded | {"fwils_plan_create", "fwils_plan_create3", "fwils_plan_destroy"} | SHIM_ONLY
     assert defined == _public()
 
 

@@ -194,3 +194,43 @@ def test_python_binding_fails_loudly_without_gpu():
 def test_missing_library_raises(tmp_path):
     with pytest.raises(_lib.FwilsLibraryError, match="not built"):
         _lib.load(str(tmp_path / "libfwils.so"))
+
+
+def _prob3(**kw):
+    import workloads as W
+    p = _lib.FwilsProblem3()
+    p.nx, p.ny, p.nz = kw.get("n", (80, 40, 32))
+    p.dx = 25.0
+    c0 = kw.get("c0", W.vti3d_background()[0])
+    for k in range(21):
+        p.c0[k] = float(c0[k])
+    p.rho0, p.freq_hz, p.damping = 2200.0, 7.0, 0.02
+    p.nsys, p.symbol, p.params = kw.get("nsys", 4), 0, kw.get("params", _lib.FWILS_PARAMS_VTI)
+    return p
+
+
+def test_plan_create3_validates_on_the_host(lib):
+    """3-D plans: supported axis lengths (2^a 3^b 5^c, 16..256, or ny = 1), a
+    positive definite background, known parametrisations; field and workspace
+    sizes follow [nsys][3][nz][ny][nx]; 3-D plans refuse the 2-D-only calls."""
+    import workloads as W
+    cases = [({}, 0), ({"n": (80, 1, 32)}, 0), ({"n": (80, 40, 33)}, _lib.FWILS_EINVAL),
+             ({"n": (512, 16, 16)}, _lib.FWILS_EINVAL), ({"params": 7}, _lib.FWILS_EINVAL),
+             ({"c0": -W.vti3d_background()[0]}, _lib.FWILS_EINVAL), ({"nsys": 0}, _lib.FWILS_EINVAL)]
+    for kw, want in cases:
+        arr = (_lib.FwilsProblem3 * 1)(_prob3(**kw))
+        h = ctypes.c_void_p()
+        assert lib.fwils_plan_create3(arr, 1, _lib.FWILS_C64, ctypes.byref(h)) == want, kw
+        if want == 0:
+            n = kw.get("n", (80, 40, 32))
+            fe = ctypes.c_int64()
+            assert lib.fwils_field_elems(h, ctypes.byref(fe)) == 0
+            assert fe.value == 4 * 3 * n[0] * n[1] * n[2]
+            t = _lib.FwilsTuning()
+            assert lib.fwils_get_tuning(h, 0, ctypes.byref(t)) == _lib.FWILS_EUNSUPPORTED
+            lib.fwils_plan_destroy(h)
+    # precision reaches the right core; general parametrisation accepted
+    arr = (_lib.FwilsProblem3 * 1)(_prob3(params=_lib.FWILS_PARAMS_GENERAL, n=(20, 24, 16)))
+    h = ctypes.c_void_p()
+    assert lib.fwils_plan_create3(arr, 1, _lib.FWILS_C128, ctypes.byref(h)) == 0
+    lib.fwils_plan_destroy(h)

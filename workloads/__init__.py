@@ -228,3 +228,107 @@ def reservoir_dbi(nx=192, nz=48, dx=20.0, nsrc=48, nrec=96, freqs=(3.0, 5.0, 7.0
     return dict(nx=nx, nz=nz, dx=dx, c0=c0, rho0=rho0, eta=0.02, freqs=tuple(freqs), m0=m0.ravel(),
                 c_true=round_f32(m0 * q_true), c_start=round_f32(m0 * q_start), src_ixz=src_ixz, src_f=src_f,
                 rec=rec)
+
+
+# ------------------------------------------------------------------ 3-D ----
+# Inputs of the 3-D problems: a general background given by the 21 constants
+# of the upper triangle of its 6 x 6 Voigt matrix (row by row), contrast maps
+# [nmaps, nz, ny, nx] and sources / receivers (ix, iy, iz).
+#
+# * VTI background from Thomsen parameters with C66 = C55 (1 + 2 gamma): the
+#   6 x 6 matrix with C22 = C11, C12 = C11 - 2 C66, C23 = C13, C44 = C55.
+# * A "triclinic" background: that VTI matrix plus a seeded random symmetric
+#   perturbation of every entry (relative size `scale` of C33), kept only if
+#   positive definite (redrawn otherwise).
+# * Smooth random 3-D fields: the 2-D recipe with a 3-D periodic filter.
+# * The stand-in for the paper's modified 3-D VTI Hess model (not available):
+#   80 x 40 x 32 cells of 25 m, VTI background with C66 = C55, six contrast
+#   maps (C11, C13, C33, C55, C66, rho) made of 4 flat layers (offsets
+#   U(-0.10, 0.10)) plus smooth noise (std 0.03, ell 4 cells) relative to the
+#   background constants, 100 vertical forces on a 10 x 10 surface grid and
+#   400 receivers on a 20 x 20 surface grid.
+def vti_voigt_upper(C11, C13, C33, C55, C66):
+    """The 21 upper-triangle constants of a VTI stiffness."""
+    C = np.zeros((6, 6))
+    C[0, 0] = C[1, 1] = C11
+    C[0, 1] = C[1, 0] = C11 - 2.0 * C66
+    C[0, 2] = C[2, 0] = C[1, 2] = C[2, 1] = C13
+    C[2, 2] = C33
+    C[3, 3] = C[4, 4] = C55
+    C[5, 5] = C66
+    return C[np.triu_indices(6)]
+
+
+def vti3d_background(gamma=0.0):
+    """21 constants and rho of the VTI background; C66 = C55 (1 + 2 gamma)."""
+    (C11, C13, C33, C55), rho = vti_background()
+    return vti_voigt_upper(C11, C13, C33, C55, C55 * (1.0 + 2.0 * gamma)), rho
+
+
+def vti3d_scales(gamma=0.0):
+    """(C11, C13, C33, C55, C66, rho) of the VTI background, shape [6, 1, 1, 1]."""
+    (C11, C13, C33, C55), rho = vti_background()
+    return np.array([C11, C13, C33, C55, C55 * (1.0 + 2.0 * gamma), rho])[:, None, None, None]
+
+
+def triclinic_background(seed, scale=0.08):
+    """21 constants of a positive definite 6 x 6 stiffness near the VTI one, and rho."""
+    c21, rho = vti3d_background(gamma=0.1)
+    C = np.zeros((6, 6))
+    C[np.triu_indices(6)] = c21
+    C = C + np.triu(C, 1).T
+    rng = np.random.default_rng(seed)
+    while True:
+        R = rng.standard_normal((6, 6))
+        Cp = C + scale * C[2, 2] * (R + R.T) / 2.0
+        if np.all(np.linalg.eigvalsh(Cp) > 0.05 * C[2, 2]):
+            return Cp[np.triu_indices(6)], rho
+
+
+def smooth_random3(rng, nz, ny, nx, ell, std):
+    w = rng.standard_normal((nz, ny, nx))
+    f = scipy.ndimage.gaussian_filter(w, sigma=ell, mode="wrap")
+    sd = f.std()
+    f = (f - f.mean()) / (sd if sd > 0 else 1.0)
+    return std * f
+
+
+def contrast3(seed, nz, ny, nx, scales, ell=2.0, std=0.05):
+    """Smooth random relative contrast times the per-map scales [nmaps, 1, 1, 1]."""
+    rng = np.random.default_rng(seed)
+    q = np.array([smooth_random3(rng, nz, ny, nx, ell, std) for _ in range(scales.shape[0])])
+    return q * scales
+
+
+def general_scales(c21, rho):
+    """Per-map scale of a 21-constant contrast: C33 of the background for
+    every constant (off-diagonal ones are often zero in the background), rho."""
+    c33 = float(c21[12])
+    return np.array([c33] * 21 + [rho])[:, None, None, None]
+
+
+def surface_grid(nx, ny, n1, n2, iz=0):
+    """n1 x n2 points evenly spread over the top face, (ix, iy, iz)."""
+    xs = [int(math.floor((i + 0.5) * nx / n1)) for i in range(n1)]
+    ys = [int(math.floor((j + 0.5) * ny / n2)) for j in range(n2)]
+    return [(x, y, iz) for y in ys for x in xs]
+
+
+def hess3d_vti(nsrc=(10, 10), nrec=(20, 20), freq_hz=7.0, seed=12):
+    """80 x 40 x 32, 25 m cells: the stand-in for the modified 3-D VTI Hess example."""
+    nx, ny, nz, dx = 80, 40, 32, 25.0
+    c21, rho = vti3d_background(gamma=0.0)
+    scales = vti3d_scales(gamma=0.0)
+    rng = np.random.default_rng(seed)
+    q = np.zeros((6, nz, ny, nx))
+    for p in range(6):
+        off = rng.uniform(-0.10, 0.10, 4)
+        for layer in range(4):
+            q[p, round(layer * nz / 4):round((layer + 1) * nz / 4)] += off[layer]
+        q[p] += smooth_random3(rng, nz, ny, nx, 4.0, 0.03)
+    maps = round_f32(q * scales)
+    src = surface_grid(nx, ny, *nsrc)
+    rec = surface_grid(nx, ny, *nrec, iz=1)
+    return dict(nx=nx, ny=ny, nz=nz, dx=dx, c0=c21, rho0=rho, freq_hz=freq_hz, eta=0.02, params="vti",
+                maps=maps, src_ixyz=src, src_f=[(0.0, 0.0, 1.0)] * len(src), rec_ixyz=rec, nsys=len(src),
+                scales=scales)
