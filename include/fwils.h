@@ -162,9 +162,13 @@ void fwils_plan_destroy(fwils_plan plan);
  * stream, contrast, receivers, incident, body force, convolve, apply,
  * apply_noalloc, solve (BiCGSTAB or GMRES), frechet, adjoint (complex128 maps
  * [nmaps][nz][ny][nx]), receiver_data, get_contrast, field_elems, solve
- * statistics and fft2 (the 3-D transform).  The Tikhonov, DBI, tuning and
- * pass-timing entry points return FWILS_EUNSUPPORTED for it; fwils_autotune
- * leaves its problems unchanged. */
+ * statistics, fft2 (the 3-D transform) and the Tikhonov / normal-equation /
+ * DBI entry points (maps [nmaps][nz][ny][nx], m0 [nmaps], the 7-point
+ * Laplacian); fwils_apply_pass / fwils_time_pass time its passes (0: stencil,
+ * 1: x transforms, 2: the y, z-with-Green and y transforms, 3: inverse x
+ * transforms with the epilogue).  The tuning and Krylov-pass timing entry
+ * points return FWILS_EUNSUPPORTED for it; fwils_autotune leaves its problems
+ * unchanged. */
 fwils_status fwils_plan_create3(const fwils_problem3* probs, int32_t nprob, fwils_precision prec,
                                 fwils_plan* out);
 
@@ -288,6 +292,18 @@ fwils_status fwils_time_pass(fwils_plan plan, int32_t pass, const void* u, void*
  * if some system stopped running during the timed launches.  Synchronous. */
 fwils_status fwils_time_krylov_pass(fwils_plan plan, int32_t reps, float* us);
 
+/* Average duration in microseconds (*us, host) of one GMRES Arnoldi-step
+ * kernel over all problems of a GMRES plan with every system running, at
+ * step j (0 <= j < restart): kind 0, the basis update w -= sum_{l <= j} c_l w_l
+ * (reads j + 2 field vectors, writes one); kind 1, the re-orthogonalisation
+ * projections <w_l, w> (reads j + 2); kind 2, the inverse row transform whose
+ * epilogue forms w = A w_j and its projections on the j + 1 basis vectors
+ * (reads the spectrum, w_j and j + 1 basis vectors, writes w).  reps
+ * (1..10000) back-to-back launches between HIP events on the plan's stream
+ * after one warm-up; the solver's per-system state is restored afterwards,
+ * the GMRES basis is left changed.  Synchronous. */
+fwils_status fwils_time_gmres_pass(fwils_plan plan, int32_t kind, int32_t j, int32_t reps, float* us);
+
 /* Per-system results of the most recent Krylov solve of this plan (from
  * fwils_solve, fwils_frechet or fwils_adjoint): completed iterations and the
  * recursive relative residual ||r|| / ||rhs||.  Host arrays [sum nsys] or
@@ -307,9 +323,11 @@ fwils_status fwils_solve_status(fwils_plan plan, int32_t* status);
 /* ---- Generalised Tikhonov step (eqs. obj, norm) ------------------------
  * Unknowns are relative maps q, real [5][nz][nx] on the device, with
  * dm_p = m0_p q_p (m0: host double[5], e.g. the background C11, C13, C33,
- * C55, rho0).  All problems of the plan must share one grid (nx, nz, dx);
- * their data stack: J q = [J_1 q; J_2 q; ...], J* r = sum_f J_f* r_f.
- * With rr = ||r||^2 and L = I or the periodic unscaled 5-point Laplacian:
+ * C55, rho0); in a 3-D plan [nmaps][nz][ny][nx] and m0[nmaps] (six VTI or
+ * 22 general maps).  All problems of the plan must share one grid (nx, ny,
+ * nz, dx, parametrisation); their data stack: J q = [J_1 q; J_2 q; ...],
+ * J* r = sum_f J_f* r_f.  With rr = ||r||^2 and L = I or the periodic
+ * unscaled 5-point (2-D) or 7-point (3-D) Laplacian:
  *   f(q)      = ||J q - r||^2 / rr + lam ||L q||^2
  *   grad f(q) = 2 m0 Re J*(J q - r) / rr + 2 lam L^T L q
  *   N q       = m0 Re J*(J q) / rr + lam L^T L q          (normal operator)
@@ -338,6 +356,22 @@ fwils_status fwils_normal_apply(fwils_plan plan, const void* ub, const double* m
 fwils_status fwils_normal_cg(fwils_plan plan, const void* ub, const void* r, const double* m0,
                              double lam, int32_t reg, int32_t niter, void* q, double* hist,
                              void* dscratch, double rtol, int32_t maxit);
+
+/* fwils_normal_cg in steps, with every iterate: first = 0 starts from q = 0
+ * exactly as fwils_normal_cg; first = k > 0 continues, for niter more
+ * iterations, the run of k iterations this plan's last call left in its
+ * workspace (same ub, r, m0, lam and reg; FWILS_EINVAL if the plan holds no
+ * such run, e.g. after another Tikhonov call).  The steps of one run give
+ * exactly the iterates and history of one call of their total length: a run
+ * that has reached the floor of fwils_normal_cg stays there.  q_iters (device real [niter][5][nz][nx], or NULL)
+ * receives the iterate after each of the niter iterations; hist (host double
+ * [niter + 1] or NULL) the residual norms from iteration first on.  For runs
+ * longer than one call should take (checkpoints, progress, comparisons of
+ * iterates).  first + niter <= 1000.  Synchronous. */
+fwils_status fwils_normal_cg_steps(fwils_plan plan, const void* ub, const void* r, const double* m0,
+                                   double lam, int32_t reg, int32_t first, int32_t niter, void* q,
+                                   double* hist, void* q_iters, void* dscratch, double rtol,
+                                   int32_t maxit);
 
 /* J and J* in the relative units of the Tikhonov step (single-grid plans):
  *   fwils_frechet_rel: d = J (m0 q)                     (q: device real [5][nz][nx])

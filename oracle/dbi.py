@@ -33,6 +33,14 @@ def data_error(res, d_obs):
     return float(np.sqrt(rr / dd))
 
 
+def _sample(P, u, rec):
+    """Receiver sampling of a 2-D or 3-D problem's fields."""
+    if hasattr(P, "ny"):
+        from .elastic3d import sample_3d
+        return sample_3d(u, rec)
+    return operators.sample(u, rec)
+
+
 def background_data(items, contrast, solve_tol=1e-12):
     """u^b and R u^b of every item under one contrast (steps 1-2)."""
     fields, data = [], []
@@ -40,7 +48,7 @@ def background_data(items, contrast, solve_tol=1e-12):
         P.set_contrast(contrast)
         ub, _ = P.solve(P.incident(src, f), tol=solve_tol)
         fields.append(ub)
-        data.append(operators.sample(ub, rec))
+        data.append(_sample(P, ub, rec))
     return fields, data
 
 
@@ -49,12 +57,13 @@ def dbi_stage(items, contrast, m0, lam0, niter, reg="identity", tol=1e-3, max_ou
     """Run one frequency stage of the DBI loop.
 
     items: list of (LSProblem, src_ixz, src_f, rec_ixz, d_obs), one per
-    frequency of the stage, all on one grid; contrast: starting [5, nz, nx]
-    maps (Pa, kg/m^3); m0: five parameter scales (dm_p = m0_p q_p).
+    frequency of the stage, all on one grid; contrast: starting maps [5, nz,
+    nx] (2-D) or [nmaps, nz, ny, nx] (3-D) in Pa and kg/m^3; m0: the
+    parameter scales (dm_p = m0_p q_p).
     Returns (contrast, eps_d history, lambda of each update, last q or None).
     """
     c = np.array(contrast, dtype=float)
-    m0b = np.asarray(m0, dtype=float).reshape(5, 1, 1)
+    m0b = np.asarray(m0, dtype=float).reshape((c.shape[0],) + (1,) * (c.ndim - 1))
     d_obs = [it[4] for it in items]
     eps_hist, lam_hist, q = [], [], None
     for k in range(max_outer + 1):

@@ -7,8 +7,8 @@ Readings:
   * Several problems (frequencies) stack their data: J q = [J_1 q; J_2 q; ...]
     and J* r = sum_f J_f* r_f.
   * L is either the identity (the paper's form of eq. obj) or the periodic,
-    unscaled 5-point Laplacian applied to each map (a generalised Tikhonov
-    operator).
+    unscaled 5-point (2-D) or 7-point (3-D) Laplacian applied to each map (a
+    generalised Tikhonov operator).
   * Real maps: the gradient and the normal operator take Re of J*.
 
     f(q)      = ||J q - r||^2 / ||r||^2 + lambda ||L q||^2
@@ -27,6 +27,11 @@ def laplacian(q):
             + np.roll(q, -1, -2) - 4.0 * q)
 
 
+def laplacian3(q):
+    """Periodic 7-point Laplacian of each map of q [..., nz, ny, nx], unscaled."""
+    return sum(np.roll(q, s, a) for a in (-1, -2, -3) for s in (1, -1)) - 6.0 * q
+
+
 class Tikhonov:
     """The stacked linear problem of one DBI step.
 
@@ -43,11 +48,15 @@ class Tikhonov:
         self.reg = reg
         self.tol = tol
 
+    def _lap(self, q):
+        # maps [nmaps, nz, nx] (2-D) or [nmaps, nz, ny, nx] (3-D)
+        return laplacian3(q) if np.ndim(q) == 4 else laplacian(q)
+
     def L(self, q):
-        return laplacian(q) if self.reg == "laplacian" else q
+        return self._lap(q) if self.reg == "laplacian" else q
 
     def LtL(self, q):
-        return laplacian(laplacian(q)) if self.reg == "laplacian" else q
+        return self._lap(self._lap(q)) if self.reg == "laplacian" else q
 
     def J(self, q):
         dm = self.m0 * q

@@ -80,12 +80,15 @@ SIGNATURES = {
     "fwils_apply_pass": (c_int32, [P, c_int32, P, P]),
     "fwils_time_pass": (c_int32, [P, c_int32, P, P, c_int32, ctypes.POINTER(ctypes.c_float)]),
     "fwils_time_krylov_pass": (c_int32, [P, c_int32, ctypes.POINTER(ctypes.c_float)]),
+    "fwils_time_gmres_pass": (c_int32, [P, c_int32, c_int32, c_int32, ctypes.POINTER(ctypes.c_float)]),
     "fwils_tikhonov_grad": (c_int32, [P, P, P, ctypes.POINTER(c_double), c_double, c_int32, P, P,
                                       ctypes.POINTER(c_double), P, c_double, c_int32]),
     "fwils_normal_apply": (c_int32, [P, P, ctypes.POINTER(c_double), c_double, c_double, c_int32, P, P, P,
                                      c_double, c_int32]),
     "fwils_normal_cg": (c_int32, [P, P, P, ctypes.POINTER(c_double), c_double, c_int32, c_int32, P,
                                   ctypes.POINTER(c_double), P, c_double, c_int32]),
+    "fwils_normal_cg_steps": (c_int32, [P, P, P, ctypes.POINTER(c_double), c_double, c_int32, c_int32, c_int32, P,
+                                        ctypes.POINTER(c_double), P, P, c_double, c_int32]),
     "fwils_frechet_rel": (c_int32, [P, P, P, ctypes.POINTER(c_double), P, c_double, c_int32]),
     "fwils_adjoint_rel": (c_int32, [P, P, P, ctypes.POINTER(c_double), P, c_double, c_int32]),
     "fwils_laplacian": (c_int32, [P, P, P]),

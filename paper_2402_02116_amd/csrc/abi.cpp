@@ -43,6 +43,8 @@
       (fwils_plan plan, int32_t pass, const void* u, void* Au, int32_t reps, float* us),                  \
       (plan, pass, u, Au, reps, us))                                                                       \
     X(fwils_status, time_krylov_pass, (fwils_plan plan, int32_t reps, float* us), (plan, reps, us))       \
+    X(fwils_status, time_gmres_pass, (fwils_plan plan, int32_t kind, int32_t j, int32_t reps, float* us),  \
+      (plan, kind, j, reps, us))                                                                           \
     X(fwils_status, solve_stats, (fwils_plan plan, int32_t* iters, double* relres), (plan, iters, relres)) \
     X(fwils_status, solve_status, (fwils_plan plan, int32_t* status), (plan, status))                    \
     X(fwils_status, tikhonov_grad,                                                                         \
@@ -57,6 +59,11 @@
       (fwils_plan plan, const void* ub, const void* r, const double* m0, double lam, int32_t reg,         \
        int32_t niter, void* q, double* hist, void* dscratch, double rtol, int32_t maxit),                 \
       (plan, ub, r, m0, lam, reg, niter, q, hist, dscratch, rtol, maxit))                                 \
+    X(fwils_status, normal_cg_steps,                                                                       \
+      (fwils_plan plan, const void* ub, const void* r, const double* m0, double lam, int32_t reg,         \
+       int32_t first, int32_t niter, void* q, double* hist, void* q_iters, void* dscratch, double rtol,  \
+       int32_t maxit),                                                                                     \
+      (plan, ub, r, m0, lam, reg, first, niter, q, hist, q_iters, dscratch, rtol, maxit))                 \
     X(fwils_status, frechet_rel,                                                                           \
       (fwils_plan plan, const void* ub, const void* q, const double* m0, void* d, double rtol,            \
        int32_t maxit),                                                                                     \

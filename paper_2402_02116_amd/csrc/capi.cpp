@@ -113,11 +113,15 @@ struct fwils_plan_s {
            *s = nullptr, *t = nullptr, *tmp = nullptr, *rhs = nullptr;
     cplx* tmp2 = nullptr;   // the separate contrast stencil's output (input of the forward rows)
     // model-map scratch of the Tikhonov step (single-grid plans only)
-    size_t map_n = 0, off_mapws = 0;
+    size_t map_n = 0, off_mapws = 0;   // cells of each model map (0: no shared grid)
+    int map_k = 5;                        // model maps (5 in 2-D, 6 or 22 in 3-D)
     real *mq_dm = nullptr, *mq_x = nullptr, *mq_res = nullptr, *mq_p = nullptr, *mq_Ap = nullptr,
           *mq_l1 = nullptr, *mq_l2 = nullptr;
     double2* mq_g = nullptr;   // FP64 J* accumulator (map units)
     double *mq_part = nullptr, *mq_sc = nullptr, *mq_hist = nullptr;
+    int cg_done = -1;           // iterations of the normal-equation CG run the map workspace holds (-1: none)
+    bool cg_floor = false;      // that run reached the floor (converged to working precision)
+    double cg_rs0 = 0.0;        // that run's initial squared residual
     // graphs of one chunk of iterations over all problems (the first chunk of
     // a solve or restart starts from r)
     hipGraphExec_t chunk = nullptr, chunk_first = nullptr;
@@ -807,15 +811,19 @@ void layout_plan(fwils_plan pl) {
     o = align256(o + align256(pl->total_sys * 3 * sizeof(int32_t)) + pl->total_sys * 3 * sizeof(double));
     pl->off_vec = o;
     o += kNumVec * align256(pl->total_field * sizeof(cplx));
-    // the Tikhonov step's model-map scratch: single-grid 2-D plans
-    bool one_grid = !pl->d3;
+    // the Tikhonov step's model-map scratch: plans whose problems share one
+    // grid (and parametrisation)
+    bool one_grid = true;
     for (int i = 1; i < nprob; ++i)
         one_grid = one_grid && pl->probs[i].p.nx == pl->probs[0].p.nx && pl->probs[i].p.nz == pl->probs[0].p.nz &&
+                   pl->probs[i].ny == pl->probs[0].ny && pl->probs[i].nmaps == pl->probs[0].nmaps &&
                    pl->probs[i].p.dx == pl->probs[0].p.dx;
-    pl->map_n = one_grid ? (size_t)pl->probs[0].p.nx * pl->probs[0].p.nz : 0;
+    pl->map_n = one_grid ? pl->probs[0].cells : 0;
+    pl->map_k = pl->probs[0].nmaps;
     pl->off_mapws = o;
+    const size_t mk = (size_t)pl->map_k;
     if (pl->map_n) {
-        o += 7 * align256(5 * pl->map_n * sizeof(real)) + align256(5 * pl->map_n * sizeof(double2));
+        o += 7 * align256(mk * pl->map_n * sizeof(real)) + align256(mk * pl->map_n * sizeof(double2));
         o += align256(kDotPartials * sizeof(double)) + align256(16 * sizeof(double)) +
              align256(kMaxCgIters + 1) * sizeof(double);
     }
@@ -1095,13 +1103,13 @@ fwils_status fwils_set_workspace(fwils_plan plan, void* dev, size_t bytes) {
     for (int i = 0; i < kNumVec; ++i) *vecs[i] = (cplx*)(w + plan->off_vec + i * vb);
     if (plan->map_n) {
         char* m = w + plan->off_mapws;
-        const size_t fb = align256(5 * plan->map_n * sizeof(real));
+        const size_t fb = align256((size_t)plan->map_k * plan->map_n * sizeof(real));
         real** fm[7] = {&plan->mq_dm, &plan->mq_x, &plan->mq_res, &plan->mq_p,
                          &plan->mq_Ap, &plan->mq_l1, &plan->mq_l2};
         for (int i = 0; i < 7; ++i) *fm[i] = (real*)(m + i * fb);
         m += 7 * fb;
         plan->mq_g = (double2*)m;
-        m += align256(5 * plan->map_n * sizeof(double2));
+        m += align256((size_t)plan->map_k * plan->map_n * sizeof(double2));
         plan->mq_part = (double*)m;
         m += align256(kDotPartials * sizeof(double));
         plan->mq_sc = (double*)m;
@@ -1118,6 +1126,7 @@ fwils_status fwils_set_workspace(fwils_plan plan, void* dev, size_t bytes) {
 }
 
 fwils_status fwils_set_contrast(fwils_plan plan, int32_t iprob, const void* maps_) {
+    if (plan) plan->cg_done = -1;   // the map workspace is reused: no CG run to continue
     const real* maps = static_cast<const real*>(maps_);
     FW_TRY(check_plan(plan));
     if (iprob < 0 || iprob >= (int)plan->probs.size() || !maps) {
@@ -1392,10 +1401,10 @@ fwils_status check_tik(fwils_plan plan, const double* m0, double lam, int32_t re
         return FWILS_EINVAL;
     }
     if (!m0 || !(lam >= 0) || (reg != FWILS_REG_IDENTITY && reg != FWILS_REG_LAPLACIAN)) {
-        set_error("%s: need m0[5], lam >= 0 and a known regulariser", what);
+        set_error("%s: need m0[%d], lam >= 0 and a known regulariser", what, plan->map_k);
         return FWILS_EINVAL;
     }
-    for (int k = 0; k < 5; ++k)
+    for (int k = 0; k < plan->map_k; ++k)
         if (!std::isfinite(m0[k])) {
             set_error("%s: m0 must be finite", what);
             return FWILS_EINVAL;
@@ -1413,8 +1422,8 @@ size_t data_elems(fwils_plan plan) {
 fwils_status regulariser(fwils_plan plan, int32_t reg, const real* q, const real** rq) {
     const ProbHost& P = plan->probs[0];
     if (reg == FWILS_REG_LAPLACIAN) {
-        FW_HIP(launch_laplacian(q, plan->mq_l1, P.p.nx, P.p.nz, 5, plan->stream));
-        FW_HIP(launch_laplacian(plan->mq_l1, plan->mq_l2, P.p.nx, P.p.nz, 5, plan->stream));
+        FW_HIP(launch_laplacian(q, plan->mq_l1, P.p.nx, P.ny, P.p.nz, plan->map_k, plan->stream));
+        FW_HIP(launch_laplacian(plan->mq_l1, plan->mq_l2, P.p.nx, P.ny, P.p.nz, plan->map_k, plan->stream));
         *rq = plan->mq_l2;
     } else {
         *rq = q;
@@ -1433,7 +1442,7 @@ fwils_status normal_apply_ws(fwils_plan plan, const void* ub, const MapScales& m
     fwils_status st = frechet_ws(plan, ub, dms.data(), dscratch, rtol, maxit);
     if (st == FWILS_EDEVICE) return st;
     std::vector<void*> gs(plan->probs.size(), plan->mq_g);
-    FW_HIP(launch_zero_d2(plan->mq_g, 5 * plan->map_n, s));
+    FW_HIP(launch_zero_d2(plan->mq_g, (size_t)plan->map_k * plan->map_n, s));
     fwils_status st2 = adjoint_ws(plan, ub, dscratch, gs.data(), true, rtol, maxit, true);
     if (st2 == FWILS_EDEVICE) return st2;
     const real* rq = nullptr;
@@ -1442,22 +1451,26 @@ fwils_status normal_apply_ws(fwils_plan plan, const void* ub, const MapScales& m
     return worst(st, st2);
 }
 
-MapScales scales(const double* m0) {
-    MapScales m;
-    for (int k = 0; k < 5; ++k) m.s[k] = m0[k];
+MapScales scales(const double* m0, int nmaps) {
+    MapScales m{};
+    m.n = nmaps;
+    for (int k = 0; k < nmaps; ++k) m.s[k] = m0[k];
     return m;
 }
 
 // niter CG iterations on eq. norm from q = 0 (validated arguments); hist:
 // host [niter + 1] or NULL.
+// CG on the normal equation.  first = 0: from q = 0 (right-hand side, first
+// residual); first = k > 0: continue the run whose k iterations the plan's
+// map workspace holds.  q_iters (or null): the iterate after each iteration.
 fwils_status normal_cg_ws(fwils_plan plan, const void* ub, const void* r, const MapScales& ms, double lam,
                           int32_t reg, int32_t niter, real* q, double* hist, void* dscratch, double rtol,
-                          int32_t maxit) {
+                          int32_t maxit, int32_t first = 0, real* q_iters = nullptr) {
     hipStream_t s = plan->stream;
     const int n = (int)plan->map_n;
-    const size_t nm = 5 * plan->map_n;
+    const size_t nm = (size_t)plan->map_k * plan->map_n;
     double* sc = plan->mq_sc;
-    // rr and the right-hand side m0 Re J* r / rr
+    // rr = ||r||^2 (the misfit's normalisation)
     FW_HIP(launch_norm2_complex(static_cast<const cplx*>(r), data_elems(plan), plan->mq_part, sc + 4, s));
     double rr = 0;
     FW_HIP(hipMemcpyAsync(&rr, sc + 4, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1466,20 +1479,27 @@ fwils_status normal_cg_ws(fwils_plan plan, const void* ub, const void* r, const 
         set_error("normal_cg: ||r|| is zero");
         return FWILS_EINVAL;
     }
-    std::vector<void*> gs(plan->probs.size(), plan->mq_g);
-    FW_HIP(launch_zero_d2(plan->mq_g, nm, s));
-    fwils_status st = adjoint_ws(plan, ub, r, gs.data(), true, rtol, maxit, true);
-    if (st == FWILS_EDEVICE) return st;
-    FW_HIP(launch_map_combine(plan->mq_g, nullptr, plan->mq_res, ms, 1.0 / rr, 0.0, n, s));
-    FW_HIP(launch_zero_f(plan->mq_x, nm, s));
-    FW_HIP(launch_copy_f(plan->mq_res, plan->mq_p, nm, s));
-    FW_HIP(launch_dot_real(plan->mq_res, plan->mq_res, nm, plan->mq_part, sc + 2, s));
-    FW_HIP(launch_cg_shift(sc, plan->mq_hist, 0, s));
-    double rs0 = 0.0;
-    FW_HIP(hipMemcpyAsync(&rs0, sc + 2, sizeof(double), hipMemcpyDeviceToHost, s));
-    FW_HIP(hipStreamSynchronize(s));
-    int done = niter;   // iterations run: fewer once the residual is at the floor
-    for (int it = 0; it < niter; ++it) {
+    fwils_status st = FWILS_OK;
+    if (first == 0) {   // the right-hand side m0 Re J* r / rr and the first residual
+        plan->cg_done = -1;
+        plan->cg_floor = false;
+        std::vector<void*> gs(plan->probs.size(), plan->mq_g);
+        FW_HIP(launch_zero_d2(plan->mq_g, nm, s));
+        st = adjoint_ws(plan, ub, r, gs.data(), true, rtol, maxit, true);
+        if (st == FWILS_EDEVICE) return st;
+        FW_HIP(launch_map_combine(plan->mq_g, nullptr, plan->mq_res, ms, 1.0 / rr, 0.0, n, s));
+        FW_HIP(launch_zero_f(plan->mq_x, nm, s));
+        FW_HIP(launch_copy_f(plan->mq_res, plan->mq_p, nm, s));
+        FW_HIP(launch_dot_real(plan->mq_res, plan->mq_res, nm, plan->mq_part, sc + 2, s));
+        FW_HIP(launch_cg_shift(sc, plan->mq_hist, 0, s));
+        FW_HIP(hipMemcpyAsync(&plan->cg_rs0, sc + 2, sizeof(double), hipMemcpyDeviceToHost, s));
+        FW_HIP(hipStreamSynchronize(s));
+    }
+    const double rs0 = plan->cg_rs0;
+    // iterations run: fewer once the residual is at the floor (none when
+    // continuing a run that reached it, as one longer run would have stopped)
+    int done = plan->cg_floor ? 0 : niter;
+    for (int it = 0; it < done; ++it) {
         fwils_status sa = normal_apply_ws(plan, ub, ms, rr, lam, reg, plan->mq_p, plan->mq_Ap, dscratch,
                                           rtol, maxit);
         if (sa == FWILS_EDEVICE) return sa;
@@ -1488,7 +1508,8 @@ fwils_status normal_cg_ws(fwils_plan plan, const void* ub, const void* r, const 
         FW_HIP(launch_cg_xr(plan->mq_x, plan->mq_res, plan->mq_p, plan->mq_Ap, sc, nm, s));
         FW_HIP(launch_dot_real(plan->mq_res, plan->mq_res, nm, plan->mq_part, sc + 2, s));
         FW_HIP(launch_cg_p(plan->mq_p, plan->mq_res, sc, nm, s));
-        FW_HIP(launch_cg_shift(sc, plan->mq_hist, it + 1, s));
+        FW_HIP(launch_cg_shift(sc, plan->mq_hist, first + it + 1, s));
+        if (q_iters) FW_HIP(launch_copy_f(plan->mq_x, q_iters + (size_t)it * nm, nm, s));
         // converged to working precision: further iterations would only push
         // the direction vectors towards underflow
         double rs = 0.0;
@@ -1496,15 +1517,20 @@ fwils_status normal_cg_ws(fwils_plan plan, const void* ub, const void* r, const 
         FW_HIP(hipStreamSynchronize(s));
         if (!(rs > kCgFloor * rs0)) {
             done = it + 1;
+            plan->cg_floor = true;
             break;
         }
     }
+    if (q_iters)
+        for (int it = done; it < niter; ++it) FW_HIP(launch_copy_f(plan->mq_x, q_iters + (size_t)it * nm, nm, s));
     FW_HIP(launch_copy_f(plan->mq_x, q, nm, s));
     if (hist)
-        FW_HIP(hipMemcpyAsync(hist, plan->mq_hist, (size_t)(done + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
+        FW_HIP(hipMemcpyAsync(hist, plan->mq_hist + first, (size_t)(done + 1) * sizeof(double), hipMemcpyDeviceToHost,
+                              s));
     FW_HIP(hipStreamSynchronize(s));
     if (hist)
         for (int i = done + 1; i <= niter; ++i) hist[i] = hist[done];
+    plan->cg_done = first + niter;
     return st;
 }
 
@@ -1557,7 +1583,7 @@ fwils_status fwils_adjoint(fwils_plan plan, const void* ub, const void* r, void*
 fwils_status fwils_normal_apply(fwils_plan plan, const void* ub, const double* m0, double rr, double lam,
                                 int32_t reg, const void* q_in_, void* q_out_, void* dscratch, double rtol,
                                 int32_t maxit) {
-    FW_TRY(only_2d(plan, "normal_apply"));
+    if (plan) plan->cg_done = -1;   // the map workspace is reused: no CG run to continue
     const real* q_in = static_cast<const real*>(q_in_);
     real* q_out = static_cast<real*>(q_out_);
     FW_TRY(check_plan(plan));
@@ -1567,7 +1593,7 @@ fwils_status fwils_normal_apply(fwils_plan plan, const void* ub, const double* m
         set_error("normal_apply: need rr > 0 and distinct q_in, q_out");
         return FWILS_EINVAL;
     }
-    fwils_status st = normal_apply_ws(plan, ub, scales(m0), rr, lam, reg, q_in, q_out, dscratch, rtol, maxit);
+    fwils_status st = normal_apply_ws(plan, ub, scales(m0, plan->map_k), rr, lam, reg, q_in, q_out, dscratch, rtol, maxit);
     if (st == FWILS_EDEVICE) return st;
     FW_HIP(hipStreamSynchronize(plan->stream));
     return st;
@@ -1576,14 +1602,14 @@ fwils_status fwils_normal_apply(fwils_plan plan, const void* ub, const double* m
 fwils_status fwils_tikhonov_grad(fwils_plan plan, const void* ub, const void* r, const double* m0, double lam,
                                  int32_t reg, const void* q_, void* grad_, double* fval, void* dscratch,
                                  double rtol, int32_t maxit) {
-    FW_TRY(only_2d(plan, "tikhonov_grad"));
+    if (plan) plan->cg_done = -1;   // the map workspace is reused: no CG run to continue
     const real* q = static_cast<const real*>(q_);
     real* grad = static_cast<real*>(grad_);
     FW_TRY(check_plan(plan));
     FW_TRY(check_field_ptrs({ub, r, q, grad, dscratch}));
     FW_TRY(check_tik(plan, m0, lam, reg, rtol, maxit, "tikhonov_grad"));
     hipStream_t s = plan->stream;
-    const MapScales ms = scales(m0);
+    const MapScales ms = scales(m0, plan->map_k);
     const int n = (int)plan->map_n;
     const size_t nd = data_elems(plan);
     double* sc = plan->mq_sc;
@@ -1597,14 +1623,14 @@ fwils_status fwils_tikhonov_grad(fwils_plan plan, const void* ub, const void* r,
     FW_HIP(launch_sub_complex(static_cast<cplx*>(dscratch), static_cast<const cplx*>(r), nd, s));
     FW_HIP(launch_norm2_complex(static_cast<const cplx*>(dscratch), nd, plan->mq_part, sc + 5, s));
     std::vector<void*> gs(plan->probs.size(), plan->mq_g);
-    FW_HIP(launch_zero_d2(plan->mq_g, 5 * plan->map_n, s));
+    FW_HIP(launch_zero_d2(plan->mq_g, (size_t)plan->map_k * plan->map_n, s));
     fwils_status st2 = adjoint_ws(plan, ub, dscratch, gs.data(), true, rtol, maxit, true);
     if (st2 == FWILS_EDEVICE) return st2;
     const real* rq = nullptr;
     FW_TRY(regulariser(plan, reg, q, &rq));
     // ||L q||^2
     const real* lq = (reg == FWILS_REG_LAPLACIAN) ? plan->mq_l1 : q;
-    FW_HIP(launch_dot_real(lq, lq, 5 * plan->map_n, plan->mq_part, sc + 6, s));
+    FW_HIP(launch_dot_real(lq, lq, (size_t)plan->map_k * plan->map_n, plan->mq_part, sc + 6, s));
     double h[3];
     FW_HIP(hipMemcpyAsync(h, sc + 4, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
     FW_HIP(hipStreamSynchronize(s));
@@ -1620,12 +1646,12 @@ fwils_status fwils_tikhonov_grad(fwils_plan plan, const void* ub, const void* r,
 
 fwils_status fwils_frechet_rel(fwils_plan plan, const void* ub, const void* q_, const double* m0, void* d,
                                double rtol, int32_t maxit) {
-    FW_TRY(only_2d(plan, "frechet_rel"));
+    if (plan) plan->cg_done = -1;   // the map workspace is reused: no CG run to continue
     const real* q = static_cast<const real*>(q_);
     FW_TRY(check_plan(plan));
     FW_TRY(check_field_ptrs({ub, q, d}));
     FW_TRY(check_tik(plan, m0, 0.0, FWILS_REG_IDENTITY, rtol, maxit, "frechet_rel"));
-    FW_HIP(launch_map_scale(q, plan->mq_dm, scales(m0), (int)plan->map_n, plan->stream));
+    FW_HIP(launch_map_scale(q, plan->mq_dm, scales(m0, plan->map_k), (int)plan->map_n, plan->stream));
     std::vector<const real*> dms(plan->probs.size(), plan->mq_dm);
     fwils_status st = frechet_ws(plan, ub, dms.data(), d, rtol, maxit);
     if (st == FWILS_EDEVICE) return st;
@@ -1635,22 +1661,22 @@ fwils_status fwils_frechet_rel(fwils_plan plan, const void* ub, const void* q_, 
 
 fwils_status fwils_adjoint_rel(fwils_plan plan, const void* ub, const void* r, const double* m0, void* gq_,
                                double rtol, int32_t maxit) {
-    FW_TRY(only_2d(plan, "adjoint_rel"));
+    if (plan) plan->cg_done = -1;   // the map workspace is reused: no CG run to continue
     real* gq = static_cast<real*>(gq_);
     FW_TRY(check_plan(plan));
     FW_TRY(check_field_ptrs({ub, r, gq}));
     FW_TRY(check_tik(plan, m0, 0.0, FWILS_REG_IDENTITY, rtol, maxit, "adjoint_rel"));
     std::vector<void*> gs(plan->probs.size(), plan->mq_g);
-    FW_HIP(launch_zero_d2(plan->mq_g, 5 * plan->map_n, plan->stream));
+    FW_HIP(launch_zero_d2(plan->mq_g, (size_t)plan->map_k * plan->map_n, plan->stream));
     fwils_status st = adjoint_ws(plan, ub, r, gs.data(), true, rtol, maxit, true);
     if (st == FWILS_EDEVICE) return st;
-    FW_HIP(launch_map_combine(plan->mq_g, nullptr, gq, scales(m0), 1.0, 0.0, (int)plan->map_n, plan->stream));
+    FW_HIP(launch_map_combine(plan->mq_g, nullptr, gq, scales(m0, plan->map_k), 1.0, 0.0, (int)plan->map_n, plan->stream));
     FW_HIP(hipStreamSynchronize(plan->stream));
     return st;
 }
 
 fwils_status fwils_laplacian(fwils_plan plan, const void* q_, void* out_) {
-    FW_TRY(only_2d(plan, "laplacian"));
+    if (plan) plan->cg_done = -1;   // the map workspace is reused: no CG run to continue
     const real* q = static_cast<const real*>(q_);
     real* out = static_cast<real*>(out_);
     FW_TRY(check_plan(plan));
@@ -1659,14 +1685,14 @@ fwils_status fwils_laplacian(fwils_plan plan, const void* q_, void* out_) {
         set_error("laplacian: needs a single-grid plan and distinct q, out");
         return FWILS_EINVAL;
     }
-    FW_HIP(launch_laplacian(q, out, plan->probs[0].p.nx, plan->probs[0].p.nz, 5, plan->stream));
+    FW_HIP(launch_laplacian(q, out, plan->probs[0].p.nx, plan->probs[0].ny, plan->probs[0].p.nz, plan->map_k,
+                            plan->stream));
     return FWILS_OK;
 }
 
 fwils_status fwils_normal_cg(fwils_plan plan, const void* ub, const void* r, const double* m0, double lam,
                              int32_t reg, int32_t niter, void* q_, double* hist, void* dscratch, double rtol,
                              int32_t maxit) {
-    FW_TRY(only_2d(plan, "normal_cg"));
     real* q = static_cast<real*>(q_);
     FW_TRY(check_plan(plan));
     FW_TRY(check_field_ptrs({ub, r, q, dscratch}));
@@ -1675,7 +1701,26 @@ fwils_status fwils_normal_cg(fwils_plan plan, const void* ub, const void* r, con
         set_error("normal_cg: niter must be 1..%d", kMaxCgIters);
         return FWILS_EINVAL;
     }
-    return normal_cg_ws(plan, ub, r, scales(m0), lam, reg, niter, q, hist, dscratch, rtol, maxit);
+    return normal_cg_ws(plan, ub, r, scales(m0, plan->map_k), lam, reg, niter, q, hist, dscratch, rtol, maxit);
+}
+
+fwils_status fwils_normal_cg_steps(fwils_plan plan, const void* ub, const void* r, const double* m0, double lam,
+                                   int32_t reg, int32_t first, int32_t niter, void* q_, double* hist, void* q_iters,
+                                   void* dscratch, double rtol, int32_t maxit) {
+    real* q = static_cast<real*>(q_);
+    FW_TRY(check_plan(plan));
+    FW_TRY(check_field_ptrs({ub, r, q, dscratch}));
+    FW_TRY(check_tik(plan, m0, lam, reg, rtol, maxit, "normal_cg_steps"));
+    if (niter < 1 || first < 0 || first + niter > kMaxCgIters) {
+        set_error("normal_cg_steps: need niter >= 1, first >= 0 and first + niter <= %d", kMaxCgIters);
+        return FWILS_EINVAL;
+    }
+    if (first > 0 && plan->cg_done != first) {
+        set_error("normal_cg_steps: first = %d, but the plan holds a run of %d iterations", first, plan->cg_done);
+        return FWILS_EINVAL;
+    }
+    return normal_cg_ws(plan, ub, r, scales(m0, plan->map_k), lam, reg, niter, q, hist, dscratch, rtol, maxit, first,
+                        static_cast<real*>(q_iters));
 }
 
 fwils_status fwils_receiver_data(fwils_plan plan, const void* u, void* d) {
@@ -1711,7 +1756,7 @@ fwils_status fwils_dbi_run(fwils_plan plan, const int32_t* src_ixz, const double
                            const double* m0, double lam0, int32_t reg, int32_t niter, double tol,
                            int32_t max_outer, void* ub_, void* r_, void* q_, void* dscratch, double* eps_hist,
                            double* lam_hist, int32_t* updates, double rtol, int32_t maxit) {
-    FW_TRY(only_2d(plan, "dbi_run"));
+    if (plan) plan->cg_done = -1;   // the map workspace is reused: no CG run to continue
     const cplx* d_obs = static_cast<const cplx*>(d_obs_);
     cplx* ub = static_cast<cplx*>(ub_);
     cplx* r = static_cast<cplx*>(r_);
@@ -1725,7 +1770,7 @@ fwils_status fwils_dbi_run(fwils_plan plan, const int32_t* src_ixz, const double
     }
     FW_TRY(upload_sources(plan, src_ixz, src_f, "dbi_run"));
     hipStream_t s = plan->stream;
-    const MapScales ms = scales(m0);
+    const MapScales ms = scales(m0, plan->map_k);
     const size_t nd = data_elems(plan);
     double* sc = plan->mq_sc;
     double dd = 0.0;
@@ -1750,7 +1795,7 @@ fwils_status fwils_dbi_run(fwils_plan plan, const int32_t* src_ixz, const double
         // r = d_obs - R u^b and the normalised data error
         for (size_t i = 0; i < plan->probs.size(); ++i) {
             const ProbHost& P = plan->probs[i];
-            FW_HIP(launch_gather(at(ub, P), r + P.data_off, plan->rec + i * kMaxRec * 3, P.nrec, P.dev, s));
+            FW_HIP(gather_any(plan, i, at(ub, P), r + P.data_off, s));
         }
         FW_HIP(launch_data_residual(r, d_obs, nd, s));
         double rr = 0.0;
@@ -1780,7 +1825,6 @@ fwils_status fwils_dbi_run(fwils_plan plan, const int32_t* src_ixz, const double
 }
 
 fwils_status fwils_apply_pass(fwils_plan plan, int32_t pass, const void* u, void* Au) {
-    FW_TRY(only_2d(plan, "apply_pass"));
     FW_TRY(check_plan(plan));
     if (pass < 0 || pass > 3 || ((pass == 0 || pass == 3) && !u) || (pass == 3 && (!Au || u == Au))) {
         set_error("apply_pass: pass must be 0..3 with u (passes 0, 3) and a distinct Au (pass 3)");
@@ -1788,8 +1832,24 @@ fwils_status fwils_apply_pass(fwils_plan plan, int32_t pass, const void* u, void
     }
     hipStream_t s = plan->stream;
     for (const ProbHost& P : plan->probs) {
-        const int rows = P.p.nsys * 2 * P.p.nz;
+        const int rows = P.p.nsys * P.rps;
         cplx* tmp = at(plan->tmp, P);
+        if (P.d3) {   // stencil / x rows / y, z (Green) and y transforms / inverse x rows
+            if (pass == 0) {
+                const StencilArgs a{at(u, P), nullptr, nullptr, nullptr, at(plan->tmp2, P), maps_at(plan, P), nullptr, 0};
+                FW_HIP(stencil_any(P, P.dev, VM_NONE, a, nullptr, s));
+            } else if (pass == 1) {
+                FW_HIP(launch_rows_fwd(P.p.nx, P.cfg.row_p, at(plan->tmp2, P), tmp, rows, P.rps, SpecLayout{}, nullptr,
+                                       plan->tw, s));
+            } else if (pass == 2) {
+                FW_HIP(spectral(plan, P, P.dev, tmp, nullptr, s));
+            } else {
+                FW_HIP(launch_rows_inv(P.p.nx, P.cfg.row_pi, EPI_APPLY, tmp, at(u, P), nullptr,
+                                       static_cast<cplx*>(Au) + P.field_off, nullptr, rows, P.rps, SpecLayout{}, nullptr,
+                                       plan->tw, s));
+            }
+            continue;
+        }
         switch (pass) {
             case 0:
                 if (P.cfg.fuse_p) {
@@ -1801,13 +1861,13 @@ fwils_status fwils_apply_pass(fwils_plan plan, int32_t pass, const void* u, void
                 break;
             case 1:   // part of pass 0 when the stencil and the rows are fused
                 if (!P.cfg.fuse_p)
-                    FW_HIP(launch_rows_fwd(P.p.nx, P.cfg.row_p, at(plan->tmp2, P), tmp, rows, 2 * P.p.nz,
+                    FW_HIP(launch_rows_fwd(P.p.nx, P.cfg.row_p, at(plan->tmp2, P), tmp, rows, P.rps,
                                            tile_rows(P.dev), nullptr, plan->tw, s));
                 break;
             case 2: FW_HIP(launch_cols(COL_GREEN, P.cfg.col, tmp, P.dev, nullptr, plan->tw, s)); break;
             default:
                 FW_HIP(launch_rows_inv(P.p.nx, P.cfg.row_pi, EPI_APPLY, tmp, at(u, P), nullptr,
-                                       static_cast<cplx*>(Au) + P.field_off, nullptr, rows, 2 * P.p.nz, tile_rows(P.dev),
+                                       static_cast<cplx*>(Au) + P.field_off, nullptr, rows, P.rps, tile_rows(P.dev),
                                        nullptr, plan->tw, s));
         }
     }
@@ -1815,7 +1875,6 @@ fwils_status fwils_apply_pass(fwils_plan plan, int32_t pass, const void* u, void
 }
 
 fwils_status fwils_time_pass(fwils_plan plan, int32_t pass, const void* u, void* Au, int32_t reps, float* us) {
-    FW_TRY(only_2d(plan, "time_pass"));
     if (!us || reps < 1 || reps > 10000) {
         set_error("time_pass: need reps 1..10000 and an output");
         return FWILS_EINVAL;
@@ -1918,6 +1977,69 @@ fwils_status fwils_time_krylov_pass(fwils_plan plan, int32_t reps, float* us) {
     if (!all_ran) {
         set_error("time_krylov_pass: a system left the running state during the timed launches");
         return FWILS_EINVAL;
+    }
+    *us = total_ms * 1e3f / (float)reps;
+    return FWILS_OK;
+}
+
+fwils_status fwils_time_gmres_pass(fwils_plan plan, int32_t kind, int32_t j, int32_t reps, float* us) {
+    FW_TRY(only_2d(plan, "time_gmres_pass"));
+    FW_TRY(check_plan(plan));
+    if (!us || reps < 1 || reps > 10000 || kind < 0 || kind > 2) {
+        set_error("time_gmres_pass: need kind 0..2, reps 1..10000 and an output");
+        return FWILS_EINVAL;
+    }
+    if (plan->krylov != FWILS_KRYLOV_GMRES || j < 0 || j >= plan->gm_m) {
+        set_error("time_gmres_pass: needs a GMRES plan and 0 <= j < restart (%d)", plan->gm_m);
+        return FWILS_EINVAL;
+    }
+    hipStream_t s = plan->stream;
+    const size_t nst = plan->total_sys;
+    SysState* orig = plan->host_pipe;   // the solver's pinned staging, idle here
+    SysState* run = plan->host_pipe + nst;
+    FW_HIP(hipMemcpyAsync(orig, plan->state, nst * sizeof(SysState), hipMemcpyDeviceToHost, s));
+    FW_HIP(hipStreamSynchronize(s));
+    for (size_t i = 0; i < nst; ++i) {
+        run[i] = orig[i];
+        run[i].status = ST_RUNNING;
+    }
+    FW_HIP(hipMemcpyAsync(plan->state, run, nst * sizeof(SysState), hipMemcpyHostToDevice, s));
+    auto launch_all = [&]() -> hipError_t {
+        for (const ProbHost& P : plan->probs) {
+            const GmArgs a = gm_args(plan, P);
+            hipError_t e;
+            if (kind == 0) {
+                e = launch_gm_update(a, j, 1, false, s);
+            } else if (kind == 1) {
+                e = launch_gm_dots(a, j, s);
+            } else {
+                const GmEpi ge{a.V, a.vstride, j + 1, a.part};
+                const int rows = P.p.nsys * P.rps;
+                e = launch_rows_inv(P.p.nx, P.cfg.row_pi, EPI_ARNOLDI, at(plan->tmp, P), a.V + (size_t)j * a.vstride,
+                                    nullptr, a.V + (size_t)(j + 1) * a.vstride, nullptr, rows, P.rps, tile_rows(P.dev),
+                                    a.st, plan->tw, s, &ge);
+            }
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    hipEvent_t e0, e1;
+    FW_HIP(hipEventCreate(&e0));
+    FW_HIP(hipEventCreate(&e1));
+    hipError_t he = launch_all();   // warm-up
+    if (he == hipSuccess) he = hipEventRecord(e0, s);
+    for (int r = 0; r < reps && he == hipSuccess; ++r) he = launch_all();
+    if (he == hipSuccess) he = hipEventRecord(e1, s);
+    if (he == hipSuccess) he = hipEventSynchronize(e1);
+    float total_ms = 0.f;
+    if (he == hipSuccess) he = hipEventElapsedTime(&total_ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (he == hipSuccess) he = hipMemcpyAsync(plan->state, orig, nst * sizeof(SysState), hipMemcpyHostToDevice, s);
+    if (he == hipSuccess) he = hipStreamSynchronize(s);
+    if (he != hipSuccess) {
+        set_error("time_gmres_pass: %s", hipGetErrorString(he));
+        return FWILS_EDEVICE;
     }
     *us = total_ms * 1e3f / (float)reps;
     return FWILS_OK;

@@ -261,6 +261,267 @@ __global__ __launch_bounds__(256) void k_stencil3(const cplx* __restrict__ u, co
     }
 }
 
+// The same stencil marching along z: a block owns a TX x TY column of cells
+// over the z range [z0, z1) of one system and walks it plane by plane.  LDS
+// holds the input (vector update applied) on three planes z, z+1, z+2 with a
+// 2-cell xy halo, and the stress s' on planes z and z+1 with a 1-cell halo;
+// the stress of plane z-1 at the thread's own cell stays in registers (only
+// the z difference of the own column needs it).  Step z: load plane z+2 into
+// the buffer of plane z-1, form the stress of plane z+1, then b on plane z.
+// Every input plane of the range is loaded once (own cells write the updated
+// vectors then), plus four halo planes per range: each input value is read
+// (TX+4)(TY+4)/(TX TY) * (z1-z0+4)/(z1-z0) times instead of the tiled kernel's
+// (TX+4)(TY+4)(TZ+4)/(TX TY TZ).
+template <int TX, int TY>
+struct March3 {
+    static constexpr int HX = TX + 4, HY = TY + 4, HP = HX * HY;   // input plane with halo 2
+    static constexpr int SX = TX + 2, SY = TY + 2, SP = SX * SY;   // stress plane with halo 1
+    static constexpr int NT = TX * TY;                             // one thread per column
+};
+
+template <int TX, int TY>
+inline size_t march3_lds() {
+    using M = March3<TX, TY>;
+    return (size_t)(3 * 3 * M::HP + 2 * 6 * M::SP) * sizeof(cplx);
+}
+
+template <int VM, bool GEN, int TX, int TY>
+__global__ __launch_bounds__(TX * TY) void k_stencil3z(const cplx* __restrict__ u, const cplx* __restrict__ a1,
+                                                       const cplx* __restrict__ a2, cplx* __restrict__ wout,
+                                                       cplx* __restrict__ b, const real* __restrict__ maps,
+                                                       ProbDev3 pd, int ZC, SysState* __restrict__ st,
+                                                       const double* __restrict__ part, int np,
+                                                       cplx* __restrict__ rhat, const cplx* __restrict__ a3,
+                                                       cplx* __restrict__ xio, cplx* __restrict__ rout) {
+    using M = March3<TX, TY>;
+    constexpr int NT = M::NT;
+    static_assert(NT == 256, "the FP64 record sums of the Krylov scalars read with 256 threads");
+    constexpr int NS = Params3<GEN>::NS;
+    extern __shared__ __align__(16) unsigned char lds3[];
+    cplx* su = reinterpret_cast<cplx*>(lds3);   // [3 planes][3 comps][HP]
+    cplx* ss = su + 9 * M::HP;                  // [2 planes][6][SP]
+    __shared__ double red[4 * kPartialNV];
+    __shared__ int s_status;
+
+    const int nx = pd.nx, ny = pd.ny, nz = pd.nz;
+    const size_t cells = (size_t)nx * ny * nz;
+    const int ntx = (nx + TX - 1) / TX, nty = (ny + TY - 1) / TY, nzc = (nz + ZC - 1) / ZC;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int sys = blk % pd.nsys;                 // neighbouring blocks: the same column, other systems
+    const int col = blk / pd.nsys;
+    const int x0 = (col % ntx) * TX, y0 = ((col / ntx) % nty) * TY, z0 = (col / (ntx * nty)) * ZC;
+    const int z1 = min(z0 + ZC, nz);
+    (void)nzc;
+    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+    const bool own_xy = x0 + tx < nx && y0 + ty < ny;
+
+    if (st != nullptr) {
+        if (threadIdx.x == 0) s_status = st[sys].status;
+        __syncthreads();
+        const int stw = s_status;
+        __syncthreads();
+        if constexpr (VM == VM_PX) {
+            if (!closing_enters(stw, kStampPx)) return;
+        } else {
+            if (stw != ST_RUNNING) {
+                if (VM == VM_S && st_tag(stw) != 0 && col == 0 && threadIdx.x == 0) st[sys].status = st_code(stw);
+                return;
+            }
+        }
+    }
+    cplx c1 = mkc(0.f, 0.f), c2 = mkc(0.f, 0.f), c3 = mkc(0.f, 0.f);
+    bool fresh = false;
+    int step = SS_FULL;
+    if constexpr (VM != VM_NONE) {
+        step = stencil_scalars<VM>(st, sys, part, np, red, col == 0 && threadIdx.x == 0, c1, c2, c3, fresh);
+        if (step == SS_SKIP) return;
+    }
+    const size_t so = (size_t)sys * 3 * cells;
+    auto gidx = [&](int x, int y, int z) -> size_t {
+        return ((size_t)wrapm(z, nz) * ny + wrapm(y, ny)) * nx + wrapm(x, nx);
+    };
+    auto close_iteration = [&](size_t gi) {
+        const cplx sv = u[so + gi], tv = a3[so + gi], pv = a1[so + gi];
+        const cplx rv = close_r(sv, tv, c2);
+        rout[so + gi] = rv;
+        xio[so + gi] = close_x(xio[so + gi], pv, sv, c3, c2);
+        if (fresh) rhat[so + gi] = rv;
+    };
+    if constexpr (VM == VM_PX) {
+        if (step == SS_XONLY) {   // stopped: the last solution update only
+            if (own_xy)
+                for (int z = z0; z < z1; ++z) {
+                    const size_t g = gidx(x0 + tx, y0 + ty, z);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) close_iteration(c * cells + g);
+                }
+            return;
+        }
+    }
+    auto field = [&](size_t gi) -> cplx {
+        if constexpr (VM == VM_NONE) {
+            return u[so + gi];
+        } else if constexpr (VM == VM_P) {
+            const cplx rv = u[so + gi];
+            if (fresh) return rv;
+            return cadd(rv, cmul(c1, csub(a1[so + gi], cmul(c2, a2[so + gi]))));
+        } else if constexpr (VM == VM_PX) {
+            const cplx rv = close_r(u[so + gi], a3[so + gi], c2);
+            if (fresh) return rv;
+            return cadd(rv, cmul(c1, csub(a1[so + gi], cmul(c2, a2[so + gi]))));
+        } else {
+            return csub(u[so + gi], cmul(c1, a1[so + gi]));
+        }
+    };
+    // input plane z (with the 2-cell xy halo) into buffer k; own cells of the
+    // range write the updated vectors
+    auto load_plane = [&](int k, int z) {
+        const bool own_z = z >= z0 && z < z1;
+        cplx* dst = su + k * 3 * M::HP;
+        for (int h = threadIdx.x; h < M::HP; h += NT) {
+            const int hx = h % M::HX, hy = h / M::HX;
+            const size_t g = gidx(x0 - 2 + hx, y0 - 2 + hy, z);
+            const bool own = own_z && hx >= 2 && hx < TX + 2 && hy >= 2 && hy < TY + 2 && x0 + hx - 2 < nx &&
+                             y0 + hy - 2 < ny;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const size_t gi = c * cells + g;
+                const cplx f = field(gi);
+                dst[c * M::HP + h] = f;
+                if constexpr (VM != VM_NONE) {
+                    if (own) {
+                        wout[so + gi] = f;
+                        if constexpr (VM == VM_P) {
+                            if (fresh) rhat[so + gi] = f;
+                        } else if constexpr (VM == VM_PX) {
+                            close_iteration(gi);
+                        }
+                    }
+                }
+            }
+        }
+    };
+    // raw strain at input-buffer position h of plane `mid` (z differences
+    // from planes lo and hi), then the stress s' = dC e'
+    auto stress_at = [&](const cplx* lo, const cplx* mid, const cplx* hi, int h, const real* mp, size_t mstride,
+                         cplx (&sg)[6]) {
+        cplx d[3][3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const cplx* w = mid + c * M::HP + h;
+            d[c][0] = csub(w[1], w[-1]);
+            d[c][1] = csub(w[M::HX], w[-M::HX]);
+            d[c][2] = csub(hi[c * M::HP + h], lo[c * M::HP + h]);
+        }
+        const cplx e[6] = {d[0][0], d[1][1], d[2][2], cadd(d[1][2], d[2][1]), cadd(d[0][2], d[2][0]),
+                           cadd(d[0][1], d[1][0])};
+        real m[NS];
+#pragma unroll
+        for (int p = 0; p < NS; ++p) m[p] = mp[p * mstride];
+        stress3<GEN>(m, 1, e, sg);
+    };
+    // stress of plane z (buffers lo = z-1, mid = z, hi = z+1) into stress buffer j
+    auto stress_plane = [&](int j, const cplx* lo, const cplx* mid, const cplx* hi, int z) {
+        cplx* dst = ss + j * 6 * M::SP;
+        for (int q = threadIdx.x; q < M::SP; q += NT) {
+            const int sx = q % M::SX, sy = q / M::SX;
+            const int h = (sy + 1) * M::HX + sx + 1;
+            cplx sg[6];
+            stress_at(lo, mid, hi, h, maps + gidx(x0 - 1 + sx, y0 - 1 + sy, z), cells, sg);
+#pragma unroll
+            for (int i = 0; i < 6; ++i) dst[i * M::SP + q] = sg[i];
+        }
+    };
+
+    // prologue: input planes z0-1, z0, z0+1; the own column's stress of plane
+    // z0-1 (its z difference reads the own cell of plane z0-2 directly); the
+    // stress plane z0
+    int kb[3] = {0, 1, 2};   // buffers of planes z-1, z, z+1 (then z, z+1, z+2)
+    load_plane(kb[0], z0 - 1);
+    load_plane(kb[1], z0);
+    load_plane(kb[2], z0 + 1);
+    __syncthreads();
+    const int hown = (ty + 2) * M::HX + tx + 2;
+    const int qown = (ty + 1) * M::SX + tx + 1;
+    cplx sprev[6];
+    {
+        const size_t g = gidx(x0 + tx, y0 + ty, z0 - 2);   // the own cell of plane z0-2
+        cplx below[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) below[c] = field(c * cells + g);
+        cplx d[3][3];
+        const cplx* mid = su + kb[0] * 3 * M::HP;
+        const cplx* hi = su + kb[1] * 3 * M::HP;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const cplx* w = mid + c * M::HP + hown;
+            d[c][0] = csub(w[1], w[-1]);
+            d[c][1] = csub(w[M::HX], w[-M::HX]);
+            d[c][2] = csub(hi[c * M::HP + hown], below[c]);
+        }
+        const cplx e[6] = {d[0][0], d[1][1], d[2][2], cadd(d[1][2], d[2][1]), cadd(d[0][2], d[2][0]),
+                           cadd(d[0][1], d[1][0])};
+        real m[NS];
+        const real* mp = maps + gidx(x0 + tx, y0 + ty, z0 - 1);
+#pragma unroll
+        for (int p = 0; p < NS; ++p) m[p] = mp[p * cells];
+        stress3<GEN>(m, 1, e, sprev);
+    }
+    int jc = 0;   // stress buffer of the current plane
+    stress_plane(jc, su + kb[0] * 3 * M::HP, su + kb[1] * 3 * M::HP, su + kb[2] * 3 * M::HP, z0);
+    __syncthreads();
+    // now kb = {z0-1, z0, z0+1}: rotate so that kb = {z, z+1, (free)}
+    const real sc = pd.inv4dx2;
+    for (int z = z0; z < z1; ++z) {
+        // buffers: kb[1] = plane z, kb[2] = plane z+1, kb[0] = plane z-1 (free now)
+        load_plane(kb[0], z + 2);
+        __syncthreads();
+        const cplx* pz = su + kb[1] * 3 * M::HP;
+        const cplx* pz1 = su + kb[2] * 3 * M::HP;
+        const cplx* pz2 = su + kb[0] * 3 * M::HP;
+        stress_plane(1 - jc, pz, pz1, pz2, z + 1);
+        __syncthreads();
+        const cplx* cur = ss + jc * 6 * M::SP;
+        const cplx* nxt = ss + (1 - jc) * 6 * M::SP;
+        if (own_xy) {
+            auto dxy = [&](int i, int off) { return csub(cur[i * M::SP + qown + off], cur[i * M::SP + qown - off]); };
+            auto dz = [&](int i) { return csub(nxt[i * M::SP + qown], sprev[i]); };
+            const cplx bx = cadd(cadd(dxy(0, 1), dxy(5, M::SX)), dz(4));
+            const cplx by = cadd(cadd(dxy(5, 1), dxy(1, M::SX)), dz(3));
+            const cplx bz = cadd(cadd(dxy(4, 1), dxy(3, M::SX)), dz(2));
+            const size_t g = gidx(x0 + tx, y0 + ty, z);
+            const cplx wr = cscale(pd.w2, maps[(size_t)NS * cells + g]);
+            b[so + g] = cadd(cmul(wr, pz[hown]), cscale(bx, sc));
+            b[so + g + cells] = cadd(cmul(wr, pz[M::HP + hown]), cscale(by, sc));
+            b[so + g + 2 * cells] = cadd(cmul(wr, pz[2 * M::HP + hown]), cscale(bz, sc));
+#pragma unroll
+            for (int i = 0; i < 6; ++i) sprev[i] = cur[i * M::SP + qown];
+        }
+        __syncthreads();   // plane z and stress plane z are read: their buffers are free
+        const int k0 = kb[0];
+        kb[0] = kb[1];
+        kb[1] = kb[2];
+        kb[2] = k0;
+        jc = 1 - jc;
+    }
+}
+
+template <int VM, bool GEN, int TX, int TY>
+static hipError_t stencil3z_launch(const StencilArgs& a, const ProbDev3& pd, SysState* st, hipStream_t s) {
+    const int ntx = (pd.nx + TX - 1) / TX, nty = (pd.ny + TY - 1) / TY;
+    // z ranges of at most 32 planes, more of them while the launch is small
+    int ZC = std::min(pd.nz, 32);
+    while (ZC > 8 && (long long)ntx * nty * ((pd.nz + ZC - 1) / ZC) * pd.nsys < 4096) ZC /= 2;
+    const long long blocks = (long long)ntx * nty * ((pd.nz + ZC - 1) / ZC) * pd.nsys;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    const size_t lds = march3_lds<TX, TY>();
+    hipError_t e = allow_lds(k_stencil3z<VM, GEN, TX, TY>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_stencil3z<VM, GEN, TX, TY>), dim3((unsigned)blocks), dim3(TX * TY), lds, s, a.u, a.a1,
+                       a.a2, a.wout, a.b, a.maps, pd, ZC, st, a.part, a.np, a.rhat, a.a3, a.xio, a.rout);
+    return hipGetLastError();
+}
+
 // Tile of the build: 8 x 8 x 4 cells (complex64), 4 x 4 x 4 (complex128,
 // twice the bytes per value).
 #ifdef FW_C128
@@ -284,12 +545,30 @@ static hipError_t stencil3_launch(const StencilArgs& a, const ProbDev3& pd, SysS
     return hipGetLastError();
 }
 
+// Column shape of the z-marching stencil (256 threads): 16 x 16 or 32 x 8
+// cells, whichever overhangs the grid less; 0 for grids thinner than 8 cells
+// in y, which take the tiled kernel.
+static int march_shape(int nx, int ny) {
+    if (ny < 8 || nx < 16) return 0;
+    const long long a = (long long)((nx + 15) / 16) * 16 * ((ny + 15) / 16) * 16;
+    const long long b = (long long)((nx + 31) / 32) * 32 * ((ny + 7) / 8) * 8;
+    return a <= b ? 16 : 32;
+}
+
+template <int VM, bool GEN>
+static hipError_t stencil3_any(const StencilArgs& a, const ProbDev3& pd, SysState* st, hipStream_t s) {
+    const int m = march_shape(pd.nx, pd.ny);
+    if (m == 16) return stencil3z_launch<VM, GEN, 16, 16>(a, pd, st, s);
+    if (m == 32) return stencil3z_launch<VM, GEN, 32, 8>(a, pd, st, s);
+    return stencil3_launch<VM, GEN>(a, pd, st, s);
+}
+
 template <bool GEN>
 static hipError_t stencil3_vm(int vm, const StencilArgs& a, const ProbDev3& pd, SysState* st, hipStream_t s) {
-    if (vm == VM_NONE) return stencil3_launch<VM_NONE, GEN>(a, pd, st, s);
-    if (vm == VM_P) return stencil3_launch<VM_P, GEN>(a, pd, st, s);
-    if (vm == VM_PX) return stencil3_launch<VM_PX, GEN>(a, pd, st, s);
-    return stencil3_launch<VM_S, GEN>(a, pd, st, s);
+    if (vm == VM_NONE) return stencil3_any<VM_NONE, GEN>(a, pd, st, s);
+    if (vm == VM_P) return stencil3_any<VM_P, GEN>(a, pd, st, s);
+    if (vm == VM_PX) return stencil3_any<VM_PX, GEN>(a, pd, st, s);
+    return stencil3_any<VM_S, GEN>(a, pd, st, s);
 }
 
 hipError_t launch_stencil3(int vm, const StencilArgs& a, const ProbDev3& pd, SysState* st, hipStream_t s) {

@@ -1,6 +1,6 @@
 // Model-map kernels of the generalised Tikhonov step (eqs. obj, norm):
-// relative maps q [5][nz][nx] (fp32), dm = m0 q, the periodic 5-point
-// Laplacian, the combination of J* output into gradient / normal-operator
+// relative maps q [nmaps][cells] (five 2-D maps, six or 22 3-D ones; the
+// plan's real type), dm = m0 q, the periodic 5- or 7-point Laplacian, the combination of J* output into gradient / normal-operator
 // maps, FP64 inner products and the CG updates with device-resident scalars;
 // the data residual and background update of the distorted-Born loop.
 #include "launch.h"
@@ -17,28 +17,35 @@ __global__ void k_map_scale(const real* __restrict__ q, real* __restrict__ out, 
 }
 
 hipError_t launch_map_scale(const real* q, real* out, const MapScales& m0, int n, hipStream_t s) {
-    hipLaunchKernelGGL(k_map_scale, dim3((n + kMapThreads - 1) / kMapThreads, 5), dim3(kMapThreads), 0, s,
+    hipLaunchKernelGGL(k_map_scale, dim3((n + kMapThreads - 1) / kMapThreads, m0.n), dim3(kMapThreads), 0, s,
                        q, out, m0, n);
     return hipGetLastError();
 }
 
-// Periodic, unscaled 5-point Laplacian of nmaps maps [nmaps][nz][nx].
-__global__ void k_laplacian(const real* __restrict__ q, real* __restrict__ out, int nx, int nz) {
+// Periodic, unscaled Laplacian of nmaps maps [nmaps][nz][ny][nx]: the
+// 5-point stencil in x-z for ny = 1 (2-D maps), the 7-point one otherwise.
+__global__ void k_laplacian(const real* __restrict__ q, real* __restrict__ out, int nx, int ny, int nz) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int p = blockIdx.y;
-    if (i >= nx * nz) return;
-    const int z = i / nx, x = i - z * nx;
-    const real* a = q + (size_t)p * nx * nz;
+    const int n = nx * ny * nz;
+    if (i >= n) return;
+    const int x = i % nx, y = (i / nx) % ny, z = i / (nx * ny);
+    const real* a = q + (size_t)p * n;
     const int xp = x + 1 == nx ? 0 : x + 1, xm = x == 0 ? nx - 1 : x - 1;
     const int zp = z + 1 == nz ? 0 : z + 1, zm = z == 0 ? nz - 1 : z - 1;
-    out[(size_t)p * nx * nz + i] = a[z * nx + xp] + a[z * nx + xm] + a[zp * nx + x] + a[zm * nx + x] -
-                                   4.0f * a[i];
+    const int row = nx * ny;
+    real v = a[i - x + xp] + a[i - x + xm] + a[zp * row + y * nx + x] + a[zm * row + y * nx + x] - 4.0f * a[i];
+    if (ny > 1) {
+        const int yp = y + 1 == ny ? 0 : y + 1, ym = y == 0 ? ny - 1 : y - 1;
+        v += a[z * row + yp * nx + x] + a[z * row + ym * nx + x] - 2.0f * a[i];
+    }
+    out[(size_t)p * n + i] = v;
 }
 
-hipError_t launch_laplacian(const real* q, real* out, int nx, int nz, int nmaps, hipStream_t s) {
-    const int n = nx * nz;
+hipError_t launch_laplacian(const real* q, real* out, int nx, int ny, int nz, int nmaps, hipStream_t s) {
+    const int n = nx * ny * nz;
     hipLaunchKernelGGL(k_laplacian, dim3((n + kMapThreads - 1) / kMapThreads, nmaps), dim3(kMapThreads), 0,
-                       s, q, out, nx, nz);
+                       s, q, out, nx, ny, nz);
     return hipGetLastError();
 }
 
@@ -56,7 +63,7 @@ __global__ void k_map_combine(const double2* __restrict__ g, const real* __restr
 
 hipError_t launch_map_combine(const double2* g, const real* reg, real* out, const MapScales& m0,
                               double cj, double cl, int n, hipStream_t s) {
-    hipLaunchKernelGGL(k_map_combine, dim3((n + kMapThreads - 1) / kMapThreads, 5), dim3(kMapThreads), 0, s,
+    hipLaunchKernelGGL(k_map_combine, dim3((n + kMapThreads - 1) / kMapThreads, m0.n), dim3(kMapThreads), 0, s,
                        g, reg, out, m0, cj, cl, n);
     return hipGetLastError();
 }
@@ -200,7 +207,7 @@ __global__ void k_map_update(real* __restrict__ maps, const real* __restrict__ q
 }
 
 hipError_t launch_map_update(real* maps, const real* q, const MapScales& m0, int n, hipStream_t s) {
-    hipLaunchKernelGGL(k_map_update, dim3((n + kMapThreads - 1) / kMapThreads, 5), dim3(kMapThreads), 0, s,
+    hipLaunchKernelGGL(k_map_update, dim3((n + kMapThreads - 1) / kMapThreads, m0.n), dim3(kMapThreads), 0, s,
                        maps, q, m0, n);
     return hipGetLastError();
 }

@@ -255,9 +255,9 @@ hipError_t launch_diff(const cplx* a, const cplx* b, cplx* out, size_t n, hipStr
 hipError_t launch_zero(cplx* dst, size_t n, hipStream_t s);
 
 // Tikhonov-step model maps (5 maps of one grid).
-struct MapScales { double s[5]; };
+struct MapScales { double s[22]; int n; };   // per-map scales m0 and the map count
 hipError_t launch_map_scale(const real* q, real* out, const MapScales& m0, int n, hipStream_t s);
-hipError_t launch_laplacian(const real* q, real* out, int nx, int nz, int nmaps, hipStream_t s);
+hipError_t launch_laplacian(const real* q, real* out, int nx, int ny, int nz, int nmaps, hipStream_t s);
 hipError_t launch_map_combine(const double2* g, const real* reg, real* out, const MapScales& m0,
                               double cj, double cl, int n, hipStream_t s);
 constexpr int kDotPartials = 512;

@@ -50,6 +50,8 @@ def _require_cuda(t, dtype, name):
 class Plan:
     """One or more (grid, frequency) problems solved together."""
 
+    CSTRIDE = 2   # ints per source / receiver cell, doubles per force
+
     def __init__(self, problems, device="cuda", precision="c64"):
         self.lib = _lib.load()
         if precision not in PRECISIONS:
@@ -320,6 +322,17 @@ class Plan:
         check(self.lib.fwils_time_krylov_pass(self._h, int(reps), ctypes.byref(us)), "fwils_time_krylov_pass")
         return us.value
 
+    GMRES_KINDS = {"update": 0, "dots": 1, "projections": 2}
+
+    def time_gmres_pass(self, kind, j, reps=20):
+        """Average duration (us) of one Arnoldi-step kernel ('update', 'dots' or
+        'projections') at step j with every system running (GMRES plans)."""
+        us = ctypes.c_float()
+        self._bind_stream()
+        check(self.lib.fwils_time_gmres_pass(self._h, self.GMRES_KINDS[kind], int(j), int(reps), ctypes.byref(us)),
+              "fwils_time_gmres_pass")
+        return us.value
+
     def solve_stats(self):
         """(iters, recursive relres) of the last Krylov solve, per system."""
         it = np.zeros(self.total_sys, dtype=np.int32)
@@ -341,16 +354,19 @@ class Plan:
     # ------------------------------------------------- Tikhonov step ----
     REGS = {"identity": _lib.FWILS_REG_IDENTITY, "laplacian": _lib.FWILS_REG_LAPLACIAN}
 
-    def _maps(self, q, name):
+    def _qshape(self):
+        """Shape of the model maps of the Tikhonov step (the first problem's)."""
         p = self.problems[0]
+        return (5, p["nz"], p["nx"])
+
+    def _maps(self, q, name):
         _require_cuda(q, self.rdtype, name)
-        if tuple(q.shape) != (5, p["nz"], p["nx"]):
-            raise ValueError(f"{name} must be [5, {p['nz']}, {p['nx']}]")
+        if tuple(q.shape) != self._qshape():
+            raise ValueError(f"{name} must be {list(self._qshape())}")
         return q
 
-    @staticmethod
-    def _m0(m0):
-        a = np.ascontiguousarray(np.asarray(m0, dtype=np.float64).reshape(5))
+    def _m0(self, m0):
+        a = np.ascontiguousarray(np.asarray(m0, dtype=np.float64).reshape(self._qshape()[0]))
         return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
     def _data(self, r, name):
@@ -377,7 +393,7 @@ class Plan:
         self._data(r, "r")
         m, mp = self._m0(m0)
         p = self.problems[0]
-        gq = torch.zeros(5, p["nz"], p["nx"], dtype=self.rdtype, device=self.device)
+        gq = torch.zeros(self._qshape(), dtype=self.rdtype, device=self.device)
         self._bind_stream()
         st = self.lib.fwils_adjoint_rel(self._h, _ptr(ub), _ptr(r), mp, _ptr(gq), float(rtol), int(maxit))
         if st != _lib.FWILS_OK:
@@ -427,7 +443,7 @@ class Plan:
         self._data(r, "r")
         m, mp = self._m0(m0)
         p = self.problems[0]
-        q = torch.empty(5, p["nz"], p["nx"], dtype=self.rdtype, device=self.device)
+        q = torch.empty(self._qshape(), dtype=self.rdtype, device=self.device)
         d = torch.empty_like(r)
         hist = np.zeros(niter + 1, dtype=np.float64)
         self._bind_stream()
@@ -437,6 +453,26 @@ class Plan:
         if st != _lib.FWILS_OK:
             check(st, "fwils_normal_cg")
         return q, hist
+
+    def normal_cg_steps(self, ub, r, m0, first, niter, lam=1e-3, reg="identity", rtol=1e-6, maxit=1000):
+        """niter CG iterations on the normal equation, from q = 0 (first = 0) or
+        continuing the plan's run of `first` iterations: (q, history of the
+        residual norm from iteration `first` on, iterates [niter, 5, nz, nx])."""
+        self._field(ub, "ub")
+        self._data(r, "r")
+        m, mp = self._m0(m0)
+        p = self.problems[0]
+        q = torch.empty(self._qshape(), dtype=self.rdtype, device=self.device)
+        qi = torch.empty((niter,) + self._qshape(), dtype=self.rdtype, device=self.device)
+        d = torch.empty_like(r)
+        hist = np.zeros(niter + 1, dtype=np.float64)
+        self._bind_stream()
+        st = self.lib.fwils_normal_cg_steps(self._h, _ptr(ub), _ptr(r), mp, float(lam), self.REGS[reg], int(first),
+                                            int(niter), _ptr(q), hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                            _ptr(qi), _ptr(d), float(rtol), int(maxit))
+        if st != _lib.FWILS_OK:
+            check(st, "fwils_normal_cg_steps")
+        return q, hist, qi
 
     def receiver_data(self, u, out=None):
         """d = R u: the fields sampled at every problem's receivers (plan data layout)."""
@@ -463,8 +499,8 @@ class Plan:
         error history eps_d, the cooled lambdas, the number of updates, the
         final background fields ub, their residual r, the last update q and
         the status of the worst solve."""
-        s = np.ascontiguousarray(np.asarray(src_ixz, dtype=np.int32).reshape(-1, 2))
-        f = np.ascontiguousarray(np.asarray(src_f, dtype=np.float64).reshape(-1, 2))
+        s = np.ascontiguousarray(np.asarray(src_ixz, dtype=np.int32).reshape(-1, self.CSTRIDE))
+        f = np.ascontiguousarray(np.asarray(src_f, dtype=np.float64).reshape(-1, self.CSTRIDE))
         if s.shape[0] != self.total_sys or f.shape[0] != self.total_sys:
             raise ValueError(f"need {self.total_sys} sources and forces")
         self._data(d_obs, "d_obs")
@@ -473,7 +509,7 @@ class Plan:
         ub = self.new_field()
         r = torch.empty_like(d_obs)
         d = torch.empty_like(d_obs)
-        q = torch.zeros(5, p["nz"], p["nx"], dtype=self.rdtype, device=self.device)
+        q = torch.zeros(self._qshape(), dtype=self.rdtype, device=self.device)
         eps = np.full(max_outer + 1, np.nan)
         lam = np.full(max(max_outer, 1), np.nan)
         upd = ctypes.c_int32(0)
@@ -577,6 +613,7 @@ class Plan3(Plan):
 
     PARAMS = {"vti": _lib.FWILS_PARAMS_VTI, "general": _lib.FWILS_PARAMS_GENERAL}
     NMAPS = {"vti": 6, "general": 22}
+    CSTRIDE = 3
 
     def __init__(self, problems, device="cuda", precision="c64"):
         self.lib = _lib.load()
@@ -626,6 +663,9 @@ class Plan3(Plan):
     def _map_shape(self, i):
         p = self.problems[i]
         return (self.nmaps(i), p["nz"], p["ny"], p["nx"])
+
+    def _qshape(self):
+        return self._map_shape(0)
 
     def set_contrast(self, i, maps):
         m = torch.as_tensor(maps, dtype=self.rdtype).to(self.device).contiguous()

@@ -194,3 +194,64 @@ def test_hess3d_grid_sampled_against_oracle():
         err = _rel(u[k], uref[0])
         print(f"  system {k}: iters {res.iters[k]}, field error {err:.2e}", flush=True)
         assert err < FIELD_TOL
+
+
+def test_tikhonov_normal_cg_and_dbi_update_3d():
+    """3-D VTI plan of two frequencies on one grid: the Tikhonov objective and
+    gradient with the 7-point Laplacian, three normal-equation CG iterations
+    (L = I) and one distorted-Born update from the homogeneous background,
+    each against the oracle (eqs. obj, norm and the DBI loop)."""
+    from oracle import dbi, tikhonov
+    from paper_2402_02116_amd.plan import Plan3
+    nx, ny, nz, dx = 16, 16, 16, 10.0
+    c21, rho = W.vti3d_background(gamma=0.1)
+    m0 = W.vti3d_scales(gamma=0.1)
+    maps = W.round_f32(W.contrast3(21, nz, ny, nx, m0, std=0.05))
+    freqs, ns = (6.0, 9.0), 2
+    src, f = [(4, 5, 0), (11, 10, 0)], [(0.0, 0.0, 1.0), (0.0, 0.5, 0.8)]
+    rec = W.surface_grid(nx, ny, 4, 4, iz=1)
+    probs = [dict(nx=nx, ny=ny, nz=nz, dx=dx, c0=c21, rho0=rho, freq_hz=fr, eta=0.02, nsys=ns, params="vti")
+             for fr in freqs]
+    plan = Plan3(probs)
+    for i in range(2):
+        plan.set_contrast(i, maps)
+        plan.set_receivers(i, rec)
+    ub = plan.solve(plan.incident(src * 2, f * 2), rtol=1e-7, maxit=800).x
+    items = []
+    for fr in freqs:
+        P = E3.LSProblem3D(nx, ny, nz, dx, c21, rho, fr, 0.02, maps=maps, params="vti")
+        items.append((P, P.solve(P.incident(src, f), tol=1e-12)[0], rec))
+    rng = np.random.default_rng(22)
+    r_np = [W.round_f32(rng.standard_normal((ns, len(rec), 3)) + 1j * rng.standard_normal((ns, len(rec), 3)))
+            for _ in freqs]
+    r = torch.as_tensor(np.concatenate([x.ravel() for x in r_np]).astype(np.complex64)).cuda()
+    q = W.round_f32(W.contrast3(23, nz, ny, nx, np.ones((6, 1, 1, 1)), std=0.02))
+    qt = torch.as_tensor(q, dtype=torch.float32).cuda()
+    m0v = m0.ravel()
+    T = tikhonov.Tikhonov(items, m0, r_np, lam=1e-3, reg="laplacian", tol=1e-12)
+    fval, g = plan.tikhonov_grad(ub, r, m0v, qt, lam=1e-3, reg="laplacian", rtol=1e-7)
+    e_g = _rel(g.double().cpu().numpy(), T.gradient(q))
+    e_f = abs(fval - T.objective(q)) / abs(T.objective(q))
+    Ti = tikhonov.Tikhonov(items, m0, r_np, lam=1e-3, reg="identity", tol=1e-12)
+    qo, ho = Ti.solve_cg(3)
+    qc, hc = plan.normal_cg(ub, r, m0v, niter=3, lam=1e-3, reg="identity", rtol=1e-7)
+    e_q = _rel(qc.double().cpu().numpy(), qo)
+    e_h = _rel(hc, np.array(ho))
+    print(f"3-D Tikhonov: objective {e_f:.2e}, gradient {e_g:.2e}; CG q {e_q:.2e}, history {e_h:.2e}", flush=True)
+    assert e_f < 1e-5 and e_g < 1e-4 and e_q < 1e-4 and e_h < 1e-4
+    # one distorted-Born update from the homogeneous background towards `maps`
+    d_obs = [E3.sample_3d(ub_ref, rec) for (_, ub_ref, _) in items]
+    pd = Plan3(probs)
+    for i in range(2):
+        pd.set_receivers(i, rec)
+    d_t = torch.as_tensor(np.concatenate([W.round_f32(x).ravel() for x in d_obs]).astype(np.complex64)).cuda()
+    out = pd.dbi_run(src * 2, f * 2, d_t, m0v, lam0=1.0, niter=3, tol=0.0, max_outer=1, rtol=1e-7, maxit=800)
+    zero = np.zeros_like(maps)
+    its = [(E3.LSProblem3D(nx, ny, nz, dx, c21, rho, fr, 0.02, params="vti"), src, f, rec, W.round_f32(d))
+           for fr, d in zip(freqs, d_obs)]
+    c1, eps, _, _ = dbi.dbi_stage(its, zero, m0v, 1.0, 3, tol=0.0, max_outer=1, solve_tol=1e-12)
+    step = pd.get_contrast(0).double().cpu().numpy()
+    e_c = _rel(step, c1)
+    e_e = _rel(np.array(out["eps"]), np.array(eps))
+    print(f"3-D DBI update: eps {out['eps']} vs {eps}; model step {e_c:.2e}", flush=True)
+    assert out["updates"] == 1 and e_c < 1e-3 and e_e < 1e-4

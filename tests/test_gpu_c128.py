@@ -214,4 +214,5 @@ def test_c64_normal_cg_against_c128_gpu_run():
     print(f"normal CG after {niter} steps: c128 vs oracle {e128:.2e}; c64 vs c128: N q {e_op:.2e}, "
           f"q {e_q:.2e}, residual history {e_h:.2e}", flush=True)
     assert e_op < 1e-5
-    assert e_q < 1e-3 and e_h < 1e-3
+    # measured 2.0e-6 (q) and 2.5e-7 (history) after 3 steps
+    assert e_q < 2e-5 and e_h < 5e-6

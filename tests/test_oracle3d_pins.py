@@ -323,3 +323,17 @@ def test_periodic_green_matches_appendix_a_3d():
     ref = np.einsum("ijn,j->in", Ga, fvec)
     err = np.linalg.norm(col[:, sel] - ref) / np.linalg.norm(ref)
     assert err < 5e-2, err
+
+
+def test_laplacian3_plane_wave_eigenvalues():
+    """The periodic 7-point Laplacian maps exp(i k.n) to (sum_a 2 cos(k_a) - 6)
+    exp(i k.n), its discrete eigenvalue, for every map and wavevector."""
+    from oracle import tikhonov
+    nz, ny, nx = 6, 5, 8
+    Z, Y, X = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    for kx, ky, kz in ((1, 0, 0), (3, 2, 1), (4, 4, 5)):
+        a = (2 * np.pi * kx / nx, 2 * np.pi * ky / ny, 2 * np.pi * kz / nz)
+        w = np.exp(1j * (a[0] * X + a[1] * Y + a[2] * Z))
+        q = np.array([w, 2 * w])
+        lam = 2 * np.cos(a[0]) + 2 * np.cos(a[1]) + 2 * np.cos(a[2]) - 6
+        assert np.allclose(tikhonov.laplacian3(q), lam * q, atol=1e-12)
