@@ -658,7 +658,7 @@ def _oracle_step(c, rec, dm, r, nsample):
 def cpu_baseline(c, rec, dm, r, nsample):
     """The oracle on the host cores, on `nsample` of the systems of one step,
     with its scipy.fft workers (at most 16, one GPU's share of the box), and
-    again on one system with one thread (scipy.fft workers and BLAS)."""
+    again on two systems with one thread (scipy.fft workers and BLAS)."""
     from threadpoolctl import threadpool_limits
     from oracle import operators
     mv, dt = _oracle_step(c, rec, dm, r, nsample)
@@ -666,7 +666,7 @@ def cpu_baseline(c, rec, dm, r, nsample):
     try:
         operators._WORKERS = 1
         with threadpool_limits(limits=1):
-            mv1, dt1 = _oracle_step(c, rec, dm, r, 1)
+            mv1, dt1 = _oracle_step(c, rec, dm, r, 2)
     finally:
         operators._WORKERS = saved
     cells = c["nx"] * c["nz"]
@@ -675,7 +675,7 @@ def cpu_baseline(c, rec, dm, r, nsample):
                 sample=f"{nsample} of the {c['nsys']} systems through the whole step (incident, solve, "
                        f"J, J*), complex128 numpy/scipy, {mv} matvecs in {dt:.1f} s",
                 one_core=dict(value=mv1 * cells / dt1 / 1e9, unit="GPoints/s", cores=1,
-                              sample=f"1 system through the whole step, one thread, {mv1} matvecs in {dt1:.1f} s"))
+                              sample=f"2 systems through the whole step, one thread, {mv1} matvecs in {dt1:.1f} s"))
 
 
 def oracle_matvec_seconds(nx, nz, dx, c0, rho0, freq_hz, maps, reps=2):
@@ -807,7 +807,7 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--reps", type=int, default=50, help="launches per kernel timing")
-    ap.add_argument("--cpu-sample", type=int, default=4, help="systems in the CPU oracle sample")
+    ap.add_argument("--cpu-sample", type=int, default=12, help="systems in the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the built-in kernel variants")
     ap.add_argument("--krylov", choices=["auto", "bicgstab", "gmres"], default="auto",
