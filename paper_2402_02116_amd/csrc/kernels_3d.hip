@@ -262,28 +262,59 @@ __global__ __launch_bounds__(256) void k_stencil3(const cplx* __restrict__ u, co
 }
 
 // The same stencil marching along z: a block owns a TX x TY column of cells
-// over the z range [z0, z1) of one system and walks it plane by plane.  LDS
-// holds the input (vector update applied) on three planes z, z+1, z+2 with a
-// 2-cell xy halo, and the stress s' on planes z and z+1 with a 1-cell halo;
-// the stress of plane z-1 at the thread's own cell stays in registers (only
-// the z difference of the own column needs it).  Step z: load plane z+2 into
-// the buffer of plane z-1, form the stress of plane z+1, then b on plane z.
-// Every input plane of the range is loaded once (own cells write the updated
-// vectors then), plus four halo planes per range: each input value is read
-// (TX+4)(TY+4)/(TX TY) * (z1-z0+4)/(z1-z0) times instead of the tiled kernel's
-// (TX+4)(TY+4)(TZ+4)/(TX TY TZ).
+// over the z range [z0, z1) of one system and walks it plane by plane.  Each
+// thread owns one cell of the column (p0) and, for the first RING threads,
+// one cell of the 2-cell xy halo ring around it (p1), and keeps the input
+// (vector update applied) of planes z, z+1, z+2 at those cells in registers
+// while the raw vectors of plane z+3 are in flight.  LDS holds only plane z+1
+// of the input (for the x and y differences) and the stress s' of plane z
+// with a 1-cell halo.  Step z: the stress of plane z+1 at the own and inner
+// ring cells (z differences from registers), then b on plane z (the z
+// difference of the own column's stress from registers), then plane z+2 and
+// the new stress replace the LDS planes.  Every input plane of the range is
+// read once (own cells write the updated vectors then), plus three halo
+// planes and the own column of a fourth per range.
 template <int TX, int TY>
 struct March3 {
     static constexpr int HX = TX + 4, HY = TY + 4, HP = HX * HY;   // input plane with halo 2
     static constexpr int SX = TX + 2, SY = TY + 2, SP = SX * SY;   // stress plane with halo 1
-    static constexpr int NT = TX * TY;                             // one thread per column
+    static constexpr int NT = TX * TY;                             // one thread per own cell
+    static constexpr int RING = HP - NT;                           // halo cells of an input plane
 };
 
 template <int TX, int TY>
 inline size_t march3_lds() {
     using M = March3<TX, TY>;
-    return (size_t)(3 * 3 * M::HP + 2 * 6 * M::SP) * sizeof(cplx);
+    return (size_t)(3 * M::HP + 6 * M::SP) * sizeof(cplx);
 }
+
+// Halo-ring cell k of a (TX+4) x (TY+4) plane: the two rows above, the two
+// rows below, then the two columns left and right of the own rows.
+template <int TX, int TY>
+__device__ __forceinline__ void ring_cell(int k, int& hx, int& hy) {
+    constexpr int HX = TX + 4;
+    if (k < 2 * HX) {
+        hy = k / HX;
+        hx = k % HX;
+    } else if (k < 4 * HX) {
+        k -= 2 * HX;
+        hy = TY + 2 + k / HX;
+        hx = k % HX;
+    } else if (k < 4 * HX + 2 * TY) {
+        k -= 4 * HX;
+        hy = 2 + k / 2;
+        hx = k % 2;
+    } else {
+        k -= 4 * HX + 2 * TY;
+        hy = 2 + k / 2;
+        hx = TX + 2 + k % 2;
+    }
+}
+
+// Raw vectors a stencil mode reads per cell: plain u; VM_P (r, p_old, v);
+// VM_PX (s, t, p_old, v); VM_S (r, v).
+template <int VM>
+struct RawN { static constexpr int N = VM == VM_NONE ? 1 : VM == VM_P ? 3 : VM == VM_PX ? 4 : 2; };
 
 template <int VM, bool GEN, int TX, int TY>
 __global__ __launch_bounds__(TX * TY) void k_stencil3z(const cplx* __restrict__ u, const cplx* __restrict__ a1,
@@ -296,27 +327,29 @@ __global__ __launch_bounds__(TX * TY) void k_stencil3z(const cplx* __restrict__ 
     using M = March3<TX, TY>;
     constexpr int NT = M::NT;
     static_assert(NT == 256, "the FP64 record sums of the Krylov scalars read with 256 threads");
+    static_assert(M::RING <= NT, "one halo-ring cell per thread at most");
     constexpr int NS = Params3<GEN>::NS;
+    constexpr int NV = RawN<VM>::N;
     extern __shared__ __align__(16) unsigned char lds3[];
-    cplx* su = reinterpret_cast<cplx*>(lds3);   // [3 planes][3 comps][HP]
-    cplx* ss = su + 9 * M::HP;                  // [2 planes][6][SP]
+    cplx* sp = reinterpret_cast<cplx*>(lds3);   // input plane [3][HP]
+    cplx* ss = sp + 3 * M::HP;                  // stress plane [6][SP]
     __shared__ double red[4 * kPartialNV];
     __shared__ int s_status;
 
     const int nx = pd.nx, ny = pd.ny, nz = pd.nz;
     const size_t cells = (size_t)nx * ny * nz;
-    const int ntx = (nx + TX - 1) / TX, nty = (ny + TY - 1) / TY, nzc = (nz + ZC - 1) / ZC;
+    const int ntx = (nx + TX - 1) / TX, nty = (ny + TY - 1) / TY;
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
     const int sys = blk % pd.nsys;                 // neighbouring blocks: the same column, other systems
     const int col = blk / pd.nsys;
     const int x0 = (col % ntx) * TX, y0 = ((col / ntx) % nty) * TY, z0 = (col / (ntx * nty)) * ZC;
     const int z1 = min(z0 + ZC, nz);
-    (void)nzc;
-    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+    const int t = threadIdx.x;
+    const int tx = t % TX, ty = t / TX;
     const bool own_xy = x0 + tx < nx && y0 + ty < ny;
 
     if (st != nullptr) {
-        if (threadIdx.x == 0) s_status = st[sys].status;
+        if (t == 0) s_status = st[sys].status;
         __syncthreads();
         const int stw = s_status;
         __syncthreads();
@@ -324,7 +357,7 @@ __global__ __launch_bounds__(TX * TY) void k_stencil3z(const cplx* __restrict__ 
             if (!closing_enters(stw, kStampPx)) return;
         } else {
             if (stw != ST_RUNNING) {
-                if (VM == VM_S && st_tag(stw) != 0 && col == 0 && threadIdx.x == 0) st[sys].status = st_code(stw);
+                if (VM == VM_S && st_tag(stw) != 0 && col == 0 && t == 0) st[sys].status = st_code(stw);
                 return;
             }
         }
@@ -333,176 +366,273 @@ __global__ __launch_bounds__(TX * TY) void k_stencil3z(const cplx* __restrict__ 
     bool fresh = false;
     int step = SS_FULL;
     if constexpr (VM != VM_NONE) {
-        step = stencil_scalars<VM>(st, sys, part, np, red, col == 0 && threadIdx.x == 0, c1, c2, c3, fresh);
+        step = stencil_scalars<VM>(st, sys, part, np, red, col == 0 && t == 0, c1, c2, c3, fresh);
         if (step == SS_SKIP) return;
     }
     const size_t so = (size_t)sys * 3 * cells;
-    auto gidx = [&](int x, int y, int z) -> size_t {
-        return ((size_t)wrapm(z, nz) * ny + wrapm(y, ny)) * nx + wrapm(x, nx);
-    };
-    auto close_iteration = [&](size_t gi) {
-        const cplx sv = u[so + gi], tv = a3[so + gi], pv = a1[so + gi];
-        const cplx rv = close_r(sv, tv, c2);
-        rout[so + gi] = rv;
-        xio[so + gi] = close_x(xio[so + gi], pv, sv, c3, c2);
-        if (fresh) rhat[so + gi] = rv;
-    };
+    const size_t plane_sz = (size_t)nx * ny;
+    auto zoff = [&](int z) -> size_t { return (size_t)wrapm(z, nz) * plane_sz; };
+    const size_t xy0 = (size_t)wrapm(y0 + ty, ny) * nx + wrapm(x0 + tx, nx);
+
     if constexpr (VM == VM_PX) {
         if (step == SS_XONLY) {   // stopped: the last solution update only
             if (own_xy)
                 for (int z = z0; z < z1; ++z) {
-                    const size_t g = gidx(x0 + tx, y0 + ty, z);
+                    const size_t g = zoff(z) + xy0;
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) close_iteration(c * cells + g);
+                    for (int c = 0; c < 3; ++c) {
+                        const size_t gi = so + c * cells + g;
+                        const cplx sv = u[gi], tv = a3[gi], pv = a1[gi];
+                        const cplx rv = close_r(sv, tv, c2);
+                        rout[gi] = rv;
+                        xio[gi] = close_x(xio[gi], pv, sv, c3, c2);
+                        if (fresh) rhat[gi] = rv;
+                    }
                 }
             return;
         }
     }
-    auto field = [&](size_t gi) -> cplx {
-        if constexpr (VM == VM_NONE) {
-            return u[so + gi];
-        } else if constexpr (VM == VM_P) {
-            const cplx rv = u[so + gi];
-            if (fresh) return rv;
-            return cadd(rv, cmul(c1, csub(a1[so + gi], cmul(c2, a2[so + gi]))));
-        } else if constexpr (VM == VM_PX) {
-            const cplx rv = close_r(u[so + gi], a3[so + gi], c2);
-            if (fresh) return rv;
-            return cadd(rv, cmul(c1, csub(a1[so + gi], cmul(c2, a2[so + gi]))));
-        } else {
-            return csub(u[so + gi], cmul(c1, a1[so + gi]));
+
+    // the thread's halo-ring cell
+    const bool has1 = t < M::RING;
+    int hx1 = 2, hy1 = 2;
+    if (has1) ring_cell<TX, TY>(t, hx1, hy1);
+    const bool st1 = has1 && hx1 >= 1 && hx1 <= TX + 2 && hy1 >= 1 && hy1 <= TY + 2;   // inner ring: stress
+    const size_t xy1 = (size_t)wrapm(y0 - 2 + hy1, ny) * nx + wrapm(x0 - 2 + hx1, nx);
+    const int h0 = (ty + 2) * M::HX + tx + 2, h1 = hy1 * M::HX + hx1;
+    const int q0 = (ty + 1) * M::SX + tx + 1, q1 = (hy1 - 1) * M::SX + hx1 - 1;
+
+    using Raw = cplx[NV][3];
+    auto load_raw = [&](Raw& r, size_t g) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const size_t gi = so + c * cells + g;
+            r[0][c] = u[gi];
+            if constexpr (VM == VM_P) {
+                r[1][c] = a1[gi];
+                r[2][c] = a2[gi];
+            } else if constexpr (VM == VM_PX) {
+                r[1][c] = a3[gi];
+                r[2][c] = a1[gi];
+                r[3][c] = a2[gi];
+            } else if constexpr (VM == VM_S) {
+                r[1][c] = a1[gi];
+            }
         }
     };
-    // input plane z (with the 2-cell xy halo) into buffer k; own cells of the
-    // range write the updated vectors
-    auto load_plane = [&](int k, int z) {
-        const bool own_z = z >= z0 && z < z1;
-        cplx* dst = su + k * 3 * M::HP;
-        for (int h = threadIdx.x; h < M::HP; h += NT) {
-            const int hx = h % M::HX, hy = h / M::HX;
-            const size_t g = gidx(x0 - 2 + hx, y0 - 2 + hy, z);
-            const bool own = own_z && hx >= 2 && hx < TX + 2 && hy >= 2 && hy < TY + 2 && x0 + hx - 2 < nx &&
-                             y0 + hy - 2 < ny;
+    auto convert = [&](const Raw& r, cplx (&f)[3]) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            if constexpr (VM == VM_NONE) {
+                f[c] = r[0][c];
+            } else if constexpr (VM == VM_P) {
+                f[c] = fresh ? r[0][c] : cadd(r[0][c], cmul(c1, csub(r[1][c], cmul(c2, r[2][c]))));
+            } else if constexpr (VM == VM_PX) {
+                const cplx rv = close_r(r[0][c], r[1][c], c2);
+                f[c] = fresh ? rv : cadd(rv, cmul(c1, csub(r[2][c], cmul(c2, r[3][c]))));
+            } else {
+                f[c] = csub(r[0][c], cmul(c1, r[1][c]));
+            }
+        }
+    };
+    // own cell of plane z in the range: the updated vectors
+    auto write_own = [&](const Raw& r, const cplx (&f)[3], const cplx (&xv)[3], int z) {
+        if constexpr (VM != VM_NONE) {
+            if (!own_xy || z < z0 || z >= z1) return;
+            const size_t g = zoff(z) + xy0;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const size_t gi = c * cells + g;
-                const cplx f = field(gi);
-                dst[c * M::HP + h] = f;
-                if constexpr (VM != VM_NONE) {
-                    if (own) {
-                        wout[so + gi] = f;
-                        if constexpr (VM == VM_P) {
-                            if (fresh) rhat[so + gi] = f;
-                        } else if constexpr (VM == VM_PX) {
-                            close_iteration(gi);
-                        }
-                    }
+                const size_t gi = so + c * cells + g;
+                wout[gi] = f[c];
+                if constexpr (VM == VM_P) {
+                    if (fresh) rhat[gi] = f[c];
+                } else if constexpr (VM == VM_PX) {
+                    const cplx rv = close_r(r[0][c], r[1][c], c2);
+                    rout[gi] = rv;
+                    xio[gi] = close_x(xv[c], r[2][c], r[0][c], c3, c2);
+                    if (fresh) rhat[gi] = rv;
                 }
             }
         }
     };
-    // raw strain at input-buffer position h of plane `mid` (z differences
-    // from planes lo and hi), then the stress s' = dC e'
-    auto stress_at = [&](const cplx* lo, const cplx* mid, const cplx* hi, int h, const real* mp, size_t mstride,
-                         cplx (&sg)[6]) {
+    auto load_x = [&](cplx (&xv)[3], int z) {
+        if constexpr (VM == VM_PX) {
+            if (own_xy && z >= z0 && z < z1) {
+                const size_t g = so + zoff(z) + xy0;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) xv[c] = xio[g + c * cells];
+            }
+        }
+    };
+    auto load_maps = [&](real (&m)[NS], size_t g) {
+#pragma unroll
+        for (int p = 0; p < NS; ++p) m[p] = maps[(size_t)p * cells + g];
+    };
+    // s' = dC e' at LDS input position h of the current plane; z differences
+    // from the planes below (lo) and above (hi)
+    auto stress_at = [&](int h, const cplx (&lo)[3], const cplx (&hi)[3], const real (&m)[NS], cplx (&sg)[6]) {
         cplx d[3][3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const cplx* w = mid + c * M::HP + h;
+            const cplx* w = sp + c * M::HP + h;
             d[c][0] = csub(w[1], w[-1]);
             d[c][1] = csub(w[M::HX], w[-M::HX]);
-            d[c][2] = csub(hi[c * M::HP + h], lo[c * M::HP + h]);
+            d[c][2] = csub(hi[c], lo[c]);
         }
         const cplx e[6] = {d[0][0], d[1][1], d[2][2], cadd(d[1][2], d[2][1]), cadd(d[0][2], d[2][0]),
                            cadd(d[0][1], d[1][0])};
-        real m[NS];
-#pragma unroll
-        for (int p = 0; p < NS; ++p) m[p] = mp[p * mstride];
         stress3<GEN>(m, 1, e, sg);
     };
-    // stress of plane z (buffers lo = z-1, mid = z, hi = z+1) into stress buffer j
-    auto stress_plane = [&](int j, const cplx* lo, const cplx* mid, const cplx* hi, int z) {
-        cplx* dst = ss + j * 6 * M::SP;
-        for (int q = threadIdx.x; q < M::SP; q += NT) {
-            const int sx = q % M::SX, sy = q / M::SX;
-            const int h = (sy + 1) * M::HX + sx + 1;
-            cplx sg[6];
-            stress_at(lo, mid, hi, h, maps + gidx(x0 - 1 + sx, y0 - 1 + sy, z), cells, sg);
+    auto put_plane = [&](const cplx (&f0)[3], const cplx (&f1)[3]) {
 #pragma unroll
-            for (int i = 0; i < 6; ++i) dst[i * M::SP + q] = sg[i];
+        for (int c = 0; c < 3; ++c) {
+            sp[c * M::HP + h0] = f0[c];
+            if (has1) sp[c * M::HP + h1] = f1[c];
         }
     };
 
-    // prologue: input planes z0-1, z0, z0+1; the own column's stress of plane
-    // z0-1 (its z difference reads the own cell of plane z0-2 directly); the
-    // stress plane z0
-    int kb[3] = {0, 1, 2};   // buffers of planes z-1, z, z+1 (then z, z+1, z+2)
-    load_plane(kb[0], z0 - 1);
-    load_plane(kb[1], z0);
-    load_plane(kb[2], z0 + 1);
-    __syncthreads();
-    const int hown = (ty + 2) * M::HX + tx + 2;
-    const int qown = (ty + 1) * M::SX + tx + 1;
-    cplx sprev[6];
+    // ---- prologue: planes z0-2 (own column), z0-1, z0, z0+1, z0+2
+    cplx fa0[3], fa1[3], fb0[3], fb1[3], fc0[3], fc1[3], xv[3] = {};
+    cplx sold[6];
     {
-        const size_t g = gidx(x0 + tx, y0 + ty, z0 - 2);   // the own cell of plane z0-2
-        cplx below[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) below[c] = field(c * cells + g);
-        cplx d[3][3];
-        const cplx* mid = su + kb[0] * 3 * M::HP;
-        const cplx* hi = su + kb[1] * 3 * M::HP;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const cplx* w = mid + c * M::HP + hown;
-            d[c][0] = csub(w[1], w[-1]);
-            d[c][1] = csub(w[M::HX], w[-M::HX]);
-            d[c][2] = csub(hi[c * M::HP + hown], below[c]);
+        Raw r0, r1;
+        cplx fm2[3], fm0[3], fm1[3];
+        load_raw(r0, zoff(z0 - 2) + xy0);
+        convert(r0, fm2);
+        load_raw(r0, zoff(z0 - 1) + xy0);
+        convert(r0, fm0);
+        if (has1) {
+            load_raw(r1, zoff(z0 - 1) + xy1);
+            convert(r1, fm1);
         }
-        const cplx e[6] = {d[0][0], d[1][1], d[2][2], cadd(d[1][2], d[2][1]), cadd(d[0][2], d[2][0]),
-                           cadd(d[0][1], d[1][0])};
+        load_raw(r0, zoff(z0) + xy0);
+        load_x(xv, z0);
+        convert(r0, fa0);
+        write_own(r0, fa0, xv, z0);
+        if (has1) {
+            load_raw(r1, zoff(z0) + xy1);
+            convert(r1, fa1);
+        }
+        put_plane(fm0, fm1);
         real m[NS];
-        const real* mp = maps + gidx(x0 + tx, y0 + ty, z0 - 1);
+        load_maps(m, zoff(z0 - 1) + xy0);
+        __syncthreads();
+        stress_at(h0, fm2, fa0, m, sold);   // own stress of plane z0-1
+        load_raw(r0, zoff(z0 + 1) + xy0);
+        load_x(xv, z0 + 1);
+        convert(r0, fb0);
+        write_own(r0, fb0, xv, z0 + 1);
+        if (has1) {
+            load_raw(r1, zoff(z0 + 1) + xy1);
+            convert(r1, fb1);
+        }
+        __syncthreads();
+        put_plane(fa0, fa1);
+        __syncthreads();
+        cplx sg[6];
+        load_maps(m, zoff(z0) + xy0);
+        stress_at(h0, fm0, fb0, m, sg);   // stress of plane z0
 #pragma unroll
-        for (int p = 0; p < NS; ++p) m[p] = mp[p * cells];
-        stress3<GEN>(m, 1, e, sprev);
+        for (int i = 0; i < 6; ++i) ss[i * M::SP + q0] = sg[i];
+        if (st1) {
+            load_maps(m, zoff(z0) + xy1);
+            stress_at(h1, fm1, fb1, m, sg);
+#pragma unroll
+            for (int i = 0; i < 6; ++i) ss[i * M::SP + q1] = sg[i];
+        }
+        load_raw(r0, zoff(z0 + 2) + xy0);
+        load_x(xv, z0 + 2);
+        convert(r0, fc0);
+        write_own(r0, fc0, xv, z0 + 2);
+        if (has1) {
+            load_raw(r1, zoff(z0 + 2) + xy1);
+            convert(r1, fc1);
+        }
+        __syncthreads();
+        put_plane(fb0, fb1);
     }
-    int jc = 0;   // stress buffer of the current plane
-    stress_plane(jc, su + kb[0] * 3 * M::HP, su + kb[1] * 3 * M::HP, su + kb[2] * 3 * M::HP, z0);
+    // in flight during a step: the raw vectors of plane z+3 and the maps of plane z+2
+    Raw rd0, rd1;
+    load_raw(rd0, zoff(z0 + 3) + xy0);
+    if (has1) load_raw(rd1, zoff(z0 + 3) + xy1);
+    load_x(xv, z0 + 3);
+    // stiffness maps of plane z+1 (and, prefetched, z+2); the 21-constant
+    // form loads them at the step instead (registers)
+    constexpr int NPF = GEN ? 1 : NS;
+    real mc0[NS], mc1[NS], mn0[NPF], mn1[NPF];
+    if constexpr (!GEN) {
+        load_maps(mc0, zoff(z0 + 1) + xy0);
+        if (st1) load_maps(mc1, zoff(z0 + 1) + xy1);
+        load_maps(mn0, zoff(z0 + 2) + xy0);
+        if (st1) load_maps(mn1, zoff(z0 + 2) + xy1);
+    }
+    const real* rho = maps + (size_t)NS * cells;
+    real rho_z = rho[zoff(z0) + xy0], rho_1 = rho[zoff(z0 + 1) + xy0], rho_2 = rho[zoff(z0 + 2) + xy0];
     __syncthreads();
-    // now kb = {z0-1, z0, z0+1}: rotate so that kb = {z, z+1, (free)}
+
     const real sc = pd.inv4dx2;
     for (int z = z0; z < z1; ++z) {
-        // buffers: kb[1] = plane z, kb[2] = plane z+1, kb[0] = plane z-1 (free now)
-        load_plane(kb[0], z + 2);
-        __syncthreads();
-        const cplx* pz = su + kb[1] * 3 * M::HP;
-        const cplx* pz1 = su + kb[2] * 3 * M::HP;
-        const cplx* pz2 = su + kb[0] * 3 * M::HP;
-        stress_plane(1 - jc, pz, pz1, pz2, z + 1);
-        __syncthreads();
-        const cplx* cur = ss + jc * 6 * M::SP;
-        const cplx* nxt = ss + (1 - jc) * 6 * M::SP;
-        if (own_xy) {
-            auto dxy = [&](int i, int off) { return csub(cur[i * M::SP + qown + off], cur[i * M::SP + qown - off]); };
-            auto dz = [&](int i) { return csub(nxt[i * M::SP + qown], sprev[i]); };
-            const cplx bx = cadd(cadd(dxy(0, 1), dxy(5, M::SX)), dz(4));
-            const cplx by = cadd(cadd(dxy(5, 1), dxy(1, M::SX)), dz(3));
-            const cplx bz = cadd(cadd(dxy(4, 1), dxy(3, M::SX)), dz(2));
-            const size_t g = gidx(x0 + tx, y0 + ty, z);
-            const cplx wr = cscale(pd.w2, maps[(size_t)NS * cells + g]);
-            b[so + g] = cadd(cmul(wr, pz[hown]), cscale(bx, sc));
-            b[so + g + cells] = cadd(cmul(wr, pz[M::HP + hown]), cscale(by, sc));
-            b[so + g + 2 * cells] = cadd(cmul(wr, pz[2 * M::HP + hown]), cscale(bz, sc));
-#pragma unroll
-            for (int i = 0; i < 6; ++i) sprev[i] = cur[i * M::SP + qown];
+        // stress of plane z+1 at the own and inner-ring cells
+        cplx s0[6], s1[6];
+        if constexpr (GEN) {
+            load_maps(mc0, zoff(z + 1) + xy0);
+            if (st1) load_maps(mc1, zoff(z + 1) + xy1);
         }
-        __syncthreads();   // plane z and stress plane z are read: their buffers are free
-        const int k0 = kb[0];
-        kb[0] = kb[1];
-        kb[1] = kb[2];
-        kb[2] = k0;
-        jc = 1 - jc;
+        stress_at(h0, fa0, fc0, mc0, s0);
+        if (st1) stress_at(h1, fa1, fc1, mc1, s1);
+        // b on plane z at the own cell
+        if (own_xy) {
+            const cplx* cur = ss;
+            auto dxy = [&](int i, int off) { return csub(cur[i * M::SP + q0 + off], cur[i * M::SP + q0 - off]); };
+            const cplx bx = cadd(cadd(dxy(0, 1), dxy(5, M::SX)), csub(s0[4], sold[4]));
+            const cplx by = cadd(cadd(dxy(5, 1), dxy(1, M::SX)), csub(s0[3], sold[3]));
+            const cplx bz = cadd(cadd(dxy(4, 1), dxy(3, M::SX)), csub(s0[2], sold[2]));
+            const size_t g = so + zoff(z) + xy0;
+            const cplx wr = cscale(pd.w2, rho_z);
+            b[g] = cadd(cmul(wr, fa0[0]), cscale(bx, sc));
+            b[g + cells] = cadd(cmul(wr, fa0[1]), cscale(by, sc));
+            b[g + 2 * cells] = cadd(cmul(wr, fa0[2]), cscale(bz, sc));
+        }
+        __syncthreads();   // the LDS planes z+1 (input) and z (stress) are read
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {   // own stress of plane z for the next z difference
+            sold[i] = ss[i * M::SP + q0];
+            ss[i * M::SP + q0] = s0[i];
+            if (st1) ss[i * M::SP + q1] = s1[i];
+        }
+        put_plane(fc0, fc1);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            fa0[c] = fb0[c];
+            fb0[c] = fc0[c];
+            fa1[c] = fb1[c];
+            fb1[c] = fc1[c];
+        }
+        convert(rd0, fc0);
+        write_own(rd0, fc0, xv, z + 3);
+        if (has1) convert(rd1, fc1);
+        if constexpr (!GEN) {
+#pragma unroll
+            for (int p = 0; p < NS; ++p) {
+                mc0[p] = mn0[p];
+                mc1[p] = mn1[p];
+            }
+        }
+        rho_z = rho_1;
+        rho_1 = rho_2;
+        if (z + 4 <= z1 + 1) {
+            load_raw(rd0, zoff(z + 4) + xy0);
+            if (has1) load_raw(rd1, zoff(z + 4) + xy1);
+            load_x(xv, z + 4);
+        }
+        if (z + 3 <= z1) {
+            if constexpr (!GEN) {
+                load_maps(mn0, zoff(z + 3) + xy0);
+                if (st1) load_maps(mn1, zoff(z + 3) + xy1);
+            }
+            rho_2 = rho[zoff(z + 3) + xy0];
+        }
+        __syncthreads();
     }
 }
 
@@ -511,7 +641,7 @@ static hipError_t stencil3z_launch(const StencilArgs& a, const ProbDev3& pd, Sys
     const int ntx = (pd.nx + TX - 1) / TX, nty = (pd.ny + TY - 1) / TY;
     // z ranges of at most 32 planes, more of them while the launch is small
     int ZC = std::min(pd.nz, 32);
-    while (ZC > 8 && (long long)ntx * nty * ((pd.nz + ZC - 1) / ZC) * pd.nsys < 4096) ZC /= 2;
+    while (ZC > 8 && (long long)ntx * nty * ((pd.nz + ZC - 1) / ZC) * pd.nsys < 2048) ZC /= 2;
     const long long blocks = (long long)ntx * nty * ((pd.nz + ZC - 1) / ZC) * pd.nsys;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
     const size_t lds = march3_lds<TX, TY>();
