@@ -265,13 +265,13 @@ __global__ __launch_bounds__(256) void k_stencil3(const cplx* __restrict__ u, co
 // over the z range [z0, z1) of one system and walks it plane by plane.  Each
 // thread owns one cell of the column (p0) and, for the first RING threads,
 // one cell of the 2-cell xy halo ring around it (p1), and keeps the input
-// (vector update applied) of planes z, z+1, z+2 at those cells in registers
-// while the raw vectors of plane z+3 are in flight.  LDS holds only plane z+1
+// (vector update applied) of planes z, z+1, z+2 at those cells in registers.  LDS holds only plane z+1
 // of the input (for the x and y differences) and the stress s' of plane z
 // with a 1-cell halo.  Step z: the stress of plane z+1 at the own and inner
 // ring cells (z differences from registers), then b on plane z (the z
 // difference of the own column's stress from registers), then plane z+2 and
-// the new stress replace the LDS planes.  Every input plane of the range is
+// the new stress replace the LDS planes; the raw vectors of the next two
+// planes are in flight meanwhile.  Every input plane of the range is
 // read once (own cells write the updated vectors then), plus three halo
 // planes and the own column of a fourth per range.
 template <int TX, int TY>
@@ -316,6 +316,11 @@ __device__ __forceinline__ void ring_cell(int k, int& hx, int& hy) {
 template <int VM>
 struct RawN { static constexpr int N = VM == VM_NONE ? 1 : VM == VM_P ? 3 : VM == VM_PX ? 4 : 2; };
 
+// Raw planes in flight per stencil mode (two where the registers of the
+// second buffer leave the occupancy unchanged).
+template <int VM>
+constexpr int march3_depth() { return VM == VM_S ? 1 : 2; }
+
 template <int VM, bool GEN, int TX, int TY>
 __global__ __launch_bounds__(TX * TY) void k_stencil3z(const cplx* __restrict__ u, const cplx* __restrict__ a1,
                                                        const cplx* __restrict__ a2, cplx* __restrict__ wout,
@@ -339,9 +344,13 @@ __global__ __launch_bounds__(TX * TY) void k_stencil3z(const cplx* __restrict__ 
     const int nx = pd.nx, ny = pd.ny, nz = pd.nz;
     const size_t cells = (size_t)nx * ny * nz;
     const int ntx = (nx + TX - 1) / TX, nty = (ny + TY - 1) / TY;
+    // neighbouring blocks (on one XCD, resident together): the neighbouring
+    // columns and z ranges of the same system, which read each other's cells
+    // as their halos while those cache lines are still in the XCD's L2
+    const int ncol = ntx * nty * ((nz + ZC - 1) / ZC);
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int sys = blk % pd.nsys;                 // neighbouring blocks: the same column, other systems
-    const int col = blk / pd.nsys;
+    const int sys = blk / ncol;
+    const int col = blk - sys * ncol;
     const int x0 = (col % ntx) * TX, y0 = ((col / ntx) % nty) * TY, z0 = (col / (ntx * nty)) * ZC;
     const int z1 = min(z0 + ZC, nz);
     const int t = threadIdx.x;
@@ -551,11 +560,20 @@ __global__ __launch_bounds__(TX * TY) void k_stencil3z(const cplx* __restrict__ 
         __syncthreads();
         put_plane(fb0, fb1);
     }
-    // in flight during a step: the raw vectors of plane z+3 and the maps of plane z+2
-    Raw rd0, rd1;
-    load_raw(rd0, zoff(z0 + 3) + xy0);
-    if (has1) load_raw(rd1, zoff(z0 + 3) + xy1);
-    load_x(xv, z0 + 3);
+    // in flight during a step: the raw vectors of planes z+3 .. z+2+PD (PD
+    // buffers, used in turn: the loop is unrolled by PD so that no register
+    // of a load in flight is moved) and the maps of plane z+2
+    constexpr int PD = march3_depth<VM>();
+    Raw rA0, rA1, rB0, rB1;
+    cplx xA[3] = {}, xB[3] = {};
+    load_raw(rA0, zoff(z0 + 3) + xy0);
+    if (has1) load_raw(rA1, zoff(z0 + 3) + xy1);
+    load_x(xA, z0 + 3);
+    if constexpr (PD == 2) {
+        load_raw(rB0, zoff(z0 + 4) + xy0);
+        if (has1) load_raw(rB1, zoff(z0 + 4) + xy1);
+        load_x(xB, z0 + 4);
+    }
     // stiffness maps of plane z+1 (and, prefetched, z+2); the 21-constant
     // form loads them at the step instead (registers)
     constexpr int NPF = GEN ? 1 : NS;
@@ -571,7 +589,8 @@ __global__ __launch_bounds__(TX * TY) void k_stencil3z(const cplx* __restrict__ 
     __syncthreads();
 
     const real sc = pd.inv4dx2;
-    for (int z = z0; z < z1; ++z) {
+    // step z: b on plane z; rd holds the raw plane z+3 and is refilled with z+3+PD
+    auto plane_step = [&](int z, Raw& rd0, Raw& rd1, cplx (&xv)[3]) {
         // stress of plane z+1 at the own and inner-ring cells
         cplx s0[6], s1[6];
         if constexpr (GEN) {
@@ -582,8 +601,7 @@ __global__ __launch_bounds__(TX * TY) void k_stencil3z(const cplx* __restrict__ 
         if (st1) stress_at(h1, fa1, fc1, mc1, s1);
         // b on plane z at the own cell
         if (own_xy) {
-            const cplx* cur = ss;
-            auto dxy = [&](int i, int off) { return csub(cur[i * M::SP + q0 + off], cur[i * M::SP + q0 - off]); };
+            auto dxy = [&](int i, int off) { return csub(ss[i * M::SP + q0 + off], ss[i * M::SP + q0 - off]); };
             const cplx bx = cadd(cadd(dxy(0, 1), dxy(5, M::SX)), csub(s0[4], sold[4]));
             const cplx by = cadd(cadd(dxy(5, 1), dxy(1, M::SX)), csub(s0[3], sold[3]));
             const cplx bz = cadd(cadd(dxy(4, 1), dxy(3, M::SX)), csub(s0[2], sold[2]));
@@ -620,10 +638,10 @@ __global__ __launch_bounds__(TX * TY) void k_stencil3z(const cplx* __restrict__ 
         }
         rho_z = rho_1;
         rho_1 = rho_2;
-        if (z + 4 <= z1 + 1) {
-            load_raw(rd0, zoff(z + 4) + xy0);
-            if (has1) load_raw(rd1, zoff(z + 4) + xy1);
-            load_x(xv, z + 4);
+        if (z + 3 + PD <= z1 + 1) {
+            load_raw(rd0, zoff(z + 3 + PD) + xy0);
+            if (has1) load_raw(rd1, zoff(z + 3 + PD) + xy1);
+            load_x(xv, z + 3 + PD);
         }
         if (z + 3 <= z1) {
             if constexpr (!GEN) {
@@ -633,6 +651,16 @@ __global__ __launch_bounds__(TX * TY) void k_stencil3z(const cplx* __restrict__ 
             rho_2 = rho[zoff(z + 3) + xy0];
         }
         __syncthreads();
+    };
+    if constexpr (PD == 2) {
+        int z = z0;
+        for (; z + 1 < z1; z += 2) {
+            plane_step(z, rA0, rA1, xA);
+            plane_step(z + 1, rB0, rB1, xB);
+        }
+        if (z < z1) plane_step(z, rA0, rA1, xA);
+    } else {
+        for (int z = z0; z < z1; ++z) plane_step(z, rA0, rA1, xA);
     }
 }
 
