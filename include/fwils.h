@@ -477,10 +477,14 @@ typedef struct {
                               3: as 1 in blocks of up to 1024 threads
                                  (complex64, power-of-two columns of 512 or
                                  more points, col_points 8)              */
-    int32_t stencil_rows;  /* contrast-stencil tile height: 4, 8 or 16 */
+    int32_t stencil_rows;  /* contrast-stencil tile height: 4, 8 or 16 (with
+                              stencil_sys = -1: rows per step, 4 or 8; complex128
+                              plans 4) */
     int32_t stencil_sys;   /* systems per stencil workgroup, 0 = from the grid size (the
                               plain stencil; the Krylov update modes always take the
-                              count from the grid size) */
+                              count from the grid size); -1 = the z-marching stencil
+                              (one system per workgroup walking a column strip down a
+                              range of rows, every mode) */
     int32_t fused_points;  /* 0: contrast stencil and forward row transform as two
                               kernels; else one fused kernel with this many points
                               per thread (rows of at most 512 points) */

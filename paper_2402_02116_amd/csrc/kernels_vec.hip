@@ -58,10 +58,14 @@ __global__ __launch_bounds__(256) void k_body_force(const cplx* __restrict__ u,
     const int nx = pd.nx, nz = pd.nz;
     const size_t plane = (size_t)nx * nz;
     const int ntx = nx / TX;
-    const int nsg = (pd.nsys + S - 1) / S;
+    const int ntiles = ntx * (nz / TZ);
+    // neighbouring blocks (on one XCD, resident together): the neighbouring
+    // tiles of the same systems, which read each other's rows and columns as
+    // their halos while those cache lines are still in the XCD's L2
     const int blk = xcd_remap(blockIdx.x, gridDim.x);
-    const int tile = blk / nsg;              // neighbouring blocks: same tile, next systems
-    const int sys0 = (blk - tile * nsg) * S;
+    const int sg = blk / ntiles;
+    const int tile = blk - sg * ntiles;
+    const int sys0 = sg * S;
     const int z0 = (tile / ntx) * TZ, x0 = (tile % ntx) * TX;
     const int tx = threadIdx.x & 63, tg = threadIdx.x >> 6;
     const bool lane = tx < TX;
@@ -222,6 +226,324 @@ __global__ __launch_bounds__(256) void k_body_force(const cplx* __restrict__ u,
     }
 }
 
+// The same stencil marching along z: a block owns a TX-column strip over the
+// row range [z0, z0 + ZR) of one system and walks it TZ rows at a time (TZ/4
+// rows per thread).  LDS holds the input rows in a ring of RU rows and the
+// stress rows in a ring of RS rows; the raw vectors of the next TZ input
+// rows, and the maps of the next step's stress rows, are in flight in
+// registers while a step computes.  Step at row z: the input rows z+2 ..
+// z+TZ+1 enter the ring (own cells of the range write the updated vectors),
+// the stress of rows z+1 .. z+TZ is formed, then b on rows z .. z+TZ-1.  Each
+// input row of the range is read once, plus four halo rows per range, instead
+// of the tiled kernel's TZ+4 rows per TZ.  The ring sizes keep every row a
+// step reads alive until the next step's first barrier (RU >= 2 TZ + 2, RS
+// >= TZ + 2), so a step needs two barriers.
+template <int TZ>
+struct MarchZ2 {
+    static constexpr int KB = TZ / 4;                  // rows per thread per step
+    static constexpr int RU = TZ == 4 ? 16 : 32;       // input ring rows
+    static constexpr int RS = TZ == 4 ? 8 : 16;        // stress ring rows
+};
+
+template <int TX, int TZ, int VM>
+__global__ __launch_bounds__(256) void k_body_force_z(const cplx* __restrict__ u,
+                                                      const cplx* __restrict__ a1,
+                                                      const cplx* __restrict__ a2,
+                                                      cplx* __restrict__ wout,
+                                                      cplx* __restrict__ b,
+                                                      const real* __restrict__ maps, ProbDev pd,
+                                                      int ZR, SysState* __restrict__ st,
+                                                      const double* __restrict__ part, int np,
+                                                      cplx* __restrict__ rhat,
+                                                      const cplx* __restrict__ a3,
+                                                      cplx* __restrict__ xio,
+                                                      cplx* __restrict__ rout) {
+    static_assert(TX <= 64 && (TZ == 4 || TZ == 8), "tile");
+    using Z = MarchZ2<TZ>;
+    constexpr int KB = Z::KB, RU = Z::RU, RS = Z::RS;
+    constexpr int HX = TX + 4, SX = TX + 2;
+    constexpr int NV = VM == VM_NONE ? 1 : VM == VM_P ? 3 : VM == VM_PX ? 4 : 2;
+    __shared__ cplx su[2][RU][HX];
+    __shared__ cplx ss[3][RS][SX];
+    __shared__ double red[4 * kPartialNV];
+    const int nx = pd.nx, nz = pd.nz;
+    const size_t plane = (size_t)nx * nz;
+    const int ntx = nx / TX;
+    const int ncol = ntx * (nz / ZR);
+    // neighbouring blocks: the neighbouring strips and row ranges of the same
+    // system, which read each other's cells as their halos
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int sys = blk / ncol;
+    const int col = blk - sys * ncol;
+    const int x0 = (col % ntx) * TX, z0 = (col / ntx) * ZR, z1 = z0 + ZR;
+    const int tx = threadIdx.x & 63, tg = threadIdx.x >> 6;
+    const bool lane = tx < TX;
+    const bool hlane = tx < 4;                // the x halo of the input rows
+    const bool slane = tx < 2;                // the x halo of the stress rows
+    const int hsx = (tx == 0) ? 0 : TX + 1;   // halo stress column of lanes 0 and 1
+    const int hux = (tx < 2) ? tx : TX + tx;  // halo input column of lanes 0..3
+    const int gxo = x0 + (lane ? tx : 0);                // own column
+    const int gxh = wrap(x0 - 2 + hux, nx);              // input halo column
+    const int gxs = wrap(x0 - 1 + hsx, nx);              // stress halo column
+
+    if (st != nullptr) {   // uniform over the block
+        const int stw = st[sys].status;
+        if constexpr (VM == VM_PX) {
+            if (!closing_enters(stw, kStampPx)) return;
+        } else {
+            if (stw != ST_RUNNING) {
+                if (VM == VM_S && st_tag(stw) != 0 && col == 0 && threadIdx.x == 0) st[sys].status = st_code(stw);
+                return;
+            }
+        }
+    }
+    cplx c1 = mkc(0.f, 0.f), c2 = mkc(0.f, 0.f), c3 = mkc(0.f, 0.f);
+    bool fresh = false;
+    int step = SS_FULL;
+    if constexpr (VM != VM_NONE) {
+        step = stencil_scalars<VM>(st, sys, part, np, red, col == 0 && threadIdx.x == 0, c1, c2, c3, fresh);
+        if (step == SS_SKIP) return;
+    }
+    const size_t so = (size_t)sys * 2 * plane;
+    auto rowoff = [&](int z) -> size_t { return (size_t)wrap(z, nz) * nx; };
+    if constexpr (VM == VM_PX) {
+        if (step == SS_XONLY) {   // stopped: the last solution update only
+            if (lane)
+                for (int z = z0 + tg; z < z1; z += 4)
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        const size_t gi = so + c * plane + rowoff(z) + gxo;
+                        const cplx sv = u[gi], tv = a3[gi], pv = a1[gi];
+                        const cplx rv = close_r(sv, tv, c2);
+                        st_wt(rout + gi, rv);
+                        st_wt(xio + gi, close_x(xio[gi], pv, sv, c3, c2));
+                        if (fresh) rhat[gi] = rv;
+                    }
+            return;
+        }
+    }
+
+    using Raw = cplx[NV][2];
+    auto load_raw = [&](Raw& r, size_t g) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const size_t gi = so + c * plane + g;
+            r[0][c] = u[gi];
+            if constexpr (VM == VM_P) {
+                r[1][c] = a1[gi];
+                r[2][c] = a2[gi];
+            } else if constexpr (VM == VM_PX) {
+                r[1][c] = a3[gi];
+                r[2][c] = a1[gi];
+                r[3][c] = a2[gi];
+            } else if constexpr (VM == VM_S) {
+                r[1][c] = a1[gi];
+            }
+        }
+    };
+    auto convert = [&](const Raw& r, cplx (&f)[2]) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            if constexpr (VM == VM_NONE) {
+                f[c] = r[0][c];
+            } else if constexpr (VM == VM_P) {
+                f[c] = fresh ? r[0][c] : cadd(r[0][c], cmul(c1, csub(r[1][c], cmul(c2, r[2][c]))));
+            } else if constexpr (VM == VM_PX) {
+                const cplx rv = close_r(r[0][c], r[1][c], c2);
+                f[c] = fresh ? rv : cadd(rv, cmul(c1, csub(r[2][c], cmul(c2, r[3][c]))));
+            } else {
+                f[c] = csub(r[0][c], cmul(c1, r[1][c]));
+            }
+        }
+    };
+    // own cell of row z in the range: the updated vectors
+    auto write_own = [&](const Raw& r, const cplx (&f)[2], const cplx (&xv)[2], int z) {
+        if constexpr (VM != VM_NONE) {
+            if (!lane || z < z0 || z >= z1) return;
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const size_t gi = so + c * plane + rowoff(z) + gxo;
+                st_wt(wout + gi, f[c]);
+                if constexpr (VM == VM_P) {
+                    if (fresh) rhat[gi] = f[c];
+                } else if constexpr (VM == VM_PX) {
+                    const cplx rv = close_r(r[0][c], r[1][c], c2);
+                    st_wt(rout + gi, rv);
+                    st_wt(xio + gi, close_x(xv[c], r[2][c], r[0][c], c3, c2));
+                    if (fresh) rhat[gi] = rv;
+                }
+            }
+        }
+    };
+    auto load_x = [&](cplx (&xv)[2], int z) {
+        if constexpr (VM == VM_PX) {
+            if (lane && z >= z0 && z < z1) {
+                const size_t gi = so + rowoff(z) + gxo;
+                xv[0] = xio[gi];
+                xv[1] = xio[gi + plane];
+            }
+        }
+    };
+    // raw rows of one step (own and halo cells of this thread's rows)
+    struct Rows {
+        Raw o[KB], h[KB];
+        cplx x[KB][2];
+    };
+    auto load_rows = [&](Rows& R, int zb) {   // rows zb + tg + 4k
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+            const int z = zb + tg + 4 * k;
+            const size_t ro = rowoff(z);
+            if (lane) load_raw(R.o[k], ro + gxo);
+            if (hlane) load_raw(R.h[k], ro + gxh);
+            load_x(R.x[k], z);
+        }
+    };
+    auto put_rows = [&](const Rows& R, int zb) {
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+            const int z = zb + tg + 4 * k;
+            const int slot = (z - z0 + 2 * RU) & (RU - 1);
+            cplx f[2];
+            if (lane) {
+                convert(R.o[k], f);
+                su[0][slot][tx + 2] = f[0];
+                su[1][slot][tx + 2] = f[1];
+                write_own(R.o[k], f, R.x[k], z);
+            }
+            if (hlane) {
+                convert(R.h[k], f);
+                su[0][slot][hux] = f[0];
+                su[1][slot][hux] = f[1];
+            }
+        }
+    };
+    // stiffness maps (C11, C13, C33, C55) of a stress row at the own and halo column
+    struct SMaps {
+        real o[KB][4], h[KB][4];
+    };
+    auto load_smaps = [&](SMaps& m, int zb) {   // stress rows zb + tg + 4k
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+            const size_t ro = rowoff(zb + tg + 4 * k);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                m.o[k][c] = lane ? maps[c * plane + ro + gxo] : 0.f;
+                m.h[k][c] = slane ? maps[c * plane + ro + gxs] : 0.f;
+            }
+        }
+    };
+    // stress of row z at stress column sx (input column sx + 1) into the ring
+    auto stress_at = [&](int z, int sx, const real (&m)[4]) {
+        const int hx = sx + 1;
+        const int lo = (z - 1 - z0 + 2 * RU) & (RU - 1), mid = (z - z0 + 2 * RU) & (RU - 1),
+                  hi = (z + 1 - z0 + 2 * RU) & (RU - 1);
+        const cplx ex = csub(su[0][mid][hx + 1], su[0][mid][hx - 1]);
+        const cplx ez = csub(su[1][hi][hx], su[1][lo][hx]);
+        const cplx exz = cadd(csub(su[0][hi][hx], su[0][lo][hx]), csub(su[1][mid][hx + 1], su[1][mid][hx - 1]));
+        const int s = (z - z0 + 2 * RS) & (RS - 1);
+        ss[0][s][sx] = mkc(m[0] * ex.x + m[1] * ez.x, m[0] * ex.y + m[1] * ez.y);
+        ss[1][s][sx] = mkc(m[1] * ex.x + m[2] * ez.x, m[1] * ex.y + m[2] * ez.y);
+        ss[2][s][sx] = cscale(exz, m[3]);
+    };
+
+    // ---- prologue: input rows z0-2 .. z0+1 (one per thread group), stress
+    // rows z0-1 and z0
+    {
+        const int z = z0 - 2 + tg;
+        Raw ro, rh;
+        cplx xv[2] = {};
+        if (lane) load_raw(ro, rowoff(z) + gxo);
+        if (hlane) load_raw(rh, rowoff(z) + gxh);
+        load_x(xv, z);
+        const int slot = (z - z0 + 2 * RU) & (RU - 1);
+        cplx f[2];
+        if (lane) {
+            convert(ro, f);
+            su[0][slot][tx + 2] = f[0];
+            su[1][slot][tx + 2] = f[1];
+            write_own(ro, f, xv, z);
+        }
+        if (hlane) {
+            convert(rh, f);
+            su[0][slot][hux] = f[0];
+            su[1][slot][hux] = f[1];
+        }
+        real m[4], mh[4];
+        if (tg < 2) {
+            const size_t rm = rowoff(z0 - 1 + tg);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                m[c] = lane ? maps[c * plane + rm + gxo] : 0.f;
+                mh[c] = slane ? maps[c * plane + rm + gxs] : 0.f;
+            }
+        }
+        __syncthreads();
+        if (tg < 2) {
+            if (lane) stress_at(z0 - 1 + tg, tx + 1, m);
+            if (slane) stress_at(z0 - 1 + tg, hsx, mh);
+        }
+    }
+    Rows RA;
+    load_rows(RA, z0 + 2);
+    SMaps mc, mn;
+    load_smaps(mc, z0 + 1);
+    real rc[KB], rn[KB];
+#pragma unroll
+    for (int k = 0; k < KB; ++k) rc[k] = lane ? maps[4 * plane + rowoff(z0 + tg + 4 * k) + gxo] : 0.f;
+    const real sc = pd.inv4dx2;
+    for (int z = z0; z < z1; z += TZ) {
+        // the new input rows enter the ring; the next step's rows and maps are issued
+        put_rows(RA, z + 2);
+        const bool more = z + TZ < z1;
+        if (more) {
+            load_rows(RA, z + TZ + 2);
+            load_smaps(mn, z + TZ + 1);
+#pragma unroll
+            for (int k = 0; k < KB; ++k) rn[k] = lane ? maps[4 * plane + rowoff(z + TZ + tg + 4 * k) + gxo] : 0.f;
+        }
+        __syncthreads();
+        // stress of rows z+1 .. z+TZ
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+            const int zs = z + 1 + tg + 4 * k;
+            if (lane) stress_at(zs, tx + 1, mc.o[k]);
+            if (slane) stress_at(zs, hsx, mc.h[k]);
+        }
+        __syncthreads();
+        // b on rows z .. z+TZ-1
+        if (lane) {
+#pragma unroll
+            for (int k = 0; k < KB; ++k) {
+                const int zo = z + tg + 4 * k;
+                const int s = (zo - z0 + 2 * RS) & (RS - 1), sm = (zo - 1 - z0 + 2 * RS) & (RS - 1),
+                          sp = (zo + 1 - z0 + 2 * RS) & (RS - 1);
+                const int uo = (zo - z0 + 2 * RU) & (RU - 1);
+                const int sx = tx + 1;
+                const cplx dx1 = csub(ss[0][s][sx + 1], ss[0][s][sx - 1]);
+                const cplx dz5 = csub(ss[2][sp][sx], ss[2][sm][sx]);
+                const cplx dx5 = csub(ss[2][s][sx + 1], ss[2][s][sx - 1]);
+                const cplx dz3 = csub(ss[1][sp][sx], ss[1][sm][sx]);
+                const cplx wr = cscale(pd.w2, rc[k]);
+                const size_t gi = so + rowoff(zo) + gxo;
+                st_wt(b + gi, cadd(cmul(wr, su[0][uo][tx + 2]), cscale(cadd(dx1, dz5), sc)));
+                st_wt(b + plane + gi, cadd(cmul(wr, su[1][uo][tx + 2]), cscale(cadd(dx5, dz3), sc)));
+            }
+        }
+        if (more) {
+#pragma unroll
+            for (int k = 0; k < KB; ++k) {
+                rc[k] = rn[k];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    mc.o[k][c] = mn.o[k][c];
+                    mc.h[k][c] = mn.h[k][c];
+                }
+            }
+        }
+    }
+}
+
 // Tile width for nx: the largest of 64, 48, 32, 24, 16 dividing it.
 static int tile_x(int nx) {
     const int cand[] = {64, 48, 32, 24, 16};
@@ -234,6 +556,14 @@ StCfg st_default() { return StCfg{STZ, 0}; }
 
 bool st_cfg_ok(int nx, int nz, const StCfg& c) {
     if (tile_x(nx) == 0) return false;
+    if (c.S == kStMarch) {   // the z-marching kernel: 4- or 8-row steps
+#ifdef FW_C128
+        if (c.TZ != 4) return false;   // its 8-row rings exceed the static LDS limit
+#else
+        if (c.TZ != 4 && c.TZ != 8) return false;
+#endif
+        return nz % c.TZ == 0 && nz >= 2 * c.TZ;
+    }
 #ifdef FW_C128
     if (c.TZ != 4 && c.TZ != 8) return false;   // 16-row complex128 tiles exceed the static LDS limit
 #else
@@ -246,7 +576,7 @@ bool st_cfg_ok(int nx, int nz, const StCfg& c) {
 int st_candidates(int nx, int nz, StCfg* out, int cap) {
     int k = 0;
     const int tzs[3] = {8, 4, 16};
-    const int ss[5] = {0, 1, 2, 4, 8};
+    const int ss[6] = {0, 1, 2, 4, 8, kStMarch};
     for (int tz : tzs)
         for (int sv : ss) {
             const StCfg c{tz, sv};
@@ -255,9 +585,34 @@ int st_candidates(int nx, int nz, StCfg* out, int cap) {
     return k;
 }
 
+// Row range of the z-marching kernel: the whole column, halved (while it
+// stays a multiple of the step and at least 32 rows) until the launch has
+// 8192 workgroups.
+static int march_rows(int nx, int tx, int nz, int tz, int nsys) {
+    int zr = nz;
+    while (zr % 2 == 0 && (zr / 2) % tz == 0 && zr / 2 >= 32 &&
+           (long long)(nx / tx) * (nz / zr) * nsys < 8192)
+        zr /= 2;
+    return zr;
+}
+
+template <int TX, int TZ, int VM>
+static void body_force_z_launch(const StencilArgs& a, const ProbDev& pd, SysState* st, hipStream_t s) {
+    const int zr = march_rows(pd.nx, TX, pd.nz, TZ, pd.nsys);
+    const long long blocks = (long long)(pd.nx / TX) * (pd.nz / zr) * pd.nsys;
+    hipLaunchKernelGGL((k_body_force_z<TX, TZ, VM>), dim3((unsigned)blocks), dim3(256), 0, s, a.u, a.a1, a.a2,
+                       a.wout, a.b, a.maps, pd, zr, st, a.part, a.np, a.rhat, a.a3, a.xio, a.rout);
+}
+
 template <int TX, int TZ, int VM>
 static void body_force_launch(const StCfg& c, const StencilArgs& a, const ProbDev& pd, SysState* st,
                               hipStream_t s) {
+    if constexpr (TZ == 4 || TZ == 8) {
+        if (c.S == kStMarch) {
+            body_force_z_launch<TX, TZ, VM>(a, pd, st, s);
+            return;
+        }
+    }
     const int ntiles = (pd.nx / TX) * (pd.nz / TZ);
     // the solver's update modes carry two to five vectors per system and take
     // the automatic count (the tuned count is timed in the plain mode)

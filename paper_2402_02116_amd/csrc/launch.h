@@ -42,9 +42,11 @@ struct ColCfg {
                // transformed by separate threads (Green pass only)
 };
 struct StCfg {
-    int TZ;    // tile height (rows)
-    int S;     // systems per block, 0 = chosen from the grid size
+    int TZ;    // tile height (rows), or the rows of a step of the z-marching kernel
+    int S;     // systems per block, 0 = chosen from the grid size, kStMarch = the
+               // z-marching kernel (one system per block)
 };
+constexpr int kStMarch = -1;
 struct KernelCfg {
     int row_p;   // forward row-transform points per thread
     int row_pi;  // inverse row-transform points per thread (its epilogues hold more registers)

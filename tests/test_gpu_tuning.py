@@ -116,3 +116,32 @@ def test_fused_solves_match_oracle_and_plain(nx, nz):
             plain = plan.solve(u0, rtol=1e-6, maxit=500, plain=True)
             assert torch.equal(res.x, plain.x) and np.array_equal(res.iters, plain.iters), (c, rp)
     print(f"{nx}x{nz}: {len(fuse) * len(rows)} solves, worst field error {worst:.2e}", flush=True)
+
+
+@pytest.mark.parametrize("nx,nz", [(128, 96), (96, 64)])
+def test_marching_stencil_solves_match_oracle_and_plain(nx, nz):
+    """The z-marching form of the separate stencil (stencil_sys = -1, 4- and
+    8-row steps) in every BiCGSTAB update mode: several strips and row ranges
+    per system (64- and 48-column strips), three systems, against the oracle,
+    and the batched solve bit-identical to the per-source one."""
+    from paper_2402_02116_amd.plan import Plan
+    p, maps = _case(nx, nz, 3, seed=13)
+    plan = Plan([p])
+    plan.set_contrast(0, maps)
+    src, f = W.surface_sources(nx, 3, iz=nz // 3)
+    u0 = plan.incident(src, f)
+    P = LSProblem(nx, nz, 8.0, p["c0"], p["rho0"], p["freq_hz"], 0.02, maps)
+    uref, _ = P.solve(P.incident(src, f), tol=1e-11)
+    march = [c for c in plan.tuning_candidates(0, "stencil") if c["stencil_sys"] == -1]
+    assert sorted(c["stencil_rows"] for c in march) == [4, 8]
+    for c in march:
+        plan.set_tuning(0, **dict(c, fused_points=0))
+        res = plan.solve(u0, rtol=1e-6, maxit=500)
+        assert res.status == 0 and np.all(res.relres <= 2e-6), (c, res.relres)
+        x = plan.view(res.x, 0).cpu().numpy().astype(np.complex128)
+        errs = [_rel(x[k], uref[k]) for k in range(3)]
+        print(f"{nx}x{nz} marching stencil, {c['stencil_rows']}-row steps: iterations {res.iters.tolist()}, "
+              f"field errors {max(errs):.2e}", flush=True)
+        assert max(errs) < 1e-4, (c, errs)
+        plain = plan.solve(u0, rtol=1e-6, maxit=500, plain=True)
+        assert torch.equal(res.x, plain.x) and np.array_equal(res.iters, plain.iters), c
