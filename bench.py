@@ -82,7 +82,8 @@ def _kernel_source_hash():
 
 # kernel-name test of each pass (template arguments vary with the tuned variant)
 # (the complex64 build's kernels live in namespace fw::c64)
-PASS_MATCH = [lambda n: (n.startswith("void fw::c64::k_body_force<") and ", 0>(" in n)
+PASS_MATCH = [lambda n: ((n.startswith("void fw::c64::k_body_force<") or n.startswith("void fw::c64::k_body_force_z<"))
+                         and ", 0>(" in n)
               or re.search(r"c64::\(anonymous namespace\)::k_srows<\d+, \d+, 0, \d+>\(", n) is not None,
               lambda n: n.startswith("void fw::c64::k_rows<") and ", false, 0>" in n,
               lambda n: (n.startswith("void fw::c64::k_cols<") and ", 0, " in n)
@@ -156,6 +157,8 @@ def _pass_instance(k, tuning, n=256):
         if tuning.get("fused_points"):
             # the plain mode always runs the 256-thread form
             return f"fw::c64::(anonymous namespace)::k_srows<{n}, {tuning['fused_points']}, 0, 256>"
+        if tuning.get("stencil_sys") == -1:   # the z-marching stencil
+            return f"fw::c64::k_body_force_z<64, {tuning['stencil_rows']}, 0>"
         return f"fw::c64::k_body_force<64, {tuning['stencil_rows']}, 0>"
     if k == 1:
         return f"fw::c64::k_rows<{n}, {tuning['row_points']}, false, 0>"
@@ -930,6 +933,27 @@ def main(argv=None):
         print(f"[bench] time to 1e-6: batched {tb[len(tb) // 2]:.3f} ms, plain {tp[len(tp) // 2]:.3f} ms, "
               f"iters {tbr.iters.min()}-{tbr.iters.max()}, max true relres {tbr.relres.max():.2e}, "
               f"identical results {same}", file=sys.stderr, flush=True)
+        # the batching gain alone: the same solves one source at a time through
+        # the graph-chunked path of a one-system plan with the same variants
+        # (no per-iteration host round trip, unlike the plain loop)
+        plan1 = Plan([dict(nx=nx, nz=nz, dx=c["dx"], c0=c["c0"], rho0=c["rho0"], freq_hz=c["freq_hz"],
+                           eta=c["eta"], nsys=1)], device="cuda:0")
+        plan1.set_contrast(0, c["maps"])
+        plan1.set_tuning(0, **{k: v for k, v in plan.tuning(0).items() if k != "time_us"})
+        if a.krylov == "gmres":
+            plan1.set_krylov("gmres", restart=a.restart, cgs2=not a.cgs1)
+        u0s = [plan1.incident([c["src_ixz"][k]], [c["src_f"][k]]) for k in range(ns)]
+        def per_source_graph():
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            its = [int(plan1.solve(u, rtol=RTOL, maxit=1000).iters[0]) for u in u0s]
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t) * 1e3, its
+        per_source_graph()
+        tg = sorted(per_source_graph()[0] for _ in range(3))
+        del plan1, u0s
+        print(f"[bench] time to 1e-6, one source at a time through the graph path: {tg[1]:.3f} ms",
+              file=sys.stderr, flush=True)
 
     # isolated batched matvec and its four kernels, HIP events on the plan's stream
     u = tbr.x
@@ -1049,6 +1073,8 @@ def main(argv=None):
                time_to_1e6_ms=dict(batched=round(tb[len(tb) // 2], 3), plain=round(tp[len(tp) // 2], 3),
                                    plain_krylov=plain_krylov,
                                    speedup=round(tp[len(tp) // 2] / tb[len(tb) // 2], 2),
+                                   per_source_graph=round(tg[1], 3),
+                                   speedup_vs_per_source_graph=round(tg[1] / tb[len(tb) // 2], 2),
                                    iters=[int(tbr.iters.min()), int(tbr.iters.max())],
                                    max_true_relres=float(tbr.relres.max()), identical=same,
                                    criterion="recursive residual <= 1e-6 and true residual <= 2e-6"),

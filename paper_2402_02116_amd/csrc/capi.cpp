@@ -56,6 +56,9 @@ void set_error(const char* fmt, ...) {
     } while (0)
 
 constexpr int kMaxRec = 65536;
+// per problem: receiver cells [kMaxRec][3], then the receivers in stable cell
+// order [kMaxRec] and the run lengths of receivers sharing a cell [kMaxRec]
+constexpr int kRecInts = 5;
 constexpr int kChunkIters = 4;        // iterations per graph chunk (even: p buffers alternate)
 constexpr int kNumVec = 11;           // field-sized workspace vectors
 constexpr int kMaxRestarts = 3;       // restarts from the true residual per solve
@@ -144,6 +147,12 @@ struct fwils_plan_s {
 };
 
 namespace {
+
+// receiver cells of problem i in the workspace, then its receivers in stable
+// cell order and the run lengths of receivers sharing a cell
+int32_t* rec_at(fwils_plan plan, size_t i) { return plan->rec + i * (size_t)kMaxRec * kRecInts; }
+int32_t* rec_perm(fwils_plan plan, size_t i) { return rec_at(plan, i) + (size_t)kMaxRec * 3; }
+int32_t* rec_glen(fwils_plan plan, size_t i) { return rec_at(plan, i) + (size_t)kMaxRec * 4; }
 
 ProbDev make_dev(const fwils_problem& p) {
     ProbDev d;
@@ -806,7 +815,7 @@ void layout_plan(fwils_plan pl) {
     pl->off_maps = o;
     o = align256(o + pl->maps_floats * sizeof(real));
     pl->off_rec = o;
-    o = align256(o + (size_t)nprob * kMaxRec * 3 * sizeof(int32_t));
+    o = align256(o + (size_t)nprob * kMaxRec * kRecInts * sizeof(int32_t));
     pl->off_src = o;   // source cells, then (256-byte aligned) source forces
     o = align256(o + align256(pl->total_sys * 3 * sizeof(int32_t)) + pl->total_sys * 3 * sizeof(double));
     pl->off_vec = o;
@@ -1155,9 +1164,28 @@ fwils_status fwils_set_receivers(fwils_plan plan, int32_t iprob, const int32_t* 
             return FWILS_EINVAL;
         }
     }
+    // the receivers in stable order of their cells, and the length of each run
+    // of receivers on one cell at its first entry (the adjoint scatter sums a
+    // run in one thread, in receiver order)
+    std::vector<int64_t> cell(nrec);
+    for (int r = 0; r < nrec; ++r) {
+        const int ix = rec_ixz[cs * r], iz = rec_ixz[cs * r + cs - 1], iy = cs == 3 ? rec_ixz[cs * r + 1] : 0;
+        cell[r] = ((int64_t)iz * P.ny + iy) * P.p.nx + ix;
+    }
+    std::vector<int32_t> perm(nrec), glen(nrec, 0);
+    for (int r = 0; r < nrec; ++r) perm[r] = r;
+    std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) { return cell[a] < cell[b]; });
+    for (int k = 0; k < nrec;) {
+        int e = k + 1;
+        while (e < nrec && cell[perm[e]] == cell[perm[k]]) ++e;
+        glen[k] = e - k;
+        k = e;
+    }
     FW_HIP(hipStreamSynchronize(plan->stream));
-    FW_HIP(hipMemcpy(plan->rec + (size_t)iprob * kMaxRec * 3, rec_ixz, (size_t)nrec * cs * sizeof(int32_t),
+    FW_HIP(hipMemcpy(rec_at(plan, iprob), rec_ixz, (size_t)nrec * cs * sizeof(int32_t),
                      hipMemcpyHostToDevice));
+    FW_HIP(hipMemcpy(rec_perm(plan, iprob), perm.data(), (size_t)nrec * sizeof(int32_t), hipMemcpyHostToDevice));
+    FW_HIP(hipMemcpy(rec_glen(plan, iprob), glen.data(), (size_t)nrec * sizeof(int32_t), hipMemcpyHostToDevice));
     P.nrec = nrec;
     size_t doff = 0;
     for (ProbHost& Q : plan->probs) {
@@ -1314,7 +1342,7 @@ namespace {
 // d = R w for problem i (either dimension).
 hipError_t gather_any(fwils_plan plan, size_t i, const cplx* w, cplx* d, hipStream_t s) {
     const ProbHost& P = plan->probs[i];
-    const int32_t* rec = plan->rec + i * kMaxRec * 3;
+    const int32_t* rec = rec_at(plan, i);
     return P.d3 ? launch_gather3(w, d, rec, P.nrec, P.dev3, s) : launch_gather(w, d, rec, P.nrec, P.dev, s);
 }
 
@@ -1349,11 +1377,11 @@ fwils_status adjoint_ws(fwils_plan plan, const void* ub, const void* r, void* co
         cplx* f = at(plan->s, P);
         FW_HIP(launch_zero(f, (size_t)P.p.nsys * P.n_per_sys, s));
         if (P.d3)
-            FW_HIP(launch_scatter_conj3(static_cast<const cplx*>(r) + P.data_off, f, plan->rec + i * kMaxRec * 3,
-                                        P.nrec, P.dev3, s));
+            FW_HIP(launch_scatter_conj3(static_cast<const cplx*>(r) + P.data_off, f, rec_at(plan, i),
+                                        rec_perm(plan, i), rec_glen(plan, i), P.nrec, P.dev3, s));
         else
-            FW_HIP(launch_scatter_conj(static_cast<const cplx*>(r) + P.data_off, f, plan->rec + i * kMaxRec * 3,
-                                       P.nrec, P.dev, s));
+            FW_HIP(launch_scatter_conj(static_cast<const cplx*>(r) + P.data_off, f, rec_at(plan, i),
+                                       rec_perm(plan, i), rec_glen(plan, i), P.nrec, P.dev, s));
         FW_HIP(conv_problem(plan, P, f, at(plan->rhs, P)));
     }
     fwils_status st = solve_ws(plan, plan->rhs, false, rtol, maxit, nullptr, nullptr, 0);

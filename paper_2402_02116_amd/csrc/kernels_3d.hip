@@ -932,24 +932,35 @@ hipError_t launch_gather3(const cplx* w, cplx* d, const int32_t* rec, int nrec, 
 
 // f (zero on entry) += conj(d) at the receivers; one thread per (sys, c) walks
 // the receivers in order, so repeated receivers add deterministically.
+// f += R^T conj(d) with the receivers in the host's stable cell order (perm,
+// run lengths glen): one thread per (system, run, component), each run
+// summed in receiver order.
 __global__ void k_scatter_conj3(const cplx* __restrict__ d, cplx* __restrict__ f, const int32_t* __restrict__ rec,
-                                int nrec, ProbDev3 pd) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= pd.nsys * 3) return;
-    const int sys = i / 3, c = i % 3;
+                                const int32_t* __restrict__ perm, const int32_t* __restrict__ glen, int nrec,
+                                ProbDev3 pd) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)pd.nsys * nrec * 3) return;
+    const int c = (int)(i % 3);
+    const size_t q = i / 3;
+    const int k = (int)(q % nrec), sys = (int)(q / nrec);
+    const int n = glen[k];
+    if (n == 0) return;
+    const cplx* ds = d + (size_t)sys * nrec * 3 + c;
+    const int r0 = perm[k];
+    cplx acc = cconj(ds[3 * (size_t)r0]);
+    for (int j = 1; j < n; ++j) acc = cadd(acc, cconj(ds[3 * (size_t)perm[k + j]]));
     const size_t cells = (size_t)pd.nx * pd.ny * pd.nz;
     cplx* fs = f + (size_t)sys * 3 * cells + c * cells;
-    for (int r = 0; r < nrec; ++r) {
-        const cplx dv = d[((size_t)sys * nrec + r) * 3 + c];
-        const size_t g = ((size_t)rec[3 * r + 2] * pd.ny + rec[3 * r + 1]) * pd.nx + rec[3 * r];
-        fs[g] = cadd(fs[g], cconj(dv));
-    }
+    const size_t g = ((size_t)rec[3 * r0 + 2] * pd.ny + rec[3 * r0 + 1]) * pd.nx + rec[3 * r0];
+    fs[g] = cadd(fs[g], acc);
 }
 
-hipError_t launch_scatter_conj3(const cplx* d, cplx* f, const int32_t* rec, int nrec, const ProbDev3& pd,
-                                hipStream_t s) {
-    const int total = pd.nsys * 3;
-    hipLaunchKernelGGL(k_scatter_conj3, dim3((total + 63) / 64), dim3(64), 0, s, d, f, rec, nrec, pd);
+hipError_t launch_scatter_conj3(const cplx* d, cplx* f, const int32_t* rec, const int32_t* perm,
+                                const int32_t* glen, int nrec, const ProbDev3& pd, hipStream_t s) {
+    const size_t total = (size_t)pd.nsys * nrec * 3;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scatter_conj3, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, d, f, rec, perm, glen,
+                       nrec, pd);
     return hipGetLastError();
 }
 

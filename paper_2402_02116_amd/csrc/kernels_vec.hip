@@ -229,9 +229,9 @@ __global__ __launch_bounds__(256) void k_body_force(const cplx* __restrict__ u,
 // The same stencil marching along z: a block owns a TX-column strip over the
 // row range [z0, z0 + ZR) of one system and walks it TZ rows at a time (TZ/4
 // rows per thread).  LDS holds the input rows in a ring of RU rows and the
-// stress rows in a ring of RS rows; the raw vectors of the next TZ input
-// rows, and the maps of the next step's stress rows, are in flight in
-// registers while a step computes.  Step at row z: the input rows z+2 ..
+// stress rows in a ring of RS rows; the raw vectors of the input rows of the
+// next one to three steps, and the maps of the next step's stress rows, are
+// in flight in registers while a step computes.  Step at row z: the input rows z+2 ..
 // z+TZ+1 enter the ring (own cells of the range write the updated vectors),
 // the stress of rows z+1 .. z+TZ is formed, then b on rows z .. z+TZ-1.  Each
 // input row of the range is read once, plus four halo rows per range, instead
@@ -243,6 +243,9 @@ struct MarchZ2 {
     static constexpr int KB = TZ / 4;                  // rows per thread per step
     static constexpr int RU = TZ == 4 ? 16 : 32;       // input ring rows
     static constexpr int RS = TZ == 4 ? 8 : 16;        // stress ring rows
+    // steps of raw rows in flight: more where a step loads few bytes
+    template <int VM>
+    static constexpr int depth() { return TZ == 8 ? 1 : VM == VM_NONE ? 3 : VM == VM_PX ? 1 : 2; }
 };
 
 template <int TX, int TZ, int VM>
@@ -484,20 +487,25 @@ __global__ __launch_bounds__(256) void k_body_force_z(const cplx* __restrict__ u
             if (slane) stress_at(z0 - 1 + tg, hsx, mh);
         }
     }
-    Rows RA;
-    load_rows(RA, z0 + 2);
+    // PD steps of raw rows in flight (buffers used in turn: the step loop is
+    // unrolled by PD so that no register of a load in flight is moved)
+    constexpr int PD = MarchZ2<TZ>::template depth<VM>();
+    Rows R[PD];
+#pragma unroll
+    for (int j = 0; j < PD; ++j)
+        if (z0 + j * TZ < z1) load_rows(R[j], z0 + j * TZ + 2);
     SMaps mc, mn;
     load_smaps(mc, z0 + 1);
     real rc[KB], rn[KB];
 #pragma unroll
     for (int k = 0; k < KB; ++k) rc[k] = lane ? maps[4 * plane + rowoff(z0 + tg + 4 * k) + gxo] : 0.f;
     const real sc = pd.inv4dx2;
-    for (int z = z0; z < z1; z += TZ) {
-        // the new input rows enter the ring; the next step's rows and maps are issued
+    auto row_step = [&](int z, Rows& RA) {
+        // the new input rows enter the ring; later rows and the next step's maps are issued
         put_rows(RA, z + 2);
+        if (z + PD * TZ < z1) load_rows(RA, z + PD * TZ + 2);
         const bool more = z + TZ < z1;
         if (more) {
-            load_rows(RA, z + TZ + 2);
             load_smaps(mn, z + TZ + 1);
 #pragma unroll
             for (int k = 0; k < KB; ++k) rn[k] = lane ? maps[4 * plane + rowoff(z + TZ + tg + 4 * k) + gxo] : 0.f;
@@ -541,6 +549,11 @@ __global__ __launch_bounds__(256) void k_body_force_z(const cplx* __restrict__ u
                 }
             }
         }
+    };
+    for (int z = z0; z < z1; z += PD * TZ) {
+#pragma unroll
+        for (int j = 0; j < PD; ++j)
+            if (z + j * TZ < z1) row_step(z + j * TZ, R[j]);   // uniform over the block
     }
 }
 
@@ -1006,24 +1019,37 @@ hipError_t launch_gather(const cplx* w, cplx* d, const int32_t* rec_ixz, int nre
 
 // f (zero on entry) += conj(d) at the receivers; one thread per (sys, c)
 // walks the receivers in order, so repeated receivers add deterministically.
+// f += R^T conj(d) (the adjoint source of eq. ua0).  Receivers are taken in
+// the stable cell order the host built (perm) with the length of each run of
+// receivers on one cell at the run's first entry (glen, 0 elsewhere): one
+// thread per (system, run, component) sums its run in receiver order, so the
+// result does not depend on the launch.
 __global__ void k_scatter_conj(const cplx* __restrict__ d, cplx* __restrict__ f,
-                               const int32_t* __restrict__ rec, int nrec, ProbDev pd) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= pd.nsys * 2) return;
-    const int sys = i >> 1, c = i & 1;
+                               const int32_t* __restrict__ rec, const int32_t* __restrict__ perm,
+                               const int32_t* __restrict__ glen, int nrec, ProbDev pd) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)pd.nsys * nrec * 2) return;
+    const int c = (int)(i & 1);
+    const size_t q = i >> 1;
+    const int k = (int)(q % nrec), sys = (int)(q / nrec);
+    const int n = glen[k];
+    if (n == 0) return;
+    const cplx* ds = d + (size_t)sys * nrec * 2 + c;
+    const int r0 = perm[k];
+    cplx acc = cconj(ds[2 * (size_t)r0]);
+    for (int j = 1; j < n; ++j) acc = cadd(acc, cconj(ds[2 * (size_t)perm[k + j]]));
     const size_t plane = (size_t)pd.nx * pd.nz;
     cplx* fs = f + (size_t)sys * 2 * plane + c * plane;
-    for (int r = 0; r < nrec; ++r) {
-        const cplx dv = d[((size_t)sys * nrec + r) * 2 + c];
-        const size_t gi = (size_t)rec[2 * r + 1] * pd.nx + rec[2 * r];
-        fs[gi] = cadd(fs[gi], cconj(dv));
-    }
+    const size_t gi = (size_t)rec[2 * r0 + 1] * pd.nx + rec[2 * r0];
+    fs[gi] = cadd(fs[gi], acc);
 }
 
-hipError_t launch_scatter_conj(const cplx* d, cplx* f, const int32_t* rec_ixz, int nrec,
-                               const ProbDev& pd, hipStream_t s) {
-    const int total = pd.nsys * 2;
-    hipLaunchKernelGGL(k_scatter_conj, dim3((total + 63) / 64), dim3(64), 0, s, d, f, rec_ixz, nrec, pd);
+hipError_t launch_scatter_conj(const cplx* d, cplx* f, const int32_t* rec_ixz, const int32_t* perm,
+                               const int32_t* glen, int nrec, const ProbDev& pd, hipStream_t s) {
+    const size_t total = (size_t)pd.nsys * nrec * 2;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scatter_conj, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, d, f, rec_ixz, perm,
+                       glen, nrec, pd);
     return hipGetLastError();
 }
 
@@ -1031,49 +1057,66 @@ hipError_t launch_scatter_conj(const cplx* d, cplx* f, const int32_t* rec_ixz, i
 // g_rho = conj(w~^2 sum_sys u^a . u^b); g_p = -conj(sum_sys eps^a . B^p eps^b),
 // with the 2-D B matrices of the maps (C11, C13, C33, C55):
 //   B11 -> e1 e1,  B13 -> e1 e3 + e3 e1,  B33 -> e3 e3,  B55 -> e5 e5.
+// A block covers 64 cells; its four thread groups take every fourth system
+// and their FP64 sums are added in group order (a fixed order: the result
+// does not depend on the launch).
 template <class OUT>
 __global__ __launch_bounds__(256) void k_correlate(const cplx* __restrict__ ua,
                                                    const cplx* __restrict__ ub,
                                                    OUT* __restrict__ g, ProbDev pd, int accumulate) {
+    constexpr int NA = 10;   // accumulators: rho, B11, B13, B33, B55 (re, im)
+    __shared__ double red[3][NA][64];
     const int nx = pd.nx, nz = pd.nz;
     const size_t plane = (size_t)nx * nz;
-    const int cell = blockIdx.x * blockDim.x + threadIdx.x;
-    if (cell >= (int)plane) return;
-    const int z = cell / nx, x = cell - z * nx;
+    const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+    const int cell = blockIdx.x * 64 + lane;
+    const bool live = cell < (int)plane;
+    const int cc = live ? cell : 0;
+    const int z = cc / nx, x = cc - z * nx;
     const int xp = (x + 1 == nx) ? 0 : x + 1, xm = (x == 0) ? nx - 1 : x - 1;
     const int zp = (z + 1 == nz) ? 0 : z + 1, zm = (z == 0) ? nz - 1 : z - 1;
-    const size_t ic = cell, ixp = (size_t)z * nx + xp, ixm = (size_t)z * nx + xm;
+    const size_t ic = cc, ixp = (size_t)z * nx + xp, ixm = (size_t)z * nx + xm;
     const size_t izp = (size_t)zp * nx + x, izm = (size_t)zm * nx + x;
-    double rr = 0, ri = 0, a11r = 0, a11i = 0, a13r = 0, a13i = 0, a33r = 0, a33i = 0, a55r = 0,
-           a55i = 0;
-    for (int s = 0; s < pd.nsys; ++s) {
+    double acc[NA] = {};
+    for (int s = grp; s < pd.nsys; s += 4) {
         const cplx* A = ua + (size_t)s * 2 * plane;
         const cplx* B = ub + (size_t)s * 2 * plane;
         const cplx ax = A[ic], az = A[plane + ic], bx = B[ic], bz = B[plane + ic];
-        rr += (double)ax.x * bx.x - (double)ax.y * bx.y + (double)az.x * bz.x - (double)az.y * bz.y;
-        ri += (double)ax.x * bx.y + (double)ax.y * bx.x + (double)az.x * bz.y + (double)az.y * bz.x;
+        acc[0] += (double)ax.x * bx.x - (double)ax.y * bx.y + (double)az.x * bz.x - (double)az.y * bz.y;
+        acc[1] += (double)ax.x * bx.y + (double)ax.y * bx.x + (double)az.x * bz.y + (double)az.y * bz.x;
         const cplx e1a = csub(A[ixp], A[ixm]);
         const cplx e3a = csub(A[plane + izp], A[plane + izm]);
         const cplx e5a = cadd(csub(A[izp], A[izm]), csub(A[plane + ixp], A[plane + ixm]));
         const cplx e1b = csub(B[ixp], B[ixm]);
         const cplx e3b = csub(B[plane + izp], B[plane + izm]);
         const cplx e5b = cadd(csub(B[izp], B[izm]), csub(B[plane + ixp], B[plane + ixm]));
-        a11r += (double)e1a.x * e1b.x - (double)e1a.y * e1b.y;
-        a11i += (double)e1a.x * e1b.y + (double)e1a.y * e1b.x;
-        a13r += (double)e1a.x * e3b.x - (double)e1a.y * e3b.y + (double)e3a.x * e1b.x - (double)e3a.y * e1b.y;
-        a13i += (double)e1a.x * e3b.y + (double)e1a.y * e3b.x + (double)e3a.x * e1b.y + (double)e3a.y * e1b.x;
-        a33r += (double)e3a.x * e3b.x - (double)e3a.y * e3b.y;
-        a33i += (double)e3a.x * e3b.y + (double)e3a.y * e3b.x;
-        a55r += (double)e5a.x * e5b.x - (double)e5a.y * e5b.y;
-        a55i += (double)e5a.x * e5b.y + (double)e5a.y * e5b.x;
+        acc[2] += (double)e1a.x * e1b.x - (double)e1a.y * e1b.y;
+        acc[3] += (double)e1a.x * e1b.y + (double)e1a.y * e1b.x;
+        acc[4] += (double)e1a.x * e3b.x - (double)e1a.y * e3b.y + (double)e3a.x * e1b.x - (double)e3a.y * e1b.y;
+        acc[5] += (double)e1a.x * e3b.y + (double)e1a.y * e3b.x + (double)e3a.x * e1b.y + (double)e3a.y * e1b.x;
+        acc[6] += (double)e3a.x * e3b.x - (double)e3a.y * e3b.y;
+        acc[7] += (double)e3a.x * e3b.y + (double)e3a.y * e3b.x;
+        acc[8] += (double)e5a.x * e5b.x - (double)e5a.y * e5b.y;
+        acc[9] += (double)e5a.x * e5b.y + (double)e5a.y * e5b.x;
     }
+    if (grp > 0) {
+#pragma unroll
+        for (int k = 0; k < NA; ++k) red[grp - 1][k][lane] = acc[k];
+    }
+    __syncthreads();
+    if (grp > 0 || !live) return;
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int k = 0; k < NA; ++k) acc[k] += red[j][k][lane];
+    const double rr = acc[0], ri = acc[1];
     const double s = (double)pd.inv4dx2;
     const double wr = pd.w2.x, wi = pd.w2.y;
     // conj(w2 * rho) ; -conj(a) * s
-    const double out[5][2] = {{-a11r * s, a11i * s},
-                              {-a13r * s, a13i * s},
-                              {-a33r * s, a33i * s},
-                              {-a55r * s, a55i * s},
+    const double out[5][2] = {{-acc[2] * s, acc[3] * s},
+                              {-acc[4] * s, acc[5] * s},
+                              {-acc[6] * s, acc[7] * s},
+                              {-acc[8] * s, acc[9] * s},
                               {wr * rr - wi * ri, -(wr * ri + wi * rr)}};
 #pragma unroll
     for (int p = 0; p < 5; ++p) {
@@ -1088,7 +1131,7 @@ __global__ __launch_bounds__(256) void k_correlate(const cplx* __restrict__ ua,
 hipError_t launch_correlate(const cplx* ua, const cplx* ub, cplx* g, const ProbDev& pd,
                             bool accumulate, hipStream_t s) {
     const int cells = pd.nx * pd.nz;
-    hipLaunchKernelGGL(k_correlate<cplx>, dim3((cells + 255) / 256), dim3(256), 0, s, ua, ub, g, pd,
+    hipLaunchKernelGGL(k_correlate<cplx>, dim3((cells + 63) / 64), dim3(256), 0, s, ua, ub, g, pd,
                        accumulate ? 1 : 0);
     return hipGetLastError();
 }
@@ -1096,7 +1139,7 @@ hipError_t launch_correlate(const cplx* ua, const cplx* ub, cplx* g, const ProbD
 hipError_t launch_correlate_f64(const cplx* ua, const cplx* ub, double2* g, const ProbDev& pd,
                                 bool accumulate, hipStream_t s) {
     const int cells = pd.nx * pd.nz;
-    hipLaunchKernelGGL(k_correlate<double2>, dim3((cells + 255) / 256), dim3(256), 0, s, ua, ub, g, pd,
+    hipLaunchKernelGGL(k_correlate<double2>, dim3((cells + 63) / 64), dim3(256), 0, s, ua, ub, g, pd,
                        accumulate ? 1 : 0);
     return hipGetLastError();
 }

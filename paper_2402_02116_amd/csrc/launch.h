@@ -189,8 +189,10 @@ hipError_t launch_axis3(int mode, int n, cplx* data, int S, int nslab, int slabs
 hipError_t launch_point_sources3(cplx* f, const int32_t* src_ixyz, const double* src_f, const ProbDev3& pd,
                                  hipStream_t s);
 hipError_t launch_gather3(const cplx* w, cplx* d, const int32_t* rec, int nrec, const ProbDev3& pd, hipStream_t s);
-hipError_t launch_scatter_conj3(const cplx* d, cplx* f, const int32_t* rec, int nrec, const ProbDev3& pd,
-                                hipStream_t s);
+// f += R^T conj(d); perm / glen: the receivers in stable cell order and the
+// run lengths of receivers sharing a cell (at each run's first entry, else 0).
+hipError_t launch_scatter_conj3(const cplx* d, cplx* f, const int32_t* rec, const int32_t* perm,
+                                const int32_t* glen, int nrec, const ProbDev3& pd, hipStream_t s);
 // J* correlation of eq. ad1 into FP64 complex maps [NS + 1][nz][ny][nx].
 hipError_t launch_correlate3(const cplx* ua, const cplx* ub, double2* g, const ProbDev3& pd, bool accumulate,
                              hipStream_t s);
@@ -243,8 +245,8 @@ hipError_t launch_point_sources(cplx* f, const int32_t* src_ixz, const double* s
                                 const ProbDev& pd, hipStream_t s);
 hipError_t launch_gather(const cplx* w, cplx* d, const int32_t* rec_ixz, int nrec,
                          const ProbDev& pd, hipStream_t s);
-hipError_t launch_scatter_conj(const cplx* d, cplx* f, const int32_t* rec_ixz, int nrec,
-                               const ProbDev& pd, hipStream_t s);
+hipError_t launch_scatter_conj(const cplx* d, cplx* f, const int32_t* rec_ixz, const int32_t* perm,
+                               const int32_t* glen, int nrec, const ProbDev& pd, hipStream_t s);
 hipError_t launch_correlate(const cplx* ua, const cplx* ub, cplx* g, const ProbDev& pd,
                             bool accumulate, hipStream_t s);
 // The same correlation into FP64 complex maps (the Tikhonov step's
