@@ -22,14 +22,14 @@ static const int kTwSizes[] = {16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 
 // thread, so they default to 8 (radix 8) to keep registers low and the
 // thread count high.  Each size also has one alternative per pass kind.
 // The complex128 build has the default variants only.
-int row_points_default(int n) { return (n % 5 == 0) ? (n <= 40 ? 10 : 20) : (n % 3 == 0) ? 12 : 16; }
+int row_points_default(int n) { return (n % 5 == 0) ? 10 : (n % 3 == 0) ? 12 : 16; }
 static int col_points_default(int n) { return (n % 3 == 0) ? 12 : 8; }
 #ifdef FW_C128
 static int row_points_alt(int n) { return row_points_default(n); }
 static int col_points_alt(int n) { return col_points_default(n); }
 static int points_radix32(int) { return 0; }
 #else
-static int row_points_alt(int n) { return (n % 5 == 0) ? row_points_default(n) : (n % 3 == 0) ? 24 : 8; }
+static int row_points_alt(int n) { return (n % 5 == 0) ? (n > 40 ? 20 : 10) : (n % 3 == 0) ? 24 : 8; }
 static int col_points_alt(int n) { return (n % 3 == 0) ? 24 : 16; }
 // A third row-pass variant for 512- and 1024-point rows: 32 points per
 // thread, radix-32 passes (32 x 32 at 1024 points: one LDS exchange per

@@ -9,14 +9,15 @@ FW_BEGIN
 #ifdef FW_C128
 #define FW_ROW_VARIANTS(X)                                                                           \
     X(16, 16) X(24, 12) X(32, 16) X(48, 12) X(64, 16) X(96, 12) X(128, 16) X(192, 12) X(256, 16)     \
-    X(384, 12) X(512, 16) X(768, 12) X(1024, 16) X(1536, 12) X(2048, 16) X(20, 10) X(40, 10) X(80, 20)  \
-    X(160, 20)
+    X(384, 12) X(512, 16) X(768, 12) X(1024, 16) X(1536, 12) X(2048, 16) X(20, 10) X(40, 10) X(80, 10)  \
+    X(160, 10)
 #else
 #define FW_ROW_VARIANTS(X)                                                                          \
     X(16, 16) X(16, 8) X(24, 12) X(24, 24) X(32, 16) X(32, 8) X(48, 12) X(48, 24) X(64, 16) X(64, 8) \
     X(96, 12) X(96, 24) X(128, 16) X(128, 8) X(192, 12) X(192, 24) X(256, 16) X(256, 8) X(384, 12)  \
     X(384, 24) X(512, 16) X(512, 8) X(768, 12) X(768, 24) X(1024, 16) X(1024, 8) X(1536, 12)         \
-    X(1536, 24) X(2048, 16) X(2048, 8) X(512, 32) X(1024, 32) X(20, 10) X(40, 10) X(80, 20) X(160, 20)
+    X(1536, 24) X(2048, 16) X(2048, 8) X(512, 32) X(1024, 32) X(20, 10) X(40, 10) X(80, 10) X(80, 20)       \
+    X(160, 10) X(160, 20)
 #endif
 
 hipError_t launch_rows_fwd(int n, int P, const cplx* in, cplx* out, int nrows, int rps, SpecLayout lay,
