@@ -378,24 +378,35 @@ __global__ __launch_bounds__(TX * TY) void k_stencil3z(const cplx* __restrict__ 
         step = stencil_scalars<VM>(st, sys, part, np, red, col == 0 && t == 0, c1, c2, c3, fresh);
         if (step == SS_SKIP) return;
     }
+    // this system's vectors; offsets within a system fit 32 bits (3 x 256^3)
     const size_t so = (size_t)sys * 3 * cells;
-    const size_t plane_sz = (size_t)nx * ny;
-    auto zoff = [&](int z) -> size_t { return (size_t)wrapm(z, nz) * plane_sz; };
-    const size_t xy0 = (size_t)wrapm(y0 + ty, ny) * nx + wrapm(x0 + tx, nx);
+    const cplx* __restrict__ us = u + so;
+    const cplx* __restrict__ a1s = a1 + so;
+    const cplx* __restrict__ a2s = a2 + so;
+    const cplx* __restrict__ a3s = a3 + so;
+    cplx* __restrict__ wos = wout + so;
+    cplx* __restrict__ rhs = rhat + so;
+    cplx* __restrict__ xs = xio + so;
+    cplx* __restrict__ ros = rout + so;
+    cplx* __restrict__ bs = b + so;
+    const uint32_t cells32 = (uint32_t)cells, plane32 = (uint32_t)nx * (uint32_t)ny;
+    // planes z0-2 .. z1+3 lie within one period of the axis
+    auto zoff = [&](int z) -> uint32_t { return (uint32_t)(z < 0 ? z + nz : (z >= nz ? z - nz : z)) * plane32; };
+    const uint32_t xy0 = (uint32_t)wrapm(y0 + ty, ny) * nx + wrapm(x0 + tx, nx);
 
     if constexpr (VM == VM_PX) {
         if (step == SS_XONLY) {   // stopped: the last solution update only
             if (own_xy)
                 for (int z = z0; z < z1; ++z) {
-                    const size_t g = zoff(z) + xy0;
+                    const uint32_t g = zoff(z) + xy0;
 #pragma unroll
                     for (int c = 0; c < 3; ++c) {
-                        const size_t gi = so + c * cells + g;
-                        const cplx sv = u[gi], tv = a3[gi], pv = a1[gi];
+                        const uint32_t gi = c * cells32 + g;
+                        const cplx sv = us[gi], tv = a3s[gi], pv = a1s[gi];
                         const cplx rv = close_r(sv, tv, c2);
-                        rout[gi] = rv;
-                        xio[gi] = close_x(xio[gi], pv, sv, c3, c2);
-                        if (fresh) rhat[gi] = rv;
+                        ros[gi] = rv;
+                        xs[gi] = close_x(xs[gi], pv, sv, c3, c2);
+                        if (fresh) rhs[gi] = rv;
                     }
                 }
             return;
@@ -407,25 +418,25 @@ __global__ __launch_bounds__(TX * TY) void k_stencil3z(const cplx* __restrict__ 
     int hx1 = 2, hy1 = 2;
     if (has1) ring_cell<TX, TY>(t, hx1, hy1);
     const bool st1 = has1 && hx1 >= 1 && hx1 <= TX + 2 && hy1 >= 1 && hy1 <= TY + 2;   // inner ring: stress
-    const size_t xy1 = (size_t)wrapm(y0 - 2 + hy1, ny) * nx + wrapm(x0 - 2 + hx1, nx);
+    const uint32_t xy1 = (uint32_t)wrapm(y0 - 2 + hy1, ny) * nx + wrapm(x0 - 2 + hx1, nx);
     const int h0 = (ty + 2) * M::HX + tx + 2, h1 = hy1 * M::HX + hx1;
     const int q0 = (ty + 1) * M::SX + tx + 1, q1 = (hy1 - 1) * M::SX + hx1 - 1;
 
     using Raw = cplx[NV][3];
-    auto load_raw = [&](Raw& r, size_t g) {
+    auto load_raw = [&](Raw& r, uint32_t g) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            const size_t gi = so + c * cells + g;
-            r[0][c] = u[gi];
+            const uint32_t gi = c * cells32 + g;
+            r[0][c] = us[gi];
             if constexpr (VM == VM_P) {
-                r[1][c] = a1[gi];
-                r[2][c] = a2[gi];
+                r[1][c] = a1s[gi];
+                r[2][c] = a2s[gi];
             } else if constexpr (VM == VM_PX) {
-                r[1][c] = a3[gi];
-                r[2][c] = a1[gi];
-                r[3][c] = a2[gi];
+                r[1][c] = a3s[gi];
+                r[2][c] = a1s[gi];
+                r[3][c] = a2s[gi];
             } else if constexpr (VM == VM_S) {
-                r[1][c] = a1[gi];
+                r[1][c] = a1s[gi];
             }
         }
     };
@@ -448,18 +459,18 @@ __global__ __launch_bounds__(TX * TY) void k_stencil3z(const cplx* __restrict__ 
     auto write_own = [&](const Raw& r, const cplx (&f)[3], const cplx (&xv)[3], int z) {
         if constexpr (VM != VM_NONE) {
             if (!own_xy || z < z0 || z >= z1) return;
-            const size_t g = zoff(z) + xy0;
+            const uint32_t g = zoff(z) + xy0;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const size_t gi = so + c * cells + g;
-                wout[gi] = f[c];
+                const uint32_t gi = c * cells32 + g;
+                wos[gi] = f[c];
                 if constexpr (VM == VM_P) {
-                    if (fresh) rhat[gi] = f[c];
+                    if (fresh) rhs[gi] = f[c];
                 } else if constexpr (VM == VM_PX) {
                     const cplx rv = close_r(r[0][c], r[1][c], c2);
-                    rout[gi] = rv;
-                    xio[gi] = close_x(xv[c], r[2][c], r[0][c], c3, c2);
-                    if (fresh) rhat[gi] = rv;
+                    ros[gi] = rv;
+                    xs[gi] = close_x(xv[c], r[2][c], r[0][c], c3, c2);
+                    if (fresh) rhs[gi] = rv;
                 }
             }
         }
@@ -467,15 +478,15 @@ __global__ __launch_bounds__(TX * TY) void k_stencil3z(const cplx* __restrict__ 
     auto load_x = [&](cplx (&xv)[3], int z) {
         if constexpr (VM == VM_PX) {
             if (own_xy && z >= z0 && z < z1) {
-                const size_t g = so + zoff(z) + xy0;
+                const uint32_t g = zoff(z) + xy0;
 #pragma unroll
-                for (int c = 0; c < 3; ++c) xv[c] = xio[g + c * cells];
+                for (int c = 0; c < 3; ++c) xv[c] = xs[g + c * cells32];
             }
         }
     };
-    auto load_maps = [&](real (&m)[NS], size_t g) {
+    auto load_maps = [&](real (&m)[NS], uint32_t g) {
 #pragma unroll
-        for (int p = 0; p < NS; ++p) m[p] = maps[(size_t)p * cells + g];
+        for (int p = 0; p < NS; ++p) m[p] = maps[p * cells32 + g];
     };
     // s' = dC e' at LDS input position h of the current plane; z differences
     // from the planes below (lo) and above (hi)
@@ -584,7 +595,7 @@ __global__ __launch_bounds__(TX * TY) void k_stencil3z(const cplx* __restrict__ 
         load_maps(mn0, zoff(z0 + 2) + xy0);
         if (st1) load_maps(mn1, zoff(z0 + 2) + xy1);
     }
-    const real* rho = maps + (size_t)NS * cells;
+    const real* rho = maps + (size_t)NS * cells;   // (uint32 offsets below)
     real rho_z = rho[zoff(z0) + xy0], rho_1 = rho[zoff(z0 + 1) + xy0], rho_2 = rho[zoff(z0 + 2) + xy0];
     __syncthreads();
 
@@ -605,11 +616,11 @@ __global__ __launch_bounds__(TX * TY) void k_stencil3z(const cplx* __restrict__ 
             const cplx bx = cadd(cadd(dxy(0, 1), dxy(5, M::SX)), csub(s0[4], sold[4]));
             const cplx by = cadd(cadd(dxy(5, 1), dxy(1, M::SX)), csub(s0[3], sold[3]));
             const cplx bz = cadd(cadd(dxy(4, 1), dxy(3, M::SX)), csub(s0[2], sold[2]));
-            const size_t g = so + zoff(z) + xy0;
+            const uint32_t g = zoff(z) + xy0;
             const cplx wr = cscale(pd.w2, rho_z);
-            b[g] = cadd(cmul(wr, fa0[0]), cscale(bx, sc));
-            b[g + cells] = cadd(cmul(wr, fa0[1]), cscale(by, sc));
-            b[g + 2 * cells] = cadd(cmul(wr, fa0[2]), cscale(bz, sc));
+            bs[g] = cadd(cmul(wr, fa0[0]), cscale(bx, sc));
+            bs[g + cells32] = cadd(cmul(wr, fa0[1]), cscale(by, sc));
+            bs[g + 2 * cells32] = cadd(cmul(wr, fa0[2]), cscale(bz, sc));
         }
         __syncthreads();   // the LDS planes z+1 (input) and z (stress) are read
 #pragma unroll
@@ -669,7 +680,7 @@ static hipError_t stencil3z_launch(const StencilArgs& a, const ProbDev3& pd, Sys
     const int ntx = (pd.nx + TX - 1) / TX, nty = (pd.ny + TY - 1) / TY;
     // z ranges of at most 32 planes, more of them while the launch is small
     int ZC = std::min(pd.nz, 32);
-    while (ZC > 8 && (long long)ntx * nty * ((pd.nz + ZC - 1) / ZC) * pd.nsys < 2048) ZC /= 2;
+    while (ZC > 8 && (long long)ntx * nty * ((pd.nz + ZC - 1) / ZC) * pd.nsys < 1024) ZC /= 2;
     const long long blocks = (long long)ntx * nty * ((pd.nz + ZC - 1) / ZC) * pd.nsys;
     if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
     const size_t lds = march3_lds<TX, TY>();
