@@ -60,17 +60,19 @@ struct dcomplex { double re, im; };
 
 // Store of one complex value that writes through the L2 (system-coherent
 // policy): the kernel's output leaves no dirty L2 lines behind, so the cache
-// write-back at the kernel boundary has nothing to flush.  A store of more
-// than 8 bytes keeps reading its data registers after issue, and the compiler
-// cannot see that inside inline assembly: the 16-byte form waits itself
-// (s_nop) before any later instruction may overwrite them.
+// write-back at the kernel boundary has nothing to flush.  A relaxed atomic
+// store at system scope is exactly that store on gfx950 (global_store with
+// sc0 sc1, no waits or fences), and the compiler sees it as a store: it
+// tracks the store's register hazards and orders it only against accesses
+// that may alias it.  The 16-byte complex128 value is two 8-byte stores.
 __device__ __forceinline__ void st_wt(cplx* p, cplx v) {
+    unsigned long long* q = reinterpret_cast<unsigned long long*>(p);
 #ifdef FW_C128
-    typedef double d2v __attribute__((ext_vector_type(2)));
-    const d2v w = {v.x, v.y};
-    asm volatile("global_store_dwordx4 %0, %1, off sc0 sc1\n\ts_nop 1" ::"v"(p), "v"(w) : "memory");
+    __hip_atomic_store(q, __builtin_bit_cast(unsigned long long, v.x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(q + 1, __builtin_bit_cast(unsigned long long, v.y), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_SYSTEM);
 #else
-    asm volatile("global_store_dwordx2 %0, %1, off sc0 sc1" ::"v"(p), "v"(v) : "memory");
+    __hip_atomic_store(q, __builtin_bit_cast(unsigned long long, v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 #endif
 }
 

@@ -16,6 +16,13 @@ namespace {
 
 __device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
+// Tile row (0..F+3, own rows 2..F+1) loaded at step lr of the load loop:
+// the own rows top to bottom, then the two halo rows above and the two below.
+__device__ __forceinline__ int srows_load_row(int lr, int F) {
+    if (lr < F) return lr + 2;
+    return lr - F < 2 ? lr - F : lr;
+}
+
 struct RowLdsF {
     cplx* p;
     __device__ __forceinline__ cplx& operator()(int, int pos) const { return p[lds_pad(pos)]; }
@@ -84,13 +91,18 @@ __global__ __launch_bounds__(NT) void k_srows(const cplx* __restrict__ u, const 
     }
     // 1. the 2F + 8 rows (F + 4 per component) of the input into LDS, kB
     //    elements per thread at a time: every load of a batch is issued before
-    //    its stores (out-of-range slots load element 0 and are dropped)
+    //    its stores (out-of-range slots load element 0 and are dropped).
+    //    Load order (both components of a row together): the own rows first,
+    //    the four halo rows last, so that a halo row, which is an own row of
+    //    the neighbouring block on the same XCD, is read after that block has
+    //    brought it into the L2.
     const int HR = F + 4;
     cplx* su = lds_dyn;                           // [2][HR][N]
     const int total = 2 * HR * N;
     constexpr int kB = VM == VM_PX ? 4 : 8;
     for (int i0 = threadIdx.x; i0 < total; i0 += kB * NT) {
         size_t gi[kB];
+        int li[kB];
         bool ok[kB], own[kB];
         cplx f[kB], sv[kB], pv[kB], rv[kB], xv[kB];
 #pragma unroll
@@ -98,10 +110,12 @@ __global__ __launch_bounds__(NT) void k_srows(const cplx* __restrict__ u, const 
             const int idx = i0 + j * NT;
             ok[j] = idx < total;
             const int id = ok[j] ? idx : 0;
-            const int c = id / (HR * N);
-            const int rem = id - c * HR * N;
-            const int tr = rem / N, x = rem - tr * N;
+            const int lr = id / (2 * N);
+            const int c = (id / N) & 1;
+            const int x = id - (id / N) * N;
+            const int tr = srows_load_row(lr, F);
             gi[j] = so + c * plane + (size_t)wrapi(z0 - 2 + tr, nz) * N + x;
+            li[j] = (c * HR + tr) * N + x;
             own[j] = ok[j] && tr >= 2 && tr < F + 2;
         }
 #pragma unroll
@@ -126,7 +140,7 @@ __global__ __launch_bounds__(NT) void k_srows(const cplx* __restrict__ u, const 
         }
 #pragma unroll
         for (int j = 0; j < kB; ++j)
-            if (ok[j]) su[i0 + j * NT] = f[j];
+            if (ok[j]) su[li[j]] = f[j];
         if constexpr (VM != VM_NONE) {
 #pragma unroll
             for (int j = 0; j < kB; ++j) {
