@@ -302,12 +302,19 @@ __global__ __launch_bounds__(NT) void k_cols(cplx* __restrict__ data, ProbDev pd
         // The inverse reads the same twiddle entries as the forward pass; an
         // opaque copy of the table pointer keeps the compiler from holding the
         // forward pass's twiddles in registers across the Green multiply.
-        // Likewise for the LDS addresses, which are the same in both passes.
-        const cplx* twi = tw;
+        // Likewise for the LDS addresses, which are the same in both passes:
+        // the opaque value is the offset into the LDS array, not the pointer,
+        // so that the compiler still knows the accesses are LDS accesses (an
+        // opaque pointer would turn them into flat memory instructions).
+        // (The same for the twiddle table: an opaque zero offset keeps its
+        // loads global loads.)
+        int toff = 0;
         int ti = tt;
-        ColLds ldi = lds;
-        asm volatile("" : "+s"(twi));
-        asm volatile("" : "+v"(ti), "+v"(ldi.base), "+v"(ldi.stride));
+        int boff = (int)(lds.base - lds_dyn), bstride = lds.stride;
+        asm volatile("" : "+s"(toff));
+        asm volatile("" : "+v"(ti), "+v"(boff), "+v"(bstride));
+        const cplx* twi = tw + toff;
+        const ColLds ldi{lds_dyn + boff, bstride, PL};
         if constexpr (SEQ) fft_run_seq<N, P, true, 2>(v, ti, twi, ldi);
         else fft_run<N, P, true, 2>(v, ti, twi, ldi);
     }
