@@ -86,13 +86,15 @@ __device__ __forceinline__ void load_coeffs(cplx* c, const double* tot, const Gm
 }
 
 // Hessenberg column j from the two projection passes and n_{j+1}^2, Givens
-// rotations, and the stopping test (one thread).
-__device__ void gm_hessenberg(SysState& z, GmSys& g, const double* tot1, const double* tot2, double n2next) {
+// rotations, and the stopping test (one thread).  hre / him: kGmMax + 1
+// doubles each of LDS for the column (a private array indexed at run time
+// would live in scratch memory).
+__device__ void gm_hessenberg(SysState& z, GmSys& g, const double* tot1, const double* tot2, double n2next,
+                              double* hre, double* him) {
     const int j = g.j;
     const int ld = kGmMax + 1;
     g.n2[j + 1] = n2next;
     const double nj = sqrt(g.n2[j]);
-    double hre[kGmMax + 1], him[kGmMax + 1];
     for (int l = 0; l <= j; ++l) {
         const double s = sqrt(g.n2[l]) / (g.n2[l] * nj);   // n_l / (n_l^2 n_j)
         hre[l] = (tot1[2 * l] + (tot2 ? tot2[2 * l] : 0.0)) * s;
@@ -233,6 +235,7 @@ __global__ __launch_bounds__(kGmThreads) void k_gm_dots(GmArgs a, int j) {
 __global__ __launch_bounds__(kGmThreads) void k_gm_sum(GmArgs a, int mode, int nb, int j, int cgs2,
                                                       double rtol, int first) {
     __shared__ double sm[kGmThreads];
+    __shared__ double hcol[2 * (kGmMax + 1)];
     const int sys = blockIdx.x;
     SysState& z = a.st[sys];
     if (z.status != ST_RUNNING) return;
@@ -243,7 +246,7 @@ __global__ __launch_bounds__(kGmThreads) void k_gm_sum(GmArgs a, int mode, int n
     if (threadIdx.x != 0) return;
     if (mode == GM_SUM_HESS)
         gm_hessenberg(z, a.gs[sys], a.tot1 + (size_t)sys * kGmRec, cgs2 ? a.tot2 + (size_t)sys * kGmRec : nullptr,
-                      tot[0]);
+                      tot[0], hcol, hcol + kGmMax + 1);
     else if (mode == GM_SUM_BEGIN)
         gm_begin(z, a.gs[sys], tot[0], tot[1], rtol, first);
 }
