@@ -147,6 +147,109 @@ def summarize_counters(fetch_csv, write_csv, cmd, out_path=None):
     return 0
 
 
+def summarize_multigrid_counters(fetch_csv, write_csv, cmd, restart, reps, out_path):
+    """profiles/counters_multigrid.json from two rocprofv3 --pmc runs of
+    `bench.py --workload multigrid --passes-only` (FETCH_SIZE, then WRITE_SIZE).
+    Per problem (grid): the four matvec passes; per Arnoldi-step kernel and
+    step j: counter bytes per launch against the algorithmic bytes.  The run
+    launches, in this order: the passes of every problem (pass k of all
+    problems, reps + 1 times), then for j = 0, m/2, m - 1 the update, dots and
+    projection kernels of every problem (reps + 1 times each, problems in plan
+    order); dispatches are attributed by that order, counting from the end
+    (the solve before them launches the same kernels)."""
+    import csv
+    import statistics
+    import workloads as W
+
+    probs = W.four_grids()
+
+    def rows(path, counter):
+        out = []
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] == counter:
+                out.append((int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"])))
+        out.sort()
+        return out
+
+    fetch, write = rows(fetch_csv, "FETCH_SIZE"), rows(write_csv, "WRITE_SIZE")
+    gib_kib = 1024.0 * 1024.0
+    copy_f = max(v for _, n, v in fetch if "copy" in n.lower())
+    copy_w = max(v for _, n, v in write if "copy" in n.lower())
+    sf, sw = gib_kib / copy_f, gib_kib / copy_w
+
+    def by_name(rs):
+        d = {}
+        for _, n, v in rs:
+            d.setdefault(n, []).append(v)
+        return d
+
+    fn, wn = by_name(fetch), by_name(write)
+    cells = [p["nx"] * p["nz"] for p in probs]
+    nsys = [p["nsys"] for p in probs]
+    steps = sorted({0, restart // 2, restart - 1})
+    out = dict(source_hash=_kernel_source_hash(), command=cmd, fetch_scale=sf, write_scale=sw,
+               copy_fetch_kib=copy_f, copy_write_kib=copy_w, grids=[p["nx"] for p in probs], restart=restart,
+               gmres=[], passes=[])
+
+    def entry(fv, wv, alg):
+        f, w = statistics.median(fv), statistics.median(wv)
+        b = (f * sf + w * sw) * 1024.0
+        return dict(fetch_kib=f, write_kib=w, launches=len(fv), counter_bytes_per_launch=b,
+                    algorithmic_bytes_per_launch=alg, ratio=round(b / alg, 4))
+
+    # Arnoldi kernels: the update and dots kernels share one name over the
+    # problems (problem = dispatch index mod the problem count); the projection
+    # epilogue is the inverse row kernel with EPI 5 (one name per grid)
+    np_ = len(probs)
+    for kind, pat in (("update", "k_gm_update("), ("dots", "k_gm_dots(")):
+        name = next((n for n in fn if pat in n), None)
+        if name is None:
+            continue
+        per = (reps + 1) * np_
+        fv, wv = fn[name][-per * len(steps):], wn[name][-per * len(steps):]
+        for gi, j in enumerate(steps):
+            for ip in range(np_):
+                sel = [i for i in range(gi * per, (gi + 1) * per) if i % np_ == ip]
+                alg = GM_BYTES[kind](j) * nsys[ip] * cells[ip]
+                out["gmres"].append(dict(kernel=kind, j=j, grid=probs[ip]["nx"],
+                                         **entry([fv[i] for i in sel], [wv[i] for i in sel], alg)))
+    for ip, p in enumerate(probs):
+        name = next((n for n in fn if re.search(rf"k_rows<{p['nx']}, \d+, true, 5>", n)), None)
+        if name is None:
+            continue
+        per = reps + 1
+        fv, wv = fn[name][-per * len(steps):], wn[name][-per * len(steps):]
+        for gi, j in enumerate(steps):
+            alg = GM_BYTES["projections"](j) * nsys[ip] * cells[ip]
+            out["gmres"].append(dict(kernel="projections", j=j, grid=p["nx"],
+                                     **entry(fv[gi * per:(gi + 1) * per], wv[gi * per:(gi + 1) * per], alg)))
+    # matvec passes: the kernel instances of each grid (template N = the grid)
+    for k, match in enumerate(PASS_MATCH[:4]):
+        for ip, p in enumerate(probs):
+            for n in fn:
+                if not match(n) or n not in wn:
+                    continue
+                nm = _instance_name(n)
+                if k == 0 and "k_body_force" in nm:
+                    continue   # the fused stencil + rows serves every grid here
+                if f"<{p['nx']}," not in nm:
+                    continue
+                alg = PASS_BYTES[k] * nsys[ip] * cells[ip] + (MAP_BYTES_PER_CELL * cells[ip] if k == 0 else 0.0)
+                # launches with every system running (a solve's launches for
+                # stopped systems exit early)
+                fv = [x for x in fn[n] if x >= 0.5 * max(fn[n])]
+                wv = [x for x in wn[n] if x >= 0.5 * max(wn[n])]
+                out["passes"].append(dict(pass_=k, grid=p["nx"], instance=nm, **entry(fv, wv, alg)))
+    out["passes"] = [{("pass" if kk == "pass_" else kk): v for kk, v in d.items()} for d in out["passes"]]
+    with open(out_path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    for d in out["gmres"]:
+        print(f"{d['kernel']:12s} j={d['j']:2d} grid={d['grid']:4d} ratio {d['ratio']:.3f}")
+    for d in out["passes"]:
+        print(f"pass {d['pass']} grid={d['grid']:4d} {d['instance']:50s} ratio {d['ratio']:.3f}")
+    return 0
+
+
 def _pass_instance(k, tuning, n=256):
     """Kernel instance of pass k on an n^2 grid under the plan's variants."""
     if k == PX_PASS:
@@ -228,6 +331,25 @@ def multigrid(a):
         plan.solve(u0, rtol=RTOL, maxit=1000)
         torch.cuda.synchronize()
         return (time.perf_counter() - t) * 1e3
+
+    if a.passes_only:
+        # counter runs: the tuned variants (same choices as a timed run), one
+        # solve so that the GMRES state exists, the passes of every problem
+        # and the Arnoldi-step kernels at steps 0, m/2 and m - 1, then the
+        # 1 GiB device copy the counters are scaled by
+        if not a.no_autotune:
+            plan.autotune(reps=10)
+        step()
+        rl = _pass_rooflines(plan, reps=a.reps)
+        gl = _gmres_rooflines(plan, probs, a.restart, reps=a.reps) if a.krylov == "gmres" else None
+        src_t = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        dst_t = torch.empty_like(src_t)
+        for _ in range(3):
+            dst_t.copy_(src_t)
+        torch.cuda.synchronize()
+        print(json.dumps(dict(passes_only=True, pass_rooflines=rl, gmres_rooflines=gl,
+                              tuning=[plan.tuning(i) for i in range(len(probs))])), flush=True)
+        return 0
 
     tuning = None
     if not a.no_autotune:
@@ -813,6 +935,8 @@ def main(argv=None):
     ap.add_argument("--cpu-sample", type=int, default=12, help="systems in the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the built-in kernel variants")
+    ap.add_argument("--tuning", default="", help="default workload: kernel variants as JSON (fwils_tuning fields), "
+                                                 "applied after the autotuner")
     ap.add_argument("--krylov", choices=["auto", "bicgstab", "gmres"], default="auto",
                     help="auto: GMRES(32) with one Gram-Schmidt pass for the four-grid workload (hard "
                          "12 Hz systems), BiCGSTAB for the others (1.7x faster than GMRES on the dbi "
@@ -835,6 +959,10 @@ def main(argv=None):
     ap.add_argument("--counter-command", default="", help="the rocprofv3 command, recorded in the summary")
     ap.add_argument("--counters-out", default=None, help="summary file (default profiles/counters_vti256x16.json)")
     a = ap.parse_args(argv)
+    if a.summarize_counters and a.workload == "multigrid":
+        return summarize_multigrid_counters(a.summarize_counters[0], a.summarize_counters[1], a.counter_command,
+                                            a.restart, a.reps, a.counters_out or os.path.join(ROOT, "profiles",
+                                                                                     "counters_multigrid.json"))
     if a.summarize_counters:
         return summarize_counters(a.summarize_counters[0], a.summarize_counters[1], a.counter_command,
                                   a.counters_out)
@@ -879,6 +1007,13 @@ def main(argv=None):
         tuning = dict(choice=plan.autotune(reps=20)[0])
         tuning["tune_s"] = round(time.perf_counter() - t0, 2)
         print(f"[bench] autotune: {tuning}", file=sys.stderr, flush=True)
+    if a.tuning:
+        # fixed kernel variants (a profiled run repeats a timed run's choice:
+        # a profiler's overhead can change what the autotuner picks)
+        fixed = json.loads(a.tuning)
+        plan.set_tuning(0, **fixed)
+        tuning = dict(choice=plan.tuning(0), fixed=True)
+        print(f"[bench] fixed variants: {tuning}", file=sys.stderr, flush=True)
     dm = torch.as_tensor(dm_np).cuda()
     r = torch.as_tensor(r_np.ravel()).cuda()
 

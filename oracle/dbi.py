@@ -82,3 +82,20 @@ def dbi_stage(items, contrast, m0, lam0, niter, reg="identity", tol=1e-3, max_ou
     for (P, *_rest) in items:
         P.set_contrast(c)
     return c, eps_hist, lam_hist, q
+
+
+def invert_sequential(stages, contrast, m0, lam0, niter, reg="identity", tol=1e-3, max_outer=10,
+                      solve_tol=1e-12):
+    """The sequential-frequency scheme of the numerical-examples section: the
+    stages (one list of items per frequency, lowest first; items as for
+    dbi_stage) are inverted one after the other, each starting from the model
+    the previous stage ended with.  Returns (final contrast, per-stage
+    (eps_d history, lambdas))."""
+    c = np.array(contrast, dtype=float)
+    records = []
+    for items in stages:
+        c, eps, lam, _ = dbi_stage(items, c, m0, lam0, niter, reg=reg, tol=tol, max_outer=max_outer,
+                                   solve_tol=solve_tol)
+        records.append((eps, lam))
+    return c, records
+

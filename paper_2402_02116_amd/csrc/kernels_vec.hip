@@ -598,6 +598,112 @@ int st_candidates(int nx, int nz, StCfg* out, int cap) {
     return k;
 }
 
+// The BiCGSTAB update of a stencil's input on its own, as a streaming pass
+// over the n complex values of each system's field: the same scalars, stop
+// decisions and element arithmetic as the update fused into the stencil
+// kernels (stencil_scalars, close_r, close_x), writing the updated input (p
+// or s) that the plain stencil then reads.  bps blocks per system; block 0 of
+// a system records its scalars and status.
+template <int VM>
+__global__ __launch_bounds__(256) void k_bicg_update(const cplx* __restrict__ u, const cplx* __restrict__ a1,
+                                                 const cplx* __restrict__ a2, cplx* __restrict__ wout,
+                                                 SysState* __restrict__ st, const double* __restrict__ part, int np,
+                                                 cplx* __restrict__ rhat, const cplx* __restrict__ a3,
+                                                 cplx* __restrict__ xio, cplx* __restrict__ rout, int n, int bps) {
+    __shared__ double red[4 * kPartialNV];
+    __shared__ int s_status;
+    const int sys = blockIdx.x / bps, bi = blockIdx.x - sys * bps;
+    const int t = threadIdx.x;
+    if (t == 0) s_status = st[sys].status;
+    __syncthreads();
+    const int stw = s_status;
+    __syncthreads();
+    if constexpr (VM == VM_PX) {
+        if (!closing_enters(stw, kStampPx)) return;
+    } else {
+        if (stw != ST_RUNNING) {
+            if (VM == VM_S && st_tag(stw) != 0 && bi == 0 && t == 0) st[sys].status = st_code(stw);
+            return;
+        }
+    }
+    cplx c1 = mkc(0.f, 0.f), c2 = mkc(0.f, 0.f), c3 = mkc(0.f, 0.f);
+    bool fresh = false;
+    const int step = stencil_scalars<VM>(st, sys, part, np, red, bi == 0 && t == 0, c1, c2, c3, fresh);
+    if (step == SS_SKIP) return;
+    const size_t so = (size_t)sys * n;
+    const cplx* __restrict__ us = u + so;
+    const cplx* __restrict__ a1s = a1 + so;
+    const cplx* __restrict__ a2s = a2 + so;
+    const cplx* __restrict__ a3s = a3 + so;
+    cplx* __restrict__ wos = wout + so;
+    cplx* __restrict__ rhs = rhat + so;
+    cplx* __restrict__ xs = xio + so;
+    cplx* __restrict__ ros = rout + so;
+    constexpr int U = 4;   // elements per thread in flight
+    const int stride = bps * 256;
+    for (int i0 = bi * 256 + t; i0 < n; i0 += U * stride) {
+        cplx r0[U], r1[U], r2[U], r3[U], xv[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int i = i0 + k * stride;
+            if (i < n) {
+                r0[k] = us[i];
+                if constexpr (VM == VM_P) {
+                    r1[k] = a1s[i];
+                    r2[k] = a2s[i];
+                } else if constexpr (VM == VM_PX) {
+                    r1[k] = a3s[i];
+                    r2[k] = a1s[i];
+                    if (step == SS_FULL) r3[k] = a2s[i];
+                    xv[k] = xs[i];
+                } else if constexpr (VM == VM_S) {
+                    r1[k] = a1s[i];
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+            const int i = i0 + k * stride;
+            if (i >= n) continue;
+            if constexpr (VM == VM_P) {
+                const cplx f = fresh ? r0[k] : cadd(r0[k], cmul(c1, csub(r1[k], cmul(c2, r2[k]))));
+                st_wt(wos + i, f);
+                if (fresh) st_wt(rhs + i, f);
+            } else if constexpr (VM == VM_PX) {
+                const cplx rv = close_r(r0[k], r1[k], c2);
+                st_wt(ros + i, rv);
+                st_wt(xs + i, close_x(xv[k], r2[k], r0[k], c3, c2));
+                if (step == SS_FULL) {
+                    const cplx f = fresh ? rv : cadd(rv, cmul(c1, csub(r2[k], cmul(c2, r3[k]))));
+                    st_wt(wos + i, f);
+                    if (fresh) st_wt(rhs + i, rv);
+                }
+            } else if constexpr (VM == VM_S) {
+                st_wt(wos + i, csub(r0[k], cmul(c1, r1[k])));
+            }
+        }
+    }
+}
+
+hipError_t launch_bicg_update(int vm, const StencilArgs& a, long long n, int nsys, SysState* st, hipStream_t s) {
+    if ((vm != VM_P && vm != VM_PX && vm != VM_S) || !st || !a.wout || n <= 0 || n > 0x7fffffffLL || nsys < 1 ||
+        ((vm == VM_P || vm == VM_PX) && !a.rhat) || (vm == VM_PX && (!a.a3 || !a.xio || !a.rout)))
+        return hipErrorInvalidValue;
+    // blocks per system: at least 2048 blocks in the launch while every
+    // thread has a few elements
+    int bps = 1;
+    while ((long long)bps * nsys < 2048 && (long long)bps * 2 * 256 * 4 <= n) bps *= 2;
+    const dim3 grid((unsigned)(bps * nsys));
+#define FW_UPD(V)                                                                                            \
+    hipLaunchKernelGGL((k_bicg_update<V>), grid, dim3(256), 0, s, a.u, a.a1, a.a2, a.wout, st, a.part, a.np, \
+                       a.rhat, a.a3, a.xio, a.rout, (int)n, bps)
+    if (vm == VM_P) FW_UPD(VM_P);
+    else if (vm == VM_PX) FW_UPD(VM_PX);
+    else FW_UPD(VM_S);
+#undef FW_UPD
+    return hipGetLastError();
+}
+
 // Row range of the z-marching kernel: the whole column, halved (while it
 // stays a multiple of the step and at least 32 rows) until the launch has
 // 8192 workgroups.
@@ -618,12 +724,12 @@ static void body_force_z_launch(const StencilArgs& a, const ProbDev& pd, SysStat
 }
 
 template <int TX, int TZ, int VM>
-static void body_force_launch(const StCfg& c, const StencilArgs& a, const ProbDev& pd, SysState* st,
-                              hipStream_t s) {
+static hipError_t body_force_launch(const StCfg& c, const StencilArgs& a, const ProbDev& pd, SysState* st,
+                                    hipStream_t s) {
     if constexpr (TZ == 4 || TZ == 8) {
         if (c.S == kStMarch) {
             body_force_z_launch<TX, TZ, VM>(a, pd, st, s);
-            return;
+            return hipGetLastError();
         }
     }
     const int ntiles = (pd.nx / TX) * (pd.nz / TZ);
@@ -639,25 +745,26 @@ static void body_force_launch(const StCfg& c, const StencilArgs& a, const ProbDe
     const int blocks = ntiles * ((pd.nsys + S - 1) / S);
     hipLaunchKernelGGL((k_body_force<TX, TZ, VM>), dim3(blocks), dim3(256), 0, s, a.u, a.a1, a.a2, a.wout,
                        a.b, a.maps, pd, S, st, a.part, a.np, a.rhat, a.a3, a.xio, a.rout);
+    return hipGetLastError();
 }
 
 template <int TX, int TZ>
-static void body_force_vm(int vm, const StCfg& c, const StencilArgs& a, const ProbDev& pd, SysState* st,
-                          hipStream_t s) {
-    if (vm == VM_NONE) body_force_launch<TX, TZ, VM_NONE>(c, a, pd, st, s);
-    else if (vm == VM_P) body_force_launch<TX, TZ, VM_P>(c, a, pd, st, s);
-    else if (vm == VM_PX) body_force_launch<TX, TZ, VM_PX>(c, a, pd, st, s);
-    else body_force_launch<TX, TZ, VM_S>(c, a, pd, st, s);
+static hipError_t body_force_vm(int vm, const StCfg& c, const StencilArgs& a, const ProbDev& pd, SysState* st,
+                                hipStream_t s) {
+    if (vm == VM_NONE) return body_force_launch<TX, TZ, VM_NONE>(c, a, pd, st, s);
+    if (vm == VM_P) return body_force_launch<TX, TZ, VM_P>(c, a, pd, st, s);
+    if (vm == VM_PX) return body_force_launch<TX, TZ, VM_PX>(c, a, pd, st, s);
+    return body_force_launch<TX, TZ, VM_S>(c, a, pd, st, s);
 }
 
 template <int TX>
-static void body_force_tz(int vm, const StCfg& c, const StencilArgs& a, const ProbDev& pd, SysState* st,
-                          hipStream_t s) {
-    if (c.TZ == 4) body_force_vm<TX, 4>(vm, c, a, pd, st, s);
+static hipError_t body_force_tz(int vm, const StCfg& c, const StencilArgs& a, const ProbDev& pd, SysState* st,
+                                hipStream_t s) {
+    if (c.TZ == 4) return body_force_vm<TX, 4>(vm, c, a, pd, st, s);
 #ifndef FW_C128
-    else if (c.TZ == 16) body_force_vm<TX, 16>(vm, c, a, pd, st, s);
+    if (c.TZ == 16) return body_force_vm<TX, 16>(vm, c, a, pd, st, s);
 #endif
-    else body_force_vm<TX, 8>(vm, c, a, pd, st, s);
+    return body_force_vm<TX, 8>(vm, c, a, pd, st, s);
 }
 
 hipError_t launch_stencil(int vm, const StCfg& c, const StencilArgs& a, const ProbDev& pd, SysState* st,
@@ -666,14 +773,13 @@ hipError_t launch_stencil(int vm, const StCfg& c, const StencilArgs& a, const Pr
         (vm == VM_PX && (!a.a3 || !a.xio || !a.rout)))
         return hipErrorInvalidValue;
     switch (tile_x(pd.nx)) {
-        case 64: body_force_tz<64>(vm, c, a, pd, st, s); break;
-        case 48: body_force_tz<48>(vm, c, a, pd, st, s); break;
-        case 32: body_force_tz<32>(vm, c, a, pd, st, s); break;
-        case 24: body_force_tz<24>(vm, c, a, pd, st, s); break;
-        case 16: body_force_tz<16>(vm, c, a, pd, st, s); break;
+        case 64: return body_force_tz<64>(vm, c, a, pd, st, s);
+        case 48: return body_force_tz<48>(vm, c, a, pd, st, s);
+        case 32: return body_force_tz<32>(vm, c, a, pd, st, s);
+        case 24: return body_force_tz<24>(vm, c, a, pd, st, s);
+        case 16: return body_force_tz<16>(vm, c, a, pd, st, s);
         default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 hipError_t launch_body_force(const StCfg& c, const cplx* u, cplx* b, const real* maps,

@@ -145,6 +145,11 @@ struct StencilArgs {
 };
 hipError_t launch_stencil(int vm, const StCfg& c, const StencilArgs& a, const ProbDev& pd, SysState* st,
                           hipStream_t s);
+// The BiCGSTAB update of a stencil's input (vm = VM_P, VM_PX or VM_S, the
+// fields of StencilArgs as for launch_stencil) as a streaming pass over the n
+// complex values per system of nsys systems, writing the updated input to
+// a.wout (and r, x, r^ as the fused modes do); the plain stencil follows.
+hipError_t launch_bicg_update(int vm, const StencilArgs& a, long long n, int nsys, SysState* st, hipStream_t s);
 // The stencil fused with the forward row transform: b (of the updated input,
 // vm as above, a.b unused) row-transformed into out.  Rows up to kSrowsMaxN.
 constexpr int kSrowsMaxN = 512;

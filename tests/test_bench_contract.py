@@ -62,3 +62,46 @@ def test_counter_summary_keeps_full_direction_update_launches(tmp_path):
     assert e["launches"] == 2 and e["hbm_bytes_per_launch"] == (100.0 * 2.0 + 50.0) * 1024.0
     m = d["passes"]["3"]["instances"]["fw::c64::k_rows<256, 8, true, 1>"]
     assert m["launches"] == 2 and m["hbm_bytes_per_launch"] == (20.0 * 2.0 + 5.0) * 1024.0
+
+
+def test_multigrid_counter_summary_attributes_dispatches_by_order(tmp_path):
+    """Arnoldi-kernel counters are attributed to (step j, grid) by dispatch
+    order, counting back from the end (the solve before the timed launches
+    runs the same kernels), and compared with the algorithmic bytes."""
+    sys.path.insert(0, ROOT)
+    import bench
+    import workloads as W
+    probs = W.four_grids()
+    reps, m = 2, 32
+    steps = [0, 16, 31]
+    upd = "fw::c64::k_gm_update(fw::c64::GmArgs, int, int, int)"
+    dots = "fw::c64::k_gm_dots(fw::c64::GmArgs, int)"
+    proj = ["void fw::c64::k_rows<%d, 12, true, 5>(int)" % p["nx"] for p in probs]
+    cp = "__amd_rocclr_copyBuffer"
+    disp = []   # (name, fetch KiB, write KiB)
+    disp += [(upd, 1e9, 1e9)] * 7          # the solve's launches: excluded
+    for j in steps:
+        for kind in ("update", "dots", "projections"):
+            for _ in range(reps + 1):
+                for ip, p in enumerate(probs):
+                    cs = p["nsys"] * p["nx"] * p["nz"]
+                    # counter bytes = 1.25 x the algorithmic bytes (fetch scaled x2 by the copy)
+                    alg = bench.GM_BYTES[kind](j) * cs
+                    name = upd if kind == "update" else dots if kind == "dots" else proj[ip]
+                    disp.append((name, 0.5 * 1.25 * alg / 2.0 / 1024.0, 0.5 * 1.25 * alg / 1024.0))
+    disp.append((cp, 524288.0, 1048576.0))
+    paths = []
+    for k, counter in ((1, "FETCH_SIZE"), (2, "WRITE_SIZE")):
+        path = tmp_path / f"{counter}.csv"
+        lines = ["Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value"]
+        lines += [f'{i},"{d[0]}",{counter},{d[k]}' for i, d in enumerate(disp)]
+        path.write_text("\n".join(lines) + "\n")
+        paths.append(str(path))
+    out = tmp_path / "mg.json"
+    bench.summarize_multigrid_counters(paths[0], paths[1], "test", m, reps, str(out))
+    import json
+    d = json.loads(out.read_text())
+    got = {(e["kernel"], e["j"], e["grid"]): e for e in d["gmres"]}
+    assert len(got) == 3 * 3 * len(probs)
+    for e in got.values():
+        assert abs(e["ratio"] - 1.25) < 1e-9 and e["launches"] == reps + 1

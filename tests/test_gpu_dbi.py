@@ -139,3 +139,32 @@ def test_stopping_rule_and_argument_errors(case):
     dm[0] = 1.0
     with pytest.raises(FwilsError):
         mixed.dbi_run(SRC * 2, SRC_F * 2, dm, case["m0"])
+
+
+def test_sequential_frequencies_match_oracle(case):
+    """invert_sequential: one single-frequency plan per frequency, lowest
+    first, each stage starting from the previous stage's model, against the
+    oracle's sequential scheme (data-error and lambda histories per stage,
+    final model)."""
+    from paper_2402_02116_amd.dbi import invert_sequential
+    from paper_2402_02116_amd.plan import Plan
+    print("dbi sequential c64", flush=True)
+    plans, d_obs = [], []
+    for i in range(len(FREQS)):
+        plan = Plan([case["probs"][i]])
+        plan.set_receivers(0, REC)
+        plans.append(plan)
+        d_obs.append(torch.as_tensor(case["items"][i][4].ravel().astype(np.complex64)).cuda())
+    c_gpu, stages = invert_sequential(plans, SRC, SRC_F, d_obs, case["c_start"], case["m0"], lam0=LAM0,
+                                      niter=NITER, tol=0.0, max_outer=MAX_OUTER, rtol=1e-7, maxit=2000)
+    c_ref, recs = dbi.invert_sequential([[it] for it in case["items"]], case["c_start"], case["m0"], LAM0, NITER,
+                                        tol=0.0, max_outer=MAX_OUTER, solve_tol=1e-13)
+    for st, (eps_ref, lam_ref) in zip(stages, recs):
+        assert st["status"] == 0 and st["updates"] == MAX_OUTER
+        e_eps, e_lam = _rel(st["eps"], eps_ref), _rel(st["lam"], lam_ref)
+        print(f"  {st['freq_hz']} Hz: eps {st['eps']} vs {eps_ref}: {e_eps:.2e}; lam {e_lam:.2e}", flush=True)
+        assert e_eps < 1e-5 and e_lam < 1e-5
+    c = c_gpu.cpu().numpy().astype(np.float64)
+    e_step = _rel(c - case["c_start"], c_ref - case["c_start"])
+    print(f"  final model step {e_step:.2e}", flush=True)
+    assert e_step < 1e-4

@@ -84,3 +84,27 @@ def test_data_error_descends_and_lambda_cools():
     assert eps[-1] < 0.5 * eps[0]
     assert lams[0] == 1.0 and all(b <= a for a, b in zip(lams, lams[1:]))
     assert np.linalg.norm(c - c_true) < np.linalg.norm(c_start - c_true)
+
+
+def test_sequential_scheme_chains_the_stages():
+    """The sequential scheme's first stage is dbi_stage from the starting model
+    and its second stage starts from the first stage's result."""
+    c0, rho0 = W.vti_background()
+    m0 = W.model_scales(c0, rho0)
+    m0b = m0.reshape(5, 1, 1)
+    nx, nz = 16, 12
+    c_true = m0b * W.smooth_maps(31, nz, nx, 2.0, 0.03)
+    start = m0b * W.smooth_maps(32, nz, nx, 2.0, 0.01)
+    src, srcf, rec = [(4, 1), (11, 1)], [(0.0, 1.0), (0.0, 1.0)], [(ix, 2) for ix in range(0, nx, 2)]
+    stages = []
+    for f in (20.0, 28.0):
+        P = LSProblem(nx, nz, 10.0, c0, rho0, f, 0.02, c_true)
+        u, _ = P.solve(P.incident(src, srcf), tol=1e-13)
+        stages.append([(LSProblem(nx, nz, 10.0, c0, rho0, f, 0.02), src, srcf, rec, operators.sample(u, rec))])
+    c_seq, recs = dbi.invert_sequential(stages, start, m0, 1.0, 4, tol=0.0, max_outer=1)
+    c1, eps1, lam1, _ = dbi.dbi_stage(stages[0], start, m0, 1.0, 4, tol=0.0, max_outer=1)
+    c2, eps2, lam2, _ = dbi.dbi_stage(stages[1], c1, m0, 1.0, 4, tol=0.0, max_outer=1)
+    assert np.allclose(c_seq, c2, rtol=0, atol=1e-12 * np.abs(c2).max())
+    assert recs[0][0] == eps1 and recs[1][0] == eps2
+    # each stage lowers its own data error
+    assert eps1[-1] < eps1[0] and eps2[-1] < eps2[0]
