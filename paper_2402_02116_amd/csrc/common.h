@@ -56,6 +56,16 @@ __device__ __forceinline__ real rsinpi(real x) {
 #endif
 }
 
+// 1 / x for the Green's-tensor multiply: the hardware reciprocal (within 1
+// ulp) in the complex64 build, the correctly rounded division in complex128.
+__device__ __forceinline__ real green_rcp(real x) {
+#ifdef FW_C128
+    return 1.0 / x;
+#else
+    return __builtin_amdgcn_rcpf(x);
+#endif
+}
+
 struct dcomplex { double re, im; };
 
 // Store of one complex value that writes through the L2 (system-coherent

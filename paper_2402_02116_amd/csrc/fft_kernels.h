@@ -215,7 +215,7 @@ __device__ __forceinline__ void green_mul(cplx& bx, cplx& bz, real gxx, real gzz
     const cplx mzz = mkc(gzz - ga.x, -ga.y);
     cplx det = cmul(mxx, mzz);
     det.x -= gxz * gxz;
-    const real s = gscale / (det.x * det.x + det.y * det.y);
+    const real s = gscale * green_rcp(det.x * det.x + det.y * det.y);
     const cplx inv = mkc(det.x * s, -det.y * s);
     const cplx gx = cmul(inv, bx), gz = cmul(inv, bz);   // inv b
     const cplx ox = csub(cmul(mzz, gx), cscale(gz, gxz));

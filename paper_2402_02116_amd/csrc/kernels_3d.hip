@@ -654,7 +654,7 @@ __device__ __forceinline__ void green_mul3(cplx (&b)[3], const real (&g)[6], cpl
     const cplx axz = csub(mkc(mxy * myz, 0.f), cscale(myy, mxz));
     const cplx ayz = csub(mkc(mxy * mxz, 0.f), cscale(mxx, myz));
     const cplx det = cadd(cmul(mxx, axx), cadd(cscale(axy, mxy), cscale(axz, mxz)));
-    const real s = gscale / (det.x * det.x + det.y * det.y);
+    const real s = gscale * green_rcp(det.x * det.x + det.y * det.y);
     const cplx inv = mkc(det.x * s, -det.y * s);
     const cplx gx = cmul(inv, b[0]), gy = cmul(inv, b[1]), gz = cmul(inv, b[2]);
     b[0] = cadd(cmul(axx, gx), cadd(cmul(axy, gy), cmul(axz, gz)));
