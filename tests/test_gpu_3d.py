@@ -86,6 +86,17 @@ def test_body_force_apply_incident_3d(params):
     assert _rel(_np(plan.view(plan.incident(src, f), 0)), P.incident(src, f)) < KERNEL_TOL
 
 
+@pytest.mark.parametrize("nx,ny,nz", [(24, 20, 16), (32, 40, 16), (32, 32, 16), (64, 24, 16)])
+def test_marching_stencil_column_shapes(nx, ny, nz):
+    """The z-marching stencil's column shapes (16 x 16 with and without
+    overhang, 32 x 8) against the oracle's contrast stencil."""
+    print(f"3-D stencil {nx}x{ny}x{nz}", flush=True)
+    plan, p, maps, P = _case(nx, ny, nz, 2)
+    u = _field(np.random.default_rng(4), 2, nx, ny, nz)
+    ut = plan.pack([u])
+    assert _rel(_np(plan.view(plan.body_force(ut), 0)), P.body_force(u)) < KERNEL_TOL
+
+
 @pytest.mark.parametrize("params", ["vti", "general"])
 def test_solve_3d_matches_oracle_batched_plain_gmres(params):
     nx, ny, nz = 24, 20, 16
