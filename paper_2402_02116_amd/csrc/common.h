@@ -68,21 +68,21 @@ __device__ __forceinline__ real green_rcp(real x) {
 
 struct dcomplex { double re, im; };
 
-// Store of one complex value that writes through the L2 (system-coherent
-// policy): the kernel's output leaves no dirty L2 lines behind, so the cache
-// write-back at the kernel boundary has nothing to flush.  A relaxed atomic
-// store at system scope is exactly that store on gfx950 (global_store with
-// sc0 sc1, no waits or fences), and the compiler sees it as a store: it
-// tracks the store's register hazards and orders it only against accesses
-// that may alias it.  The 16-byte complex128 value is two 8-byte stores.
+// Store of one complex value.  complex64: a write-through store (system-
+// coherent policy), so the kernel's output leaves no dirty L2 lines behind
+// and the cache write-back at the kernel boundary has nothing to flush.  A
+// relaxed atomic store at system scope is exactly that store on gfx950
+// (global_store with sc0 sc1, no waits or fences), and the compiler sees it
+// as a store: it tracks the store's register hazards and orders it only
+// against accesses that may alias it.  complex128: a plain 16-byte store (an
+// atomic store is at most 8 bytes, and two 8-byte write-through stores per
+// lane write every cache line in two halves).
 __device__ __forceinline__ void st_wt(cplx* p, cplx v) {
-    unsigned long long* q = reinterpret_cast<unsigned long long*>(p);
 #ifdef FW_C128
-    __hip_atomic_store(q, __builtin_bit_cast(unsigned long long, v.x), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-    __hip_atomic_store(q + 1, __builtin_bit_cast(unsigned long long, v.y), __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_SYSTEM);
+    *p = v;
 #else
-    __hip_atomic_store(q, __builtin_bit_cast(unsigned long long, v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(reinterpret_cast<unsigned long long*>(p), __builtin_bit_cast(unsigned long long, v),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 #endif
 }
 
