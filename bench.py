@@ -337,8 +337,9 @@ def multigrid(a):
         # solve so that the GMRES state exists, the passes of every problem
         # and the Arnoldi-step kernels at steps 0, m/2 and m - 1, then the
         # 1 GiB device copy the counters are scaled by
-        if not a.no_autotune:
+        if not (a.no_autotune or a.tuning):
             plan.autotune(reps=10)
+        _fixed_tuning(plan, a)
         step()
         rl = _pass_rooflines(plan, reps=a.reps)
         gl = _gmres_rooflines(plan, probs, a.restart, reps=a.reps) if a.krylov == "gmres" else None
@@ -463,6 +464,21 @@ def _pass_rooflines(plan, reps=5):
     return [{("pass" if k == "pass_" else k): v for k, v in d.items()} for d in out]
 
 
+def _fixed_tuning(plan, a):
+    """Apply --tuning (a JSON object for every problem, or a list with one
+    object per problem); returns the plan's variants, or None without it."""
+    if not a.tuning:
+        return None
+    fixed = json.loads(a.tuning)
+    n = len(plan.problems)
+    per = fixed if isinstance(fixed, list) else [fixed] * n
+    if len(per) != n:
+        raise SystemExit(f"--tuning: {len(per)} entries for {n} problems")
+    for i, t in enumerate(per):
+        plan.set_tuning(i, **{k: v for k, v in t.items() if k != "time_us"})
+    return [plan.tuning(i) for i in range(n)]
+
+
 def _tik_plan(probs, rec, krylov, a, precision="c64"):
     from paper_2402_02116_amd.plan import Plan
     plan = Plan([dict(nx=p["nx"], nz=p["nz"], dx=p["dx"], c0=p["c0"], rho0=p["rho0"], freq_hz=p["freq_hz"],
@@ -472,8 +488,8 @@ def _tik_plan(probs, rec, krylov, a, precision="c64"):
         plan.set_receivers(i, rec)
     if krylov == "gmres":
         plan.set_krylov("gmres", restart=a.restart, cgs2=not a.cgs1)
-    tuned = None if a.no_autotune else plan.autotune(reps=5)
-    return plan, tuned
+    tuned = None if (a.no_autotune or a.tuning) else plan.autotune(reps=5)
+    return plan, _fixed_tuning(plan, a) or tuned
 
 
 def jacobian(a):
@@ -935,8 +951,9 @@ def main(argv=None):
     ap.add_argument("--cpu-sample", type=int, default=12, help="systems in the CPU oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the built-in kernel variants")
-    ap.add_argument("--tuning", default="", help="default workload: kernel variants as JSON (fwils_tuning fields), "
-                                                 "applied after the autotuner")
+    ap.add_argument("--tuning", default="", help="kernel variants as JSON (fwils_tuning fields): one object for "
+                                                 "every problem or a list with one per problem; replaces the "
+                                                 "autotuner's choice (default, normal, multigrid --passes-only)")
     ap.add_argument("--krylov", choices=["auto", "bicgstab", "gmres"], default="auto",
                     help="auto: GMRES(32) with one Gram-Schmidt pass for the four-grid workload (hard "
                          "12 Hz systems), BiCGSTAB for the others (1.7x faster than GMRES on the dbi "
@@ -1014,9 +1031,7 @@ def main(argv=None):
     if a.tuning:
         # fixed kernel variants (a profiled run repeats a timed run's choice:
         # a profiler's overhead can change what the autotuner picks)
-        fixed = json.loads(a.tuning)
-        plan.set_tuning(0, **fixed)
-        tuning = dict(choice=plan.tuning(0), fixed=True)
+        tuning = dict(choice=_fixed_tuning(plan, a)[0], fixed=True)
         print(f"[bench] fixed variants: {tuning}", file=sys.stderr, flush=True)
     dm = torch.as_tensor(dm_np).cuda()
     r = torch.as_tensor(r_np.ravel()).cuda()
