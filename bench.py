@@ -202,7 +202,7 @@ def summarize_multigrid_counters(fetch_csv, write_csv, cmd, restart, reps, out_p
     # epilogue is the inverse row kernel with EPI 5 (one name per grid)
     np_ = len(probs)
     for kind, pat in (("update", "k_gm_update("), ("dots", "k_gm_dots(")):
-        name = next((n for n in fn if pat in n), None)
+        name = next((n for n in fn if pat in n and n in wn), None)
         if name is None:
             continue
         per = (reps + 1) * np_
@@ -214,7 +214,7 @@ def summarize_multigrid_counters(fetch_csv, write_csv, cmd, restart, reps, out_p
                 out["gmres"].append(dict(kernel=kind, j=j, grid=probs[ip]["nx"],
                                          **entry([fv[i] for i in sel], [wv[i] for i in sel], alg)))
     for ip, p in enumerate(probs):
-        name = next((n for n in fn if re.search(rf"k_rows<{p['nx']}, \d+, true, 5>", n)), None)
+        name = next((n for n in fn if re.search(rf"k_rows<{p['nx']}, \d+, true, 5>", n) and n in wn), None)
         if name is None:
             continue
         per = reps + 1
