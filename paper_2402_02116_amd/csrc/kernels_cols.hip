@@ -12,10 +12,10 @@ constexpr bool kWideCols = false;   // the 1024-thread pass is complex64 only
 #else
 constexpr bool kWideCols = true;
 #define FW_COL_VARIANTS(X)                                                                        \
-    X(16, 8) X(16, 16) X(24, 12) X(24, 24) X(32, 8) X(32, 16) X(48, 12) X(48, 24) X(64, 8) X(64, 16) \
-    X(96, 12) X(96, 24) X(128, 8) X(128, 16) X(192, 12) X(192, 24) X(256, 8) X(256, 16) X(384, 12)  \
-    X(384, 24) X(512, 8) X(512, 16) X(768, 12) X(768, 24) X(1024, 8) X(1024, 16) X(1536, 12)         \
-    X(1536, 24) X(2048, 8) X(2048, 16)
+    X(16, 8) X(16, 16) X(16, 4) X(24, 12) X(24, 24) X(32, 8) X(32, 16) X(32, 4) X(48, 12) X(48, 24)  \
+    X(64, 8) X(64, 16) X(64, 4) X(96, 12) X(96, 24) X(128, 8) X(128, 16) X(128, 4) X(192, 12)        \
+    X(192, 24) X(256, 8) X(256, 16) X(256, 4) X(384, 12) X(384, 24) X(512, 8) X(512, 16) X(768, 12)  \
+    X(768, 24) X(1024, 8) X(1024, 16) X(1536, 12) X(1536, 24) X(2048, 8) X(2048, 16)
 #endif
 
 hipError_t launch_cols(int mode, const ColCfg& c, cplx* data, const ProbDev& pd, const SysState* st,

@@ -27,8 +27,13 @@ static int col_points_default(int n) { return (n % 3 == 0) ? 12 : 8; }
 #ifdef FW_C128
 static int row_points_alt(int n) { return row_points_default(n); }
 static int col_points_alt(int n) { return col_points_default(n); }
+static int col_points_small(int) { return 0; }
 static int points_radix32(int) { return 0; }
 #else
+// A third column-pass variant for power-of-two columns up to 256 points: 4
+// points per thread (radix-4 passes), four times the threads of the 16-point
+// variant, for small batches where a block per CU leaves the pass latency-bound.
+static int col_points_small(int n) { return (n % 3 != 0 && n % 5 != 0 && n <= 256) ? 4 : 0; }
 static int row_points_alt(int n) { return (n % 5 == 0) ? (n > 40 ? 20 : 10) : (n % 3 == 0) ? 24 : 8; }
 static int col_points_alt(int n) { return (n % 3 == 0) ? 24 : 16; }
 // A third row-pass variant for 512- and 1024-point rows: 32 points per
@@ -131,7 +136,7 @@ ColGeom col_geom(int nz, int nx, const ColCfg& c) {
 
 bool col_cfg_ok(int nz, int nx, const ColCfg& c) {
     if (!fft_size_supported(nz) || c.P <= 0 || nz % c.P != 0) return false;
-    if (c.P != col_points_default(nz) && c.P != col_points_alt(nz)) return false;
+    if (c.P != col_points_default(nz) && c.P != col_points_alt(nz) && c.P != col_points_small(nz)) return false;
     if (c.seq < 0 || c.seq > 3) return false;
     if (c.W < 1 || c.W > 64 || nx % c.W != 0 || (c.W & (c.W - 1)) != 0) return false;
     const ColGeom g = col_geom(nz, nx, c);
@@ -151,9 +156,10 @@ ColCfg col_default(int nz, int nx) {
 
 int col_candidates(int nz, int nx, ColCfg* out, int cap) {
     int k = 0;
-    const int ps[2] = {col_points_default(nz), col_points_alt(nz)};
-    for (int i = 0; i < (ps[1] == ps[0] ? 1 : 2); ++i) {
+    const int ps[3] = {col_points_default(nz), col_points_alt(nz), col_points_small(nz)};
+    for (int i = 0; i < 3; ++i) {
         const int P = ps[i];
+        if (P == 0 || (i > 0 && P == ps[0]) || (i > 1 && P == ps[1])) continue;
         for (int seq = 3; seq >= 0; --seq)
             for (int W = 4; W <= 32; W *= 2) {
                 const ColCfg c{P, W, seq};
