@@ -29,8 +29,9 @@ hipError_t launch_cols(int mode, const ColCfg& c, cplx* data, const ProbDev& pd,
         if (mode == COL_GREEN) {                                                                \
             if constexpr (kWideCols && N >= 512 && N % 3 != 0 && PP == 8)                                    \
                 if (c.seq == 3) return cols_launch<N, PP, COL_GREEN, true, 1024>(data, pd, c.W, st, t, s); \
-            return c.seq == 2 ? cols_split_launch<N, PP>(data, pd, c.W, st, t, s)               \
-                 : c.seq == 1 ? cols_launch<N, PP, COL_GREEN, true>(data, pd, c.W, st, t, s)     \
+            if constexpr (PP < 24)                                                              \
+                if (c.seq == 2) return cols_split_launch<N, PP>(data, pd, c.W, st, t, s);     \
+            return c.seq == 1 ? cols_launch<N, PP, COL_GREEN, true>(data, pd, c.W, st, t, s)    \
                               : cols_launch<N, PP, COL_GREEN, false>(data, pd, c.W, st, t, s);  \
         }                                                                                       \
         if constexpr (PP == ((N % 3 == 0) ? 12 : 8)) {                                         \

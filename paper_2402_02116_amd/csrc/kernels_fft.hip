@@ -140,7 +140,8 @@ bool col_cfg_ok(int nz, int nx, const ColCfg& c) {
     if (c.seq < 0 || c.seq > 3) return false;
     if (c.W < 1 || c.W > 64 || nx % c.W != 0 || (c.W & (c.W - 1)) != 0) return false;
     const ColGeom g = col_geom(nz, nx, c);
-    if (c.seq == 2) return g.threads % 64 == 0 && g.threads <= 512 && g.lds <= kMaxLds;
+    // the component-split pass at 24 points per thread spills registers
+    if (c.seq == 2) return c.P < 24 && g.threads % 64 == 0 && g.threads <= 512 && g.lds <= kMaxLds;
     if (c.seq == 3) return cols_wide_built(nz, c.P) && g.threads > 512 && g.threads <= 1024 && g.lds <= kMaxLds;
     return g.threads <= 512 && g.lds <= kMaxLds;
 }
