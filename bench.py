@@ -268,6 +268,8 @@ def _pass_instance(k, tuning, n=256):
     if k == 2:
         if tuning["col_shared"] == 2:
             return f"fw::c64::k_cols_split<{n}, {tuning['col_points']}>"
+        if tuning["col_shared"] == 4:   # twiddles in LDS, compile-time tile width
+            return f"fw::c64::k_cols_tw<{n}, {tuning['col_points']}, {tuning['col_width']}>"
         seq = "true" if tuning["col_shared"] else "false"
         nt = 1024 if tuning["col_shared"] == 3 else 512
         return f"fw::c64::k_cols<{n}, {tuning['col_points']}, 0, {seq}, {nt}>"

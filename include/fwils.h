@@ -476,7 +476,10 @@ typedef struct {
                               2: separate threads transform them;
                               3: as 1 in blocks of up to 1024 threads
                                  (complex64, power-of-two columns of 512 or
-                                 more points, col_points 8)              */
+                                 more points, col_points 8);
+                              4: as 0, with the twiddle table copied to
+                                 LDS (complex64, power-of-two columns,
+                                 col_points 4 or 8, col_width 4 to 16)     */
     int32_t stencil_rows;  /* contrast-stencil tile height: 4, 8 or 16 (with
                               stencil_sys = -1: rows per step, 4 or 8; complex128
                               plans 4) */

@@ -54,6 +54,40 @@ struct FftShape {
     }
 };
 
+// Padded LDS index: one spare slot every 16 elements keeps the stride-R
+// autosort writes of the first passes off a single bank.
+__device__ __forceinline__ int lds_pad(int pos) { return pos + (pos >> 4); }
+template <int N>
+struct PaddedLen { static constexpr int value = N + N / 16 + 1; };
+
+// The padding is linear over the positions one thread touches in one step:
+// pad(b + d) = pad(b) + pad_step(d) whenever (b mod 16) + (d mod 16) < 16.
+// The checks below confirm it at compile time, over every thread, for the
+// R outputs a radix-R butterfly writes (b = its autosort base, d = r NS)
+// and for the P points a thread reads back (b = t, d = T m); those accesses
+// then take one padded base per thread plus compile-time offsets, which LDS
+// instructions carry as immediates.  LDS accessors provide padded(f, pp),
+// the element at an already padded position pp.
+constexpr int pad_step(int d) { return d + d / 16; }
+constexpr bool pad_linear_writes(int N, int NS, int R) {
+    for (int q = 0; q < N; q += NS * R)
+        for (int k = 0; k < NS; ++k)
+            for (int r = 0; r < R; ++r) {
+                const int b = q + k, p = b + r * NS;
+                if (p + p / 16 != b + b / 16 + pad_step(r * NS)) return false;
+            }
+    return true;
+}
+constexpr bool pad_linear_reads(int N, int P) {
+    const int T = N / P;
+    for (int t = 0; t < T; ++t)
+        for (int m = 0; m < P; ++m) {
+            const int p = t + T * m;
+            if (p + p / 16 != t + t / 16 + pad_step(T * m)) return false;
+        }
+    return true;
+}
+
 // --------------------------------------------------------- small DFTs -----
 template <bool INV>
 __device__ __forceinline__ void dft2(cplx& a, cplx& b) {
@@ -278,11 +312,50 @@ __device__ __forceinline__ void twiddles(cplx (&w)[R], const cplx* __restrict__ 
     }
 }
 
+// The R outputs of a butterfly with autosort base `base`: x[r] to position
+// base + r NS of transform f.
+template <int N, int NS, int R, class Lds>
+__device__ __forceinline__ void lds_store_outputs(const Lds& lds, int f, int base, const cplx (&x)[R]) {
+    if constexpr (pad_linear_writes(N, NS, R)) {
+        const int pb = lds_pad(base);
+#pragma unroll
+        for (int r = 0; r < R; ++r) lds.padded(f, pb + pad_step(r * NS)) = x[r];
+    } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) lds(f, base + r * NS) = x[r];
+    }
+}
+
+// A thread's P points t + T m of transform f back from LDS.
+template <int N, int P, class Lds>
+__device__ __forceinline__ void lds_load_points(const Lds& lds, int f, int t, cplx (&v)[P]) {
+    constexpr int T = N / P;
+    if constexpr (pad_linear_reads(N, P)) {
+        const int pt = lds_pad(t);
+#pragma unroll
+        for (int m = 0; m < P; ++m) v[m] = lds.padded(f, pt + pad_step(T * m));
+    } else {
+#pragma unroll
+        for (int m = 0; m < P; ++m) v[m] = lds(f, t + T * m);
+    }
+}
+
+// w[r] = W^(r e) = tw[r e] for r = 1..R-1, each read from the table
+// (r e < N: e is a multiple of N / (NS R) below N / R).
+template <int R, bool INV>
+__device__ __forceinline__ void twiddles_direct(cplx (&w)[R], const cplx* __restrict__ tw, int e) {
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+        const cplx x = tw[r * e];
+        w[r] = INV ? cconj(x) : x;
+    }
+}
+
 // ----------------------------------------------------------- one pass -----
 // Pass I of an N-point transform for NF independent transforms held by this
 // thread (v[f][m] at position t + T*m).  Non-final passes write to LDS through
 // the accessor `lds(f, pos)`; the final pass leaves its outputs in v.
-template <int N, int P, int I, bool INV, int NF, class Lds>
+template <int N, int P, int I, bool INV, int NF, bool TWD, class Lds>
 __device__ __forceinline__ void fft_pass(cplx (&v)[NF][P], int t,
                                          const cplx* __restrict__ tw, const Lds& lds) {
     using S = FftShape<N, P>;
@@ -295,8 +368,12 @@ __device__ __forceinline__ void fft_pass(cplx (&v)[NF][P], int t,
     for (int b = 0; b < NB; ++b) {
         const int j = t + S::T * b;
         const int k = j % NS;
+        const int base = (j / NS) * NS * R + k;
         cplx w[R];
-        if constexpr (NS > 1) twiddles<R, INV>(w, tw, k * TWS);
+        if constexpr (NS > 1) {
+            if constexpr (TWD) twiddles_direct<R, INV>(w, tw, k * TWS);
+            else twiddles<R, INV>(w, tw, k * TWS);
+        }
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             cplx x[R];
@@ -311,36 +388,33 @@ __device__ __forceinline__ void fft_pass(cplx (&v)[NF][P], int t,
 #pragma unroll
                 for (int r = 0; r < R; ++r) v[f][b + r * NB] = x[r];
             } else {
-                const int base = (j / NS) * NS * R + k;
-#pragma unroll
-                for (int r = 0; r < R; ++r) lds(f, base + r * NS) = x[r];
+                lds_store_outputs<N, NS, R>(lds, f, base, x);
             }
         }
     }
 }
 
-template <int N, int P, bool INV, int NF, int I, class Lds>
+template <int N, int P, bool INV, int NF, int I, bool TWD, class Lds>
 __device__ __forceinline__ void fft_from(cplx (&v)[NF][P], int t,
                                          const cplx* __restrict__ tw, const Lds& lds) {
     using S = FftShape<N, P>;
-    fft_pass<N, P, I, INV, NF>(v, t, tw, lds);
+    fft_pass<N, P, I, INV, NF, TWD>(v, t, tw, lds);
     if constexpr (I + 1 < S::NP) {
         __syncthreads();
 #pragma unroll
-        for (int f = 0; f < NF; ++f) {
-#pragma unroll
-            for (int m = 0; m < P; ++m) v[f][m] = lds(f, t + S::T * m);
-        }
+        for (int f = 0; f < NF; ++f) lds_load_points<N, P>(lds, f, t, v[f]);
         __syncthreads();
-        fft_from<N, P, INV, NF, I + 1>(v, t, tw, lds);
+        fft_from<N, P, INV, NF, I + 1, TWD>(v, t, tw, lds);
     }
 }
 
 // Full transform.  Every thread of the workgroup must call this (barriers).
-template <int N, int P, bool INV, int NF, class Lds>
+// TWD: read every twiddle of a butterfly from the table (a table in LDS),
+// instead of the one to three table reads and the products of `twiddles`.
+template <int N, int P, bool INV, int NF, bool TWD = false, class Lds>
 __device__ __forceinline__ void fft_run(cplx (&v)[NF][P], int t,
                                         const cplx* __restrict__ tw, const Lds& lds) {
-    fft_from<N, P, INV, NF, 0>(v, t, tw, lds);
+    fft_from<N, P, INV, NF, 0, TWD>(v, t, tw, lds);
 }
 
 // ------------------------------------------- sequential LDS exchange -----
@@ -377,15 +451,12 @@ __device__ __forceinline__ void fft_pass_seq(cplx (&v)[NF][P], int t,
 #pragma unroll
                 for (int r = 0; r < R; ++r) v[f][b + r * NB] = x[r];
             } else {
-                const int base = (j / NS) * NS * R + k;
-#pragma unroll
-                for (int r = 0; r < R; ++r) lds(0, base + r * NS) = x[r];
+                lds_store_outputs<N, NS, R>(lds, 0, (j / NS) * NS * R + k, x);
             }
         }
         if constexpr (!LAST) {
             __syncthreads();
-#pragma unroll
-            for (int m = 0; m < P; ++m) v[f][m] = lds(0, t + S::T * m);
+            lds_load_points<N, P>(lds, 0, t, v[f]);
             __syncthreads();
         }
     }
@@ -406,10 +477,5 @@ __device__ __forceinline__ void fft_run_seq(cplx (&v)[NF][P], int t,
     fft_from_seq<N, P, INV, NF, 0>(v, t, tw, lds);
 }
 
-// Padded LDS index: one spare slot every 16 elements keeps the stride-R
-// autosort writes of the first passes off a single bank.
-__device__ __forceinline__ int lds_pad(int pos) { return pos + (pos >> 4); }
-template <int N>
-struct PaddedLen { static constexpr int value = N + N / 16 + 1; };
 
 FW_END

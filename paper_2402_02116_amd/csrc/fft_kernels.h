@@ -42,6 +42,7 @@ __device__ __forceinline__ void block_sum_to0(double (&acc)[NV], double* smem) {
 struct RowLds {
     cplx* p;
     __device__ __forceinline__ cplx& operator()(int, int pos) const { return p[lds_pad(pos)]; }
+    __device__ __forceinline__ cplx& padded(int, int pp) const { return p[pp]; }
 };
 
 // Row transforms of F rows per block, P points per thread (T = N / P threads
@@ -202,9 +203,8 @@ struct ColLds {
     cplx* base;   // this thread's column (or its private dummy slot)
     int stride;     // W (columns interleaved) or 1 (dummy slot)
     int PL;
-    __device__ __forceinline__ cplx& operator()(int f, int pos) const {
-        return base[(f * PL + lds_pad(pos)) * stride];
-    }
+    __device__ __forceinline__ cplx& operator()(int f, int pos) const { return padded(f, lds_pad(pos)); }
+    __device__ __forceinline__ cplx& padded(int f, int pp) const { return base[(f * PL + pp) * stride]; }
 };
 
 // (bx, bz) <- G_hat (bx, bz) with G_hat = gscale (Gamma' - ga I)^-1 for the
@@ -226,6 +226,34 @@ __device__ __forceinline__ void green_mul(cplx& bx, cplx& bz, real gxx, real gzz
 
 // Signed FFT index of i on an n-point axis (numpy fftfreq order).
 __device__ __forceinline__ int fft_signed(int i, int n) { return (i < (n + 1) / 2) ? i : i - n; }
+
+// u_hat = G_hat(k) b_hat(k) at the P points t + T*m of column ix of a
+// transformed spectrum, with the IFFT normalisation folded in (eqs. u0 and A
+// in the wavenumber domain).  The central-difference symbol sin(2 pi iz / N)
+// / dx comes from the twiddle table (tw[iz] = exp(-2 pi i iz / N)).
+template <int N, int P>
+__device__ __forceinline__ void green_column(cplx (&v)[2][P], int t, int ix, const ProbDev& pd,
+                                             const cplx* tw) {
+    constexpr int T = N / P;
+    const int nx = pd.nx;
+    const int sx = fft_signed(ix, nx);
+    const bool central = pd.symbol == 1;
+    const real kx = central ? rsinpi(2.0f * (real)sx / (real)nx) / pd.dx : (real)sx * pd.dkx;
+    const real kxo = ((nx % 2) == 0 && ix == nx / 2) ? 0.f : kx;
+    const real kx2 = kx * kx;
+    const real axx = pd.gc11 * kx2, azz = pd.gc55 * kx2, axz = pd.gc1355 * kxo;
+    const real rdx = 1.0f / pd.dx;
+#pragma unroll
+    for (int m = 0; m < P; ++m) {
+        const int iz = t + T * m;
+        const int sz = fft_signed(iz, N);
+        const real kz = central ? -tw[iz].y * rdx : (real)sz * pd.dkz;
+        const real kzo = ((N % 2) == 0 && iz == N / 2) ? 0.f : kz;
+        green_mul(v[0][m], v[1][m], axx + pd.gc55 * kz * kz, azz + pd.gc33 * kz * kz, axz * kzo, pd.ga,
+                  pd.gscale);
+        __builtin_amdgcn_sched_barrier(0);   // one point at a time: bounded registers
+    }
+}
 
 // Column transforms (with the Green multiply in COL_GREEN mode) of W columns
 // per block, P points per thread.  SEQ: the two field components share one
@@ -275,27 +303,7 @@ __global__ __launch_bounds__(NT) void k_cols(cplx* __restrict__ data, ProbDev pd
         else fft_run<N, P, false, 2>(v, tt, tw, lds);
     }
     if constexpr (MODE == COL_GREEN) {
-        // u_hat = G_hat(k) b_hat(k), with the IFFT normalisation folded in
-        const int ix = x0 + c;
-        const int sx = fft_signed(ix, nx);
-        const bool central = pd.symbol == 1;
-        const real kx = central ? rsinpi(2.0f * (real)sx / (real)nx) / pd.dx : (real)sx * pd.dkx;
-        const real kxo = ((nx % 2) == 0 && ix == nx / 2) ? 0.f : kx;
-        const real kx2 = kx * kx;
-        const real axx = pd.gc11 * kx2, azz = pd.gc55 * kx2, axz = pd.gc1355 * kxo;
-        const real rdx = 1.0f / pd.dx;
-#pragma unroll
-        for (int m = 0; m < P; ++m) {
-            const int iz = tt + T * m;
-            const int sz = fft_signed(iz, N);
-            // central symbol sin(2 pi iz / N) / dx from the twiddle table
-            // (tw[iz] = exp(-2 pi i iz / N))
-            const real kz = central ? -tw[iz].y * rdx : (real)sz * pd.dkz;
-            const real kzo = ((N % 2) == 0 && iz == N / 2) ? 0.f : kz;
-            green_mul(v[0][m], v[1][m], axx + pd.gc55 * kz * kz, azz + pd.gc33 * kz * kz, axz * kzo,
-                      pd.ga, pd.gscale);
-            __builtin_amdgcn_sched_barrier(0);   // one point at a time: bounded registers
-        }
+        green_column<N, P>(v, tt, x0 + c, pd, tw);
         __syncthreads();
     }
     if constexpr (MODE != COL_FWD) {
@@ -400,6 +408,65 @@ __global__ __launch_bounds__(512) void k_cols_split(cplx* __restrict__ data, Pro
     for (int m = 0; m < P; ++m) st_wt(base + (size_t)(t + T * m) * cs, v[0][m]);
 }
 
+// The Green-multiply column pass with the twiddle table in LDS and the tile
+// width W fixed at compile time (LDS addresses then fold into the
+// instructions' immediate offsets).  The table is copied once per block,
+// after the block's column loads are issued; the transforms' twiddle reads
+// are then LDS reads.  Blocks are exactly W x T threads (no idle threads).
+template <int N, int P, int W>
+__global__ __launch_bounds__(512) void k_cols_tw(cplx* __restrict__ data, ProbDev pd,
+                                                  const SysState* __restrict__ st,
+                                                  const cplx* __restrict__ tw) {
+    using S = FftShape<N, P>;
+    constexpr int T = S::T;
+    constexpr int NT = W * T;
+    constexpr int PL = PaddedLen<N>::value;
+    constexpr int NTW = (N + NT - 1) / NT;   // table entries per thread
+    extern __shared__ cplx lds_dyn[];
+
+    const int nx = pd.nx;
+    const int tid = threadIdx.x;
+    const int c = tid % W, t = tid / W;
+    const int ntile = nx / W;
+    const int blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int sys = blk / ntile;
+    if (st != nullptr && st[sys].status != ST_RUNNING) return;
+    const int ix = (blk - sys * ntile) * W + c;
+
+    const size_t plane = (size_t)N * nx;
+    const int cs = pd.tile_sh ? (1 << pd.tile_sh) : nx;   // column stride: row-major or column-tiled
+    cplx* base = data + (size_t)sys * 2 * plane + spec_off(0, ix, nx, pd.tile_sh ? N : 0, pd.tile_sh);
+    cplx v[2][P];
+#pragma unroll
+    for (int f = 0; f < 2; ++f)
+#pragma unroll
+        for (int m = 0; m < P; ++m) v[f][m] = base[f * plane + (size_t)(t + T * m) * cs];
+    cplx twv[NTW];
+#pragma unroll
+    for (int i = 0; i < NTW; ++i)
+        if (tid + i * NT < N) twv[i] = tw[tid + i * NT];
+#pragma unroll
+    for (int i = 0; i < NTW; ++i)
+        if (tid + i * NT < N) lds_dyn[tid + i * NT] = twv[i];
+    const ColLds lds{lds_dyn + N + c, W, PL};
+    __syncthreads();   // the twiddle table is in LDS
+
+    fft_run<N, P, false, 2, true>(v, t, lds_dyn, lds);
+    green_column<N, P>(v, t, ix, pd, lds_dyn);
+    // as in k_cols: opaque copies keep the forward pass's twiddles and LDS
+    // addresses from being held in registers across the Green multiply
+    int toff = 0;
+    int ti = t;
+    int boff = c + N;
+    asm volatile("" : "+v"(ti), "+v"(boff), "+v"(toff));
+    const ColLds ldi{lds_dyn + boff, W, PL};
+    fft_run<N, P, true, 2, true>(v, ti, lds_dyn + toff, ldi);
+#pragma unroll
+    for (int f = 0; f < 2; ++f)
+#pragma unroll
+        for (int m = 0; m < P; ++m) st_wt(base + f * plane + (size_t)(t + T * m) * cs, v[f][m]);
+}
+
 // ----------------------------------------------------- launch helpers ----
 // Dynamic LDS above the default limit must be enabled once per kernel.
 template <class K>
@@ -448,6 +515,25 @@ inline hipError_t cols_launch(cplx* data, const ProbDev& pd, int W, const SysSta
     hipLaunchKernelGGL((k_cols<N, P, MODE, SEQ, NT>), dim3(blocks), dim3(g.threads), g.lds, s, data, pd, W,
                        st, tw);
     return hipGetLastError();
+}
+
+// The LDS-twiddle pass: W from {4, 8, 16} as a template parameter.
+template <int N, int P>
+inline hipError_t cols_tw_launch(cplx* data, const ProbDev& pd, int W, const SysState* st, const cplx* tw,
+                                 hipStream_t s) {
+    const ColGeom g = col_geom(N, pd.nx, ColCfg{P, W, 4});
+    if (g.threads != W * (N / P) || g.threads > 512) return hipErrorInvalidValue;
+    const int blocks = pd.nsys * (pd.nx / W);
+    auto go = [&](auto kernel) -> hipError_t {
+        hipError_t e = allow_lds(kernel, g.lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(kernel, dim3(blocks), dim3(g.threads), g.lds, s, data, pd, st, tw);
+        return hipGetLastError();
+    };
+    if (W == 4) return go(k_cols_tw<N, P, 4>);
+    if (W == 8) return go(k_cols_tw<N, P, 8>);
+    if (W == 16) return go(k_cols_tw<N, P, 16>);
+    return hipErrorInvalidValue;
 }
 
 FW_END

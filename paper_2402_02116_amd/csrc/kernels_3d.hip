@@ -638,9 +638,8 @@ hipError_t launch_stencil3(int vm, const StencilArgs& a, const ProbDev3& pd, Sys
 struct AxisLds {
     cplx* base;
     int stride, PL;
-    __device__ __forceinline__ cplx& operator()(int f, int pos) const {
-        return base[(f * PL + lds_pad(pos)) * stride];
-    }
+    __device__ __forceinline__ cplx& operator()(int f, int pos) const { return padded(f, lds_pad(pos)); }
+    __device__ __forceinline__ cplx& padded(int f, int pp) const { return base[(f * PL + pp) * stride]; }
 };
 
 // out = gscale (Gamma' - ga I)^-1 b for the real symmetric scaled

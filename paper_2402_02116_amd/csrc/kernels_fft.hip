@@ -56,6 +56,19 @@ static bool cols_wide_built(int n, int P) {
 #endif
 }
 
+// The column pass with the twiddle table in LDS (seq 4) exists for
+// power-of-two columns with 4 or 8 points per thread and tiles of 4, 8 or 16
+// columns (complex64).
+static bool cols_tw_built(int n, int P) {
+#ifdef FW_C128
+    (void)n;
+    (void)P;
+    return false;
+#else
+    return n % 3 != 0 && n % 5 != 0 && (P == 4 || P == 8);
+#endif
+}
+
 bool fft_size_supported(int n) {
     for (int s : kSizes)
         if (s == n) return true;
@@ -122,6 +135,12 @@ ColGeom col_geom(int nz, int nx, const ColCfg& c) {
     const int T = nz / c.P;
     ColGeom g;
     // seq 3: the shared-buffer pass (seq 1) in blocks of up to 1024 threads
+    if (c.seq == 4) {   // two column buffers and the twiddle table
+        g.threads = c.W * T;
+        g.slots = c.W;
+        g.lds = ((size_t)padded_len(nz) * c.W * 2 + nz) * sizeof(cplx);
+        return g;
+    }
     if (c.seq == 2) {   // both components' columns in LDS, no idle threads
         g.threads = 2 * c.W * T;
         g.slots = c.W;
@@ -137,12 +156,15 @@ ColGeom col_geom(int nz, int nx, const ColCfg& c) {
 bool col_cfg_ok(int nz, int nx, const ColCfg& c) {
     if (!fft_size_supported(nz) || c.P <= 0 || nz % c.P != 0) return false;
     if (c.P != col_points_default(nz) && c.P != col_points_alt(nz) && c.P != col_points_small(nz)) return false;
-    if (c.seq < 0 || c.seq > 3) return false;
+    if (c.seq < 0 || c.seq > 4) return false;
     if (c.W < 1 || c.W > 64 || nx % c.W != 0 || (c.W & (c.W - 1)) != 0) return false;
     const ColGeom g = col_geom(nz, nx, c);
     // the component-split pass at 24 points per thread spills registers
     if (c.seq == 2) return c.P < 24 && g.threads % 64 == 0 && g.threads <= 512 && g.lds <= kMaxLds;
     if (c.seq == 3) return cols_wide_built(nz, c.P) && g.threads > 512 && g.threads <= 1024 && g.lds <= kMaxLds;
+    if (c.seq == 4)
+        return cols_tw_built(nz, c.P) && c.W >= 4 && c.W <= 16 && g.threads % 64 == 0 && g.threads <= 512 &&
+               g.lds <= kMaxLds;
     return g.threads <= 512 && g.lds <= kMaxLds;
 }
 
@@ -161,7 +183,7 @@ int col_candidates(int nz, int nx, ColCfg* out, int cap) {
     for (int i = 0; i < 3; ++i) {
         const int P = ps[i];
         if (P == 0 || (i > 0 && P == ps[0]) || (i > 1 && P == ps[1])) continue;
-        for (int seq = 3; seq >= 0; --seq)
+        for (int seq = 4; seq >= 0; --seq)
             for (int W = 4; W <= 32; W *= 2) {
                 const ColCfg c{P, W, seq};
                 if (col_cfg_ok(nz, nx, c) && k < cap) out[k++] = c;

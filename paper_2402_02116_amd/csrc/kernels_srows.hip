@@ -26,6 +26,7 @@ __device__ __forceinline__ int srows_load_row(int lr, int F) {
 struct RowLdsF {
     cplx* p;
     __device__ __forceinline__ cplx& operator()(int, int pos) const { return p[lds_pad(pos)]; }
+    __device__ __forceinline__ cplx& padded(int, int pp) const { return p[pp]; }
 };
 
 template <int N, int P, int VM, int NT>

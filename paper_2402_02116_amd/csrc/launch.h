@@ -39,7 +39,9 @@ struct ColCfg {
     int P;     // points per thread
     int W;     // columns per block
     int seq;   // 1: the two components share one LDS buffer; 2: they are
-               // transformed by separate threads (Green pass only)
+               // transformed by separate threads (Green pass only); 3: as 1 in
+               // blocks of up to 1024 threads; 4: as 0 with the twiddle
+               // table in LDS and W a compile-time constant (Green pass only)
 };
 struct StCfg {
     int TZ;    // tile height (rows), or the rows of a step of the z-marching kernel

@@ -24,6 +24,7 @@ def test_counter_summary_keys_match_the_kernel_names():
     assert bench._pass_instance(0, t) == "fw::c64::(anonymous namespace)::k_srows<256, 16, 0, 256>"
     assert bench._pass_instance(2, t) == "fw::c64::k_cols<256, 16, 0, true, 512>"
     assert bench._pass_instance(2, dict(t, col_shared=2)) == "fw::c64::k_cols_split<256, 16>"
+    assert bench._pass_instance(2, dict(t, col_points=4, col_shared=4)) == "fw::c64::k_cols_tw<256, 4, 8>"
     assert bench._pass_instance(3, t) == "fw::c64::k_rows<256, 8, true, 1>"
     name = ("void fw::c64::k_rows<256, 8, true, 1>(HIP_vector_type<float, 2u> const*, int)")
     assert bench._instance_name(name) == "fw::c64::k_rows<256, 8, true, 1>"
