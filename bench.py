@@ -87,7 +87,7 @@ PASS_MATCH = [lambda n: ((n.startswith("void fw::c64::k_body_force<") or n.start
               or re.search(r"c64::\(anonymous namespace\)::k_srows<\d+, \d+, 0, \d+>\(", n) is not None,
               lambda n: n.startswith("void fw::c64::k_rows<") and ", false, 0>" in n,
               lambda n: (n.startswith("void fw::c64::k_cols<") and ", 0, " in n)
-              or n.startswith("void fw::c64::k_cols_split<"),
+              or n.startswith("void fw::c64::k_cols_split<") or n.startswith("void fw::c64::k_cols_tw<"),
               lambda n: n.startswith("void fw::c64::k_rows<") and ", true, 1>" in n,
               lambda n: re.search(r"c64::\(anonymous namespace\)::k_srows<\d+, \d+, 3, \d+>\(", n) is not None]
 

@@ -29,6 +29,8 @@ def test_counter_summary_keys_match_the_kernel_names():
     name = ("void fw::c64::k_rows<256, 8, true, 1>(HIP_vector_type<float, 2u> const*, int)")
     assert bench._instance_name(name) == "fw::c64::k_rows<256, 8, true, 1>"
     assert bench.PASS_MATCH[3](name) and not bench.PASS_MATCH[1](name)
+    tw = "void fw::c64::k_cols_tw<256, 4, 8>(HIP_vector_type<float, 2u>*, fw::c64::ProbDev)"
+    assert bench.PASS_MATCH[2](tw) and bench._instance_name(tw) == "fw::c64::k_cols_tw<256, 4, 8>"
     # the direction-update mode of the fused kernel (the roofline kernel)
     px = bench._pass_instance(bench.PX_PASS, t)
     assert px == "fw::c64::(anonymous namespace)::k_srows<256, 16, 3, 512>"
