@@ -163,9 +163,9 @@ __global__ __launch_bounds__(256) void k_stencil3(const cplx* __restrict__ u, co
         auto close_iteration = [&](size_t gi) {
             const cplx sv = u[so + gi], tv = a3[so + gi], pv = a1[so + gi];
             const cplx rv = close_r(sv, tv, c2);
-            rout[so + gi] = rv;
-            xio[so + gi] = close_x(xio[so + gi], pv, sv, c3, c2);
-            if (fresh) rhat[so + gi] = rv;
+            st_wt(rout + so + gi, rv);
+            st_wt(xio + so + gi, close_x(xio[so + gi], pv, sv, c3, c2));
+            if (fresh) st_wt(rhat + so + gi, rv);
         };
         if constexpr (VM == VM_PX) {
             if (step == SS_XONLY) {   // stopped: the last solution update only
@@ -210,9 +210,9 @@ __global__ __launch_bounds__(256) void k_stencil3(const cplx* __restrict__ u, co
                 su[c * T::HC + h] = f;
                 if constexpr (VM != VM_NONE) {
                     if (own) {
-                        wout[so + gi] = f;
+                        st_wt(wout + so + gi, f);
                         if constexpr (VM == VM_P) {
-                            if (fresh) rhat[so + gi] = f;   // p = r here
+                            if (fresh) st_wt(rhat + so + gi, f);   // p = r here
                         } else if constexpr (VM == VM_PX) {
                             close_iteration(gi);
                         }
@@ -254,9 +254,9 @@ __global__ __launch_bounds__(256) void k_stencil3(const cplx* __restrict__ u, co
             const int h = ((oz + 2) * T::HY + oy + 2) * T::HX + ox + 2;
             const cplx wr = cscale(pd.w2, sm[NS * T::SC + o]);
             const size_t g = so + gcell(ox, oy, oz);
-            b[g] = cadd(cmul(wr, su[h]), cscale(bx, sc));
-            b[g + cells] = cadd(cmul(wr, su[T::HC + h]), cscale(by, sc));
-            b[g + 2 * cells] = cadd(cmul(wr, su[2 * T::HC + h]), cscale(bz, sc));
+            st_wt(b + g, cadd(cmul(wr, su[h]), cscale(bx, sc)));
+            st_wt(b + g + cells, cadd(cmul(wr, su[T::HC + h]), cscale(by, sc)));
+            st_wt(b + g + 2 * cells, cadd(cmul(wr, su[2 * T::HC + h]), cscale(bz, sc)));
         }
     }
 }
@@ -495,9 +495,9 @@ __global__ __launch_bounds__(TX * TY) void k_stencil3z(const cplx* __restrict__ 
             const cplx bz = cadd(cadd(dxy(4, 1), dxy(3, M::SX)), csub(s0[2], sold[2]));
             const uint32_t g = zoff(z) + xy0;
             const cplx wr = cscale(pd.w2, rho_z);
-            bs[g] = cadd(cmul(wr, fa0[0]), cscale(bx, sc));
-            bs[g + cells32] = cadd(cmul(wr, fa0[1]), cscale(by, sc));
-            bs[g + 2 * cells32] = cadd(cmul(wr, fa0[2]), cscale(bz, sc));
+            st_wt(bs + g, cadd(cmul(wr, fa0[0]), cscale(bx, sc)));
+            st_wt(bs + g + cells32, cadd(cmul(wr, fa0[1]), cscale(by, sc)));
+            st_wt(bs + g + 2 * cells32, cadd(cmul(wr, fa0[2]), cscale(bz, sc)));
         }
         __syncthreads();   // the LDS planes z+1 (input) and z (stress) are read
 #pragma unroll
@@ -736,7 +736,7 @@ __global__ __launch_bounds__(256) void k_axis(cplx* __restrict__ data, int S, in
 #pragma unroll
         for (int f = 0; f < NC; ++f)
 #pragma unroll
-            for (int m = 0; m < P; ++m) base[f * span + (size_t)(t + T * m) * S] = v[f][m];
+            for (int m = 0; m < P; ++m) st_wt(base + f * span + (size_t)(t + T * m) * S, v[f][m]);
     }
 }
 

@@ -181,7 +181,7 @@ __global__ __launch_bounds__(kGmThreads) void k_gm_update(GmArgs a, int j, int p
         if (i < a.n) {
             cplx x = w[i];
             for (int l = 0; l <= j; ++l) x = csub(x, cmul(c[l], a.V[(size_t)l * a.vstride + off + i]));
-            w[i] = x;
+            st_wt(w + i, x);
             acc[0] += (double)x.x * x.x + (double)x.y * x.y;
         }
     }
@@ -294,7 +294,7 @@ __global__ __launch_bounds__(kGmThreads) void k_gm_xupdate(cplx* __restrict__ x,
         if (i < a.n) {
             cplx s = x[off + i];
             for (int l = 0; l < k; ++l) s = cadd(s, cmul(c[l], a.V[(size_t)l * a.vstride + off + i]));
-            x[off + i] = s;
+            st_wt(x + off + i, s);
         }
     }
 }
