@@ -145,3 +145,34 @@ def test_marching_stencil_solves_match_oracle_and_plain(nx, nz):
         assert max(errs) < 1e-4, (c, errs)
         plain = plan.solve(u0, rtol=1e-6, maxit=500, plain=True)
         assert torch.equal(res.x, plain.x) and np.array_equal(res.iters, plain.iters), c
+
+
+@pytest.mark.parametrize("nx,nz", [(96, 64), (64, 256)])
+def test_lds_twiddle_column_solves_match_oracle_and_plain(nx, nz):
+    """The column pass with the twiddle table in LDS (col_shared 4: 4- and
+    8-point columns, 4 to 16 columns per block) through whole BiCGSTAB solves
+    of three systems that stop at different iterations (so blocks of stopped
+    systems exit while the others run), against the oracle, and the batched
+    solve bit-identical to the per-source one."""
+    from paper_2402_02116_amd.plan import Plan
+    p, maps = _case(nx, nz, 3, seed=17)
+    plan = Plan([p])
+    plan.set_contrast(0, maps)
+    src, _ = W.surface_sources(nx, 3, iz=nz // 5)
+    f = [(0.0, 1.0), (1.0, 0.0), (0.6, -0.8)]   # different force directions: different iteration counts
+    u0 = plan.incident(src, f)
+    P = LSProblem(nx, nz, 8.0, p["c0"], p["rho0"], p["freq_hz"], 0.02, maps)
+    uref, _ = P.solve(P.incident(src, f), tol=1e-11)
+    tw = [c for c in plan.tuning_candidates(0, "cols") if c["col_shared"] == 4]
+    assert {c["col_points"] for c in tw} == {4, 8}, tw
+    for c in tw:
+        plan.set_tuning(0, **c)
+        res = plan.solve(u0, rtol=1e-6, maxit=500)
+        assert res.status == 0 and np.all(res.relres <= 2e-6), (c, res.relres)
+        x = plan.view(res.x, 0).cpu().numpy().astype(np.complex128)
+        errs = [_rel(x[k], uref[k]) for k in range(3)]
+        print(f"{nx}x{nz} LDS-twiddle columns P={c['col_points']} W={c['col_width']}: iterations "
+              f"{res.iters.tolist()}, field errors {max(errs):.2e}", flush=True)
+        assert max(errs) < 1e-4, (c, errs)
+        plain = plan.solve(u0, rtol=1e-6, maxit=500, plain=True)
+        assert torch.equal(res.x, plain.x) and np.array_equal(res.iters, plain.iters), c
