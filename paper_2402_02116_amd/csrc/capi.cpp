@@ -59,7 +59,13 @@ constexpr int kMaxRec = 65536;
 // per problem: receiver cells [kMaxRec][3], then the receivers in stable cell
 // order [kMaxRec] and the run lengths of receivers sharing a cell [kMaxRec]
 constexpr int kRecInts = 5;
-constexpr int kChunkIters = 4;        // iterations per graph chunk (even: p buffers alternate)
+// Iterations per graph chunk (even: the p buffers alternate).  Each chunk
+// boundary costs a graph launch and a state readback; each iteration of the
+// last chunk past convergence costs six near-empty launches.  At the 16-18
+// iterations of the 256^2 solves, six per chunk: 2.06 ms per batched solve
+// against 2.14 (four), 2.13 (eight) and 2.24 ms (two); the 3-D, 1024^2 and
+// DBI workloads are equal or faster with six than with four.
+constexpr int kChunkIters = 6;
 constexpr int kNumVec = 11;           // field-sized workspace vectors
 constexpr int kMaxRestarts = 3;       // restarts from the true residual per solve
 constexpr double kTrueResFactor = 2.0; // restart when ||b - A x|| > 2 rtol ||b||
