@@ -134,13 +134,13 @@ ColGeom col_geom(int nz, int nx, const ColCfg& c) {
     (void)nx;
     const int T = nz / c.P;
     ColGeom g;
-    // seq 3: the shared-buffer pass (seq 1) in blocks of up to 1024 threads
-    if (c.seq == 4) {   // two column buffers and the twiddle table
+    if (c.seq == 4) {   // the LDS-twiddle pass: two column buffers and the twiddle table
         g.threads = c.W * T;
         g.slots = c.W;
         g.lds = ((size_t)padded_len(nz) * c.W * 2 + nz) * sizeof(cplx);
         return g;
     }
+    // seq 3: the shared-buffer pass (seq 1) in blocks of up to 1024 threads
     if (c.seq == 2) {   // both components' columns in LDS, no idle threads
         g.threads = 2 * c.W * T;
         g.slots = c.W;
