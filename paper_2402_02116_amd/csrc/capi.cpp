@@ -66,6 +66,10 @@ constexpr int kRecInts = 5;
 // against 2.14 (four), 2.13 (eight) and 2.24 ms (two); the 3-D, 1024^2 and
 // DBI workloads are equal or faster with six than with four.
 constexpr int kChunkIters = 6;
+// A chunk that the host launches after seeing that the previous one, expected
+// to be the last, was not, runs this many iterations when the residual trend
+// says they suffice (even, like kChunkIters).
+constexpr int kTailIters = 2;
 constexpr int kNumVec = 11;           // field-sized workspace vectors
 constexpr int kMaxRestarts = 3;       // restarts from the true residual per solve
 constexpr double kTrueResFactor = 2.0; // restart when ||b - A x|| > 2 rtol ||b||
@@ -133,7 +137,7 @@ struct fwils_plan_s {
     double cg_rs0 = 0.0;        // that run's initial squared residual
     // graphs of one chunk of iterations over all problems (the first chunk of
     // a solve or restart starts from r)
-    hipGraphExec_t chunk = nullptr, chunk_first = nullptr;
+    hipGraphExec_t chunk = nullptr, chunk_first = nullptr, chunk_tail = nullptr;
     // Krylov method; GMRES state lives in a caller-provided workspace
     int krylov = FWILS_KRYLOV_BICGSTAB;
     bool bicg_state = false;   // the workspace holds the state of a finished BiCGSTAB solve
@@ -378,11 +382,12 @@ hipError_t bicg_close(fwils_plan pl, const ProbHost& P, const SysView& V, int pa
                              (int)P.n_per_sys, s);
 }
 
-// One chunk of kChunkIters iterations and the close kernel; `first` when the
-// chunk starts a solve or a restart (its first iteration reads r).
-hipError_t bicg_chunk(fwils_plan pl, const ProbHost& P, const SysView& V, bool first, hipStream_t s) {
+// One chunk of `iters` (even) iterations and the close kernel; `first` when
+// the chunk starts a solve or a restart (its first iteration reads r).
+hipError_t bicg_chunk(fwils_plan pl, const ProbHost& P, const SysView& V, bool first, hipStream_t s,
+                      int iters = kChunkIters) {
     hipError_t e = hipSuccess;
-    for (int it = 0; it < kChunkIters && e == hipSuccess; ++it)
+    for (int it = 0; it < iters && e == hipSuccess; ++it)
         e = bicg_iteration(pl, P, V, it & 1, first && it == 0, s);
     if (e == hipSuccess) e = bicg_close(pl, P, V, (kChunkIters - 1) & 1, s);
     return e;
@@ -421,11 +426,11 @@ fwils_status capture_graph(fwils_plan pl, hipGraphExec_t* out,
 }
 
 fwils_status build_chunk_graphs(fwils_plan pl) {
-    for (int f = 0; f < 2; ++f) {
-        hipGraphExec_t* g = f ? &pl->chunk_first : &pl->chunk;
+    for (int f = 0; f < 3; ++f) {   // chunk, first chunk, tail chunk
+        hipGraphExec_t* g = f == 1 ? &pl->chunk_first : f == 2 ? &pl->chunk_tail : &pl->chunk;
         if (*g) continue;
         FW_TRY(capture_graph(pl, g, [pl, f](const ProbHost& P, hipStream_t s) -> hipError_t {
-            return bicg_chunk(pl, P, make_view(pl, P, 0, P.p.nsys), f == 1, s);
+            return bicg_chunk(pl, P, make_view(pl, P, 0, P.p.nsys), f == 1, s, f == 2 ? kTailIters : kChunkIters);
         }));
     }
     return FWILS_OK;
@@ -474,7 +479,7 @@ fwils_status bicg_solve_ws(fwils_plan pl, const cplx* b, bool use_x0, double rto
             }
             return FWILS_OK;
         }
-        const int max_chunks = maxit / kChunkIters + 2;
+        const int max_chunks = maxit / kTailIters + 2;   // a bound: the device stops systems at maxit
         bool done = false;
         if (known) {
             done = true;
@@ -487,14 +492,17 @@ fwils_status bicg_solve_ws(fwils_plan pl, const cplx* b, bool use_x0, double rto
         // the device does not wait for the host between chunks; a chunk queued
         // after every system stopped only runs kernels that exit at once.  The
         // speculation is skipped when the residual trend says the chunk just
-        // queued is likely the last one.
+        // queued is likely the last one; when that chunk then was not the last,
+        // the next one is a short tail chunk if the trend says it suffices.
         SysState* hp[2] = {pl->host_pipe, pl->host_pipe + nst};
-        auto launch = [&](int c) -> fwils_status {
+        std::vector<int> len(max_chunks + 1, kChunkIters);   // iterations of each chunk
+        auto launch = [&](int c, bool tail) -> fwils_status {
+            len[c] = tail ? kTailIters : kChunkIters;
             if (flags & FWILS_SOLVE_NOGRAPH) {
                 for (const ProbHost& P : pl->probs)
-                    FW_HIP(bicg_chunk(pl, P, make_view(pl, P, 0, P.p.nsys), c == 0, s));
+                    FW_HIP(bicg_chunk(pl, P, make_view(pl, P, 0, P.p.nsys), c == 0, s, len[c]));
             } else {
-                FW_HIP(hipGraphLaunch(c == 0 ? pl->chunk_first : pl->chunk, s));
+                FW_HIP(hipGraphLaunch(c == 0 ? pl->chunk_first : tail ? pl->chunk_tail : pl->chunk, s));
             }
             FW_HIP(hipMemcpyAsync(hp[c & 1], pl->state, nst * sizeof(SysState), hipMemcpyDeviceToHost, s));
             FW_HIP(hipEventRecord(pl->pipe_ev[c & 1], s));
@@ -504,28 +512,31 @@ fwils_status bicg_solve_ws(fwils_plan pl, const cplx* b, bool use_x0, double rto
         for (size_t i = 0; i < nst; ++i) prev[i] = known ? pl->host_state[i].rnorm2 : 0.0;
         int launched = 0;
         bool last_likely = false;
-        FW_TRY(launch(0));
+        FW_TRY(launch(0, false));
         launched = 1;
         for (int c = 0; c < max_chunks; ++c) {
             if (launched == c + 1 && c + 1 < max_chunks && !last_likely) {
-                FW_TRY(launch(c + 1));
+                FW_TRY(launch(c + 1, false));
                 ++launched;
             }
             FW_HIP(hipEventSynchronize(pl->pipe_ev[c & 1]));
             const SysState* h = hp[c & 1];
             done = true;
             last_likely = true;
+            bool tail_enough = true;
             for (size_t i = 0; i < nst; ++i) {
                 if (h[i].status != ST_RUNNING) continue;
                 done = false;
-                // geometric extrapolation of ||r||^2 over one more chunk
-                const double cur = h[i].rnorm2, ratio = prev[i] > 0.0 ? cur / prev[i] : 1.0;
-                if (!(cur * ratio <= h[i].tol2)) last_likely = false;
+                // geometric extrapolation of ||r||^2 at the rate of chunk c
+                const double cur = h[i].rnorm2;
+                const double rate = prev[i] > 0.0 && cur > 0.0 ? std::log(cur / prev[i]) / len[c] : 0.0;
+                if (!(cur * std::exp(rate * kChunkIters) <= h[i].tol2)) last_likely = false;
+                if (!(cur * std::exp(rate * kTailIters) <= h[i].tol2)) tail_enough = false;
                 prev[i] = cur;
             }
             if (done) break;
             if (launched == c + 1 && c + 1 < max_chunks) {
-                FW_TRY(launch(c + 1));
+                FW_TRY(launch(c + 1, tail_enough));
                 ++launched;
             }
         }
@@ -593,7 +604,9 @@ fwils_status bicg_solve_ws(fwils_plan pl, const cplx* b, bool use_x0, double rto
 void drop_graphs(fwils_plan pl) {
     if (pl->chunk) (void)hipGraphExecDestroy(pl->chunk);
     if (pl->chunk_first) (void)hipGraphExecDestroy(pl->chunk_first);
+    if (pl->chunk_tail) (void)hipGraphExecDestroy(pl->chunk_tail);
     pl->chunk_first = nullptr;
+    pl->chunk_tail = nullptr;
     if (pl->gm_cycle) (void)hipGraphExecDestroy(pl->gm_cycle);
     pl->chunk = nullptr;
     pl->gm_cycle = nullptr;
