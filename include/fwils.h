@@ -77,7 +77,7 @@ typedef enum {
     FWILS_EDEVICE = 3,       /* HIP runtime error                             */
     FWILS_ENOCONV = 4,       /* some system did not reach the tolerance       */
     FWILS_EBREAKDOWN = 5,    /* Krylov breakdown or non-finite residual       */
-    FWILS_EUNSUPPORTED = 6   /* valid request this build does not implement   */
+    FWILS_EUNSUPPORTED = 6   /* valid request the library does not implement   */
 } fwils_status;
 
 typedef enum {

@@ -1277,7 +1277,7 @@ void* g_scratch_ptr[kMaxDevices] = {};
 // address: only the looked-up pointer is ever handed to kernels.
 fwils_status noalloc_scratch(int dev, void** out) {
     if (dev < 0 || dev >= kMaxDevices) {
-        set_error("apply_noalloc: device %d beyond the %d this build tracks", dev, kMaxDevices);
+        set_error("apply_noalloc: device %d beyond the %d devices the library tracks", dev, kMaxDevices);
         return FWILS_EINVAL;
     }
     std::lock_guard<std::mutex> lock(g_scratch_mu);

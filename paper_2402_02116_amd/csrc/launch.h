@@ -29,7 +29,7 @@ struct GmEpi {
 
 enum ColMode : int { COL_GREEN = 0, COL_FWD = 1, COL_INV = 2 };
 
-// FFT sizes with kernels in this build: 2^a 3^b, 16 <= n <= 2048.
+// FFT sizes the library has kernels for: 2^a 3^b, 16 <= n <= 2048.
 bool fft_size_supported(int n);
 
 constexpr size_t kMaxLds = 160 * 1024;   // LDS per workgroup on gfx950
