@@ -29,8 +29,10 @@ def _case(nx, nz, nsys, seed=5):
 # (1024, 32): the radix-32 row variant; (64, 1024): the 1024-thread column
 # variant and the longest columns of the shared / split variants; (512, 64):
 # the 512-point rows (radix-32, 16- and 8-point variants) and the fused
-# stencil + rows kernels of that width, which the 512^2 workload runs
-@pytest.mark.parametrize("nx,nz", [(96, 64), (64, 96), (256, 384), (1024, 32), (64, 1024), (512, 64), (128, 256)])
+# stencil + rows kernels of that width, which the 512^2 workload runs;
+# (64, 512), (128, 16): the LDS-twiddle column variants at those lengths
+@pytest.mark.parametrize("nx,nz", [(96, 64), (64, 96), (256, 384), (1024, 32), (64, 1024), (512, 64), (128, 256),
+                                   (64, 512), (128, 16)])
 def test_every_variant_matches_oracle(nx, nz):
     from paper_2402_02116_amd.plan import Plan
     p, maps = _case(nx, nz, 2)
