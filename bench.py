@@ -258,8 +258,9 @@ def _pass_instance(k, tuning, n=256):
         return f"fw::c64::(anonymous namespace)::k_srows<{n}, {p}, 3, {512 if n >= 256 and n // p <= 32 else 256}>"
     if k == 0:
         if tuning.get("fused_points"):
-            # the plain mode always runs the 256-thread form
-            return f"fw::c64::(anonymous namespace)::k_srows<{n}, {tuning['fused_points']}, 0, 256>"
+            # the plain mode runs 512-thread blocks on rows of 384 points or more (short row segments)
+            p = tuning["fused_points"]
+            return f"fw::c64::(anonymous namespace)::k_srows<{n}, {p}, 0, {512 if n >= 384 and n // p <= 32 else 256}>"
         if tuning.get("stencil_sys") == -1:   # the z-marching stencil
             return f"fw::c64::k_body_force_z<64, {tuning['stencil_rows']}, 0>"
         return f"fw::c64::k_body_force<64, {tuning['stencil_rows']}, 0>"

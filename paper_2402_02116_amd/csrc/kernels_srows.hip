@@ -260,10 +260,14 @@ __global__ __launch_bounds__(NT) void k_srows(const cplx* __restrict__ u, const 
 }  // namespace
 
 // Threads of the fused kernel: 512 (twice the rows per block, so a smaller
-// share of halo rows) for the heaviest input update, VM_PX, which reads four
-// vectors in the halo, where a thread's row segment is short enough; 256
-// otherwise (measured: no gain for the lighter modes).
-constexpr bool srows_wide(int nx, int P, int vm) { return vm == VM_PX && nx >= 256 && nx / P <= 32; }
+// share of halo rows) where a thread's row segment is short enough, for the
+// heaviest input update, VM_PX, which reads four vectors in the halo, and for
+// the plain mode on rows of 384 points or more (four own rows per block
+// otherwise: 232 -> 228 us for the plain pass over the four grids 128^2 ..
+// 384^2); 256 otherwise (measured: no gain for the lighter update modes).
+constexpr bool srows_wide(int nx, int P, int vm) {
+    return (vm == VM_PX && nx >= 256 && nx / P <= 32) || (vm == VM_NONE && nx >= 384 && nx / P <= 32);
+}
 
 // Rows per block (a power of two <= threads / 2T dividing nz) for n-point
 // rows with P points per thread in stencil mode vm; 0 when the fused kernel

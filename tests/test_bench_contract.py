@@ -22,6 +22,8 @@ def test_counter_summary_keys_match_the_kernel_names():
     t = dict(row_points=16, row_points_inv=8, col_points=16, col_width=8, col_shared=1, stencil_rows=8,
              fused_points=16)
     assert bench._pass_instance(0, t) == "fw::c64::(anonymous namespace)::k_srows<256, 16, 0, 256>"
+    assert (bench._pass_instance(0, dict(t, fused_points=12), n=384) ==
+            "fw::c64::(anonymous namespace)::k_srows<384, 12, 0, 512>")
     assert bench._pass_instance(2, t) == "fw::c64::k_cols<256, 16, 0, true, 512>"
     assert bench._pass_instance(2, dict(t, col_shared=2)) == "fw::c64::k_cols_split<256, 16>"
     assert bench._pass_instance(2, dict(t, col_points=4, col_shared=4)) == "fw::c64::k_cols_tw<256, 4, 8>"
